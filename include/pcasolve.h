@@ -1,0 +1,242 @@
+/*
+ * pcasolve -- per-projection PCA lung-motion solve on MI355X (gfx950).
+ *
+ * Method: Li et al., "3D tumor localization through real-time volumetric
+ * x-ray imaging for lung cancer radiotherapy".  Given one cone-beam x-ray
+ * projection y at a known gantry angle, find the PCA coefficients w that
+ * minimise (Eq. 2)
+ *
+ *     J(w, a, b) = || P f(x, f0) - a y - b 1 ||^2,   x = xbar + U w   (Eq. 1)
+ *
+ * where f is the reference image f0 pulled back through the deformation
+ * field x by trilinear interpolation (Eqs. A.3, A.5) and P is the cone-beam
+ * projection at that angle; then locate the tumour by inverting the solved
+ * pull-back field at one point.
+ *
+ * C ABI: plain pointers and sizes only.
+ *   - "device" arrays live in GPU memory owned by the caller; the library
+ *     never frees them and never keeps a pointer past the call.
+ *   - "host" arrays are ordinary CPU memory owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Unless stated otherwise an entry point only enqueues work on `stream`
+ *     and returns; outputs are valid once the stream reaches that point.
+ *   - `dtype` selects the element type of every floating-point device array
+ *     of the call (all of them share it): PCAS_F32 (float) or PCAS_F64
+ *     (double).  Reductions always accumulate in double.
+ *   - Every argument is validated on the host before the first HIP call;
+ *     an invalid call returns a negative status and touches no memory.
+ *
+ * Layouts (0-based versions of the Appendix's 1-based (i, j, k)):
+ *   volume       f[i + n1*(j + n2*k)]            i = lateral, fastest
+ *   vector field x[c*N + v], c = 0 lateral, 1 AP, 2 SI, in mm, N = n1*n2*n3
+ *   modes        U[(k*3 + c)*N + v], k = 0..K-1 (mm per unit coefficient)
+ *   detector     p[iu + nu*iv]                   u (tangential) fastest
+ *
+ * Geometry (the paper fixes only that P depends on the gantry angle):
+ *   voxel (i,j,k) centre = origin + (i,j,k) * spacing  (mm)
+ *   source = (SAD sin t, -SAD cos t, 0); flat detector at distance SID from
+ *   the source with axes e_u = (cos t, sin t, 0), e_v = (0, 0, 1); pixel
+ *   (iu, iv) centre at u = (iu - (nu-1)/2) pitch_u + offset_u (same for v).
+ *   One ray per pixel centre.  P integrates the trilinear interpolant of the
+ *   volume along the chord through the box spanned by the first and last
+ *   voxel centres with the midpoint rule: n = ceil(L / step) samples of
+ *   width dt = L / n.  Outside the grid every volume reads as zero.
+ */
+#ifndef PCASOLVE_H
+#define PCASOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCAS_ABI_VERSION 1
+#define PCAS_MAX_K 8
+
+typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
+
+/* status codes (return values) */
+enum {
+    PCAS_OK = 0,
+    PCAS_EINVAL = -1,      /* null pointer, dimension < 2, K outside [1, 8], bad dtype, bad option */
+    PCAS_EGEOM = -2,       /* SAD <= 0, SID <= SAD, pitch <= 0, step <= 0, source inside the volume */
+    PCAS_ESINGULAR = -3,   /* Y^T Y of Eq. A.1 singular (constant measured projection) */
+    PCAS_ENONFINITE = -4,  /* NaN or Inf in y, w0 or an objective value */
+    PCAS_EWORKSPACE = -5,  /* workspace missing, too small or misaligned */
+    PCAS_EHIP = -6         /* a HIP runtime call failed; see pcas_last_error() */
+};
+
+/* solve_projection termination reasons (pcas_report.status, >= 0) */
+enum { PCAS_STOP_CONVERGED = 0, PCAS_STOP_MAXITER = 1, PCAS_STOP_LINESEARCH = 2 };
+
+typedef struct {
+    int32_t n[3];          /* n1, n2, n3 (each >= 2) */
+    double spacing[3];     /* mm, > 0 */
+    double origin[3];      /* mm, centre of voxel (0, 0, 0) */
+} pcas_vol;
+
+typedef struct {
+    double angle;          /* gantry angle t (radians) */
+    double sad, sid;       /* source-axis and source-detector distances (mm) */
+    int32_t nu, nv;        /* detector pixels (>= 1) */
+    double pitch_u, pitch_v;   /* pixel pitch at the detector (mm) */
+    double offset_u, offset_v; /* detector shift (mm), 0 for a centred full fan */
+    double step;           /* ray-march sample spacing (mm) */
+} pcas_proj;
+
+typedef struct {
+    int32_t method;        /* 0: Appendix algorithm (Eq. A.1 + Eq. A.2 + Armijo); 1: PR+ CG */
+    int32_t max_iter;      /* accepted iterations */
+    int32_t fit_intensity; /* 1: (a, b) from Eq. A.1; 0: a = 1, b = 0 */
+    int32_t max_backtracks;/* line-search trials per iteration (CG) */
+    double mu0;            /* first step length (in units of w) */
+    double alpha, beta;    /* Armijo sufficient-decrease and shrink factors */
+    double mu_min;         /* method 0: stop once the step falls below it */
+    double gtol_rel;       /* method 1: stop when ||g|| <= gtol_rel ||g0|| */
+    double beta_lo;        /* method 1: lower safeguard of the interpolated shrink */
+    double xtol;           /* method 1: a trial step shorter than xtol fails the search */
+    int32_t locate;        /* 1: also run tumour_position at c0_mm after the solve */
+    int32_t locate_max_iter;
+    double locate_tol;     /* mm */
+    double c0_mm[3];       /* tumour centre in the reference image (mm) */
+    int32_t profile;       /* 1: time every kernel with HIP events (report.kernel_ms) */
+    int32_t reserved;
+} pcas_opts;
+
+/* kernel classes of pcas_report.kernel_ms / kernel_launches */
+enum {
+    PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
+    PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7
+};
+
+typedef struct {
+    int32_t status;        /* PCAS_STOP_* */
+    int32_t iters;         /* accepted iterations */
+    int32_t n_fevals;      /* forward evaluations (warp + projection) */
+    int32_t n_grads;       /* gradient evaluations (adjoint + Jacobian chain) */
+    double J0, J;          /* objective at w0 and at the returned w */
+    double a, b;           /* intensity fit at the returned w */
+    double gnorm0, gnorm;  /* ||dJ/dw|| at w0 and at the returned w */
+    double tumour_mm[3];   /* located tumour position (if opts.locate) */
+    int32_t locate_iters;  /* fixed-point iterations, -1 if not converged */
+    int32_t reserved;
+    double kernel_ms[8];   /* with opts.profile: summed kernel time per class (ms) */
+    int32_t kernel_launches[8];
+} pcas_report;
+
+/* ---- utilities --------------------------------------------------------- */
+
+int pcas_abi_version(void);
+const char *pcas_status_string(int status);
+/* Text of the last PCAS_EHIP failure on the calling thread ("" if none). */
+const char *pcas_last_error(void);
+/* Defaults: method 1 (CG), 30 iterations, fit on, 12 backtracks, mu0 = 1,
+ * alpha = 0.1, beta = 0.5 (the Appendix's Armijo constants), mu_min = 0.01,
+ * gtol_rel = 1e-9, beta_lo = 0.1, xtol = 1e-10, no localisation, 100
+ * localisation iterations, 1e-9 mm tolerance. */
+void pcas_default_opts(pcas_opts *opts);
+/* Appendix algorithm: method 0, 10 iterations, mu0 = 0.2, alpha = 0.1,
+ * beta = 0.5, stop below mu_min = 0.01 (the paper's 2 and 0.1 rescaled from
+ * its coefficient standard deviation of 10 to ours of 1). */
+void pcas_paper_opts(pcas_opts *opts);
+
+/* ---- a1: ray table (Sec. II.A: P depends on the gantry angle) ----------
+ * One record per detector pixel: entry point and per-sample step in voxel
+ * index units, sample width dt (mm) and sample count n, computed in double
+ * from the geometry above and stored in `dtype`.  Every projection and
+ * back-projection call of one geometry reads the same table, which is what
+ * makes drr_adjoint the exact transpose of drr_forward.
+ * rays: device, pcas_ray_table_bytes() bytes, 16-byte aligned. */
+size_t pcas_ray_table_bytes(pcas_dtype dtype, const pcas_proj *proj);
+int ray_table(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, void *rays,
+              void *stream);
+
+/* ---- a2: Eq. 1, x = xbar + sum_k w_k u_k ---------------------------------
+ * mean: device [3][N] or NULL (zero mean); U: device [K][3][N];
+ * w: host double[K]; dvf_out: device [3][N] (mm). */
+int pca_dvf(pcas_dtype dtype, int64_t nvox, int32_t K, const void *mean, const void *U,
+            const double *w, void *dvf_out, void *stream);
+
+/* ---- a3: Eqs. A.3 / A.5, f(i,j,k) = f0 at (i,j,k) + x/spacing ------------
+ * Trilinear pull-back with zero extension outside the grid.
+ * f0: device [N]; dvf: device [3][N] (mm); f_out: device [N] (no aliasing). */
+int warp_trilinear(pcas_dtype dtype, const pcas_vol *vol, const void *f0, const void *dvf,
+                   void *f_out, void *stream);
+
+/* ---- a2 + a3 fused: the field of Eq. 1 is formed per voxel in registers
+ * and never stored.  Arguments as pca_dvf / warp_trilinear. */
+int warp_pca(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, const void *mean,
+             const void *U, const double *w, void *f_out, void *stream);
+
+/* ---- a4: forward projection p = P f (Eq. 2) ------------------------------
+ * rays: device table from ray_table() for the same (dtype, vol, proj);
+ * f: device [N]; p_out: device [nv][nu].  Pixels whose ray misses the box
+ * get 0. */
+int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
+                const void *f, void *p_out, void *stream);
+
+/* ---- a6: back-projection bp = P^T r (Appendix, gradient of J) -----------
+ * The exact transpose of drr_forward for the same ray table: every sample
+ * of every ray adds dt * r * (its trilinear weight) to its eight voxels.
+ * Accumulated per voxel brick in on-chip memory with no global atomics;
+ * bit-for-bit reproducible.  r: device [nv][nu]; bp_out: device [N],
+ * fully overwritten. */
+int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
+                const void *r, void *bp_out, void *stream);
+
+/* ---- a5: intensity fit (Eq. A.1) and residual ----------------------------
+ * stats_out: device double[8] =
+ *   { J, a, b, sum p, sum p*y, sum p*p, sum y, sum y*y }
+ * with (a, b) from Eq. A.1 (or (1, 0) if fit_intensity == 0), J = ||r||^2;
+ * r_out: device [M] = p - a y - b (may be NULL; may alias p).
+ * If Y^T Y is singular a, b and J are NaN (checked by the caller).
+ * workspace: device, residual_fit_workspace_bytes() bytes. */
+size_t residual_fit_workspace_bytes(int64_t npix);
+int residual_fit(pcas_dtype dtype, int64_t npix, const void *p, const void *y, int32_t fit_intensity,
+                 void *r_out, double *stats_out, void *workspace, size_t workspace_bytes,
+                 void *stream);
+
+/* ---- a7: Jacobian chain and K-reduction ----------------------------------
+ * g = 2 U^T (df/dx) bp with df/dx the diagonal Jacobian of Eq. A.8 (and its
+ * two analogues) at x = xbar + U w, per mm; the right-side derivative at
+ * integer positions.  bp is normally P^T r, making g = dJ/dw at fixed (a, b).
+ * f0, bp: device [N]; mean: device [3][N] or NULL; U: device [K][3][N];
+ * w: host double[K]; g_out: device double[K].  Deterministic (fixed-order
+ * reduction).  workspace: device, grad_w_workspace_bytes() bytes. */
+size_t grad_w_workspace_bytes(pcas_dtype dtype, const pcas_vol *vol, int32_t K);
+int grad_w(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, const void *mean,
+           const void *U, const double *w, const void *bp, double *g_out, void *workspace,
+           size_t workspace_bytes, void *stream);
+
+/* ---- a9: tumour position (Sec. II.A, pull-back inversion at one point) --
+ * Fixed point y <- c0 - x(y) from y = c0, with x the trilinear value of the
+ * field of Eq. 1 at y (zero outside the grid); stops when a step is shorter
+ * than tol (mm) or after max_iter iterations.
+ * out: device double[4] = { y1, y2, y3 (mm), iterations or -1 }. */
+int tumour_position(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *mean,
+                    const void *U, const double *w, const double c0_mm[3], double tol,
+                    int32_t max_iter, double *out, void *stream);
+
+/* ---- a1-a9: the per-projection solve -------------------------------------
+ * Minimise Eq. 2 over w from w0 with the method in opts (Appendix algorithm
+ * or CG; see pcas_opts), then optionally locate the tumour.
+ * f0: device [N]; mean: device [3][N] or NULL; U: device [K][3][N];
+ * y: device [nv][nu]; w0: host double[K]; w_out: host double[K];
+ * report: host.  workspace: device, solve_projection_workspace() bytes,
+ * 256-byte aligned, used exclusively by this call until it returns.
+ * Synchronous: returns after the result has been copied to the host.
+ * Returns PCAS_OK (with the stop reason in report->status) or an error. */
+size_t solve_projection_workspace(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
+                                  int32_t K);
+int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, int32_t K,
+                     const void *f0, const void *mean, const void *U, const void *y,
+                     const double *w0, const pcas_opts *opts, void *workspace,
+                     size_t workspace_bytes, double *w_out, pcas_report *report, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCASOLVE_H */

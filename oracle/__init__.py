@@ -261,6 +261,7 @@ class SolveOptions:
     mu_min: float = 0.01
     gtol_rel: float = 1e-9
     beta_lo: float = 0.1
+    xtol: float = 1e-10
 
     @staticmethod
     def paper() -> "SolveOptions":
@@ -369,8 +370,9 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     minimiser, Eq. A.1).  Armijo backtracking on phi with the paper's alpha;
     the first trial step is mu0/||d|| on the first iteration and
     t_prev (g_prev.d_prev) / (g.d) afterwards; a rejected trial moves to the
-    safeguarded quadratic-interpolation step.  A failed search restarts along
-    -g once; a second failure ends the solve."""
+    safeguarded quadratic-interpolation step, and a step shorter than xtol
+    (in units of w) counts as a failed search.  A failed search restarts
+    along -g once; a second failure ends the solve."""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
     rep = SolveReport()
@@ -398,7 +400,10 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             restart = True
         t = o.mu0 / float(np.linalg.norm(d)) if first else t_prev * gd_prev / gd
         accepted = False
+        dn = float(np.linalg.norm(d))
         for _ in range(o.max_backtracks):
+            if t * dn < o.xtol:                        # step too short to matter
+                break
             w_try = w + t * d
             phi_t, a_t, b_t, r_t = prob.objective(w_try)
             rep.n_fevals += 1

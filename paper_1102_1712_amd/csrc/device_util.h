@@ -1,0 +1,119 @@
+// Device helpers: wave64 / block reductions in double and the
+// "last block finishes" grid reduction (fixed order, hence deterministic).
+#pragma once
+
+#include "internal.h"
+
+namespace pcas {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ double load_agent(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_agent(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sums vals[0..NS) over the block (any multiple of 64 threads up to 1024),
+// publishes the block's partials, and lets the last block to arrive reduce
+// all partials in block order into out[j] * scale.  The counter must be
+// zero on entry; the last block resets it.  Every thread of every block
+// must call this exactly once.
+template <int NS>
+__device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ partials,
+                            uint32_t *counter, double *__restrict__ out, int bid, int nblocks,
+                            double scale) {
+    static_assert(NS <= RED_SLOTS, "too many reduction slots");
+    __shared__ double sm[NS][16];
+    __shared__ int is_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        double v = wave_sum(vals[j]);
+        if (lane == 0) sm[j][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            double t = 0.0;
+            for (int w = 0; w < nwaves; ++w) t += sm[j][w];
+            store_agent(&partials[(int64_t)bid * RED_SLOTS + j], t);
+        }
+        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (prev == (uint32_t)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double acc[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) acc[j] += load_agent(&partials[(int64_t)b * RED_SLOTS + j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        double v = wave_sum(acc[j]);
+        if (lane == 0) sm[j][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            double t = 0.0;
+            for (int w = 0; w < nwaves; ++w) t += sm[j][w];
+            store_agent(&out[j], scale * t);
+        }
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Split a displacement x (mm) into whole voxels and the fractional part
+// (Eq. A.5's integer and fractional parts): d = x / spacing rounded once,
+// l = floor(d), z = d - l, exactly.  Contraction is off here so that z is the
+// fraction of the rounded d (in [0, 1)) and an integer d gives z = 0.
+template <typename T>
+__device__ __forceinline__ void split_disp(T x, T inv_s, int &l, T &z) {
+#pragma clang fp contract(off)
+    const T d = x * inv_s;
+    const T fl = floor(d);
+    l = (int)fl;
+    z = d - fl;
+}
+
+// Position of sample s of a ray in voxel-index units, clamped to the grid,
+// split into the lower corner l (so that l + 1 is still inside) and the
+// fractional part z.  drr_forward and drr_adjoint both call this, so a
+// sample's corners and weights are bit-identical in the two kernels.
+template <typename T>
+__device__ __forceinline__ void sample_cell(const T (&e)[3], const T (&d)[3], int s, int n0, int n1,
+                                            int n2, int (&l)[3], T (&z)[3]) {
+    const T sh = (T)s + (T)0.5;
+    const int nn[3] = {n0, n1, n2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T q = fma_t(sh, d[c], e[c]);
+        q = q < (T)0 ? (T)0 : q;
+        const T top = (T)(nn[c] - 1);
+        q = q > top ? top : q;
+        int li = (int)q;
+        li = li > nn[c] - 2 ? nn[c] - 2 : li;
+        l[c] = li;
+        z[c] = q - (T)li;
+    }
+}
+
+}  // namespace pcas

@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP translation units of libpcasolve.
+// Kernels are written for gfx950 (CDNA4): wave64, LDS-staged reductions,
+// double accumulation for every reduction, no global atomics on data.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pcasolve.h"
+
+namespace pcas {
+
+// Launch-time volume description (index space).  inv_s is 1/spacing.
+struct VolDims {
+    int n0, n1, n2;       // n1, n2, n3 of the API (i fastest)
+    double inv_s[3];
+    double spacing[3];
+    double origin[3];
+};
+
+// Cone-beam frame of one projection, precomputed on the host in double.
+struct Frame {
+    double src[3];        // source position (mm)
+    double det[3];        // detector centre (mm)
+    double eu[3], ev[3];  // detector axes
+    double en[3];         // unit vector source -> detector centre
+    double sid;
+    double pitch_u, pitch_v, offset_u, offset_v, step;
+    int nu, nv;
+};
+
+// Per-ray record: entry point and per-sample step in voxel-index units,
+// sample width dt (mm), sample count n.  Sample s sits at e + (s + 1/2) d.
+template <typename T> struct RayRec;
+template <> struct alignas(16) RayRec<float> {
+    float e[3];
+    float d[3];
+    float dt;
+    int32_t n;
+};
+template <> struct alignas(16) RayRec<double> {
+    double e[3];
+    double d[3];
+    double dt;
+    int32_t n;
+    int32_t pad_;
+};
+static_assert(sizeof(RayRec<float>) == 32, "RayRec<float> layout");
+static_assert(sizeof(RayRec<double>) == 64, "RayRec<double> layout");
+
+// Adjoint brick (voxels owned by one wavefront).
+constexpr int BRICK_X = 16, BRICK_Y = 16, BRICK_Z = 8;
+// Forward tile: a 256-thread block covers 16 x 16 pixels, each wave an 8 x 8 quadrant.
+constexpr int TILE_U = 16, TILE_V = 16;
+// Reductions: partial-sum slots per block.
+constexpr int RED_SLOTS = 8;
+constexpr int GRAD_BLOCKS_MAX = 2048;
+
+// Coefficients passed by value to kernels.
+struct WVec {
+    double w[PCAS_MAX_K];
+};
+
+// Spread consecutive workgroup ids (dispatched round-robin over the 8 XCDs)
+// so that each XCD works on a contiguous range of tiles and its L2 sees a
+// compact footprint.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+    const int per = nblocks >> 3;
+    const int full = per << 3;
+    if (bid >= full) return bid;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+// ---- launchers (return the HIP error of the launch) ----------------------
+hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s);
+
+hipError_t launch_ray_table(pcas_dtype dt, const VolDims &v, const Frame &fr, void *rays,
+                            hipStream_t s);
+
+hipError_t launch_pca_dvf(pcas_dtype dt, int64_t N, int K, const void *mean, const void *U,
+                          const double *w, void *dvf, hipStream_t s);
+hipError_t launch_warp_trilinear(pcas_dtype dt, const VolDims &v, const void *f0, const void *dvf,
+                                 void *f, hipStream_t s);
+hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f0,
+                           const void *mean, const void *U, const double *w, void *f,
+                           hipStream_t s);
+
+// Forward projection.  If sums != nullptr also reduces (sum p, sum p*y,
+// sum p*p) into sums[0..2] (double) via per-block partials and a last-block
+// pass; partials needs drr_forward_blocks() * RED_SLOTS doubles, counter one
+// zeroed uint32 (left zeroed on exit).
+int drr_forward_blocks(int nu, int nv);
+hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, int nu, int nv, const void *rays,
+                              const void *f, void *p, const void *y, double *partials,
+                              uint32_t *counter, double *sums, hipStream_t s);
+
+// Back-projection.  If y != nullptr the residual r = p - a*y - b is formed
+// on the fly from p (passed as r_or_p); otherwise r_or_p is r.
+hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *rays,
+                              const void *r_or_p, const void *y, double a, double b, void *bp,
+                              hipStream_t s);
+
+int grad_w_blocks(int64_t N);
+hipError_t launch_grad_w(pcas_dtype dt, const VolDims &v, int K, const void *f0, const void *mean,
+                         const void *U, const double *w, const void *bp, double *partials,
+                         uint32_t *counter, double *g_out, hipStream_t s);
+
+// Sums over two length-M arrays: (sum a, sum a*b, sum a*a, sum b, sum b*b)
+// into out[0..4]; partials needs sums_blocks(M) * RED_SLOTS doubles.
+int sums_blocks(int64_t M);
+hipError_t launch_pair_sums(pcas_dtype dt, int64_t M, const void *a, const void *b,
+                            double *partials, uint32_t *counter, double *out, hipStream_t s);
+// How the residual pass obtains (a, b):
+//   FIT_COEF:  read a = src[0], b = src[1] (device)
+//   FIT_REFIT: Eq. A.1 from sum p = src[0], sum p*y = src[1] (device) and the
+//              host-known sum y, sum y^2 and pixel count (NaN if singular)
+//   FIT_FIXED: the values a, b given here
+enum { FIT_COEF = 0, FIT_REFIT = 1, FIT_FIXED = 2 };
+struct FitArgs {
+    int mode;
+    double a, b, sy, syy, m;
+};
+// r = p - a*y - b; out[0] = J = sum r^2, out[1] = a, out[2] = b.
+// r may be nullptr or alias p.
+hipError_t launch_residual(pcas_dtype dt, int64_t M, const void *p, const void *y,
+                           const FitArgs &fa, const double *src, void *r, double *partials,
+                           uint32_t *counter, double *out, hipStream_t s);
+// Intensity fit (Eq. A.1) from the sums produced by launch_pair_sums(p, y):
+// writes stats[0..1] = (a, b) (NaN if singular) -- one thread.
+hipError_t launch_fit_from_sums(int64_t M, int fit, const double *sums, double *stats,
+                                hipStream_t s);
+
+hipError_t launch_locate(pcas_dtype dt, const VolDims &v, int K, const void *mean, const void *U,
+                         const double *w, const double c0[3], double tol, int max_iter,
+                         double *out, hipStream_t s);
+
+}  // namespace pcas

@@ -1,0 +1,87 @@
+// a1: per-projection ray table, plus a small fill kernel.
+#include "device_util.h"
+
+namespace pcas {
+
+__global__ void k_fill_u32(uint32_t *p, int count, uint32_t value) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((count + 255) / 256), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+// One thread per detector pixel, all geometry in double with contraction
+// off, so the record is the correctly rounded evaluation of: pixel centre,
+// unit direction from the source, slab intersection with the box of voxel
+// centres, n = ceil(L / step), dt = L / n; stored as the entry point and the
+// per-sample step in voxel-index units.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ray_table(VolDims v, Frame fr, RayRec<T> *__restrict__ rays) {
+#pragma clang fp contract(off)
+    const int M = fr.nu * fr.nv;
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= M) return;
+    const int iu = pix % fr.nu, iv = pix / fr.nu;
+    const double u = (iu - 0.5 * (fr.nu - 1)) * fr.pitch_u + fr.offset_u;
+    const double w = (iv - 0.5 * (fr.nv - 1)) * fr.pitch_v + fr.offset_v;
+    double dir[3], len2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double P = fr.det[c] + u * fr.eu[c] + w * fr.ev[c];
+        dir[c] = P - fr.src[c];
+        len2 += dir[c] * dir[c];
+    }
+    const double len = sqrt(len2);
+    for (int c = 0; c < 3; ++c) dir[c] = dir[c] / len;
+    const int nn[3] = {v.n0, v.n1, v.n2};
+    double t0 = -INFINITY, t1 = INFINITY;
+    bool missed = false;
+    for (int c = 0; c < 3; ++c) {
+        const double lo = v.origin[c];
+        const double hi = v.origin[c] + (nn[c] - 1) * v.spacing[c];
+        if (dir[c] == 0.0) {
+            if (fr.src[c] < lo || fr.src[c] > hi) missed = true;
+            continue;
+        }
+        double ta = (lo - fr.src[c]) / dir[c];
+        double tb = (hi - fr.src[c]) / dir[c];
+        if (ta > tb) { double t = ta; ta = tb; tb = t; }
+        t0 = ta > t0 ? ta : t0;
+        t1 = tb < t1 ? tb : t1;
+    }
+    const double L = t1 - t0;
+    RayRec<T> r;
+    if (missed || !(L > 0.0)) {
+        for (int c = 0; c < 3; ++c) { r.e[c] = (T)0; r.d[c] = (T)0; }
+        r.dt = (T)0;
+        r.n = 0;
+    } else {
+        const double nd = ceil(L / fr.step);
+        const double dt = L / nd;
+        for (int c = 0; c < 3; ++c) {
+            const double X0 = fr.src[c] + t0 * dir[c];
+            r.e[c] = (T)((X0 - v.origin[c]) / v.spacing[c]);
+            r.d[c] = (T)(dt * dir[c] / v.spacing[c]);
+        }
+        r.dt = (T)dt;
+        r.n = (int32_t)nd;
+    }
+    if constexpr (sizeof(T) == 8) r.pad_ = 0;
+    rays[pix] = r;
+}
+
+hipError_t launch_ray_table(pcas_dtype dt, const VolDims &v, const Frame &fr, void *rays,
+                            hipStream_t s) {
+    const int M = fr.nu * fr.nv;
+    dim3 grid((M + 255) / 256), block(256);
+    if (dt == PCAS_F32)
+        hipLaunchKernelGGL(k_ray_table<float>, grid, block, 0, s, v, fr, (RayRec<float> *)rays);
+    else
+        hipLaunchKernelGGL(k_ray_table<double>, grid, block, 0, s, v, fr, (RayRec<double> *)rays);
+    return hipGetLastError();
+}
+
+}  // namespace pcas

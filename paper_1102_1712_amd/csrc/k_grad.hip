@@ -1,0 +1,127 @@
+// a7: the Jacobian chain of the Appendix, g = 2 U^T (df/dx) bp.
+//
+// A voxel stream: each block owns a contiguous run of voxels (lanes step by
+// 256 inside it, so every load is coalesced), recomputes x = xbar + U w and
+// the diagonal Jacobian of Eq. A.8 from the eight f0 neighbours of the
+// pulled-back position, and accumulates bp * sum_c U_kc * df/dx_c in double.
+// Voxels with bp = 0 contribute nothing and are skipped without touching
+// the mode streams.  Block partials are reduced in block order by the last
+// block to finish, so g is bit-for-bit reproducible.
+#include "device_util.h"
+
+namespace pcas {
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_grad_w(VolDims vd, const T *__restrict__ f0,
+                                                const T *__restrict__ mean,
+                                                const T *__restrict__ U, WVec w,
+                                                const T *__restrict__ bp,
+                                                double *__restrict__ partials, uint32_t *counter,
+                                                double *__restrict__ g_out) {
+    const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const int nb = gridDim.x;
+    const int bid = xcd_remap(blockIdx.x, nb);
+    int64_t per = (N + nb - 1) / nb;
+    per = (per + 255) & ~(int64_t)255;
+    const int64_t v_begin = (int64_t)bid * per;
+    const int64_t v_end = min(N, v_begin + per);
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    T wk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wk[k] = (T)w.w[k];
+    const T is0 = (T)vd.inv_s[0], is1 = (T)vd.inv_s[1], is2 = (T)vd.inv_s[2];
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+
+    for (int64_t v = v_begin + threadIdx.x; v < v_end; v += 256) {
+        const T bpv = bp[v];
+        if (bpv == (T)0) continue;
+        const int i = (int)(v % n0);
+        const int j = (int)((v / n0) % n1);
+        const int k = (int)(v / s2);
+        T u[K][3];
+        T x[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[c] = mean ? mean[c * N + v] : (T)0;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                u[kk][c] = U[(int64_t)(kk * 3 + c) * N + v];
+                x[c] = fma_t(wk[kk], u[kk][c], x[c]);
+            }
+        }
+        int o0, o1, o2;
+        T z1, z2, z3;                                           // the Appendix's z_1..z_3
+        split_disp(x[0], is0, o0, z1);
+        split_disp(x[1], is1, o1, z2);
+        split_disp(x[2], is2, o2, z3);
+        const int l = i + o0, m = j + o1, n = k + o2;
+        // neighbour values with zero extension
+        const bool vl = l >= 0 && l < n0, vl1 = l + 1 >= 0 && l + 1 < n0;
+        const bool vm = m >= 0 && m < n1, vm1 = m + 1 >= 0 && m + 1 < n1;
+        const bool vn = n >= 0 && n < n2, vn1 = n + 1 >= 0 && n + 1 < n2;
+        if (!((vl || vl1) && (vm || vm1) && (vn || vn1))) continue;
+        const int cl = min(max(l, 0), n0 - 1), cl1 = min(max(l + 1, 0), n0 - 1);
+        const int cm = min(max(m, 0), n1 - 1), cm1 = min(max(m + 1, 0), n1 - 1);
+        const int cn = min(max(n, 0), n2 - 1), cn1 = min(max(n + 1, 0), n2 - 1);
+        auto F = [&](int ii, int jj, int kk, bool ok) -> T {
+            return ok ? f0[ii + s1 * jj + s2 * kk] : (T)0;
+        };
+        const T f000 = F(cl, cm, cn, vl && vm && vn), f100 = F(cl1, cm, cn, vl1 && vm && vn);
+        const T f010 = F(cl, cm1, cn, vl && vm1 && vn), f110 = F(cl1, cm1, cn, vl1 && vm1 && vn);
+        const T f001 = F(cl, cm, cn1, vl && vm && vn1), f101 = F(cl1, cm, cn1, vl1 && vm && vn1);
+        const T f011 = F(cl, cm1, cn1, vl && vm1 && vn1), f111 = F(cl1, cm1, cn1, vl1 && vm1 && vn1);
+        // Eq. A.8 and its analogues (index units), then per mm
+        const T g1 = ((f100 - f000) * ((T)1 - z2) + (f110 - f010) * z2) * ((T)1 - z3) +
+                     ((f101 - f001) * ((T)1 - z2) + (f111 - f011) * z2) * z3;
+        const T g2 = ((f010 - f000) * ((T)1 - z1) + (f110 - f100) * z1) * ((T)1 - z3) +
+                     ((f011 - f001) * ((T)1 - z1) + (f111 - f101) * z1) * z3;
+        const T g3 = ((f001 - f000) * ((T)1 - z1) + (f101 - f100) * z1) * ((T)1 - z2) +
+                     ((f011 - f010) * ((T)1 - z1) + (f111 - f110) * z1) * z2;
+        const T j0 = g1 * is0 * bpv, j1 = g2 * is1 * bpv, j2 = g3 * is2 * bpv;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+            acc[kk] += (double)fma_t(u[kk][0], j0, fma_t(u[kk][1], j1, u[kk][2] * j2));
+    }
+    grid_reduce<K>(acc, partials, counter, g_out, bid, nb, 2.0);
+}
+
+int grad_w_blocks(int64_t N) {
+    int64_t b = (N + 255) / 256;
+    return (int)(b < GRAD_BLOCKS_MAX ? b : GRAD_BLOCKS_MAX);
+}
+
+namespace {
+template <typename T, int K>
+hipError_t grad_k(const VolDims &v, const void *f0, const void *mean, const void *U,
+                  const WVec &w, const void *bp, double *partials, uint32_t *counter,
+                  double *g_out, hipStream_t s) {
+    const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
+    hipLaunchKernelGGL((k_grad_w<T, K>), dim3(grad_w_blocks(N)), dim3(256), 0, s, v,
+                       (const T *)f0, (const T *)mean, (const T *)U, w, (const T *)bp, partials,
+                       counter, g_out);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_grad_w(pcas_dtype dt, const VolDims &v, int K, const void *f0, const void *mean,
+                         const void *U, const double *w, const void *bp, double *partials,
+                         uint32_t *counter, double *g_out, hipStream_t s) {
+    WVec wv{};
+    for (int k = 0; k < K; ++k) wv.w[k] = w[k];
+#define G(TT, KK) \
+    case KK: return grad_k<TT, KK>(v, f0, mean, U, wv, bp, partials, counter, g_out, s)
+    if (dt == PCAS_F32) {
+        switch (K) { G(float, 1); G(float, 2); G(float, 3); G(float, 4);
+                     G(float, 5); G(float, 6); G(float, 7); G(float, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+    switch (K) { G(double, 1); G(double, 2); G(double, 3); G(double, 4);
+                 G(double, 5); G(double, 6); G(double, 7); G(double, 8);
+                 default: return hipErrorInvalidValue; }
+#undef G
+}
+
+}  // namespace pcas

@@ -1,0 +1,116 @@
+// a5: sums for the intensity fit of Eq. A.1 and the objective of Eq. 2.
+// Grid-stride streams over the detector with double accumulation and the
+// fixed-order last-block reduction.
+#include "device_util.h"
+
+namespace pcas {
+
+constexpr int SUMS_BLOCKS_MAX = 512;
+
+int sums_blocks(int64_t M) {
+    int64_t b = (M + 255) / 256;
+    return (int)(b < SUMS_BLOCKS_MAX ? (b > 0 ? b : 1) : SUMS_BLOCKS_MAX);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_sums(int64_t M, const T *__restrict__ a,
+                                                   const T *__restrict__ b,
+                                                   double *__restrict__ partials,
+                                                   uint32_t *counter, double *__restrict__ out) {
+    const int nb = gridDim.x;
+    const int bid = blockIdx.x;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = (int64_t)bid * 256 + threadIdx.x; t < M; t += (int64_t)nb * 256) {
+        const double av = (double)a[t], bv = (double)b[t];
+        s[0] += av;
+        s[1] += av * bv;
+        s[2] += av * av;
+        s[3] += bv;
+        s[4] += bv * bv;
+    }
+    grid_reduce<5>(s, partials, counter, out, bid, nb, 1.0);
+}
+
+// (a, b) of Eq. A.1 by the 2 x 2 normal equations (Y^T Y)(a, b)^T = Y^T p
+// with Y = [y, 1]; NaN when Y^T Y is singular.
+__device__ __forceinline__ void fit_normal_equations(double sp, double spy, double sy, double syy,
+                                                     double m, double *a, double *b) {
+    const double det = syy * m - sy * sy;
+    if (!(fabs(det) > 1e-12 * syy * m)) {
+        *a = *b = NAN;
+        return;
+    }
+    *a = (m * spy - sy * sp) / det;
+    *b = (syy * sp - sy * spy) / det;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(int64_t M, const T *__restrict__ p,
+                                                  const T *__restrict__ y, FitArgs fa,
+                                                  const double *__restrict__ src, T *r,
+                                                  double *__restrict__ partials, uint32_t *counter,
+                                                  double *__restrict__ out) {
+    const int nb = gridDim.x;
+    const int bid = blockIdx.x;
+    double A = fa.a, B = fa.b;
+    if (fa.mode == FIT_COEF) {
+        A = src[0];
+        B = src[1];
+    } else if (fa.mode == FIT_REFIT) {
+        fit_normal_equations(src[0], src[1], fa.sy, fa.syy, fa.m, &A, &B);
+    }
+    if (bid == 0 && threadIdx.x == 0) {
+        out[1] = A;
+        out[2] = B;
+    }
+    double s[1] = {0.0};
+    for (int64_t t = (int64_t)bid * 256 + threadIdx.x; t < M; t += (int64_t)nb * 256) {
+        const double rv = (double)p[t] - A * (double)y[t] - B;
+        if (r) r[t] = (T)rv;
+        s[0] += rv * rv;
+    }
+    grid_reduce<1>(s, partials, counter, out, bid, nb, 1.0);
+}
+
+// (a, b) of Eq. A.1 from (sum p, sum p y, sum p p, sum y, sum y y).
+__global__ void k_fit_from_sums(int64_t M, int fit, const double *__restrict__ sums,
+                                double *__restrict__ stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 1.0, b = 0.0;
+    if (fit) fit_normal_equations(sums[0], sums[1], sums[3], sums[4], (double)M, &a, &b);
+    stats[0] = a;
+    stats[1] = b;
+}
+
+hipError_t launch_pair_sums(pcas_dtype dt, int64_t M, const void *a, const void *b,
+                            double *partials, uint32_t *counter, double *out, hipStream_t s) {
+    const int nb = sums_blocks(M);
+    if (dt == PCAS_F32)
+        hipLaunchKernelGGL(k_pair_sums<float>, dim3(nb), dim3(256), 0, s, M, (const float *)a,
+                           (const float *)b, partials, counter, out);
+    else
+        hipLaunchKernelGGL(k_pair_sums<double>, dim3(nb), dim3(256), 0, s, M, (const double *)a,
+                           (const double *)b, partials, counter, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(pcas_dtype dt, int64_t M, const void *p, const void *y,
+                           const FitArgs &fa, const double *src, void *r, double *partials,
+                           uint32_t *counter, double *out, hipStream_t s) {
+    const int nb = sums_blocks(M);
+    if (dt == PCAS_F32)
+        hipLaunchKernelGGL(k_residual<float>, dim3(nb), dim3(256), 0, s, M, (const float *)p,
+                           (const float *)y, fa, src, (float *)r, partials, counter, out);
+    else
+        hipLaunchKernelGGL(k_residual<double>, dim3(nb), dim3(256), 0, s, M, (const double *)p,
+                           (const double *)y, fa, src, (double *)r, partials, counter, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_from_sums(int64_t M, int fit, const double *sums, double *stats,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_fit_from_sums, dim3(1), dim3(64), 0, s, M, fit, sums, stats);
+    return hipGetLastError();
+}
+
+}  // namespace pcas

@@ -1,0 +1,184 @@
+// a2 + a3: deformation field of Eq. 1 and the trilinear pull-back warp of
+// Eqs. A.3 / A.5.  One lane per voxel, i fastest, so the mean / mode /
+// output streams are fully coalesced; the eight f0 neighbours of a voxel lie
+// within a few voxels of it and are served by L2.
+#include "device_util.h"
+
+namespace pcas {
+
+// Gather the trilinear value of vol at voxel (i, j, k) displaced by the
+// field value (x0, x1, x2) mm, zero outside the grid.  The displacement is
+// split into whole voxels + fraction before the voxel index is added, which
+// keeps the fraction as accurate as the (small) displacement itself.
+template <typename T>
+__device__ __forceinline__ T warp_gather(const T *__restrict__ f0, int n0, int n1, int n2, int i,
+                                         int j, int k, T x0, T x1, T x2, T is0, T is1, T is2) {
+    int o0, o1, o2;
+    T z0, z1, z2;
+    split_disp(x0, is0, o0, z0);
+    split_disp(x1, is1, o1, z1);
+    split_disp(x2, is2, o2, z2);
+    const int l0 = i + o0, l1 = j + o1, l2 = k + o2;
+    // per-axis weights, zeroed for neighbours outside the grid
+    const T a0 = (l0 >= 0 && l0 < n0) ? (T)1 - z0 : (T)0;
+    const T b0 = (l0 + 1 >= 0 && l0 + 1 < n0) ? z0 : (T)0;
+    const T a1 = (l1 >= 0 && l1 < n1) ? (T)1 - z1 : (T)0;
+    const T b1 = (l1 + 1 >= 0 && l1 + 1 < n1) ? z1 : (T)0;
+    const T a2 = (l2 >= 0 && l2 < n2) ? (T)1 - z2 : (T)0;
+    const T b2 = (l2 + 1 >= 0 && l2 + 1 < n2) ? z2 : (T)0;
+    if ((a0 == (T)0 && b0 == (T)0) || (a1 == (T)0 && b1 == (T)0) || (a2 == (T)0 && b2 == (T)0))
+        return (T)0;
+    // clamped indices (a clamped neighbour always carries weight 0)
+    const int c0a = min(max(l0, 0), n0 - 1), c0b = min(max(l0 + 1, 0), n0 - 1);
+    const int c1a = min(max(l1, 0), n1 - 1), c1b = min(max(l1 + 1, 0), n1 - 1);
+    const int c2a = min(max(l2, 0), n2 - 1), c2b = min(max(l2 + 1, 0), n2 - 1);
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    const T *pa = f0 + c2a * s2, *pb = f0 + c2b * s2;
+    const T v000 = pa[c1a * s1 + c0a], v100 = pa[c1a * s1 + c0b];
+    const T v010 = pa[c1b * s1 + c0a], v110 = pa[c1b * s1 + c0b];
+    const T v001 = pb[c1a * s1 + c0a], v101 = pb[c1a * s1 + c0b];
+    const T v011 = pb[c1b * s1 + c0a], v111 = pb[c1b * s1 + c0b];
+    const T x00 = a0 * v000 + b0 * v100, x10 = a0 * v010 + b0 * v110;
+    const T x01 = a0 * v001 + b0 * v101, x11 = a0 * v011 + b0 * v111;
+    const T y0 = a1 * x00 + b1 * x10, y1 = a1 * x01 + b1 * x11;
+    return a2 * y0 + b2 * y1;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_pca_dvf(int64_t N, const T *__restrict__ mean,
+                                                 const T *__restrict__ U, WVec w,
+                                                 T *__restrict__ dvf) {
+    const int64_t nb = gridDim.x;
+    const int64_t b = xcd_remap(blockIdx.x, (int)nb);
+    const int64_t v = b * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    T wk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wk[k] = (T)w.w[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T x = mean ? mean[c * N + v] : (T)0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) x = fma_t(wk[k], U[(int64_t)(k * 3 + c) * N + v], x);
+        dvf[c * N + v] = x;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_warp_trilinear(VolDims vd, const T *__restrict__ f0,
+                                                        const T *__restrict__ dvf,
+                                                        T *__restrict__ f) {
+    const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t v = b * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const int i = (int)(v % vd.n0);
+    const int j = (int)((v / vd.n0) % vd.n1);
+    const int k = (int)(v / ((int64_t)vd.n0 * vd.n1));
+    f[v] = warp_gather(f0, vd.n0, vd.n1, vd.n2, i, j, k, dvf[v], dvf[N + v], dvf[2 * N + v],
+                       (T)vd.inv_s[0], (T)vd.inv_s[1], (T)vd.inv_s[2]);
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restrict__ f0,
+                                                  const T *__restrict__ mean,
+                                                  const T *__restrict__ U, WVec w,
+                                                  T *__restrict__ f) {
+    const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t v = b * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const int i = (int)(v % vd.n0);
+    const int j = (int)((v / vd.n0) % vd.n1);
+    const int k = (int)(v / ((int64_t)vd.n0 * vd.n1));
+    T x[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = mean ? mean[c * N + v] : (T)0;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+            x[c] = fma_t((T)w.w[kk], U[(int64_t)(kk * 3 + c) * N + v], x[c]);
+    }
+    f[v] = warp_gather(f0, vd.n0, vd.n1, vd.n2, i, j, k, x[0], x[1], x[2], (T)vd.inv_s[0],
+                       (T)vd.inv_s[1], (T)vd.inv_s[2]);
+}
+
+namespace {
+template <typename T, int K>
+hipError_t pca_dvf_k(int64_t N, const void *mean, const void *U, const WVec &w, void *dvf,
+                     hipStream_t s) {
+    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    hipLaunchKernelGGL((k_pca_dvf<T, K>), grid, block, 0, s, N, (const T *)mean, (const T *)U, w,
+                       (T *)dvf);
+    return hipGetLastError();
+}
+template <typename T, int K>
+hipError_t warp_pca_k(const VolDims &v, const void *f0, const void *mean, const void *U,
+                      const WVec &w, void *f, hipStream_t s) {
+    const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
+    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    hipLaunchKernelGGL((k_warp_pca<T, K>), grid, block, 0, s, v, (const T *)f0, (const T *)mean,
+                       (const T *)U, w, (T *)f);
+    return hipGetLastError();
+}
+WVec make_w(const double *w, int K) {
+    WVec r{};
+    for (int k = 0; k < K; ++k) r.w[k] = w[k];
+    return r;
+}
+}  // namespace
+
+#define PCAS_K_SWITCH(K, CALL)         \
+    switch (K) {                       \
+    case 1: return CALL(1);            \
+    case 2: return CALL(2);            \
+    case 3: return CALL(3);            \
+    case 4: return CALL(4);            \
+    case 5: return CALL(5);            \
+    case 6: return CALL(6);            \
+    case 7: return CALL(7);            \
+    case 8: return CALL(8);            \
+    default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_pca_dvf(pcas_dtype dt, int64_t N, int K, const void *mean, const void *U,
+                          const double *w, void *dvf, hipStream_t s) {
+    const WVec wv = make_w(w, K);
+    if (dt == PCAS_F32) {
+#define CALL(KK) pca_dvf_k<float, KK>(N, mean, U, wv, dvf, s)
+        PCAS_K_SWITCH(K, CALL)
+#undef CALL
+    }
+#define CALL(KK) pca_dvf_k<double, KK>(N, mean, U, wv, dvf, s)
+    PCAS_K_SWITCH(K, CALL)
+#undef CALL
+}
+
+hipError_t launch_warp_trilinear(pcas_dtype dt, const VolDims &v, const void *f0, const void *dvf,
+                                 void *f, hipStream_t s) {
+    const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
+    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    if (dt == PCAS_F32)
+        hipLaunchKernelGGL(k_warp_trilinear<float>, grid, block, 0, s, v, (const float *)f0,
+                           (const float *)dvf, (float *)f);
+    else
+        hipLaunchKernelGGL(k_warp_trilinear<double>, grid, block, 0, s, v, (const double *)f0,
+                           (const double *)dvf, (double *)f);
+    return hipGetLastError();
+}
+
+hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f0,
+                           const void *mean, const void *U, const double *w, void *f,
+                           hipStream_t s) {
+    const WVec wv = make_w(w, K);
+    if (dt == PCAS_F32) {
+#define CALL(KK) warp_pca_k<float, KK>(v, f0, mean, U, wv, f, s)
+        PCAS_K_SWITCH(K, CALL)
+#undef CALL
+    }
+#define CALL(KK) warp_pca_k<double, KK>(v, f0, mean, U, wv, f, s)
+    PCAS_K_SWITCH(K, CALL)
+#undef CALL
+}
+
+}  // namespace pcas

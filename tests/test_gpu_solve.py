@@ -1,0 +1,122 @@
+"""Solve parity: solve_projection through the C ABI against the oracle's
+solver on the same inputs and the same w0.  The objective is non-convex in
+general and iterate sequences may part ways on rounding, so converged
+minimisers are compared (1e-4 relative in w, 0.05 mm in the tumour
+position)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1102_1712_amd import binding as B
+from paper_1102_1712_amd import synth
+
+from gpu_common import Dev, measured, say, to_dev, to_np, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_or_skip()
+
+
+def _gpu_solve(d, y, opts):
+    c = d.case
+    return B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), np.zeros(c.K), opts)
+
+
+def _oracle_problem(c, y, fit=True):
+    return O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y, fit_intensity=fit)
+
+
+def test_tiny_cg_matches_oracle(torch):
+    """64^3 FP64, 128x128 detector, 1% noise, CG from w0 = 0 (the tiny workload)."""
+    c = synth.tiny()
+    d = Dev(c)
+    y = measured(c)
+    say("tiny CG solve")
+    opts = B.default_opts(locate=1, c0_mm=tuple(c.tumour_c0))
+    w, rep = _gpu_solve(d, y, opts)
+    w_o, rep_o = O.solve_cg(_oracle_problem(c, y), np.zeros(c.K))
+    say("gpu", w, rep)
+    say("oracle", w_o, rep_o.status, rep_o.iters, rep_o.J)
+    # both sides stop at a stationary point: the gradient test or a line
+    # search that can no longer decrease J (rounding floor)
+    assert rep["status"] in ("converged", "line_search")
+    assert rep["gnorm"] <= 1e-6 * rep["gnorm0"]
+    assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)
+    assert abs(rep["J"] - rep_o.J) <= 1e-8 * rep_o.J
+    loc_o, _ = O.locate(c.vol, c.mean, c.U, w_o, c.tumour_c0)
+    assert np.linalg.norm(np.array(rep["tumour_mm"]) - loc_o) <= 0.05
+    assert rep["locate_iters"] > 0
+
+
+def test_tiny_paper_mode_matches_oracle(torch):
+    """The Appendix algorithm (10 iterations, Armijo on the normalised
+    gradient) in FP64: same accepted steps as the oracle."""
+    c = synth.tiny()
+    d = Dev(c)
+    y = measured(c)
+    say("tiny paper-mode solve")
+    w, rep = _gpu_solve(d, y, B.paper_opts())
+    w_o, rep_o = O.solve_paper(_oracle_problem(c, y), np.zeros(c.K))
+    say("gpu", w, rep)
+    say("oracle", w_o, rep_o.iters, rep_o.J)
+    assert rep["iters"] == rep_o.iters
+    assert np.linalg.norm(w - w_o) <= 1e-8 * np.linalg.norm(w_o)
+    assert abs(rep["J"] - rep_o.J) <= 1e-9 * rep_o.J
+
+
+def test_recovery32_noise_free(torch):
+    """Noise-free 32^3 FP64: the GPU solve recovers the planted w."""
+    c = synth.recovery32()
+    d = Dev(c)
+    y = measured(c)
+    say("recovery32 solve")
+    w, rep = _gpu_solve(d, y, B.default_opts())
+    say("gpu", w, rep)
+    assert np.linalg.norm(w - c.w_star) <= 1e-8 * np.linalg.norm(c.w_star)
+
+
+@pytest.mark.parametrize("fit", [True, False])
+def test_small_f32_cg_matches_oracle(torch, fit):
+    """Ragged anisotropic FP32 case: converged w within 1e-4 of the FP64 oracle."""
+    c = synth.small(dtype="f32", seed=6)
+    d = Dev(c)
+    y = measured(c)
+    say("small f32 solve fit=", fit)
+    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7)
+    w, rep = _gpu_solve(d, y, opts)
+    w_o, rep_o = O.solve_cg(_oracle_problem(c, y, fit), np.zeros(c.K))
+    say("gpu", w, rep)
+    say("oracle", w_o, rep_o.status, rep_o.iters)
+    assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)
+
+
+def test_k1_solve(torch):
+    """K = 1 (the physical-phantom setting of the paper)."""
+    c = synth.small(dtype="f64", seed=16, K=1)
+    d = Dev(c)
+    y = measured(c)
+    say("K=1 solve")
+    w, rep = _gpu_solve(d, y, B.default_opts())
+    w_o, _ = O.solve_cg(_oracle_problem(c, y), np.zeros(1))
+    assert abs(w[0] - w_o[0]) <= 1e-4 * max(abs(w_o[0]), 1.0)
+
+
+def test_solve_errors_from_data(torch):
+    c = synth.small(dtype="f64", seed=5)
+    d = Dev(c)
+    say("solve error paths")
+    y_const = np.full((c.proj.nv, c.proj.nu), 3.0)
+    with pytest.raises(B.PcasError) as e:
+        _gpu_solve(d, y_const, B.default_opts())
+    assert e.value.code == -3
+    y_nan = measured(c)
+    y_nan[3, 4] = np.nan
+    with pytest.raises(B.PcasError) as e:
+        _gpu_solve(d, y_nan, B.default_opts())
+    assert e.value.code == -4
+    # zero iterations: returns w0 and J0
+    w, rep = _gpu_solve(d, measured(c), B.default_opts(max_iter=0))
+    assert np.all(w == 0) and rep["iters"] == 0 and rep["status"] == "max_iter"
