@@ -103,6 +103,9 @@ typedef struct {
     double c0_mm[3];       /* tumour centre in the reference image (mm) */
     int32_t profile;       /* 1: time every kernel with HIP events (report.kernel_ms) */
     int32_t reserved;
+    double ftol_rel;       /* method 1: a rejected trial with |J_t - J| <= ftol_rel J ends the
+                              solve as converged (the change is below the objective's rounding
+                              noise); < 0 selects 1e-8 for PCAS_F32 and 0 for PCAS_F64 */
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches */

@@ -262,6 +262,7 @@ class SolveOptions:
     gtol_rel: float = 1e-9
     beta_lo: float = 0.1
     xtol: float = 1e-10
+    ftol_rel: float = 0.0
 
     @staticmethod
     def paper() -> "SolveOptions":
@@ -399,7 +400,7 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             gd = -gn * gn
             restart = True
         t = o.mu0 / float(np.linalg.norm(d)) if first else t_prev * gd_prev / gd
-        accepted = False
+        accepted = at_noise = False
         dn = float(np.linalg.norm(d))
         for _ in range(o.max_backtracks):
             if t * dn < o.xtol:                        # step too short to matter
@@ -410,8 +411,14 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             if phi_t <= phi + o.alpha * t * gd:
                 accepted = True
                 break
+            if abs(phi_t - phi) <= o.ftol_rel * phi:    # change below rounding noise
+                at_noise = True
+                break
             t_q = -gd * t * t / (2.0 * (phi_t - phi - gd * t))
             t = min(max(t_q, o.beta_lo * t), o.beta * t)
+        if at_noise:
+            rep.status = STOP_CONVERGED
+            break
         if not accepted:
             if restart:
                 rep.status = STOP_LINESEARCH

@@ -58,7 +58,8 @@ class Opts(ctypes.Structure):
                 ("beta_lo", ctypes.c_double), ("xtol", ctypes.c_double),
                 ("locate", ctypes.c_int32), ("locate_max_iter", ctypes.c_int32),
                 ("locate_tol", ctypes.c_double), ("c0_mm", ctypes.c_double * 3),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ftol_rel", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):

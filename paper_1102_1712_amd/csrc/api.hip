@@ -217,6 +217,7 @@ void pcas_default_opts(pcas_opts *o) {
     o->locate = 0;
     o->locate_max_iter = 100;
     o->locate_tol = 1e-9;
+    o->ftol_rel = -1.0;
 }
 
 void pcas_paper_opts(pcas_opts *o) {
@@ -572,6 +573,7 @@ int run_paper(Solver &S, const pcas_opts &o, double *w, pcas_report *rep) {
 // PR+ nonlinear CG on the reduced objective phi(w) = min_{a,b} J(w, a, b).
 int run_cg(Solver &S, const pcas_opts &o, double *w, pcas_report *rep) {
     const int K = S.K;
+    const double ftol = o.ftol_rel >= 0.0 ? o.ftol_rel : (S.dt == PCAS_F32 ? 1e-8 : 0.0);
     double phi, a, b, g[PCAS_MAX_K], d[PCAS_MAX_K], wt[PCAS_MAX_K], gnew[PCAS_MAX_K];
     int st = S.evaluate(w, nullptr, &phi, &a, &b);
     if (st) return st;
@@ -598,7 +600,7 @@ int run_cg(Solver &S, const pcas_opts &o, double *w, pcas_report *rep) {
         }
         const double dn = sqrt(dot(d, d, K));
         double t = first ? o.mu0 / dn : t_prev * gd_prev / gd;
-        bool accepted = false;
+        bool accepted = false, at_noise = false;
         double phi_t = 0.0, a_t = 0.0, b_t = 0.0;
         for (int bt = 0; bt < o.max_backtracks; ++bt) {
             if (t * dn < o.xtol) break;
@@ -608,9 +610,17 @@ int run_cg(Solver &S, const pcas_opts &o, double *w, pcas_report *rep) {
                 accepted = true;
                 break;
             }
+            if (fabs(phi_t - phi) <= ftol * phi) {   // below the objective's noise
+                at_noise = true;
+                break;
+            }
             const double tq = -gd * t * t / (2.0 * (phi_t - phi - gd * t));
             const double lo = o.beta_lo * t, hi = o.beta * t;
             t = tq < lo ? lo : (tq > hi ? hi : tq);
+        }
+        if (at_noise) {
+            rep->status = PCAS_STOP_CONVERGED;
+            break;
         }
         if (!accepted) {
             if (restart) {
