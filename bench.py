@@ -29,6 +29,44 @@ METRIC = "per-projection solve latency p50/p99 ms; DRR+adjoint Gsamples/s; % HBM
 HBM_PEAK_GBS = 8000.0
 # fp32 vector peak without packed math: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 VALU_F32_PEAK_TFLOPS = 78.6
+# Algorithmic flops per projection sample.  Forward: position e + sh d
+# (3 fma = 6), fractions (3), trilinear value as 7 lerps of 3 flops (21),
+# accumulation (1) = 31.  Back-projection: position (6), fractions (3),
+# corner weights (9), 8 weighted accumulations (16) = 34.
+FLOPS_PER_SAMPLE = {"drr_forward": 31.0, "drr_adjoint": 34.0}
+
+
+KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip", "warp_pca": "k_warp.hip",
+                  "grad_w": "k_grad.hip"}
+
+
+def kernel_digest(kernel: str) -> str:
+    """sha256[:16] of the kernel's source file and the shared device headers."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1102_1712_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCES[kernel], "device_util.h", "internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if that summary is for another workload or the kernel's source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 4 and parts[0] == kernel:
+                if parts[3] != kernel_digest(kernel):
+                    return None
+                return int(parts[1]) + int(parts[2])
+    return None
 
 
 def log(*a):
@@ -109,6 +147,100 @@ def cpu_baseline(case, n_fevals: int, n_grads: int, budget_s: float):
     }
 
 
+def kernels_mode(case, dev, dt, reps: int) -> int:
+    """Each hot kernel alone, `reps` times, plus a device copy of known size
+    (the calibration kernel for HBM byte counters).  Prints one JSON line of
+    HIP-event timings."""
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+
+    vol, proj = case.vol, case.proj
+    w = case.w_star * 0.5
+    f = B.warp_pca(vol, dev["f0"], dev["mean"], dev["U"], w)
+    p = B.drr_forward(vol, proj, dev["rays"], f)
+    r = (p - dev["y"]).contiguous()
+    bp = B.drr_adjoint(vol, proj, dev["rays"], r)
+    g = B.grad_w(vol, dev["f0"], dev["mean"], dev["U"], w, bp)
+    copy_bytes = 256 << 20
+    src = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    calls = {
+        "warp_pca": lambda: B.warp_pca(vol, dev["f0"], dev["mean"], dev["U"], w, out=f),
+        "drr_forward": lambda: B.drr_forward(vol, proj, dev["rays"], f, out=p),
+        "drr_adjoint": lambda: B.drr_adjoint(vol, proj, dev["rays"], r, out=bp),
+        "grad_w": lambda: B.grad_w(vol, dev["f0"], dev["mean"], dev["U"], w, bp, out=g),
+        "copy_256MiB": lambda: dst.copy_(src),
+    }
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[name] = {"median_ms": float(np.median(ts)), "min_ms": float(np.min(ts))}
+        log(f"{name}: median {out[name]['median_ms']:.4f} ms")
+    out["copy_256MiB"]["bytes"] = 2 * copy_bytes
+    print(json.dumps({"mode": "kernels", "workload": case.name, "reps": reps, "kernels": out}),
+          flush=True)
+    return 0
+
+
+def stream_mode(case, dev, dt, args) -> int:
+    """A sequence of projections over one rotation (15 frames/s): the planted
+    coefficients follow a seeded irregular breathing trace, each solve is
+    warm-started by the Eq. 3 prediction, and the located tumour is compared
+    with the planted trajectory's."""
+    import dataclasses
+
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+    from paper_1102_1712_amd import stream as S
+
+    n = args.frames
+    fps = 15.0
+    trace = S.breathing_trace(n + 60, fps, seed=args.seed + 100)
+    w_all = S.planted_trajectory(trace, case.K, seed=args.seed + 101, scale=0.05)
+    coeffs = S.fit_predictor(w_all[:60], L=2)
+    w_true = w_all[60:]
+    angles = case.proj.angle + np.arange(n) * (2 * np.pi / n)
+    gen = torch.Generator(device="cuda").manual_seed(args.seed + 102)
+    xtol = 1e-7 if case.dtype == "f32" else 1e-10
+    solver = S.StreamSolver(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"],
+                            opts=B.default_opts(xtol=xtol), c0_mm=case.tumour_c0,
+                            predictor=coeffs)
+    truth = np.zeros((n, 3))
+    loc = torch.empty(4, dtype=torch.float64, device="cuda")
+    for t in range(n):
+        pj = dataclasses.replace(case.proj, angle=float(angles[t]))
+        rays = B.ray_table(case.vol, pj, dt, out=dev["rays"])
+        f = B.warp_pca(case.vol, dev["f0"], dev["mean"], dev["U"], w_true[t])
+        p = B.drr_forward(case.vol, pj, rays, f)
+        rms = torch.sqrt(torch.mean(p.double() ** 2))
+        y = (p.double() + 0.01 * rms * torch.randn(p.shape, generator=gen, device="cuda",
+                                                    dtype=torch.float64)).to(dt).contiguous()
+        B.tumour_position(case.vol, dev["mean"], dev["U"], w_true[t], case.tumour_c0, out=loc)
+        truth[t] = loc.cpu().numpy()[:3]
+        solver.step(angles[t], y)
+        if (t + 1) % 100 == 0:
+            log(f"stream frame {t + 1}/{n}: p50 so far {np.median(solver.report.latencies()):.2f} ms")
+    located = np.array([fr.tumour_mm for fr in solver.report.frames])
+    summ = solver.report.summary()
+    errs = S.localisation_errors(located, truth)
+    print(json.dumps({"mode": "stream", "workload": case.name, "frames": n, "fps": fps,
+                      "init": "Eq. 3 prediction (L = 2, fitted on the first 60 frames)",
+                      **summ, **errs}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +252,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events")
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "stream"],
+                    help="solve: the contract line; kernels: each hot kernel alone plus a "
+                         "copy of known size (for profiler counters); stream: a warm-started "
+                         "projection sequence")
+    ap.add_argument("--frames", type=int, default=600)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -137,6 +274,10 @@ def main() -> int:
         return 2
     B.lib()
     case, dev, dt = build_inputs(args.workload, args.seed)
+    if args.mode == "kernels":
+        return kernels_mode(case, dev, dt, max(args.steps, 1))
+    if args.mode == "stream":
+        return stream_mode(case, dev, dt, args)
     S = samples_per_drr(dev["rays"], case.dtype)
     ws = torch.empty(B.solve_projection_workspace(case.vol, case.proj, case.K, dt),
                      dtype=torch.uint8, device="cuda")
@@ -193,20 +334,22 @@ def main() -> int:
             d["Gsamples_s"] = S / (a * 1e-3) / 1e9
             d["effective_GBs"] = 8 * es * S / (a * 1e-3) / 1e9
         kernel_stats[k] = d
-    dominant = max((k for k in kms if kn.get(k)), key=lambda k: kms[k]) if kms else None
+    measured = [k for k in kms if kn.get(k)]
+    dominant = max(measured, key=lambda k: kms[k]) if measured else None
 
     roofline = None
+    wl = "clinical" if args.workload == "clinical" else args.workload
+    traffic = measured_traffic(dominant, wl) if dominant else None
     if dominant in alg_bytes and avg.get(dominant):
         if dominant in ("warp_pca", "grad_w"):
             ach = alg_bytes[dominant] / (avg[dominant] * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": dominant}
+                        "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant}
         else:
-            # gather / VALU bound: 8 corners x (1 fma-weight + 1 fma-accumulate)
-            # plus 3 position fma = 2*(16+3) = 38 flop per sample
-            ach = 38.0 * S / (avg[dominant] * 1e-3) / 1e12
+            # gather / VALU bound: algorithmic flops per projection sample
+            ach = FLOPS_PER_SAMPLE[dominant] * S / (avg[dominant] * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": ach, "peak": VALU_F32_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": None,
+                        "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": traffic,
                         "kernel": dominant}
 
     cpu = None

@@ -23,7 +23,8 @@
  *   - `dtype` selects the element type of every floating-point device array
  *     of the call (all of them share it): PCAS_F32 (float) or PCAS_F64
  *     (double).  Reductions always accumulate in double.
- *   - Every argument is validated on the host before the first HIP call;
+ *   - Every argument is validated on the host before the first HIP call
+ *     (a volume must be smaller than 2 GiB: kernels use 32-bit offsets);
  *     an invalid call returns a negative status and touches no memory.
  *
  * Layouts (0-based versions of the Appendix's 1-based (i, j, k)):

@@ -45,6 +45,11 @@ int check_vol(const pcas_vol *v) {
 }
 
 int64_t nvox_of(const pcas_vol *v) { return (int64_t)v->n[0] * v->n[1] * v->n[2]; }
+
+// Kernels address a volume with 32-bit byte offsets: it must stay below 2 GiB.
+int check_vol_bytes(const pcas_vol *v, pcas_dtype dt) {
+    return nvox_of(v) * (int64_t)esize(dt) < ((int64_t)1 << 31) ? PCAS_OK : PCAS_EINVAL;
+}
 int64_t npix_of(const pcas_proj *p) { return (int64_t)p->nu * p->nv; }
 
 int check_proj(const pcas_proj *p, const pcas_vol *v) {
@@ -239,6 +244,7 @@ int ray_table(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, void
     if (!dtype_ok(dtype)) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!rays || !aligned(rays, 16)) return PCAS_EINVAL;
     HIPCHK(launch_ray_table(dtype, make_dims(vol), make_frame(proj), rays, (hipStream_t)stream));
@@ -260,6 +266,7 @@ int warp_trilinear(pcas_dtype dtype, const pcas_vol *vol, const void *f0, const 
     if (!dtype_ok(dtype)) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if (!f0 || !dvf || !f_out || f_out == f0) return PCAS_EINVAL;
     HIPCHK(launch_warp_trilinear(dtype, make_dims(vol), f0, dvf, f_out, (hipStream_t)stream));
     return PCAS_OK;
@@ -270,6 +277,7 @@ int warp_pca(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, c
     if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if (!f0 || !U || !w || !f_out || f_out == f0) return PCAS_EINVAL;
     if (!finite_vec(w, K)) return PCAS_ENONFINITE;
     HIPCHK(launch_warp_pca(dtype, make_dims(vol), K, f0, mean, U, w, f_out, (hipStream_t)stream));
@@ -281,6 +289,7 @@ int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     if (!dtype_ok(dtype)) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!rays || !aligned(rays, 16) || !f || !p_out) return PCAS_EINVAL;
     HIPCHK(launch_drr_forward(dtype, make_dims(vol), proj->nu, proj->nv, rays, f, p_out, nullptr,
@@ -293,6 +302,7 @@ int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     if (!dtype_ok(dtype)) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!rays || !aligned(rays, 16) || !r || !bp_out) return PCAS_EINVAL;
     HIPCHK(launch_drr_adjoint(dtype, make_dims(vol), make_frame(proj), rays, r, nullptr, 0.0, 0.0,
@@ -338,6 +348,7 @@ int grad_w(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, con
     if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if (!f0 || !U || !w || !bp || !g_out) return PCAS_EINVAL;
     if (!finite_vec(w, K)) return PCAS_ENONFINITE;
     if (!workspace || !aligned(workspace, 256) ||
@@ -359,6 +370,7 @@ int tumour_position(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void
     if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if (!U || !w || !c0_mm || !out || !(tol > 0.0) || max_iter < 1) return PCAS_EINVAL;
     if (!finite_vec(w, K) || !finite_vec(c0_mm, 3)) return PCAS_ENONFINITE;
     HIPCHK(launch_locate(dtype, make_dims(vol), K, mean, U, w, c0_mm, tol, max_iter, out,
@@ -668,6 +680,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
     if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!f0 || !U || !y || !w0 || !w_out || !report) return PCAS_EINVAL;
     if ((st = check_opts(opts))) return st;

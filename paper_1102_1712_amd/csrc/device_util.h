@@ -94,26 +94,44 @@ __device__ __forceinline__ void split_disp(T x, T inv_s, int &l, T &z) {
     z = d - fl;
 }
 
-// Position of sample s of a ray in voxel-index units, clamped to the grid,
-// split into the lower corner l (so that l + 1 is still inside) and the
-// fractional part z.  drr_forward and drr_adjoint both call this, so a
-// sample's corners and weights are bit-identical in the two kernels.
+__device__ __forceinline__ float clamp_t(float q, float top) {
+    return __builtin_amdgcn_fmed3f(q, 0.0f, top);
+}
+__device__ __forceinline__ double clamp_t(double q, double top) {
+    return fmin(fmax(q, 0.0), top);
+}
+
+// Position of a ray sample in voxel-index units, clamped to the grid, split
+// into the lower corner l (so that l + 1 is still inside) and the fraction
+// z.  sh is the sample index plus one half (exact in T), so the position is
+// e + sh d with one rounding per axis.  drr_forward and drr_adjoint both
+// call this, so a sample's corners and weights are bit-identical in the two
+// kernels.
 template <typename T>
-__device__ __forceinline__ void sample_cell(const T (&e)[3], const T (&d)[3], int s, int n0, int n1,
+__device__ __forceinline__ void sample_cell(const T (&e)[3], const T (&d)[3], T sh, int n0, int n1,
                                             int n2, int (&l)[3], T (&z)[3]) {
-    const T sh = (T)s + (T)0.5;
     const int nn[3] = {n0, n1, n2};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        T q = fma_t(sh, d[c], e[c]);
-        q = q < (T)0 ? (T)0 : q;
-        const T top = (T)(nn[c] - 1);
-        q = q > top ? top : q;
-        int li = (int)q;
-        li = li > nn[c] - 2 ? nn[c] - 2 : li;
+        const T q = clamp_t(fma_t(sh, d[c], e[c]), (T)(nn[c] - 1));
+        const int li = min((int)q, nn[c] - 2);
         l[c] = li;
         z[c] = q - (T)li;
     }
+}
+
+// Raw buffer access (gfx9-family descriptor): the eight neighbours of a cell
+// are read through one 32-bit byte offset plus wave-uniform strides, and any
+// offset past num_records reads as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
 }  // namespace pcas

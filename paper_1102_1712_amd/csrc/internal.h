@@ -50,8 +50,8 @@ static_assert(sizeof(RayRec<double>) == 64, "RayRec<double> layout");
 
 // Adjoint brick (voxels owned by one wavefront).
 constexpr int BRICK_X = 16, BRICK_Y = 16, BRICK_Z = 8;
-// Forward tile: a 256-thread block covers 16 x 16 pixels, each wave an 8 x 8 quadrant.
-constexpr int TILE_U = 16, TILE_V = 16;
+// Forward tile: a 256-thread block covers 8 x 8 rays, each wave a 4 x 4 quadrant.
+constexpr int TILE_U = 8, TILE_V = 8;
 // Reductions: partial-sum slots per block.
 constexpr int RED_SLOTS = 8;
 constexpr int GRAD_BLOCKS_MAX = 2048;

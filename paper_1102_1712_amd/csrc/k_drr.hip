@@ -1,18 +1,22 @@
 // a4: forward projection P f and a6: back-projection P^T r.
 //
-// Forward: one lane per ray; a wave marches an 8 x 8 tile of neighbouring
-// rays, whose samples at equal index sit within a few voxels of each other,
-// so the 8-neighbour gathers of a wave hit a handful of cache lines.
+// Forward: each ray is marched by 4 lanes that take interleaved samples
+// (s = seg, seg + 4, ...); a wave covers a 4 x 4 tile of neighbouring rays,
+// whose samples at equal index sit within a few voxels of each other, so
+// the 8-neighbour gathers of a wave hit a handful of cache lines.  The four
+// partial sums are combined by a fixed butterfly.
 //
-// Adjoint: the exact transpose of the forward without global atomics.  One
-// wavefront owns a 16 x 16 x 8 voxel brick held in LDS.  It visits every
-// ray whose pixel lies in the detector footprint of the brick (plus a
-// one-voxel apron), re-creates exactly the samples of that ray whose 2x2x2
-// cell touches the brick (same ray record, same sample_cell arithmetic as
-// the forward), and adds dt * r * weight for the corners inside the brick.
-// Each (sample, corner) pair therefore lands in exactly one brick, and the
-// brick is written to HBM once.  Only the lanes of one wave touch a brick,
-// so the LDS accumulation order is fixed and the result is reproducible.
+// Adjoint: the exact transpose of the forward without global atomics.  A
+// 256-thread workgroup owns a 16 x 16 x 8 voxel brick held in LDS.  It
+// visits every ray whose pixel lies in the detector footprint of the brick
+// (plus a one-voxel apron), re-creates exactly the samples of that ray whose
+// 2x2x2 cell touches the brick (same ray record, same sample_cell
+// arithmetic as the forward), and adds dt * r * weight for the corners of
+// that cell.  Each (sample, corner) pair therefore lands in exactly one
+// brick, and the brick is written to HBM once.  Accumulation is in 64-bit
+// fixed point with a per-brick scale chosen so that no partial sum can
+// overflow; integer addition is associative, so the result does not depend
+// on the order in which the four waves add, and is bit-for-bit reproducible.
 #include "device_util.h"
 
 namespace pcas {
@@ -29,41 +33,55 @@ __global__ __launch_bounds__(256) void k_drr_forward(int n0, int n1, int n2, int
                                                      const T *__restrict__ y,
                                                      double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ sums) {
+    constexpr int SPLIT = 4;
     const int nb = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, nb);
     const int tu = bid % tiles_u, tv = bid / tiles_u;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int iu = tu * TILE_U + (wave & 1) * 8 + (lane & 7);
-    const int iv = tv * TILE_V + (wave >> 1) * 8 + (lane >> 3);
+    const int seg = lane & (SPLIT - 1), rl = lane / SPLIT;
+    const int iu = tu * TILE_U + (wave & 1) * 4 + (rl & 3);
+    const int iv = tv * TILE_V + (wave >> 1) * 4 + (rl >> 2);
     const bool valid = iu < nu && iv < nv;
     const int pix = iv * nu + iu;
-    double pv = 0.0;
+    double acc = 0.0;
+    T dtr = (T)0;
     if (valid) {
         const RayRec<T> r = rays[pix];
+        dtr = r.dt;
         const T e[3] = {r.e[0], r.e[1], r.e[2]};
         const T d[3] = {r.d[0], r.d[1], r.d[2]};
-        const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
-        double acc = 0.0;
-        for (int s = 0; s < r.n; ++s) {
+        const __amdgpu_buffer_rsrc_t rf = make_rsrc(f, (uint32_t)((size_t)n0 * n1 * n2 * sizeof(T)));
+        constexpr int ES = (int)sizeof(T);
+        const int sb1 = n0 * ES, sb2 = n0 * n1 * ES, sb12 = sb1 + sb2;   // wave-uniform strides
+        T sh = (T)seg + (T)0.5;
+        for (int s = seg; s < r.n; s += SPLIT, sh += (T)SPLIT) {
             int l[3];
             T z[3];
-            sample_cell(e, d, s, n0, n1, n2, l, z);
-            const T *b = f + (l[0] + s1 * l[1] + s2 * l[2]);
-            const T v000 = b[0], v100 = b[1];
-            const T v010 = b[s1], v110 = b[s1 + 1];
-            const T v001 = b[s2], v101 = b[s2 + 1];
-            const T v011 = b[s2 + s1], v111 = b[s2 + s1 + 1];
+            sample_cell(e, d, sh, n0, n1, n2, l, z);
+            const int vo = (l[0] + n0 * (l[1] + n1 * l[2])) * ES;
+            const T v000 = buf_load(rf, vo, 0, T()), v100 = buf_load(rf, vo + ES, 0, T());
+            const T v010 = buf_load(rf, vo, sb1, T()), v110 = buf_load(rf, vo + ES, sb1, T());
+            const T v001 = buf_load(rf, vo, sb2, T()), v101 = buf_load(rf, vo + ES, sb2, T());
+            const T v011 = buf_load(rf, vo, sb12, T()), v111 = buf_load(rf, vo + ES, sb12, T());
             const T x00 = lerp_t(v000, v100, z[0]), x10 = lerp_t(v010, v110, z[0]);
             const T x01 = lerp_t(v001, v101, z[0]), x11 = lerp_t(v011, v111, z[0]);
             const T y0 = lerp_t(x00, x10, z[1]), y1 = lerp_t(x01, x11, z[1]);
             acc += (double)lerp_t(y0, y1, z[2]);
         }
-        const T pt = (T)((double)r.dt * acc);
+    }
+    // combine the four interleaved partial sums of a ray (same order in all
+    // four lanes, so they agree bit for bit)
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    double pv = 0.0;
+    const bool writer = valid && seg == 0;
+    if (writer) {
+        const T pt = (T)((double)dtr * acc);
         p[pix] = pt;
         pv = (double)pt;
     }
     if constexpr (SUMS) {
-        const double yv = valid ? (double)y[pix] : 0.0;
+        const double yv = writer ? (double)y[pix] : 0.0;
         const double vals[3] = {pv, pv * yv, pv * pv};
         grid_reduce<3>(vals, partials, counter, sums, bid, nb, 1.0);
     }
@@ -120,7 +138,23 @@ __device__ __forceinline__ double wave_max(double v) {
 constexpr int ACC_YP = BRICK_X + 2;
 constexpr int ACC_ZP = (BRICK_Y + 2) * ACC_YP + 1;
 constexpr int ACC_WORDS = (BRICK_Z + 2) * ACC_ZP;
-constexpr int QCAP = 128;   // queued rays per wave (two batches)
+constexpr int ADJ_WAVES = 4;   // waves sharing one brick
+constexpr int QCAP = 128;      // queued rays per wave (two batches)
+
+// Fixed-point value of a contribution v at scale S: round(v S) as a 64-bit
+// two's-complement integer, read off the mantissa of v S + 1.5 * 2^52 (exact
+// for |v S| < 2^51, which the caller's choice of S guarantees).
+__device__ __forceinline__ unsigned long long to_fixed(double vS) {
+    const double m = vS + 6755399441055744.0;
+    return __builtin_bit_cast(unsigned long long, m) - 0x4338000000000000ull;
+}
+
+// Samples of ray r whose 2x2x2 cell may touch the brick [lo, hi]: the
+// parameter range where every coordinate lies in [lo - 1, hi + 1], widened
+// by one sample each side to absorb rounding in this estimate (the cell
+// test in the sample loop is exact).
+__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_approx(double x) { return 1.0 / x; }
 
 template <typename T>
 __device__ __forceinline__ bool brick_sample_range(const RayRec<T> &r, const T (&lob)[3],
@@ -129,7 +163,7 @@ __device__ __forceinline__ bool brick_sample_range(const RayRec<T> &r, const T (
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if (r.d[c] != (T)0) {
-            const T inv = (T)1 / r.d[c];
+            const T inv = rcp_approx(r.d[c]);
             T ta = (lob[c] - r.e[c]) * inv - (T)0.5;
             T tb = (hib[c] - r.e[c]) * inv - (T)0.5;
             if (ta > tb) { const T tmp = ta; ta = tb; tb = tmp; }
@@ -146,17 +180,14 @@ __device__ __forceinline__ bool brick_sample_range(const RayRec<T> &r, const T (
 }
 
 template <typename T>
-__device__ __forceinline__ void flush_cell(T *acc, int base, const T (&cw)[8]) {
+__device__ __forceinline__ void flush_cell(unsigned long long *acc, int base, const T (&cw)[8],
+                                           double S) {
     if (base < 0) return;
-    T *p = acc + base;
-    atomicAdd(p, cw[0]);
-    atomicAdd(p + 1, cw[1]);
-    atomicAdd(p + ACC_YP, cw[2]);
-    atomicAdd(p + ACC_YP + 1, cw[3]);
-    atomicAdd(p + ACC_ZP, cw[4]);
-    atomicAdd(p + ACC_ZP + 1, cw[5]);
-    atomicAdd(p + ACC_ZP + ACC_YP, cw[6]);
-    atomicAdd(p + ACC_ZP + ACC_YP + 1, cw[7]);
+    unsigned long long *p = acc + base;
+    const int off[8] = {0, 1, ACC_YP, ACC_YP + 1, ACC_ZP, ACC_ZP + 1, ACC_ZP + ACC_YP,
+                        ACC_ZP + ACC_YP + 1};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) atomicAdd(p + off[q], to_fixed((double)cw[q] * S));
 }
 
 // One lane walks the queued ray's samples near the brick.  Samples whose
@@ -164,26 +195,27 @@ __device__ __forceinline__ void flush_cell(T *acc, int base, const T (&cw)[8]) {
 // consecutive samples sharing a cell are summed in registers and added to
 // LDS when the cell changes.
 template <typename T>
-__device__ __forceinline__ void splat_ray(T *acc, const RayRec<T> &r, T cst, int s0, int s1,
-                                          int n0, int n1, int n2, const int (&lo)[3],
-                                          const int (&hi)[3]) {
+__device__ __forceinline__ void splat_ray(unsigned long long *acc, const RayRec<T> &r, T cst,
+                                          int s0, int s1, int n0, int n1, int n2,
+                                          const int (&lo)[3], const int (&hi)[3], double S) {
     const T e[3] = {r.e[0], r.e[1], r.e[2]};
     const T d[3] = {r.d[0], r.d[1], r.d[2]};
     int cur = -1;   // halo-array offset of the cell being accumulated
     T cw[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) cw[q] = (T)0;
-    for (int s = s0; s <= s1; ++s) {
+    T sh = (T)s0 + (T)0.5;
+    for (int s = s0; s <= s1; ++s, sh += (T)1) {
         int l[3];
         T z[3];
-        sample_cell(e, d, s, n0, n1, n2, l, z);
+        sample_cell(e, d, sh, n0, n1, n2, l, z);
         const int lx = l[0] - lo[0] + 1, ly = l[1] - lo[1] + 1, lz = l[2] - lo[2] + 1;
         const bool touches = lx >= 0 && lx <= hi[0] - lo[0] + 1 && ly >= 0 &&
                              ly <= hi[1] - lo[1] + 1 && lz >= 0 && lz <= hi[2] - lo[2] + 1;
         if (!touches) continue;
         const int base = lz * ACC_ZP + ly * ACC_YP + lx;
         if (base != cur) {
-            flush_cell(acc, cur, cw);
+            flush_cell(acc, cur, cw, S);
 #pragma unroll
             for (int q = 0; q < 8; ++q) cw[q] = (T)0;
             cur = base;
@@ -201,32 +233,50 @@ __device__ __forceinline__ void splat_ray(T *acc, const RayRec<T> &r, T cst, int
         cw[6] = fma_t(w11, xa, cw[6]);
         cw[7] = fma_t(w11, xb, cw[7]);
     }
-    flush_cell(acc, cur, cw);
+    flush_cell(acc, cur, cw, S);
 }
 
 template <typename T, bool FORM_R>
-__global__ __launch_bounds__(64) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
-                                                    const RayRec<T> *__restrict__ rays,
-                                                    const T *__restrict__ rp,
-                                                    const T *__restrict__ y, double a, double b,
-                                                    T *__restrict__ bp) {
-    __shared__ T acc[ACC_WORDS];
-    __shared__ int q_pix[QCAP], q_s0[QCAP], q_s1[QCAP];
-    __shared__ T q_c[QCAP];
+__device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__restrict__ y, double a,
+                                         double b, int pix) {
+    if constexpr (FORM_R)
+        return (T)((double)rp[pix] - a * (double)y[pix] - b);
+    else
+        return rp[pix];
+}
+
+// hb bounds the summed weight one ray can give one voxel (1/h + 1 for the
+// smallest per-sample index step h of any ray with two or more samples).
+template <typename T, bool FORM_R>
+__global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
+                                                     double hb,
+                                                     const RayRec<T> *__restrict__ rays,
+                                                     const T *__restrict__ rp,
+                                                     const T *__restrict__ y, double a, double b,
+                                                     T *__restrict__ bp) {
+    __shared__ unsigned long long acc[ACC_WORDS];
+    __shared__ int q_pix[ADJ_WAVES][QCAP], q_s0[ADJ_WAVES][QCAP], q_s1[ADJ_WAVES][QCAP];
+    __shared__ T q_c[ADJ_WAVES][QCAP];
+    __shared__ double red[ADJ_WAVES];
     const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
     const int nb = gridDim.x;
-    const int bid = xcd_remap(blockIdx.x, nb);
+    // Bricks go round-robin over the XCDs in launch order: only bricks inside
+    // the x-ray cone carry work, so contiguous per-XCD ranges would leave the
+    // XCDs that hold the outer z-slabs idle.
+    (void)nb;
+    const int bid = blockIdx.x;
     const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
     const int lo[3] = {bx * BRICK_X, by * BRICK_Y, bz * BRICK_Z};
     const int hi[3] = {min(lo[0] + BRICK_X, n0) - 1, min(lo[1] + BRICK_Y, n1) - 1,
                        min(lo[2] + BRICK_Z, n2) - 1};
     const int nn[3] = {n0, n1, n2};
-    const int lane = threadIdx.x;
-    for (int t = lane; t < ACC_WORDS; t += 64) acc[t] = (T)0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int t = tid; t < ACC_WORDS; t += 256) acc[t] = 0ull;
 
     // Detector footprint of the region whose samples can reach the brick:
     // index box [lo - 1, hi + 1] clipped to the grid, projected through its
     // eight corners (the source is outside the volume, so every depth > 0).
+    // Every wave computes it (identically).
     double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
     if (lane < 8) {
         double rel[3];
@@ -251,20 +301,44 @@ __global__ __launch_bounds__(64) void k_drr_adjoint(VolDims vd, Frame fr, int nb
     const int iv0 = (int)fmin(fmax(floor(vmin) - 1.0, 0.0), (double)fr.nv);
     const int iv1 = (int)fmin(fmax(ceil(vmax) + 1.0, -1.0), (double)(fr.nv - 1));
     const int W = iu1 - iu0 + 1, H = iv1 - iv0 + 1;
-    // Candidate batches interleave the footprint: lane (lu, lv) of batch
-    // (bu, bv) takes pixel (iu0 + lu*Su + bu, iv0 + lv*Sv + bv), so the rays
-    // of one batch sit Su x Sv pixels apart and rarely share a cell.
-    const int Su = W > 0 ? (W + 7) / 8 : 0;
-    const int Sv = H > 0 ? (H + 7) / 8 : 0;
-    const int ntiles = (W > 0 && H > 0) ? Su * Sv : 0;
+    const int npix = (W > 0 && H > 0) ? W * H : 0;
+
+    // Per-brick fixed-point scale from the largest |r| in the footprint:
+    // every contribution is |dt r w| <= step * rmax = C; a flushed cell sum
+    // is <= C hb; a voxel total is <= C hb * npix.  S keeps the former below
+    // 2^50 and the latter below 2^62 (64-bit accumulators never overflow).
+    double rmax = 0.0;
+    for (int t = tid; t < npix; t += 256) {
+        const int pix = (iv0 + t / W) * fr.nu + (iu0 + t % W);
+        rmax = fmax(rmax, fabs((double)residual_at<T, FORM_R>(rp, y, a, b, pix)));
+    }
+    rmax = wave_max(rmax);
+    if (lane == 0) red[wave] = rmax;
     __syncthreads();
+    rmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double C = fr.step * rmax * (1.0 + 1e-6);
+    double Sd = 0.0;
+    if (C > 0.0) {
+        const double lim_cell = 1125899906842624.0 / (C * hb);                  // 2^50
+        const double lim_vox = 4611686018427387904.0 / (C * hb * (double)npix);   // 2^62
+        Sd = fmin(fmin(lim_cell, lim_vox), 1e300);
+    }
 
     const T lob[3] = {(T)(lo[0] - 1), (T)(lo[1] - 1), (T)(lo[2] - 1)};
     const T hib[3] = {(T)(hi[0] + 1), (T)(hi[1] + 1), (T)(hi[2] + 1)};
+    // Candidate batches interleave the footprint: lane (lu, lv) of batch
+    // (bu, bv) takes pixel (iu0 + lu*Su + bu, iv0 + lv*Sv + bv), so the rays
+    // of one batch sit Su x Sv pixels apart; batches go round-robin to the
+    // four waves, each with its own queue of rays with non-empty ranges.
+    const int Su = W > 0 ? (W + 7) / 8 : 0;
+    const int Sv = H > 0 ? (H + 7) / 8 : 0;
+    const int ntiles = (C > 0.0 && npix > 0) ? Su * Sv : 0;
+    int *qp = q_pix[wave], *qa = q_s0[wave], *qb = q_s1[wave];
+    T *qc = q_c[wave];
     int qn = 0;   // wave-uniform queue length
-    for (int tile = 0; tile <= ntiles; ++tile) {
-        if (tile < ntiles) {
-            // candidate ray of this lane
+    for (int tile = wave;; tile += ADJ_WAVES) {
+        const bool more = tile < ntiles;
+        if (more) {
             const int iu = iu0 + (lane & 7) * Su + tile % Su;
             const int iv = iv0 + (lane >> 3) * Sv + tile / Su;
             bool active = false;
@@ -274,53 +348,62 @@ __global__ __launch_bounds__(64) void k_drr_adjoint(VolDims vd, Frame fr, int nb
                 pix = iv * fr.nu + iu;
                 const RayRec<T> r = rays[pix];
                 if (r.n > 0) {
-                    T rv;
-                    if constexpr (FORM_R)
-                        rv = (T)((double)rp[pix] - a * (double)y[pix] - b);
-                    else
-                        rv = rp[pix];
-                    cst = r.dt * rv;
+                    cst = r.dt * residual_at<T, FORM_R>(rp, y, a, b, pix);
                     active = cst != (T)0 && brick_sample_range(r, lob, hib, &s0, &s1);
                 }
             }
             const uint64_t mask = __ballot(active);
             if (active) {
                 const int pos = qn + __popcll(mask & ((1ull << lane) - 1ull));
-                q_pix[pos] = pix;
-                q_s0[pos] = s0;
-                q_s1[pos] = s1;
-                q_c[pos] = cst;
+                qp[pos] = pix;
+                qa[pos] = s0;
+                qb[pos] = s1;
+                qc[pos] = cst;
             }
             qn += __popcll(mask);
-            __syncthreads();
             if (qn < 64) continue;
         } else if (qn == 0) {
             break;
         }
-        // drain one batch of up to 64 queued rays, one per lane
+        // drain one batch of up to 64 queued rays, one per lane (the queue
+        // lives in this wave's LDS slice and is only touched by this wave)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         if (lane < qn) {
-            const int pix = q_pix[lane];
-            const RayRec<T> r = rays[pix];
-            splat_ray(acc, r, q_c[lane], q_s0[lane], q_s1[lane], n0, n1, n2, lo, hi);
+            const RayRec<T> r = rays[qp[lane]];
+            splat_ray(acc, r, qc[lane], qa[lane], qb[lane], n0, n1, n2, lo, hi, Sd);
         }
         const int rest = qn > 64 ? qn - 64 : 0;
-        __syncthreads();
+        int mp = 0, ma = 0, mb = 0;
+        T mc = (T)0;
         if (lane < rest) {
-            q_pix[lane] = q_pix[64 + lane];
-            q_s0[lane] = q_s0[64 + lane];
-            q_s1[lane] = q_s1[64 + lane];
-            q_c[lane] = q_c[64 + lane];
+            mp = qp[64 + lane];
+            ma = qa[64 + lane];
+            mb = qb[64 + lane];
+            mc = qc[64 + lane];
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) {
+            qp[lane] = mp;
+            qa[lane] = ma;
+            qb[lane] = mb;
+            qc[lane] = mc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         qn = rest;
+        if (!more) break;
     }
     __syncthreads();
     const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
-    for (int t = lane; t < BRICK_X * BRICK_Y * BRICK_Z; t += 64) {
+    const double inv_S = Sd > 0.0 ? 1.0 / Sd : 0.0;
+    for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
         const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
         const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
-        if (i < n0 && j < n1 && k < n2)
-            bp[i + s1 * j + s2 * k] = acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
+        if (i < n0 && j < n1 && k < n2) {
+            const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
+            bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
+        }
     }
 }
 
@@ -330,23 +413,29 @@ hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, 
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
     const int nbz = (v.n2 + BRICK_Z - 1) / BRICK_Z;
-    dim3 grid(nbx * nby * nbz), block(64);
+    // A ray with n >= 2 samples has dt >= step / 2, and its largest
+    // per-sample index step is >= dt / (sqrt(3) max spacing); the tent
+    // weights one ray gives a voxel then sum to at most 1/h + 1.  (A ray
+    // with one sample gives at most 1.)
+    const double smax = fmax(v.spacing[0], fmax(v.spacing[1], v.spacing[2]));
+    const double hb = 2.0 * sqrt(3.0) * smax / fr.step + 2.0;
+    dim3 grid(nbx * nby * nbz), block(256);
     if (dt == PCAS_F32) {
         if (y)
-            hipLaunchKernelGGL((k_drr_adjoint<float, true>), grid, block, 0, s, v, fr, nbx, nby,
+            hipLaunchKernelGGL((k_drr_adjoint<float, true>), grid, block, 0, s, v, fr, nbx, nby, hb,
                                (const RayRec<float> *)rays, (const float *)r_or_p,
                                (const float *)y, a, b, (float *)bp);
         else
-            hipLaunchKernelGGL((k_drr_adjoint<float, false>), grid, block, 0, s, v, fr, nbx, nby,
+            hipLaunchKernelGGL((k_drr_adjoint<float, false>), grid, block, 0, s, v, fr, nbx, nby, hb,
                                (const RayRec<float> *)rays, (const float *)r_or_p,
                                (const float *)nullptr, 0.0, 0.0, (float *)bp);
     } else {
         if (y)
-            hipLaunchKernelGGL((k_drr_adjoint<double, true>), grid, block, 0, s, v, fr, nbx, nby,
+            hipLaunchKernelGGL((k_drr_adjoint<double, true>), grid, block, 0, s, v, fr, nbx, nby, hb,
                                (const RayRec<double> *)rays, (const double *)r_or_p,
                                (const double *)y, a, b, (double *)bp);
         else
-            hipLaunchKernelGGL((k_drr_adjoint<double, false>), grid, block, 0, s, v, fr, nbx, nby,
+            hipLaunchKernelGGL((k_drr_adjoint<double, false>), grid, block, 0, s, v, fr, nbx, nby, hb,
                                (const RayRec<double> *)rays, (const double *)r_or_p,
                                (const double *)nullptr, 0.0, 0.0, (double *)bp);
     }

@@ -21,7 +21,9 @@ __global__ __launch_bounds__(256) void k_grad_w(VolDims vd, const T *__restrict_
     const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
     const int64_t N = (int64_t)n0 * n1 * n2;
     const int nb = gridDim.x;
-    const int bid = xcd_remap(blockIdx.x, nb);
+    // round-robin over the XCDs: voxels outside the x-ray cone (bp = 0) are
+    // skipped, so the work per block is uneven along z
+    const int bid = blockIdx.x;
     int64_t per = (N + nb - 1) / nb;
     per = (per + 255) & ~(int64_t)255;
     const int64_t v_begin = (int64_t)bid * per;

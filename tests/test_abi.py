@@ -106,6 +106,15 @@ def test_invalid_dtype_dims_and_pointers(L, geom):
     assert L.warp_trilinear(0, ctypes.byref(v), FAKE, FAKE, FAKE, None) == EINVAL   # f_out aliases f0
 
 
+def test_volume_over_2gib_rejected(L, geom):
+    """Kernels address a volume with 32-bit byte offsets."""
+    _, p = geom
+    big = B.c_vol(synth.centred_volume((1024, 1024, 512), (0.5, 0.5, 0.5)))
+    assert L.ray_table(0, ctypes.byref(big), ctypes.byref(p), FAKE, None) == EINVAL
+    half = B.c_vol(synth.centred_volume((1024, 1024, 256), (0.5, 0.5, 0.5)))
+    assert L.drr_forward(1, ctypes.byref(half), ctypes.byref(p), FAKE, FAKE, FAKE, None) == EINVAL
+
+
 def test_invalid_geometry(L, geom):
     v, p = geom
     for field, val in (("sad", 0.0), ("sid", 900.0), ("pitch_u", 0.0), ("step", -1.0),

@@ -1,0 +1,88 @@
+"""Streaming solve (warm start + Eq. 3 prediction) on a short sequence at
+changing gantry angles: every frame's coefficients against the oracle solve
+from the same initial guess, and localisation error against the planted
+trajectory."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1102_1712_amd import binding as B
+from paper_1102_1712_amd import stream as S
+from paper_1102_1712_amd import synth
+
+from gpu_common import Dev, say, to_dev, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_or_skip()
+
+
+def test_stream_small_f64(torch):
+    c = synth.small(dtype="f64", seed=5)
+    d = Dev(c)
+    n_frames, fps = 24, 15.0
+    trace = S.breathing_trace(n_frames + 40, fps, seed=11)
+    w_all = S.planted_trajectory(trace, c.K, seed=12, scale=0.04)
+    train, w_true = w_all[:40], w_all[40:]
+    coeffs = S.fit_predictor(train, L=2)
+    angles = c.proj.angle + np.arange(n_frames) * (2 * np.pi / 600.0)
+    rng = np.random.default_rng(13)
+    ys = []
+    for t in range(n_frames):
+        pj = dataclasses.replace(c.proj, angle=float(angles[t]))
+        xi = rng.normal(size=(pj.nv, pj.nu))
+        ys.append(O.measured_projection(c.vol, pj, c.f0, c.mean, c.U, w_true[t], xi, 0.01))
+    say("stream small f64", n_frames, "frames")
+    solver = S.StreamSolver(c.vol, c.proj, d.f0, d.mean, d.U, c0_mm=c.tumour_c0,
+                            predictor=coeffs)
+    w0s = []
+    for t in range(n_frames):
+        w0s.append(solver.initial_guess())
+        solver.step(angles[t], to_dev(ys[t], d.dt))
+    rep = solver.report
+    for t in (0, 3, 11, n_frames - 1):
+        pj = dataclasses.replace(c.proj, angle=float(angles[t]))
+        prob = O.Problem(c.vol, pj, c.f0, c.mean, c.U, ys[t])
+        w_o, _ = O.solve_cg(prob, w0s[t])
+        w_g = rep.frames[t].w
+        assert np.linalg.norm(w_g - w_o) <= 1e-4 * max(np.linalg.norm(w_o), 1e-3), t
+    truth = np.array([O.locate(c.vol, c.mean, c.U, w, c.tumour_c0)[0] for w in w_true])
+    located = np.array([f.tumour_mm for f in rep.frames])
+    err = S.localisation_errors(located, truth)
+    say("stream errors", err, rep.summary())
+    assert err["e_mean_mm"] < 1.0
+
+
+def test_prediction_vs_previous_init(torch):
+    """Both warm starts reach the same solutions; report the evaluation
+    counts (the paper reports ~10% less time with prediction)."""
+    c = synth.small(dtype="f32", seed=6)
+    d = Dev(c)
+    n_frames = 16
+    trace = S.breathing_trace(n_frames + 40, 15.0, seed=21)
+    w_all = S.planted_trajectory(trace, c.K, seed=22, scale=0.04)
+    coeffs = S.fit_predictor(w_all[:40], L=2)
+    w_true = w_all[40:]
+    angles = c.proj.angle + np.arange(n_frames) * (2 * np.pi / 600.0)
+    ys = []
+    for t in range(n_frames):
+        pj = dataclasses.replace(c.proj, angle=float(angles[t]))
+        ys.append(O.measured_projection(c.vol, pj, c.f0, c.mean, c.U, w_true[t],
+                                        np.zeros((pj.nv, pj.nu)), 0.0).astype(np.float32))
+    out = {}
+    for init in ("predict", "previous"):
+        say("stream init", init)
+        sv = S.StreamSolver(c.vol, c.proj, d.f0, d.mean, d.U, init=init, predictor=coeffs,
+                            opts=B.default_opts(xtol=1e-7))
+        sv.run(angles, lambda t, a: to_dev(ys[t], d.dt))
+        out[init] = sv.report
+    wp = np.array([f.w for f in out["predict"].frames])
+    wq = np.array([f.w for f in out["previous"].frames])
+    assert np.max(np.abs(wp - wq)) <= 1e-3 * max(1.0, np.abs(wq).max())
+    say("fevals predict", out["predict"].summary()["mean_fevals"],
+        "previous", out["previous"].summary()["mean_fevals"])
