@@ -292,8 +292,10 @@ int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!rays || !aligned(rays, 16) || !f || !p_out) return PCAS_EINVAL;
-    HIPCHK(launch_drr_forward(dtype, make_dims(vol), proj->nu, proj->nv, rays, f, p_out, nullptr,
-                              nullptr, nullptr, nullptr, (hipStream_t)stream));
+    const VolDims vd = make_dims(vol);
+    const Frame fr = make_frame(proj);
+    HIPCHK(launch_drr_forward(dtype, vd, fr, plan_drr_forward(dtype, vd, fr), rays, f, p_out,
+                              nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream));
     return PCAS_OK;
 }
 
@@ -435,6 +437,7 @@ struct Solver {
     pcas_dtype dt;
     VolDims vd;
     Frame fr;
+    ForwardPlan fplan;
     int K;
     int64_t M;
     const void *f0, *mean, *U, *y;
@@ -505,7 +508,7 @@ struct Solver {
             return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s);
         }));
         HIPCHK(timed(PCAS_K_DRR, [&] {
-            return launch_drr_forward(dt, vd, fr.nu, fr.nv, ws + L.rays, ws + L.f, ws + L.p, y,
+            return launch_drr_forward(dt, vd, fr, fplan, ws + L.rays, ws + L.f, ws + L.p, y,
                                       (double *)(ws + L.partials), &counters()[0], scal(), s);
         }));
         ++n_fevals;
@@ -694,6 +697,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
     S.dt = dtype;
     S.vd = make_dims(vol);
     S.fr = make_frame(proj);
+    S.fplan = plan_drr_forward(dtype, S.vd, S.fr);
     S.K = K;
     S.M = npix_of(proj);
     S.f0 = f0;

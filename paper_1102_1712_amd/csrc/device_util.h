@@ -101,23 +101,50 @@ __device__ __forceinline__ double clamp_t(double q, double top) {
     return fmin(fmax(q, 0.0), top);
 }
 
-// Position of a ray sample in voxel-index units, clamped to the grid, split
-// into the lower corner l (so that l + 1 is still inside) and the fraction
-// z.  sh is the sample index plus one half (exact in T), so the position is
-// e + sh d with one rounding per axis.  drr_forward and drr_adjoint both
-// call this, so a sample's corners and weights are bit-identical in the two
-// kernels.
+// Largest index-space position a sample takes along an axis of n >= 2
+// voxels: the representable value just below n - 1, so that the lower corner
+// floor(q) is at most n - 2 and the fraction stays below 1.  (A sample lands
+// on the last voxel centre only where a ray runs along the grid's far face;
+// its weights then move by one ulp.)
+template <typename T> __device__ __forceinline__ T below_last(int n);
+template <> __device__ __forceinline__ float below_last<float>(int n) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, (float)(n - 1)) - 1u);
+}
+template <> __device__ __forceinline__ double below_last<double>(int n) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, (double)(n - 1)) - 1ull);
+}
+
+template <typename T> struct GridTop {
+    T t[3];
+};
 template <typename T>
-__device__ __forceinline__ void sample_cell(const T (&e)[3], const T (&d)[3], T sh, int n0, int n1,
-                                            int n2, int (&l)[3], T (&z)[3]) {
-    const int nn[3] = {n0, n1, n2};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const T q = clamp_t(fma_t(sh, d[c], e[c]), (T)(nn[c] - 1));
-        const int li = min((int)q, nn[c] - 2);
-        l[c] = li;
-        z[c] = q - (T)li;
-    }
+__device__ __forceinline__ GridTop<T> grid_top(int n0, int n1, int n2) {
+    return {{below_last<T>(n0), below_last<T>(n1), below_last<T>(n2)}};
+}
+
+__device__ __forceinline__ float fract_t(float q) { return __builtin_amdgcn_fractf(q); }
+__device__ __forceinline__ double fract_t(double q) { return __builtin_amdgcn_fract(q); }
+
+// Position of a ray sample along one axis in voxel-index units, clamped to
+// [0, top], split into the lower corner l and the fraction z (exact: q is
+// non-negative, so z = q - floor(q) is representable).  sh is the sample
+// index plus one half (exact in T), so the position is e + sh d with one
+// rounding.  For a fixed ray, l is monotone in sh (every step here is).
+template <typename T>
+__device__ __forceinline__ void axis_cell(T e, T d, T sh, T top, int &l, T &z) {
+    const T q = clamp_t(fma_t(sh, d, e), top);
+    l = (int)q;
+    z = fract_t(q);
+}
+
+// The three axes of a sample.  drr_forward and drr_adjoint both call this,
+// so a sample's corners and weights are bit-identical in the two kernels.
+template <typename T>
+__device__ __forceinline__ void sample_cell(const T (&e)[3], const T (&d)[3], T sh,
+                                            const GridTop<T> &top, int (&l)[3], T (&z)[3]) {
+    axis_cell(e[0], d[0], sh, top.t[0], l[0], z[0]);
+    axis_cell(e[1], d[1], sh, top.t[1], l[1], z[1]);
+    axis_cell(e[2], d[2], sh, top.t[2], l[2], z[2]);
 }
 
 // Raw buffer access (gfx9-family descriptor): the eight neighbours of a cell

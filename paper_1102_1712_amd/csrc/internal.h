@@ -50,8 +50,16 @@ static_assert(sizeof(RayRec<double>) == 64, "RayRec<double> layout");
 
 // Adjoint brick (voxels owned by one wavefront).
 constexpr int BRICK_X = 16, BRICK_Y = 16, BRICK_Z = 8;
-// Forward tile: a 256-thread block covers 8 x 8 rays, each wave a 4 x 4 quadrant.
-constexpr int TILE_U = 8, TILE_V = 8;
+// Forward projection: FWD_SPLIT lanes march one ray (interleaved samples),
+// a wave covers FWD_WU x FWD_WV neighbouring rays, a 256-thread block 2 x 2
+// such wave tiles (a bundle of TILE_U x TILE_V rays).  The bundle stages its
+// footprint in the volume slab by slab in an LDS box of FWD_LDS_BYTES.
+constexpr int FWD_SPLIT = 4, FWD_WU = 4;
+constexpr int FWD_WV = 64 / FWD_SPLIT / FWD_WU;
+constexpr int TILE_U = 2 * FWD_WU, TILE_V = 2 * FWD_WV;
+constexpr int FWD_LDS_BYTES = 16384;
+constexpr int FWD_MAX_SLABS = 128;
+static_assert(FWD_WU * FWD_WV * FWD_SPLIT == 64, "forward wave tile");
 // Reductions: partial-sum slots per block.
 constexpr int RED_SLOTS = 8;
 constexpr int GRAD_BLOCKS_MAX = 2048;
@@ -89,10 +97,17 @@ hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f
 // sum p*p) into sums[0..2] (double) via per-block partials and a last-block
 // pass; partials needs drr_forward_blocks() * RED_SLOTS doubles, counter one
 // zeroed uint32 (left zeroed on exit).
+// The geometry-only launch plan (slab axis and thickness) is computed once
+// per projection on the host.
 int drr_forward_blocks(int nu, int nv);
-hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, int nu, int nv, const void *rays,
-                              const void *f, void *p, const void *y, double *partials,
-                              uint32_t *counter, double *sums, hipStream_t s);
+struct ForwardPlan {
+    int axis = 0, slab = 0;
+};
+ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr);
+hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                              const ForwardPlan &plan, const void *rays, const void *f, void *p,
+                              const void *y, double *partials, uint32_t *counter, double *sums,
+                              hipStream_t s);
 
 // Back-projection.  If y != nullptr the residual r = p - a*y - b is formed
 // on the fly from p (passed as r_or_p); otherwise r_or_p is r.

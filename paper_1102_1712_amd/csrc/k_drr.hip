@@ -1,10 +1,10 @@
 // a4: forward projection P f and a6: back-projection P^T r.
 //
-// Forward: each ray is marched by 4 lanes that take interleaved samples
-// (s = seg, seg + 4, ...); a wave covers a 4 x 4 tile of neighbouring rays,
-// whose samples at equal index sit within a few voxels of each other, so
-// the 8-neighbour gathers of a wave hit a handful of cache lines.  The four
-// partial sums are combined by a fixed butterfly.
+// Forward: each ray is marched by FWD_SPLIT lanes that take interleaved
+// samples (s = seg, seg + FWD_SPLIT, ...); a wave covers a tile of
+// neighbouring rays, whose samples at equal index sit within a few voxels of
+// each other, so the 8-neighbour gathers of a wave hit a handful of cache
+// lines.  The partial sums of a ray are combined by a fixed butterfly.
 //
 // Adjoint: the exact transpose of the forward without global atomics.  A
 // 256-thread workgroup owns a 16 x 16 x 8 voxel brick held in LDS.  It
@@ -17,6 +17,8 @@
 // fixed point with a per-brick scale chosen so that no partial sum can
 // overflow; integer addition is associative, so the result does not depend
 // on the order in which the four waves add, and is bit-for-bit reproducible.
+#include <algorithm>
+
 #include "device_util.h"
 
 namespace pcas {
@@ -26,57 +28,314 @@ __device__ __forceinline__ T lerp_t(T a, T b, T z) {
     return fma_t(z, b - a, a);
 }
 
-template <typename T, bool SUMS>
-__global__ __launch_bounds__(256) void k_drr_forward(int n0, int n1, int n2, int nu, int nv,
-                                                     int tiles_u, const RayRec<T> *__restrict__ rays,
+// Trilinear value from the eight corners of a cell (vXYZ: X, Y, Z = 0 or 1
+// for the lower or upper corner), x pairs first, then y, then z.
+template <typename T>
+__device__ __forceinline__ T trilinear(T v000, T v100, T v010, T v110, T v001, T v101, T v011,
+                                       T v111, const T (&z)[3]) {
+    const T x00 = lerp_t(v000, v100, z[0]), x10 = lerp_t(v010, v110, z[0]);
+    const T x01 = lerp_t(v001, v101, z[0]), x11 = lerp_t(v011, v111, z[0]);
+    const T y0 = lerp_t(x00, x10, z[1]), y1 = lerp_t(x01, x11, z[1]);
+    return lerp_t(y0, y1, z[2]);
+}
+
+// Value at a sample from the volume in global memory: corner byte offset vo,
+// wave-uniform byte strides sb1 (y) and sb2 (z).
+template <typename T>
+__device__ __forceinline__ T gather_global(__amdgpu_buffer_rsrc_t rf, int vo, int sb1, int sb2,
+                                           const T (&z)[3]) {
+    constexpr int ES = (int)sizeof(T);
+    const int sb12 = sb1 + sb2;
+    const T v000 = buf_load(rf, vo, 0, T()), v100 = buf_load(rf, vo + ES, 0, T());
+    const T v010 = buf_load(rf, vo, sb1, T()), v110 = buf_load(rf, vo + ES, sb1, T());
+    const T v001 = buf_load(rf, vo, sb2, T()), v101 = buf_load(rf, vo + ES, sb2, T());
+    const T v011 = buf_load(rf, vo, sb12, T()), v111 = buf_load(rf, vo + ES, sb12, T());
+    return trilinear(v000, v100, v010, v110, v001, v101, v011, v111, z);
+}
+
+// Geometric ray of detector pixel (iu, iv) in voxel-index coordinates:
+// points o + t q, t >= 0 (o is the source).
+struct IdxRay {
+    double o[3], q[3];
+};
+
+__host__ __device__ inline IdxRay pixel_ray(const VolDims &v, const Frame &fr, int iu, int iv) {
+    const double u = (iu - 0.5 * (fr.nu - 1)) * fr.pitch_u + fr.offset_u;
+    const double w = (iv - 0.5 * (fr.nv - 1)) * fr.pitch_v + fr.offset_v;
+    IdxRay r;
+    for (int c = 0; c < 3; ++c) {
+        const double P = fr.det[c] + u * fr.eu[c] + w * fr.ev[c];
+        r.o[c] = (fr.src[c] - v.origin[c]) * v.inv_s[c];
+        r.q[c] = (P - fr.src[c]) * v.inv_s[c];
+    }
+    return r;
+}
+
+// Where the ray of pixel (iu, iv) crosses the plane AX = plane: the two
+// other index coordinates (in increasing axis order).  False when the ray
+// runs (almost) parallel to the plane or crosses it absurdly far away.
+__host__ __device__ inline bool plane_point(const VolDims &v, const Frame &fr, int AX, int iu,
+                                            int iv, double plane, double &pb, double &pc) {
+    const IdxRay r = pixel_ray(v, fr, iu, iv);
+    const int B = AX == 0 ? 1 : 0, C = AX == 2 ? 1 : 2;
+    if (!(fabs(r.q[AX]) > 1e-9)) return false;
+    const double t = (plane - r.o[AX]) / r.q[AX];
+    pb = r.o[B] + t * r.q[B];
+    pc = r.o[C] + t * r.q[C];
+    return fabs(pb) < 1e9 && fabs(pc) < 1e9;
+}
+
+// Cell range [lo, hi] along an axis of n voxels holding positions in
+// [mn, mx], widened by 1/20 cell (far above the rounding of sample positions
+// in either precision, far below a cell) and clamped to the grid.
+__host__ __device__ inline void cell_range(double mn, double mx, int n, int &lo, int &hi) {
+    lo = (int)fmin(fmax(floor(mn - 0.05), 0.0), (double)(n - 2));
+    hi = (int)fmin(fmax(floor(mx + 0.05), 0.0), (double)(n - 2));
+}
+
+// Cells that samples of a bundle of rays (pixels [iu0, iu1] x [iv0, iv1])
+// can occupy across axis AX while their cell along AX lies in [A0, A0 + S):
+// on every plane AX = const the bundle's crossing points lie in the convex
+// quadrilateral of its four corner rays (a central projection maps the
+// detector rectangle onto it), so the box of the corner rays' crossings of
+// the planes AX = A0 - 1 and AX = A0 + S + 1 (points 0..7: corner = p & 3,
+// far plane = p >> 2), slightly widened and clamped, holds every such
+// sample's cell.
+__host__ __device__ inline bool slab_corner_point(const VolDims &v, const Frame &fr, int AX,
+                                                  int iu0, int iu1, int iv0, int iv1, int A0,
+                                                  int S, int pt, double &pb, double &pc) {
+    const double plane = (pt >> 2) ? (double)(A0 + S + 1) : (double)(A0 - 1);
+    return plane_point(v, fr, AX, (pt & 1) ? iu1 : iu0, (pt & 2) ? iv1 : iv0, plane, pb, pc);
+}
+
+static bool slab_cells_host(const VolDims &v, const Frame &fr, int AX, int iu0, int iu1, int iv0,
+                            int iv1, int A0, int S, int (&lo)[2], int (&hi)[2]) {
+    double mn[2] = {1e300, 1e300}, mx[2] = {-1e300, -1e300};
+    for (int pt = 0; pt < 8; ++pt) {
+        double pb, pc;
+        if (!slab_corner_point(v, fr, AX, iu0, iu1, iv0, iv1, A0, S, pt, pb, pc)) return false;
+        mn[0] = fmin(mn[0], pb);
+        mx[0] = fmax(mx[0], pb);
+        mn[1] = fmin(mn[1], pc);
+        mx[1] = fmax(mx[1], pc);
+    }
+    const int nb = AX == 0 ? v.n1 : v.n0;
+    cell_range(mn[0], mx[0], nb, lo[0], hi[0]);
+    cell_range(mn[1], mx[1], v.n2, lo[1], hi[1]);
+    return true;
+}
+
+// Forward projection of one bundle of TILE_U x TILE_V rays.  The bundle
+// walks the volume in slabs of `slab` cells along the axis AX its rays
+// mostly travel (x or y): per slab the block copies the box of voxels its
+// samples can touch (slab_cells) into LDS with coalesced row reads, then
+// every lane takes its ray's samples whose cell lies in the slab from LDS.
+// The gathers thus hit LDS instead of the texture path; a sample outside
+// the staged box (never expected) reads global memory, so the result does
+// not depend on the box estimate.  A block whose rays do not all travel the
+// same way along AX (or that spans too many slabs) marches from global
+// memory.  Samples of a slab are summed in T and the slab sums in double;
+// the order depends only on the geometry, so p is bit-for-bit reproducible.
+template <typename T, int AX, bool SUMS>
+__global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int tiles_u, int slab,
+                                                     const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ f, T *__restrict__ p,
                                                      const T *__restrict__ y,
                                                      double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ sums) {
-    constexpr int SPLIT = 4;
+    constexpr int SPLIT = FWD_SPLIT;
+    constexpr int CAP = FWD_LDS_BYTES / (int)sizeof(T);
+    constexpr int ES = (int)sizeof(T);
+    __shared__ T box[CAP];
+    __shared__ int sbox[FWD_MAX_SLABS][4];
+    __shared__ int sred[3];
+    const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
+    const int nn[3] = {n0, n1, n2};
+    const int nu = fr.nu, nv = fr.nv;
     const int nb = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, nb);
     const int tu = bid % tiles_u, tv = bid / tiles_u;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int seg = lane & (SPLIT - 1), rl = lane / SPLIT;
-    const int iu = tu * TILE_U + (wave & 1) * 4 + (rl & 3);
-    const int iv = tv * TILE_V + (wave >> 1) * 4 + (rl >> 2);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int seg = lane % SPLIT, rl = lane / SPLIT;
+    const int iu = tu * TILE_U + (wave & 1) * FWD_WU + rl % FWD_WU;
+    const int iv = tv * TILE_V + (wave >> 1) * FWD_WV + rl / FWD_WU;
     const bool valid = iu < nu && iv < nv;
     const int pix = iv * nu + iu;
-    double acc = 0.0;
-    T dtr = (T)0;
+    RayRec<T> r;
     if (valid) {
-        const RayRec<T> r = rays[pix];
-        dtr = r.dt;
-        const T e[3] = {r.e[0], r.e[1], r.e[2]};
-        const T d[3] = {r.d[0], r.d[1], r.d[2]};
-        const __amdgpu_buffer_rsrc_t rf = make_rsrc(f, (uint32_t)((size_t)n0 * n1 * n2 * sizeof(T)));
-        constexpr int ES = (int)sizeof(T);
-        const int sb1 = n0 * ES, sb2 = n0 * n1 * ES, sb12 = sb1 + sb2;   // wave-uniform strides
-        T sh = (T)seg + (T)0.5;
-        for (int s = seg; s < r.n; s += SPLIT, sh += (T)SPLIT) {
+        r = rays[pix];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r.e[c] = r.d[c] = (T)0;
+        r.dt = (T)0;
+        r.n = 0;
+    }
+    const T e[3] = {r.e[0], r.e[1], r.e[2]};
+    const T d[3] = {r.d[0], r.d[1], r.d[2]};
+    const __amdgpu_buffer_rsrc_t rf = make_rsrc(f, (uint32_t)((size_t)n0 * n1 * n2 * sizeof(T)));
+    const int sb1 = n0 * ES, sb2 = n0 * n1 * ES;   // wave-uniform strides
+    const GridTop<T> top = grid_top<T>(n0, n1, n2);
+
+    // Slabs the bundle's samples span, and the direction they are crossed.
+    if (tid == 0) {
+        sred[0] = 0x7fffffff;
+        sred[1] = -1;
+        sred[2] = 0;
+    }
+    __syncthreads();
+    if (r.n > 0 && seg == 0 && slab > 0) {
+        int la0, la1;
+        T zz;
+        axis_cell(e[AX], d[AX], (T)0.5, top.t[AX], la0, zz);
+        axis_cell(e[AX], d[AX], (T)(r.n - 1) + (T)0.5, top.t[AX], la1, zz);
+        atomicMin(&sred[0], min(la0, la1) / slab);
+        atomicMax(&sred[1], max(la0, la1) / slab);
+        atomicOr(&sred[2], d[AX] > (T)0 ? 1 : (d[AX] < (T)0 ? 2 : 4));
+    }
+    __syncthreads();
+    const int kmin = sred[0], kmax = sred[1], votes = sred[2];
+    const bool use_slabs = (votes == 1 || votes == 2) && kmax - kmin < FWD_MAX_SLABS;
+
+    double acc = 0.0;
+    const T shn = (T)r.n;          // sample s exists iff s + 1/2 < n
+    T sh = (T)seg + (T)0.5;
+    if (use_slabs) {
+        const int iu0 = tu * TILE_U, iu1 = min(iu0 + TILE_U, nu) - 1;
+        const int iv0 = tv * TILE_V, iv1 = min(iv0 + TILE_V, nv) - 1;
+        // staged box of every slab: eight lanes per slab, one per corner ray
+        // and plane, reduced with shuffles (keeps the FP64 geometry out of
+        // the march's register budget)
+        const int nsl = kmax - kmin + 1;
+        for (int j0 = 0; j0 < nsl; j0 += 32) {
+            const int j = j0 + (tid >> 3), pt = tid & 7;
+            double mnb = 1e300, mxb = -1e300, mnc = 1e300, mxc = -1e300;
+            int ok = 1;
+            if (j < nsl) {
+                double pb = 0.0, pc = 0.0;
+                ok = slab_corner_point(vd, fr, AX, iu0, iu1, iv0, iv1, (kmin + j) * slab, slab, pt,
+                                       pb, pc);
+                mnb = mxb = pb;
+                mnc = mxc = pc;
+            }
+#pragma unroll
+            for (int m = 1; m < 8; m <<= 1) {
+                mnb = fmin(mnb, __shfl_xor(mnb, m, 64));
+                mxb = fmax(mxb, __shfl_xor(mxb, m, 64));
+                mnc = fmin(mnc, __shfl_xor(mnc, m, 64));
+                mxc = fmax(mxc, __shfl_xor(mxc, m, 64));
+                ok &= __shfl_xor(ok, m, 64);
+            }
+            if (j < nsl && pt == 0) {
+                int *sb = sbox[j];
+                if (ok) {
+                    constexpr int B = AX == 0 ? 1 : 0;
+                    cell_range(mnb, mxb, nn[B], sb[0], sb[1]);
+                    cell_range(mnc, mxc, n2, sb[2], sb[3]);
+                } else {
+                    sb[0] = 1;
+                    sb[1] = 0;   // empty: march this slab from global memory
+                    sb[2] = 1;
+                    sb[3] = 0;
+                }
+            }
+        }
+        // the lane's next sample, computed once and carried across slabs
+        int l[3];
+        T z[3];
+        bool have = sh < shn;
+        if (have) sample_cell(e, d, sh, top, l, z);
+        __syncthreads();
+        for (int i = 0; i < nsl; ++i) {
+            const int k = votes == 1 ? kmin + i : kmax - i;
+            const int A0 = k * slab;
+            const int *sb = sbox[k - kmin];
+            // staged voxel box [o, o + ext) per axis
+            int o[3], ext[3];
+            o[AX] = A0;
+            ext[AX] = min(A0 + slab, nn[AX] - 1) - A0 + 1;
+            constexpr int B = AX == 0 ? 1 : 0;
+            o[B] = sb[0];
+            ext[B] = sb[1] - sb[0] + 2;
+            o[2] = sb[2];
+            ext[2] = sb[3] - sb[2] + 2;
+            const bool staged = sb[0] <= sb[1] && sb[2] <= sb[3] && ext[0] <= CAP &&
+                                ext[1] <= CAP && ext[2] <= CAP && ext[0] * ext[1] <= CAP &&
+                                ext[0] * ext[1] * ext[2] <= CAP;
+            const int ex = ext[0], exy = ext[0] * ext[1];
+            if (staged) {
+                // element t of the box is voxel o + (t % ex, t / ex % ey, t / exy); the
+                // quotients are exact in float for t < 2^12 (rounding error well
+                // below the 0.5 / divisor margin of (t + 0.5) / divisor)
+                const int size = exy * ext[2];
+                const float iex = 1.0f / (float)ex, iey = 1.0f / (float)ext[1];
+                const int gbase = o[0] + n0 * (o[1] + n1 * o[2]);
+                for (int t = tid; t < size; t += 256) {
+                    const int q = (int)(((float)t + 0.5f) * iex);
+                    const int tx = t - __mul24(q, ex);
+                    const int tz = (int)(((float)q + 0.5f) * iey);
+                    const int ty = q - __mul24(tz, ext[1]);
+                    box[t] = buf_load(rf, (gbase + tx + __mul24(ty, n0) + tz * (n0 * n1)) * ES, 0, T());
+                }
+            }
+            __syncthreads();
+            // byte pitches of the box; offsets fit 24-bit products
+            const int px = ex * ES, pxy = exy * ES;
+            const char *boxb = (const char *)box;
+            T part = (T)0;   // this slab's samples, added to acc once
+            const T sh0 = sh;
+            bool miss = !staged;
+            if (staged) {
+                while (have && (unsigned)(l[AX] - A0) < (unsigned)slab) {
+                    // along AX the slab test already bounds the cell (l <= n - 2)
+                    constexpr int B2 = AX == 0 ? 1 : 0;
+                    const int lx = l[0] - o[0], ly = l[1] - o[1], lz = l[2] - o[2];
+                    const int lb = B2 == 0 ? lx : ly;
+                    const bool in = (unsigned)lb < (unsigned)(ext[B2] - 1) &&
+                                    (unsigned)lz < (unsigned)(ext[2] - 1);
+                    miss |= !in;
+                    const int off = in ? lx * ES + __mul24(ly, px) + __mul24(lz, pxy) : 0;
+                    const char *c = boxb + off;
+                    const T *c0 = (const T *)c, *c1 = (const T *)(c + px);
+                    const T *c2 = (const T *)(c + pxy), *c3 = (const T *)(c + pxy + px);
+                    part += trilinear(c0[0], c0[1], c1[0], c1[1], c2[0], c2[1], c3[0], c3[1], z);
+                    sh += (T)SPLIT;
+                    have = sh < shn;
+                    if (have) sample_cell(e, d, sh, top, l, z);
+                }
+            }
+            if (miss) {
+                // a sample outside the staged box (or no box): redo this lane's
+                // samples of the slab from global memory
+                part = (T)0;
+                sh = sh0;
+                have = sh < shn;
+                if (have) sample_cell(e, d, sh, top, l, z);
+                while (have && (unsigned)(l[AX] - A0) < (unsigned)slab) {
+                    part += gather_global(rf, (l[0] + n0 * (l[1] + n1 * l[2])) * ES, sb1, sb2, z);
+                    sh += (T)SPLIT;
+                    have = sh < shn;
+                    if (have) sample_cell(e, d, sh, top, l, z);
+                }
+            }
+            acc += (double)part;
+            __syncthreads();
+        }
+    } else {
+        for (; sh < shn; sh += (T)SPLIT) {
             int l[3];
             T z[3];
-            sample_cell(e, d, sh, n0, n1, n2, l, z);
-            const int vo = (l[0] + n0 * (l[1] + n1 * l[2])) * ES;
-            const T v000 = buf_load(rf, vo, 0, T()), v100 = buf_load(rf, vo + ES, 0, T());
-            const T v010 = buf_load(rf, vo, sb1, T()), v110 = buf_load(rf, vo + ES, sb1, T());
-            const T v001 = buf_load(rf, vo, sb2, T()), v101 = buf_load(rf, vo + ES, sb2, T());
-            const T v011 = buf_load(rf, vo, sb12, T()), v111 = buf_load(rf, vo + ES, sb12, T());
-            const T x00 = lerp_t(v000, v100, z[0]), x10 = lerp_t(v010, v110, z[0]);
-            const T x01 = lerp_t(v001, v101, z[0]), x11 = lerp_t(v011, v111, z[0]);
-            const T y0 = lerp_t(x00, x10, z[1]), y1 = lerp_t(x01, x11, z[1]);
-            acc += (double)lerp_t(y0, y1, z[2]);
+            sample_cell(e, d, sh, top, l, z);
+            acc += (double)gather_global(rf, (l[0] + n0 * (l[1] + n1 * l[2])) * ES, sb1, sb2, z);
         }
     }
-    // combine the four interleaved partial sums of a ray (same order in all
-    // four lanes, so they agree bit for bit)
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
+    // combine the SPLIT interleaved partial sums of a ray (same butterfly
+    // order in every lane of the group, so they agree bit for bit)
+#pragma unroll
+    for (int m = 1; m < SPLIT; m <<= 1) acc += __shfl_xor(acc, m, 64);
     double pv = 0.0;
     const bool writer = valid && seg == 0;
     if (writer) {
-        const T pt = (T)((double)dtr * acc);
+        const T pt = (T)((double)r.dt * acc);
         p[pix] = pt;
         pv = (double)pt;
     }
@@ -91,29 +350,82 @@ int drr_forward_blocks(int nu, int nv) {
     return ((nu + TILE_U - 1) / TILE_U) * ((nv + TILE_V - 1) / TILE_V);
 }
 
-hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, int nu, int nv, const void *rays,
-                              const void *f, void *p, const void *y, double *partials,
-                              uint32_t *counter, double *sums, hipStream_t s) {
-    const int tiles_u = (nu + TILE_U - 1) / TILE_U;
-    dim3 grid(drr_forward_blocks(nu, nv)), block(256);
+// Slab axis and thickness for a projection: the in-plane axis (x or y) the
+// central ray advances fastest along in index units, and the thickest slab
+// (32, 16 or 8 cells) whose staged box fits the LDS budget for bundles at
+// the centre, edges and corners of the detector.  slab 0 means "no slabs".
+static void forward_plan(const VolDims &v, const Frame &fr, int esize, int *axis, int *slab);
+
+ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr) {
+    ForwardPlan pl;
+    forward_plan(v, fr, dt == PCAS_F32 ? 4 : 8, &pl.axis, &pl.slab);
+    return pl;
+}
+
+static void forward_plan(const VolDims &v, const Frame &fr, int esize, int *axis, int *slab) {
+    const double ax = fabs(fr.en[0]) * v.inv_s[0], ay = fabs(fr.en[1]) * v.inv_s[1];
+    const int AX = ay > ax ? 1 : 0;
+    const int na = AX == 0 ? v.n0 : v.n1;
+    const int cap = FWD_LDS_BYTES / esize;
+    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U, tiles_v = (fr.nv + TILE_V - 1) / TILE_V;
+    *axis = AX;
+    *slab = 0;
+    for (int S = 32; S >= 8; S >>= 1) {
+        if ((na + S - 1) / S > FWD_MAX_SLABS) break;
+        bool fits = true;
+        for (int gv = 0; gv < 3 && fits; ++gv)
+            for (int gu = 0; gu < 3 && fits; ++gu) {
+                const int tu = gu * (tiles_u - 1) / 2, tv = gv * (tiles_v - 1) / 2;
+                const int iu0 = tu * TILE_U, iu1 = std::min(iu0 + TILE_U, fr.nu) - 1;
+                const int iv0 = tv * TILE_V, iv1 = std::min(iv0 + TILE_V, fr.nv) - 1;
+                for (int A0 = 0; A0 <= na - 2 && fits; A0 += S) {
+                    int lo[2], hi[2];
+                    if (!slab_cells_host(v, fr, AX, iu0, iu1, iv0, iv1, A0, S, lo, hi)) {
+                        fits = false;
+                        break;
+                    }
+                    const long long size = (long long)(S + 1) * (hi[0] - lo[0] + 2) * (hi[1] - lo[1] + 2);
+                    if (size > cap) fits = false;
+                }
+            }
+        if (fits) {
+            *slab = S;
+            return;
+        }
+    }
+}
+
+template <typename T, int AX>
+static void launch_fwd(dim3 grid, const VolDims &v, const Frame &fr, int tiles_u, int slab,
+                       const void *rays, const void *f, void *p, const void *y, double *partials,
+                       uint32_t *counter, double *sums, hipStream_t s) {
+    if (sums)
+        hipLaunchKernelGGL((k_drr_forward<T, AX, true>), grid, dim3(256), 0, s, v, fr, tiles_u, slab,
+                           (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, partials,
+                           counter, sums);
+    else
+        hipLaunchKernelGGL((k_drr_forward<T, AX, false>), grid, dim3(256), 0, s, v, fr, tiles_u,
+                           slab, (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)nullptr,
+                           nullptr, nullptr, nullptr);
+}
+
+hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                              const ForwardPlan &plan, const void *rays, const void *f, void *p,
+                              const void *y, double *partials, uint32_t *counter, double *sums,
+                              hipStream_t s) {
+    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
+    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
+    const int AX = plan.axis, slab = plan.slab;
     if (dt == PCAS_F32) {
-        if (sums)
-            hipLaunchKernelGGL((k_drr_forward<float, true>), grid, block, 0, s, v.n0, v.n1, v.n2, nu,
-                               nv, tiles_u, (const RayRec<float> *)rays, (const float *)f,
-                               (float *)p, (const float *)y, partials, counter, sums);
+        if (AX == 0)
+            launch_fwd<float, 0>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
         else
-            hipLaunchKernelGGL((k_drr_forward<float, false>), grid, block, 0, s, v.n0, v.n1, v.n2,
-                               nu, nv, tiles_u, (const RayRec<float> *)rays, (const float *)f,
-                               (float *)p, (const float *)nullptr, nullptr, nullptr, nullptr);
+            launch_fwd<float, 1>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
     } else {
-        if (sums)
-            hipLaunchKernelGGL((k_drr_forward<double, true>), grid, block, 0, s, v.n0, v.n1, v.n2,
-                               nu, nv, tiles_u, (const RayRec<double> *)rays, (const double *)f,
-                               (double *)p, (const double *)y, partials, counter, sums);
+        if (AX == 0)
+            launch_fwd<double, 0>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
         else
-            hipLaunchKernelGGL((k_drr_forward<double, false>), grid, block, 0, s, v.n0, v.n1, v.n2,
-                               nu, nv, tiles_u, (const RayRec<double> *)rays, (const double *)f,
-                               (double *)p, (const double *)nullptr, nullptr, nullptr, nullptr);
+            launch_fwd<double, 1>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
     }
     return hipGetLastError();
 }
@@ -196,7 +508,7 @@ __device__ __forceinline__ void flush_cell(unsigned long long *acc, int base, co
 // LDS when the cell changes.
 template <typename T>
 __device__ __forceinline__ void splat_ray(unsigned long long *acc, const RayRec<T> &r, T cst,
-                                          int s0, int s1, int n0, int n1, int n2,
+                                          int s0, int s1, const GridTop<T> &top,
                                           const int (&lo)[3], const int (&hi)[3], double S) {
     const T e[3] = {r.e[0], r.e[1], r.e[2]};
     const T d[3] = {r.d[0], r.d[1], r.d[2]};
@@ -208,7 +520,7 @@ __device__ __forceinline__ void splat_ray(unsigned long long *acc, const RayRec<
     for (int s = s0; s <= s1; ++s, sh += (T)1) {
         int l[3];
         T z[3];
-        sample_cell(e, d, sh, n0, n1, n2, l, z);
+        sample_cell(e, d, sh, top, l, z);
         const int lx = l[0] - lo[0] + 1, ly = l[1] - lo[1] + 1, lz = l[2] - lo[2] + 1;
         const bool touches = lx >= 0 && lx <= hi[0] - lo[0] + 1 && ly >= 0 &&
                              ly <= hi[1] - lo[1] + 1 && lz >= 0 && lz <= hi[2] - lo[2] + 1;
@@ -324,6 +636,7 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
         Sd = fmin(fmin(lim_cell, lim_vox), 1e300);
     }
 
+    const GridTop<T> top = grid_top<T>(n0, n1, n2);
     const T lob[3] = {(T)(lo[0] - 1), (T)(lo[1] - 1), (T)(lo[2] - 1)};
     const T hib[3] = {(T)(hi[0] + 1), (T)(hi[1] + 1), (T)(hi[2] + 1)};
     // Candidate batches interleave the footprint: lane (lu, lv) of batch
@@ -371,7 +684,7 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
         __builtin_amdgcn_wave_barrier();
         if (lane < qn) {
             const RayRec<T> r = rays[qp[lane]];
-            splat_ray(acc, r, qc[lane], qa[lane], qb[lane], n0, n1, n2, lo, hi, Sd);
+            splat_ray(acc, r, qc[lane], qa[lane], qb[lane], top, lo, hi, Sd);
         }
         const int rest = qn > 64 ? qn - 64 : 0;
         int mp = 0, ma = 0, mb = 0;
