@@ -3,7 +3,8 @@
 
 One step = one call of solve_projection on the clinical-size workload: ray
 table, then CG iterations of (DVF synthesis + warp, cone-beam projection,
-intensity fit and objective, back-projection, Jacobian chain), then the
+intensity fit and objective; at accepted points the gradient as the
+projections of the K Jacobian volumes against the residual), then the
 tumour-position inversion.  Inputs (reference volume, mean field and K = 3
 modes, measured projection) are resident in HBM before the timed region.
 
@@ -32,12 +33,16 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # Algorithmic flops per projection sample.  Forward: position e + sh d
 # (3 fma = 6), fractions (3), trilinear value as 7 lerps of 3 flops (21),
 # accumulation (1) = 31.  Back-projection: position (6), fractions (3),
-# corner weights (9), 8 weighted accumulations (16) = 34.
-FLOPS_PER_SAMPLE = {"drr_forward": 31.0, "drr_adjoint": 34.0}
+# corner weights (9), 8 weighted accumulations (16) = 34.  Projection of K
+# volumes at once: position and fractions once (9), then 22 per volume.
+def flops_per_sample(kernel: str, K: int) -> float:
+    return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
 
 
-KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip", "warp_pca": "k_warp.hip",
-                  "grad_w": "k_grad.hip"}
+SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_forward_dot")
+KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
+                  "drr_forward_dot": "k_drr.hip", "warp_pca": "k_warp.hip",
+                  "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
 
 
 def kernel_digest(kernel: str) -> str:
@@ -241,6 +246,31 @@ def stream_mode(case, dev, dt, args) -> int:
     return 0
 
 
+def adjoint_alone(case, dev, S: int) -> dict:
+    """The back-projection is not on the default gradient route; time it on
+    its own (HIP events on the current stream) for the DRR+adjoint figure."""
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+
+    es = 4 if case.dtype == "f32" else 8
+    r = dev["y"].clone()
+    bp = B.drr_adjoint(case.vol, case.proj, dev["rays"], r)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.drr_adjoint(case.vol, case.proj, dev["rays"], r, out=bp)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    a = float(np.median(ts))
+    return {"avg_ms": a, "launches": len(ts), "Gsamples_s": S / (a * 1e-3) / 1e9,
+            "effective_GBs": 8 * es * S / (a * 1e-3) / 1e9, "timed": "alone"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,8 +350,10 @@ def main() -> int:
     alg_bytes = {
         "warp_pca": (3 + 3 * K + 2) * es * N,
         "grad_w": (3 + 3 * K + 2) * es * N,
+        "jacobian": (3 + 3 * K + 1 + K) * es * N,
         "drr_forward": es * N + 32 * M + 2 * es * M,
         "drr_adjoint": es * N + 32 * M + 2 * es * M,
+        "drr_forward_dot": K * es * N + 32 * M + 2 * es * M,
     }
     kernel_stats = {}
     for k, a in avg.items():
@@ -330,9 +362,10 @@ def main() -> int:
         d = {"avg_ms": a, "launches": kn[k], "total_ms": kms[k]}
         if k in alg_bytes:
             d["alg_GBs"] = alg_bytes[k] / (a * 1e-3) / 1e9
-        if k in ("drr_forward", "drr_adjoint"):
+        if k in SAMPLE_KERNELS:
+            nvol = K if k == "drr_forward_dot" else 1
             d["Gsamples_s"] = S / (a * 1e-3) / 1e9
-            d["effective_GBs"] = 8 * es * S / (a * 1e-3) / 1e9
+            d["effective_GBs"] = 8 * es * nvol * S / (a * 1e-3) / 1e9
         kernel_stats[k] = d
     measured = [k for k in kms if kn.get(k)]
     dominant = max(measured, key=lambda k: kms[k]) if measured else None
@@ -341,13 +374,13 @@ def main() -> int:
     wl = "clinical" if args.workload == "clinical" else args.workload
     traffic = measured_traffic(dominant, wl) if dominant else None
     if dominant in alg_bytes and avg.get(dominant):
-        if dominant in ("warp_pca", "grad_w"):
+        if dominant in ("warp_pca", "grad_w", "jacobian"):
             ach = alg_bytes[dominant] / (avg[dominant] * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant}
         else:
             # gather / VALU bound: algorithmic flops per projection sample
-            ach = FLOPS_PER_SAMPLE[dominant] * S / (avg[dominant] * 1e-3) / 1e12
+            ach = flops_per_sample(dominant, K) * S / (avg[dominant] * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": ach, "peak": VALU_F32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": traffic,
                         "kernel": dominant}
@@ -358,7 +391,7 @@ def main() -> int:
         cpu = cpu_baseline(case, rep["n_fevals"], rep["n_grads"], args.cpu_baseline_s)
 
     drr = kernel_stats.get("drr_forward", {})
-    adj = kernel_stats.get("drr_adjoint", {})
+    adj = kernel_stats.get("drr_adjoint") or adjoint_alone(case, dev, S)
     out = {
         "metric": METRIC,
         "value": args.steps / total,

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 1
+#define PCAS_ABI_VERSION 2
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -103,7 +103,12 @@ typedef struct {
     double locate_tol;     /* mm */
     double c0_mm[3];       /* tumour centre in the reference image (mm) */
     int32_t profile;       /* 1: time every kernel with HIP events (report.kernel_ms) */
-    int32_t reserved;
+    int32_t grad_mode;     /* how dJ/dw is formed (the same quantity either way, by the
+                              adjoint identity <P^T r, J_k> = <r, P J_k>):
+                              0: project the K Jacobian volumes J_k = U_k^T (df/dx) and take
+                                 g_k = 2 <r, P J_k> (gathers only; the default)
+                              1: back-project r, then g = 2 U^T (df/dx) P^T r (drr_adjoint
+                                 followed by grad_w) */
     double ftol_rel;       /* method 1: a rejected trial with |J_t - J| <= ftol_rel J ends the
                               solve as converged (the change is below the objective's rounding
                               noise); < 0 selects 1e-8 for PCAS_F32 and 0 for PCAS_F64 */
@@ -112,22 +117,23 @@ typedef struct {
 /* kernel classes of pcas_report.kernel_ms / kernel_launches */
 enum {
     PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
-    PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7
+    PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
+    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_CLASSES = 10
 };
 
 typedef struct {
     int32_t status;        /* PCAS_STOP_* */
     int32_t iters;         /* accepted iterations */
     int32_t n_fevals;      /* forward evaluations (warp + projection) */
-    int32_t n_grads;       /* gradient evaluations (adjoint + Jacobian chain) */
+    int32_t n_grads;       /* gradient evaluations (see opts.grad_mode) */
     double J0, J;          /* objective at w0 and at the returned w */
     double a, b;           /* intensity fit at the returned w */
     double gnorm0, gnorm;  /* ||dJ/dw|| at w0 and at the returned w */
     double tumour_mm[3];   /* located tumour position (if opts.locate) */
     int32_t locate_iters;  /* fixed-point iterations, -1 if not converged */
     int32_t reserved;
-    double kernel_ms[8];   /* with opts.profile: summed kernel time per class (ms) */
-    int32_t kernel_launches[8];
+    double kernel_ms[PCAS_K_CLASSES];   /* with opts.profile: summed kernel time per class (ms) */
+    int32_t kernel_launches[PCAS_K_CLASSES];
 } pcas_report;
 
 /* ---- utilities --------------------------------------------------------- */
@@ -222,6 +228,17 @@ int grad_w(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, con
 int tumour_position(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *mean,
                     const void *U, const double *w, const double c0_mm[3], double tol,
                     int32_t max_iter, double *out, void *stream);
+
+/* ---- a5 + a6 + a7: objective and gradient at one point ------------------
+ * J(w) of Eq. 2 with (a, b) from Eq. A.1 (fit_intensity = 1) or a = 1, b = 0,
+ * and dJ/dw at that (a, b), exactly as solve_projection forms them, the
+ * gradient by the route grad_mode selects (see pcas_opts.grad_mode).
+ * Arguments as solve_projection; w: host double[K];
+ * out: host double[3 + K] = { J, a, b, g_0 .. g_{K-1} }.  Synchronous. */
+int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, int32_t K,
+                       const void *f0, const void *mean, const void *U, const void *y,
+                       const double *w, int32_t fit_intensity, int32_t grad_mode,
+                       void *workspace, size_t workspace_bytes, double *out, void *stream);
 
 /* ---- a1-a9: the per-projection solve -------------------------------------
  * Minimise Eq. 2 over w from w0 with the method in opts (Appendix algorithm

@@ -25,7 +25,7 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
            "warp_pca", "drr_forward", "drr_adjoint", "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
-           "solve_projection_workspace", "solve_projection")
+           "objective_gradient", "solve_projection_workspace", "solve_projection")
 
 
 class PcasError(RuntimeError):
@@ -58,7 +58,7 @@ class Opts(ctypes.Structure):
                 ("beta_lo", ctypes.c_double), ("xtol", ctypes.c_double),
                 ("locate", ctypes.c_int32), ("locate_max_iter", ctypes.c_int32),
                 ("locate_tol", ctypes.c_double), ("c0_mm", ctypes.c_double * 3),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
                 ("ftol_rel", ctypes.c_double)]
 
 
@@ -68,12 +68,12 @@ class Report(ctypes.Structure):
                 ("J0", ctypes.c_double), ("J", ctypes.c_double), ("a", ctypes.c_double),
                 ("b", ctypes.c_double), ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double),
                 ("tumour_mm", ctypes.c_double * 3), ("locate_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
-                ("kernel_launches", ctypes.c_int32 * 8)]
+                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 10),
+                ("kernel_launches", ctypes.c_int32 * 10)]
 
 
 KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint", "grad_w",
-                  "tumour_position", "y_sums")
+                  "tumour_position", "y_sums", "jacobian", "drr_forward_dot")
 
 
 _lib = None
@@ -108,6 +108,8 @@ def lib():
             "grad_w_workspace_bytes": (SZ, [I32, VP, I32]),
             "grad_w": (I32, [I32, VP, I32, P, P, P, DP, P, P, P, SZ, P]),
             "tumour_position": (I32, [I32, VP, I32, P, P, DP, DP, D, I32, P, P]),
+            "objective_gradient": (I32, [I32, VP, PP, I32, P, P, P, P, DP, I32, I32, P, SZ, DP,
+                                         P]),
             "solve_projection_workspace": (SZ, [I32, VP, PP, I32]),
             "solve_projection": (I32, [I32, VP, PP, I32, P, P, P, P, DP, ctypes.POINTER(Opts), P,
                                        SZ, DP, ctypes.POINTER(Report), P]),
@@ -352,7 +354,7 @@ def _apply(o: Opts, overrides) -> Opts:
             for c in range(3):
                 o.c0_mm[c] = float(v[c])
         elif k in ("method", "max_iter", "fit_intensity", "max_backtracks", "locate",
-                   "locate_max_iter", "profile"):
+                   "locate_max_iter", "profile", "grad_mode"):
             setattr(o, k, int(v))
         else:
             setattr(o, k, float(v))
@@ -397,3 +399,27 @@ def solve_projection(vol, proj, f0, mean, U, y, w0, opts: Optional[Opts] = None,
                                   w_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   ctypes.byref(rep), _stream(stream)), "solve_projection")
     return w_out, report_dict(rep)
+
+
+def objective_gradient(vol, proj, f0, mean, U, y, w, fit_intensity: bool = True,
+                       grad_mode: int = 0, workspace=None, stream=None):
+    """a5 + a6 + a7 at one point: (J, a, b, g as float64 numpy [K]) exactly as
+    the solver forms them (grad_mode 0: projected Jacobian volumes; 1:
+    back-projection + Jacobian chain).  Synchronous."""
+    torch = _torch()
+    K = _K_of(U, vol)
+    code = _dtype_code(f0)
+    cv, cp = c_vol(vol), c_proj(proj)
+    need = lib().solve_projection_workspace(code, ctypes.byref(cv), ctypes.byref(cp), K)
+    if workspace is None:
+        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=f0.device)
+    _, wp = _host_doubles(w, K)
+    out = np.zeros(3 + K)
+    _check(lib().objective_gradient(code, ctypes.byref(cv), ctypes.byref(cp), K, _dev(f0, "f0"),
+                                    _dev(mean, "mean", f0.dtype), _dev(U, "U", f0.dtype),
+                                    _dev(y, "y", f0.dtype), wp, int(bool(fit_intensity)),
+                                    int(grad_mode), _dev(workspace, "workspace"),
+                                    workspace.numel(),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _stream(stream)), "objective_gradient")
+    return float(out[0]), float(out[1]), float(out[2]), out[3:].copy()

@@ -145,7 +145,7 @@ int readback(double *host, const double *dev, int count, hipStream_t s) {
 // ---- workspace layouts ---------------------------------------------------
 
 struct SolveWs {
-    size_t rays, f, p, bp, partials, counters, scalars, total;
+    size_t rays, f, p, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
 };
 
 int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
@@ -155,14 +155,14 @@ int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
     return m;
 }
 
-SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p) {
+SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p, int K) {
     SolveWs L;
     const size_t M = (size_t)npix_of(p), N = (size_t)nvox_of(v), es = esize(dt);
     size_t off = 0;
     L.rays = off; off += align256(M * rec_size(dt));
     L.f = off; off += align256(N * es);
     L.p = off; off += align256(M * es);
-    L.bp = off; off += align256(N * es);
+    L.vol2 = off; off += align256((size_t)(K > 1 ? K : 1) * N * es);
     L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
     L.counters = off; off += 256;
     L.scalars = off; off += align256(64 * sizeof(double));
@@ -173,6 +173,7 @@ SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p) {
 int check_opts(const pcas_opts *o) {
     if (!o) return PCAS_EINVAL;
     if (o->method != 0 && o->method != 1) return PCAS_EINVAL;
+    if (o->grad_mode != 0 && o->grad_mode != 1) return PCAS_EINVAL;
     if (o->max_iter < 0 || o->max_backtracks < 1 || o->locate_max_iter < 1) return PCAS_EINVAL;
     if (!(o->mu0 > 0.0) || !(o->alpha > 0.0 && o->alpha < 1.0) || !(o->beta > 0.0 && o->beta < 1.0))
         return PCAS_EINVAL;
@@ -294,7 +295,7 @@ int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     if (!rays || !aligned(rays, 16) || !f || !p_out) return PCAS_EINVAL;
     const VolDims vd = make_dims(vol);
     const Frame fr = make_frame(proj);
-    HIPCHK(launch_drr_forward(dtype, vd, fr, plan_drr_forward(dtype, vd, fr), rays, f, p_out,
+    HIPCHK(launch_drr_forward(dtype, vd, fr, plan_drr_forward(dtype, vd, fr, 1), rays, f, p_out,
                               nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream));
     return PCAS_OK;
 }
@@ -382,9 +383,10 @@ int tumour_position(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void
 
 size_t solve_projection_workspace(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
                                   int32_t K) {
-    (void)K;
-    if (!dtype_ok(dtype) || check_vol(vol) != PCAS_OK || check_proj(proj, vol) != PCAS_OK) return 0;
-    return solve_layout(dtype, vol, proj).total;
+    if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K || check_vol(vol) != PCAS_OK ||
+        check_proj(proj, vol) != PCAS_OK)
+        return 0;
+    return solve_layout(dtype, vol, proj, K).total;
 }
 
 }  // extern "C"
@@ -399,8 +401,8 @@ thread_local std::vector<hipEvent_t> t_events;
 
 struct Profile {
     bool on = false;
-    double ms[8] = {0};
-    int n[8] = {0};
+    double ms[PCAS_K_CLASSES] = {0};
+    int n[PCAS_K_CLASSES] = {0};
     struct Pending {
         int cls;
         size_t a, b;
@@ -437,8 +439,9 @@ struct Solver {
     pcas_dtype dt;
     VolDims vd;
     Frame fr;
-    ForwardPlan fplan;
+    ForwardPlan fplan, fplan_k;   // projection of f; of the K Jacobian volumes
     int K;
+    int grad_mode = 0;
     int64_t M;
     const void *f0, *mean, *U, *y;
     char *ws;
@@ -515,20 +518,73 @@ struct Solver {
         return residual(ab_fixed, J, a, b);
     }
 
-    // Gradient at the w whose projection is in the p buffer.
+    // Gradient at the w whose projection is in the p buffer, at (a, b).
     int gradient(const double *w, double a, double b, double *g) {
-        HIPCHK(timed(PCAS_K_ADJOINT, [&] {
-            return launch_drr_adjoint(dt, vd, fr, ws + L.rays, ws + L.p, y, a, b, ws + L.bp, s);
-        }));
-        HIPCHK(timed(PCAS_K_GRAD, [&] {
-            return launch_grad_w(dt, vd, K, f0, mean, U, w, ws + L.bp,
-                                 (double *)(ws + L.partials), &counters()[1], scal() + 8, s);
-        }));
+        if (grad_mode == 0) {
+            HIPCHK(timed(PCAS_K_JACOBIAN, [&] {
+                return launch_jacobian(dt, vd, K, f0, mean, U, w, ws + L.vol2, s);
+            }));
+            HIPCHK(timed(PCAS_K_DRR_DOT, [&] {
+                return launch_drr_forward_dot(dt, vd, fr, fplan_k, K, ws + L.rays, ws + L.vol2,
+                                              ws + L.p, y, a, b, (double *)(ws + L.partials),
+                                              &counters()[1], scal() + 8, s);
+            }));
+        } else {
+            HIPCHK(timed(PCAS_K_ADJOINT, [&] {
+                return launch_drr_adjoint(dt, vd, fr, ws + L.rays, ws + L.p, y, a, b, ws + L.vol2, s);
+            }));
+            HIPCHK(timed(PCAS_K_GRAD, [&] {
+                return launch_grad_w(dt, vd, K, f0, mean, U, w, ws + L.vol2,
+                                     (double *)(ws + L.partials), &counters()[1], scal() + 8, s);
+            }));
+        }
         ++n_grads;
         int st = sync_read(g, scal() + 8, K);
         if (st) return st;
         for (int k = 0; k < K; ++k)
             if (!isfinite(g[k])) return PCAS_ENONFINITE;
+        return PCAS_OK;
+    }
+
+    // Everything a solve needs before its first evaluation: the ray table,
+    // the measured image's sums and the fit's solvability.
+    int prepare(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, int32_t K_,
+                const void *f0_, const void *mean_, const void *U_, const void *y_, int fit_,
+                int grad_mode_, bool profile, void *workspace, void *stream) {
+        dt = dtype;
+        vd = make_dims(vol);
+        fr = make_frame(proj);
+        K = K_;
+        grad_mode = grad_mode_;
+        fplan = plan_drr_forward(dtype, vd, fr, 1);
+        fplan_k = plan_drr_forward(dtype, vd, fr, K_);
+        M = npix_of(proj);
+        f0 = f0_;
+        mean = mean_;
+        U = U_;
+        y = y_;
+        ws = (char *)workspace;
+        L = solve_layout(dtype, vol, proj, K_);
+        s = (hipStream_t)stream;
+        fit = fit_ ? 1 : 0;
+        prof.on = profile;
+        HIPCHK(launch_fill_u32(counters(), 64, 0u, s));
+        HIPCHK(timed(PCAS_K_RAYS, [&] { return launch_ray_table(dt, vd, fr, ws + L.rays, s); }));
+        // sums of the measured image: (sum y, sum y^2, ., ., .)
+        HIPCHK(timed(PCAS_K_YSUMS, [&] {
+            return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],
+                                    scal() + 16, s);
+        }));
+        double ys[5];
+        int st = sync_read(ys, scal() + 16, 5);
+        if (st) return st;
+        if (!isfinite(ys[0]) || !isfinite(ys[2])) return PCAS_ENONFINITE;
+        sy = ys[0];
+        syy = ys[2];
+        if (fit) {
+            const double m = (double)M, det = syy * m - sy * sy;
+            if (!(fabs(det) > 1e-12 * syy * m)) return PCAS_ESINGULAR;
+        }
         return PCAS_OK;
     }
 };
@@ -688,46 +744,15 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
     if (!f0 || !U || !y || !w0 || !w_out || !report) return PCAS_EINVAL;
     if ((st = check_opts(opts))) return st;
     if (!finite_vec(w0, K)) return PCAS_ENONFINITE;
-    const SolveWs L = solve_layout(dtype, vol, proj);
+    const SolveWs L = solve_layout(dtype, vol, proj, K);
     if (!workspace || !aligned(workspace, 256) || workspace_bytes < L.total) return PCAS_EWORKSPACE;
 
     memset(report, 0, sizeof(*report));
     report->locate_iters = -1;
     Solver S;
-    S.dt = dtype;
-    S.vd = make_dims(vol);
-    S.fr = make_frame(proj);
-    S.fplan = plan_drr_forward(dtype, S.vd, S.fr);
-    S.K = K;
-    S.M = npix_of(proj);
-    S.f0 = f0;
-    S.mean = mean;
-    S.U = U;
-    S.y = y;
-    S.ws = (char *)workspace;
-    S.L = L;
-    S.s = (hipStream_t)stream;
-    S.fit = opts->fit_intensity ? 1 : 0;
-
-    S.prof.on = opts->profile != 0;
-    HIPCHK(launch_fill_u32(S.counters(), 64, 0u, S.s));
-    HIPCHK(S.timed(PCAS_K_RAYS, [&] {
-        return launch_ray_table(dtype, S.vd, S.fr, S.ws + L.rays, S.s);
-    }));
-    // sums of the measured image: (sum y, sum y^2, ., ., .)
-    HIPCHK(S.timed(PCAS_K_YSUMS, [&] {
-        return launch_pair_sums(dtype, S.M, y, y, (double *)(S.ws + L.partials), &S.counters()[2],
-                                S.scal() + 16, S.s);
-    }));
-    double ys[5];
-    if ((st = S.sync_read(ys, S.scal() + 16, 5))) return st;
-    if (!isfinite(ys[0]) || !isfinite(ys[2])) return PCAS_ENONFINITE;
-    S.sy = ys[0];
-    S.syy = ys[2];
-    if (S.fit) {
-        const double m = (double)S.M, det = S.syy * m - S.sy * S.sy;
-        if (!(fabs(det) > 1e-12 * S.syy * m)) return PCAS_ESINGULAR;
-    }
+    if ((st = S.prepare(dtype, vol, proj, K, f0, mean, U, y, opts->fit_intensity, opts->grad_mode,
+                        opts->profile != 0, workspace, stream)))
+        return st;
 
     double w[PCAS_MAX_K];
     for (int k = 0; k < K; ++k) w[k] = w0[k];
@@ -747,9 +772,37 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
         for (int c = 0; c < 3; ++c) report->tumour_mm[c] = loc[c];
         report->locate_iters = (int32_t)loc[3];
     }
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < PCAS_K_CLASSES; ++c) {
         report->kernel_ms[c] = S.prof.ms[c];
         report->kernel_launches[c] = S.prof.n[c];
     }
+    return PCAS_OK;
+}
+
+extern "C" int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
+                                  int32_t K, const void *f0, const void *mean, const void *U,
+                                  const void *y, const double *w, int32_t fit_intensity,
+                                  int32_t grad_mode, void *workspace, size_t workspace_bytes,
+                                  double *out, void *stream) {
+    if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K) return PCAS_EINVAL;
+    int st = check_vol(vol);
+    if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
+    if ((st = check_proj(proj, vol))) return st;
+    if (!f0 || !U || !y || !w || !out) return PCAS_EINVAL;
+    if (grad_mode != 0 && grad_mode != 1) return PCAS_EINVAL;
+    if (!finite_vec(w, K)) return PCAS_ENONFINITE;
+    const SolveWs L = solve_layout(dtype, vol, proj, K);
+    if (!workspace || !aligned(workspace, 256) || workspace_bytes < L.total) return PCAS_EWORKSPACE;
+    Solver S;
+    if ((st = S.prepare(dtype, vol, proj, K, f0, mean, U, y, fit_intensity, grad_mode, false,
+                        workspace, stream)))
+        return st;
+    double J, a, b;
+    if ((st = S.evaluate(w, nullptr, &J, &a, &b))) return st;
+    if ((st = S.gradient(w, a, b, out + 3))) return st;
+    out[0] = J;
+    out[1] = a;
+    out[2] = b;
     return PCAS_OK;
 }

@@ -103,17 +103,31 @@ int drr_forward_blocks(int nu, int nv);
 struct ForwardPlan {
     int axis = 0, slab = 0;
 };
-ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr);
+ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr, int nvol);
 hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
                               const ForwardPlan &plan, const void *rays, const void *f, void *p,
                               const void *y, double *partials, uint32_t *counter, double *sums,
                               hipStream_t s);
+// Projections of the K volumes J[k][voxel] (plan for nvol = K) against the
+// residual of the stored projection p: g_out[k] = 2 sum_rays (p - a y - b)
+// (P J_k); partials needs drr_forward_blocks() * RED_SLOTS doubles, counter
+// one zeroed uint32 (left zeroed on exit).
+hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                                  const ForwardPlan &plan, int K, const void *rays, const void *J,
+                                  const void *p, const void *y, double a, double b,
+                                  double *partials, uint32_t *counter, double *g_out,
+                                  hipStream_t s);
 
 // Back-projection.  If y != nullptr the residual r = p - a*y - b is formed
 // on the fly from p (passed as r_or_p); otherwise r_or_p is r.
 hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *rays,
                               const void *r_or_p, const void *y, double a, double b, void *bp,
                               hipStream_t s);
+
+// J[k][v] = sum_c U_kc(v) df/dx_c(v) at w (Eq. A.8 chain per voxel).
+hipError_t launch_jacobian(pcas_dtype dt, const VolDims &v, int K, const void *f0,
+                           const void *mean, const void *U, const double *w, void *J,
+                           hipStream_t s);
 
 int grad_w_blocks(int64_t N);
 hipError_t launch_grad_w(pcas_dtype dt, const VolDims &v, int K, const void *f0, const void *mean,

@@ -125,32 +125,47 @@ static bool slab_cells_host(const VolDims &v, const Frame &fr, int AX, int iu0, 
     return true;
 }
 
-// Forward projection of one bundle of TILE_U x TILE_V rays.  The bundle
-// walks the volume in slabs of `slab` cells along the axis AX its rays
-// mostly travel (x or y): per slab the block copies the box of voxels its
-// samples can touch (slab_cells) into LDS with coalesced row reads, then
-// every lane takes its ray's samples whose cell lies in the slab from LDS.
-// The gathers thus hit LDS instead of the texture path; a sample outside
-// the staged box (never expected) reads global memory, so the result does
-// not depend on the box estimate.  A block whose rays do not all travel the
-// same way along AX (or that spans too many slabs) marches from global
-// memory.  Samples of a slab are summed in T and the slab sums in double;
-// the order depends only on the geometry, so p is bit-for-bit reproducible.
-template <typename T, int AX, bool SUMS>
+// What the projection kernel does with each ray's value.
+enum { FWD_WRITE = 0, FWD_SUMS = 1, FWD_DOT = 2 };
+
+// LDS budget of the staged boxes: one volume 16 KB, several 32 KB.
+constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_LDS_BYTES; }
+
+// Forward projection of one bundle of TILE_U x TILE_V rays through NV
+// volumes f[v * N + voxel] at once (same rays, same samples, same weights).
+// The bundle walks the volume in slabs of `slab` cells along the axis AX
+// its rays mostly travel (x or y): per slab the block copies the box of
+// voxels its samples can touch (slab boxes from the bundle's corner rays)
+// into LDS with coalesced row reads, then every lane takes its ray's samples
+// whose cell lies in the slab from LDS.  The gathers thus hit LDS instead of
+// the texture path; a lane with a sample outside the staged box (never
+// expected) redoes that slab from global memory, so the result does not
+// depend on the box estimate.  A block whose rays do not all travel the same
+// way along AX (or that spans too many slabs) marches from global memory.
+// Samples of a slab are summed in T and the slab sums in double; the order
+// depends only on the geometry, so results are bit-for-bit reproducible.
+//
+// MODE FWD_WRITE / FWD_SUMS (NV = 1): p = P f, and for FWD_SUMS also
+// (sum p, sum p y, sum p^2) into out[0..2].  MODE FWD_DOT: the ray values
+// q_v = (P f_v) are not stored; out[v] = 2 sum_rays r q_v with the residual
+// r = p - a y - b of the stored projection p.
+template <typename T, int AX, int NV, int MODE>
 __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int tiles_u, int slab,
                                                      const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ f, T *__restrict__ p,
-                                                     const T *__restrict__ y,
+                                                     const T *__restrict__ y, double fa, double fb,
                                                      double *__restrict__ partials,
-                                                     uint32_t *counter, double *__restrict__ sums) {
+                                                     uint32_t *counter, double *__restrict__ out) {
     constexpr int SPLIT = FWD_SPLIT;
-    constexpr int CAP = FWD_LDS_BYTES / (int)sizeof(T);
+    constexpr int CAPT = fwd_lds_bytes(NV) / (int)sizeof(T);   // all volumes
+    constexpr int CAP = CAPT / NV;                               // one volume's box
     constexpr int ES = (int)sizeof(T);
-    __shared__ T box[CAP];
+    __shared__ T box[CAPT];
     __shared__ int sbox[FWD_MAX_SLABS][4];
     __shared__ int sred[3];
     const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
     const int nn[3] = {n0, n1, n2};
+    const int64_t N = (int64_t)n0 * n1 * n2;
     const int nu = fr.nu, nv = fr.nv;
     const int nb = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, nb);
@@ -172,7 +187,9 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
     }
     const T e[3] = {r.e[0], r.e[1], r.e[2]};
     const T d[3] = {r.d[0], r.d[1], r.d[2]};
-    const __amdgpu_buffer_rsrc_t rf = make_rsrc(f, (uint32_t)((size_t)n0 * n1 * n2 * sizeof(T)));
+    __amdgpu_buffer_rsrc_t rf[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rf[v] = make_rsrc(f + v * N, (uint32_t)(N * ES));
     const int sb1 = n0 * ES, sb2 = n0 * n1 * ES;   // wave-uniform strides
     const GridTop<T> top = grid_top<T>(n0, n1, n2);
 
@@ -196,7 +213,9 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
     const int kmin = sred[0], kmax = sred[1], votes = sred[2];
     const bool use_slabs = (votes == 1 || votes == 2) && kmax - kmin < FWD_MAX_SLABS;
 
-    double acc = 0.0;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     const T shn = (T)r.n;          // sample s exists iff s + 1/2 < n
     T sh = (T)seg + (T)0.5;
     if (use_slabs) {
@@ -262,11 +281,11 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
                                 ext[1] <= CAP && ext[2] <= CAP && ext[0] * ext[1] <= CAP &&
                                 ext[0] * ext[1] * ext[2] <= CAP;
             const int ex = ext[0], exy = ext[0] * ext[1];
+            const int size = exy * ext[2];
             if (staged) {
-                // element t of the box is voxel o + (t % ex, t / ex % ey, t / exy); the
-                // quotients are exact in float for t < 2^12 (rounding error well
+                // element t of a box is voxel o + (t % ex, t / ex % ey, t / exy); the
+                // quotients are exact in float for t < 2^13 (rounding error well
                 // below the 0.5 / divisor margin of (t + 0.5) / divisor)
-                const int size = exy * ext[2];
                 const float iex = 1.0f / (float)ex, iey = 1.0f / (float)ext[1];
                 const int gbase = o[0] + n0 * (o[1] + n1 * o[2]);
                 for (int t = tid; t < size; t += 256) {
@@ -274,14 +293,18 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
                     const int tx = t - __mul24(q, ex);
                     const int tz = (int)(((float)q + 0.5f) * iey);
                     const int ty = q - __mul24(tz, ext[1]);
-                    box[t] = buf_load(rf, (gbase + tx + __mul24(ty, n0) + tz * (n0 * n1)) * ES, 0, T());
+                    const int go = (gbase + tx + __mul24(ty, n0) + tz * (n0 * n1)) * ES;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) box[v * size + t] = buf_load(rf[v], go, 0, T());
                 }
             }
             __syncthreads();
             // byte pitches of the box; offsets fit 24-bit products
-            const int px = ex * ES, pxy = exy * ES;
+            const int px = ex * ES, pxy = exy * ES, pv = size * ES;
             const char *boxb = (const char *)box;
-            T part = (T)0;   // this slab's samples, added to acc once
+            T part[NV];   // this slab's samples, added to acc once
+#pragma unroll
+            for (int v = 0; v < NV; ++v) part[v] = (T)0;
             const T sh0 = sh;
             bool miss = !staged;
             if (staged) {
@@ -294,10 +317,13 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
                                     (unsigned)lz < (unsigned)(ext[2] - 1);
                     miss |= !in;
                     const int off = in ? lx * ES + __mul24(ly, px) + __mul24(lz, pxy) : 0;
-                    const char *c = boxb + off;
-                    const T *c0 = (const T *)c, *c1 = (const T *)(c + px);
-                    const T *c2 = (const T *)(c + pxy), *c3 = (const T *)(c + pxy + px);
-                    part += trilinear(c0[0], c0[1], c1[0], c1[1], c2[0], c2[1], c3[0], c3[1], z);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const char *c = boxb + (off + v * pv);
+                        const T *c0 = (const T *)c, *c1 = (const T *)(c + px);
+                        const T *c2 = (const T *)(c + pxy), *c3 = (const T *)(c + pxy + px);
+                        part[v] += trilinear(c0[0], c0[1], c1[0], c1[1], c2[0], c2[1], c3[0], c3[1], z);
+                    }
                     sh += (T)SPLIT;
                     have = sh < shn;
                     if (have) sample_cell(e, d, sh, top, l, z);
@@ -306,18 +332,22 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
             if (miss) {
                 // a sample outside the staged box (or no box): redo this lane's
                 // samples of the slab from global memory
-                part = (T)0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) part[v] = (T)0;
                 sh = sh0;
                 have = sh < shn;
                 if (have) sample_cell(e, d, sh, top, l, z);
                 while (have && (unsigned)(l[AX] - A0) < (unsigned)slab) {
-                    part += gather_global(rf, (l[0] + n0 * (l[1] + n1 * l[2])) * ES, sb1, sb2, z);
+                    const int go = (l[0] + n0 * (l[1] + n1 * l[2])) * ES;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) part[v] += gather_global(rf[v], go, sb1, sb2, z);
                     sh += (T)SPLIT;
                     have = sh < shn;
                     if (have) sample_cell(e, d, sh, top, l, z);
                 }
             }
-            acc += (double)part;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += (double)part[v];
             __syncthreads();
         }
     } else {
@@ -325,24 +355,37 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
             int l[3];
             T z[3];
             sample_cell(e, d, sh, top, l, z);
-            acc += (double)gather_global(rf, (l[0] + n0 * (l[1] + n1 * l[2])) * ES, sb1, sb2, z);
+            const int go = (l[0] + n0 * (l[1] + n1 * l[2])) * ES;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += (double)gather_global(rf[v], go, sb1, sb2, z);
         }
     }
     // combine the SPLIT interleaved partial sums of a ray (same butterfly
     // order in every lane of the group, so they agree bit for bit)
 #pragma unroll
-    for (int m = 1; m < SPLIT; m <<= 1) acc += __shfl_xor(acc, m, 64);
-    double pv = 0.0;
-    const bool writer = valid && seg == 0;
-    if (writer) {
-        const T pt = (T)((double)r.dt * acc);
-        p[pix] = pt;
-        pv = (double)pt;
+    for (int m = 1; m < SPLIT; m <<= 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += __shfl_xor(acc[v], m, 64);
     }
-    if constexpr (SUMS) {
-        const double yv = writer ? (double)y[pix] : 0.0;
-        const double vals[3] = {pv, pv * yv, pv * pv};
-        grid_reduce<3>(vals, partials, counter, sums, bid, nb, 1.0);
+    const bool writer = valid && seg == 0;
+    if constexpr (MODE == FWD_DOT) {
+        double vals[NV];
+        const double rr = writer ? (double)p[pix] - fa * (double)y[pix] - fb : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) vals[v] = rr * ((double)r.dt * acc[v]);
+        grid_reduce<NV>(vals, partials, counter, out, bid, nb, 2.0);
+    } else {
+        double pv = 0.0;
+        if (writer) {
+            const T pt = (T)((double)r.dt * acc[0]);
+            p[pix] = pt;
+            pv = (double)pt;
+        }
+        if constexpr (MODE == FWD_SUMS) {
+            const double yv = writer ? (double)y[pix] : 0.0;
+            const double vals[3] = {pv, pv * yv, pv * pv};
+            grid_reduce<3>(vals, partials, counter, out, bid, nb, 1.0);
+        }
     }
 }
 
@@ -352,21 +395,12 @@ int drr_forward_blocks(int nu, int nv) {
 
 // Slab axis and thickness for a projection: the in-plane axis (x or y) the
 // central ray advances fastest along in index units, and the thickest slab
-// (32, 16 or 8 cells) whose staged box fits the LDS budget for bundles at
+// (32, 16 or 8 cells) whose staged boxes fit the LDS budget for bundles at
 // the centre, edges and corners of the detector.  slab 0 means "no slabs".
-static void forward_plan(const VolDims &v, const Frame &fr, int esize, int *axis, int *slab);
-
-ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr) {
-    ForwardPlan pl;
-    forward_plan(v, fr, dt == PCAS_F32 ? 4 : 8, &pl.axis, &pl.slab);
-    return pl;
-}
-
-static void forward_plan(const VolDims &v, const Frame &fr, int esize, int *axis, int *slab) {
+static void forward_plan(const VolDims &v, const Frame &fr, int cap, int *axis, int *slab) {
     const double ax = fabs(fr.en[0]) * v.inv_s[0], ay = fabs(fr.en[1]) * v.inv_s[1];
     const int AX = ay > ax ? 1 : 0;
     const int na = AX == 0 ? v.n0 : v.n1;
-    const int cap = FWD_LDS_BYTES / esize;
     const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U, tiles_v = (fr.nv + TILE_V - 1) / TILE_V;
     *axis = AX;
     *slab = 0;
@@ -395,18 +429,33 @@ static void forward_plan(const VolDims &v, const Frame &fr, int esize, int *axis
     }
 }
 
-template <typename T, int AX>
+ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr, int nvol) {
+    ForwardPlan pl;
+    const int es = dt == PCAS_F32 ? 4 : 8;
+    forward_plan(v, fr, fwd_lds_bytes(nvol) / es / nvol, &pl.axis, &pl.slab);
+    return pl;
+}
+
+template <typename T, int AX, int NV, int MODE>
 static void launch_fwd(dim3 grid, const VolDims &v, const Frame &fr, int tiles_u, int slab,
-                       const void *rays, const void *f, void *p, const void *y, double *partials,
-                       uint32_t *counter, double *sums, hipStream_t s) {
-    if (sums)
-        hipLaunchKernelGGL((k_drr_forward<T, AX, true>), grid, dim3(256), 0, s, v, fr, tiles_u, slab,
-                           (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, partials,
-                           counter, sums);
+                       const void *rays, const void *f, void *p, const void *y, double a, double b,
+                       double *partials, uint32_t *counter, double *out, hipStream_t s) {
+    hipLaunchKernelGGL((k_drr_forward<T, AX, NV, MODE>), grid, dim3(256), 0, s, v, fr, tiles_u, slab,
+                       (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, a, b, partials,
+                       counter, out);
+}
+
+template <typename T, int NV, int MODE>
+static void launch_fwd_axis(const ForwardPlan &pl, dim3 grid, const VolDims &v, const Frame &fr,
+                            int tiles_u, const void *rays, const void *f, void *p, const void *y,
+                            double a, double b, double *partials, uint32_t *counter, double *out,
+                            hipStream_t s) {
+    if (pl.axis == 0)
+        launch_fwd<T, 0, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, partials,
+                                   counter, out, s);
     else
-        hipLaunchKernelGGL((k_drr_forward<T, AX, false>), grid, dim3(256), 0, s, v, fr, tiles_u,
-                           slab, (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)nullptr,
-                           nullptr, nullptr, nullptr);
+        launch_fwd<T, 1, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, partials,
+                                   counter, out, s);
 }
 
 hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
@@ -415,18 +464,47 @@ hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
                               hipStream_t s) {
     const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
     const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
-    const int AX = plan.axis, slab = plan.slab;
     if (dt == PCAS_F32) {
-        if (AX == 0)
-            launch_fwd<float, 0>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
+        if (sums)
+            launch_fwd_axis<float, 1, FWD_SUMS>(plan, grid, v, fr, tiles_u, rays, f, p, y, 0.0, 0.0,
+                                                partials, counter, sums, s);
         else
-            launch_fwd<float, 1>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
+            launch_fwd_axis<float, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
+                                                 0.0, 0.0, nullptr, nullptr, nullptr, s);
     } else {
-        if (AX == 0)
-            launch_fwd<double, 0>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
+        if (sums)
+            launch_fwd_axis<double, 1, FWD_SUMS>(plan, grid, v, fr, tiles_u, rays, f, p, y, 0.0,
+                                                 0.0, partials, counter, sums, s);
         else
-            launch_fwd<double, 1>(grid, v, fr, tiles_u, slab, rays, f, p, y, partials, counter, sums, s);
+            launch_fwd_axis<double, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
+                                                  0.0, 0.0, nullptr, nullptr, nullptr, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                                  const ForwardPlan &plan, int K, const void *rays, const void *J,
+                                  const void *p, const void *y, double a, double b,
+                                  double *partials, uint32_t *counter, double *g_out,
+                                  hipStream_t s) {
+    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
+    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
+    void *pp = const_cast<void *>(p);
+#define D(TT, KK)                                                                                  \
+    case KK:                                                                                       \
+        launch_fwd_axis<TT, KK, FWD_DOT>(plan, grid, v, fr, tiles_u, rays, J, pp, y, a, b,         \
+                                         partials, counter, g_out, s);                             \
+        break
+    if (dt == PCAS_F32) {
+        switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);
+                     D(float, 5); D(float, 6); D(float, 7); D(float, 8);
+                     default: return hipErrorInvalidValue; }
+    } else {
+        switch (K) { D(double, 1); D(double, 2); D(double, 3); D(double, 4);
+                     D(double, 5); D(double, 6); D(double, 7); D(double, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+#undef D
     return hipGetLastError();
 }
 

@@ -1,4 +1,6 @@
-// a7: the Jacobian chain of the Appendix, g = 2 U^T (df/dx) bp.
+// a7: the Jacobian chain of the Appendix, g = 2 U^T (df/dx) bp, and the
+// Jacobian volumes J_k = U_k^T (df/dx) whose projections give the same
+// gradient as g_k = 2 <r, P J_k> (the adjoint identity).
 //
 // A voxel stream: each block owns a contiguous run of voxels (lanes step by
 // 256 inside it, so every load is coalesced), recomputes x = xbar + U w and
@@ -10,6 +12,65 @@
 #include "device_util.h"
 
 namespace pcas {
+
+// Diagonal Jacobian of the warped image at voxel (i, j, k) pulled back by
+// x (mm): Eq. A.8 and its analogues for the other two axes from the eight
+// f0 neighbours of the pulled-back position (zero outside the grid), per mm.
+// Returns false when no neighbour is inside the grid (all derivatives 0).
+template <typename T>
+__device__ __forceinline__ bool voxel_jacobian(const T *__restrict__ f0, int n0, int n1, int n2,
+                                               int i, int j, int k, const T (&x)[3], T is0, T is1,
+                                               T is2, T (&jac)[3]) {
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    int o0, o1, o2;
+    T z1, z2, z3;                                           // the Appendix's z_1..z_3
+    split_disp(x[0], is0, o0, z1);
+    split_disp(x[1], is1, o1, z2);
+    split_disp(x[2], is2, o2, z3);
+    const int l = i + o0, m = j + o1, n = k + o2;
+    // neighbour values with zero extension
+    const bool vl = l >= 0 && l < n0, vl1 = l + 1 >= 0 && l + 1 < n0;
+    const bool vm = m >= 0 && m < n1, vm1 = m + 1 >= 0 && m + 1 < n1;
+    const bool vn = n >= 0 && n < n2, vn1 = n + 1 >= 0 && n + 1 < n2;
+    if (!((vl || vl1) && (vm || vm1) && (vn || vn1))) return false;
+    const int cl = min(max(l, 0), n0 - 1), cl1 = min(max(l + 1, 0), n0 - 1);
+    const int cm = min(max(m, 0), n1 - 1), cm1 = min(max(m + 1, 0), n1 - 1);
+    const int cn = min(max(n, 0), n2 - 1), cn1 = min(max(n + 1, 0), n2 - 1);
+    auto F = [&](int ii, int jj, int kk, bool ok) -> T {
+        return ok ? f0[ii + s1 * jj + s2 * kk] : (T)0;
+    };
+    const T f000 = F(cl, cm, cn, vl && vm && vn), f100 = F(cl1, cm, cn, vl1 && vm && vn);
+    const T f010 = F(cl, cm1, cn, vl && vm1 && vn), f110 = F(cl1, cm1, cn, vl1 && vm1 && vn);
+    const T f001 = F(cl, cm, cn1, vl && vm && vn1), f101 = F(cl1, cm, cn1, vl1 && vm && vn1);
+    const T f011 = F(cl, cm1, cn1, vl && vm1 && vn1), f111 = F(cl1, cm1, cn1, vl1 && vm1 && vn1);
+    // Eq. A.8 and its analogues (index units), then per mm
+    const T g1 = ((f100 - f000) * ((T)1 - z2) + (f110 - f010) * z2) * ((T)1 - z3) +
+                 ((f101 - f001) * ((T)1 - z2) + (f111 - f011) * z2) * z3;
+    const T g2 = ((f010 - f000) * ((T)1 - z1) + (f110 - f100) * z1) * ((T)1 - z3) +
+                 ((f011 - f001) * ((T)1 - z1) + (f111 - f101) * z1) * z3;
+    const T g3 = ((f001 - f000) * ((T)1 - z1) + (f101 - f100) * z1) * ((T)1 - z2) +
+                 ((f011 - f010) * ((T)1 - z1) + (f111 - f110) * z1) * z2;
+    jac[0] = g1 * is0;
+    jac[1] = g2 * is1;
+    jac[2] = g3 * is2;
+    return true;
+}
+
+// x = xbar + U w at voxel v and the modes' three components there.
+template <typename T, int K>
+__device__ __forceinline__ void voxel_field(const T *__restrict__ mean, const T *__restrict__ U,
+                                            const T (&wk)[K], int64_t N, int64_t v, T (&u)[K][3],
+                                            T (&x)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = mean ? mean[c * N + v] : (T)0;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            u[kk][c] = U[(int64_t)(kk * 3 + c) * N + v];
+            x[c] = fma_t(wk[kk], u[kk][c], x[c]);
+        }
+    }
+}
 
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_grad_w(VolDims vd, const T *__restrict__ f0,
@@ -28,7 +89,7 @@ __global__ __launch_bounds__(256) void k_grad_w(VolDims vd, const T *__restrict_
     per = (per + 255) & ~(int64_t)255;
     const int64_t v_begin = (int64_t)bid * per;
     const int64_t v_end = min(N, v_begin + per);
-    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    const int64_t s2 = (int64_t)n0 * n1;
     T wk[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) wk[k] = (T)w.w[k];
@@ -43,51 +104,44 @@ __global__ __launch_bounds__(256) void k_grad_w(VolDims vd, const T *__restrict_
         const int i = (int)(v % n0);
         const int j = (int)((v / n0) % n1);
         const int k = (int)(v / s2);
-        T u[K][3];
-        T x[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            x[c] = mean ? mean[c * N + v] : (T)0;
-#pragma unroll
-            for (int kk = 0; kk < K; ++kk) {
-                u[kk][c] = U[(int64_t)(kk * 3 + c) * N + v];
-                x[c] = fma_t(wk[kk], u[kk][c], x[c]);
-            }
-        }
-        int o0, o1, o2;
-        T z1, z2, z3;                                           // the Appendix's z_1..z_3
-        split_disp(x[0], is0, o0, z1);
-        split_disp(x[1], is1, o1, z2);
-        split_disp(x[2], is2, o2, z3);
-        const int l = i + o0, m = j + o1, n = k + o2;
-        // neighbour values with zero extension
-        const bool vl = l >= 0 && l < n0, vl1 = l + 1 >= 0 && l + 1 < n0;
-        const bool vm = m >= 0 && m < n1, vm1 = m + 1 >= 0 && m + 1 < n1;
-        const bool vn = n >= 0 && n < n2, vn1 = n + 1 >= 0 && n + 1 < n2;
-        if (!((vl || vl1) && (vm || vm1) && (vn || vn1))) continue;
-        const int cl = min(max(l, 0), n0 - 1), cl1 = min(max(l + 1, 0), n0 - 1);
-        const int cm = min(max(m, 0), n1 - 1), cm1 = min(max(m + 1, 0), n1 - 1);
-        const int cn = min(max(n, 0), n2 - 1), cn1 = min(max(n + 1, 0), n2 - 1);
-        auto F = [&](int ii, int jj, int kk, bool ok) -> T {
-            return ok ? f0[ii + s1 * jj + s2 * kk] : (T)0;
-        };
-        const T f000 = F(cl, cm, cn, vl && vm && vn), f100 = F(cl1, cm, cn, vl1 && vm && vn);
-        const T f010 = F(cl, cm1, cn, vl && vm1 && vn), f110 = F(cl1, cm1, cn, vl1 && vm1 && vn);
-        const T f001 = F(cl, cm, cn1, vl && vm && vn1), f101 = F(cl1, cm, cn1, vl1 && vm && vn1);
-        const T f011 = F(cl, cm1, cn1, vl && vm1 && vn1), f111 = F(cl1, cm1, cn1, vl1 && vm1 && vn1);
-        // Eq. A.8 and its analogues (index units), then per mm
-        const T g1 = ((f100 - f000) * ((T)1 - z2) + (f110 - f010) * z2) * ((T)1 - z3) +
-                     ((f101 - f001) * ((T)1 - z2) + (f111 - f011) * z2) * z3;
-        const T g2 = ((f010 - f000) * ((T)1 - z1) + (f110 - f100) * z1) * ((T)1 - z3) +
-                     ((f011 - f001) * ((T)1 - z1) + (f111 - f101) * z1) * z3;
-        const T g3 = ((f001 - f000) * ((T)1 - z1) + (f101 - f100) * z1) * ((T)1 - z2) +
-                     ((f011 - f010) * ((T)1 - z1) + (f111 - f110) * z1) * z2;
-        const T j0 = g1 * is0 * bpv, j1 = g2 * is1 * bpv, j2 = g3 * is2 * bpv;
+        T u[K][3], x[3], jac[3];
+        voxel_field<T, K>(mean, U, wk, N, v, u, x);
+        if (!voxel_jacobian(f0, n0, n1, n2, i, j, k, x, is0, is1, is2, jac)) continue;
+        const T j0 = jac[0] * bpv, j1 = jac[1] * bpv, j2 = jac[2] * bpv;
 #pragma unroll
         for (int kk = 0; kk < K; ++kk)
             acc[kk] += (double)fma_t(u[kk][0], j0, fma_t(u[kk][1], j1, u[kk][2] * j2));
     }
     grid_reduce<K>(acc, partials, counter, g_out, bid, nb, 2.0);
+}
+
+// The K Jacobian volumes J_k = sum_c U_kc df/dx_c of the warp at w (the
+// chain of Eq. A.8 without the back-projection), J[k][v].
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_jacobian(VolDims vd, const T *__restrict__ f0,
+                                                  const T *__restrict__ mean,
+                                                  const T *__restrict__ U, WVec w,
+                                                  T *__restrict__ J) {
+    const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t v = b * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const int i = (int)(v % n0);
+    const int j = (int)((v / n0) % n1);
+    const int k = (int)(v / ((int64_t)n0 * n1));
+    T wk[K];
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) wk[kk] = (T)w.w[kk];
+    T u[K][3], x[3], jac[3];
+    voxel_field<T, K>(mean, U, wk, N, v, u, x);
+    if (!voxel_jacobian(f0, n0, n1, n2, i, j, k, x, (T)vd.inv_s[0], (T)vd.inv_s[1],
+                        (T)vd.inv_s[2], jac)) {
+        jac[0] = jac[1] = jac[2] = (T)0;
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+        J[kk * N + v] = fma_t(u[kk][0], jac[0], fma_t(u[kk][1], jac[1], u[kk][2] * jac[2]));
 }
 
 int grad_w_blocks(int64_t N) {
@@ -107,6 +161,35 @@ hipError_t grad_k(const VolDims &v, const void *f0, const void *mean, const void
     return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <typename T, int K>
+hipError_t jacobian_k(const VolDims &v, const void *f0, const void *mean, const void *U,
+                      const WVec &w, void *J, hipStream_t s) {
+    const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
+    hipLaunchKernelGGL((k_jacobian<T, K>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, v,
+                       (const T *)f0, (const T *)mean, (const T *)U, w, (T *)J);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_jacobian(pcas_dtype dt, const VolDims &v, int K, const void *f0,
+                           const void *mean, const void *U, const double *w, void *J,
+                           hipStream_t s) {
+    WVec wv{};
+    for (int k = 0; k < K; ++k) wv.w[k] = w[k];
+#define G(TT, KK) \
+    case KK: return jacobian_k<TT, KK>(v, f0, mean, U, wv, J, s)
+    if (dt == PCAS_F32) {
+        switch (K) { G(float, 1); G(float, 2); G(float, 3); G(float, 4);
+                     G(float, 5); G(float, 6); G(float, 7); G(float, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+    switch (K) { G(double, 1); G(double, 2); G(double, 3); G(double, 4);
+                 G(double, 5); G(double, 6); G(double, 7); G(double, 8);
+                 default: return hipErrorInvalidValue; }
+#undef G
+}
 
 hipError_t launch_grad_w(pcas_dtype dt, const VolDims &v, int K, const void *f0, const void *mean,
                          const void *U, const double *w, const void *bp, double *partials,

@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.pcas_abi_version() == 1
+    assert L.pcas_abi_version() == 2
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.pcas_status_string(code)
     assert L.pcas_last_error() == b""
@@ -179,5 +179,28 @@ def test_solve_option_and_input_validation(L, geom):
     assert call(B.default_opts(beta_lo=0.9)) == EINVAL
     assert call(B.default_opts(locate=1, c0_mm=(0.0, float("nan"), 0.0))) == EINVAL
     assert call(B.default_opts(), K=0) == EINVAL
+    assert call(B.default_opts(grad_mode=2)) == EINVAL
     assert L.solve_projection(1, ctypes.byref(v), ctypes.byref(p), 3, FAKE, None, FAKE, FAKE, good_w,
                               None, FAKE, ws, wout, ctypes.byref(rep), None) == EINVAL
+
+
+def test_objective_gradient_validation(L, geom):
+    v, p = geom
+    ws = L.solve_projection_workspace(0, ctypes.byref(v), ctypes.byref(p), 3)
+    # the workspace holds the K Jacobian volumes
+    assert ws >= 3 * 4 * 5760 + 4 * 5760
+    assert L.solve_projection_workspace(0, ctypes.byref(v), ctypes.byref(p), 0) == 0
+    w = (ctypes.c_double * 3)(0.1, 0.2, 0.3)
+    out = (ctypes.c_double * 6)()
+
+    def call(K=3, w=w, mode=0, ws_ptr=FAKE, ws_bytes=ws):
+        return L.objective_gradient(0, ctypes.byref(v), ctypes.byref(p), K, FAKE, None, FAKE, FAKE,
+                                    w, 1, mode, ws_ptr, ws_bytes, out, None)
+
+    assert call(mode=2) == EINVAL
+    assert call(K=9) == EINVAL
+    assert call(w=(ctypes.c_double * 3)(0.1, float("nan"), 0.3)) == ENONFIN
+    assert call(ws_bytes=ws - 1) == EWS
+    assert call(ws_ptr=ctypes.c_void_p(0x100010)) == EWS
+    assert L.objective_gradient(0, ctypes.byref(v), ctypes.byref(p), 3, FAKE, None, FAKE, FAKE, w,
+                                1, 0, FAKE, ws, None, None) == EINVAL

@@ -1,0 +1,123 @@
+"""objective_gradient through the C ABI: J, (a, b) and dJ/dw by both routes
+(projected Jacobian volumes, grad_mode 0; back-projection + Jacobian chain,
+grad_mode 1) against the FP64 oracle's objective and Appendix gradient, and
+the solve by either route."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1102_1712_amd import binding as B
+from paper_1102_1712_amd import synth
+
+from gpu_common import Dev, measured, say, to_dev, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_or_skip()
+
+
+def _oracle(c, y, w, fit):
+    prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y, fit_intensity=fit)
+    J, a, b, r = prob.objective(w)
+    return J, a, b, prob.gradient(w, r)
+
+
+def _check(c, d, y, w, fit, tol_g, tol_j):
+    J_o, a_o, b_o, g_o = _oracle(c, y, w, fit)
+    gs = []
+    for mode in (0, 1):
+        J, a, b, g = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w,
+                                          fit_intensity=fit, grad_mode=mode)
+        say(f"mode {mode}: J {J:.10e} (oracle {J_o:.10e}) g {g} (oracle {g_o})")
+        assert abs(J - J_o) <= tol_j * J_o
+        assert abs(a - a_o) <= tol_j * max(1.0, abs(a_o)) and abs(b - b_o) <= tol_j * max(1.0, abs(b_o))
+        assert np.linalg.norm(g - g_o) <= tol_g * np.linalg.norm(g_o)
+        gs.append(g)
+    return gs
+
+
+@pytest.mark.parametrize("fit", [True, False])
+def test_small_f64_both_routes(torch, fit):
+    """Ragged anisotropic 40x36x28 FP64 case: both routes reach the oracle's
+    gradient to rounding and agree with each other."""
+    c = synth.small(dtype="f64", seed=5)
+    d = Dev(c)
+    y = measured(c)
+    w = c.w_star + 0.3 * np.array([1.0, -0.5, 0.8])
+    g0, g1 = _check(c, d, y, w, fit, 1e-10, 1e-12)
+    assert np.linalg.norm(g0 - g1) <= 1e-11 * np.linalg.norm(g1)
+
+
+def test_tiny_f64_at_zero(torch):
+    """The 64^3 FP64 workload at w = 0 (the solve's first gradient)."""
+    c = synth.tiny()
+    d = Dev(c)
+    y = measured(c)
+    _check(c, d, y, np.zeros(c.K), True, 1e-10, 1e-12)
+
+
+@pytest.mark.parametrize("angle", [None, 0.0, np.pi / 4, 2.5])
+def test_small_f64_angles(torch, angle):
+    """Slab axis x or y, both travel directions, a 45 degree tilt."""
+    c = synth.small(dtype="f64", seed=8)
+    if angle is not None:
+        c = synth.with_angle(c, angle)
+    d = Dev(c)
+    y = measured(c)
+    _check(c, d, y, c.w_star * 0.7, True, 1e-10, 1e-12)
+
+
+def test_clinical_f32(torch):
+    """256x256x128 FP32, K = 3, 512x384 detector, away from the optimum
+    (w* + 0.3 xi): both routes within 1e-4 of the FP64 oracle."""
+    c = synth.clinical()
+    d = Dev(c)
+    y = measured(c)
+    w = c.w_star + 0.3 * np.array([1.0, -0.5, 0.8])
+    say("clinical objective_gradient")
+    _check(c, d, y, np.asarray(w, dtype=np.float64), True, 1e-4, 1e-5)
+
+
+def test_clinical_k5_f32_projected(torch):
+    """K = 5 modes: the projected-Jacobian route with five volumes at once."""
+    c = synth.clinical_k5()
+    d = Dev(c)
+    y = measured(c)
+    w = 0.5 * c.w_star
+    J_o, a_o, b_o, g_o = _oracle(c, y, w, True)
+    J, a, b, g = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w,
+                                      grad_mode=0)
+    say("K=5", g, g_o)
+    assert abs(J - J_o) <= 1e-5 * J_o
+    assert np.linalg.norm(g - g_o) <= 1e-4 * np.linalg.norm(g_o)
+
+
+def test_solve_same_by_either_route(torch):
+    """FP64 small solve: both gradient routes converge to the same w."""
+    c = synth.small(dtype="f64", seed=5)
+    d = Dev(c)
+    y = to_dev(measured(c), d.dt)
+    ws = []
+    for mode in (0, 1):
+        w, rep = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
+                                    B.default_opts(grad_mode=mode))
+        say(f"mode {mode}", w, rep["status"], rep["iters"])
+        assert rep["status"] in ("converged", "line_search")
+        ws.append(w)
+    assert np.linalg.norm(ws[0] - ws[1]) <= 1e-8 * np.linalg.norm(ws[1])
+
+
+def test_errors(torch):
+    c = synth.small(dtype="f32", seed=6)
+    d = Dev(c)
+    y = to_dev(measured(c), d.dt)
+    with pytest.raises(B.PcasError):
+        B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, y, c.w_star, grad_mode=2)
+    with pytest.raises(B.PcasError):
+        B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, y, c.w_star * np.nan)
+    flat = torch.ones_like(y)
+    with pytest.raises(B.PcasError):
+        B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, flat, c.w_star)
