@@ -3,9 +3,10 @@
 
 One step = one call of solve_projection on the clinical-size workload: ray
 table, then CG iterations of (DVF synthesis + warp, cone-beam projection,
-intensity fit and objective; at accepted points the gradient as the
-projections of the K Jacobian volumes against the residual), then the
-tumour-position inversion.  Inputs (reference volume, mean field and K = 3
+intensity fit and objective, and at accepted points back-projection of the
+residual and the Jacobian chain), then the tumour-position inversion.  The
+same solve with the gradient formed from projections of the Jacobian
+volumes (no back-projection) is reported beside it.  Inputs (reference volume, mean field and K = 3
 modes, measured projection) are resident in HBM before the timed region.
 
 Prints ONE JSON line (see the keys below).  Kernel durations come from HIP
@@ -36,13 +37,20 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # corner weights (9), 8 weighted accumulations (16) = 34.  Projection of K
 # volumes at once: position and fractions once (9), then 22 per volume.
 def flops_per_sample(kernel: str, K: int) -> float:
-    return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
+    return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_adjoint_chain": 34.0,
+            "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
 
 
-SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_forward_dot")
+# Jacobian chain per voxel: field 6K, displacement split 6, Eq. A.8 and its
+# two analogues 3 x 13, per-mm and bp scaling 6, mode sums 5K + K.
+def chain_flops_per_voxel(K: int) -> float:
+    return 12.0 * K + 51.0
+
+
+SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot")
 KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
-                  "drr_forward_dot": "k_drr.hip", "warp_pca": "k_warp.hip",
-                  "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
+                  "drr_adjoint_chain": "k_drr.hip", "drr_forward_dot": "k_drr.hip",
+                  "warp_pca": "k_warp.hip", "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
 
 
 def kernel_digest(kernel: str) -> str:
@@ -353,6 +361,7 @@ def main() -> int:
         "jacobian": (3 + 3 * K + 1 + K) * es * N,
         "drr_forward": es * N + 32 * M + 2 * es * M,
         "drr_adjoint": es * N + 32 * M + 2 * es * M,
+        "drr_adjoint_chain": (3 + 3 * K + 1) * es * N + 32 * M + 2 * es * M,
         "drr_forward_dot": K * es * N + 32 * M + 2 * es * M,
     }
     kernel_stats = {}
@@ -379,11 +388,32 @@ def main() -> int:
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant}
         else:
-            # gather / VALU bound: algorithmic flops per projection sample
-            ach = flops_per_sample(dominant, K) * S / (avg[dominant] * 1e-3) / 1e12
+            # gather / VALU bound: algorithmic flops per projection sample (plus
+            # the chain per voxel for the fused back-projection)
+            work = flops_per_sample(dominant, K) * S
+            if dominant == "drr_adjoint_chain":
+                work += chain_flops_per_voxel(K) * N
+            ach = work / (avg[dominant] * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": ach, "peak": VALU_F32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": traffic,
                         "kernel": dominant}
+
+    # the other gradient route (projected Jacobian volumes, no back-projection),
+    # same solve otherwise; reported beside the contract line, not as `value`
+    alt_t = []
+    opts_alt = B.default_opts(grad_mode=0, **base)
+    step(opts_alt)
+    for _ in range(max(5, args.steps // 5)):
+        t0 = time.perf_counter()
+        w_alt, rep_alt = step(opts_alt)
+        alt_t.append(time.perf_counter() - t0)
+    alt_ms = np.array(alt_t) * 1e3
+    alt = {"grad_mode": 0, "steps": len(alt_t), "p50_ms": float(np.percentile(alt_ms, 50)),
+           "p99_ms": float(np.percentile(alt_ms, 99)),
+           "solves_s": float(1e3 / np.mean(alt_ms)), "n_fevals": rep_alt["n_fevals"],
+           "n_grads": rep_alt["n_grads"],
+           "w_rel_diff_vs_default_route": float(np.linalg.norm(w_alt - w) / np.linalg.norm(w))}
+    log(f"projected-gradient route: p50 {alt['p50_ms']:.3f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -391,7 +421,9 @@ def main() -> int:
         cpu = cpu_baseline(case, rep["n_fevals"], rep["n_grads"], args.cpu_baseline_s)
 
     drr = kernel_stats.get("drr_forward", {})
-    adj = kernel_stats.get("drr_adjoint") or adjoint_alone(case, dev, S)
+    # the back-projection alone (in the solve it runs fused with the chain)
+    adj = adjoint_alone(case, dev, S)
+    kernel_stats["drr_adjoint_alone"] = adj
     out = {
         "metric": METRIC,
         "value": args.steps / total,
@@ -420,6 +452,7 @@ def main() -> int:
         "drr_effective_hbm_frac": (drr.get("effective_GBs", 0) / HBM_PEAK_GBS) if drr else None,
         "adjoint_effective_hbm_frac": (adj.get("effective_GBs", 0) / HBM_PEAK_GBS) if adj else None,
         "kernels": kernel_stats,
+        "projected_gradient_route": alt,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "0.1-0.3 s per projection on a Tesla C1060 (different sizes; context only)",

@@ -105,16 +105,19 @@ typedef struct {
     int32_t profile;       /* 1: time every kernel with HIP events (report.kernel_ms) */
     int32_t grad_mode;     /* how dJ/dw is formed (the same quantity either way, by the
                               adjoint identity <P^T r, J_k> = <r, P J_k>):
+                              1: back-project r, then g = 2 U^T (df/dx) P^T r (the Appendix's
+                                 route, the default); the solver runs drr_adjoint's kernel
+                                 with grad_w's chain applied to each brick as it completes,
+                                 so P^T r never goes to device memory
                               0: project the K Jacobian volumes J_k = U_k^T (df/dx) and take
-                                 g_k = 2 <r, P J_k> (gathers only; the default)
-                              1: back-project r, then g = 2 U^T (df/dx) P^T r (drr_adjoint
-                                 followed by grad_w) */
+                                 g_k = 2 <r, P J_k> (gathers only, no back-projection) */
     double ftol_rel;       /* method 1: a rejected trial with |J_t - J| <= ftol_rel J ends the
                               solve as converged (the change is below the objective's rounding
                               noise); < 0 selects 1e-8 for PCAS_F32 and 0 for PCAS_F64 */
 } pcas_opts;
 
-/* kernel classes of pcas_report.kernel_ms / kernel_launches */
+/* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
+   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain) */
 enum {
     PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
     PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
@@ -145,7 +148,7 @@ const char *pcas_last_error(void);
 /* Defaults: method 1 (CG), 30 iterations, fit on, 12 backtracks, mu0 = 1,
  * alpha = 0.1, beta = 0.5 (the Appendix's Armijo constants), mu_min = 0.01,
  * gtol_rel = 1e-9, beta_lo = 0.1, xtol = 1e-10, no localisation, 100
- * localisation iterations, 1e-9 mm tolerance. */
+ * localisation iterations, 1e-9 mm tolerance, grad_mode 1 (back-projection). */
 void pcas_default_opts(pcas_opts *opts);
 /* Appendix algorithm: method 0, 10 iterations, mu0 = 0.2, alpha = 0.1,
  * beta = 0.5, stop below mu_min = 0.01 (the paper's 2 and 0.1 rescaled from

@@ -72,8 +72,10 @@ class Report(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int32 * 10)]
 
 
-KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint", "grad_w",
-                  "tumour_position", "y_sums", "jacobian", "drr_forward_dot")
+# report.kernel_ms classes; in a solve class 4 is the back-projection with the
+# Jacobian chain fused into it
+KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint_chain",
+                  "grad_w", "tumour_position", "y_sums", "jacobian", "drr_forward_dot")
 
 
 _lib = None
@@ -402,10 +404,10 @@ def solve_projection(vol, proj, f0, mean, U, y, w0, opts: Optional[Opts] = None,
 
 
 def objective_gradient(vol, proj, f0, mean, U, y, w, fit_intensity: bool = True,
-                       grad_mode: int = 0, workspace=None, stream=None):
+                       grad_mode: int = 1, workspace=None, stream=None):
     """a5 + a6 + a7 at one point: (J, a, b, g as float64 numpy [K]) exactly as
-    the solver forms them (grad_mode 0: projected Jacobian volumes; 1:
-    back-projection + Jacobian chain).  Synchronous."""
+    the solver forms them (grad_mode 1: back-projection + Jacobian chain; 0:
+    projected Jacobian volumes).  Synchronous."""
     torch = _torch()
     K = _K_of(U, vol)
     code = _dtype_code(f0)

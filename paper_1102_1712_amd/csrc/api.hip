@@ -150,6 +150,8 @@ struct SolveWs {
 
 int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
     int m = drr_forward_blocks(p->nu, p->nv);
+    const int nbr = drr_adjoint_blocks(make_dims(v));
+    m = m > nbr ? m : nbr;
     m = m > grad_w_blocks(nvox_of(v)) ? m : grad_w_blocks(nvox_of(v));
     m = m > sums_blocks(npix_of(p)) ? m : sums_blocks(npix_of(p));
     return m;
@@ -224,6 +226,7 @@ void pcas_default_opts(pcas_opts *o) {
     o->locate_max_iter = 100;
     o->locate_tol = 1e-9;
     o->ftol_rel = -1.0;
+    o->grad_mode = 1;
 }
 
 void pcas_paper_opts(pcas_opts *o) {
@@ -530,12 +533,11 @@ struct Solver {
                                               &counters()[1], scal() + 8, s);
             }));
         } else {
+            // back-projection and Jacobian chain in one pass (bp stays on chip)
             HIPCHK(timed(PCAS_K_ADJOINT, [&] {
-                return launch_drr_adjoint(dt, vd, fr, ws + L.rays, ws + L.p, y, a, b, ws + L.vol2, s);
-            }));
-            HIPCHK(timed(PCAS_K_GRAD, [&] {
-                return launch_grad_w(dt, vd, K, f0, mean, U, w, ws + L.vol2,
-                                     (double *)(ws + L.partials), &counters()[1], scal() + 8, s);
+                return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, ws + L.p, y, a, b, f0,
+                                                mean, U, w, (double *)(ws + L.partials),
+                                                &counters()[1], scal() + 8, s);
             }));
         }
         ++n_grads;

@@ -123,6 +123,16 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
 hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *rays,
                               const void *r_or_p, const void *y, double a, double b, void *bp,
                               hipStream_t s);
+// Back-projection of the residual r = p - a y - b fused with the Jacobian
+// chain: g_out[k] = 2 sum_v (P^T r)(v) sum_c U_kc df/dx_c (bp stays on
+// chip); partials needs drr_adjoint_blocks() * RED_SLOTS doubles, counter
+// one zeroed uint32 (left zeroed on exit).
+int drr_adjoint_blocks(const VolDims &v);
+hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame &fr, int K,
+                                    const void *rays, const void *p, const void *y, double a,
+                                    double b, const void *f0, const void *mean, const void *U,
+                                    const double *w, double *partials, uint32_t *counter,
+                                    double *g_out, hipStream_t s);
 
 // J[k][v] = sum_c U_kc(v) df/dx_c(v) at w (Eq. A.8 chain per voxel).
 hipError_t launch_jacobian(pcas_dtype dt, const VolDims &v, int K, const void *f0,

@@ -19,7 +19,7 @@
 // on the order in which the four waves add, and is bit-for-bit reproducible.
 #include <algorithm>
 
-#include "device_util.h"
+#include "jacobian.h"
 
 namespace pcas {
 
@@ -529,15 +529,23 @@ constexpr int ACC_YP = BRICK_X + 2;
 constexpr int ACC_ZP = (BRICK_Y + 2) * ACC_YP + 1;
 constexpr int ACC_WORDS = (BRICK_Z + 2) * ACC_ZP;
 constexpr int ADJ_WAVES = 4;   // waves sharing one brick
-constexpr int QCAP = 128;      // queued rays per wave (two batches)
+constexpr int QCAP = 128;      // ring queue of rays per wave (power of two)
+constexpr int ADJ_RUN = 8;     // samples per lane between queue refills
 
-// Fixed-point value of a contribution v at scale S: round(v S) as a 64-bit
-// two's-complement integer, read off the mantissa of v S + 1.5 * 2^52 (exact
-// for |v S| < 2^51, which the caller's choice of S guarantees).
-__device__ __forceinline__ unsigned long long to_fixed(double vS) {
-    const double m = vS + 6755399441055744.0;
+// Fixed-point image of one already-scaled contribution v as a 64-bit two's
+// complement integer.  float: |v| <= 2^30, rounded to the nearest integer
+// and sign-extended; double: |v| <= 2^50, rounded by reading the mantissa
+// of v + 1.5 * 2^52.
+__device__ __forceinline__ unsigned long long fixed_of(float v) {
+    return (unsigned long long)(long long)(int)__builtin_rintf(v);
+}
+__device__ __forceinline__ unsigned long long fixed_of(double v) {
+    const double m = v + 6755399441055744.0;
     return __builtin_bit_cast(unsigned long long, m) - 0x4338000000000000ull;
 }
+template <typename T> struct FixedRange;
+template <> struct FixedRange<float> { static constexpr double per_add = 1073741824.0; };       // 2^30
+template <> struct FixedRange<double> { static constexpr double per_add = 1125899906842624.0; };  // 2^50
 
 // Samples of ray r whose 2x2x2 cell may touch the brick [lo, hi]: the
 // parameter range where every coordinate lies in [lo - 1, hi + 1], widened
@@ -569,63 +577,6 @@ __device__ __forceinline__ bool brick_sample_range(const RayRec<T> &r, const T (
     return *s0 <= *s1;
 }
 
-template <typename T>
-__device__ __forceinline__ void flush_cell(unsigned long long *acc, int base, const T (&cw)[8],
-                                           double S) {
-    if (base < 0) return;
-    unsigned long long *p = acc + base;
-    const int off[8] = {0, 1, ACC_YP, ACC_YP + 1, ACC_ZP, ACC_ZP + 1, ACC_ZP + ACC_YP,
-                        ACC_ZP + ACC_YP + 1};
-#pragma unroll
-    for (int q = 0; q < 8; ++q) atomicAdd(p + off[q], to_fixed((double)cw[q] * S));
-}
-
-// One lane walks the queued ray's samples near the brick.  Samples whose
-// cell has no corner in the brick are skipped; the eight corner weights of
-// consecutive samples sharing a cell are summed in registers and added to
-// LDS when the cell changes.
-template <typename T>
-__device__ __forceinline__ void splat_ray(unsigned long long *acc, const RayRec<T> &r, T cst,
-                                          int s0, int s1, const GridTop<T> &top,
-                                          const int (&lo)[3], const int (&hi)[3], double S) {
-    const T e[3] = {r.e[0], r.e[1], r.e[2]};
-    const T d[3] = {r.d[0], r.d[1], r.d[2]};
-    int cur = -1;   // halo-array offset of the cell being accumulated
-    T cw[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) cw[q] = (T)0;
-    T sh = (T)s0 + (T)0.5;
-    for (int s = s0; s <= s1; ++s, sh += (T)1) {
-        int l[3];
-        T z[3];
-        sample_cell(e, d, sh, top, l, z);
-        const int lx = l[0] - lo[0] + 1, ly = l[1] - lo[1] + 1, lz = l[2] - lo[2] + 1;
-        const bool touches = lx >= 0 && lx <= hi[0] - lo[0] + 1 && ly >= 0 &&
-                             ly <= hi[1] - lo[1] + 1 && lz >= 0 && lz <= hi[2] - lo[2] + 1;
-        if (!touches) continue;
-        const int base = lz * ACC_ZP + ly * ACC_YP + lx;
-        if (base != cur) {
-            flush_cell(acc, cur, cw, S);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) cw[q] = (T)0;
-            cur = base;
-        }
-        const T c1a = cst * ((T)1 - z[1]), c1b = cst * z[1];
-        const T za = (T)1 - z[2], zb = z[2];
-        const T w00 = c1a * za, w10 = c1b * za, w01 = c1a * zb, w11 = c1b * zb;
-        const T xa = (T)1 - z[0], xb = z[0];
-        cw[0] = fma_t(w00, xa, cw[0]);
-        cw[1] = fma_t(w00, xb, cw[1]);
-        cw[2] = fma_t(w10, xa, cw[2]);
-        cw[3] = fma_t(w10, xb, cw[3]);
-        cw[4] = fma_t(w01, xa, cw[4]);
-        cw[5] = fma_t(w01, xb, cw[5]);
-        cw[6] = fma_t(w11, xa, cw[6]);
-        cw[7] = fma_t(w11, xb, cw[7]);
-    }
-    flush_cell(acc, cur, cw, S);
-}
-
 template <typename T, bool FORM_R>
 __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__restrict__ y, double a,
                                          double b, int pix) {
@@ -637,23 +588,41 @@ __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__re
 
 // hb bounds the summed weight one ray can give one voxel (1/h + 1 for the
 // smallest per-sample index step h of any ray with two or more samples).
-template <typename T, bool FORM_R>
+//
+// Work distribution: the rays of the brick's detector footprint with a
+// non-empty sample range near the brick go into a per-wave ring queue
+// (geometry, range and scaled dt * r); every lane takes a ray, walks ADJ_RUN
+// samples, and lanes whose ray is done take the next queued one, so lanes
+// stay busy whatever the spread of ray lengths.  Each sample whose cell
+// touches the brick adds its eight corner weights to the LDS accumulator in
+// fixed point (per-brick power-of-two scale from the largest |r| of the
+// footprint).  Integer addition is associative, so the brick's sums do not
+// depend on which lane adds when.
+//
+// K = 0: bp is written.  K > 0 (the solver's gradient): bp never leaves the
+// chip; each brick voxel's value is chained at once through the warp
+// Jacobian (Eq. A.8 and the modes, as grad_w does) and the block sums of
+// bp * sum_c U_kc df/dx_c go through the fixed-order grid reduction into
+// g_out[k] (times 2).
+template <typename T, bool FORM_R, int K>
 __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
                                                      double hb,
                                                      const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ rp,
                                                      const T *__restrict__ y, double a, double b,
-                                                     T *__restrict__ bp) {
+                                                     T *__restrict__ bp, const T *__restrict__ f0,
+                                                     const T *__restrict__ mean,
+                                                     const T *__restrict__ U, WVec w,
+                                                     double *__restrict__ partials,
+                                                     uint32_t *counter, double *__restrict__ g_out) {
     __shared__ unsigned long long acc[ACC_WORDS];
-    __shared__ int q_pix[ADJ_WAVES][QCAP], q_s0[ADJ_WAVES][QCAP], q_s1[ADJ_WAVES][QCAP];
-    __shared__ T q_c[ADJ_WAVES][QCAP];
+    __shared__ T q_f[ADJ_WAVES][7][QCAP];       // e[3], d[3], scaled dt * r
+    __shared__ int q_s[ADJ_WAVES][2][QCAP];     // first and last sample
     __shared__ double red[ADJ_WAVES];
     const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
-    const int nb = gridDim.x;
     // Bricks go round-robin over the XCDs in launch order: only bricks inside
     // the x-ray cone carry work, so contiguous per-XCD ranges would leave the
     // XCDs that hold the outer z-slabs idle.
-    (void)nb;
     const int bid = blockIdx.x;
     const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
     const int lo[3] = {bx * BRICK_X, by * BRICK_Y, bz * BRICK_Z};
@@ -693,10 +662,11 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
     const int W = iu1 - iu0 + 1, H = iv1 - iv0 + 1;
     const int npix = (W > 0 && H > 0) ? W * H : 0;
 
-    // Per-brick fixed-point scale from the largest |r| in the footprint:
-    // every contribution is |dt r w| <= step * rmax = C; a flushed cell sum
-    // is <= C hb; a voxel total is <= C hb * npix.  S keeps the former below
-    // 2^50 and the latter below 2^62 (64-bit accumulators never overflow).
+    // Per-brick fixed-point scale S from the largest |r| in the footprint:
+    // every contribution is |dt r w| <= step * rmax = C, a voxel total is
+    // <= C hb * npix.  S keeps the former within FixedRange (so fixed_of is
+    // exact rounding) and the latter below 2^62 (no 64-bit overflow), and is
+    // a power of two, so scaling dt * r by it is exact.
     double rmax = 0.0;
     for (int t = tid; t < npix; t += 256) {
         const int pix = (iv0 + t / W) * fr.nu + (iu0 + t % W);
@@ -709,127 +679,234 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
     const double C = fr.step * rmax * (1.0 + 1e-6);
     double Sd = 0.0;
     if (C > 0.0) {
-        const double lim_cell = 1125899906842624.0 / (C * hb);                  // 2^50
+        const double lim_add = FixedRange<T>::per_add / C;
         const double lim_vox = 4611686018427387904.0 / (C * hb * (double)npix);   // 2^62
-        Sd = fmin(fmin(lim_cell, lim_vox), 1e300);
+        int ex;
+        frexp(fmin(fmin(lim_add, lim_vox), 1e300), &ex);
+        Sd = ldexp(0.5, ex);   // the largest power of two not above the limits
     }
 
     const GridTop<T> top = grid_top<T>(n0, n1, n2);
     const T lob[3] = {(T)(lo[0] - 1), (T)(lo[1] - 1), (T)(lo[2] - 1)};
     const T hib[3] = {(T)(hi[0] + 1), (T)(hi[1] + 1), (T)(hi[2] + 1)};
-    // Candidate batches interleave the footprint: lane (lu, lv) of batch
-    // (bu, bv) takes pixel (iu0 + lu*Su + bu, iv0 + lv*Sv + bv), so the rays
-    // of one batch sit Su x Sv pixels apart; batches go round-robin to the
-    // four waves, each with its own queue of rays with non-empty ranges.
+    const int ext[3] = {hi[0] - lo[0] + 2, hi[1] - lo[1] + 2, hi[2] - lo[2] + 2};
+    // Candidate tiles interleave the footprint: lane (lu, lv) of tile (bu,
+    // bv) takes pixel (iu0 + lu*Su + bu, iv0 + lv*Sv + bv), so the rays of one
+    // tile sit Su x Sv pixels apart; tiles go round-robin to the four waves.
     const int Su = W > 0 ? (W + 7) / 8 : 0;
     const int Sv = H > 0 ? (H + 7) / 8 : 0;
     const int ntiles = (C > 0.0 && npix > 0) ? Su * Sv : 0;
-    int *qp = q_pix[wave], *qa = q_s0[wave], *qb = q_s1[wave];
-    T *qc = q_c[wave];
-    int qn = 0;   // wave-uniform queue length
-    for (int tile = wave;; tile += ADJ_WAVES) {
-        const bool more = tile < ntiles;
-        if (more) {
+    T(*qf)[QCAP] = q_f[wave];
+    int(*qs)[QCAP] = q_s[wave];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int head = 0, tail = 0;   // wave-uniform ring positions
+    int tile = wave;
+    bool busy = false;
+    T e[3] = {0, 0, 0}, d[3] = {0, 0, 0}, cst = (T)0, sh = (T)0;
+    int s = 0, s_end = -1;
+    __syncthreads();   // accumulator cleared
+    for (;;) {
+        // top up the queue while a whole tile of candidates fits
+        while (tile < ntiles && tail - head <= QCAP - 64) {
             const int iu = iu0 + (lane & 7) * Su + tile % Su;
             const int iv = iv0 + (lane >> 3) * Sv + tile / Su;
             bool active = false;
-            int pix = 0, s0 = 0, s1 = -1;
-            T cst = (T)0;
+            int s0 = 0, s1 = -1;
+            T c = (T)0;
+            RayRec<T> r;
             if (iu <= iu1 && iv <= iv1) {
-                pix = iv * fr.nu + iu;
-                const RayRec<T> r = rays[pix];
+                const int pix = iv * fr.nu + iu;
+                r = rays[pix];
                 if (r.n > 0) {
-                    cst = r.dt * residual_at<T, FORM_R>(rp, y, a, b, pix);
-                    active = cst != (T)0 && brick_sample_range(r, lob, hib, &s0, &s1);
+                    c = (T)((double)r.dt * (double)residual_at<T, FORM_R>(rp, y, a, b, pix) * Sd);
+                    active = c != (T)0 && brick_sample_range(r, lob, hib, &s0, &s1);
                 }
             }
             const uint64_t mask = __ballot(active);
             if (active) {
-                const int pos = qn + __popcll(mask & ((1ull << lane) - 1ull));
-                qp[pos] = pix;
-                qa[pos] = s0;
-                qb[pos] = s1;
-                qc[pos] = cst;
+                const int q = (tail + __popcll(mask & lt)) & (QCAP - 1);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    qf[k][q] = r.e[k];
+                    qf[3 + k][q] = r.d[k];
+                }
+                qf[6][q] = c;
+                qs[0][q] = s0;
+                qs[1][q] = s1;
             }
-            qn += __popcll(mask);
-            if (qn < 64) continue;
-        } else if (qn == 0) {
-            break;
-        }
-        // drain one batch of up to 64 queued rays, one per lane (the queue
-        // lives in this wave's LDS slice and is only touched by this wave)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (lane < qn) {
-            const RayRec<T> r = rays[qp[lane]];
-            splat_ray(acc, r, qc[lane], qa[lane], qb[lane], top, lo, hi, Sd);
-        }
-        const int rest = qn > 64 ? qn - 64 : 0;
-        int mp = 0, ma = 0, mb = 0;
-        T mc = (T)0;
-        if (lane < rest) {
-            mp = qp[64 + lane];
-            ma = qa[64 + lane];
-            mb = qb[64 + lane];
-            mc = qc[64 + lane];
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane < rest) {
-            qp[lane] = mp;
-            qa[lane] = ma;
-            qb[lane] = mb;
-            qc[lane] = mc;
+            tail += __popcll(mask);
+            tile += ADJ_WAVES;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        qn = rest;
-        if (!more) break;
+        // idle lanes take queued rays in lane order
+        const uint64_t idle = __ballot(!busy);
+        const int avail = tail - head;
+        if (!busy) {
+            const int rank = __popcll(idle & lt);
+            if (rank < avail) {
+                const int q = (head + rank) & (QCAP - 1);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    e[k] = qf[k][q];
+                    d[k] = qf[3 + k][q];
+                }
+                cst = qf[6][q];
+                s = qs[0][q];
+                s_end = qs[1][q];
+                sh = (T)s + (T)0.5;
+                busy = true;
+            }
+        }
+        head += min(__popcll(idle), avail);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (__ballot(busy) == 0ull) {
+            if (tile >= ntiles) break;   // queue empty (idle lanes took all) and no tiles left
+            continue;
+        }
+        for (int it = 0; it < ADJ_RUN; ++it) {
+            if (busy) {
+                int l[3];
+                T z[3];
+                sample_cell(e, d, sh, top, l, z);
+                // halo-array coordinates of the cell's lower corner
+                const int lx = l[0] - lo[0] + 1, ly = l[1] - lo[1] + 1, lz = l[2] - lo[2] + 1;
+                if ((unsigned)lx < (unsigned)ext[0] && (unsigned)ly < (unsigned)ext[1] &&
+                    (unsigned)lz < (unsigned)ext[2]) {
+                    unsigned long long *pa = acc + (lz * ACC_ZP + ly * ACC_YP + lx);
+                    const T c1a = cst * ((T)1 - z[1]), c1b = cst * z[1];
+                    const T za = (T)1 - z[2], zb = z[2];
+                    const T w00 = c1a * za, w10 = c1b * za, w01 = c1a * zb, w11 = c1b * zb;
+                    const T xa = (T)1 - z[0], xb = z[0];
+                    atomicAdd(pa, fixed_of(w00 * xa));
+                    atomicAdd(pa + 1, fixed_of(w00 * xb));
+                    atomicAdd(pa + ACC_YP, fixed_of(w10 * xa));
+                    atomicAdd(pa + ACC_YP + 1, fixed_of(w10 * xb));
+                    atomicAdd(pa + ACC_ZP, fixed_of(w01 * xa));
+                    atomicAdd(pa + ACC_ZP + 1, fixed_of(w01 * xb));
+                    atomicAdd(pa + ACC_ZP + ACC_YP, fixed_of(w11 * xa));
+                    atomicAdd(pa + ACC_ZP + ACC_YP + 1, fixed_of(w11 * xb));
+                }
+                sh += (T)1;
+                busy = ++s <= s_end;
+            }
+        }
     }
     __syncthreads();
     const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
     const double inv_S = Sd > 0.0 ? 1.0 / Sd : 0.0;
-    for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
-        const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
-        const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
-        if (i < n0 && j < n1 && k < n2) {
-            const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
-            bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
+    if constexpr (K == 0) {
+        for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
+            const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
+            const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
+            if (i < n0 && j < n1 && k < n2) {
+                const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
+                bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
+            }
         }
+    } else {
+        const int64_t N = (int64_t)n0 * n1 * n2;
+        T wk[K];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) wk[kk] = (T)w.w[kk];
+        const T is0 = (T)vd.inv_s[0], is1 = (T)vd.inv_s[1], is2 = (T)vd.inv_s[2];
+        double gacc[K];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) gacc[kk] = 0.0;
+        if (Sd > 0.0) {
+            for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
+                const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
+                const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
+                if (i >= n0 || j >= n1 || k >= n2) continue;
+                const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
+                const T bpv = (T)((double)v * inv_S);
+                if (bpv == (T)0) continue;
+                const int64_t vox = i + s1 * j + s2 * k;
+                T u[K][3], x[3], jac[3];
+                voxel_field<T, K>(mean, U, wk, N, vox, u, x);
+                if (!voxel_jacobian(f0, n0, n1, n2, i, j, k, x, is0, is1, is2, jac)) continue;
+                const T j0 = jac[0] * bpv, j1 = jac[1] * bpv, j2 = jac[2] * bpv;
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk)
+                    gacc[kk] += (double)fma_t(u[kk][0], j0, fma_t(u[kk][1], j1, u[kk][2] * j2));
+            }
+        }
+        grid_reduce<K>(gacc, partials, counter, g_out, bid, gridDim.x, 2.0);
     }
+}
+
+// A ray with n >= 2 samples has dt >= step / 2, and its largest per-sample
+// index step is >= dt / (sqrt(3) max spacing); the tent weights one ray
+// gives a voxel then sum to at most 1/h + 1.  (A ray with one sample gives
+// at most 1.)
+static double ray_weight_bound(const VolDims &v, const Frame &fr) {
+    const double smax = fmax(v.spacing[0], fmax(v.spacing[1], v.spacing[2]));
+    return 2.0 * sqrt(3.0) * smax / fr.step + 2.0;
+}
+
+int drr_adjoint_blocks(const VolDims &v) {
+    return ((v.n0 + BRICK_X - 1) / BRICK_X) * ((v.n1 + BRICK_Y - 1) / BRICK_Y) *
+           ((v.n2 + BRICK_Z - 1) / BRICK_Z);
+}
+
+template <typename T, bool FORM_R, int K>
+static void launch_adj(const VolDims &v, const Frame &fr, const void *rays, const void *r_or_p,
+                       const void *y, double a, double b, void *bp, const void *f0,
+                       const void *mean, const void *U, const WVec &w, double *partials,
+                       uint32_t *counter, double *g_out, hipStream_t s) {
+    const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
+    const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
+    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K>), dim3(drr_adjoint_blocks(v)), dim3(256), 0, s,
+                       v, fr, nbx, nby, ray_weight_bound(v, fr), (const RayRec<T> *)rays,
+                       (const T *)r_or_p, (const T *)y, a, b, (T *)bp, (const T *)f0,
+                       (const T *)mean, (const T *)U, w, partials, counter, g_out);
 }
 
 hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *rays,
                               const void *r_or_p, const void *y, double a, double b, void *bp,
                               hipStream_t s) {
-    const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
-    const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
-    const int nbz = (v.n2 + BRICK_Z - 1) / BRICK_Z;
-    // A ray with n >= 2 samples has dt >= step / 2, and its largest
-    // per-sample index step is >= dt / (sqrt(3) max spacing); the tent
-    // weights one ray gives a voxel then sum to at most 1/h + 1.  (A ray
-    // with one sample gives at most 1.)
-    const double smax = fmax(v.spacing[0], fmax(v.spacing[1], v.spacing[2]));
-    const double hb = 2.0 * sqrt(3.0) * smax / fr.step + 2.0;
-    dim3 grid(nbx * nby * nbz), block(256);
+    const WVec w{};
     if (dt == PCAS_F32) {
         if (y)
-            hipLaunchKernelGGL((k_drr_adjoint<float, true>), grid, block, 0, s, v, fr, nbx, nby, hb,
-                               (const RayRec<float> *)rays, (const float *)r_or_p,
-                               (const float *)y, a, b, (float *)bp);
+            launch_adj<float, true, 0>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr,
+                                       w, nullptr, nullptr, nullptr, s);
         else
-            hipLaunchKernelGGL((k_drr_adjoint<float, false>), grid, block, 0, s, v, fr, nbx, nby, hb,
-                               (const RayRec<float> *)rays, (const float *)r_or_p,
-                               (const float *)nullptr, 0.0, 0.0, (float *)bp);
+            launch_adj<float, false, 0>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr,
+                                        nullptr, nullptr, w, nullptr, nullptr, nullptr, s);
     } else {
         if (y)
-            hipLaunchKernelGGL((k_drr_adjoint<double, true>), grid, block, 0, s, v, fr, nbx, nby, hb,
-                               (const RayRec<double> *)rays, (const double *)r_or_p,
-                               (const double *)y, a, b, (double *)bp);
+            launch_adj<double, true, 0>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr,
+                                        w, nullptr, nullptr, nullptr, s);
         else
-            hipLaunchKernelGGL((k_drr_adjoint<double, false>), grid, block, 0, s, v, fr, nbx, nby, hb,
-                               (const RayRec<double> *)rays, (const double *)r_or_p,
-                               (const double *)nullptr, 0.0, 0.0, (double *)bp);
+            launch_adj<double, false, 0>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr,
+                                         nullptr, nullptr, w, nullptr, nullptr, nullptr, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame &fr, int K,
+                                    const void *rays, const void *p, const void *y, double a,
+                                    double b, const void *f0, const void *mean, const void *U,
+                                    const double *w, double *partials, uint32_t *counter,
+                                    double *g_out, hipStream_t s) {
+    WVec wv{};
+    for (int k = 0; k < K; ++k) wv.w[k] = w[k];
+#define A(TT, KK)                                                                                 \
+    case KK:                                                                                      \
+        launch_adj<TT, true, KK>(v, fr, rays, p, y, a, b, nullptr, f0, mean, U, wv, partials,     \
+                                 counter, g_out, s);                                              \
+        break
+    if (dt == PCAS_F32) {
+        switch (K) { A(float, 1); A(float, 2); A(float, 3); A(float, 4);
+                     A(float, 5); A(float, 6); A(float, 7); A(float, 8);
+                     default: return hipErrorInvalidValue; }
+    } else {
+        switch (K) { A(double, 1); A(double, 2); A(double, 3); A(double, 4);
+                     A(double, 5); A(double, 6); A(double, 7); A(double, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+#undef A
     return hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ def test_default_and_paper_options(L):
     o = B.default_opts()
     assert (o.method, o.max_iter, o.fit_intensity, o.max_backtracks) == (1, 30, 1, 12)
     assert (o.mu0, o.alpha, o.beta, o.beta_lo) == (1.0, 0.1, 0.5, 0.1)
+    assert o.grad_mode == 1
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
     p = B.paper_opts()
     scale = 1.0 / g["coefficient_std"]
