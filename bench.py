@@ -54,12 +54,12 @@ KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
 
 
 def kernel_digest(kernel: str) -> str:
-    """sha256[:16] of the kernel's source file and the shared device headers."""
+    """sha256[:16] of the kernel's source file and every shared header."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_1102_1712_amd", "csrc")
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCES[kernel], "device_util.h", "internal.h"):
+    for f in (KERNEL_SOURCES[kernel], *sorted(x for x in os.listdir(csrc) if x.endswith(".h"))):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -208,9 +208,10 @@ def kernels_mode(case, dev, dt, reps: int) -> int:
 
 def stream_mode(case, dev, dt, args) -> int:
     """A sequence of projections over one rotation (15 frames/s): the planted
-    coefficients follow a seeded irregular breathing trace, each solve is
-    warm-started by the Eq. 3 prediction, and the located tumour is compared
-    with the planted trajectory's."""
+    coefficients follow a seeded irregular breathing trace; the sequence is
+    solved twice, each solve warm-started by the Eq. 3 prediction, then by
+    the previous solution, and the located tumour is compared with the
+    planted trajectory's."""
     import dataclasses
 
     import torch
@@ -227,36 +228,44 @@ def stream_mode(case, dev, dt, args) -> int:
     angles = case.proj.angle + np.arange(n) * (2 * np.pi / n)
     gen = torch.Generator(device="cuda").manual_seed(args.seed + 102)
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
-    solver = S.StreamSolver(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"],
-                            opts=B.default_opts(xtol=xtol), c0_mm=case.tumour_c0,
-                            predictor=coeffs)
+    # measured projections (same forward model, 1% noise) and true positions
     truth = np.zeros((n, 3))
     loc = torch.empty(4, dtype=torch.float64, device="cuda")
+    ys = []
     for t in range(n):
         pj = dataclasses.replace(case.proj, angle=float(angles[t]))
         rays = B.ray_table(case.vol, pj, dt, out=dev["rays"])
         f = B.warp_pca(case.vol, dev["f0"], dev["mean"], dev["U"], w_true[t])
         p = B.drr_forward(case.vol, pj, rays, f)
         rms = torch.sqrt(torch.mean(p.double() ** 2))
-        y = (p.double() + 0.01 * rms * torch.randn(p.shape, generator=gen, device="cuda",
-                                                    dtype=torch.float64)).to(dt).contiguous()
+        ys.append((p.double() + 0.01 * rms * torch.randn(p.shape, generator=gen, device="cuda",
+                                                          dtype=torch.float64)).to(dt).contiguous())
         B.tumour_position(case.vol, dev["mean"], dev["U"], w_true[t], case.tumour_c0, out=loc)
         truth[t] = loc.cpu().numpy()[:3]
-        solver.step(angles[t], y)
-        if (t + 1) % 100 == 0:
-            log(f"stream frame {t + 1}/{n}: p50 so far {np.median(solver.report.latencies()):.2f} ms")
-    located = np.array([fr.tumour_mm for fr in solver.report.frames])
-    summ = solver.report.summary()
-    errs = S.localisation_errors(located, truth)
-    print(json.dumps({"mode": "stream", "workload": case.name, "frames": n, "fps": fps,
-                      "init": "Eq. 3 prediction (L = 2, fitted on the first 60 frames)",
-                      **summ, **errs}), flush=True)
+    log(f"stream: {n} measured projections made")
+    out = {"mode": "stream", "workload": case.name, "frames": n, "fps": fps,
+           "data": "synthetic (measured images from the same forward model, 1% noise)"}
+    for init in ("predict", "previous"):
+        solver = S.StreamSolver(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"],
+                                opts=B.default_opts(xtol=xtol), c0_mm=case.tumour_c0,
+                                predictor=coeffs, init=init)
+        for t in range(n):
+            solver.step(angles[t], ys[t])
+            if (t + 1) % 200 == 0:
+                log(f"stream {init} frame {t + 1}/{n}: p50 so far "
+                    f"{np.median(solver.report.latencies()):.2f} ms")
+        located = np.array([fr.tumour_mm for fr in solver.report.frames])
+        out[init] = {**solver.report.summary(), **S.localisation_errors(located, truth)}
+    out["predict"]["init"] = "Eq. 3 prediction (L = 2, fitted on 60 earlier frames)"
+    out["previous"]["init"] = "previous frame's solution"
+    print(json.dumps(out), flush=True)
     return 0
 
 
 def adjoint_alone(case, dev, S: int) -> dict:
-    """The back-projection is not on the default gradient route; time it on
-    its own (HIP events on the current stream) for the DRR+adjoint figure."""
+    """The back-projection on its own (in the solve it runs fused with the
+    Jacobian chain), HIP events on the current stream, for the DRR+adjoint
+    figure."""
     import torch
 
     from paper_1102_1712_amd import binding as B
