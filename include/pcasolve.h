@@ -259,6 +259,54 @@ int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *pro
                      const double *w0, const pcas_opts *opts, void *workspace,
                      size_t workspace_bytes, double *w_out, pcas_report *report, void *stream);
 
+/* ---- serving: many solves in flight, batched into shared launches -------
+ * A server solves requests (one projection of one registered model each)
+ * concurrently.  Its device memory is one caller-owned arena (256-byte
+ * aligned): pcas_server_reserved_bytes() for its launch tables, the rest
+ * carved per request (pcas_server_request_bytes(): ray table, warped
+ * volume, projection, reduction scratch).  A submitted request waits until
+ * its footprint fits in the free arena and one of max_active slots is free;
+ * requests behind it that fit may go first.  Registered models (f0, mean, U)
+ * stay resident in the caller's memory; a request's y (device) must stay
+ * valid until its result has been polled.
+ * Each pcas_server_step() admits what fits, runs one operation of every
+ * admitted request's solve (an evaluation of Eq. 2, a residual, a gradient
+ * by back-projection with the chain fused; the admission work; or the
+ * tumour localisation), batching each kind of operation for all requests
+ * of one dtype and K (or slab axis) into one launch, reads back all their
+ * scalars in one transfer and returns the number of requests completed.
+ * A batched block runs what the request's own launch would run, so every
+ * result equals solve_projection's for the same request, bit for bit.
+ * Requests run the solve of their opts (method, fit, tolerances, locate);
+ * grad_mode must be 1.  report.kernel_ms is not filled.
+ * The server keeps pinned host staging for its tables and read-backs.
+ * Synchronous steps on `stream`; one thread at a time per server. */
+typedef struct pcas_server pcas_server;
+size_t pcas_server_reserved_bytes(int32_t max_active);
+int pcas_server_create(void *arena, size_t arena_bytes, int32_t max_active, void *stream,
+                       pcas_server **out);
+int pcas_server_destroy(pcas_server *server);
+/* model_id: 0, 1, ... in registration order. */
+int pcas_server_add_model(pcas_server *server, pcas_dtype dtype, const pcas_vol *vol, int32_t K,
+                          const void *f0, const void *mean, const void *U, int32_t *model_id);
+/* Arena bytes a request of this model and geometry occupies while admitted
+ * (0 for an invalid model or geometry). */
+size_t pcas_server_request_bytes(pcas_server *server, int32_t model_id, const pcas_proj *proj);
+/* w0: host double[K]; request_id: unique, increasing.  PCAS_EWORKSPACE if
+ * the request could never fit in the arena. */
+int pcas_server_submit(pcas_server *server, int32_t model_id, const pcas_proj *proj,
+                       const void *y, const double *w0, const pcas_opts *opts,
+                       int64_t *request_id);
+int pcas_server_step(pcas_server *server, int32_t *n_completed);
+/* *done = 1 and the request's status (PCAS_OK or the error that ended it)
+ * once it has completed, with w_out (host double[K], may be NULL) and
+ * report (may be NULL) filled; the request is then forgotten.  *done = 0
+ * while it is pending or running. */
+int pcas_server_poll(pcas_server *server, int64_t request_id, double *w_out, pcas_report *report,
+                     int32_t *done);
+int pcas_server_stats(pcas_server *server, int32_t *n_pending, int32_t *n_active,
+                      size_t *arena_used);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,10 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
            "warp_pca", "drr_forward", "drr_adjoint", "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
-           "objective_gradient", "solve_projection_workspace", "solve_projection")
+           "objective_gradient", "solve_projection_workspace", "solve_projection",
+           "pcas_server_reserved_bytes", "pcas_server_create", "pcas_server_destroy",
+           "pcas_server_add_model", "pcas_server_request_bytes", "pcas_server_submit",
+           "pcas_server_step", "pcas_server_poll", "pcas_server_stats")
 
 
 class PcasError(RuntimeError):
@@ -112,6 +115,17 @@ def lib():
             "tumour_position": (I32, [I32, VP, I32, P, P, DP, DP, D, I32, P, P]),
             "objective_gradient": (I32, [I32, VP, PP, I32, P, P, P, P, DP, I32, I32, P, SZ, DP,
                                          P]),
+            "pcas_server_reserved_bytes": (SZ, [I32]),
+            "pcas_server_create": (I32, [P, SZ, I32, P, ctypes.POINTER(P)]),
+            "pcas_server_destroy": (I32, [P]),
+            "pcas_server_add_model": (I32, [P, I32, VP, I32, P, P, P, ctypes.POINTER(I32)]),
+            "pcas_server_request_bytes": (SZ, [P, I32, PP]),
+            "pcas_server_submit": (I32, [P, I32, PP, P, DP, ctypes.POINTER(Opts),
+                                         ctypes.POINTER(I64)]),
+            "pcas_server_step": (I32, [P, ctypes.POINTER(I32)]),
+            "pcas_server_poll": (I32, [P, I64, DP, ctypes.POINTER(Report), ctypes.POINTER(I32)]),
+            "pcas_server_stats": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                        ctypes.POINTER(SZ)]),
             "solve_projection_workspace": (SZ, [I32, VP, PP, I32]),
             "solve_projection": (I32, [I32, VP, PP, I32, P, P, P, P, DP, ctypes.POINTER(Opts), P,
                                        SZ, DP, ctypes.POINTER(Report), P]),
@@ -425,3 +439,94 @@ def objective_gradient(vol, proj, f0, mean, U, y, w, fit_intensity: bool = True,
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     _stream(stream)), "objective_gradient")
     return float(out[0]), float(out[1]), float(out[2]), out[3:].copy()
+
+
+class Server:
+    """Serving loop over the C ABI: requests of different models (volume
+    sizes, K) solved concurrently with their work batched into shared
+    launches; admission by the footprint each request needs in the arena.
+
+    The arena is one device byte tensor owned by this object; registered
+    models' tensors and submitted measurements are kept alive here until
+    the request has been polled."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 16, device="cuda", stream=None):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().pcas_server_create(_dev(self.arena, "arena"), self.arena.numel(),
+                                        int(max_active), _stream(stream), ctypes.byref(h)),
+               "pcas_server_create")
+        self._h = h
+        self._models = []          # (vol, K, dtype, tensors)
+        self._inflight = {}        # request id -> (model id, y tensor)
+
+    @staticmethod
+    def reserved_bytes(max_active: int) -> int:
+        return int(lib().pcas_server_reserved_bytes(int(max_active)))
+
+    def add_model(self, vol, f0, mean, U) -> int:
+        K = _K_of(U, vol)
+        mid = ctypes.c_int32()
+        _check(lib().pcas_server_add_model(self._h, _dtype_code(f0), ctypes.byref(c_vol(vol)), K,
+                                           _dev(f0, "f0"), _dev(mean, "mean", f0.dtype),
+                                           _dev(U, "U", f0.dtype), ctypes.byref(mid)),
+               "pcas_server_add_model")
+        self._models.append((vol, K, f0.dtype, (f0, mean, U)))
+        return int(mid.value)
+
+    def request_bytes(self, model_id: int, proj) -> int:
+        return int(lib().pcas_server_request_bytes(self._h, int(model_id),
+                                                   ctypes.byref(c_proj(proj))))
+
+    def submit(self, model_id: int, proj, y, w0, opts: Optional[Opts] = None) -> int:
+        vol, K, dt, _ = self._models[model_id]
+        o = default_opts() if opts is None else opts
+        _, w0p = _host_doubles(w0, K)
+        rid = ctypes.c_int64()
+        _check(lib().pcas_server_submit(self._h, int(model_id), ctypes.byref(c_proj(proj)),
+                                        _dev(y, "y", dt), w0p, ctypes.byref(o),
+                                        ctypes.byref(rid)), "pcas_server_submit")
+        self._inflight[int(rid.value)] = (model_id, y)
+        return int(rid.value)
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().pcas_server_step(self._h, ctypes.byref(n)), "pcas_server_step")
+        return int(n.value)
+
+    def poll(self, request_id: int):
+        """(done, status, w, report dict); status is 0 or the request's error
+        code.  A completed request is returned once."""
+        mid, _ = self._inflight[request_id]
+        K = self._models[mid][1]
+        w = np.zeros(K)
+        rep = Report()
+        done = ctypes.c_int32()
+        st = lib().pcas_server_poll(self._h, int(request_id),
+                                    w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.byref(rep), ctypes.byref(done))
+        if not done.value:
+            if st != 0:
+                _check(st, "pcas_server_poll")
+            return False, 0, None, None
+        del self._inflight[request_id]
+        return True, int(st), w, report_dict(rep)
+
+    def stats(self):
+        p, a, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().pcas_server_stats(self._h, ctypes.byref(p), ctypes.byref(a), ctypes.byref(u)),
+               "pcas_server_stats")
+        return {"pending": int(p.value), "active": int(a.value), "arena_used": int(u.value)}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().pcas_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

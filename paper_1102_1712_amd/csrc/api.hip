@@ -6,187 +6,14 @@
 #include <string>
 #include <vector>
 
+#include "host.h"
 #include "internal.h"
+#include "solver.h"
 
 using namespace pcas;
 
-namespace {
+using namespace pcas::host;
 
-thread_local std::string g_last_error;
-
-int hip_fail(hipError_t e, const char *what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
-    return PCAS_EHIP;
-}
-
-#define HIPCHK(expr)                                        \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
-    } while (0)
-
-bool dtype_ok(int dt) { return dt == PCAS_F32 || dt == PCAS_F64; }
-size_t esize(pcas_dtype dt) { return dt == PCAS_F32 ? 4 : 8; }
-size_t rec_size(pcas_dtype dt) { return dt == PCAS_F32 ? sizeof(RayRec<float>) : sizeof(RayRec<double>); }
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
-
-int check_vol(const pcas_vol *v) {
-    if (!v) return PCAS_EINVAL;
-    int64_t N = 1;
-    for (int c = 0; c < 3; ++c) {
-        if (v->n[c] < 2) return PCAS_EINVAL;
-        if (!(v->spacing[c] > 0.0) || !isfinite(v->spacing[c]) || !isfinite(v->origin[c]))
-            return PCAS_EINVAL;
-        N *= v->n[c];
-    }
-    if (N > (int64_t)INT32_MAX) return PCAS_EINVAL;
-    return PCAS_OK;
-}
-
-int64_t nvox_of(const pcas_vol *v) { return (int64_t)v->n[0] * v->n[1] * v->n[2]; }
-
-// Kernels address a volume with 32-bit byte offsets: it must stay below 2 GiB.
-int check_vol_bytes(const pcas_vol *v, pcas_dtype dt) {
-    return nvox_of(v) * (int64_t)esize(dt) < ((int64_t)1 << 31) ? PCAS_OK : PCAS_EINVAL;
-}
-int64_t npix_of(const pcas_proj *p) { return (int64_t)p->nu * p->nv; }
-
-int check_proj(const pcas_proj *p, const pcas_vol *v) {
-    if (!p) return PCAS_EINVAL;
-    if (p->nu < 1 || p->nv < 1 || npix_of(p) > (int64_t)INT32_MAX) return PCAS_EINVAL;
-    const double vals[] = {p->angle, p->sad, p->sid, p->pitch_u, p->pitch_v,
-                           p->offset_u, p->offset_v, p->step};
-    for (double x : vals)
-        if (!isfinite(x)) return PCAS_EGEOM;
-    if (!(p->sad > 0.0) || !(p->sid > p->sad) || !(p->pitch_u > 0.0) || !(p->pitch_v > 0.0) ||
-        !(p->step > 0.0))
-        return PCAS_EGEOM;
-    // The source circles the SI axis at radius SAD; it must stay outside the
-    // volume box grown by one voxel (the back-projection footprints project
-    // that box through the source).
-    double diag2 = 0.0;
-    for (int xs = 0; xs < 2; ++xs)
-        for (int ys = 0; ys < 2; ++ys) {
-            const double x = xs ? v->origin[0] + v->n[0] * v->spacing[0] : v->origin[0] - v->spacing[0];
-            const double y = ys ? v->origin[1] + v->n[1] * v->spacing[1] : v->origin[1] - v->spacing[1];
-            if (sqrt(x * x + y * y) >= p->sad * (1.0 - 1e-9)) return PCAS_EGEOM;
-        }
-    for (int c = 0; c < 3; ++c) {
-        const double e = (v->n[c] - 1) * v->spacing[c];
-        diag2 += e * e;
-    }
-    if (sqrt(diag2) / p->step > 1.0e8) return PCAS_EGEOM;   // samples per ray must fit int32
-    return PCAS_OK;
-}
-
-VolDims make_dims(const pcas_vol *v) {
-    VolDims d;
-    d.n0 = v->n[0];
-    d.n1 = v->n[1];
-    d.n2 = v->n[2];
-    for (int c = 0; c < 3; ++c) {
-        d.spacing[c] = v->spacing[c];
-        d.inv_s[c] = 1.0 / v->spacing[c];
-        d.origin[c] = v->origin[c];
-    }
-    return d;
-}
-
-Frame make_frame(const pcas_proj *p) {
-    Frame f;
-    const double st = sin(p->angle), ct = cos(p->angle);
-    f.src[0] = p->sad * st;
-    f.src[1] = -p->sad * ct;
-    f.src[2] = 0.0;
-    const double mag = (p->sid - p->sad) / p->sad;
-    f.det[0] = -mag * f.src[0];
-    f.det[1] = -mag * f.src[1];
-    f.det[2] = 0.0;
-    f.eu[0] = ct; f.eu[1] = st; f.eu[2] = 0.0;
-    f.ev[0] = 0.0; f.ev[1] = 0.0; f.ev[2] = 1.0;
-    f.en[0] = -st; f.en[1] = ct; f.en[2] = 0.0;
-    f.sid = p->sid;
-    f.pitch_u = p->pitch_u;
-    f.pitch_v = p->pitch_v;
-    f.offset_u = p->offset_u;
-    f.offset_v = p->offset_v;
-    f.step = p->step;
-    f.nu = p->nu;
-    f.nv = p->nv;
-    return f;
-}
-
-bool finite_vec(const double *w, int K) {
-    for (int k = 0; k < K; ++k)
-        if (!isfinite(w[k])) return false;
-    return true;
-}
-
-// Small pinned host buffer per thread for scalar read-backs.
-double *host_scalars() {
-    thread_local double *buf = nullptr;
-    if (!buf) {
-        if (hipHostMalloc((void **)&buf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-            buf = nullptr;
-    }
-    return buf;
-}
-
-int readback(double *host, const double *dev, int count, hipStream_t s) {
-    double *hb = host_scalars();
-    if (!hb) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(scalars)");
-    HIPCHK(hipMemcpyAsync(hb, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    memcpy(host, hb, count * sizeof(double));
-    return PCAS_OK;
-}
-
-// ---- workspace layouts ---------------------------------------------------
-
-struct SolveWs {
-    size_t rays, f, p, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
-};
-
-int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
-    int m = drr_forward_blocks(p->nu, p->nv);
-    const int nbr = drr_adjoint_blocks(make_dims(v));
-    m = m > nbr ? m : nbr;
-    m = m > grad_w_blocks(nvox_of(v)) ? m : grad_w_blocks(nvox_of(v));
-    m = m > sums_blocks(npix_of(p)) ? m : sums_blocks(npix_of(p));
-    return m;
-}
-
-SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p, int K) {
-    SolveWs L;
-    const size_t M = (size_t)npix_of(p), N = (size_t)nvox_of(v), es = esize(dt);
-    size_t off = 0;
-    L.rays = off; off += align256(M * rec_size(dt));
-    L.f = off; off += align256(N * es);
-    L.p = off; off += align256(M * es);
-    L.vol2 = off; off += align256((size_t)(K > 1 ? K : 1) * N * es);
-    L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
-    L.counters = off; off += 256;
-    L.scalars = off; off += align256(64 * sizeof(double));
-    L.total = off;
-    return L;
-}
-
-int check_opts(const pcas_opts *o) {
-    if (!o) return PCAS_EINVAL;
-    if (o->method != 0 && o->method != 1) return PCAS_EINVAL;
-    if (o->grad_mode != 0 && o->grad_mode != 1) return PCAS_EINVAL;
-    if (o->max_iter < 0 || o->max_backtracks < 1 || o->locate_max_iter < 1) return PCAS_EINVAL;
-    if (!(o->mu0 > 0.0) || !(o->alpha > 0.0 && o->alpha < 1.0) || !(o->beta > 0.0 && o->beta < 1.0))
-        return PCAS_EINVAL;
-    if (!(o->mu_min >= 0.0) || !(o->gtol_rel >= 0.0) || !(o->xtol >= 0.0) || !(o->locate_tol > 0.0))
-        return PCAS_EINVAL;
-    if (!(o->beta_lo > 0.0 && o->beta_lo <= o->beta)) return PCAS_EINVAL;
-    if (o->locate && !finite_vec(o->c0_mm, 3)) return PCAS_EINVAL;
-    return PCAS_OK;
-}
-
-}  // namespace
 
 // =========================================================================
 extern "C" {
@@ -591,143 +418,31 @@ struct Solver {
     }
 };
 
-double dot(const double *a, const double *b, int K) {
-    double s = 0.0;
-    for (int k = 0; k < K; ++k) s += a[k] * b[k];
-    return s;
-}
-
-// Appendix algorithm: alternate Eq. A.1 with the normalised gradient step of
-// Eq. A.2, the step from Armijo backtracking with (a, b) held fixed.
-int run_paper(Solver &S, const pcas_opts &o, double *w, pcas_report *rep) {
-    const int K = S.K;
-    double a, b, J, g[PCAS_MAX_K], d[PCAS_MAX_K], wt[PCAS_MAX_K];
-    int st = S.evaluate(w, nullptr, &J, &a, &b);       // step 1 at w0
-    if (st) return st;
-    rep->J0 = J;
-    rep->status = PCAS_STOP_MAXITER;
-    for (int it = 0; it < o.max_iter; ++it) {
-        if (it > 0 && (st = S.residual(nullptr, &J, &a, &b))) return st;   // step 1
-        rep->J = J;
-        rep->a = a;
-        rep->b = b;
-        if ((st = S.gradient(w, a, b, g))) return st;
-        const double gn = sqrt(dot(g, g, K));
-        if (it == 0) rep->gnorm0 = gn;
-        rep->gnorm = gn;
-        if (gn == 0.0 || J == 0.0) {
-            rep->status = PCAS_STOP_CONVERGED;
-            return PCAS_OK;
-        }
-        for (int k = 0; k < K; ++k) d[k] = g[k] / gn;                   // step 2
-        double mu = o.mu0;
-        const double ab[2] = {a, b};
-        for (;;) {
-            for (int k = 0; k < K; ++k) wt[k] = w[k] - mu * d[k];
-            double Jt, at, bt;
-            if ((st = S.evaluate(wt, ab, &Jt, &at, &bt))) return st;
-            if (Jt <= J - o.alpha * mu * gn) break;
-            mu *= o.beta;
-            if (mu < o.mu_min) {
-                rep->status = PCAS_STOP_CONVERGED;
-                return PCAS_OK;
-            }
-        }
-        for (int k = 0; k < K; ++k) w[k] = wt[k];
-        rep->iters = it + 1;
-    }
-    if (o.max_iter > 0 && (st = S.residual(nullptr, &J, &a, &b))) return st;
-    rep->a = a;
-    rep->b = b;
-    rep->J = J;
-    return PCAS_OK;
-}
-
-// PR+ nonlinear CG on the reduced objective phi(w) = min_{a,b} J(w, a, b).
-int run_cg(Solver &S, const pcas_opts &o, double *w, pcas_report *rep) {
-    const int K = S.K;
-    const double ftol = o.ftol_rel >= 0.0 ? o.ftol_rel : (S.dt == PCAS_F32 ? 1e-8 : 0.0);
-    double phi, a, b, g[PCAS_MAX_K], d[PCAS_MAX_K], wt[PCAS_MAX_K], gnew[PCAS_MAX_K];
-    int st = S.evaluate(w, nullptr, &phi, &a, &b);
-    if (st) return st;
-    if ((st = S.gradient(w, a, b, g))) return st;
-    rep->J0 = phi;
-    const double g0 = sqrt(dot(g, g, K));
-    rep->gnorm0 = g0;
-    for (int k = 0; k < K; ++k) d[k] = -g[k];
-    bool restart = true, first = true;
-    double t_prev = 0.0, gd_prev = 0.0;
-    int it = 0;
-    rep->status = PCAS_STOP_MAXITER;
-    while (it < o.max_iter) {
-        const double gn = sqrt(dot(g, g, K));
-        if (gn <= o.gtol_rel * g0 || phi == 0.0) {
-            rep->status = PCAS_STOP_CONVERGED;
+// Runs the solve's state machine against this solver's operations.
+int drive(Solver &S, SolveMachine &m) {
+    while (!m.done()) {
+        const SolveOp &op = m.op();
+        double J, a, b;
+        int st;
+        switch (op.kind) {
+        case OP_EVAL:
+            if ((st = S.evaluate(op.w, op.fixed_ab ? op.ab : nullptr, &J, &a, &b))) return st;
+            m.eval_result(J, a, b);
+            break;
+        case OP_RESID:
+            if ((st = S.residual(nullptr, &J, &a, &b))) return st;
+            m.eval_result(J, a, b);
+            break;
+        case OP_GRAD: {
+            double g[PCAS_MAX_K];
+            if ((st = S.gradient(op.w, op.ab[0], op.ab[1], g))) return st;
+            m.grad_result(g);
             break;
         }
-        double gd = dot(g, d, K);
-        if (gd >= 0.0) {
-            for (int k = 0; k < K; ++k) d[k] = -g[k];
-            gd = -gn * gn;
-            restart = true;
-        }
-        const double dn = sqrt(dot(d, d, K));
-        double t = first ? o.mu0 / dn : t_prev * gd_prev / gd;
-        bool accepted = false, at_noise = false;
-        double phi_t = 0.0, a_t = 0.0, b_t = 0.0;
-        for (int bt = 0; bt < o.max_backtracks; ++bt) {
-            if (t * dn < o.xtol) break;
-            for (int k = 0; k < K; ++k) wt[k] = w[k] + t * d[k];
-            if ((st = S.evaluate(wt, nullptr, &phi_t, &a_t, &b_t))) return st;
-            if (phi_t <= phi + o.alpha * t * gd) {
-                accepted = true;
-                break;
-            }
-            if (fabs(phi_t - phi) <= ftol * phi) {   // below the objective's noise
-                at_noise = true;
-                break;
-            }
-            const double tq = -gd * t * t / (2.0 * (phi_t - phi - gd * t));
-            const double lo = o.beta_lo * t, hi = o.beta * t;
-            t = tq < lo ? lo : (tq > hi ? hi : tq);
-        }
-        if (at_noise) {
-            rep->status = PCAS_STOP_CONVERGED;
+        case OP_DONE:
             break;
         }
-        if (!accepted) {
-            if (restart) {
-                rep->status = PCAS_STOP_LINESEARCH;
-                break;
-            }
-            for (int k = 0; k < K; ++k) d[k] = -g[k];
-            restart = true;
-            continue;
-        }
-        for (int k = 0; k < K; ++k) w[k] = wt[k];
-        phi = phi_t;
-        a = a_t;
-        b = b_t;
-        if ((st = S.gradient(w, a, b, gnew))) return st;
-        double num = 0.0;
-        for (int k = 0; k < K; ++k) num += gnew[k] * (gnew[k] - g[k]);
-        double beta_pr = num / dot(g, g, K);
-        beta_pr = beta_pr > 0.0 ? beta_pr : 0.0;
-        for (int k = 0; k < K; ++k) {
-            d[k] = -gnew[k] + beta_pr * d[k];
-            g[k] = gnew[k];
-        }
-        t_prev = t;
-        gd_prev = gd;
-        restart = false;
-        first = false;
-        ++it;
     }
-    rep->iters = it;
-    rep->J = phi;
-    rep->a = a;
-    rep->b = b;
-    rep->gnorm = sqrt(dot(g, g, K));
     return PCAS_OK;
 }
 
@@ -756,13 +471,14 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
                         opts->profile != 0, workspace, stream)))
         return st;
 
-    double w[PCAS_MAX_K];
-    for (int k = 0; k < K; ++k) w[k] = w0[k];
-    st = opts->method == 0 ? run_paper(S, *opts, w, report) : run_cg(S, *opts, w, report);
-    report->n_fevals = S.n_fevals;
-    report->n_grads = S.n_grads;
+    SolveMachine m;
+    const double ftol = opts->ftol_rel >= 0.0 ? opts->ftol_rel : (dtype == PCAS_F32 ? 1e-8 : 0.0);
+    m.start(*opts, K, ftol, w0);
+    st = drive(S, m);
+    *report = m.report();
     if (st) return st;
-    for (int k = 0; k < K; ++k) w_out[k] = w[k];
+    double w[PCAS_MAX_K];
+    for (int k = 0; k < K; ++k) w_out[k] = w[k] = m.w()[k];
 
     if (opts->locate) {
         HIPCHK(S.timed(PCAS_K_LOCATE, [&] {

@@ -161,4 +161,13 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, i
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
+// The job of a batched launch that owns this block (jobs sorted by block0;
+// the scan is wave-uniform).
+template <typename Job>
+__device__ __forceinline__ int job_of(const Job *__restrict__ jobs, int njobs) {
+    int j = 0;
+    while (j + 1 < njobs && (int)blockIdx.x >= jobs[j + 1].block0) ++j;
+    return j;
+}
+
 }  // namespace pcas

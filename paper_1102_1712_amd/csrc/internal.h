@@ -79,6 +79,64 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Intensity-fit mode of the residual pass (see launch_residual).
+enum { FIT_COEF = 0, FIT_REFIT = 1, FIT_FIXED = 2 };
+struct FitArgs {
+    int mode;
+    double a, b, sy, syy, m;
+};
+
+// ---- batched launches: one launch serves several requests ----------------
+// A job holds one request's arguments and the range [block0, block0 +
+// nblocks) of the launch's blocks it owns; block blockIdx.x - block0 of a
+// job runs exactly what block of that index runs in the request's own
+// launch (same tiles, same reduction slots and order), so a request's
+// results do not depend on what it is batched with.  Jobs are sorted by
+// block0 and live in device memory.
+struct WarpJob {
+    VolDims vd;
+    const void *f0, *mean, *U;
+    WVec w;
+    void *f;
+    int block0, nblocks;
+};
+struct FwdJob {                 // projection with the fit sums (FWD_SUMS)
+    VolDims vd;
+    Frame fr;
+    int tiles_u, slab;
+    const void *rays, *f;
+    void *p;
+    const void *y;
+    double *partials;
+    uint32_t *counter;
+    double *out;
+    int block0, nblocks;
+};
+struct ResJob {
+    int64_t M;
+    const void *p, *y;
+    FitArgs fa;
+    const double *src;
+    double *partials;
+    uint32_t *counter;
+    double *out;
+    int block0, nblocks;
+};
+struct AdjJob {                 // back-projection of the residual + Jacobian chain
+    VolDims vd;
+    Frame fr;
+    int nbx, nby;
+    double hb;
+    const void *rays, *p, *y;
+    double a, b;
+    const void *f0, *mean, *U;
+    WVec w;
+    double *partials;
+    uint32_t *counter;
+    double *g_out;
+    int block0, nblocks;
+};
+
 // ---- launchers (return the HIP error of the launch) ----------------------
 hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s);
 
@@ -154,11 +212,6 @@ hipError_t launch_pair_sums(pcas_dtype dt, int64_t M, const void *a, const void 
 //   FIT_REFIT: Eq. A.1 from sum p = src[0], sum p*y = src[1] (device) and the
 //              host-known sum y, sum y^2 and pixel count (NaN if singular)
 //   FIT_FIXED: the values a, b given here
-enum { FIT_COEF = 0, FIT_REFIT = 1, FIT_FIXED = 2 };
-struct FitArgs {
-    int mode;
-    double a, b, sy, syy, m;
-};
 // r = p - a*y - b; out[0] = J = sum r^2, out[1] = a, out[2] = b.
 // r may be nullptr or alias p.
 hipError_t launch_residual(pcas_dtype dt, int64_t M, const void *p, const void *y,
@@ -172,5 +225,28 @@ hipError_t launch_fit_from_sums(int64_t M, int fit, const double *sums, double *
 hipError_t launch_locate(pcas_dtype dt, const VolDims &v, int K, const void *mean, const void *U,
                          const double *w, const double c0[3], double tol, int max_iter,
                          double *out, hipStream_t s);
+
+// Batched forms (jobs: device array sorted by block0; total_blocks = sum of
+// the jobs' nblocks).  A job is filled like the corresponding single launch;
+// the make_* helpers give its arguments and block count (block0 = 0).
+int warp_blocks(int64_t N);
+hipError_t launch_warp_pca_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,
+                                 int total_blocks, hipStream_t s);
+FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, const void *rays,
+                    const void *f, void *p, const void *y, double *partials, uint32_t *counter,
+                    double *sums);
+hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *jobs, int njobs,
+                                         int total_blocks, hipStream_t s);
+hipError_t launch_residual_batch(pcas_dtype dt, const ResJob *jobs, int njobs, int total_blocks,
+                                 hipStream_t s);
+AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,
+                    const void *y, double a, double b, const void *f0, const void *mean,
+                    const void *U, const double *w, double *partials, uint32_t *counter,
+                    double *g_out);
+hipError_t launch_drr_adjoint_chain_batch(pcas_dtype dt, int K, const AdjJob *jobs, int njobs,
+                                          int total_blocks, hipStream_t s);
+// dst[i * count + t] = src[i][t] for i < n (src: device array of pointers).
+hipError_t launch_gather_scalars(const double *const *src, double *dst, int n, int count,
+                                 hipStream_t s);
 
 }  // namespace pcas

@@ -150,12 +150,13 @@ constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_L
 // q_v = (P f_v) are not stored; out[v] = 2 sum_rays r q_v with the residual
 // r = p - a y - b of the stored projection p.
 template <typename T, int AX, int NV, int MODE>
-__global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int tiles_u, int slab,
-                                                     const RayRec<T> *__restrict__ rays,
-                                                     const T *__restrict__ f, T *__restrict__ p,
-                                                     const T *__restrict__ y, double fa, double fb,
-                                                     double *__restrict__ partials,
-                                                     uint32_t *counter, double *__restrict__ out) {
+__device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame &fr, int tiles_u,
+                                                  int slab, const RayRec<T> *__restrict__ rays,
+                                                  const T *__restrict__ f, T *__restrict__ p,
+                                                  const T *__restrict__ y, double fa, double fb,
+                                                  double *__restrict__ partials,
+                                                  uint32_t *counter, double *__restrict__ out,
+                                                  int lb, int nb) {
     constexpr int SPLIT = FWD_SPLIT;
     constexpr int CAPT = fwd_lds_bytes(NV) / (int)sizeof(T);   // all volumes
     constexpr int CAP = CAPT / NV;                               // one volume's box
@@ -167,8 +168,7 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
     const int nn[3] = {n0, n1, n2};
     const int64_t N = (int64_t)n0 * n1 * n2;
     const int nu = fr.nu, nv = fr.nv;
-    const int nb = gridDim.x;
-    const int bid = xcd_remap(blockIdx.x, nb);
+    const int bid = xcd_remap(lb, nb);
     const int tu = bid % tiles_u, tv = bid / tiles_u;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int seg = lane % SPLIT, rl = lane / SPLIT;
@@ -389,6 +389,29 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
     }
 }
 
+template <typename T, int AX, int NV, int MODE>
+__global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int tiles_u, int slab,
+                                                     const RayRec<T> *__restrict__ rays,
+                                                     const T *__restrict__ f, T *__restrict__ p,
+                                                     const T *__restrict__ y, double fa, double fb,
+                                                     double *__restrict__ partials,
+                                                     uint32_t *counter, double *__restrict__ out) {
+    drr_forward_block<T, AX, NV, MODE>(vd, fr, tiles_u, slab, rays, f, p, y, fa, fb, partials,
+                                       counter, out, blockIdx.x, gridDim.x);
+}
+
+// Several requests' projections (with the fit sums) in one launch.
+template <typename T, int AX>
+__global__ __launch_bounds__(256) void k_drr_forward_batch(const FwdJob *__restrict__ jobs,
+                                                           int njobs) {
+    const int j = job_of(jobs, njobs);
+    const FwdJob &J = jobs[j];
+    drr_forward_block<T, AX, 1, FWD_SUMS>(J.vd, J.fr, J.tiles_u, J.slab,
+                                          (const RayRec<T> *)J.rays, (const T *)J.f, (T *)J.p,
+                                          (const T *)J.y, 0.0, 0.0, J.partials, J.counter, J.out,
+                                          blockIdx.x - J.block0, J.nblocks);
+}
+
 int drr_forward_blocks(int nu, int nv) {
     return ((nu + TILE_U - 1) / TILE_U) * ((nv + TILE_V - 1) / TILE_V);
 }
@@ -478,6 +501,44 @@ hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
         else
             launch_fwd_axis<double, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
                                                   0.0, 0.0, nullptr, nullptr, nullptr, s);
+    }
+    return hipGetLastError();
+}
+
+FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, const void *rays,
+                    const void *f, void *p, const void *y, double *partials, uint32_t *counter,
+                    double *sums) {
+    FwdJob J;
+    J.vd = v;
+    J.fr = fr;
+    J.tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
+    J.slab = plan.slab;
+    J.rays = rays;
+    J.f = f;
+    J.p = p;
+    J.y = y;
+    J.partials = partials;
+    J.counter = counter;
+    J.out = sums;
+    J.block0 = 0;
+    J.nblocks = drr_forward_blocks(fr.nu, fr.nv);
+    return J;
+}
+
+hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *jobs, int njobs,
+                                         int total_blocks, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    const dim3 grid(total_blocks), block(256);
+    if (dt == PCAS_F32) {
+        if (axis == 0)
+            hipLaunchKernelGGL((k_drr_forward_batch<float, 0>), grid, block, 0, s, jobs, njobs);
+        else
+            hipLaunchKernelGGL((k_drr_forward_batch<float, 1>), grid, block, 0, s, jobs, njobs);
+    } else {
+        if (axis == 0)
+            hipLaunchKernelGGL((k_drr_forward_batch<double, 0>), grid, block, 0, s, jobs, njobs);
+        else
+            hipLaunchKernelGGL((k_drr_forward_batch<double, 1>), grid, block, 0, s, jobs, njobs);
     }
     return hipGetLastError();
 }
@@ -605,16 +666,17 @@ __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__re
 // bp * sum_c U_kc df/dx_c go through the fixed-order grid reduction into
 // g_out[k] (times 2).
 template <typename T, bool FORM_R, int K>
-__global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
-                                                     double hb,
-                                                     const RayRec<T> *__restrict__ rays,
-                                                     const T *__restrict__ rp,
-                                                     const T *__restrict__ y, double a, double b,
-                                                     T *__restrict__ bp, const T *__restrict__ f0,
-                                                     const T *__restrict__ mean,
-                                                     const T *__restrict__ U, WVec w,
-                                                     double *__restrict__ partials,
-                                                     uint32_t *counter, double *__restrict__ g_out) {
+__device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame &fr, int nbx,
+                                                  int nby, double hb,
+                                                  const RayRec<T> *__restrict__ rays,
+                                                  const T *__restrict__ rp,
+                                                  const T *__restrict__ y, double a, double b,
+                                                  T *__restrict__ bp, const T *__restrict__ f0,
+                                                  const T *__restrict__ mean,
+                                                  const T *__restrict__ U, const WVec &w,
+                                                  double *__restrict__ partials,
+                                                  uint32_t *counter, double *__restrict__ g_out,
+                                                  int lb, int nb) {
     __shared__ unsigned long long acc[ACC_WORDS];
     __shared__ T q_f[ADJ_WAVES][7][QCAP];       // e[3], d[3], scaled dt * r
     __shared__ int q_s[ADJ_WAVES][2][QCAP];     // first and last sample
@@ -623,7 +685,7 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
     // Bricks go round-robin over the XCDs in launch order: only bricks inside
     // the x-ray cone carry work, so contiguous per-XCD ranges would leave the
     // XCDs that hold the outer z-slabs idle.
-    const int bid = blockIdx.x;
+    const int bid = lb;
     const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
     const int lo[3] = {bx * BRICK_X, by * BRICK_Y, bz * BRICK_Z};
     const int hi[3] = {min(lo[0] + BRICK_X, n0) - 1, min(lo[1] + BRICK_Y, n1) - 1,
@@ -832,8 +894,36 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
                     gacc[kk] += (double)fma_t(u[kk][0], j0, fma_t(u[kk][1], j1, u[kk][2] * j2));
             }
         }
-        grid_reduce<K>(gacc, partials, counter, g_out, bid, gridDim.x, 2.0);
+        grid_reduce<K>(gacc, partials, counter, g_out, bid, nb, 2.0);
     }
+}
+
+template <typename T, bool FORM_R, int K>
+__global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
+                                                     double hb,
+                                                     const RayRec<T> *__restrict__ rays,
+                                                     const T *__restrict__ rp,
+                                                     const T *__restrict__ y, double a, double b,
+                                                     T *__restrict__ bp, const T *__restrict__ f0,
+                                                     const T *__restrict__ mean,
+                                                     const T *__restrict__ U, WVec w,
+                                                     double *__restrict__ partials,
+                                                     uint32_t *counter, double *__restrict__ g_out) {
+    drr_adjoint_block<T, FORM_R, K>(vd, fr, nbx, nby, hb, rays, rp, y, a, b, bp, f0, mean, U, w,
+                                    partials, counter, g_out, blockIdx.x, gridDim.x);
+}
+
+// Several requests' gradients (back-projection + chain) in one launch.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_drr_adjoint_batch(const AdjJob *__restrict__ jobs,
+                                                           int njobs) {
+    const int j = job_of(jobs, njobs);
+    const AdjJob &J = jobs[j];
+    drr_adjoint_block<T, true, K>(J.vd, J.fr, J.nbx, J.nby, J.hb, (const RayRec<T> *)J.rays,
+                                  (const T *)J.p, (const T *)J.y, J.a, J.b, (T *)nullptr,
+                                  (const T *)J.f0, (const T *)J.mean, (const T *)J.U, J.w,
+                                  J.partials, J.counter, J.g_out, blockIdx.x - J.block0,
+                                  J.nblocks);
 }
 
 // A ray with n >= 2 samples has dt >= step / 2, and its largest per-sample
@@ -896,6 +986,55 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
     case KK:                                                                                      \
         launch_adj<TT, true, KK>(v, fr, rays, p, y, a, b, nullptr, f0, mean, U, wv, partials,     \
                                  counter, g_out, s);                                              \
+        break
+    if (dt == PCAS_F32) {
+        switch (K) { A(float, 1); A(float, 2); A(float, 3); A(float, 4);
+                     A(float, 5); A(float, 6); A(float, 7); A(float, 8);
+                     default: return hipErrorInvalidValue; }
+    } else {
+        switch (K) { A(double, 1); A(double, 2); A(double, 3); A(double, 4);
+                     A(double, 5); A(double, 6); A(double, 7); A(double, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+#undef A
+    return hipGetLastError();
+}
+
+AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,
+                    const void *y, double a, double b, const void *f0, const void *mean,
+                    const void *U, const double *w, double *partials, uint32_t *counter,
+                    double *g_out) {
+    AdjJob J;
+    J.vd = v;
+    J.fr = fr;
+    J.nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
+    J.nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
+    J.hb = ray_weight_bound(v, fr);
+    J.rays = rays;
+    J.p = p;
+    J.y = y;
+    J.a = a;
+    J.b = b;
+    J.f0 = f0;
+    J.mean = mean;
+    J.U = U;
+    J.w = WVec{};
+    for (int k = 0; k < K; ++k) J.w.w[k] = w[k];
+    J.partials = partials;
+    J.counter = counter;
+    J.g_out = g_out;
+    J.block0 = 0;
+    J.nblocks = drr_adjoint_blocks(v);
+    return J;
+}
+
+hipError_t launch_drr_adjoint_chain_batch(pcas_dtype dt, int K, const AdjJob *jobs, int njobs,
+                                          int total_blocks, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+#define A(TT, KK)                                                                                 \
+    case KK:                                                                                      \
+        hipLaunchKernelGGL((k_drr_adjoint_batch<TT, KK>), dim3(total_blocks), dim3(256), 0, s,     \
+                           jobs, njobs);                                                          \
         break
     if (dt == PCAS_F32) {
         switch (K) { A(float, 1); A(float, 2); A(float, 3); A(float, 4);

@@ -45,13 +45,11 @@ __device__ __forceinline__ void fit_normal_equations(double sp, double spy, doub
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual(int64_t M, const T *__restrict__ p,
-                                                  const T *__restrict__ y, FitArgs fa,
-                                                  const double *__restrict__ src, T *r,
-                                                  double *__restrict__ partials, uint32_t *counter,
-                                                  double *__restrict__ out) {
-    const int nb = gridDim.x;
-    const int bid = blockIdx.x;
+__device__ __forceinline__ void residual_block(int64_t M, const T *__restrict__ p,
+                                               const T *__restrict__ y, const FitArgs &fa,
+                                               const double *__restrict__ src, T *r,
+                                               double *__restrict__ partials, uint32_t *counter,
+                                               double *__restrict__ out, int bid, int nb) {
     double A = fa.a, B = fa.b;
     if (fa.mode == FIT_COEF) {
         A = src[0];
@@ -70,6 +68,36 @@ __global__ __launch_bounds__(256) void k_residual(int64_t M, const T *__restrict
         s[0] += rv * rv;
     }
     grid_reduce<1>(s, partials, counter, out, bid, nb, 1.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(int64_t M, const T *__restrict__ p,
+                                                  const T *__restrict__ y, FitArgs fa,
+                                                  const double *__restrict__ src, T *r,
+                                                  double *__restrict__ partials, uint32_t *counter,
+                                                  double *__restrict__ out) {
+    residual_block<T>(M, p, y, fa, src, r, partials, counter, out, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_batch(const ResJob *__restrict__ jobs,
+                                                        int njobs) {
+    const int j = job_of(jobs, njobs);
+    const ResJob &J = jobs[j];
+    residual_block<T>(J.M, (const T *)J.p, (const T *)J.y, J.fa, J.src, (T *)nullptr, J.partials,
+                      J.counter, J.out, blockIdx.x - J.block0, J.nblocks);
+}
+
+hipError_t launch_residual_batch(pcas_dtype dt, const ResJob *jobs, int njobs, int total_blocks,
+                                 hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    if (dt == PCAS_F32)
+        hipLaunchKernelGGL(k_residual_batch<float>, dim3(total_blocks), dim3(256), 0, s, jobs,
+                           njobs);
+    else
+        hipLaunchKernelGGL(k_residual_batch<double>, dim3(total_blocks), dim3(256), 0, s, jobs,
+                           njobs);
+    return hipGetLastError();
 }
 
 // (a, b) of Eq. A.1 from (sum p, sum p y, sum p p, sum y, sum y y).
@@ -110,6 +138,21 @@ hipError_t launch_residual(pcas_dtype dt, int64_t M, const void *p, const void *
 hipError_t launch_fit_from_sums(int64_t M, int fit, const double *sums, double *stats,
                                 hipStream_t s) {
     hipLaunchKernelGGL(k_fit_from_sums, dim3(1), dim3(64), 0, s, M, fit, sums, stats);
+    return hipGetLastError();
+}
+
+// Copies count doubles from each of n device locations into dst (n x count),
+// so a batch's scalars come back in one transfer.
+__global__ void k_gather_scalars(const double *const *__restrict__ src, double *__restrict__ dst,
+                                 int count) {
+    const int b = blockIdx.x;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) dst[b * count + t] = src[b][t];
+}
+
+hipError_t launch_gather_scalars(const double *const *src, double *dst, int n, int count,
+                                 hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_scalars, dim3(n), dim3(64), 0, s, src, dst, count);
     return hipGetLastError();
 }
 

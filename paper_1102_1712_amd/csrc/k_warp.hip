@@ -79,13 +79,15 @@ __global__ __launch_bounds__(256) void k_warp_trilinear(VolDims vd, const T *__r
                        (T)vd.inv_s[0], (T)vd.inv_s[1], (T)vd.inv_s[2]);
 }
 
+// Block lb of nb blocks of one warp (the single and the batched launch both
+// run this).
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restrict__ f0,
-                                                  const T *__restrict__ mean,
-                                                  const T *__restrict__ U, WVec w,
-                                                  T *__restrict__ f) {
+__device__ __forceinline__ void warp_pca_block(const VolDims &vd, const T *__restrict__ f0,
+                                               const T *__restrict__ mean,
+                                               const T *__restrict__ U, const WVec &w,
+                                               T *__restrict__ f, int lb, int nb) {
     const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t b = xcd_remap(lb, nb);
     const int64_t v = b * blockDim.x + threadIdx.x;
     if (v >= N) return;
     const int i = (int)(v % vd.n0);
@@ -101,6 +103,24 @@ __global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restric
     }
     f[v] = warp_gather(f0, vd.n0, vd.n1, vd.n2, i, j, k, x[0], x[1], x[2], (T)vd.inv_s[0],
                        (T)vd.inv_s[1], (T)vd.inv_s[2]);
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restrict__ f0,
+                                                  const T *__restrict__ mean,
+                                                  const T *__restrict__ U, WVec w,
+                                                  T *__restrict__ f) {
+    warp_pca_block<T, K>(vd, f0, mean, U, w, f, blockIdx.x, gridDim.x);
+}
+
+// Several requests' warps in one launch (jobs sorted by block0).
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_warp_pca_batch(const WarpJob *__restrict__ jobs,
+                                                        int njobs) {
+    const int j = job_of(jobs, njobs);
+    const WarpJob &J = jobs[j];
+    warp_pca_block<T, K>(J.vd, (const T *)J.f0, (const T *)J.mean, (const T *)J.U, J.w, (T *)J.f,
+                         blockIdx.x - J.block0, J.nblocks);
 }
 
 namespace {
@@ -150,6 +170,29 @@ hipError_t launch_pca_dvf(pcas_dtype dt, int64_t N, int K, const void *mean, con
 #undef CALL
     }
 #define CALL(KK) pca_dvf_k<double, KK>(N, mean, U, wv, dvf, s)
+    PCAS_K_SWITCH(K, CALL)
+#undef CALL
+}
+
+int warp_blocks(int64_t N) { return (int)((N + 255) / 256); }
+
+namespace {
+template <typename T, int K>
+hipError_t warp_batch_k(const WarpJob *jobs, int njobs, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_warp_pca_batch<T, K>), dim3(total_blocks), dim3(256), 0, s, jobs, njobs);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_warp_pca_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,
+                                 int total_blocks, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    if (dt == PCAS_F32) {
+#define CALL(KK) warp_batch_k<float, KK>(jobs, njobs, total_blocks, s)
+        PCAS_K_SWITCH(K, CALL)
+#undef CALL
+    }
+#define CALL(KK) warp_batch_k<double, KK>(jobs, njobs, total_blocks, s)
     PCAS_K_SWITCH(K, CALL)
 #undef CALL
 }

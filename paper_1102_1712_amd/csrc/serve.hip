@@ -1,0 +1,520 @@
+// Serving loop: many per-projection solves in flight at once, of different
+// volume sizes, their work batched into shared launches.
+//
+// The caller hands the server one device arena.  A request is admitted when
+// its workspace (ray table, warped volume, projection, reduction scratch)
+// fits in the arena's free space and a slot is free; the volumes and modes
+// of the registered models stay resident in the caller's memory.  Every
+// step() runs one operation of every admitted request's solve state machine
+// (an evaluation, a residual or a gradient; or the admission work; or the
+// tumour localisation at the end), with each kind of operation for all
+// requests in one launch per (dtype, K) or (dtype, slab axis) group, then
+// reads back all their scalars in one transfer and advances the machines.
+// Requests that arrive while others run are admitted at the next step as
+// memory and slots free up.  A batched block runs exactly what the same
+// block of the request's own launch runs, so every request's result is bit
+// for bit the one solve_projection gives for it alone.
+#include <algorithm>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "host.h"
+#include "internal.h"
+#include "solver.h"
+
+using namespace pcas;
+using namespace pcas::host;
+
+namespace {
+
+constexpr int GATHER = 32;   // scalars read back per request and step
+
+struct Model {
+    pcas_dtype dt;
+    pcas_vol vol;
+    VolDims vd;
+    int K;
+    const void *f0, *mean, *U;
+};
+
+enum Phase { PH_PREPARE, PH_RUN, PH_LOCATE, PH_DONE };
+
+struct Request {
+    int64_t id = 0;
+    int model = 0;
+    pcas_proj proj{};
+    Frame fr{};
+    ForwardPlan plan{};
+    const void *y = nullptr;
+    pcas_opts opts{};
+    double w0[PCAS_MAX_K] = {0};
+    SolveWs L{};
+    size_t off = 0;
+    char *ws = nullptr;
+    int64_t M = 0;
+    double sy = 0.0, syy = 0.0;
+    SolveMachine m;
+    Phase phase = PH_PREPARE;
+    int status = PCAS_OK;
+    double w[PCAS_MAX_K] = {0};
+    pcas_report rep{};
+
+    double *scal() const { return (double *)(ws + L.scalars); }
+    uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
+    double *partials() const { return (double *)(ws + L.partials); }
+};
+
+// First-fit allocation over [0, size) in 256-byte units, coalescing on free.
+class Arena {
+public:
+    void init(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used_ += bytes;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0;
+};
+
+}  // namespace
+
+struct pcas_server {
+    hipStream_t s = nullptr;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    int max_active = 0;
+    Arena pool;                       // the arena beyond the reserved tables
+    size_t pool_base = 0;
+    // reserved at the start of the arena: job tables, gather pointers, gather output
+    char *tables_dev = nullptr;
+    size_t tables_bytes = 0;
+    char *tables_host = nullptr;      // pinned staging of the tables
+    double *gather_host = nullptr;    // pinned
+    std::vector<Model> models;
+    std::deque<Request *> pending;
+    std::vector<Request *> active;
+    std::map<int64_t, Request *> finished;
+    int64_t next_id = 1;
+};
+
+namespace {
+
+size_t table_bytes(int max_active) {
+    const size_t per = sizeof(WarpJob) + sizeof(FwdJob) + sizeof(ResJob) + sizeof(AdjJob) +
+                       sizeof(double *) + GATHER * sizeof(double);
+    return align256(per * (size_t)max_active + 4096);
+}
+
+size_t request_bytes(const Model &md, const pcas_proj *proj) {
+    return solve_layout(md.dt, &md.vol, proj, md.K, false).total;
+}
+
+void finish_request(pcas_server *S, Request *r, int status) {
+    r->status = status;
+    r->phase = PH_DONE;
+    S->pool.release(r->off, r->L.total);
+    r->ws = nullptr;
+    S->finished[r->id] = r;
+}
+
+// Work of a newly admitted request: counters, ray table, sums of y.
+int admit(pcas_server *S, Request *r) {
+    const Model &md = S->models[r->model];
+    r->ws = S->arena + S->pool_base + r->off;
+    HIPCHK(launch_fill_u32(r->counters(), 64, 0u, S->s));
+    HIPCHK(launch_ray_table(md.dt, md.vd, r->fr, r->ws + r->L.rays, S->s));
+    HIPCHK(launch_pair_sums(md.dt, r->M, r->y, r->y, r->partials(), &r->counters()[2],
+                            r->scal() + 16, S->s));
+    r->phase = PH_PREPARE;
+    return PCAS_OK;
+}
+
+// Appends jobs to a table in groups with a common launch key, assigning
+// block0 within each group; returns (key, first job, count, blocks) per group.
+template <class Job, class Key>
+struct Groups {
+    struct G {
+        Key key;
+        int first, count, blocks;
+    };
+    std::vector<std::pair<Key, Job>> items;
+    std::vector<G> groups;
+    void add(const Key &k, const Job &j) { items.push_back({k, j}); }
+    // Writes the jobs to dst, grouped and in submission order within a group.
+    size_t emit(Job *dst) {
+        std::stable_sort(items.begin(), items.end(),
+                         [](const auto &a, const auto &b) { return a.first < b.first; });
+        groups.clear();
+        int n = 0;
+        for (size_t i = 0; i < items.size(); ++i) {
+            if (i == 0 || !(items[i].first == items[i - 1].first))
+                groups.push_back({items[i].first, n, 0, 0});
+            G &g = groups.back();
+            Job j = items[i].second;
+            j.block0 = g.blocks;
+            g.blocks += j.nblocks;
+            g.count += 1;
+            dst[n++] = j;
+        }
+        return (size_t)n;
+    }
+};
+
+int step(pcas_server *S, int32_t *n_done) {
+    *n_done = 0;
+    // 1. admission: every pending request that fits, in arrival order
+    for (auto it = S->pending.begin(); it != S->pending.end() && (int)S->active.size() < S->max_active;) {
+        Request *r = *it;
+        if (!S->pool.alloc(r->L.total, &r->off)) {
+            ++it;
+            continue;
+        }
+        int st = admit(S, r);
+        if (st) return st;
+        S->active.push_back(r);
+        it = S->pending.erase(it);
+    }
+    if (S->active.empty()) return PCAS_OK;
+
+    // 2. this step's operations, batched
+    typedef std::pair<int, int> DK;   // (dtype, K) or (dtype, axis)
+    Groups<WarpJob, DK> warps;
+    Groups<FwdJob, DK> fwds;
+    Groups<ResJob, int> ress;
+    Groups<AdjJob, DK> adjs;
+    std::vector<Request *> locates;
+    for (Request *r : S->active) {
+        const Model &md = S->models[r->model];
+        if (r->phase == PH_LOCATE) {
+            locates.push_back(r);
+            continue;
+        }
+        if (r->phase != PH_RUN) continue;
+        const SolveOp &op = r->m.op();
+        if (op.kind == OP_EVAL) {
+            WarpJob wj;
+            wj.vd = md.vd;
+            wj.f0 = md.f0;
+            wj.mean = md.mean;
+            wj.U = md.U;
+            wj.w = WVec{};
+            for (int k = 0; k < md.K; ++k) wj.w.w[k] = op.w[k];
+            wj.f = r->ws + r->L.f;
+            wj.block0 = 0;
+            wj.nblocks = warp_blocks(nvox_of(&md.vol));
+            warps.add({md.dt, md.K}, wj);
+            fwds.add({md.dt, r->plan.axis},
+                     make_fwd_job(md.vd, r->fr, r->plan, r->ws + r->L.rays, r->ws + r->L.f,
+                                  r->ws + r->L.p, r->y, r->partials(), &r->counters()[0], r->scal()));
+        }
+        if (op.kind == OP_EVAL || op.kind == OP_RESID) {
+            ResJob rj;
+            rj.M = r->M;
+            rj.p = r->ws + r->L.p;
+            rj.y = r->y;
+            rj.fa = FitArgs{FIT_FIXED, 1.0, 0.0, r->sy, r->syy, (double)r->M};
+            if (op.fixed_ab) {
+                rj.fa.a = op.ab[0];
+                rj.fa.b = op.ab[1];
+            } else if (r->opts.fit_intensity) {
+                rj.fa.mode = FIT_REFIT;
+            }
+            rj.src = r->scal();
+            rj.partials = r->partials();
+            rj.counter = &r->counters()[3];
+            rj.out = r->scal() + 3;
+            rj.block0 = 0;
+            rj.nblocks = sums_blocks(r->M);
+            ress.add(md.dt, rj);
+        } else if (op.kind == OP_GRAD) {
+            adjs.add({md.dt, md.K},
+                     make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->ws + r->L.p, r->y,
+                                  op.ab[0], op.ab[1], md.f0, md.mean, md.U, op.w, r->partials(),
+                                  &r->counters()[1], r->scal() + 8));
+        }
+    }
+    // tables: [warp jobs][fwd jobs][res jobs][adj jobs][gather pointers][gather out]
+    const int na = (int)S->active.size();
+    char *h = S->tables_host;
+    size_t o = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t at = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_w = carve(warps.items.size() * sizeof(WarpJob));
+    warps.emit((WarpJob *)(h + o_w));
+    const size_t o_f = carve(fwds.items.size() * sizeof(FwdJob));
+    fwds.emit((FwdJob *)(h + o_f));
+    const size_t o_r = carve(ress.items.size() * sizeof(ResJob));
+    ress.emit((ResJob *)(h + o_r));
+    const size_t o_a = carve(adjs.items.size() * sizeof(AdjJob));
+    adjs.emit((AdjJob *)(h + o_a));
+    const size_t o_p = carve(na * sizeof(double *));
+    for (int i = 0; i < na; ++i) ((const double **)(h + o_p))[i] = S->active[i]->scal();
+    const size_t o_g = carve(na * GATHER * sizeof(double));
+    if (o > S->tables_bytes) return hip_fail(hipErrorInvalidValue, "serving tables overflow");
+    HIPCHK(hipMemcpyAsync(S->tables_dev, h, o_g, hipMemcpyHostToDevice, S->s));
+    char *d = S->tables_dev;
+    for (auto &g : warps.groups)
+        HIPCHK(launch_warp_pca_batch((pcas_dtype)g.key.first, g.key.second,
+                                     (const WarpJob *)(d + o_w) + g.first, g.count, g.blocks, S->s));
+    for (auto &g : fwds.groups)
+        HIPCHK(launch_drr_forward_sums_batch((pcas_dtype)g.key.first, g.key.second,
+                                             (const FwdJob *)(d + o_f) + g.first, g.count, g.blocks,
+                                             S->s));
+    for (auto &g : ress.groups)
+        HIPCHK(launch_residual_batch((pcas_dtype)g.key, (const ResJob *)(d + o_r) + g.first,
+                                     g.count, g.blocks, S->s));
+    for (auto &g : adjs.groups)
+        HIPCHK(launch_drr_adjoint_chain_batch((pcas_dtype)g.key.first, g.key.second,
+                                              (const AdjJob *)(d + o_a) + g.first, g.count,
+                                              g.blocks, S->s));
+    for (Request *r : locates) {
+        const Model &md = S->models[r->model];
+        HIPCHK(launch_locate(md.dt, md.vd, md.K, md.mean, md.U, r->w, r->opts.c0_mm,
+                             r->opts.locate_tol, r->opts.locate_max_iter, r->scal() + 24, S->s));
+    }
+    HIPCHK(launch_gather_scalars((const double *const *)(d + o_p), (double *)(d + o_g), na, GATHER,
+                                 S->s));
+    HIPCHK(hipMemcpyAsync(S->gather_host, d + o_g, na * GATHER * sizeof(double),
+                          hipMemcpyDeviceToHost, S->s));
+    HIPCHK(hipStreamSynchronize(S->s));
+
+    // 3. advance every request with its results
+    std::vector<Request *> still;
+    for (int i = 0; i < na; ++i) {
+        Request *r = S->active[i];
+        const double *sc = S->gather_host + i * GATHER;
+        const Model &md = S->models[r->model];
+        bool done = false;
+        int status = PCAS_OK;
+        if (r->phase == PH_PREPARE) {
+            r->sy = sc[16];
+            r->syy = sc[18];
+            if (!isfinite(r->sy) || !isfinite(r->syy)) {
+                status = PCAS_ENONFINITE;
+                done = true;
+            } else if (r->opts.fit_intensity) {
+                const double m = (double)r->M, det = r->syy * m - r->sy * r->sy;
+                if (!(fabs(det) > 1e-12 * r->syy * m)) {
+                    status = PCAS_ESINGULAR;
+                    done = true;
+                }
+            }
+            if (!done) {
+                const double ftol = r->opts.ftol_rel >= 0.0 ? r->opts.ftol_rel
+                                                            : (md.dt == PCAS_F32 ? 1e-8 : 0.0);
+                r->m.start(r->opts, md.K, ftol, r->w0);
+                r->phase = PH_RUN;
+            }
+        } else if (r->phase == PH_RUN) {
+            const SolveOp &op = r->m.op();
+            if (op.kind == OP_EVAL || op.kind == OP_RESID) {
+                const double J = sc[3], a = sc[4], b = sc[5];
+                if (!isfinite(a) || !isfinite(b)) {
+                    status = PCAS_ESINGULAR;
+                    done = true;
+                } else if (!isfinite(J)) {
+                    status = PCAS_ENONFINITE;
+                    done = true;
+                } else {
+                    r->m.eval_result(J, a, b);
+                }
+            } else if (op.kind == OP_GRAD) {
+                for (int k = 0; k < md.K; ++k)
+                    if (!isfinite(sc[8 + k])) {
+                        status = PCAS_ENONFINITE;
+                        done = true;
+                    }
+                if (!done) r->m.grad_result(sc + 8);
+            }
+            if (!done && r->m.done()) {
+                r->rep = r->m.report();
+                for (int k = 0; k < md.K; ++k) r->w[k] = r->m.w()[k];
+                if (r->opts.locate)
+                    r->phase = PH_LOCATE;
+                else
+                    done = true;
+            }
+            if (done && status != PCAS_OK) r->rep = r->m.report();
+        } else if (r->phase == PH_LOCATE) {
+            for (int c = 0; c < 3; ++c) r->rep.tumour_mm[c] = sc[24 + c];
+            r->rep.locate_iters = (int32_t)sc[27];
+            done = true;
+        }
+        if (done) {
+            finish_request(S, r, status);
+            ++*n_done;
+        } else {
+            still.push_back(r);
+        }
+    }
+    S->active.swap(still);
+    return PCAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcas_server_reserved_bytes(int32_t max_active) {
+    return max_active < 1 ? 0 : table_bytes(max_active);
+}
+
+int pcas_server_create(void *arena, size_t arena_bytes, int32_t max_active, void *stream,
+                       pcas_server **out) {
+    if (!out || !arena || !aligned(arena, 256) || max_active < 1 || max_active > 4096)
+        return PCAS_EINVAL;
+    const size_t tb = table_bytes(max_active);
+    if (arena_bytes < tb + 256) return PCAS_EWORKSPACE;
+    pcas_server *S = new pcas_server();
+    S->s = (hipStream_t)stream;
+    S->arena = (char *)arena;
+    S->arena_bytes = arena_bytes;
+    S->max_active = max_active;
+    S->tables_dev = S->arena;
+    S->tables_bytes = tb;
+    S->pool_base = tb;
+    S->pool.init((arena_bytes - tb) & ~(size_t)255);
+    hipError_t e = hipHostMalloc((void **)&S->tables_host, tb, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&S->gather_host, (size_t)max_active * GATHER * sizeof(double),
+                          hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (S->tables_host) (void)hipHostFree(S->tables_host);
+        delete S;
+        return hip_fail(e, "hipHostMalloc(serving tables)");
+    }
+    *out = S;
+    return PCAS_OK;
+}
+
+int pcas_server_destroy(pcas_server *S) {
+    if (!S) return PCAS_EINVAL;
+    for (Request *r : S->pending) delete r;
+    for (Request *r : S->active) delete r;
+    for (auto &kv : S->finished) delete kv.second;
+    if (S->tables_host) (void)hipHostFree(S->tables_host);
+    if (S->gather_host) (void)hipHostFree(S->gather_host);
+    delete S;
+    return PCAS_OK;
+}
+
+int pcas_server_add_model(pcas_server *S, pcas_dtype dtype, const pcas_vol *vol, int32_t K,
+                          const void *f0, const void *mean, const void *U, int32_t *model_id) {
+    if (!S || !dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K || !f0 || !U || !model_id)
+        return PCAS_EINVAL;
+    int st = check_vol(vol);
+    if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
+    Model md{dtype, *vol, make_dims(vol), K, f0, mean, U};
+    S->models.push_back(md);
+    *model_id = (int32_t)S->models.size() - 1;
+    return PCAS_OK;
+}
+
+size_t pcas_server_request_bytes(pcas_server *S, int32_t model_id, const pcas_proj *proj) {
+    if (!S || model_id < 0 || model_id >= (int)S->models.size()) return 0;
+    const Model &md = S->models[model_id];
+    if (check_proj(proj, &md.vol) != PCAS_OK) return 0;
+    return request_bytes(md, proj);
+}
+
+int pcas_server_submit(pcas_server *S, int32_t model_id, const pcas_proj *proj, const void *y,
+                       const double *w0, const pcas_opts *opts, int64_t *request_id) {
+    if (!S || model_id < 0 || model_id >= (int)S->models.size() || !y || !w0 || !request_id)
+        return PCAS_EINVAL;
+    const Model &md = S->models[model_id];
+    int st = check_proj(proj, &md.vol);
+    if (st) return st;
+    if ((st = check_opts(opts))) return st;
+    if (opts->grad_mode != 1) return PCAS_EINVAL;   // the server runs the fused back-projection
+    if (!finite_vec(w0, md.K)) return PCAS_ENONFINITE;
+    const size_t need = request_bytes(md, proj);
+    if (need > S->arena_bytes - S->pool_base) return PCAS_EWORKSPACE;   // could never be admitted
+    Request *r = new Request();
+    r->id = S->next_id++;
+    r->model = model_id;
+    r->proj = *proj;
+    r->fr = make_frame(proj);
+    r->plan = plan_drr_forward(md.dt, md.vd, r->fr, 1);
+    r->y = y;
+    r->opts = *opts;
+    for (int k = 0; k < md.K; ++k) r->w0[k] = w0[k];
+    r->L = solve_layout(md.dt, &md.vol, proj, md.K, false);
+    r->M = npix_of(proj);
+    S->pending.push_back(r);
+    *request_id = r->id;
+    return PCAS_OK;
+}
+
+int pcas_server_step(pcas_server *S, int32_t *n_completed) {
+    if (!S || !n_completed) return PCAS_EINVAL;
+    return step(S, n_completed);
+}
+
+int pcas_server_poll(pcas_server *S, int64_t request_id, double *w_out, pcas_report *report,
+                     int32_t *done) {
+    if (!S || !done) return PCAS_EINVAL;
+    auto it = S->finished.find(request_id);
+    if (it == S->finished.end()) {
+        *done = 0;
+        return PCAS_OK;
+    }
+    Request *r = it->second;
+    const int K = S->models[r->model].K;
+    if (w_out)
+        for (int k = 0; k < K; ++k) w_out[k] = r->w[k];
+    if (report) *report = r->rep;
+    const int status = r->status;
+    S->finished.erase(it);
+    delete r;
+    *done = 1;
+    return status;
+}
+
+int pcas_server_stats(pcas_server *S, int32_t *n_pending, int32_t *n_active, size_t *arena_used) {
+    if (!S) return PCAS_EINVAL;
+    if (n_pending) *n_pending = (int32_t)S->pending.size();
+    if (n_active) *n_active = (int32_t)S->active.size();
+    if (arena_used) *arena_used = S->pool.used() + S->pool_base;
+    return PCAS_OK;
+}
+
+}  // extern "C"

@@ -294,3 +294,17 @@ def small(n=(40, 36, 28), spacing=(5.0, 6.0, 7.0), det=(48, 40), pitch=(7.0, 8.0
 
 def with_angle(case: Case, angle: float) -> Case:
     return replace(case, proj=replace(case.proj, angle=float(angle)))
+
+
+def serve_small(seed: int = 40, **kw) -> Case:
+    """Serving mix, small requests: 128x128x96 FP32 at 3 x 3 x 3.33 mm, K=3,
+    512x384 detector at 0.4 mm, step 1.5 mm."""
+    return make_case("serve-128x128x96-K3-f32", (128, 128, 96), (3.0, 3.0, 10.0 / 3.0),
+                     (512, 384), (0.4, 0.4), 1.5, 3, "f32", seed, **kw)
+
+
+def serve_large(seed: int = 41, **kw) -> Case:
+    """Serving mix, large requests: 512x512x256 FP32 at 0.75 x 0.75 x 1.25 mm,
+    K=5, 1024x768 detector at 0.4 mm, step 0.375 mm."""
+    return make_case("serve-512x512x256-K5-f32", (512, 512, 256), (0.75, 0.75, 1.25),
+                     (1024, 768), (0.4, 0.4), 0.375, 5, "f32", seed, **kw)

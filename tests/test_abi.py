@@ -205,3 +205,18 @@ def test_objective_gradient_validation(L, geom):
     assert call(ws_ptr=ctypes.c_void_p(0x100010)) == EWS
     assert L.objective_gradient(0, ctypes.byref(v), ctypes.byref(p), 3, FAKE, None, FAKE, FAKE, w,
                                 1, 0, FAKE, ws, None, None) == EINVAL
+
+
+def test_server_validation(L):
+    """Argument checks that return before any HIP call."""
+    out = ctypes.c_void_p()
+    assert L.pcas_server_create(None, 1 << 20, 4, None, ctypes.byref(out)) == EINVAL
+    assert L.pcas_server_create(ctypes.c_void_p(0x100010), 1 << 20, 4, None,
+                                ctypes.byref(out)) == EINVAL          # misaligned
+    assert L.pcas_server_create(FAKE, 1 << 20, 0, None, ctypes.byref(out)) == EINVAL
+    small = L.pcas_server_reserved_bytes(4)
+    assert small > 0 and L.pcas_server_reserved_bytes(0) == 0
+    assert L.pcas_server_create(FAKE, small, 4, None, ctypes.byref(out)) == EWS
+    assert L.pcas_server_step(None, None) == EINVAL
+    assert L.pcas_server_destroy(None) == EINVAL
+    assert L.pcas_server_request_bytes(None, 0, None) == 0
