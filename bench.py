@@ -262,6 +262,129 @@ def stream_mode(case, dev, dt, args) -> int:
     return 0
 
 
+def serve_mode(args) -> int:
+    """Batched mixed-size serving: Poisson arrivals (200 requests/s) of
+    projections of two resident models -- 128x128x96 K=3 with a 512x384
+    detector and 512x512x256 K=5 with a 1024x768 detector, 0.4 mm pitch --
+    at random angles through the batching server (16 slots, admission by
+    footprint, warm starts per model); the same requests solved one after
+    another by solve_projection for comparison."""
+    import dataclasses
+
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+    from paper_1102_1712_amd import serve as SV
+    from paper_1102_1712_amd import synth
+
+    t_build = time.perf_counter()
+    cases = [synth.serve_small(progress=log), synth.serve_large(progress=log)]
+    devs = []
+    for c in cases:
+        f0, mean, U = c.arrays(np.float32)
+        devs.append({k: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+                     for k, a in (("f0", f0), ("mean", mean), ("U", U))})
+    log(f"serve: models built in {time.perf_counter() - t_build:.1f} s")
+    rng = np.random.default_rng(args.seed + 200)
+    n = args.requests
+    times = SV.poisson_times(args.rate, n, seed=args.seed + 201)
+    gen = torch.Generator(device="cuda").manual_seed(args.seed + 202)
+    arrivals = []
+    for j in range(n):
+        m = int(rng.integers(0, 2))
+        c, d = cases[m], devs[m]
+        pj = dataclasses.replace(c.proj, angle=float(rng.uniform(0.0, 2 * np.pi)))
+        # a breathing-like planted state per request
+        w_true = c.w_star * (1.0 + 0.3 * np.sin(2 * np.pi * times[j] / 4.0))
+        rays = B.ray_table(c.vol, pj, torch.float32)
+        f = B.warp_pca(c.vol, d["f0"], d["mean"], d["U"], w_true)
+        p = B.drr_forward(c.vol, pj, rays, f)
+        rms = torch.sqrt(torch.mean(p.double() ** 2))
+        y = (p.double() + 0.01 * rms * torch.randn(p.shape, generator=gen, device="cuda",
+                                                    dtype=torch.float64)).float().contiguous()
+        arrivals.append(SV.Arrival(t=float(times[j]), model=m, proj=pj, y=y, w_true=w_true))
+        del rays, f, p
+    torch.cuda.synchronize()
+    opts = {m: B.default_opts(xtol=1e-7) for m in range(2)}
+    Ks = {m: cases[m].K for m in range(2)}
+
+    def new_server():
+        srv0 = B.Server(B.Server.reserved_bytes(args.slots) + (64 << 20), max_active=args.slots)
+        for c, d in zip(cases, devs):
+            srv0.add_model(c.vol, d["f0"], d["mean"], d["U"])
+        need = max(srv0.request_bytes(m, cases[m].proj) for m in range(2))
+        srv0.close()
+        srv = B.Server(B.Server.reserved_bytes(args.slots) + args.slots * need + (1 << 20),
+                       max_active=args.slots)
+        for c, d in zip(cases, devs):
+            srv.add_model(c.vol, d["f0"], d["mean"], d["U"])
+        return srv, need
+
+    out = {"mode": "serve", "requests": n, "rate_hz": args.rate, "slots": args.slots,
+           "models": [{"workload": c.name, "volume": list(c.vol.n), "K": c.K,
+                       "detector": [c.proj.nu, c.proj.nv], "pitch_mm": c.proj.pitch_u,
+                       "step_mm": c.proj.step} for c in cases],
+           "data": "synthetic (measured images from the same forward model, 1% noise)"}
+    # warm-started serving run (the configuration), then the zero-start pair
+    runs = {}
+    for label, warm in (("served_warm", True), ("served_zero", False)):
+        srv, need = new_server()
+        out["arena_bytes"] = int(srv.arena.numel())
+        out["request_bytes_max"] = int(need)
+        SV.run(srv, arrivals[:2], opts, Ks, warm=warm)          # warm the kernels up
+        done = SV.run(srv, arrivals, opts, Ks, warm=warm)
+        srv.close()
+        runs[label] = done
+        summ = SV.summary(done)
+        for m in range(2):
+            lat = [d.latency_ms for d in done if d.model == m]
+            summ[f"model{m}_p50_ms"] = float(np.percentile(lat, 50))
+            summ[f"model{m}_p99_ms"] = float(np.percentile(lat, 99))
+        out[label] = summ
+        log(f"serve {label}: {summ}")
+    # the same requests one after another, each alone (zero start)
+    ws = {m: torch.empty(B.solve_projection_workspace(cases[m].vol, cases[m].proj, cases[m].K,
+                                                      torch.float32), dtype=torch.uint8,
+                         device="cuda") for m in range(2)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = []
+    for a in arrivals:
+        d = devs[a.model]
+        w, rep = B.solve_projection(cases[a.model].vol, a.proj, d["f0"], d["mean"], d["U"], a.y,
+                                    np.zeros(Ks[a.model]), opts[a.model], workspace=ws[a.model])
+        plain.append(w)
+    t_plain = time.perf_counter() - t0
+    zero = {dn.index: dn.w for dn in runs["served_zero"]}
+    out["plain_sequential"] = {"solves_s": n / t_plain, "total_s": t_plain}
+    out["served_zero_equals_plain_bitwise"] = bool(all(np.array_equal(zero[i], plain[i])
+                                                       for i in range(n)))
+    for label, done in runs.items():
+        for m in range(2):
+            err = [np.linalg.norm(dn.w - arrivals[dn.index].w_true) /
+                   np.linalg.norm(arrivals[dn.index].w_true) for dn in done if dn.model == m]
+            out[label][f"model{m}_w_rel_err_vs_planted_median"] = float(np.median(err))
+            out[label][f"model{m}_w_rel_err_vs_planted_max"] = float(np.max(err))
+    # small requests only: where one request leaves the GPU idle between
+    # launches, batching many pays most
+    small = [a for a in arrivals if a.model == 0]
+    srv, _ = new_server()
+    SV.run(srv, small[:2], opts, Ks, warm=False)
+    done = SV.run(srv, small, opts, Ks, warm=False)
+    srv.close()
+    t0 = time.perf_counter()
+    for a in small:
+        d = devs[0]
+        B.solve_projection(cases[0].vol, a.proj, d["f0"], d["mean"], d["U"], a.y,
+                           np.zeros(Ks[0]), opts[0], workspace=ws[0])
+    t_small = time.perf_counter() - t0
+    out["small_only"] = {"served": SV.summary(done),
+                         "plain_sequential_solves_s": len(small) / t_small}
+    log(f"serve small only: {out['small_only']}")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def adjoint_alone(case, dev, S: int) -> dict:
     """The back-projection on its own (in the solve it runs fused with the
     Jacobian chain), HIP events on the current stream, for the DRR+adjoint
@@ -299,11 +422,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events")
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "stream"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "stream", "serve"],
                     help="solve: the contract line; kernels: each hot kernel alone plus a "
                          "copy of known size (for profiler counters); stream: a warm-started "
-                         "projection sequence")
+                         "projection sequence; serve: batched mixed-size serving")
     ap.add_argument("--frames", type=int, default=600)
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=16)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -320,6 +446,8 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     B.lib()
+    if args.mode == "serve":
+        return serve_mode(args)
     case, dev, dt = build_inputs(args.workload, args.seed)
     if args.mode == "kernels":
         return kernels_mode(case, dev, dt, max(args.steps, 1))

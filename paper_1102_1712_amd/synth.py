@@ -193,10 +193,16 @@ def _rms(v: np.ndarray, nvox: int) -> float:
     return float(np.sqrt(np.sum(v * v) / nvox))
 
 
-def modes(vol: Volume, K: int, rng: np.random.Generator) -> np.ndarray:
+def modes(vol: Volume, K: int, rng: np.random.Generator, progress=None) -> np.ndarray:
     """K orthonormal (1 mm RMS) smooth vector fields, [K][3][n3][n2][n1]."""
     N = vol.nvox
-    U = np.stack([_bump_field(vol, rng) for _ in range(K)])
+    fields = []
+    for k in range(K):
+        fields.append(_bump_field(vol, rng))
+        if progress:
+            progress(f"mode {k + 1}/{K} drawn")
+    U = np.stack(fields)
+    del fields
     for k in range(K):          # modified Gram-Schmidt
         for j in range(k):
             U[k] -= (np.sum(U[k] * U[j]) / N) * U[j]
@@ -236,20 +242,31 @@ def planted_w(K: int, rng: np.random.Generator, mode_bounds, mean_bound: float,
 
 def make_case(name: str, n, spacing, det, pitch, step, K: int, dtype: str, seed: int,
               noise_level: float = 0.01, with_mean: bool = True, angle=None,
-              sad: float = 1000.0, sid: float = 1500.0, offset_u: float = 0.0) -> Case:
+              sad: float = 1000.0, sid: float = 1500.0, offset_u: float = 0.0,
+              progress=None) -> Case:
+    """progress: optional callable told each finished stage (large volumes
+    take minutes to draw)."""
     vol = centred_volume(n, spacing)
     ss = np.random.SeedSequence(seed).spawn(6)
     r_tex, r_modes, r_mean, r_w, r_noise, r_angle = (np.random.default_rng(s) for s in ss)
     f0 = phantom(vol, r_tex)
-    U = modes(vol, K, r_modes)
+    if progress:
+        progress(f"{name}: phantom drawn")
+    U = modes(vol, K, r_modes, progress)
     mean = mean_field(vol, r_mean) if with_mean else None
+    if progress:
+        progress(f"{name}: modes and mean field done")
     np_dt = np.float32 if dtype == "f32" else np.float64
     # round to the compute type once; every consumer sees the same discrete problem
     f0 = f0.astype(np_dt).astype(np.float64)
     U = U.astype(np_dt).astype(np.float64)
     if mean is not None:
         mean = mean.astype(np_dt).astype(np.float64)
-    mb = [_max_jacobian_norm(U[k], vol) for k in range(K)]
+    mb = []
+    for k in range(K):
+        mb.append(_max_jacobian_norm(U[k], vol))
+        if progress:
+            progress(f"{name}: mode {k + 1}/{K} gradient bound")
     meanb = 0.0 if mean is None else _max_jacobian_norm(mean, vol)
     w_star = planted_w(K, r_w, mb, meanb)
     theta = float(r_angle.uniform(0.0, 2.0 * np.pi)) if angle is None else float(angle)
