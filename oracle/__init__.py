@@ -71,6 +71,7 @@ def lib():
         L.orc_locate.argtypes = [VP, ctypes.c_int32, P, P, P, P, ctypes.c_double, ctypes.c_int32, P]
         L.orc_locate.restype = ctypes.c_int32
         L.orc_ray_table.argtypes = [VP, PP, P, P, P, P]
+        L.orc_siddon_forward.argtypes = [VP, PP, P, P]
         _lib = L
     return _lib
 
@@ -191,6 +192,15 @@ def locate(vol, mean, U, w, c0, tol: float = 1e-9, max_iter: int = 100):
     it = lib().orc_locate(ctypes.byref(_vol(vol)), K, _ptr(mean), _ptr(U), _ptr(_f64(w)),
                           _ptr(_f64(c0)), float(tol), int(max_iter), _ptr(out))
     return out, int(it)
+
+
+def siddon_forward(vol, proj, f) -> np.ndarray:
+    """Exact-path projection of the voxel-constant volume (Siddon's method),
+    shape [nv][nu]."""
+    p = np.empty(int(proj.nu) * int(proj.nv))
+    lib().orc_siddon_forward(ctypes.byref(_vol(vol)), ctypes.byref(_proj(proj)), _ptr(_f64(f)),
+                             _ptr(p))
+    return p.reshape(int(proj.nv), int(proj.nu))
 
 
 def ray_table(vol, proj):
