@@ -190,6 +190,17 @@ int warp_pca(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, c
 int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
                 const void *f, void *p_out, void *stream);
 
+/* ---- exact-path projection (Siddon's method; Sec. II.B simulates the
+ * digital projections with it) -------------------------------------------
+ * The volume read as constant over voxel cells [centre - s/2, centre + s/2];
+ * each pixel gets the sum over cells of (length of the source-to-pixel ray
+ * inside the cell) x (cell value).  A second operator beside drr_forward's
+ * trilinear ray march, e.g. to make measurements that the solve's own P did
+ * not produce.  Geometry and sums in double.  f: device [N]; p_out: device
+ * [nv][nu]. */
+int drr_siddon(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *f,
+               void *p_out, void *stream);
+
 /* ---- a6: back-projection bp = P^T r (Appendix, gradient of J) -----------
  * The exact transpose of drr_forward for the same ray table: every sample
  * of every ray adds dt * r * (its trilinear weight) to its eight voxels.

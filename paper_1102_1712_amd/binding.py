@@ -23,7 +23,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "invalid geometry", -3: "singular
 STOP = {0: "converged", 1: "max_iter", 2: "line_search"}
 EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_default_opts",
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
-           "warp_pca", "drr_forward", "drr_adjoint", "residual_fit_workspace_bytes",
+           "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
            "objective_gradient", "solve_projection_workspace", "solve_projection",
            "pcas_server_reserved_bytes", "pcas_server_create", "pcas_server_destroy",
@@ -108,6 +108,7 @@ def lib():
             "warp_pca": (I32, [I32, VP, I32, P, P, P, DP, P, P]),
             "drr_forward": (I32, [I32, VP, PP, P, P, P, P]),
             "drr_adjoint": (I32, [I32, VP, PP, P, P, P, P]),
+            "drr_siddon": (I32, [I32, VP, PP, P, P, P]),
             "residual_fit_workspace_bytes": (SZ, [I64]),
             "residual_fit": (I32, [I32, I64, P, P, I32, P, P, P, SZ, P]),
             "grad_w_workspace_bytes": (SZ, [I32, VP, I32]),
@@ -287,6 +288,17 @@ def drr_forward(vol, proj, rays, f, out=None, stream=None):
     _check(lib().drr_forward(_dtype_code(f), ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)),
                              _dev(rays, "rays"), _dev(f, "f"), _dev(out, "p", f.dtype),
                              _stream(stream)), "drr_forward")
+    return out
+
+
+def drr_siddon(vol, proj, f, out=None, stream=None):
+    """Exact-path (Siddon) projection of the voxel-constant volume, [nv][nu]."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((int(proj.nv), int(proj.nu)), dtype=f.dtype, device=f.device)
+    _check(lib().drr_siddon(_dtype_code(f), ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)),
+                            _dev(f, "f"), _dev(out, "out", f.dtype), _stream(stream)),
+           "drr_siddon")
     return out
 
 

@@ -130,6 +130,18 @@ int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     return PCAS_OK;
 }
 
+int drr_siddon(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *f,
+               void *p_out, void *stream) {
+    if (!dtype_ok(dtype)) return PCAS_EINVAL;
+    int st = check_vol(vol);
+    if (st) return st;
+    if ((st = check_vol_bytes(vol, dtype))) return st;
+    if ((st = check_proj(proj, vol))) return st;
+    if (!f || !p_out) return PCAS_EINVAL;
+    HIPCHK(launch_siddon(dtype, make_dims(vol), make_frame(proj), f, p_out, (hipStream_t)stream));
+    return PCAS_OK;
+}
+
 int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
                 const void *r, void *bp_out, void *stream) {
     if (!dtype_ok(dtype)) return PCAS_EINVAL;

@@ -222,6 +222,10 @@ hipError_t launch_residual(pcas_dtype dt, int64_t M, const void *p, const void *
 hipError_t launch_fit_from_sums(int64_t M, int fit, const double *sums, double *stats,
                                 hipStream_t s);
 
+// Exact-path (Siddon) projection of the voxel-constant volume f into p.
+hipError_t launch_siddon(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *f, void *p,
+                         hipStream_t s);
+
 hipError_t launch_locate(pcas_dtype dt, const VolDims &v, int K, const void *mean, const void *U,
                          const double *w, const double c0[3], double tol, int max_iter,
                          double *out, hipStream_t s);
