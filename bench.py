@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METHODS = {"paper": 0, "cg": 1, "bfgs": 2}
 METRIC = "per-projection solve latency p50/p99 ms; DRR+adjoint Gsamples/s; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 # fp32 vector peak without packed math: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
@@ -93,7 +94,12 @@ def build_inputs(workload: str, seed: int):
     from paper_1102_1712_amd import synth
 
     t0 = time.time()
-    case = synth.clinical(seed=seed) if workload == "clinical" else synth.tiny(seed=seed)
+    if workload == "clinical":
+        case = synth.clinical(seed=seed)
+    elif workload == "clinical_k5":
+        case = synth.clinical_k5()
+    else:
+        case = synth.tiny(seed=seed)
     dt = torch.float32 if case.dtype == "f32" else torch.float64
     f0, mean, U = case.arrays()
     dev = dict(f0=torch.from_numpy(f0).cuda(), mean=torch.from_numpy(mean).cuda(),
@@ -243,11 +249,12 @@ def stream_mode(case, dev, dt, args) -> int:
         B.tumour_position(case.vol, dev["mean"], dev["U"], w_true[t], case.tumour_c0, out=loc)
         truth[t] = loc.cpu().numpy()[:3]
     log(f"stream: {n} measured projections made")
-    out = {"mode": "stream", "workload": case.name, "frames": n, "fps": fps,
+    out = {"mode": "stream", "workload": case.name, "frames": n, "fps": fps, "method": args.method,
            "data": "synthetic (measured images from the same forward model, 1% noise)"}
     for init in ("predict", "previous"):
         solver = S.StreamSolver(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"],
-                                opts=B.default_opts(xtol=xtol), c0_mm=case.tumour_c0,
+                                opts=B.default_opts(xtol=xtol, method=METHODS[args.method]),
+                                c0_mm=case.tumour_c0,
                                 predictor=coeffs, init=init)
         for t in range(n):
             solver.step(angles[t], ys[t])
@@ -256,6 +263,11 @@ def stream_mode(case, dev, dt, args) -> int:
                     f"{np.median(solver.report.latencies()):.2f} ms")
         located = np.array([fr.tumour_mm for fr in solver.report.frames])
         out[init] = {**solver.report.summary(), **S.localisation_errors(located, truth)}
+        frames = solver.report.frames
+        slow = sorted(range(n), key=lambda t: -frames[t].latency_ms)[:6]
+        out[init]["slowest_frames"] = [
+            {"frame": t, "ms": frames[t].latency_ms, "iters": frames[t].iters,
+             "n_fevals": frames[t].n_fevals, "status": frames[t].status} for t in slow]
     out["predict"]["init"] = "Eq. 3 prediction (L = 2, fitted on 60 earlier frames)"
     out["previous"]["init"] = "previous frame's solution"
     print(json.dumps(out), flush=True)
@@ -305,7 +317,7 @@ def serve_mode(args) -> int:
         arrivals.append(SV.Arrival(t=float(times[j]), model=m, proj=pj, y=y, w_true=w_true))
         del rays, f, p
     torch.cuda.synchronize()
-    opts = {m: B.default_opts(xtol=1e-7) for m in range(2)}
+    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method]) for m in range(2)}
     Ks = {m: cases[m].K for m in range(2)}
 
     def new_server():
@@ -409,7 +421,8 @@ def resolution_mode(case, dev, dt, args) -> int:
     B.tumour_position(case.vol, dev["mean"], dev["U"], case.w_star, case.tumour_c0, out=loc)
     truth = loc.cpu().numpy()[:3]
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
-    opts = B.default_opts(xtol=xtol, locate=1, c0_mm=tuple(case.tumour_c0))
+    opts = B.default_opts(xtol=xtol, locate=1, c0_mm=tuple(case.tumour_c0),
+                          method=METHODS[args.method])
     rows = []
     for b in (1, 2, 4, 8, 16, 32):
         pj = dataclasses.replace(fine, nu=fine.nu // b, nv=fine.nv // b, pitch_u=fine.pitch_u * b,
@@ -437,6 +450,93 @@ def resolution_mode(case, dev, dt, args) -> int:
     print(json.dumps({"mode": "resolution", "workload": case.name,
                       "measurement": "Siddon exact path at 1024x768, 0.4 mm, 1% noise, binned",
                       "rows": rows}), flush=True)
+    return 0
+
+
+def autograd_mode(args) -> int:
+    """The differentiation form against the plain solve (clinical volume,
+    K = 5, 512x384): the same objective minimised by torch.optim.LBFGS
+    (strong-Wolfe line search) over the autograd projector -- whose backward
+    is the back-projection + Jacobian chain -- with the intensity fit done in
+    torch, and by solve_projection; p50/p99 latency per projection and the
+    agreement of the two minimisers."""
+    import torch
+
+    from paper_1102_1712_amd import autograd as AG
+    from paper_1102_1712_amd import binding as B
+
+    case, dev, dt = build_inputs("clinical_k5", args.seed)
+    y = dev["y"]
+    yd = y.double()
+    M = float(yd.numel())
+    sy, syy = float(yd.sum()), float((yd * yd).sum())
+    det = syy * M - sy * sy
+    model = AG.PCAProjector(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"])
+
+    def objective(w):
+        p = model(w).double()
+        sp, spy = p.sum(), (p * yd).sum()
+        a = (M * spy - sy * sp) / det           # Eq. A.1 (an exact minimiser: the
+        b = (syy * sp - sy * spy) / det         # envelope gradient is the fixed-(a, b) one)
+        r = p - a * yd - b
+        return (r * r).sum()
+
+    def solve_autograd():
+        w = torch.zeros(case.K, dtype=torch.float64, requires_grad=True)
+        opt = torch.optim.LBFGS([w], lr=1.0, max_iter=60, tolerance_grad=1e-10,
+                                tolerance_change=1e-12, history_size=10,
+                                line_search_fn="strong_wolfe")
+        nev = [0]
+
+        def closure():
+            opt.zero_grad()
+            J = objective(w)
+            J.backward()
+            nev[0] += 1
+            return J
+
+        opt.step(closure)
+        with torch.no_grad():
+            J = float(objective(w))
+        return w.detach().numpy().copy(), J, nev[0]
+
+    xtol = 1e-7 if case.dtype == "f32" else 1e-10
+    ws = torch.empty(B.solve_projection_workspace(case.vol, case.proj, case.K, dt),
+                     dtype=torch.uint8, device="cuda")
+
+    def plain(method):
+        opts = B.default_opts(xtol=xtol, method=method)
+
+        def solve_plain():
+            w, rep = B.solve_projection(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"], y,
+                                        np.zeros(case.K), opts, workspace=ws)
+            return w, rep["J"], rep["n_fevals"] + rep["n_grads"]
+        return solve_plain
+
+    out = {"mode": "autograd", "workload": case.name, "K": case.K,
+           "autograd_optimizer": "torch.optim.LBFGS, strong Wolfe, history 10"}
+    for label, fn in (("plain", plain(1)), ("plain_bfgs", plain(2)), ("autograd", solve_autograd)):
+        fn()
+        ts = []
+        for _ in range(max(5, args.steps // 5)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            w, J, nev = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        out[label] = {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)),
+                      "J": J, "evaluations": nev, "w": list(map(float, w)),
+                      "w_rel_err_vs_planted": float(np.linalg.norm(w - case.w_star) /
+                                                    np.linalg.norm(case.w_star))}
+        log(f"autograd mode {label}: {out[label]}")
+    wa, wp = np.array(out["autograd"]["w"]), np.array(out["plain"]["w"])
+    out["w_rel_diff"] = float(np.linalg.norm(wa - wp) / np.linalg.norm(wp))
+    out["J_rel_diff"] = float(abs(out["autograd"]["J"] - out["plain"]["J"]) / out["plain"]["J"])
+    wq = np.array(out["plain_bfgs"]["w"])
+    out["bfgs_w_rel_diff"] = float(np.linalg.norm(wa - wq) / np.linalg.norm(wq))
+    out["bfgs_J_rel_diff"] = float(abs(out["autograd"]["J"] - out["plain_bfgs"]["J"]) /
+                                   out["plain_bfgs"]["J"])
+    print(json.dumps(out), flush=True)
     return 0
 
 
@@ -478,11 +578,14 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events")
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "kernels", "stream", "serve", "resolution"],
+                    choices=["solve", "kernels", "stream", "serve", "resolution", "autograd"],
                     help="solve: the contract line; kernels: each hot kernel alone plus a "
                          "copy of known size (for profiler counters); stream: a warm-started "
                          "projection sequence; serve: batched mixed-size serving; "
-                         "resolution: detector-binning sweep on exact-path data")
+                         "resolution: detector-binning sweep on exact-path data; autograd: "
+                         "the differentiation form against the plain solve")
+    ap.add_argument("--method", default="cg", choices=list(METHODS),
+                    help="solver: PR+ CG (the configured one), BFGS, or the Appendix algorithm")
     ap.add_argument("--frames", type=int, default=600)
     ap.add_argument("--requests", type=int, default=32)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -505,6 +608,8 @@ def main() -> int:
     B.lib()
     if args.mode == "serve":
         return serve_mode(args)
+    if args.mode == "autograd":
+        return autograd_mode(args)
     case, dev, dt = build_inputs(args.workload, args.seed)
     if args.mode == "kernels":
         return kernels_mode(case, dev, dt, max(args.steps, 1))
@@ -517,6 +622,7 @@ def main() -> int:
                      dtype=torch.uint8, device="cuda")
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
     base = dict(locate=1, c0_mm=tuple(case.tumour_c0), xtol=xtol)
+    base["method"] = METHODS[args.method]
     opts_warm = B.default_opts(**base)
     opts_timed = B.default_opts(profile=0 if args.no_profile else 1, **base)
     w0 = np.zeros(case.K)
@@ -611,6 +717,26 @@ def main() -> int:
            "w_rel_diff_vs_default_route": float(np.linalg.norm(w_alt - w) / np.linalg.norm(w))}
     log(f"projected-gradient route: p50 {alt['p50_ms']:.3f} ms")
 
+    # the quasi-Newton solver on the same problem (same line search, same
+    # stops), beside the configured CG: latency and agreement of the minimisers
+    qn = None
+    if args.method == "cg":
+        opts_qn = B.default_opts(**{**base, "method": 2})
+        step(opts_qn)
+        qn_t = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            w_qn, rep_qn = step(opts_qn)
+            qn_t.append(time.perf_counter() - t0)
+        qn_ms = np.array(qn_t) * 1e3
+        qn = {"method": "bfgs", "steps": len(qn_t), "p50_ms": float(np.percentile(qn_ms, 50)),
+              "p99_ms": float(np.percentile(qn_ms, 99)), "solves_s": float(1e3 / np.mean(qn_ms)),
+              "iters": rep_qn["iters"], "n_fevals": rep_qn["n_fevals"],
+              "n_grads": rep_qn["n_grads"], "status": rep_qn["status"],
+              "w_rel_diff_vs_cg": float(np.linalg.norm(w_qn - w) / np.linalg.norm(w)),
+              "J_rel_diff_vs_cg": float((rep_qn["J"] - rep["J"]) / rep["J"])}
+        log(f"quasi-Newton: p50 {qn['p50_ms']:.3f} ms, {qn['n_fevals']} evaluations")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host cores")
@@ -638,7 +764,7 @@ def main() -> int:
         "config": {"workload": case.name, "volume": list(case.vol.n),
                    "spacing_mm": list(case.vol.spacing),
                    "detector": [case.proj.nu, case.proj.nv], "pitch_mm": case.proj.pitch_u,
-                   "step_mm": case.proj.step, "K": K, "method": "cg", "max_iter": 30,
+                   "step_mm": case.proj.step, "K": K, "method": args.method, "max_iter": 30,
                    "samples_per_drr": S, "angle_rad": case.proj.angle},
         "solve": {"iters": rep["iters"], "n_fevals": rep["n_fevals"], "n_grads": rep["n_grads"],
                   "status": rep["status"], "w_rel_err_vs_planted": werr,
@@ -649,6 +775,7 @@ def main() -> int:
         "adjoint_effective_hbm_frac": (adj.get("effective_GBs", 0) / HBM_PEAK_GBS) if adj else None,
         "kernels": kernel_stats,
         "projected_gradient_route": alt,
+        "quasi_newton": qn,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "0.1-0.3 s per projection on a Tesla C1060 (different sizes; context only)",

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 2
+#define PCAS_ABI_VERSION 3
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -88,16 +88,18 @@ typedef struct {
 } pcas_proj;
 
 typedef struct {
-    int32_t method;        /* 0: Appendix algorithm (Eq. A.1 + Eq. A.2 + Armijo); 1: PR+ CG */
+    int32_t method;        /* 0: Appendix algorithm (Eq. A.1 + Eq. A.2 + Armijo); 1: PR+ CG;
+                              2: BFGS (dense K x K inverse-Hessian estimate); 1 and 2 work on
+                              the reduced objective min_{a,b} J and share one line search */
     int32_t max_iter;      /* accepted iterations */
     int32_t fit_intensity; /* 1: (a, b) from Eq. A.1; 0: a = 1, b = 0 */
-    int32_t max_backtracks;/* line-search trials per iteration (CG) */
+    int32_t max_backtracks;/* line-search trials per iteration (methods 1, 2) */
     double mu0;            /* first step length (in units of w) */
     double alpha, beta;    /* Armijo sufficient-decrease and shrink factors */
     double mu_min;         /* method 0: stop once the step falls below it */
-    double gtol_rel;       /* method 1: stop when ||g|| <= gtol_rel ||g0|| */
-    double beta_lo;        /* method 1: lower safeguard of the interpolated shrink */
-    double xtol;           /* method 1: a trial step shorter than xtol fails the search */
+    double gtol_rel;       /* methods 1, 2: stop when ||g|| <= gtol_rel ||g0|| */
+    double beta_lo;        /* methods 1, 2: lower safeguard of the interpolated shrink */
+    double xtol;           /* methods 1, 2: a trial step shorter than xtol fails the search */
     int32_t locate;        /* 1: also run tumour_position at c0_mm after the solve */
     int32_t locate_max_iter;
     double locate_tol;     /* mm */
@@ -111,9 +113,14 @@ typedef struct {
                                  so P^T r never goes to device memory
                               0: project the K Jacobian volumes J_k = U_k^T (df/dx) and take
                                  g_k = 2 <r, P J_k> (gathers only, no back-projection) */
-    double ftol_rel;       /* method 1: a rejected trial with |J_t - J| <= ftol_rel J ends the
-                              solve as converged (the change is below the objective's rounding
-                              noise); < 0 selects 1e-8 for PCAS_F32 and 0 for PCAS_F64 */
+    double ftol_rel;       /* methods 1, 2: a rejected trial with |J_t - J| <= ftol_rel J ends
+                              the solve as converged (the change is below the objective's
+                              rounding noise); < 0 selects 1e-8 for PCAS_F32 and 1e-14 for
+                              PCAS_F64 */
+    double ls_extrap;      /* methods 1, 2: when the first trial of a line search passes Armijo
+                              and the quadratic through J(0), J'(0), J(t) has its minimiser
+                              t_q > 2t, one more trial at min(t_q, ls_extrap t) follows and the
+                              lower point is kept; 0 turns this off (>= 0, finite) */
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
@@ -148,7 +155,8 @@ const char *pcas_last_error(void);
 /* Defaults: method 1 (CG), 30 iterations, fit on, 12 backtracks, mu0 = 1,
  * alpha = 0.1, beta = 0.5 (the Appendix's Armijo constants), mu_min = 0.01,
  * gtol_rel = 1e-9, beta_lo = 0.1, xtol = 1e-10, no localisation, 100
- * localisation iterations, 1e-9 mm tolerance, grad_mode 1 (back-projection). */
+ * localisation iterations, 1e-9 mm tolerance, grad_mode 1 (back-projection),
+ * ftol_rel by dtype, ls_extrap = 10. */
 void pcas_default_opts(pcas_opts *opts);
 /* Appendix algorithm: method 0, 10 iterations, mu0 = 0.2, alpha = 0.1,
  * beta = 0.5, stop below mu_min = 0.01 (the paper's 2 and 0.1 rescaled from

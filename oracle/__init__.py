@@ -16,6 +16,9 @@ the Jacobian of Eq. A.8, the tumour-position inversion) are plain C in
 * ``solve_cg`` -- the nonlinear conjugate-gradient variant (not in the paper):
   Polak-Ribiere+ directions on the reduced objective min_{a,b} J, with the
   same Armijo rule.
+* ``solve_bfgs`` -- a quasi-Newton variant (not in the paper): BFGS updates of
+  a dense K x K inverse-Hessian estimate on the same reduced objective, with
+  the same Armijo rule and the unit quasi-Newton step tried first.
 
 All arithmetic is float64.
 """
@@ -251,16 +254,18 @@ STOP_CONVERGED, STOP_MAXITER, STOP_LINESEARCH = 0, 1, 2
 @dataclass
 class SolveOptions:
     """method 0: the Appendix algorithm (Eq. A.1 alternated with Eq. A.2 and
-    Armijo); method 1: PR+ nonlinear CG on the reduced objective.
+    Armijo); method 1: PR+ nonlinear CG on the reduced objective; method 2:
+    BFGS on the reduced objective.
 
     The Appendix states mu0 = 2, alpha = 0.1, beta = 0.5, a stop when the step
     drops below 0.1, and at most 10 iterations, for coefficients scaled to a
     standard deviation of 10.  Our modes carry unit-variance coefficients, so
     the paper-mode step sizes are scaled by 1/10 (mu0 = 0.2, mu_min = 0.01).
 
-    In CG mode a failed Armijo trial shrinks the step to the minimiser of the
-    quadratic through phi(0), phi'(0) and phi(t), kept within
-    [beta_lo * t, beta * t]; mu_min is unused there."""
+    In CG and BFGS modes the line search (_line_search) shrinks a failed
+    Armijo trial to the minimiser of the quadratic through phi(0), phi'(0)
+    and phi(t), kept within [beta_lo * t, beta * t], and may lengthen an
+    accepted first trial once (ls_extrap); mu_min is unused there."""
     method: int = 1
     max_iter: int = 30
     fit_intensity: bool = True
@@ -272,7 +277,8 @@ class SolveOptions:
     gtol_rel: float = 1e-9
     beta_lo: float = 0.1
     xtol: float = 1e-10
-    ftol_rel: float = 0.0
+    ftol_rel: float = 1e-14
+    ls_extrap: float = 10.0
 
     @staticmethod
     def paper() -> "SolveOptions":
@@ -374,16 +380,58 @@ def solve_paper(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     return w, rep
 
 
+def _line_search(prob, o, w, phi, d, gd, t):
+    """Armijo search along d from w (phi = J(w), gd = g.d < 0), first trial
+    step t, shared by solve_cg and solve_bfgs.
+
+    A trial with phi_t <= phi + alpha t gd is accepted.  A rejected one moves
+    t to the minimiser of the quadratic through phi(0), phi'(0) = gd and
+    phi(t), kept within [beta_lo t, beta t]; a rejected trial whose change is
+    within ftol_rel of phi ends the search at the noise floor, and a step
+    shorter than xtol (in units of w) or max_backtracks trials fail it.
+
+    When the first trial is accepted and that quadratic puts its minimiser
+    beyond twice the trial step, one more trial is made there (capped at
+    ls_extrap times the step; ls_extrap = 0 turns this off) and the lower of
+    the two points is kept: backtracking can only shorten a step, so a first
+    guess that is too short would otherwise stay short.
+
+    Returns (status, t, w_t, phi_t, a_t, b_t, r_t, n_evals) with status
+    "ok", "noise" or "fail"."""
+    dn = float(np.linalg.norm(d))
+    n = 0
+    for trial in range(o.max_backtracks):
+        if t * dn < o.xtol:                            # step too short to matter
+            break
+        w_t = w + t * d
+        phi_t, a_t, b_t, r_t = prob.objective(w_t)
+        n += 1
+        if phi_t <= phi + o.alpha * t * gd:
+            if trial == 0 and o.ls_extrap > 0.0:
+                t_q = -gd * t * t / (2.0 * (phi_t - phi - gd * t))
+                if t_q > 2.0 * t:
+                    t_x = min(t_q, o.ls_extrap * t)
+                    w_x = w + t_x * d
+                    phi_x, a_x, b_x, r_x = prob.objective(w_x)
+                    n += 1
+                    if phi_x < phi_t:
+                        return "ok", t_x, w_x, phi_x, a_x, b_x, r_x, n
+            return "ok", t, w_t, phi_t, a_t, b_t, r_t, n
+        if abs(phi_t - phi) <= o.ftol_rel * phi:       # change below rounding noise
+            return "noise", t, None, None, None, None, None, n
+        t_q = -gd * t * t / (2.0 * (phi_t - phi - gd * t))
+        t = min(max(t_q, o.beta_lo * t), o.beta * t)
+    return "fail", t, None, None, None, None, None, n
+
+
 def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     """PR+ nonlinear CG on phi(w) = min_{a,b} J(w, a, b).
 
     phi's gradient is dJ/dw at the fitted (a, b) (the fit is an exact
-    minimiser, Eq. A.1).  Armijo backtracking on phi with the paper's alpha;
-    the first trial step is mu0/||d|| on the first iteration and
-    t_prev (g_prev.d_prev) / (g.d) afterwards; a rejected trial moves to the
-    safeguarded quadratic-interpolation step, and a step shorter than xtol
-    (in units of w) counts as a failed search.  A failed search restarts
-    along -g once; a second failure ends the solve."""
+    minimiser, Eq. A.1).  The first trial step is mu0/||d|| on the first
+    iteration and t_prev (g_prev.d_prev) / (g.d) afterwards, searched with
+    _line_search.  A failed search restarts along -g once; a second failure
+    ends the solve."""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
     rep = SolveReport()
@@ -410,33 +458,19 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             gd = -gn * gn
             restart = True
         t = o.mu0 / float(np.linalg.norm(d)) if first else t_prev * gd_prev / gd
-        accepted = at_noise = False
-        dn = float(np.linalg.norm(d))
-        for _ in range(o.max_backtracks):
-            if t * dn < o.xtol:                        # step too short to matter
-                break
-            w_try = w + t * d
-            phi_t, a_t, b_t, r_t = prob.objective(w_try)
-            rep.n_fevals += 1
-            if phi_t <= phi + o.alpha * t * gd:
-                accepted = True
-                break
-            if abs(phi_t - phi) <= o.ftol_rel * phi:    # change below rounding noise
-                at_noise = True
-                break
-            t_q = -gd * t * t / (2.0 * (phi_t - phi - gd * t))
-            t = min(max(t_q, o.beta_lo * t), o.beta * t)
-        if at_noise:
+        st, t, w_t, phi_t, a_t, b_t, r_t, n = _line_search(prob, o, w, phi, d, gd, t)
+        rep.n_fevals += n
+        if st == "noise":
             rep.status = STOP_CONVERGED
             break
-        if not accepted:
+        if st == "fail":
             if restart:
                 rep.status = STOP_LINESEARCH
                 break
             d = -g
             restart = True
             continue
-        w, phi, a, b, r = w_try, phi_t, a_t, b_t, r_t
+        w, phi, a, b, r = w_t, phi_t, a_t, b_t, r_t
         g_new = prob.gradient(w, r)
         rep.n_grads += 1
         beta_pr = max(0.0, float(g_new @ (g_new - g)) / float(g @ g))
@@ -452,9 +486,89 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     return w, rep
 
 
+def bfgs_update(H, s, y):
+    """Inverse-Hessian BFGS update (Nocedal and Wright, Numerical
+    Optimization, Eq. 6.17): H+ = (I - rho s y^T) H (I - rho y s^T) +
+    rho s s^T with rho = 1 / (y.s).  H+ satisfies the secant equation
+    H+ y = s and stays symmetric positive definite when y.s > 0."""
+    n = s.size
+    rho = 1.0 / float(y @ s)
+    L = np.eye(n) - rho * np.outer(s, y)
+    return L @ H @ L.T + rho * np.outer(s, s)
+
+
+def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
+    """BFGS on phi(w) = min_{a,b} J(w, a, b), the reduced objective of
+    solve_cg.
+
+    The first iteration, and any after a reset, steps along -g with trial
+    length mu0/||g||; the others along d = -H g with unit trial step.  Both
+    are searched with _line_search.  After the first accepted step H starts
+    as (y.s / y.y) I (Nocedal and Wright, Eq. 6.20) before its first update.
+    An update is skipped when y.s <= 1e-12 ||s|| ||y||.  A failed search
+    with an estimate resets it and retries along -g; a failed search along
+    -g ends the solve."""
+    o = opts or SolveOptions()
+    w = _f64(w0).copy()
+    K = w.size
+    rep = SolveReport()
+    phi, a, b, r = prob.objective(w)
+    rep.n_fevals += 1
+    g = prob.gradient(w, r)
+    rep.n_grads += 1
+    rep.J0 = phi
+    rep.J_trace.append(phi)
+    g0 = float(np.linalg.norm(g))
+    H = None
+    it = 0
+    rep.status = STOP_MAXITER
+    while it < o.max_iter:
+        gn = float(np.linalg.norm(g))
+        if gn <= o.gtol_rel * g0 or phi == 0.0:
+            rep.status = STOP_CONVERGED
+            break
+        if H is not None:
+            d = -(H @ g)
+            gd = float(g @ d)
+            t = 1.0
+            if gd >= 0.0:                                  # estimate lost definiteness
+                H = None
+        if H is None:
+            d = -g
+            gd = -gn * gn
+            t = o.mu0 / gn
+        st, t, w_t, phi_t, a_t, b_t, r_t, n = _line_search(prob, o, w, phi, d, gd, t)
+        rep.n_fevals += n
+        if st == "noise":
+            rep.status = STOP_CONVERGED
+            break
+        if st == "fail":
+            if H is None:
+                rep.status = STOP_LINESEARCH
+                break
+            H = None
+            continue
+        g_new = prob.gradient(w_t, r_t)
+        rep.n_grads += 1
+        s_k = w_t - w
+        y_k = g_new - g
+        sy = float(s_k @ y_k)
+        if sy > 1e-12 * float(np.linalg.norm(s_k)) * float(np.linalg.norm(y_k)):
+            if H is None:
+                H = (sy / float(y_k @ y_k)) * np.eye(K)
+            H = bfgs_update(H, s_k, y_k)
+        w, phi, a, b, g = w_t, phi_t, a_t, b_t, g_new
+        it += 1
+        rep.J_trace.append(phi)
+    rep.iters = it
+    rep.J, rep.a, rep.b = phi, a, b
+    rep.gnorm = float(np.linalg.norm(g))
+    return w, rep
+
+
 def solve(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     o = opts or SolveOptions()
-    return solve_paper(prob, w0, o) if o.method == 0 else solve_cg(prob, w0, o)
+    return {0: solve_paper, 1: solve_cg, 2: solve_bfgs}[o.method](prob, w0, o)
 
 
 def measured_projection(vol, proj, f0, mean, U, w_star, xi, noise_level):

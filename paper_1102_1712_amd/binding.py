@@ -62,7 +62,7 @@ class Opts(ctypes.Structure):
                 ("locate", ctypes.c_int32), ("locate_max_iter", ctypes.c_int32),
                 ("locate_tol", ctypes.c_double), ("c0_mm", ctypes.c_double * 3),
                 ("profile", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
-                ("ftol_rel", ctypes.c_double)]
+                ("ftol_rel", ctypes.c_double), ("ls_extrap", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):

@@ -54,6 +54,7 @@ void pcas_default_opts(pcas_opts *o) {
     o->locate_tol = 1e-9;
     o->ftol_rel = -1.0;
     o->grad_mode = 1;
+    o->ls_extrap = 10.0;
 }
 
 void pcas_paper_opts(pcas_opts *o) {
@@ -330,10 +331,13 @@ struct Solver {
 
     // J = ||p - a y - b||^2 for the projection in the p buffer, summed
     // directly over the residual; (a, b) refitted by Eq. A.1 unless fixed.
-    int residual(const double *ab_fixed, double *J, double *a, double *b) {
+    // Projection buffer of a line-search slot (0 or 1).
+    char *proj_slot(int slot) const { return ws + (slot ? L.p2 : L.p); }
+
+    int residual(const double *ab_fixed, int slot, double *J, double *a, double *b) {
         const FitArgs fa = fit_args(ab_fixed);
         HIPCHK(timed(PCAS_K_RESIDUAL, [&] {
-            return launch_residual(dt, M, ws + L.p, y, fa, scal(), nullptr,
+            return launch_residual(dt, M, proj_slot(slot), y, fa, scal(), nullptr,
                                    (double *)(ws + L.partials), &counters()[3], scal() + 3, s);
         }));
         double out[3];
@@ -347,34 +351,35 @@ struct Solver {
         return PCAS_OK;
     }
 
-    // Warp + projection at w, then the residual pass (one read-back).
-    int evaluate(const double *w, const double *ab_fixed, double *J, double *a, double *b) {
+    // Warp + projection at w into a slot, then the residual pass (one read-back).
+    int evaluate(const double *w, const double *ab_fixed, int slot, double *J, double *a,
+                 double *b) {
         HIPCHK(timed(PCAS_K_WARP, [&] {
             return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s);
         }));
         HIPCHK(timed(PCAS_K_DRR, [&] {
-            return launch_drr_forward(dt, vd, fr, fplan, ws + L.rays, ws + L.f, ws + L.p, y,
+            return launch_drr_forward(dt, vd, fr, fplan, ws + L.rays, ws + L.f, proj_slot(slot), y,
                                       (double *)(ws + L.partials), &counters()[0], scal(), s);
         }));
         ++n_fevals;
-        return residual(ab_fixed, J, a, b);
+        return residual(ab_fixed, slot, J, a, b);
     }
 
-    // Gradient at the w whose projection is in the p buffer, at (a, b).
-    int gradient(const double *w, double a, double b, double *g) {
+    // Gradient at the w whose projection is in the slot, at (a, b).
+    int gradient(const double *w, double a, double b, int slot, double *g) {
         if (grad_mode == 0) {
             HIPCHK(timed(PCAS_K_JACOBIAN, [&] {
                 return launch_jacobian(dt, vd, K, f0, mean, U, w, ws + L.vol2, s);
             }));
             HIPCHK(timed(PCAS_K_DRR_DOT, [&] {
                 return launch_drr_forward_dot(dt, vd, fr, fplan_k, K, ws + L.rays, ws + L.vol2,
-                                              ws + L.p, y, a, b, (double *)(ws + L.partials),
+                                              proj_slot(slot), y, a, b, (double *)(ws + L.partials),
                                               &counters()[1], scal() + 8, s);
             }));
         } else {
             // back-projection and Jacobian chain in one pass (bp stays on chip)
             HIPCHK(timed(PCAS_K_ADJOINT, [&] {
-                return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, ws + L.p, y, a, b, f0,
+                return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, proj_slot(slot), y, a, b, f0,
                                                 mean, U, w, (double *)(ws + L.partials),
                                                 &counters()[1], scal() + 8, s);
             }));
@@ -438,16 +443,17 @@ int drive(Solver &S, SolveMachine &m) {
         int st;
         switch (op.kind) {
         case OP_EVAL:
-            if ((st = S.evaluate(op.w, op.fixed_ab ? op.ab : nullptr, &J, &a, &b))) return st;
+            if ((st = S.evaluate(op.w, op.fixed_ab ? op.ab : nullptr, op.slot, &J, &a, &b)))
+                return st;
             m.eval_result(J, a, b);
             break;
         case OP_RESID:
-            if ((st = S.residual(nullptr, &J, &a, &b))) return st;
+            if ((st = S.residual(nullptr, op.slot, &J, &a, &b))) return st;
             m.eval_result(J, a, b);
             break;
         case OP_GRAD: {
             double g[PCAS_MAX_K];
-            if ((st = S.gradient(op.w, op.ab[0], op.ab[1], g))) return st;
+            if ((st = S.gradient(op.w, op.ab[0], op.ab[1], op.slot, g))) return st;
             m.grad_result(g);
             break;
         }
@@ -484,8 +490,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
         return st;
 
     SolveMachine m;
-    const double ftol = opts->ftol_rel >= 0.0 ? opts->ftol_rel : (dtype == PCAS_F32 ? 1e-8 : 0.0);
-    m.start(*opts, K, ftol, w0);
+    m.start(*opts, K, noise_floor(dtype, *opts), w0);
     st = drive(S, m);
     *report = m.report();
     if (st) return st;
@@ -529,8 +534,8 @@ extern "C" int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const p
                         workspace, stream)))
         return st;
     double J, a, b;
-    if ((st = S.evaluate(w, nullptr, &J, &a, &b))) return st;
-    if ((st = S.gradient(w, a, b, out + 3))) return st;
+    if ((st = S.evaluate(w, nullptr, 0, &J, &a, &b))) return st;
+    if ((st = S.gradient(w, a, b, 0, out + 3))) return st;
     out[0] = J;
     out[1] = a;
     out[2] = b;

@@ -148,7 +148,7 @@ inline int readback(double *host, const double *dev, int count, hipStream_t s) {
 // ---- workspace layouts ---------------------------------------------------
 
 struct SolveWs {
-    size_t rays, f, p, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
+    size_t rays, f, p, p2, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
 };
 
 inline int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
@@ -170,6 +170,7 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
     L.rays = off; off += align256(M * rec_size(dt));
     L.f = off; off += align256(N * es);
     L.p = off; off += align256(M * es);
+    L.p2 = off; off += align256(M * es);   // second projection slot of the line search
     L.vol2 = off; off += with_vol2 ? align256((size_t)(K > 1 ? K : 1) * N * es) : 0;
     L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
     L.counters = off; off += 256;
@@ -180,7 +181,7 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
 
 inline int check_opts(const pcas_opts *o) {
     if (!o) return PCAS_EINVAL;
-    if (o->method != 0 && o->method != 1) return PCAS_EINVAL;
+    if (o->method < 0 || o->method > 2) return PCAS_EINVAL;
     if (o->grad_mode != 0 && o->grad_mode != 1) return PCAS_EINVAL;
     if (o->max_iter < 0 || o->max_backtracks < 1 || o->locate_max_iter < 1) return PCAS_EINVAL;
     if (!(o->mu0 > 0.0) || !(o->alpha > 0.0 && o->alpha < 1.0) || !(o->beta > 0.0 && o->beta < 1.0))
@@ -188,8 +189,15 @@ inline int check_opts(const pcas_opts *o) {
     if (!(o->mu_min >= 0.0) || !(o->gtol_rel >= 0.0) || !(o->xtol >= 0.0) || !(o->locate_tol > 0.0))
         return PCAS_EINVAL;
     if (!(o->beta_lo > 0.0 && o->beta_lo <= o->beta)) return PCAS_EINVAL;
+    if (!(o->ls_extrap >= 0.0) || !isfinite(o->ls_extrap) || isnan(o->ftol_rel)) return PCAS_EINVAL;
     if (o->locate && !finite_vec(o->c0_mm, 3)) return PCAS_EINVAL;
     return PCAS_OK;
+}
+
+// Relative change of J below which a rejected line-search trial counts as
+// rounding noise (opts.ftol_rel, or by dtype when negative).
+inline double noise_floor(pcas_dtype dt, const pcas_opts &o) {
+    return o.ftol_rel >= 0.0 ? o.ftol_rel : (dt == PCAS_F32 ? 1e-8 : 1e-14);
 }
 
 }  // namespace host

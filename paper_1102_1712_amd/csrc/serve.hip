@@ -63,6 +63,7 @@ struct Request {
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
     double *partials() const { return (double *)(ws + L.partials); }
+    char *proj_slot(int slot) const { return ws + (slot ? L.p2 : L.p); }
 };
 
 // First-fit allocation over [0, size) in 256-byte units, coalescing on free.
@@ -240,12 +241,13 @@ int step(pcas_server *S, int32_t *n_done) {
             warps.add({md.dt, md.K}, wj);
             fwds.add({md.dt, r->plan.axis},
                      make_fwd_job(md.vd, r->fr, r->plan, r->ws + r->L.rays, r->ws + r->L.f,
-                                  r->ws + r->L.p, r->y, r->partials(), &r->counters()[0], r->scal()));
+                                  r->proj_slot(op.slot), r->y, r->partials(), &r->counters()[0],
+                                  r->scal()));
         }
         if (op.kind == OP_EVAL || op.kind == OP_RESID) {
             ResJob rj;
             rj.M = r->M;
-            rj.p = r->ws + r->L.p;
+            rj.p = r->proj_slot(op.slot);
             rj.y = r->y;
             rj.fa = FitArgs{FIT_FIXED, 1.0, 0.0, r->sy, r->syy, (double)r->M};
             if (op.fixed_ab) {
@@ -263,7 +265,7 @@ int step(pcas_server *S, int32_t *n_done) {
             ress.add(md.dt, rj);
         } else if (op.kind == OP_GRAD) {
             adjs.add({md.dt, md.K},
-                     make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->ws + r->L.p, r->y,
+                     make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot), r->y,
                                   op.ab[0], op.ab[1], md.f0, md.mean, md.U, op.w, r->partials(),
                                   &r->counters()[1], r->scal() + 8));
         }
@@ -338,9 +340,7 @@ int step(pcas_server *S, int32_t *n_done) {
                 }
             }
             if (!done) {
-                const double ftol = r->opts.ftol_rel >= 0.0 ? r->opts.ftol_rel
-                                                            : (md.dt == PCAS_F32 ? 1e-8 : 0.0);
-                r->m.start(r->opts, md.K, ftol, r->w0);
+                r->m.start(r->opts, md.K, noise_floor(md.dt, r->opts), r->w0);
                 r->phase = PH_RUN;
             }
         } else if (r->phase == PH_RUN) {

@@ -17,11 +17,16 @@ namespace pcas {
 
 enum OpKind { OP_EVAL = 0, OP_RESID = 1, OP_GRAD = 2, OP_DONE = 3 };
 
+// Two projection buffers ("slots") per solve: OP_EVAL writes its projection
+// to op.slot, OP_RESID and OP_GRAD read the projection in op.slot.  A line
+// search that tries one more point after an accepted one keeps both, so the
+// gradient can be taken at whichever of the two it accepts.
 struct SolveOp {
     OpKind kind = OP_DONE;
-    double w[PCAS_MAX_K] = {0};   // OP_EVAL: the point; OP_GRAD: the point (last evaluated)
+    double w[PCAS_MAX_K] = {0};   // OP_EVAL: the point; OP_GRAD: the point of the slot
     bool fixed_ab = false;        // OP_EVAL / OP_RESID: (a, b) = ab instead of Eq. A.1
     double ab[2] = {1.0, 0.0};    // OP_EVAL fixed: (a, b); OP_GRAD: (a, b) of the residual
+    int slot = 0;                 // projection buffer, 0 or 1
 };
 
 class SolveMachine {
@@ -37,7 +42,7 @@ public:
         for (int k = 0; k < K; ++k) w_[k] = w0[k];
         memset(&rep_, 0, sizeof(rep_));
         rep_.locate_iters = -1;
-        pc_ = o.method == 0 ? P_START : CG_START;
+        pc_ = o.method == 0 ? P_START : (o.method == 1 ? CG_START : QN_START);
         run();
     }
 
@@ -64,8 +69,10 @@ public:
 
 private:
     enum Pc {
-        CG_START, CG_AFTER_EVAL0, CG_AFTER_GRAD0, CG_LOOP, CG_LS, CG_AFTER_LS_EVAL, CG_LS_END,
-        CG_AFTER_GRAD, CG_FINISH,
+        LS_TRIAL, LS_AFTER_TRIAL, LS_AFTER_EXTRAP,
+        CG_START, CG_AFTER_EVAL0, CG_AFTER_GRAD0, CG_LOOP, CG_LS_END, CG_AFTER_GRAD,
+        QN_START, QN_AFTER_EVAL0, QN_AFTER_GRAD0, QN_LOOP, QN_LS_END, QN_AFTER_GRAD,
+        SOLVE_FINISH,
         P_START, P_AFTER_EVAL0, P_LOOP, P_AFTER_RESID, P_GRAD, P_AFTER_GRAD, P_LS, P_AFTER_LS,
         P_END, P_AFTER_FINAL,
         FINISHED
@@ -77,25 +84,43 @@ private:
         return s;
     }
 
-    void want_eval(const double *w, bool fixed, double a, double b, Pc next) {
+    void want_eval(const double *w, bool fixed, double a, double b, Pc next, int slot = 0) {
         op_.kind = OP_EVAL;
         for (int k = 0; k < K_; ++k) op_.w[k] = w[k];
         op_.fixed_ab = fixed;
         op_.ab[0] = a;
         op_.ab[1] = b;
+        op_.slot = slot;
         pc_ = next;
     }
     void want_resid(Pc next) {
         op_.kind = OP_RESID;
         op_.fixed_ab = false;
+        op_.slot = 0;
         pc_ = next;
     }
-    void want_grad(const double *w, double a, double b, Pc next) {
+    void want_grad(const double *w, double a, double b, Pc next, int slot = 0) {
         op_.kind = OP_GRAD;
         for (int k = 0; k < K_; ++k) op_.w[k] = w[k];
         op_.ab[0] = a;
         op_.ab[1] = b;
+        op_.slot = slot;
         pc_ = next;
+    }
+    // Line search along d_ from w_ (phi_ = J(w_), gd_ = g.d_ < 0, dn_ = ||d_||)
+    // with first trial step t_; on return to `ret`, ls_ holds the outcome and,
+    // when accepted, wt_ / phi_t_ / a_t_ / b_t_ / t_ the accepted point, whose
+    // projection is in slot ls_slot_.
+    enum LsOutcome { LS_OK, LS_NOISE, LS_FAIL };
+    void line_search(Pc ret) {
+        ls_ret_ = ret;
+        bt_ = 0;
+        pc_ = LS_TRIAL;
+    }
+    void ls_end(LsOutcome outcome, int slot) {
+        ls_ = outcome;
+        ls_slot_ = slot;
+        pc_ = ls_ret_;
     }
     void finish() {
         op_.kind = OP_DONE;
@@ -107,6 +132,60 @@ private:
         const int K = K_;
         for (;;) {
             switch (pc_) {
+            // ---- line search shared by CG and BFGS -----------------------
+            // Armijo trials; a rejected trial shrinks t to the minimiser of
+            // the quadratic through phi(0), phi'(0), phi(t), kept within
+            // [beta_lo t, beta t]; a rejected change below the noise floor
+            // ends the solve.  An accepted first trial whose quadratic puts
+            // the minimiser beyond 2t is followed by one trial there (capped
+            // at ls_extrap t; backtracking alone cannot lengthen a step) and
+            // the lower of the two points is kept.
+            case LS_TRIAL:
+                if (bt_ >= o_.max_backtracks || t_ * dn_ < o_.xtol) {
+                    ls_end(LS_FAIL, 0);
+                    break;
+                }
+                for (int k = 0; k < K; ++k) wt_[k] = w_[k] + t_ * d_[k];
+                want_eval(wt_, false, 1.0, 0.0, LS_AFTER_TRIAL, 0);
+                return;
+            case LS_AFTER_TRIAL: {
+                phi_t_ = rJ_;
+                a_t_ = ra_;
+                b_t_ = rb_;
+                const double tq = -gd_ * t_ * t_ / (2.0 * (phi_t_ - phi_ - gd_ * t_));
+                if (phi_t_ <= phi_ + o_.alpha * t_ * gd_) {
+                    if (bt_ == 0 && o_.ls_extrap > 0.0 && tq > 2.0 * t_) {
+                        tx_ = tq < o_.ls_extrap * t_ ? tq : o_.ls_extrap * t_;
+                        for (int k = 0; k < K; ++k) wx_[k] = w_[k] + tx_ * d_[k];
+                        want_eval(wx_, false, 1.0, 0.0, LS_AFTER_EXTRAP, 1);
+                        return;
+                    }
+                    ls_end(LS_OK, 0);
+                    break;
+                }
+                if (fabs(phi_t_ - phi_) <= ftol_ * phi_) {   // below the objective's noise
+                    ls_end(LS_NOISE, 0);
+                    break;
+                }
+                const double lo = o_.beta_lo * t_, hi = o_.beta * t_;
+                t_ = tq < lo ? lo : (tq > hi ? hi : tq);
+                ++bt_;
+                pc_ = LS_TRIAL;
+                break;
+            }
+            case LS_AFTER_EXTRAP:
+                if (rJ_ < phi_t_) {
+                    t_ = tx_;
+                    for (int k = 0; k < K; ++k) wt_[k] = wx_[k];
+                    phi_t_ = rJ_;
+                    a_t_ = ra_;
+                    b_t_ = rb_;
+                    ls_end(LS_OK, 1);
+                } else {
+                    ls_end(LS_OK, 0);
+                }
+                break;
+
             // ---- PR+ nonlinear CG on the reduced objective ----------------
             case CG_START:
                 want_eval(w_, false, 1.0, 0.0, CG_AFTER_EVAL0);
@@ -133,13 +212,13 @@ private:
                 break;
             case CG_LOOP: {
                 if (it_ >= o_.max_iter) {
-                    pc_ = CG_FINISH;
+                    pc_ = SOLVE_FINISH;
                     break;
                 }
                 const double gn = sqrt(dot(g_, g_, K));
                 if (gn <= o_.gtol_rel * g0_ || phi_ == 0.0) {
                     rep_.status = PCAS_STOP_CONVERGED;
-                    pc_ = CG_FINISH;
+                    pc_ = SOLVE_FINISH;
                     break;
                 }
                 gd_ = dot(g_, d_, K);
@@ -150,50 +229,19 @@ private:
                 }
                 dn_ = sqrt(dot(d_, d_, K));
                 t_ = first_ ? o_.mu0 / dn_ : t_prev_ * gd_prev_ / gd_;
-                accepted_ = at_noise_ = false;
-                bt_ = 0;
-                pc_ = CG_LS;
-                break;
-            }
-            case CG_LS:
-                if (bt_ >= o_.max_backtracks || t_ * dn_ < o_.xtol) {
-                    pc_ = CG_LS_END;
-                    break;
-                }
-                for (int k = 0; k < K; ++k) wt_[k] = w_[k] + t_ * d_[k];
-                want_eval(wt_, false, 1.0, 0.0, CG_AFTER_LS_EVAL);
-                return;
-            case CG_AFTER_LS_EVAL: {
-                phi_t_ = rJ_;
-                a_t_ = ra_;
-                b_t_ = rb_;
-                if (phi_t_ <= phi_ + o_.alpha * t_ * gd_) {
-                    accepted_ = true;
-                    pc_ = CG_LS_END;
-                    break;
-                }
-                if (fabs(phi_t_ - phi_) <= ftol_ * phi_) {   // below the objective's noise
-                    at_noise_ = true;
-                    pc_ = CG_LS_END;
-                    break;
-                }
-                const double tq = -gd_ * t_ * t_ / (2.0 * (phi_t_ - phi_ - gd_ * t_));
-                const double lo = o_.beta_lo * t_, hi = o_.beta * t_;
-                t_ = tq < lo ? lo : (tq > hi ? hi : tq);
-                ++bt_;
-                pc_ = CG_LS;
+                line_search(CG_LS_END);
                 break;
             }
             case CG_LS_END:
-                if (at_noise_) {
+                if (ls_ == LS_NOISE) {
                     rep_.status = PCAS_STOP_CONVERGED;
-                    pc_ = CG_FINISH;
+                    pc_ = SOLVE_FINISH;
                     break;
                 }
-                if (!accepted_) {
+                if (ls_ == LS_FAIL) {
                     if (restart_) {
                         rep_.status = PCAS_STOP_LINESEARCH;
-                        pc_ = CG_FINISH;
+                        pc_ = SOLVE_FINISH;
                         break;
                     }
                     for (int k = 0; k < K; ++k) d_[k] = -g_[k];
@@ -205,7 +253,7 @@ private:
                 phi_ = phi_t_;
                 a_ = a_t_;
                 b_ = b_t_;
-                want_grad(w_, a_, b_, CG_AFTER_GRAD);
+                want_grad(w_, a_, b_, CG_AFTER_GRAD, ls_slot_);
                 return;
             case CG_AFTER_GRAD: {
                 double num = 0.0;
@@ -224,7 +272,120 @@ private:
                 pc_ = CG_LOOP;
                 break;
             }
-            case CG_FINISH:
+
+            // ---- BFGS on the reduced objective ------------------------------
+            // d = -H g with unit first trial; -g with mu0/||g|| while there is
+            // no estimate.  H starts as (y.s / y.y) I at the first accepted
+            // step, then takes the inverse BFGS update
+            //   H+ = (I - rho s y^T) H (I - rho y s^T) + rho s s^T, rho = 1/(y.s),
+            // expanded for symmetric H; an update with y.s <= 1e-12 |s| |y| is
+            // skipped.  A failed search drops the estimate and retries along
+            // -g; a failed search along -g ends the solve.
+            case QN_START:
+                want_eval(w_, false, 1.0, 0.0, QN_AFTER_EVAL0);
+                return;
+            case QN_AFTER_EVAL0:
+                phi_ = rJ_;
+                a_ = ra_;
+                b_ = rb_;
+                want_grad(w_, a_, b_, QN_AFTER_GRAD0);
+                return;
+            case QN_AFTER_GRAD0:
+                for (int k = 0; k < K; ++k) g_[k] = rg_[k];
+                rep_.J0 = phi_;
+                g0_ = sqrt(dot(g_, g_, K));
+                rep_.gnorm0 = g0_;
+                have_h_ = false;
+                it_ = 0;
+                rep_.status = PCAS_STOP_MAXITER;
+                pc_ = QN_LOOP;
+                break;
+            case QN_LOOP: {
+                if (it_ >= o_.max_iter) {
+                    pc_ = SOLVE_FINISH;
+                    break;
+                }
+                const double gn = sqrt(dot(g_, g_, K));
+                if (gn <= o_.gtol_rel * g0_ || phi_ == 0.0) {
+                    rep_.status = PCAS_STOP_CONVERGED;
+                    pc_ = SOLVE_FINISH;
+                    break;
+                }
+                if (have_h_) {
+                    for (int i = 0; i < K; ++i) {
+                        double v = 0.0;
+                        for (int j = 0; j < K; ++j) v += H_[i * PCAS_MAX_K + j] * g_[j];
+                        d_[i] = -v;
+                    }
+                    gd_ = dot(g_, d_, K);
+                    t_ = 1.0;
+                    if (gd_ >= 0.0) have_h_ = false;   // the estimate lost definiteness
+                }
+                if (!have_h_) {
+                    for (int k = 0; k < K; ++k) d_[k] = -g_[k];
+                    gd_ = -gn * gn;
+                    t_ = o_.mu0 / gn;
+                }
+                dn_ = sqrt(dot(d_, d_, K));
+                line_search(QN_LS_END);
+                break;
+            }
+            case QN_LS_END:
+                if (ls_ == LS_NOISE) {
+                    rep_.status = PCAS_STOP_CONVERGED;
+                    pc_ = SOLVE_FINISH;
+                    break;
+                }
+                if (ls_ == LS_FAIL) {
+                    if (!have_h_) {
+                        rep_.status = PCAS_STOP_LINESEARCH;
+                        pc_ = SOLVE_FINISH;
+                        break;
+                    }
+                    have_h_ = false;
+                    pc_ = QN_LOOP;
+                    break;
+                }
+                want_grad(wt_, a_t_, b_t_, QN_AFTER_GRAD, ls_slot_);
+                return;
+            case QN_AFTER_GRAD: {
+                double sv[PCAS_MAX_K], yv[PCAS_MAX_K];
+                for (int k = 0; k < K; ++k) {
+                    sv[k] = wt_[k] - w_[k];
+                    yv[k] = rg_[k] - g_[k];
+                }
+                const double sy = dot(sv, yv, K), yy = dot(yv, yv, K);
+                if (sy > 1e-12 * sqrt(dot(sv, sv, K)) * sqrt(yy)) {
+                    if (!have_h_) {
+                        for (int i = 0; i < K; ++i)
+                            for (int j = 0; j < K; ++j) H_[i * PCAS_MAX_K + j] = i == j ? sy / yy : 0.0;
+                        have_h_ = true;
+                    }
+                    const double rho = 1.0 / sy;
+                    double hy[PCAS_MAX_K];
+                    for (int i = 0; i < K; ++i) {
+                        double v = 0.0;
+                        for (int j = 0; j < K; ++j) v += H_[i * PCAS_MAX_K + j] * yv[j];
+                        hy[i] = v;
+                    }
+                    const double c = rho + rho * rho * dot(yv, hy, K);
+                    for (int i = 0; i < K; ++i)
+                        for (int j = 0; j < K; ++j)
+                            H_[i * PCAS_MAX_K + j] += c * sv[i] * sv[j] - rho * (sv[i] * hy[j] + hy[i] * sv[j]);
+                }
+                for (int k = 0; k < K; ++k) {
+                    w_[k] = wt_[k];
+                    g_[k] = rg_[k];
+                }
+                phi_ = phi_t_;
+                a_ = a_t_;
+                b_ = b_t_;
+                ++it_;
+                pc_ = QN_LOOP;
+                break;
+            }
+
+            case SOLVE_FINISH:
                 rep_.iters = it_;
                 rep_.J = phi_;
                 rep_.a = a_;
@@ -332,12 +493,16 @@ private:
     // results of the last operation
     double rJ_ = 0.0, ra_ = 0.0, rb_ = 0.0, rg_[PCAS_MAX_K] = {0};
     // solver state
-    double w_[PCAS_MAX_K] = {0}, wt_[PCAS_MAX_K] = {0}, g_[PCAS_MAX_K] = {0}, d_[PCAS_MAX_K] = {0};
+    double w_[PCAS_MAX_K] = {0}, wt_[PCAS_MAX_K] = {0}, wx_[PCAS_MAX_K] = {0};
+    double g_[PCAS_MAX_K] = {0}, d_[PCAS_MAX_K] = {0};
+    double H_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // BFGS inverse-Hessian estimate (row-major)
     double phi_ = 0.0, a_ = 0.0, b_ = 0.0, phi_t_ = 0.0, a_t_ = 0.0, b_t_ = 0.0;
-    double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
+    double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, tx_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
     double J_ = 0.0, gn_ = 0.0, mu_ = 0.0;
-    bool restart_ = true, first_ = true, accepted_ = false, at_noise_ = false;
-    int it_ = 0, bt_ = 0;
+    bool restart_ = true, first_ = true, have_h_ = false;
+    int it_ = 0, bt_ = 0, ls_slot_ = 0;
+    LsOutcome ls_ = LS_FAIL;
+    Pc ls_ret_ = FINISHED;
 };
 
 }  // namespace pcas

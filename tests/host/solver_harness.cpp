@@ -1,0 +1,39 @@
+// CPU harness for the host-side solver state machine: drives one
+// SolveMachine with callbacks in place of GPU evaluations, so its iterates
+// can be compared with an independent implementation on the CPU.  Test
+// infrastructure only; built with g++ by the host-logic tests.
+#include "solver.h"
+
+extern "C" {
+
+// J, (a, b) at w; the callee records which point now occupies `slot`.
+typedef double (*harness_eval_fn)(const double *w, int slot, int fixed_ab, const double *ab,
+                                  double *a, double *b);
+// g at w from the projection in `slot` (the callee checks that slot holds w).
+typedef void (*harness_grad_fn)(const double *w, int slot, double a, double b, double *g);
+
+int harness_solve(const pcas_opts *opts, int K, double ftol, const double *w0,
+                  harness_eval_fn ev, harness_grad_fn gr, double *w_out, pcas_report *rep) {
+    pcas::SolveMachine m;
+    m.start(*opts, K, ftol, w0);
+    int guard = 0;
+    while (!m.done()) {
+        if (++guard > 100000) return -1;
+        const pcas::SolveOp &op = m.op();
+        if (op.kind == pcas::OP_EVAL || op.kind == pcas::OP_RESID) {
+            double a = 1.0, b = 0.0;
+            const double J = ev(op.kind == pcas::OP_EVAL ? op.w : nullptr, op.slot,
+                                op.fixed_ab ? 1 : 0, op.ab, &a, &b);
+            m.eval_result(J, a, b);
+        } else {
+            double g[PCAS_MAX_K];
+            gr(op.w, op.slot, op.ab[0], op.ab[1], g);
+            m.grad_result(g);
+        }
+    }
+    for (int k = 0; k < K; ++k) w_out[k] = m.w()[k];
+    *rep = m.report();
+    return 0;
+}
+
+}  // extern "C"

@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.pcas_abi_version() == 2
+    assert L.pcas_abi_version() == 3
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.pcas_status_string(code)
     assert L.pcas_last_error() == b""
@@ -60,7 +60,7 @@ def test_default_and_paper_options(L):
     o = B.default_opts()
     assert (o.method, o.max_iter, o.fit_intensity, o.max_backtracks) == (1, 30, 1, 12)
     assert (o.mu0, o.alpha, o.beta, o.beta_lo) == (1.0, 0.1, 0.5, 0.1)
-    assert o.grad_mode == 1
+    assert o.grad_mode == 1 and o.ls_extrap == 10.0 and o.ftol_rel < 0
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
     p = B.paper_opts()
     scale = 1.0 / g["coefficient_std"]
@@ -172,7 +172,11 @@ def test_solve_option_and_input_validation(L, geom):
                                   ctypes.byref(o), FAKE, ws, wout, ctypes.byref(rep), None)
 
     assert call(B.default_opts(), w=nan_w) == ENONFIN
-    assert call(B.default_opts(method=2)) == EINVAL
+    assert call(B.default_opts(method=3)) == EINVAL
+    assert call(B.default_opts(method=-1)) == EINVAL
+    assert call(B.default_opts(ls_extrap=-1.0)) == EINVAL
+    assert call(B.default_opts(ls_extrap=float("inf"))) == EINVAL
+    assert call(B.default_opts(ftol_rel=float("nan"))) == EINVAL
     assert call(B.default_opts(alpha=1.5)) == EINVAL
     assert call(B.default_opts(beta=0.0)) == EINVAL
     assert call(B.default_opts(mu0=0.0)) == EINVAL

@@ -52,7 +52,8 @@ def test_batched_results_equal_alone(torch):
     cases = _models()
     devs = [Dev(c) for c in cases]
     reqs = _requests(cases, devs, 3)
-    # one request of model 0 runs the Appendix algorithm, one without the fit
+    # one request of model 0 runs the Appendix algorithm, one without the
+    # fit, two with the quasi-Newton solver
     opts = []
     for i, (m, pj, y) in enumerate(reqs):
         o = _opts(cases[m])
@@ -60,6 +61,8 @@ def test_batched_results_equal_alone(torch):
             o = B.paper_opts(locate=1, c0_mm=tuple(cases[m].tumour_c0))
         if i == 4:
             o.fit_intensity = 0
+        if i in (2, 6):
+            o.method = 2
         opts.append(o)
     srv = B.Server(256 << 20, max_active=16)
     mids = [srv.add_model(c.vol, d.f0, d.mean, d.U) for c, d in zip(cases, devs)]

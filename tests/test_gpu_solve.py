@@ -67,27 +67,64 @@ def test_tiny_paper_mode_matches_oracle(torch):
     assert abs(rep["J"] - rep_o.J) <= 1e-9 * rep_o.J
 
 
-def test_recovery32_noise_free(torch):
+@pytest.mark.parametrize("method", [1, 2])
+def test_recovery32_noise_free(torch, method):
     """Noise-free 32^3 FP64: the GPU solve recovers the planted w."""
     c = synth.recovery32()
     d = Dev(c)
     y = measured(c)
-    say("recovery32 solve")
-    w, rep = _gpu_solve(d, y, B.default_opts())
+    say("recovery32 solve method", method)
+    w, rep = _gpu_solve(d, y, B.default_opts(method=method))
     say("gpu", w, rep)
     assert np.linalg.norm(w - c.w_star) <= 1e-8 * np.linalg.norm(c.w_star)
 
 
+def test_tiny_bfgs_matches_oracle(torch):
+    """The tiny workload with the quasi-Newton solver: the same minimiser as
+    the oracle's BFGS, in fewer evaluations than CG."""
+    c = synth.tiny()
+    d = Dev(c)
+    y = measured(c)
+    say("tiny BFGS solve")
+    w, rep = _gpu_solve(d, y, B.default_opts(method=2))
+    w_o, rep_o = O.solve_bfgs(_oracle_problem(c, y), np.zeros(c.K))
+    _, rep_cg = _gpu_solve(d, y, B.default_opts())
+    say("gpu", w, rep)
+    say("oracle", w_o, rep_o.status, rep_o.iters, rep_o.n_fevals, rep_o.J)
+    assert rep["status"] in ("converged", "line_search")
+    assert rep["gnorm"] <= 1e-6 * rep["gnorm0"]
+    assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)
+    assert abs(rep["J"] - rep_o.J) <= 1e-8 * rep_o.J
+    assert rep["n_fevals"] < rep_cg["n_fevals"]
+
+
+@pytest.mark.parametrize("method,extrap", [(1, 10.0), (1, 0.0), (2, 10.0)])
+def test_reported_point_is_consistent(torch, method, extrap):
+    """The returned J, (a, b) and ||g|| are those of the returned w: the
+    gradient of every accepted point was taken from the projection slot that
+    holds that point (an extrapolated trial writes the second slot)."""
+    c = synth.small(dtype="f64", seed=21)
+    d = Dev(c)
+    y = measured(c)
+    say("consistency method", method, "extrap", extrap)
+    w, rep = _gpu_solve(d, y, B.default_opts(method=method, ls_extrap=extrap, max_iter=6))
+    J, a, b, g = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w)
+    say("gpu", rep, "J", J, "g", g)
+    assert rep["J"] == J and rep["a"] == a and rep["b"] == b
+    assert abs(rep["gnorm"] - np.linalg.norm(g)) <= 1e-13 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
-def test_small_f32_cg_matches_oracle(torch, fit):
+def test_small_f32_solve_matches_oracle(torch, fit, method):
     """Ragged anisotropic FP32 case: converged w within 1e-4 of the FP64 oracle."""
     c = synth.small(dtype="f32", seed=6)
     d = Dev(c)
     y = measured(c)
-    say("small f32 solve fit=", fit)
-    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7)
+    say("small f32 solve fit=", fit, "method", method)
+    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method)
     w, rep = _gpu_solve(d, y, opts)
-    w_o, rep_o = O.solve_cg(_oracle_problem(c, y, fit), np.zeros(c.K))
+    w_o, rep_o = O.solve(_oracle_problem(c, y, fit), np.zeros(c.K), O.SolveOptions(method=method))
     say("gpu", w, rep)
     say("oracle", w_o, rep_o.status, rep_o.iters)
     assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)

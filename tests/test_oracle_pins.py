@@ -397,23 +397,109 @@ def test_paper_solver_monotone_and_stops():
     assert rep.status in (O.STOP_CONVERGED, O.STOP_MAXITER)
 
 
-def test_planted_w_exact_recovery_32():
+@pytest.mark.parametrize("solver", ["cg", "bfgs"])
+def test_planted_w_exact_recovery_32(solver):
     """Noise-free 32^3 FP64 volume: the solve recovers the planted w to
     1e-8 relative (the measured image is exactly P f(w*), so w* is a
     zero-residual minimiser with (a, b) = (1, 0))."""
     c = synth.recovery32()
     prob, _ = _problem(c)
-    w, rep = O.solve_cg(prob, np.zeros(c.K))
+    w, rep = getattr(O, "solve_" + solver)(prob, np.zeros(c.K))
     assert rep.status == O.STOP_CONVERGED
     assert np.linalg.norm(w - c.w_star) <= 1e-8 * np.linalg.norm(c.w_star)
     np.testing.assert_allclose([rep.a, rep.b], [1.0, 0.0], atol=1e-8)
 
 
-def test_cg_monotone():
+@pytest.mark.parametrize("solver", ["cg", "bfgs"])
+def test_solver_monotone(solver):
     c = synth.small(seed=15)
     prob, _ = _problem(c)
-    w, rep = O.solve_cg(prob, np.zeros(c.K))
+    w, rep = getattr(O, "solve_" + solver)(prob, np.zeros(c.K))
     assert np.all(np.diff(rep.J_trace) <= 0.0)
+
+
+class _Quadratic:
+    """phi(w) = w.A w / 2 - c.w + 10 in the solvers' problem interface, with
+    (a, b) reported as (1, 0): its minimiser is A^-1 c in closed form."""
+
+    def __init__(self, A, c):
+        self.A, self.c = A, c
+
+    def objective(self, w):
+        return float(0.5 * w @ self.A @ w - self.c @ w + 10.0), 1.0, 0.0, None
+
+    def gradient(self, w, r):
+        return self.A @ w - self.c
+
+
+def _spd(rng, K, kappa):
+    Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
+    return Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T, Q
+
+
+def test_bfgs_update_secant_symmetric_definite():
+    """Eq. 6.17 of Nocedal and Wright: the updated inverse-Hessian estimate
+    maps y to s (the secant equation), is symmetric, and stays positive
+    definite for y.s > 0."""
+    rng = np.random.default_rng(40)
+    for K in (1, 3, 8):
+        A, _ = _spd(rng, K, 20.0)
+        H = np.linalg.inv(_spd(rng, K, 5.0)[0])
+        s = rng.normal(size=K)
+        y = A @ s
+        Hn = O.bfgs_update(H, s, y)
+        np.testing.assert_allclose(Hn @ y, s, rtol=0, atol=1e-12 * np.linalg.norm(s))
+        np.testing.assert_allclose(Hn, Hn.T, rtol=0, atol=1e-14 * np.abs(Hn).max())
+        assert np.linalg.eigvalsh(0.5 * (Hn + Hn.T)).min() > 0.0
+
+
+def test_bfgs_update_reaches_inverse_after_conjugate_steps():
+    """On a quadratic, K updates along mutually A-conjugate steps (here A's
+    eigenvectors) with y = A s turn any SPD start into A^-1 exactly."""
+    rng = np.random.default_rng(41)
+    K = 5
+    A, Q = _spd(rng, K, 50.0)
+    H = 0.3 * np.eye(K)
+    for i in range(K):
+        H = O.bfgs_update(H, Q[:, i], A @ Q[:, i])
+    np.testing.assert_allclose(H, np.linalg.inv(A), rtol=0, atol=1e-13)
+
+
+def test_cg_extrapolation_lands_on_1d_quadratic_minimiser():
+    """phi(w) = w^2 - 6 w: minimiser 3, gradient -6 at 0.  With mu0 = 0.6 the
+    first trial (w = 0.6) passes Armijo, and the quadratic through phi(0),
+    phi'(0), phi(0.6) is phi itself, so the extrapolated trial is the exact
+    minimiser when the cap allows it (ls_extrap >= 5), the cap otherwise,
+    and no trial at all when switched off."""
+    q = _Quadratic(np.array([[2.0]]), np.array([6.0]))
+    for extrap, want, nf in ((10.0, 3.0, 3), (3.0, 1.8, 3), (0.0, 0.6, 2)):
+        w, rep = O.solve_cg(q, np.zeros(1), O.SolveOptions(mu0=0.6, max_iter=1, ls_extrap=extrap))
+        assert abs(w[0] - want) <= 1e-14 * want and rep.n_fevals == nf
+
+
+def test_solvers_reach_quadratic_minimiser():
+    """Both solvers end at A^-1 c on ill-conditioned quadratics."""
+    rng = np.random.default_rng(42)
+    for K, kappa, solver, max_iter, tol in ((5, 1e3, O.solve_bfgs, 30, 1e-7),
+                                            (8, 1e3, O.solve_bfgs, 30, 1e-7),
+                                            (5, 1e2, O.solve_cg, 200, 1e-6)):
+        A, _ = _spd(rng, K, kappa)
+        c = 3.0 * rng.normal(size=K)
+        ws = np.linalg.solve(A, c)
+        w, rep = solver(_Quadratic(A, c), np.zeros(K), O.SolveOptions(max_iter=max_iter))
+        assert np.linalg.norm(w - ws) <= tol * np.linalg.norm(ws), (K, kappa, rep)
+
+
+def test_bfgs_and_cg_agree_on_noisy_small():
+    """With 1% noise the minimiser is not w*, but it is the same point
+    whichever solver finds it."""
+    c = synth.small(seed=17)
+    prob, _ = _problem(c)
+    w_cg, r_cg = O.solve_cg(prob, np.zeros(c.K))
+    w_q, r_q = O.solve_bfgs(prob, np.zeros(c.K))
+    assert r_cg.status == O.STOP_CONVERGED and r_q.status == O.STOP_CONVERGED
+    assert np.linalg.norm(w_cg - w_q) <= 1e-6 * np.linalg.norm(w_cg)
+    assert r_q.n_fevals < r_cg.n_fevals
 
 
 def test_k1_matches_bruteforce_line_search():
