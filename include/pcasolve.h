@@ -115,8 +115,9 @@ typedef struct {
                                  g_k = 2 <r, P J_k> (gathers only, no back-projection) */
     double ftol_rel;       /* methods 1, 2: a rejected trial with |J_t - J| <= ftol_rel J ends
                               the solve as converged (the change is below the objective's
-                              rounding noise); < 0 selects 1e-8 for PCAS_F32 and 1e-14 for
-                              PCAS_F64 */
+                              rounding noise); < 0 selects 3e-8 for PCAS_F32 and 1e-14 for
+                              PCAS_F64.  Method 2 also ends, converged, when its model
+                              predicts a decrease g.H g / 2 <= ftol_rel J */
     double ls_extrap;      /* methods 1, 2: when the first trial of a line search passes Armijo
                               and the quadratic through J(0), J'(0), J(t) has its minimiser
                               t_q > 2t, one more trial at min(t_q, ls_extrap t) follows and the

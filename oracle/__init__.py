@@ -507,7 +507,9 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     as (y.s / y.y) I (Nocedal and Wright, Eq. 6.20) before its first update.
     An update is skipped when y.s <= 1e-12 ||s|| ||y||.  A failed search
     with an estimate resets it and retries along -g; a failed search along
-    -g ends the solve."""
+    -g ends the solve.  With an estimate, the solve also ends (converged)
+    when the decrease the quadratic model predicts, g.H g / 2, is within
+    ftol_rel of J: what is left lies below the objective's noise."""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
     K = w.size
@@ -533,6 +535,9 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             t = 1.0
             if gd >= 0.0:                                  # estimate lost definiteness
                 H = None
+            elif -0.5 * gd <= o.ftol_rel * phi:           # predicted decrease below the noise
+                rep.status = STOP_CONVERGED
+                break
         if H is None:
             d = -g
             gd = -gn * gn

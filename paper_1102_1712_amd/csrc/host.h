@@ -197,7 +197,7 @@ inline int check_opts(const pcas_opts *o) {
 // Relative change of J below which a rejected line-search trial counts as
 // rounding noise (opts.ftol_rel, or by dtype when negative).
 inline double noise_floor(pcas_dtype dt, const pcas_opts &o) {
-    return o.ftol_rel >= 0.0 ? o.ftol_rel : (dt == PCAS_F32 ? 1e-8 : 1e-14);
+    return o.ftol_rel >= 0.0 ? o.ftol_rel : (dt == PCAS_F32 ? 3e-8 : 1e-14);
 }
 
 }  // namespace host

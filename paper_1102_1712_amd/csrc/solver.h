@@ -280,7 +280,9 @@ private:
             //   H+ = (I - rho s y^T) H (I - rho y s^T) + rho s s^T, rho = 1/(y.s),
             // expanded for symmetric H; an update with y.s <= 1e-12 |s| |y| is
             // skipped.  A failed search drops the estimate and retries along
-            // -g; a failed search along -g ends the solve.
+            // -g; a failed search along -g ends the solve.  With an estimate,
+            // a predicted decrease g.H g / 2 within the noise floor ends the
+            // solve as converged.
             case QN_START:
                 want_eval(w_, false, 1.0, 0.0, QN_AFTER_EVAL0);
                 return;
@@ -319,7 +321,14 @@ private:
                     }
                     gd_ = dot(g_, d_, K);
                     t_ = 1.0;
-                    if (gd_ >= 0.0) have_h_ = false;   // the estimate lost definiteness
+                    if (gd_ >= 0.0) {
+                        have_h_ = false;   // the estimate lost definiteness
+                    } else if (-0.5 * gd_ <= ftol_ * phi_) {
+                        // the model's predicted decrease g.H g / 2 is below the noise
+                        rep_.status = PCAS_STOP_CONVERGED;
+                        pc_ = SOLVE_FINISH;
+                        break;
+                    }
                 }
                 if (!have_h_) {
                     for (int k = 0; k < K; ++k) d_[k] = -g_[k];

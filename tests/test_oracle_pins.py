@@ -490,6 +490,25 @@ def test_solvers_reach_quadratic_minimiser():
         assert np.linalg.norm(w - ws) <= tol * np.linalg.norm(ws), (K, kappa, rep)
 
 
+def test_bfgs_decrement_stop():
+    """With an estimate H, BFGS ends when g.H g / 2 (the decrease its model
+    predicts) is within ftol_rel of phi.  On a quadratic, once H is near A^-1
+    that is the true remaining decrease phi - phi*: a stop at ftol_rel = 1e-6
+    is converged, leaves phi - phi* within a few ftol_rel phi, and saves
+    evaluations over a run to the rounding floor."""
+    rng = np.random.default_rng(43)
+    for K, kappa in ((3, 10.0), (5, 100.0), (8, 1e3)):
+        A, _ = _spd(rng, K, kappa)
+        c = 3.0 * rng.normal(size=K)
+        q = _Quadratic(A, c)
+        phi_star = q.objective(np.linalg.solve(A, c))[0]
+        w, rep = O.solve_bfgs(q, np.zeros(K), O.SolveOptions(ftol_rel=1e-6, gtol_rel=0.0))
+        w_f, rep_f = O.solve_bfgs(q, np.zeros(K), O.SolveOptions(ftol_rel=0.0, gtol_rel=1e-12))
+        assert rep.status == O.STOP_CONVERGED
+        assert 0.0 <= rep.J - phi_star <= 4e-6 * rep.J
+        assert rep.n_fevals < rep_f.n_fevals
+
+
 def test_bfgs_and_cg_agree_on_noisy_small():
     """With 1% noise the minimiser is not w*, but it is the same point
     whichever solver finds it."""

@@ -135,6 +135,19 @@ def test_machine_matches_oracle_on_quadratics(harness, method, K, kappa, seed):
     assert rep.n_fevals > 0
 
 
+@pytest.mark.parametrize("K,kappa,seed", [(3, 10.0, 4), (8, 1e3, 5)])
+def test_machine_decrement_stop_matches_oracle(harness, K, kappa, seed):
+    """BFGS ending on its predicted decrease (ftol_rel = 1e-6, no gradient
+    test): same stop, same evaluations as the oracle."""
+    rng = np.random.default_rng(200 + seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
+    A = Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T
+    c = 3.0 * rng.normal(size=K)
+    rep, _ = _compare(harness, _Quadratic(A, c), K, np.zeros(K),
+                      _opts(2, ftol_rel=1e-6, gtol_rel=0.0), 1e-9)
+    assert rep.status == O.STOP_CONVERGED
+
+
 @pytest.mark.parametrize("extrap", [0.0, 3.0, 10.0])
 def test_machine_extrapolation_and_slots(harness, extrap):
     """phi(w) = w^2 - 6 w from 0 with mu0 = 0.6: the extrapolated trial is
