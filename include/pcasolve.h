@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 3
+#define PCAS_ABI_VERSION 4
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -113,23 +113,33 @@ typedef struct {
                                  so P^T r never goes to device memory
                               0: project the K Jacobian volumes J_k = U_k^T (df/dx) and take
                                  g_k = 2 <r, P J_k> (gathers only, no back-projection) */
-    double ftol_rel;       /* methods 1, 2: a rejected trial with |J_t - J| <= ftol_rel J ends
-                              the solve as converged (the change is below the objective's
-                              rounding noise); < 0 selects 3e-8 for PCAS_F32 and 1e-14 for
-                              PCAS_F64.  Method 2 also ends, converged, when its model
-                              predicts a decrease g.H g / 2 <= ftol_rel J */
+    double ftol_rel;       /* methods 1, 2: the noise band of J (relative): a rejected trial
+                              with |J_t - J| <= ftol_rel J ends the solve as converged, and
+                              method 2 also ends, converged, when its model predicts a
+                              decrease g.H g / 2 <= ftol_rel J.  < 0 (default): a rounding
+                              model per point, 6 u sqrt(sum p^2 / (M J)) with u = 2^-24 for
+                              PCAS_F32 and 2^-53 for PCAS_F64 (three times the spread of J
+                              that rounding each p_i by u |p_i| produces) */
     double ls_extrap;      /* methods 1, 2: when the first trial of a line search passes Armijo
                               and the quadratic through J(0), J'(0), J(t) has its minimiser
                               t_q > 2t, one more trial at min(t_q, ls_extrap t) follows and the
                               lower point is kept; 0 turns this off (>= 0, finite) */
+    int32_t polish;        /* methods 1, 2: 1 = when the solve stops at the noise band (noise
+                              or decrement stop, failed search), try one step w - H g with
+                              the inverse-Hessian estimate (method 2's own; method 1 keeps
+                              one from its steps) and keep it if ||g|| drops; costs one
+                              evaluation and one gradient.  The gradient resolves the
+                              minimiser below the noise of J.  Default 0 */
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
-   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain) */
+   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain, and
+   PCAS_K_BOUNDS the once-per-projection back-projection of the all-ones
+   image that sizes its FP32 accumulators) */
 enum {
     PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
     PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
-    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_CLASSES = 10
+    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_BOUNDS = 10, PCAS_K_CLASSES = 11
 };
 
 typedef struct {
@@ -218,6 +228,13 @@ int drr_siddon(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, con
  * fully overwritten. */
 int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
                 const void *r, void *bp_out, void *stream);
+
+/* Bound B on the summed trilinear weight that all rays of a projection give
+ * one voxel: (P^T 1)(v) <= step * B for every voxel v.  The back-projection
+ * sizes its fixed-point accumulators from it (a brick's voxel totals stay
+ * below step * max|r| * B in magnitude).  Host-only, no device memory.
+ * Returns a negative value for an invalid volume or projection. */
+double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj);
 
 /* ---- a5: intensity fit (Eq. A.1) and residual ----------------------------
  * stats_out: device double[8] =

@@ -265,7 +265,14 @@ class SolveOptions:
     In CG and BFGS modes the line search (_line_search) shrinks a failed
     Armijo trial to the minimiser of the quadratic through phi(0), phi'(0)
     and phi(t), kept within [beta_lo * t, beta * t], and may lengthen an
-    accepted first trial once (ls_extrap); mu_min is unused there."""
+    accepted first trial once (ls_extrap); mu_min is unused there.
+
+    polish: when a CG or BFGS solve ends at the noise floor (the noise or
+    decrement stop, or a failed search), one more step w - H g is tried with
+    an inverse-Hessian estimate H (BFGS's own; CG keeps one from its steps by
+    the same updates) and kept if it lowers ||g||.  The gradient stays
+    accurate far below the noise of J, so this reaches the minimiser more
+    closely than comparisons of J can."""
     method: int = 1
     max_iter: int = 30
     fit_intensity: bool = True
@@ -279,6 +286,7 @@ class SolveOptions:
     xtol: float = 1e-10
     ftol_rel: float = 1e-14
     ls_extrap: float = 10.0
+    polish: bool = False
 
     @staticmethod
     def paper() -> "SolveOptions":
@@ -445,6 +453,8 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     d = -g
     restart, first = True, True
     t_prev = gd_prev = 0.0
+    H = None                                           # for the polish step only
+    floor = False                                      # ended at the noise floor
     it = 0
     rep.status = STOP_MAXITER
     while it < o.max_iter:
@@ -462,17 +472,21 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
         rep.n_fevals += n
         if st == "noise":
             rep.status = STOP_CONVERGED
+            floor = True
             break
         if st == "fail":
             if restart:
                 rep.status = STOP_LINESEARCH
+                floor = True
                 break
             d = -g
             restart = True
             continue
-        w, phi, a, b, r = w_t, phi_t, a_t, b_t, r_t
-        g_new = prob.gradient(w, r)
+        g_new = prob.gradient(w_t, r_t)
         rep.n_grads += 1
+        if o.polish:
+            H = _hessian_update(H, w_t - w, g_new - g)
+        w, phi, a, b, r = w_t, phi_t, a_t, b_t, r_t
         beta_pr = max(0.0, float(g_new @ (g_new - g)) / float(g @ g))
         d = -g_new + beta_pr * d
         t_prev, gd_prev = t, gd
@@ -480,6 +494,8 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
         restart, first = False, False
         it += 1
         rep.J_trace.append(phi)
+    if floor and o.polish:
+        w, phi, a, b, g = _polish(prob, H, w, phi, a, b, g, rep)
     rep.iters = it
     rep.J, rep.a, rep.b = phi, a, b
     rep.gnorm = float(np.linalg.norm(g))
@@ -497,6 +513,35 @@ def bfgs_update(H, s, y):
     return L @ H @ L.T + rho * np.outer(s, s)
 
 
+def _hessian_update(H, s_k, y_k):
+    """The estimate's update after an accepted step (solve_bfgs's rule; also
+    kept by solve_cg for the polish step): scaled identity at the first
+    usable pair, then bfgs_update; pairs with y.s <= 1e-12 |s| |y| skipped."""
+    sy = float(s_k @ y_k)
+    if sy > 1e-12 * float(np.linalg.norm(s_k)) * float(np.linalg.norm(y_k)):
+        if H is None:
+            H = (sy / float(y_k @ y_k)) * np.eye(s_k.size)
+        H = bfgs_update(H, s_k, y_k)
+    return H
+
+
+def _polish(prob, H, w, phi, a, b, g, rep):
+    """One step w - H g, kept if ||g|| drops (SolveOptions.polish)."""
+    if H is None:
+        return w, phi, a, b, g
+    d = -(H @ g)
+    if float(g @ d) >= 0.0:
+        return w, phi, a, b, g
+    w_p = w + d
+    phi_p, a_p, b_p, r_p = prob.objective(w_p)
+    rep.n_fevals += 1
+    g_p = prob.gradient(w_p, r_p)
+    rep.n_grads += 1
+    if float(np.linalg.norm(g_p)) < float(np.linalg.norm(g)):
+        return w_p, phi_p, a_p, b_p, g_p
+    return w, phi, a, b, g
+
+
 def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     """BFGS on phi(w) = min_{a,b} J(w, a, b), the reduced objective of
     solve_cg.
@@ -512,7 +557,6 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     ftol_rel of J: what is left lies below the objective's noise."""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
-    K = w.size
     rep = SolveReport()
     phi, a, b, r = prob.objective(w)
     rep.n_fevals += 1
@@ -522,6 +566,8 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     rep.J_trace.append(phi)
     g0 = float(np.linalg.norm(g))
     H = None
+    H_last = None                                      # last estimate, for the polish step
+    floor = False
     it = 0
     rep.status = STOP_MAXITER
     while it < o.max_iter:
@@ -537,6 +583,7 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
                 H = None
             elif -0.5 * gd <= o.ftol_rel * phi:           # predicted decrease below the noise
                 rep.status = STOP_CONVERGED
+                floor = True
                 break
         if H is None:
             d = -g
@@ -546,25 +593,23 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
         rep.n_fevals += n
         if st == "noise":
             rep.status = STOP_CONVERGED
+            floor = True
             break
         if st == "fail":
             if H is None:
                 rep.status = STOP_LINESEARCH
+                floor = True
                 break
-            H = None
+            H_last, H = H, None
             continue
         g_new = prob.gradient(w_t, r_t)
         rep.n_grads += 1
-        s_k = w_t - w
-        y_k = g_new - g
-        sy = float(s_k @ y_k)
-        if sy > 1e-12 * float(np.linalg.norm(s_k)) * float(np.linalg.norm(y_k)):
-            if H is None:
-                H = (sy / float(y_k @ y_k)) * np.eye(K)
-            H = bfgs_update(H, s_k, y_k)
+        H = _hessian_update(H, w_t - w, g_new - g)
         w, phi, a, b, g = w_t, phi_t, a_t, b_t, g_new
         it += 1
         rep.J_trace.append(phi)
+    if floor and o.polish:
+        w, phi, a, b, g = _polish(prob, H if H is not None else H_last, w, phi, a, b, g, rep)
     rep.iters = it
     rep.J, rep.a, rep.b = phi, a, b
     rep.gnorm = float(np.linalg.norm(g))

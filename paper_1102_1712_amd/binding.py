@@ -23,7 +23,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "invalid geometry", -3: "singular
 STOP = {0: "converged", 1: "max_iter", 2: "line_search"}
 EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_default_opts",
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
-           "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "residual_fit_workspace_bytes",
+           "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "pcas_backprojection_bound",
+           "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
            "objective_gradient", "solve_projection_workspace", "solve_projection",
            "pcas_server_reserved_bytes", "pcas_server_create", "pcas_server_destroy",
@@ -62,7 +63,8 @@ class Opts(ctypes.Structure):
                 ("locate", ctypes.c_int32), ("locate_max_iter", ctypes.c_int32),
                 ("locate_tol", ctypes.c_double), ("c0_mm", ctypes.c_double * 3),
                 ("profile", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
-                ("ftol_rel", ctypes.c_double), ("ls_extrap", ctypes.c_double)]
+                ("ftol_rel", ctypes.c_double), ("ls_extrap", ctypes.c_double),
+                ("polish", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -71,14 +73,16 @@ class Report(ctypes.Structure):
                 ("J0", ctypes.c_double), ("J", ctypes.c_double), ("a", ctypes.c_double),
                 ("b", ctypes.c_double), ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double),
                 ("tumour_mm", ctypes.c_double * 3), ("locate_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 10),
-                ("kernel_launches", ctypes.c_int32 * 10)]
+                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 11),
+                ("kernel_launches", ctypes.c_int32 * 11)]
 
 
 # report.kernel_ms classes; in a solve class 4 is the back-projection with the
-# Jacobian chain fused into it
+# Jacobian chain fused into it, class 10 the per-projection all-ones
+# back-projection that bounds its FP32 accumulators
 KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint_chain",
-                  "grad_w", "tumour_position", "y_sums", "jacobian", "drr_forward_dot")
+                  "grad_w", "tumour_position", "y_sums", "jacobian", "drr_forward_dot",
+                  "adjoint_bounds")
 
 
 _lib = None
@@ -109,6 +113,7 @@ def lib():
             "drr_forward": (I32, [I32, VP, PP, P, P, P, P]),
             "drr_adjoint": (I32, [I32, VP, PP, P, P, P, P]),
             "drr_siddon": (I32, [I32, VP, PP, P, P, P]),
+            "pcas_backprojection_bound": (D, [VP, PP]),
             "residual_fit_workspace_bytes": (SZ, [I64]),
             "residual_fit": (I32, [I32, I64, P, P, I32, P, P, P, SZ, P]),
             "grad_w_workspace_bytes": (SZ, [I32, VP, I32]),
@@ -313,6 +318,14 @@ def drr_adjoint(vol, proj, rays, r, out=None, stream=None):
     return out
 
 
+def backprojection_bound(vol, proj) -> float:
+    """B with (P^T 1)(v) <= step * B for every voxel (host-only query)."""
+    b = lib().pcas_backprojection_bound(ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)))
+    if b < 0:
+        raise PcasError(-1, "backprojection_bound: invalid volume or projection")
+    return b
+
+
 def residual_fit(p, y, fit_intensity: bool = True, r_out=None, want_r: bool = True, stream=None):
     """a5 (Eq. A.1, Eq. 2): returns (r, stats) with stats a float64 device
     tensor [J, a, b, sum p, sum p y, sum p p, sum y, sum y y]."""
@@ -382,7 +395,7 @@ def _apply(o: Opts, overrides) -> Opts:
             for c in range(3):
                 o.c0_mm[c] = float(v[c])
         elif k in ("method", "max_iter", "fit_intensity", "max_backtracks", "locate",
-                   "locate_max_iter", "profile", "grad_mode"):
+                   "locate_max_iter", "profile", "grad_mode", "polish"):
             setattr(o, k, int(v))
         else:
             setattr(o, k, float(v))

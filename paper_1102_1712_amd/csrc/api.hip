@@ -156,6 +156,11 @@ int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     return PCAS_OK;
 }
 
+double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj) {
+    if (check_vol(vol) || check_proj(proj, vol)) return -1.0;
+    return backprojection_weight_bound(make_dims(vol), make_frame(proj));
+}
+
 size_t residual_fit_workspace_bytes(int64_t npix) {
     if (npix < 1) return 0;
     return align256((size_t)sums_blocks(npix) * RED_SLOTS * sizeof(double)) + 512;
@@ -331,6 +336,8 @@ struct Solver {
 
     // J = ||p - a y - b||^2 for the projection in the p buffer, summed
     // directly over the residual; (a, b) refitted by Eq. A.1 unless fixed.
+    // Per-brick (P^T 1) maxima for the FP32 back-projection's accumulators.
+    float *bounds() const { return (float *)(ws + L.bounds); }
     // Projection buffer of a line-search slot (0 or 1).
     char *proj_slot(int slot) const { return ws + (slot ? L.p2 : L.p); }
 
@@ -381,7 +388,8 @@ struct Solver {
             HIPCHK(timed(PCAS_K_ADJOINT, [&] {
                 return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, proj_slot(slot), y, a, b, f0,
                                                 mean, U, w, (double *)(ws + L.partials),
-                                                &counters()[1], scal() + 8, s);
+                                                &counters()[1], scal() + 8,
+                                                dt == PCAS_F32 ? bounds() : nullptr, s);
             }));
         }
         ++n_grads;
@@ -416,6 +424,10 @@ struct Solver {
         prof.on = profile;
         HIPCHK(launch_fill_u32(counters(), 64, 0u, s));
         HIPCHK(timed(PCAS_K_RAYS, [&] { return launch_ray_table(dt, vd, fr, ws + L.rays, s); }));
+        if (dt == PCAS_F32 && grad_mode == 1)
+            HIPCHK(timed(PCAS_K_BOUNDS, [&] {
+                return launch_backprojection_bounds(dt, vd, fr, ws + L.rays, bounds(), s);
+            }));
         // sums of the measured image: (sum y, sum y^2, ., ., .)
         HIPCHK(timed(PCAS_K_YSUMS, [&] {
             return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],
@@ -490,7 +502,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
         return st;
 
     SolveMachine m;
-    m.start(*opts, K, noise_floor(dtype, *opts), w0);
+    m.start(*opts, K, noise_model(dtype, *opts, S.M, S.sy, S.syy), w0);
     st = drive(S, m);
     *report = m.report();
     if (st) return st;

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "internal.h"
+#include "solver.h"
 
 namespace pcas {
 namespace host {
@@ -148,7 +149,7 @@ inline int readback(double *host, const double *dev, int count, hipStream_t s) {
 // ---- workspace layouts ---------------------------------------------------
 
 struct SolveWs {
-    size_t rays, f, p, p2, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
+    size_t rays, f, p, p2, vol2, bounds, partials, counters, scalars, total;   // vol2: bp, or the J_k
 };
 
 inline int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
@@ -172,6 +173,7 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
     L.p = off; off += align256(M * es);
     L.p2 = off; off += align256(M * es);   // second projection slot of the line search
     L.vol2 = off; off += with_vol2 ? align256((size_t)(K > 1 ? K : 1) * N * es) : 0;
+    L.bounds = off; off += align256((size_t)drr_adjoint_blocks(make_dims(v)) * sizeof(float));
     L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
     L.counters = off; off += 256;
     L.scalars = off; off += align256(64 * sizeof(double));
@@ -190,14 +192,23 @@ inline int check_opts(const pcas_opts *o) {
         return PCAS_EINVAL;
     if (!(o->beta_lo > 0.0 && o->beta_lo <= o->beta)) return PCAS_EINVAL;
     if (!(o->ls_extrap >= 0.0) || !isfinite(o->ls_extrap) || isnan(o->ftol_rel)) return PCAS_EINVAL;
+    if (o->polish != 0 && o->polish != 1) return PCAS_EINVAL;
     if (o->locate && !finite_vec(o->c0_mm, 3)) return PCAS_EINVAL;
     return PCAS_OK;
 }
 
-// Relative change of J below which a rejected line-search trial counts as
-// rounding noise (opts.ftol_rel, or by dtype when negative).
-inline double noise_floor(pcas_dtype dt, const pcas_opts &o) {
-    return o.ftol_rel >= 0.0 ? o.ftol_rel : (dt == PCAS_F32 ? 3e-8 : 1e-14);
+// The solver's noise band of J: opts.ftol_rel when >= 0, else the rounding
+// model at the evaluation type's unit roundoff with the measured image's
+// sums (sum y, sum y^2) and pixel count.
+inline NoiseModel noise_model(pcas_dtype dt, const pcas_opts &o, int64_t M, double sy,
+                              double syy) {
+    NoiseModel n;
+    n.fixed = o.ftol_rel;
+    n.u = dt == PCAS_F32 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;   // 2^-24, 2^-53
+    n.M = (double)M;
+    n.sy = sy;
+    n.syy = syy;
+    return n;
 }
 
 }  // namespace host

@@ -126,7 +126,8 @@ struct AdjJob {                 // back-projection of the residual + Jacobian ch
     VolDims vd;
     Frame fr;
     int nbx, nby;
-    double hb;
+    double hb, vb;   // one ray's, and all rays', summed weight bound for one voxel
+    const float *bounds;   // FP32: per-brick (P^T 1) maxima (launch_backprojection_bounds)
     const void *rays, *p, *y;
     double a, b;
     const void *f0, *mean, *U;
@@ -184,13 +185,22 @@ hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, 
 // Back-projection of the residual r = p - a y - b fused with the Jacobian
 // chain: g_out[k] = 2 sum_v (P^T r)(v) sum_c U_kc df/dx_c (bp stays on
 // chip); partials needs drr_adjoint_blocks() * RED_SLOTS doubles, counter
-// one zeroed uint32 (left zeroed on exit).
+// one zeroed uint32 (left zeroed on exit).  FP32 needs bounds, the output of
+// launch_backprojection_bounds for the same geometry (hipErrorInvalidValue
+// without it).
 int drr_adjoint_blocks(const VolDims &v);
+// Bound on sum over rays and samples of the trilinear weight one voxel gets.
+double backprojection_weight_bound(const VolDims &v, const Frame &fr);
+// bound_out[brick] (drr_adjoint_blocks() floats) >= the largest (P^T 1)(v)
+// over the brick's voxels: the back-projection of the all-ones image, a
+// function of the ray table alone, rounded up.
+hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                                       const void *rays, float *bound_out, hipStream_t s);
 hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame &fr, int K,
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,
                                     const double *w, double *partials, uint32_t *counter,
-                                    double *g_out, hipStream_t s);
+                                    double *g_out, const float *bounds, hipStream_t s);
 
 // J[k][v] = sum_c U_kc(v) df/dx_c(v) at w (Eq. A.8 chain per voxel).
 hipError_t launch_jacobian(pcas_dtype dt, const VolDims &v, int K, const void *f0,
@@ -246,7 +256,7 @@ hipError_t launch_residual_batch(pcas_dtype dt, const ResJob *jobs, int njobs, i
 AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,
                     const void *y, double a, double b, const void *f0, const void *mean,
                     const void *U, const double *w, double *partials, uint32_t *counter,
-                    double *g_out);
+                    double *g_out, const float *bounds);
 hipError_t launch_drr_adjoint_chain_batch(pcas_dtype dt, int K, const AdjJob *jobs, int njobs,
                                           int total_blocks, hipStream_t s);
 // dst[i * count + t] = src[i][t] for i < n (src: device array of pointers).

@@ -18,6 +18,7 @@
 // overflow; integer addition is associative, so the result does not depend
 // on the order in which the four waves add, and is bit-for-bit reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "jacobian.h"
 
@@ -594,15 +595,29 @@ constexpr int QCAP = 128;      // ring queue of rays per wave (power of two)
 constexpr int ADJ_RUN = 8;     // samples per lane between queue refills
 
 // Fixed-point image of one already-scaled contribution v as a 64-bit two's
-// complement integer.  float: |v| <= 2^30, rounded to the nearest integer
-// and sign-extended; double: |v| <= 2^50, rounded by reading the mantissa
-// of v + 1.5 * 2^52.
+// complement integer.  float: |v| <= 2^30, truncated toward zero and
+// sign-extended (one unit is at most 2^-30 of the largest contribution, far
+// below the float product's own rounding); double: |v| <= 2^50, rounded to
+// nearest by reading the mantissa of v + 1.5 * 2^52.
 __device__ __forceinline__ unsigned long long fixed_of(float v) {
-    return (unsigned long long)(long long)(int)__builtin_rintf(v);
+    return (unsigned long long)(long long)(int)v;
 }
 __device__ __forceinline__ unsigned long long fixed_of(double v) {
     const double m = v + 6755399441055744.0;
     return __builtin_bit_cast(unsigned long long, m) - 0x4338000000000000ull;
+}
+// 32-bit image of an already-scaled float contribution, |v| < 2^31, truncated
+// toward zero (the accumulator of the solver's FP32 gradient, whose scale
+// comes from the measured per-brick bound).
+__device__ __forceinline__ unsigned int fixed32_of(float v) { return (unsigned int)(int)v; }
+__device__ __forceinline__ long long acc_value(unsigned int a) { return (long long)(int)a; }
+__device__ __forceinline__ long long acc_value(unsigned long long a) { return (long long)a; }
+template <bool A32, typename V>
+__device__ __forceinline__ auto acc_image(V v) {
+    if constexpr (A32)
+        return fixed32_of(v);
+    else
+        return fixed_of(v);
 }
 template <typename T> struct FixedRange;
 template <> struct FixedRange<float> { static constexpr double per_add = 1073741824.0; };       // 2^30
@@ -644,11 +659,13 @@ __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__re
     if constexpr (FORM_R)
         return (T)((double)rp[pix] - a * (double)y[pix] - b);
     else
-        return rp[pix];
+        return rp ? rp[pix] : (T)1;   // no residual: the all-ones image
 }
 
-// hb bounds the summed weight one ray can give one voxel (1/h + 1 for the
-// smallest per-sample index step h of any ray with two or more samples).
+// hb bounds the summed weight one ray can give one voxel (samples within the
+// voxel's cube of index half-width 1, each of weight at most 1); vb bounds
+// the summed weight of all rays (backprojection_weight_bound).  A brick's
+// voxel totals are at most step * max|r| * min(hb * footprint pixels, vb).
 //
 // Work distribution: the rays of the brick's detector footprint with a
 // non-empty sample range near the brick go into a per-wave ring queue
@@ -660,14 +677,24 @@ __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__re
 // footprint).  Integer addition is associative, so the brick's sums do not
 // depend on which lane adds when.
 //
-// K = 0: bp is written.  K > 0 (the solver's gradient): bp never leaves the
+// K = 0: bp is written, or with bound_out (and no residual, r = 1) the
+// largest voxel value of the brick, (P^T 1)(v) = sum of dt * weight, goes to
+// bound_out[brick].  K > 0 (the solver's gradient): bp never leaves the
 // chip; each brick voxel's value is chained at once through the warp
 // Jacobian (Eq. A.8 and the modes, as grad_w does) and the block sums of
 // bp * sum_c U_kc df/dx_c go through the fixed-order grid reduction into
 // g_out[k] (times 2).
+//
+// Accumulator: 64-bit fixed point, except for the FP32 gradient (K > 0),
+// which adds 32-bit fixed point (half the LDS traffic and bank conflicts).
+// Its scale comes from bounds[]: every voxel total of a brick, halo slots
+// included, is at most max|r| times the largest (P^T 1) of the brick and its
+// 26 neighbours, and S keeps that below 2^31.
 template <typename T, bool FORM_R, int K>
 __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame &fr, int nbx,
-                                                  int nby, double hb,
+                                                  int nby, double hb, double vb,
+                                                  const float *__restrict__ bounds,
+                                                  float *__restrict__ bound_out,
                                                   const RayRec<T> *__restrict__ rays,
                                                   const T *__restrict__ rp,
                                                   const T *__restrict__ y, double a, double b,
@@ -677,7 +704,9 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                                                   double *__restrict__ partials,
                                                   uint32_t *counter, double *__restrict__ g_out,
                                                   int lb, int nb) {
-    __shared__ unsigned long long acc[ACC_WORDS];
+    constexpr bool ACC32 = std::is_same<T, float>::value && K > 0;
+    using AccT = typename std::conditional<ACC32, unsigned int, unsigned long long>::type;
+    __shared__ AccT acc[ACC_WORDS];
     __shared__ T q_f[ADJ_WAVES][7][QCAP];       // e[3], d[3], scaled dt * r
     __shared__ int q_s[ADJ_WAVES][2][QCAP];     // first and last sample
     __shared__ double red[ADJ_WAVES];
@@ -692,7 +721,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                        min(lo[2] + BRICK_Z, n2) - 1};
     const int nn[3] = {n0, n1, n2};
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int t = tid; t < ACC_WORDS; t += 256) acc[t] = 0ull;
+    for (int t = tid; t < ACC_WORDS; t += 256) acc[t] = 0;
 
     // Detector footprint of the region whose samples can reach the brick:
     // index box [lo - 1, hi + 1] clipped to the grid, projected through its
@@ -726,9 +755,9 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
 
     // Per-brick fixed-point scale S from the largest |r| in the footprint:
     // every contribution is |dt r w| <= step * rmax = C, a voxel total is
-    // <= C hb * npix.  S keeps the former within FixedRange (so fixed_of is
-    // exact rounding) and the latter below 2^62 (no 64-bit overflow), and is
-    // a power of two, so scaling dt * r by it is exact.
+    // <= C min(hb * npix, vb).  S keeps the former within FixedRange (so
+    // fixed_of's conversion is in range) and the latter below 2^62 (no 64-bit
+    // overflow), and is a power of two, so scaling dt * r by it is exact.
     double rmax = 0.0;
     for (int t = tid; t < npix; t += 256) {
         const int pix = (iv0 + t / W) * fr.nu + (iu0 + t % W);
@@ -740,9 +769,25 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     rmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     const double C = fr.step * rmax * (1.0 + 1e-6);
     double Sd = 0.0;
-    if (C > 0.0) {
+    if constexpr (ACC32) {
+        // largest (P^T 1) over the brick and its neighbours (halo slots hold
+        // parts of the neighbours' voxel totals)
+        double bmax = 0.0;
+        for (int nz = max(bz - 1, 0); nz <= min(bz + 1, (n2 + BRICK_Z - 1) / BRICK_Z - 1); ++nz)
+            for (int ny = max(by - 1, 0); ny <= min(by + 1, nby - 1); ++ny)
+                for (int nx = max(bx - 1, 0); nx <= min(bx + 1, nbx - 1); ++nx)
+                    bmax = fmax(bmax, (double)bounds[(nz * nby + ny) * nbx + nx]);
+        // totals <= rmax * bmax; 1e-5 covers the float products' rounding,
+        // 2^-12 of the range the truncations (a few thousand adds per voxel)
+        const double lim = 2147483648.0 * (1.0 - 1.0 / 4096.0) / (rmax * bmax * (1.0 + 1e-5));
+        if (rmax > 0.0 && bmax > 0.0) {
+            int ex;
+            frexp(fmin(lim, 1e300), &ex);
+            Sd = ldexp(0.5, ex);
+        }
+    } else if (C > 0.0) {
         const double lim_add = FixedRange<T>::per_add / C;
-        const double lim_vox = 4611686018427387904.0 / (C * hb * (double)npix);   // 2^62
+        const double lim_vox = 4611686018427387904.0 / (C * fmin(hb * (double)npix, vb));   // 2^62
         int ex;
         frexp(fmin(fmin(lim_add, lim_vox), 1e300), &ex);
         Sd = ldexp(0.5, ex);   // the largest power of two not above the limits
@@ -752,12 +797,13 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const T lob[3] = {(T)(lo[0] - 1), (T)(lo[1] - 1), (T)(lo[2] - 1)};
     const T hib[3] = {(T)(hi[0] + 1), (T)(hi[1] + 1), (T)(hi[2] + 1)};
     const int ext[3] = {hi[0] - lo[0] + 2, hi[1] - lo[1] + 2, hi[2] - lo[2] + 2};
+    const int lom[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};   // halo origin
     // Candidate tiles interleave the footprint: lane (lu, lv) of tile (bu,
     // bv) takes pixel (iu0 + lu*Su + bu, iv0 + lv*Sv + bv), so the rays of one
     // tile sit Su x Sv pixels apart; tiles go round-robin to the four waves.
     const int Su = W > 0 ? (W + 7) / 8 : 0;
     const int Sv = H > 0 ? (H + 7) / 8 : 0;
-    const int ntiles = (C > 0.0 && npix > 0) ? Su * Sv : 0;
+    const int ntiles = (Sd > 0.0 && npix > 0) ? Su * Sv : 0;
     T(*qf)[QCAP] = q_f[wave];
     int(*qs)[QCAP] = q_s[wave];
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -833,22 +879,23 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                 T z[3];
                 sample_cell(e, d, sh, top, l, z);
                 // halo-array coordinates of the cell's lower corner
-                const int lx = l[0] - lo[0] + 1, ly = l[1] - lo[1] + 1, lz = l[2] - lo[2] + 1;
+                const int lx = l[0] - lom[0], ly = l[1] - lom[1], lz = l[2] - lom[2];
                 if ((unsigned)lx < (unsigned)ext[0] && (unsigned)ly < (unsigned)ext[1] &&
                     (unsigned)lz < (unsigned)ext[2]) {
-                    unsigned long long *pa = acc + (lz * ACC_ZP + ly * ACC_YP + lx);
+                    AccT *pa =
+                        acc + (__umul24((unsigned)lz, ACC_ZP) + __umul24((unsigned)ly, ACC_YP) + lx);
                     const T c1a = cst * ((T)1 - z[1]), c1b = cst * z[1];
                     const T za = (T)1 - z[2], zb = z[2];
                     const T w00 = c1a * za, w10 = c1b * za, w01 = c1a * zb, w11 = c1b * zb;
                     const T xa = (T)1 - z[0], xb = z[0];
-                    atomicAdd(pa, fixed_of(w00 * xa));
-                    atomicAdd(pa + 1, fixed_of(w00 * xb));
-                    atomicAdd(pa + ACC_YP, fixed_of(w10 * xa));
-                    atomicAdd(pa + ACC_YP + 1, fixed_of(w10 * xb));
-                    atomicAdd(pa + ACC_ZP, fixed_of(w01 * xa));
-                    atomicAdd(pa + ACC_ZP + 1, fixed_of(w01 * xb));
-                    atomicAdd(pa + ACC_ZP + ACC_YP, fixed_of(w11 * xa));
-                    atomicAdd(pa + ACC_ZP + ACC_YP + 1, fixed_of(w11 * xb));
+                    atomicAdd(pa, acc_image<ACC32>(w00 * xa));
+                    atomicAdd(pa + 1, acc_image<ACC32>(w00 * xb));
+                    atomicAdd(pa + ACC_YP, acc_image<ACC32>(w10 * xa));
+                    atomicAdd(pa + ACC_YP + 1, acc_image<ACC32>(w10 * xb));
+                    atomicAdd(pa + ACC_ZP, acc_image<ACC32>(w01 * xa));
+                    atomicAdd(pa + ACC_ZP + 1, acc_image<ACC32>(w01 * xb));
+                    atomicAdd(pa + ACC_ZP + ACC_YP, acc_image<ACC32>(w11 * xa));
+                    atomicAdd(pa + ACC_ZP + ACC_YP + 1, acc_image<ACC32>(w11 * xb));
                 }
                 sh += (T)1;
                 busy = ++s <= s_end;
@@ -859,12 +906,28 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
     const double inv_S = Sd > 0.0 ? 1.0 / Sd : 0.0;
     if constexpr (K == 0) {
+        long long vmax = 0;
         for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
             const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
             const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
             if (i < n0 && j < n1 && k < n2) {
                 const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
-                bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
+                if (bound_out)
+                    vmax = v > vmax ? v : vmax;
+                else
+                    bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
+            }
+        }
+        if (bound_out) {
+            // each truncated addend is low by < 1 unit; 1e-6 more covers the
+            // rounding of dt * weight in T
+            double m = wave_max((double)vmax);
+            if (lane == 0) red[wave] = m;
+            __syncthreads();
+            if (tid == 0) {
+                m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+                const double vb_brick = m > 0.0 ? (m + 65536.0) * inv_S * (1.0 + 1e-6) : 0.0;
+                bound_out[bid] = __double2float_ru(vb_brick);
             }
         }
     } else {
@@ -881,7 +944,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                 const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
                 const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
                 if (i >= n0 || j >= n1 || k >= n2) continue;
-                const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
+                const long long v = acc_value(acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)]);
                 const T bpv = (T)((double)v * inv_S);
                 if (bpv == (T)0) continue;
                 const int64_t vox = i + s1 * j + s2 * k;
@@ -900,7 +963,9 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
 
 template <typename T, bool FORM_R, int K>
 __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
-                                                     double hb,
+                                                     double hb, double vb,
+                                                     const float *__restrict__ bounds,
+                                                     float *__restrict__ bound_out,
                                                      const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ rp,
                                                      const T *__restrict__ y, double a, double b,
@@ -909,7 +974,8 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
                                                      const T *__restrict__ U, WVec w,
                                                      double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ g_out) {
-    drr_adjoint_block<T, FORM_R, K>(vd, fr, nbx, nby, hb, rays, rp, y, a, b, bp, f0, mean, U, w,
+    drr_adjoint_block<T, FORM_R, K>(vd, fr, nbx, nby, hb, vb, bounds, bound_out, rays, rp, y, a, b,
+                                    bp, f0, mean, U, w,
                                     partials, counter, g_out, blockIdx.x, gridDim.x);
 }
 
@@ -919,7 +985,8 @@ __global__ __launch_bounds__(256) void k_drr_adjoint_batch(const AdjJob *__restr
                                                            int njobs) {
     const int j = job_of(jobs, njobs);
     const AdjJob &J = jobs[j];
-    drr_adjoint_block<T, true, K>(J.vd, J.fr, J.nbx, J.nby, J.hb, (const RayRec<T> *)J.rays,
+    drr_adjoint_block<T, true, K>(J.vd, J.fr, J.nbx, J.nby, J.hb, J.vb, J.bounds, nullptr,
+                                  (const RayRec<T> *)J.rays,
                                   (const T *)J.p, (const T *)J.y, J.a, J.b, (T *)nullptr,
                                   (const T *)J.f0, (const T *)J.mean, (const T *)J.U, J.w,
                                   J.partials, J.counter, J.g_out, blockIdx.x - J.block0,
@@ -935,6 +1002,43 @@ static double ray_weight_bound(const VolDims &v, const Frame &fr) {
     return 2.0 * sqrt(3.0) * smax / fr.step + 2.0;
 }
 
+// Bound on the summed trilinear weight all rays give one voxel.  Samples
+// reaching voxel v lie in the cube of index half-width 1 around it (and in
+// the grid box), whose points are at most diam = 2 sqrt(sum s_c^2) mm apart.
+// On the grid box the detector coordinates u = SID (p.eu) / D and
+// v = SID p_z / D, with depth D = p.en + SAD, change by at most
+// (SID / D_min)(1 + A / D_min) per mm, A the largest |p.eu| (|p_z|) over the
+// box (all three are linear in p, so their extremes sit at box corners).  So
+// at most (floor(diam |grad u| / pitch_u) + 1)(... v ...) pixel centres see
+// the cube, and each of those rays gives the voxel at most ray_weight_bound.
+double backprojection_weight_bound(const VolDims &v, const Frame &fr) {
+    double dmin = INFINITY, au = 0.0, av = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        double p[3];
+        p[0] = v.origin[0] + ((corner & 1) ? (v.n0 - 1) * v.spacing[0] : 0.0);
+        p[1] = v.origin[1] + ((corner & 2) ? (v.n1 - 1) * v.spacing[1] : 0.0);
+        p[2] = v.origin[2] + ((corner & 4) ? (v.n2 - 1) * v.spacing[2] : 0.0);
+        double rel[3], depth = 0.0, pu = 0.0, pv = 0.0;
+        for (int c = 0; c < 3; ++c) rel[c] = p[c] - fr.src[c];
+        for (int c = 0; c < 3; ++c) {
+            depth += rel[c] * fr.en[c];
+            pu += rel[c] * fr.eu[c];
+            pv += rel[c] * fr.ev[c];
+        }
+        dmin = fmin(dmin, depth);
+        au = fmax(au, fabs(pu));
+        av = fmax(av, fabs(pv));
+    }
+    if (!(dmin > 0.0)) return INFINITY;
+    double diam = 0.0;
+    for (int c = 0; c < 3; ++c) diam += v.spacing[c] * v.spacing[c];
+    diam = 2.0 * sqrt(diam);
+    const double gu = fr.sid / dmin * (1.0 + au / dmin), gv = fr.sid / dmin * (1.0 + av / dmin);
+    const double nu = fmin(floor(diam * gu / fr.pitch_u) + 1.0, (double)fr.nu);
+    const double nv = fmin(floor(diam * gv / fr.pitch_v) + 1.0, (double)fr.nv);
+    return ray_weight_bound(v, fr) * nu * nv;
+}
+
 int drr_adjoint_blocks(const VolDims &v) {
     return ((v.n0 + BRICK_X - 1) / BRICK_X) * ((v.n1 + BRICK_Y - 1) / BRICK_Y) *
            ((v.n2 + BRICK_Z - 1) / BRICK_Z);
@@ -944,11 +1048,13 @@ template <typename T, bool FORM_R, int K>
 static void launch_adj(const VolDims &v, const Frame &fr, const void *rays, const void *r_or_p,
                        const void *y, double a, double b, void *bp, const void *f0,
                        const void *mean, const void *U, const WVec &w, double *partials,
-                       uint32_t *counter, double *g_out, hipStream_t s) {
+                       uint32_t *counter, double *g_out, const float *bounds, float *bound_out,
+                       hipStream_t s) {
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
     hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K>), dim3(drr_adjoint_blocks(v)), dim3(256), 0, s,
-                       v, fr, nbx, nby, ray_weight_bound(v, fr), (const RayRec<T> *)rays,
+                       v, fr, nbx, nby, ray_weight_bound(v, fr), backprojection_weight_bound(v, fr),
+                       bounds, bound_out, (const RayRec<T> *)rays,
                        (const T *)r_or_p, (const T *)y, a, b, (T *)bp, (const T *)f0,
                        (const T *)mean, (const T *)U, w, partials, counter, g_out);
 }
@@ -960,18 +1066,32 @@ hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, 
     if (dt == PCAS_F32) {
         if (y)
             launch_adj<float, true, 0>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr,
-                                       w, nullptr, nullptr, nullptr, s);
+                                       w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
         else
             launch_adj<float, false, 0>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr,
-                                        nullptr, nullptr, w, nullptr, nullptr, nullptr, s);
+                                        nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
     } else {
         if (y)
             launch_adj<double, true, 0>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr,
-                                        w, nullptr, nullptr, nullptr, s);
+                                        w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
         else
             launch_adj<double, false, 0>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr,
-                                         nullptr, nullptr, w, nullptr, nullptr, nullptr, s);
+                                         nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                                       const void *rays, float *bound_out, hipStream_t s) {
+    const WVec w{};
+    if (dt == PCAS_F32)
+        launch_adj<float, false, 0>(v, fr, rays, nullptr, nullptr, 0.0, 0.0, nullptr, nullptr,
+                                    nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr,
+                                    bound_out, s);
+    else
+        launch_adj<double, false, 0>(v, fr, rays, nullptr, nullptr, 0.0, 0.0, nullptr, nullptr,
+                                     nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr,
+                                     bound_out, s);
     return hipGetLastError();
 }
 
@@ -979,13 +1099,14 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,
                                     const double *w, double *partials, uint32_t *counter,
-                                    double *g_out, hipStream_t s) {
+                                    double *g_out, const float *bounds, hipStream_t s) {
+    if (dt == PCAS_F32 && !bounds) return hipErrorInvalidValue;
     WVec wv{};
     for (int k = 0; k < K; ++k) wv.w[k] = w[k];
 #define A(TT, KK)                                                                                 \
     case KK:                                                                                      \
         launch_adj<TT, true, KK>(v, fr, rays, p, y, a, b, nullptr, f0, mean, U, wv, partials,     \
-                                 counter, g_out, s);                                              \
+                                 counter, g_out, bounds, nullptr, s);                             \
         break
     if (dt == PCAS_F32) {
         switch (K) { A(float, 1); A(float, 2); A(float, 3); A(float, 4);
@@ -1003,13 +1124,15 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
 AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,
                     const void *y, double a, double b, const void *f0, const void *mean,
                     const void *U, const double *w, double *partials, uint32_t *counter,
-                    double *g_out) {
+                    double *g_out, const float *bounds) {
     AdjJob J;
+    J.bounds = bounds;
     J.vd = v;
     J.fr = fr;
     J.nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     J.nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
     J.hb = ray_weight_bound(v, fr);
+    J.vb = backprojection_weight_bound(v, fr);
     J.rays = rays;
     J.p = p;
     J.y = y;

@@ -29,16 +29,33 @@ struct SolveOp {
     int slot = 0;                 // projection buffer, 0 or 1
 };
 
+// Relative rounding noise of an evaluated J, the band within which two
+// values of J cannot be told apart.  fixed >= 0: that value.  Otherwise a
+// model of the projection's rounding: each p_i carries an error of about
+// u |p_i| (u the unit roundoff of the evaluation's type), which moves
+// J = sum r_i^2 by about 2 u sqrt(sum r_i^2 p_i^2) ~ 2 u sqrt(J sum p_i^2 / M);
+// the band is three of those.  At the fitted (a, b), sum p^2 = a^2 sum y^2 +
+// 2 a b sum y + M b^2 + J exactly (the fit's normal equations make r
+// orthogonal to y and to 1), so the band needs no extra pass.
+struct NoiseModel {
+    double fixed = -1.0;
+    double u = 0.0, M = 1.0, sy = 0.0, syy = 0.0;
+    double rel(double J, double a, double b) const {
+        if (fixed >= 0.0) return fixed;
+        if (!(J > 0.0)) return 0.0;
+        const double sp2 = a * a * syy + 2.0 * a * b * sy + M * b * b + J;
+        return 6.0 * u * sqrt(fmax(sp2, 0.0) / (M * J));
+    }
+};
+
 class SolveMachine {
 public:
     SolveMachine() = default;
 
-    // ftol: noise-floor threshold (opts.ftol_rel, with < 0 resolved by the
-    // caller for the dtype).
-    void start(const pcas_opts &o, int K, double ftol, const double *w0) {
+    void start(const pcas_opts &o, int K, const NoiseModel &noise, const double *w0) {
         o_ = o;
         K_ = K;
-        ftol_ = ftol;
+        noise_ = noise;
         for (int k = 0; k < K; ++k) w_[k] = w0[k];
         memset(&rep_, 0, sizeof(rep_));
         rep_.locate_iters = -1;
@@ -72,7 +89,7 @@ private:
         LS_TRIAL, LS_AFTER_TRIAL, LS_AFTER_EXTRAP,
         CG_START, CG_AFTER_EVAL0, CG_AFTER_GRAD0, CG_LOOP, CG_LS_END, CG_AFTER_GRAD,
         QN_START, QN_AFTER_EVAL0, QN_AFTER_GRAD0, QN_LOOP, QN_LS_END, QN_AFTER_GRAD,
-        SOLVE_FINISH,
+        POLISH, POLISH_AFTER_EVAL, POLISH_AFTER_GRAD, SOLVE_FINISH,
         P_START, P_AFTER_EVAL0, P_LOOP, P_AFTER_RESID, P_GRAD, P_AFTER_GRAD, P_LS, P_AFTER_LS,
         P_END, P_AFTER_FINAL,
         FINISHED
@@ -107,6 +124,38 @@ private:
         op_.slot = slot;
         pc_ = next;
     }
+    // The inverse-Hessian estimate's update after an accepted step s with
+    // gradient change y: scaled identity (y.s / y.y) at the first usable
+    // pair, then the BFGS update expanded for symmetric H; a pair with
+    // y.s <= 1e-12 |s| |y| is skipped.
+    void hessian_update(double *H, bool &have, const double *sv, const double *yv) {
+        const int K = K_;
+        const double sy = dot(sv, yv, K), yy = dot(yv, yv, K);
+        if (!(sy > 1e-12 * sqrt(dot(sv, sv, K)) * sqrt(yy))) return;
+        if (!have) {
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) H[i * PCAS_MAX_K + j] = i == j ? sy / yy : 0.0;
+            have = true;
+        }
+        const double rho = 1.0 / sy;
+        double hy[PCAS_MAX_K];
+        for (int i = 0; i < K; ++i) {
+            double v = 0.0;
+            for (int j = 0; j < K; ++j) v += H[i * PCAS_MAX_K + j] * yv[j];
+            hy[i] = v;
+        }
+        const double c = rho + rho * rho * dot(yv, hy, K);
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j)
+                H[i * PCAS_MAX_K + j] += c * sv[i] * sv[j] - rho * (sv[i] * hy[j] + hy[i] * sv[j]);
+    }
+    // A solve that stops at the noise floor (noise or decrement stop, failed
+    // search) may take the polish step first.
+    void end_at_floor(int status) {
+        rep_.status = status;
+        pc_ = o_.polish ? POLISH : SOLVE_FINISH;
+    }
+
     // Line search along d_ from w_ (phi_ = J(w_), gd_ = g.d_ < 0, dn_ = ||d_||)
     // with first trial step t_; on return to `ret`, ls_ holds the outcome and,
     // when accepted, wt_ / phi_t_ / a_t_ / b_t_ / t_ the accepted point, whose
@@ -163,7 +212,7 @@ private:
                     ls_end(LS_OK, 0);
                     break;
                 }
-                if (fabs(phi_t_ - phi_) <= ftol_ * phi_) {   // below the objective's noise
+                if (fabs(phi_t_ - phi_) <= nu_ * phi_) {   // below the objective's noise
                     ls_end(LS_NOISE, 0);
                     break;
                 }
@@ -194,6 +243,7 @@ private:
                 phi_ = rJ_;
                 a_ = ra_;
                 b_ = rb_;
+                nu_ = noise_.rel(phi_, a_, b_);
                 want_grad(w_, a_, b_, CG_AFTER_GRAD0);
                 return;
             case CG_AFTER_GRAD0:
@@ -206,6 +256,7 @@ private:
                 rep_.gnorm0 = g0_;
                 restart_ = first_ = true;
                 t_prev_ = gd_prev_ = 0.0;
+                have_hc_ = have_h_ = false;
                 it_ = 0;
                 rep_.status = PCAS_STOP_MAXITER;
                 pc_ = CG_LOOP;
@@ -234,14 +285,12 @@ private:
             }
             case CG_LS_END:
                 if (ls_ == LS_NOISE) {
-                    rep_.status = PCAS_STOP_CONVERGED;
-                    pc_ = SOLVE_FINISH;
+                    end_at_floor(PCAS_STOP_CONVERGED);
                     break;
                 }
                 if (ls_ == LS_FAIL) {
                     if (restart_) {
-                        rep_.status = PCAS_STOP_LINESEARCH;
-                        pc_ = SOLVE_FINISH;
+                        end_at_floor(PCAS_STOP_LINESEARCH);
                         break;
                     }
                     for (int k = 0; k < K; ++k) d_[k] = -g_[k];
@@ -249,13 +298,25 @@ private:
                     pc_ = CG_LOOP;
                     break;
                 }
-                for (int k = 0; k < K; ++k) w_[k] = wt_[k];
+                for (int k = 0; k < K; ++k) {
+                    wprev_[k] = w_[k];
+                    w_[k] = wt_[k];
+                }
                 phi_ = phi_t_;
                 a_ = a_t_;
                 b_ = b_t_;
+                nu_ = noise_.rel(phi_, a_, b_);
                 want_grad(w_, a_, b_, CG_AFTER_GRAD, ls_slot_);
                 return;
             case CG_AFTER_GRAD: {
+                if (o_.polish) {   // an estimate for the polish step only
+                    double sv[PCAS_MAX_K], yv[PCAS_MAX_K];
+                    for (int k = 0; k < K; ++k) {
+                        sv[k] = w_[k] - wprev_[k];
+                        yv[k] = rg_[k] - g_[k];
+                    }
+                    hessian_update(Hc_, have_hc_, sv, yv);
+                }
                 double num = 0.0;
                 for (int k = 0; k < K; ++k) num += rg_[k] * (rg_[k] - g_[k]);
                 double beta_pr = num / dot(g_, g_, K);
@@ -290,6 +351,7 @@ private:
                 phi_ = rJ_;
                 a_ = ra_;
                 b_ = rb_;
+                nu_ = noise_.rel(phi_, a_, b_);
                 want_grad(w_, a_, b_, QN_AFTER_GRAD0);
                 return;
             case QN_AFTER_GRAD0:
@@ -297,7 +359,7 @@ private:
                 rep_.J0 = phi_;
                 g0_ = sqrt(dot(g_, g_, K));
                 rep_.gnorm0 = g0_;
-                have_h_ = false;
+                have_h_ = have_hc_ = false;
                 it_ = 0;
                 rep_.status = PCAS_STOP_MAXITER;
                 pc_ = QN_LOOP;
@@ -323,10 +385,9 @@ private:
                     t_ = 1.0;
                     if (gd_ >= 0.0) {
                         have_h_ = false;   // the estimate lost definiteness
-                    } else if (-0.5 * gd_ <= ftol_ * phi_) {
+                    } else if (-0.5 * gd_ <= nu_ * phi_) {
                         // the model's predicted decrease g.H g / 2 is below the noise
-                        rep_.status = PCAS_STOP_CONVERGED;
-                        pc_ = SOLVE_FINISH;
+                        end_at_floor(PCAS_STOP_CONVERGED);
                         break;
                     }
                 }
@@ -341,16 +402,17 @@ private:
             }
             case QN_LS_END:
                 if (ls_ == LS_NOISE) {
-                    rep_.status = PCAS_STOP_CONVERGED;
-                    pc_ = SOLVE_FINISH;
+                    end_at_floor(PCAS_STOP_CONVERGED);
                     break;
                 }
                 if (ls_ == LS_FAIL) {
                     if (!have_h_) {
-                        rep_.status = PCAS_STOP_LINESEARCH;
-                        pc_ = SOLVE_FINISH;
+                        end_at_floor(PCAS_STOP_LINESEARCH);
                         break;
                     }
+                    // keep the estimate for a polish step, then retry along -g
+                    memcpy(Hc_, H_, sizeof(H_));
+                    have_hc_ = true;
                     have_h_ = false;
                     pc_ = QN_LOOP;
                     break;
@@ -363,25 +425,7 @@ private:
                     sv[k] = wt_[k] - w_[k];
                     yv[k] = rg_[k] - g_[k];
                 }
-                const double sy = dot(sv, yv, K), yy = dot(yv, yv, K);
-                if (sy > 1e-12 * sqrt(dot(sv, sv, K)) * sqrt(yy)) {
-                    if (!have_h_) {
-                        for (int i = 0; i < K; ++i)
-                            for (int j = 0; j < K; ++j) H_[i * PCAS_MAX_K + j] = i == j ? sy / yy : 0.0;
-                        have_h_ = true;
-                    }
-                    const double rho = 1.0 / sy;
-                    double hy[PCAS_MAX_K];
-                    for (int i = 0; i < K; ++i) {
-                        double v = 0.0;
-                        for (int j = 0; j < K; ++j) v += H_[i * PCAS_MAX_K + j] * yv[j];
-                        hy[i] = v;
-                    }
-                    const double c = rho + rho * rho * dot(yv, hy, K);
-                    for (int i = 0; i < K; ++i)
-                        for (int j = 0; j < K; ++j)
-                            H_[i * PCAS_MAX_K + j] += c * sv[i] * sv[j] - rho * (sv[i] * hy[j] + hy[i] * sv[j]);
-                }
+                hessian_update(H_, have_h_, sv, yv);
                 for (int k = 0; k < K; ++k) {
                     w_[k] = wt_[k];
                     g_[k] = rg_[k];
@@ -389,10 +433,54 @@ private:
                 phi_ = phi_t_;
                 a_ = a_t_;
                 b_ = b_t_;
+                nu_ = noise_.rel(phi_, a_, b_);
                 ++it_;
                 pc_ = QN_LOOP;
                 break;
             }
+
+            // ---- polish: one step w - H g at the noise floor ----------------
+            // H: BFGS's estimate (or its last one), or CG's from its steps.
+            // The step is kept if ||g|| drops; the gradient resolves the
+            // minimiser far below the noise of J.
+            case POLISH: {
+                const double *H = o_.method == 2 && have_h_ ? H_ : (have_hc_ ? Hc_ : nullptr);
+                if (!H) {
+                    pc_ = SOLVE_FINISH;
+                    break;
+                }
+                double gd = 0.0;
+                for (int i = 0; i < K; ++i) {
+                    double v = 0.0;
+                    for (int j = 0; j < K; ++j) v += H[i * PCAS_MAX_K + j] * g_[j];
+                    wx_[i] = w_[i] - v;
+                    gd -= g_[i] * v;
+                }
+                if (!(gd < 0.0)) {
+                    pc_ = SOLVE_FINISH;
+                    break;
+                }
+                want_eval(wx_, false, 1.0, 0.0, POLISH_AFTER_EVAL, 1);
+                return;
+            }
+            case POLISH_AFTER_EVAL:
+                phi_t_ = rJ_;
+                a_t_ = ra_;
+                b_t_ = rb_;
+                want_grad(wx_, a_t_, b_t_, POLISH_AFTER_GRAD, 1);
+                return;
+            case POLISH_AFTER_GRAD:
+                if (dot(rg_, rg_, K) < dot(g_, g_, K)) {
+                    for (int k = 0; k < K; ++k) {
+                        w_[k] = wx_[k];
+                        g_[k] = rg_[k];
+                    }
+                    phi_ = phi_t_;
+                    a_ = a_t_;
+                    b_ = b_t_;
+                }
+                pc_ = SOLVE_FINISH;
+                break;
 
             case SOLVE_FINISH:
                 rep_.iters = it_;
@@ -495,7 +583,8 @@ private:
 
     pcas_opts o_{};
     int K_ = 0;
-    double ftol_ = 0.0;
+    NoiseModel noise_;
+    double nu_ = 0.0;   // noise band of J at the current point (relative)
     Pc pc_ = FINISHED;
     SolveOp op_;
     pcas_report rep_{};
@@ -503,12 +592,14 @@ private:
     double rJ_ = 0.0, ra_ = 0.0, rb_ = 0.0, rg_[PCAS_MAX_K] = {0};
     // solver state
     double w_[PCAS_MAX_K] = {0}, wt_[PCAS_MAX_K] = {0}, wx_[PCAS_MAX_K] = {0};
+    double wprev_[PCAS_MAX_K] = {0};
     double g_[PCAS_MAX_K] = {0}, d_[PCAS_MAX_K] = {0};
     double H_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // BFGS inverse-Hessian estimate (row-major)
+    double Hc_[PCAS_MAX_K * PCAS_MAX_K] = {0};  // estimate kept for the polish step
     double phi_ = 0.0, a_ = 0.0, b_ = 0.0, phi_t_ = 0.0, a_t_ = 0.0, b_t_ = 0.0;
     double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, tx_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
     double J_ = 0.0, gn_ = 0.0, mu_ = 0.0;
-    bool restart_ = true, first_ = true, have_h_ = false;
+    bool restart_ = true, first_ = true, have_h_ = false, have_hc_ = false;
     int it_ = 0, bt_ = 0, ls_slot_ = 0;
     LsOutcome ls_ = LS_FAIL;
     Pc ls_ret_ = FINISHED;

@@ -15,7 +15,9 @@ typedef void (*harness_grad_fn)(const double *w, int slot, double a, double b, d
 int harness_solve(const pcas_opts *opts, int K, double ftol, const double *w0,
                   harness_eval_fn ev, harness_grad_fn gr, double *w_out, pcas_report *rep) {
     pcas::SolveMachine m;
-    m.start(*opts, K, ftol, w0);
+    pcas::NoiseModel noise;
+    noise.fixed = ftol;
+    m.start(*opts, K, noise, w0);
     int guard = 0;
     while (!m.done()) {
         if (++guard > 100000) return -1;
@@ -34,6 +36,18 @@ int harness_solve(const pcas_opts *opts, int K, double ftol, const double *w0,
     for (int k = 0; k < K; ++k) w_out[k] = m.w()[k];
     *rep = m.report();
     return 0;
+}
+
+// The solver's noise band at one point (the rounding model, or `fixed`).
+double harness_noise_rel(double fixed, double u, double M, double sy, double syy, double J,
+                         double a, double b) {
+    pcas::NoiseModel n;
+    n.fixed = fixed;
+    n.u = u;
+    n.M = M;
+    n.sy = sy;
+    n.syy = syy;
+    return n.rel(J, a, b);
 }
 
 }  // extern "C"

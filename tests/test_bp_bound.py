@@ -1,0 +1,61 @@
+"""The back-projection's per-voxel weight bound (host logic, CPU).
+
+The GPU back-projection sizes its fixed-point accumulators from
+pcas_backprojection_bound: a brick's voxel totals must stay below
+step * max|r| * B.  Here the bound is checked against the exact
+back-projection of an all-ones image computed by the oracle, (P^T 1)(v) =
+sum over rays and samples of dt * weight, on geometries chosen to stress it:
+high magnification (source close to the volume), fine detector pitch,
+detector offsets, anisotropic voxels, steep cone angles and steps above and
+below the voxel size.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1102_1712_amd import binding as B
+from paper_1102_1712_amd import synth
+
+
+def _geom(n, spacing, det, pitch, step, sad=1000.0, sid=1500.0, angle=0.3, offset=(0.0, 0.0)):
+    vol = synth.centred_volume(n, spacing)
+    proj = synth.Projection(angle=angle, sad=sad, sid=sid, nu=det[0], nv=det[1], pitch_u=pitch[0],
+                            pitch_v=pitch[1], offset_u=offset[0], offset_v=offset[1], step=step)
+    return vol, proj
+
+
+GEOMS = {
+    "tiny": _geom((64, 64, 64), (4.0, 4.0, 4.0), (128, 128), (3.0, 3.0), 2.0),
+    "ragged_aniso": _geom((40, 36, 28), (5.0, 6.0, 7.0), (48, 40), (7.0, 8.0), 2.5),
+    "fine_pitch": _geom((24, 24, 16), (2.0, 2.0, 3.0), (160, 120), (0.25, 0.25), 1.0),
+    "close_source": _geom((32, 32, 24), (4.0, 4.0, 4.0), (200, 160), (1.0, 1.0), 2.0,
+                          sad=120.0, sid=300.0, angle=0.9),
+    "steep_cone": _geom((20, 20, 60), (3.0, 3.0, 3.0), (64, 200), (1.5, 1.5), 1.5,
+                        sad=150.0, sid=400.0, angle=2.2),
+    "half_fan": _geom((32, 32, 20), (4.0, 4.0, 5.0), (96, 64), (1.2, 1.2), 2.0,
+                      offset=(40.0, -10.0), angle=4.0),
+    "long_step": _geom((30, 30, 30), (1.0, 1.0, 1.0), (80, 80), (0.5, 0.5), 3.5),
+    "short_step": _geom((30, 26, 22), (3.0, 2.0, 4.0), (64, 48), (2.0, 2.0), 0.3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+def test_backprojection_bound_holds(oracle_lib, name):
+    vol, proj = GEOMS[name]
+    bound = B.backprojection_bound(vol, proj)
+    bp = O.drr_adjoint(vol, proj, np.ones(proj.nu * proj.nv))
+    peak = float(bp.max())
+    assert peak > 0.0
+    assert peak <= proj.step * bound, (name, peak / (proj.step * bound))
+    # not vacuous: within a modest factor of the exact peak
+    assert proj.step * bound <= 200.0 * peak, (name, peak / (proj.step * bound))
+
+
+def test_backprojection_bound_rejects_invalid():
+    vol, proj = GEOMS["tiny"]
+    with pytest.raises(B.PcasError):
+        B.backprojection_bound(vol, dataclasses.replace(proj, step=0.0))
+    with pytest.raises(B.PcasError):
+        B.backprojection_bound(vol, dataclasses.replace(proj, sad=100.0))   # source inside

@@ -419,14 +419,18 @@ def test_solver_monotone(solver):
 
 
 class _Quadratic:
-    """phi(w) = w.A w / 2 - c.w + 10 in the solvers' problem interface, with
-    (a, b) reported as (1, 0): its minimiser is A^-1 c in closed form."""
+    """phi(w) = (w - w*).A (w - w*) / 2 + 10 with w* = A^-1 c, in the solvers'
+    problem interface, with (a, b) reported as (1, 0): its minimiser is
+    A^-1 c in closed form, its gradient A w - c, and phi >= 10 > 0 (the
+    noise band is relative to phi)."""
 
     def __init__(self, A, c):
         self.A, self.c = A, c
+        self.ws = np.linalg.solve(A, c)
 
     def objective(self, w):
-        return float(0.5 * w @ self.A @ w - self.c @ w + 10.0), 1.0, 0.0, None
+        e = w - self.ws
+        return float(0.5 * e @ self.A @ e + 10.0), 1.0, 0.0, None
 
     def gradient(self, w, r):
         return self.A @ w - self.c
@@ -507,6 +511,30 @@ def test_bfgs_decrement_stop():
         assert rep.status == O.STOP_CONVERGED
         assert 0.0 <= rep.J - phi_star <= 4e-6 * rep.J
         assert rep.n_fevals < rep_f.n_fevals
+
+
+def test_polish_step_on_quadratics():
+    """SolveOptions.polish: a solve stopped at a coarse noise band (ftol_rel
+    = 1e-6) takes one step w - H g.  On a quadratic, with H from the
+    solver's own BFGS updates (CG keeps one from its steps), the step lands
+    far closer to A^-1 c than the stop did; it costs one evaluation and one
+    gradient."""
+    rng = np.random.default_rng(44)
+    cases = ((3, 10.0, O.solve_cg), (8, 1e3, O.solve_bfgs))
+    for K, kappa, solver in cases:
+        A, _ = _spd(rng, K, kappa)
+        c = 3.0 * rng.normal(size=K)
+        ws = np.linalg.solve(A, c)
+        q = _Quadratic(A, c)
+        o = dict(ftol_rel=1e-6, gtol_rel=0.0, max_iter=200)
+        w0, r0 = solver(q, np.zeros(K), O.SolveOptions(**o))
+        w1, r1 = solver(q, np.zeros(K), O.SolveOptions(polish=True, **o))
+        e0 = np.linalg.norm(w0 - ws) / np.linalg.norm(ws)
+        e1 = np.linalg.norm(w1 - ws) / np.linalg.norm(ws)
+        assert r0.status == O.STOP_CONVERGED and r1.status == O.STOP_CONVERGED
+        assert e1 <= 0.1 * e0, (K, e0, e1)
+        assert (r1.n_fevals, r1.n_grads) == (r0.n_fevals + 1, r0.n_grads + 1)
+        assert r1.gnorm < r0.gnorm
 
 
 def test_bfgs_and_cg_agree_on_noisy_small():

@@ -35,6 +35,8 @@ def harness(tmp_path_factory):
                     "-I", os.path.join(ROOT, "paper_1102_1712_amd", "csrc"), src, "-o", out],
                    check=True)
     lib = ctypes.CDLL(out)
+    lib.harness_noise_rel.restype = ctypes.c_double
+    lib.harness_noise_rel.argtypes = [ctypes.c_double] * 8
     lib.harness_solve.restype = ctypes.c_int
     lib.harness_solve.argtypes = [ctypes.POINTER(B.Opts), ctypes.c_int, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_double), EVAL, GRAD,
@@ -79,11 +81,15 @@ def _machine_solve(lib, prob, K, w0, opts: B.Opts, ftol):
 
 
 class _Quadratic:
+    """(w - w*).A (w - w*) / 2 + 10, w* = A^-1 c: phi > 0 at every point."""
+
     def __init__(self, A, c):
         self.A, self.c = A, c
+        self.ws = np.linalg.solve(A, c)
 
     def objective(self, w):
-        return float(0.5 * w @ self.A @ w - self.c @ w + 10.0), 1.0, 0.0, None
+        e = w - self.ws
+        return float(0.5 * e @ self.A @ e + 10.0), 1.0, 0.0, None
 
     def gradient(self, w, r):
         return self.A @ w - self.c
@@ -106,7 +112,7 @@ def _oracle_opts(o: B.Opts):
     return O.SolveOptions(method=o.method, max_iter=o.max_iter, max_backtracks=o.max_backtracks,
                           mu0=o.mu0, alpha=o.alpha, beta=o.beta, mu_min=o.mu_min,
                           gtol_rel=o.gtol_rel, beta_lo=o.beta_lo, xtol=o.xtol,
-                          ftol_rel=o.ftol_rel, ls_extrap=o.ls_extrap)
+                          ftol_rel=o.ftol_rel, ls_extrap=o.ls_extrap, polish=bool(o.polish))
 
 
 def _compare(lib, prob, K, w0, o, rtol):
@@ -185,3 +191,51 @@ def test_machine_matches_oracle_on_small_problem(harness, oracle_lib, method):
     prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y)
     rep, acc = _compare(harness, prob, c.K, np.zeros(c.K), _opts(method), 1e-9)
     assert rep.status == O.STOP_CONVERGED
+
+
+@pytest.mark.parametrize("method,K,kappa,seed", [(1, 3, 10.0, 6), (1, 5, 100.0, 7),
+                                                 (2, 3, 10.0, 6), (2, 8, 1e3, 7)])
+def test_machine_polish_matches_oracle(harness, method, K, kappa, seed):
+    """The polish step after a stop at a coarse noise band: same steps,
+    same final point as the oracle."""
+    rng = np.random.default_rng(300 + seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
+    A = Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T
+    c = 3.0 * rng.normal(size=K)
+    o = _opts(method, ftol_rel=1e-6, gtol_rel=0.0, max_iter=200, polish=1)
+    rep, _ = _compare(harness, _Quadratic(A, c), K, np.zeros(K), o, 1e-9 if kappa <= 10.0 else 1e-6)
+    assert rep.status in (O.STOP_CONVERGED, O.STOP_LINESEARCH)   # both end at the band
+
+
+def test_noise_model_identity_and_band(harness, oracle_lib):
+    """The noise band of J.  (1) sum p^2 from the fit's identity
+    a^2 sum y^2 + 2 a b sum y + M b^2 + J equals the direct sum at the fitted
+    (a, b).  (2) Rounding the projection to float32 at many points a hair
+    apart moves J by a spread the FP32 band covers, within a modest factor."""
+    c = synth.small(seed=6)
+    y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
+    prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y)
+    w = c.w_star + 0.01
+    J, a, b, r = prob.objective(w)
+    p = (r + a * y + b).reshape(-1)
+    yv = y.reshape(-1)
+    M = float(p.size)
+    u32 = 2.0 ** -24
+    band = harness.harness_noise_rel(-1.0, u32, M, float(yv.sum()), float(yv @ yv), J, a, b)
+    want = 6.0 * u32 * np.sqrt(float(p @ p) / (M * J))
+    assert band == pytest.approx(want, rel=1e-10)
+    assert harness.harness_noise_rel(2.5e-7, u32, M, 1.0, 1.0, J, a, b) == 2.5e-7
+    # Spread of J when p is rounded to float32 at points a hair apart: scale p
+    # by 1 + e_i (|e_i| ~ 1e-6 reshuffles the rounded bits), take J_i, and
+    # remove J's smooth change with e_i by a least-squares line in e_i.
+    rng = np.random.default_rng(8)
+    e = 1e-6 * rng.standard_normal(200)
+    Js = np.empty(e.size)
+    for i, ei in enumerate(e):
+        p32 = (p * (1.0 + ei)).astype(np.float32).astype(np.float64)
+        rr = p32 - a * yv - b
+        Js[i] = float(rr @ rr)
+    coef = np.polyfit(e, Js, 2)
+    spread = float(np.std(Js - np.polyval(coef, e)))
+    assert spread > 0.0
+    assert spread <= band * J <= 30.0 * spread, (spread / J, band)
