@@ -39,7 +39,7 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # volumes at once: position and fractions once (9), then 22 per volume.
 def flops_per_sample(kernel: str, K: int) -> float:
     return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_adjoint_chain": 34.0,
-            "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
+            "adjoint_bounds": 34.0, "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
 
 
 # Jacobian chain per voxel: field 6K, displacement split 6, Eq. A.8 and its
@@ -48,10 +48,18 @@ def chain_flops_per_voxel(K: int) -> float:
     return 12.0 * K + 51.0
 
 
-SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot")
+SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot",
+                  "adjoint_bounds")
 KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
                   "drr_adjoint_chain": "k_drr.hip", "drr_forward_dot": "k_drr.hip",
+                  "adjoint_bounds": "k_drr.hip",
                   "warp_pca": "k_warp.hip", "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
+
+
+def drr_bricks(vol) -> int:
+    """Bricks of the back-projection (16 x 16 x 8 voxels each)."""
+    n = vol.n
+    return -(-n[0] // 16) * -(-n[1] // 16) * -(-n[2] // 8)
 
 
 def kernel_digest(kernel: str) -> str:
@@ -664,6 +672,7 @@ def main() -> int:
         "drr_forward": es * N + 32 * M + 2 * es * M,
         "drr_adjoint": es * N + 32 * M + 2 * es * M,
         "drr_adjoint_chain": (3 + 3 * K + 1) * es * N + 32 * M + 2 * es * M,
+        "adjoint_bounds": 32 * M + 4 * drr_bricks(case.vol),
         "drr_forward_dot": K * es * N + 32 * M + 2 * es * M,
     }
     kernel_stats = {}

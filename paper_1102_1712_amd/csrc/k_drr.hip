@@ -979,6 +979,20 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
                                     partials, counter, g_out, blockIdx.x, gridDim.x);
 }
 
+// The per-brick maxima of the all-ones image's back-projection (the scale
+// source of the FP32 gradient's 32-bit accumulators); its own entry so that
+// traces tell it from drr_adjoint.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint_bounds(VolDims vd, Frame fr, int nbx, int nby,
+                                                        double hb, double vb,
+                                                        const RayRec<T> *__restrict__ rays,
+                                                        float *__restrict__ bound_out) {
+    const WVec w{};
+    drr_adjoint_block<T, false, 0>(vd, fr, nbx, nby, hb, vb, nullptr, bound_out, rays, nullptr,
+                                   nullptr, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr, w,
+                                   nullptr, nullptr, nullptr, blockIdx.x, gridDim.x);
+}
+
 // Several requests' gradients (back-projection + chain) in one launch.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_drr_adjoint_batch(const AdjJob *__restrict__ jobs,
@@ -1083,15 +1097,15 @@ hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, 
 
 hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const Frame &fr,
                                        const void *rays, float *bound_out, hipStream_t s) {
-    const WVec w{};
+    const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
+    const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
+    const double hb = ray_weight_bound(v, fr), vb = backprojection_weight_bound(v, fr);
     if (dt == PCAS_F32)
-        launch_adj<float, false, 0>(v, fr, rays, nullptr, nullptr, 0.0, 0.0, nullptr, nullptr,
-                                    nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr,
-                                    bound_out, s);
+        hipLaunchKernelGGL((k_adjoint_bounds<float>), dim3(drr_adjoint_blocks(v)), dim3(256), 0, s,
+                           v, fr, nbx, nby, hb, vb, (const RayRec<float> *)rays, bound_out);
     else
-        launch_adj<double, false, 0>(v, fr, rays, nullptr, nullptr, 0.0, 0.0, nullptr, nullptr,
-                                     nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr,
-                                     bound_out, s);
+        hipLaunchKernelGGL((k_adjoint_bounds<double>), dim3(drr_adjoint_blocks(v)), dim3(256), 0,
+                           s, v, fr, nbx, nby, hb, vb, (const RayRec<double> *)rays, bound_out);
     return hipGetLastError();
 }
 
