@@ -724,3 +724,20 @@ def test_siddon_matches_fine_riemann_sum():
         vals[ok] = f[q[ok, 2], q[ok, 1], q[ok, 0]]
         riemann = vals.sum() * np.linalg.norm(d) / m
         assert abs(riemann - p[r]) <= 1e-3 * max(abs(p[r]), 1e-9) + 1e-6
+
+
+@pytest.mark.slow
+def test_clinical_golden_is_stationary():
+    """tests/golden/clinical_minimiser.json (the GPU full-size solve parity
+    reference) is a minimiser of the current oracle's clinical objective:
+    its gradient is below 1e-5 of the gradient at w = 0, for both fit modes."""
+    gold = json.load(open(os.path.join(GOLDEN, "clinical_minimiser.json")))
+    c = synth.clinical()
+    assert gold["workload"] == c.name and gold["angle"] == c.proj.angle
+    y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
+    y = y.astype(np.float32).astype(np.float64)
+    for key, fit in (("fit", True), ("nofit", False)):
+        prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y, fit_intensity=fit)
+        g = prob.gradient(np.array(gold[key]["w"]), prob.objective(np.array(gold[key]["w"]))[3])
+        g0 = prob.gradient(np.zeros(c.K), prob.objective(np.zeros(c.K))[3])
+        assert np.linalg.norm(g) <= 1e-5 * np.linalg.norm(g0), key
