@@ -328,7 +328,7 @@ def serve_mode(args) -> int:
     opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method]) for m in range(2)}
     Ks = {m: cases[m].K for m in range(2)}
 
-    def new_server():
+    def new_server(share=args.substep_share):
         srv0 = B.Server(B.Server.reserved_bytes(args.slots) + (64 << 20), max_active=args.slots)
         for c, d in zip(cases, devs):
             srv0.add_model(c.vol, d["f0"], d["mean"], d["U"])
@@ -336,19 +336,23 @@ def serve_mode(args) -> int:
         srv0.close()
         srv = B.Server(B.Server.reserved_bytes(args.slots) + args.slots * need + (1 << 20),
                        max_active=args.slots)
+        srv.set_substep_share(share)
         for c, d in zip(cases, devs):
             srv.add_model(c.vol, d["f0"], d["mean"], d["U"])
         return srv, need
 
     out = {"mode": "serve", "requests": n, "rate_hz": args.rate, "slots": args.slots,
+           "substep_share": args.substep_share,
            "models": [{"workload": c.name, "volume": list(c.vol.n), "K": c.K,
                        "detector": [c.proj.nu, c.proj.nv], "pitch_mm": c.proj.pitch_u,
                        "step_mm": c.proj.step} for c in cases],
            "data": "synthetic (measured images from the same forward model, 1% noise)"}
     # warm-started serving run (the configuration), then the zero-start pair
     runs = {}
-    for label, warm in (("served_warm", True), ("served_zero", False)):
-        srv, need = new_server()
+    for label, warm, share in (("served_warm", True, args.substep_share),
+                               ("served_zero", False, args.substep_share),
+                               ("served_warm_one_pass", True, 0.0)):
+        srv, need = new_server(share)
         out["arena_bytes"] = int(srv.arena.numel())
         out["request_bytes_max"] = int(need)
         SV.run(srv, arrivals[:2], opts, Ks, warm=warm)          # warm the kernels up
@@ -598,6 +602,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=32)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--substep-share", type=float, default=0.25,
+                    help="serving: extra passes for cheap requests, share of the main pass")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

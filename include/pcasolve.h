@@ -334,7 +334,15 @@ size_t pcas_server_request_bytes(pcas_server *server, int32_t model_id, const pc
 int pcas_server_submit(pcas_server *server, int32_t model_id, const pcas_proj *proj,
                        const void *y, const double *w0, const pcas_opts *opts,
                        int64_t *request_id);
+/* One step: admits what fits, runs one operation of every admitted request
+ * (a main pass), then extra passes for the cheap requests, those whose
+ * operation costs at most a quarter of the most expensive admitted one's
+ * (estimated as N + M * volume diagonal / step), while the extra passes'
+ * summed cost stays within substep_share (default 0.25) of the main pass's.
+ * A request's result does not depend on the passes it ran in. */
 int pcas_server_step(pcas_server *server, int32_t *n_completed);
+/* share in [0, 16]; 0 gives one pass per step. */
+int pcas_server_set_substep_share(pcas_server *server, double share);
 /* *done = 1 and the request's status (PCAS_OK or the error that ended it)
  * once it has completed, with w_out (host double[K], may be NULL) and
  * report (may be NULL) filled; the request is then forgotten.  *done = 0

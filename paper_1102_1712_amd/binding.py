@@ -29,7 +29,8 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "objective_gradient", "solve_projection_workspace", "solve_projection",
            "pcas_server_reserved_bytes", "pcas_server_create", "pcas_server_destroy",
            "pcas_server_add_model", "pcas_server_request_bytes", "pcas_server_submit",
-           "pcas_server_step", "pcas_server_poll", "pcas_server_stats")
+           "pcas_server_step", "pcas_server_set_substep_share", "pcas_server_poll",
+           "pcas_server_stats")
 
 
 class PcasError(RuntimeError):
@@ -128,6 +129,7 @@ def lib():
             "pcas_server_request_bytes": (SZ, [P, I32, PP]),
             "pcas_server_submit": (I32, [P, I32, PP, P, DP, ctypes.POINTER(Opts),
                                          ctypes.POINTER(I64)]),
+            "pcas_server_set_substep_share": (I32, [P, D]),
             "pcas_server_step": (I32, [P, ctypes.POINTER(I32)]),
             "pcas_server_poll": (I32, [P, I64, DP, ctypes.POINTER(Report), ctypes.POINTER(I32)]),
             "pcas_server_stats": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -520,6 +522,12 @@ class Server:
         n = ctypes.c_int32()
         _check(lib().pcas_server_step(self._h, ctypes.byref(n)), "pcas_server_step")
         return int(n.value)
+
+    def set_substep_share(self, share: float) -> None:
+        """Extra passes for cheap requests per step, as a share of the main
+        pass's estimated cost (0 = one pass per step)."""
+        _check(lib().pcas_server_set_substep_share(self._h, float(share)),
+               "pcas_server_set_substep_share")
 
     def poll(self, request_id: int):
         """(done, status, w, report dict); status is 0 or the request's error

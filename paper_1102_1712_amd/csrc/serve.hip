@@ -59,6 +59,7 @@ struct Request {
     int status = PCAS_OK;
     double w[PCAS_MAX_K] = {0};
     pcas_report rep{};
+    double cost = 0.0;   // relative GPU work of one of its operations (see op_cost)
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -132,6 +133,7 @@ struct pcas_server {
     std::vector<Request *> active;
     std::map<int64_t, Request *> finished;
     int64_t next_id = 1;
+    double substep_share = 0.25;      // extra passes for cheap requests (see step)
 };
 
 namespace {
@@ -200,30 +202,20 @@ struct Groups {
     }
 };
 
-int step(pcas_server *S, int32_t *n_done) {
-    *n_done = 0;
-    // 1. admission: every pending request that fits, in arrival order
-    for (auto it = S->pending.begin(); it != S->pending.end() && (int)S->active.size() < S->max_active;) {
-        Request *r = *it;
-        if (!S->pool.alloc(r->L.total, &r->off)) {
-            ++it;
-            continue;
-        }
-        int st = admit(S, r);
-        if (st) return st;
-        S->active.push_back(r);
-        it = S->pending.erase(it);
-    }
-    if (S->active.empty()) return PCAS_OK;
+// One pass: the next operation of every request in `set`, batched by kind
+// (one launch per kind, dtype and K or slab axis), one read-back, and every
+// machine advanced.  Finished requests leave with phase PH_DONE.
+int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done) {
+    if (set.empty()) return PCAS_OK;
 
-    // 2. this step's operations, batched
+    // this pass's operations, batched
     typedef std::pair<int, int> DK;   // (dtype, K) or (dtype, axis)
     Groups<WarpJob, DK> warps;
     Groups<FwdJob, DK> fwds;
     Groups<ResJob, int> ress;
     Groups<AdjJob, DK> adjs;
     std::vector<Request *> locates;
-    for (Request *r : S->active) {
+    for (Request *r : set) {
         const Model &md = S->models[r->model];
         if (r->phase == PH_LOCATE) {
             locates.push_back(r);
@@ -276,7 +268,7 @@ int step(pcas_server *S, int32_t *n_done) {
         }
     }
     // tables: [warp jobs][fwd jobs][res jobs][adj jobs][gather pointers][gather out]
-    const int na = (int)S->active.size();
+    const int na = (int)set.size();
     char *h = S->tables_host;
     size_t o = 0;
     auto carve = [&](size_t bytes) {
@@ -293,7 +285,7 @@ int step(pcas_server *S, int32_t *n_done) {
     const size_t o_a = carve(adjs.items.size() * sizeof(AdjJob));
     adjs.emit((AdjJob *)(h + o_a));
     const size_t o_p = carve(na * sizeof(double *));
-    for (int i = 0; i < na; ++i) ((const double **)(h + o_p))[i] = S->active[i]->scal();
+    for (int i = 0; i < na; ++i) ((const double **)(h + o_p))[i] = set[i]->scal();
     const size_t o_g = carve(na * GATHER * sizeof(double));
     if (o > S->tables_bytes) return hip_fail(hipErrorInvalidValue, "serving tables overflow");
     HIPCHK(hipMemcpyAsync(S->tables_dev, h, o_g, hipMemcpyHostToDevice, S->s));
@@ -323,10 +315,9 @@ int step(pcas_server *S, int32_t *n_done) {
                           hipMemcpyDeviceToHost, S->s));
     HIPCHK(hipStreamSynchronize(S->s));
 
-    // 3. advance every request with its results
-    std::vector<Request *> still;
+    // advance every request of the pass with its results
     for (int i = 0; i < na; ++i) {
-        Request *r = S->active[i];
+        Request *r = set[i];
         const double *sc = S->gather_host + i * GATHER;
         const Model &md = S->models[r->model];
         bool done = false;
@@ -385,16 +376,77 @@ int step(pcas_server *S, int32_t *n_done) {
             done = true;
         }
         if (done) {
-            finish_request(S, r, status);
+            finish_request(S, r, status);   // phase becomes PH_DONE
             ++*n_done;
-        } else {
-            still.push_back(r);
         }
     }
-    S->active.swap(still);
     return PCAS_OK;
 }
 
+
+// Relative work of one operation of a request: its warp streams the volume
+// (N voxels) and its projection marches about M * diagonal / step samples.
+double op_cost(const Model &md, const Request &r) {
+    double diag = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double e = (md.vol.n[c] - 1) * md.vol.spacing[c];
+        diag += e * e;
+    }
+    return (double)nvox_of(&md.vol) + (double)r.M * sqrt(diag) / r.proj.step;
+}
+
+int step(pcas_server *S, int32_t *n_done) {
+    *n_done = 0;
+    // 1. admission: every pending request that fits, in arrival order
+    for (auto it = S->pending.begin(); it != S->pending.end() && (int)S->active.size() < S->max_active;) {
+        Request *r = *it;
+        if (!S->pool.alloc(r->L.total, &r->off)) {
+            ++it;
+            continue;
+        }
+        int st = admit(S, r);
+        if (st) return st;
+        r->cost = op_cost(S->models[r->model], *r);
+        S->active.push_back(r);
+        it = S->pending.erase(it);
+    }
+
+    if (S->active.empty()) return PCAS_OK;
+
+    // main pass: every admitted request
+    int st = run_pass(S, S->active, n_done);
+    if (st) return st;
+    // extra passes for the cheap requests (operation cost at most a quarter of
+    // the most expensive one's) while their summed cost stays within
+    // substep_share of the main pass's: small requests then advance several
+    // operations while large ones advance one, instead of waiting out every
+    // large step.
+    if (S->substep_share > 0.0) {
+        double main_cost = 0.0, max_cost = 0.0;
+        for (Request *r : S->active) {
+            main_cost += r->cost;
+            max_cost = fmax(max_cost, r->cost);
+        }
+        double spent = 0.0;
+        for (int pass = 0; pass < 64; ++pass) {
+            std::vector<Request *> small;
+            double c = 0.0;
+            for (Request *r : S->active)
+                if ((r->phase == PH_RUN || r->phase == PH_LOCATE) && r->cost <= 0.25 * max_cost) {
+                    small.push_back(r);
+                    c += r->cost;
+                }
+            if (small.empty() || spent + c > S->substep_share * main_cost) break;
+            if ((st = run_pass(S, small, n_done))) return st;
+            spent += c;
+        }
+    }
+    std::vector<Request *> still;
+    for (Request *r : S->active)
+        if (r->phase != PH_DONE) still.push_back(r);
+    S->active.swap(still);
+    return PCAS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -513,6 +565,12 @@ int pcas_server_poll(pcas_server *S, int64_t request_id, double *w_out, pcas_rep
     delete r;
     *done = 1;
     return status;
+}
+
+int pcas_server_set_substep_share(pcas_server *S, double share) {
+    if (!S || !(share >= 0.0 && share <= 16.0)) return PCAS_EINVAL;
+    S->substep_share = share;
+    return PCAS_OK;
 }
 
 int pcas_server_stats(pcas_server *S, int32_t *n_pending, int32_t *n_active, size_t *arena_used) {

@@ -222,5 +222,6 @@ def test_server_validation(L):
     assert small > 0 and L.pcas_server_reserved_bytes(0) == 0
     assert L.pcas_server_create(FAKE, small, 4, None, ctypes.byref(out)) == EWS
     assert L.pcas_server_step(None, None) == EINVAL
+    assert L.pcas_server_set_substep_share(None, 0.25) == EINVAL
     assert L.pcas_server_destroy(None) == EINVAL
     assert L.pcas_server_request_bytes(None, 0, None) == 0

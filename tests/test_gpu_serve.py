@@ -48,7 +48,10 @@ def _opts(c):
     return B.default_opts(xtol=xtol, locate=1, c0_mm=tuple(c.tumour_c0))
 
 
-def test_batched_results_equal_alone(torch):
+@pytest.mark.parametrize("share", [0.25, 0.0, 4.0])
+def test_batched_results_equal_alone(torch, share):
+    """Every request's result equals its solve alone, bit for bit, whatever
+    the passes it ran in (one per step, or extra passes for cheap ones)."""
     cases = _models()
     devs = [Dev(c) for c in cases]
     reqs = _requests(cases, devs, 3)
@@ -65,6 +68,7 @@ def test_batched_results_equal_alone(torch):
             o.method = 2
         opts.append(o)
     srv = B.Server(256 << 20, max_active=16)
+    srv.set_substep_share(share)
     mids = [srv.add_model(c.vol, d.f0, d.mean, d.U) for c, d in zip(cases, devs)]
     assert mids == [0, 1, 2]
     say("serving", len(reqs), "requests of 3 models")
