@@ -95,6 +95,20 @@ def test_clinical_k5_f32_projected(torch):
     assert np.linalg.norm(g - g_o) <= 1e-4 * np.linalg.norm(g_o)
 
 
+@pytest.mark.parametrize("K", [1, 8])
+def test_small_f32_extreme_K(torch, K):
+    """FP32 with the fewest and the most modes: the back-projection route
+    (32-bit accumulators sized by the per-brick bounds) against the oracle
+    and against the projected-Jacobian route, on the ragged 40x36x28 case
+    (bricks cut by every face) at a point off the minimiser."""
+    c = synth.small(dtype="f32", seed=9, K=K)
+    d = Dev(c)
+    y = measured(c)
+    w = c.w_star + 0.2 * np.linspace(-1.0, 1.0, K)
+    g0, g1 = _check(c, d, y, w, True, 1e-4, 1e-5)
+    assert np.linalg.norm(g0 - g1) <= 1e-5 * np.linalg.norm(g1)
+
+
 def test_solve_same_by_either_route(torch):
     """FP64 small solve: both gradient routes converge to the same w."""
     c = synth.small(dtype="f64", seed=5)
