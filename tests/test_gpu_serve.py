@@ -56,7 +56,8 @@ def test_batched_results_equal_alone(torch, share):
     devs = [Dev(c) for c in cases]
     reqs = _requests(cases, devs, 3)
     # one request of model 0 runs the Appendix algorithm, one without the
-    # fit, two with the quasi-Newton solver
+    # fit, two with the quasi-Newton solver, two with the polish step (which
+    # evaluates into the second projection slot)
     opts = []
     for i, (m, pj, y) in enumerate(reqs):
         o = _opts(cases[m])
@@ -66,6 +67,8 @@ def test_batched_results_equal_alone(torch, share):
             o.fit_intensity = 0
         if i in (2, 6):
             o.method = 2
+        if i in (5, 6):
+            o.polish = 1
         opts.append(o)
     srv = B.Server(256 << 20, max_active=16)
     srv.set_substep_share(share)
