@@ -116,7 +116,9 @@ typedef struct {
     double ftol_rel;       /* methods 1, 2: the noise band of J (relative): a rejected trial
                               with |J_t - J| <= ftol_rel J ends the solve as converged, and
                               method 2 also ends, converged, when its model predicts a
-                              decrease g.H g / 2 <= ftol_rel J.  < 0 (default): a rounding
+                              decrease g.H g / 2 <= ftol_rel J while trusting its model (the
+                              last step's decrease was also <= ftol_rel J, or within a factor
+                              2 of the model's prediction for that unit step).  < 0 (default): a rounding
                               model per point, 6 u sqrt(sum p^2 / (M J)) with u = 2^-24 for
                               PCAS_F32 and 2^-53 for PCAS_F64 (three times the spread of J
                               that rounding each p_i by u |p_i| produces) */

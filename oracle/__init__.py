@@ -437,9 +437,12 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
 
     phi's gradient is dJ/dw at the fitted (a, b) (the fit is an exact
     minimiser, Eq. A.1).  The first trial step is mu0/||d|| on the first
-    iteration and t_prev (g_prev.d_prev) / (g.d) afterwards, searched with
-    _line_search.  A failed search restarts along -g once; a second failure
-    ends the solve."""
+    iteration; afterwards it minimises the quadratic model along d with the
+    curvature the last accepted step measured, c = (s.y) / (s.s) for the
+    step s and gradient change y: t = -(g.d) / (c ||d||^2), or, when s.y <= 0,
+    t_prev (g_prev.d_prev) / (g.d).  It is searched with _line_search.  A
+    failed search restarts along -g once; a second failure ends the
+    solve."""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
     rep = SolveReport()
@@ -453,6 +456,7 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     d = -g
     restart, first = True, True
     t_prev = gd_prev = 0.0
+    curv = 0.0                                         # (s.y) / (s.s) of the last accepted step
     H = None                                           # for the polish step only
     floor = False                                      # ended at the noise floor
     it = 0
@@ -467,7 +471,12 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             d = -g
             gd = -gn * gn
             restart = True
-        t = o.mu0 / float(np.linalg.norm(d)) if first else t_prev * gd_prev / gd
+        if first:
+            t = o.mu0 / float(np.linalg.norm(d))
+        elif curv > 0.0:
+            t = -gd / (curv * float(d @ d))
+        else:
+            t = t_prev * gd_prev / gd
         st, t, w_t, phi_t, a_t, b_t, r_t, n = _line_search(prob, o, w, phi, d, gd, t)
         rep.n_fevals += n
         if st == "noise":
@@ -484,8 +493,11 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             continue
         g_new = prob.gradient(w_t, r_t)
         rep.n_grads += 1
+        s_k, y_k = w_t - w, g_new - g
+        ss = float(s_k @ s_k)
+        curv = float(s_k @ y_k) / ss if ss > 0.0 else 0.0
         if o.polish:
-            H = _hessian_update(H, w_t - w, g_new - g)
+            H = _hessian_update(H, s_k, y_k)
         w, phi, a, b, r = w_t, phi_t, a_t, b_t, r_t
         beta_pr = max(0.0, float(g_new @ (g_new - g)) / float(g @ g))
         d = -g_new + beta_pr * d
@@ -554,7 +566,10 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     with an estimate resets it and retries along -g; a failed search along
     -g ends the solve.  With an estimate, the solve also ends (converged)
     when the decrease the quadratic model predicts, g.H g / 2, is within
-    ftol_rel of J: what is left lies below the objective's noise."""
+    ftol_rel of J and the model is trusted: the last accepted step's decrease
+    was within ftol_rel of J as well, or, for a unit quasi-Newton step, within
+    a factor 2 of the g.H g / 2 predicted for it.  (The prediction alone can
+    be far too small while H still underestimates flat directions.)"""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
     rep = SolveReport()
@@ -567,6 +582,8 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     g0 = float(np.linalg.norm(g))
     H = None
     H_last = None                                      # last estimate, for the polish step
+    last_drop = float("inf")                           # J decrease of the last accepted step
+    last_pred = -1.0                                   # the model's prediction of it (< 0: none)
     floor = False
     it = 0
     rep.status = STOP_MAXITER
@@ -581,7 +598,11 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             t = 1.0
             if gd >= 0.0:                                  # estimate lost definiteness
                 H = None
-            elif -0.5 * gd <= o.ftol_rel * phi:           # predicted decrease below the noise
+            elif -0.5 * gd <= o.ftol_rel * phi and (
+                    last_drop <= o.ftol_rel * phi or 0.5 * last_pred <= last_drop <= 2.0 * last_pred):
+                # the decrease the model still predicts is below the noise, and
+                # the model is trusted: the last step's decrease was below the
+                # noise too, or within a factor 2 of the model's prediction
                 rep.status = STOP_CONVERGED
                 floor = True
                 break
@@ -604,7 +625,11 @@ def solve_bfgs(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             continue
         g_new = prob.gradient(w_t, r_t)
         rep.n_grads += 1
+        # the quadratic model's decrease at the accepted step, when it took
+        # the unit quasi-Newton step (phi(w + d) ~ phi + g.d - g.d / 2)
+        last_pred = -0.5 * gd if (H is not None and t == 1.0) else -1.0
         H = _hessian_update(H, w_t - w, g_new - g)
+        last_drop = phi - phi_t
         w, phi, a, b, g = w_t, phi_t, a_t, b_t, g_new
         it += 1
         rep.J_trace.append(phi)

@@ -256,6 +256,7 @@ private:
                 rep_.gnorm0 = g0_;
                 restart_ = first_ = true;
                 t_prev_ = gd_prev_ = 0.0;
+                curv_ = 0.0;
                 have_hc_ = have_h_ = false;
                 it_ = 0;
                 rep_.status = PCAS_STOP_MAXITER;
@@ -279,7 +280,14 @@ private:
                     restart_ = true;
                 }
                 dn_ = sqrt(dot(d_, d_, K));
-                t_ = first_ ? o_.mu0 / dn_ : t_prev_ * gd_prev_ / gd_;
+                // first trial: the quadratic model's minimiser along d with the
+                // curvature the last accepted step measured, (s.y) / (s.s)
+                if (first_)
+                    t_ = o_.mu0 / dn_;
+                else if (curv_ > 0.0)
+                    t_ = -gd_ / (curv_ * dn_ * dn_);
+                else
+                    t_ = t_prev_ * gd_prev_ / gd_;
                 line_search(CG_LS_END);
                 break;
             }
@@ -309,13 +317,15 @@ private:
                 want_grad(w_, a_, b_, CG_AFTER_GRAD, ls_slot_);
                 return;
             case CG_AFTER_GRAD: {
-                if (o_.polish) {   // an estimate for the polish step only
+                {
                     double sv[PCAS_MAX_K], yv[PCAS_MAX_K];
                     for (int k = 0; k < K; ++k) {
                         sv[k] = w_[k] - wprev_[k];
                         yv[k] = rg_[k] - g_[k];
                     }
-                    hessian_update(Hc_, have_hc_, sv, yv);
+                    const double ss = dot(sv, sv, K);
+                    curv_ = ss > 0.0 ? dot(sv, yv, K) / ss : 0.0;
+                    if (o_.polish) hessian_update(Hc_, have_hc_, sv, yv);   // polish only
                 }
                 double num = 0.0;
                 for (int k = 0; k < K; ++k) num += rg_[k] * (rg_[k] - g_[k]);
@@ -343,7 +353,10 @@ private:
             // skipped.  A failed search drops the estimate and retries along
             // -g; a failed search along -g ends the solve.  With an estimate,
             // a predicted decrease g.H g / 2 within the noise floor ends the
-            // solve as converged.
+            // solve as converged when the model is trusted: the last step's
+            // decrease was within the floor too, or (unit step) within a
+            // factor 2 of its prediction (H can still underestimate flat
+            // directions).
             case QN_START:
                 want_eval(w_, false, 1.0, 0.0, QN_AFTER_EVAL0);
                 return;
@@ -360,6 +373,8 @@ private:
                 g0_ = sqrt(dot(g_, g_, K));
                 rep_.gnorm0 = g0_;
                 have_h_ = have_hc_ = false;
+                last_drop_ = INFINITY;
+                last_pred_ = -1.0;
                 it_ = 0;
                 rep_.status = PCAS_STOP_MAXITER;
                 pc_ = QN_LOOP;
@@ -385,8 +400,13 @@ private:
                     t_ = 1.0;
                     if (gd_ >= 0.0) {
                         have_h_ = false;   // the estimate lost definiteness
-                    } else if (-0.5 * gd_ <= nu_ * phi_) {
-                        // the model's predicted decrease g.H g / 2 is below the noise
+                    } else if (-0.5 * gd_ <= nu_ * phi_ &&
+                               (last_drop_ <= nu_ * phi_ ||
+                                (0.5 * last_pred_ <= last_drop_ && last_drop_ <= 2.0 * last_pred_))) {
+                        // the model's predicted decrease g.H g / 2 is below the
+                        // noise, and the model is trusted (the last step's
+                        // decrease was below the noise, or within a factor 2
+                        // of what the model predicted for it)
                         end_at_floor(PCAS_STOP_CONVERGED);
                         break;
                     }
@@ -425,7 +445,11 @@ private:
                     sv[k] = wt_[k] - w_[k];
                     yv[k] = rg_[k] - g_[k];
                 }
+                // the model's decrease at the accepted step, for a unit
+                // quasi-Newton step (phi(w + d) ~ phi + g.d - g.d / 2)
+                last_pred_ = (have_h_ && t_ == 1.0) ? -0.5 * gd_ : -1.0;
                 hessian_update(H_, have_h_, sv, yv);
+                last_drop_ = phi_ - phi_t_;
                 for (int k = 0; k < K; ++k) {
                     w_[k] = wt_[k];
                     g_[k] = rg_[k];
@@ -598,6 +622,9 @@ private:
     double Hc_[PCAS_MAX_K * PCAS_MAX_K] = {0};  // estimate kept for the polish step
     double phi_ = 0.0, a_ = 0.0, b_ = 0.0, phi_t_ = 0.0, a_t_ = 0.0, b_t_ = 0.0;
     double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, tx_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
+    double curv_ = 0.0;   // CG: (s.y) / (s.s) of the last accepted step
+    double last_drop_ = 0.0;   // BFGS: J decrease of the last accepted step
+    double last_pred_ = -1.0;  // BFGS: the model's prediction of it (< 0: none)
     double J_ = 0.0, gn_ = 0.0, mu_ = 0.0;
     bool restart_ = true, first_ = true, have_h_ = false, have_hc_ = false;
     int it_ = 0, bt_ = 0, ls_slot_ = 0;

@@ -189,7 +189,9 @@ def test_machine_matches_oracle_on_small_problem(harness, oracle_lib, method):
     c = synth.small(seed=18)
     y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
     prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y)
-    rep, acc = _compare(harness, prob, c.K, np.zeros(c.K), _opts(method), 1e-9)
+    # stops on the gradient test, above the rounding floor where a near-tie
+    # between the two sides' summation orders could end them an iteration apart
+    rep, acc = _compare(harness, prob, c.K, np.zeros(c.K), _opts(method, gtol_rel=1e-6), 1e-9)
     assert rep.status == O.STOP_CONVERGED
 
 
