@@ -63,12 +63,23 @@ def drr_bricks(vol) -> int:
 
 
 def kernel_digest(kernel: str) -> str:
-    """sha256[:16] of the kernel's source file and every shared header."""
+    """sha256[:16] of the kernel's source file and every header it includes,
+    directly or through other headers (device code only: host-side files
+    such as the solver do not change a kernel's traffic)."""
     import hashlib
+    import re
 
     csrc = os.path.join(ROOT, "paper_1102_1712_amd", "csrc")
+    files, todo = [], [KERNEL_SOURCES[kernel]]
+    while todo:
+        f = todo.pop(0)
+        if f in files or not os.path.exists(os.path.join(csrc, f)):
+            continue
+        files.append(f)
+        with open(os.path.join(csrc, f)) as fh:
+            todo += re.findall(r'#include "([A-Za-z0-9_]+\.h)"', fh.read())
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCES[kernel], *sorted(x for x in os.listdir(csrc) if x.endswith(".h"))):
+    for f in [files[0]] + sorted(files[1:]):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
