@@ -145,7 +145,7 @@ def samples_per_drr(rays, dtype: str) -> int:
     return int(n.astype(np.int64).sum())
 
 
-def cpu_baseline(case, n_fevals: int, n_grads: int, budget_s: float):
+def cpu_baseline(case, n_fevals: int, n_grads: int, budget_s: float, samples: int = 0):
     """Time the FP64 oracle on the host cores on a bounded sample of the same
     workload -- whole forward evaluations (warp + projection + fit) and whole
     gradient evaluations (back-projection + Jacobian chain) at full size --
@@ -178,6 +178,7 @@ def cpu_baseline(case, n_fevals: int, n_grads: int, budget_s: float):
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return {
         "value": 1.0 / t_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
+        "forward_gsamples_s": samples / tf / 1e9 if samples else None,
         "sample": (f"{len(t_fwd)} forward + {len(t_grad)} gradient evaluations of the FP64 oracle "
                    f"on the full {case.name} workload (median forward {tf:.2f} s, gradient "
                    f"{tg:.2f} s), scaled by the GPU solve's {n_fevals} forward and {n_grads} "
@@ -563,6 +564,49 @@ def autograd_mode(args) -> int:
     return 0
 
 
+def random_angles(case, dev, dt, args, base: dict) -> dict:
+    """p50/p99 of solves at args.angles seeded random angles in [0, 2 pi),
+    CG and BFGS, each angle with its own measured projection."""
+    import dataclasses
+
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+
+    rng = np.random.default_rng(args.seed + 400)
+    gen = torch.Generator(device="cuda").manual_seed(args.seed + 401)
+    angles = rng.uniform(0.0, 2.0 * np.pi, args.angles)
+    probs = []
+    for th in angles:
+        pj = dataclasses.replace(case.proj, angle=float(th))
+        rays = B.ray_table(case.vol, pj, dt)
+        f = B.warp_pca(case.vol, dev["f0"], dev["mean"], dev["U"], case.w_star)
+        p = B.drr_forward(case.vol, pj, rays, f)
+        rms = torch.sqrt(torch.mean(p.double() ** 2))
+        y = (p.double() + case.noise_level * rms * torch.randn(p.shape, generator=gen, device="cuda",
+                                                              dtype=torch.float64)).to(dt)
+        probs.append((pj, y.contiguous()))
+        del rays, f, p
+    ws = torch.empty(B.solve_projection_workspace(case.vol, case.proj, case.K, dt),
+                     dtype=torch.uint8, device="cuda")
+    out = {"angles": int(args.angles)}
+    for label, method in (("cg", 1), ("bfgs", 2)):
+        o = B.default_opts(**{**base, "method": method})
+        ts, ev, err = [], [], []
+        for pj, y in probs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            w, rep = B.solve_projection(case.vol, pj, dev["f0"], dev["mean"], dev["U"], y,
+                                        np.zeros(case.K), o, workspace=ws)
+            ts.append((time.perf_counter() - t0) * 1e3)
+            ev.append(rep["n_fevals"] + rep["n_grads"])
+            err.append(np.linalg.norm(w - case.w_star) / np.linalg.norm(case.w_star))
+        out[label] = {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)),
+                      "mean_ms": float(np.mean(ts)), "mean_evaluations": float(np.mean(ev)),
+                      "w_rel_err_vs_planted_median": float(np.median(err))}
+    return out
+
+
 def adjoint_alone(case, dev, S: int) -> dict:
     """The back-projection on its own (in the solve it runs fused with the
     Jacobian chain), HIP events on the current stream, for the DRR+adjoint
@@ -609,6 +653,8 @@ def main() -> int:
                          "the differentiation form against the plain solve")
     ap.add_argument("--method", default="cg", choices=list(METHODS),
                     help="solver: PR+ CG (the configured one), BFGS, or the Appendix algorithm")
+    ap.add_argument("--angles", type=int, default=100,
+                    help="solve mode: seeded random angles timed besides the fixed one")
     ap.add_argument("--frames", type=int, default=600)
     ap.add_argument("--requests", type=int, default=32)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -763,10 +809,15 @@ def main() -> int:
               "J_rel_diff_vs_cg": float((rep_qn["J"] - rep["J"]) / rep["J"])}
         log(f"quasi-Newton: p50 {qn['p50_ms']:.3f} ms, {qn['n_fevals']} evaluations")
 
+    # the same solve at seeded random gantry angles, each with its own
+    # measured projection (same recipe: P f(w*) + 1% noise)
+    rand = random_angles(case, dev, dt, args, base)
+    log(f"random angles: {rand}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host cores")
-        cpu = cpu_baseline(case, rep["n_fevals"], rep["n_grads"], args.cpu_baseline_s)
+        cpu = cpu_baseline(case, rep["n_fevals"], rep["n_grads"], args.cpu_baseline_s, S)
 
     drr = kernel_stats.get("drr_forward", {})
     # the back-projection alone (in the solve it runs fused with the chain)
@@ -802,6 +853,7 @@ def main() -> int:
         "kernels": kernel_stats,
         "projected_gradient_route": alt,
         "quasi_newton": qn,
+        "random_angles": rand,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "0.1-0.3 s per projection on a Tesla C1060 (different sizes; context only)",
