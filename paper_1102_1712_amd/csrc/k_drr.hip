@@ -606,10 +606,15 @@ __device__ __forceinline__ unsigned long long fixed_of(double v) {
     const double m = v + 6755399441055744.0;
     return __builtin_bit_cast(unsigned long long, m) - 0x4338000000000000ull;
 }
-// 32-bit image of an already-scaled float contribution, |v| < 2^31, truncated
-// toward zero (the accumulator of the solver's FP32 gradient, whose scale
-// comes from the measured per-brick bound).
-__device__ __forceinline__ unsigned int fixed32_of(float v) { return (unsigned int)(int)v; }
+// 32-bit image of an already-scaled float contribution, |v| < 2^31, rounded to
+// nearest (the accumulator of the solver's FP32 gradient, whose scale comes
+// from the measured per-brick bound).  A voxel near the source takes ~10^4
+// adds at ~20 bits each; truncation's bias (half a unit per add, one sign
+// where the residual is smooth) would add up with the count, rounding's
+// errors only with its square root.
+__device__ __forceinline__ unsigned int fixed32_of(float v) {
+    return (unsigned int)(int)__builtin_rintf(v);
+}
 __device__ __forceinline__ long long acc_value(unsigned int a) { return (long long)(int)a; }
 __device__ __forceinline__ long long acc_value(unsigned long long a) { return (long long)a; }
 template <bool A32, typename V>

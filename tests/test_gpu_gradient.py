@@ -109,6 +109,40 @@ def test_small_f32_extreme_K(torch, K):
     assert np.linalg.norm(g0 - g1) <= 1e-5 * np.linalg.norm(g1)
 
 
+# Geometries that stress the FP32 gradient's 32-bit accumulators: their
+# scale comes from per-brick bounds of P^T 1, so an understated bound would
+# wrap silently.  (The same shapes pin the weight bound on the CPU.)
+STRESS = {
+    "close_source": dict(n=(32, 32, 24), spacing=(4.0, 4.0, 4.0), det=(200, 160), pitch=(1.0, 1.0),
+                         step=2.0, sad=120.0, sid=300.0, angle=0.9),
+    "fine_pitch": dict(n=(24, 24, 16), spacing=(2.0, 2.0, 3.0), det=(160, 120), pitch=(0.25, 0.25),
+                       step=1.0),
+    "steep_cone": dict(n=(20, 20, 60), spacing=(3.0, 3.0, 3.0), det=(64, 200), pitch=(1.5, 1.5),
+                       step=1.5, sad=150.0, sid=400.0, angle=2.2),
+    "half_fan": dict(n=(32, 32, 20), spacing=(4.0, 4.0, 5.0), det=(96, 64), pitch=(1.2, 1.2), step=2.0,
+                     offset_u=40.0, angle=4.0),
+    "long_step": dict(n=(30, 30, 30), spacing=(1.0, 1.0, 1.0), det=(80, 80), pitch=(0.5, 0.5),
+                      step=3.5),
+    "short_step": dict(n=(30, 26, 22), spacing=(3.0, 2.0, 4.0), det=(64, 48), pitch=(2.0, 2.0),
+                       step=0.3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STRESS))
+def test_f32_gradient_stress_geometries(torch, name):
+    """FP32 gradient by the back-projection route (32-bit accumulators) on
+    extreme geometries: against the oracle and the projected-Jacobian route,
+    which shares no accumulation with it."""
+    g = dict(STRESS[name])
+    n, spacing, det, pitch, step = g.pop("n"), g.pop("spacing"), g.pop("det"), g.pop("pitch"), g.pop("step")
+    c = synth.make_case(f"stress-{name}", n, spacing, det, pitch, step, 3, "f32", 31, **g)
+    d = Dev(c)
+    y = measured(c)
+    w = c.w_star + np.array([0.3, -0.2, 0.25])
+    g0, g1 = _check(c, d, y, w, True, 1e-4, 1e-5)
+    assert np.linalg.norm(g0 - g1) <= 1e-5 * np.linalg.norm(g1)
+
+
 def test_solve_same_by_either_route(torch):
     """FP64 small solve: both gradient routes converge to the same w."""
     c = synth.small(dtype="f64", seed=5)
