@@ -654,7 +654,7 @@ def main() -> int:
     ap.add_argument("--method", default="cg", choices=list(METHODS),
                     help="solver: PR+ CG (the configured one), BFGS, or the Appendix algorithm")
     ap.add_argument("--angles", type=int, default=100,
-                    help="solve mode: seeded random angles timed besides the fixed one")
+                    help="solve mode: seeded random angles timed besides the fixed one (0: none)")
     ap.add_argument("--frames", type=int, default=600)
     ap.add_argument("--requests", type=int, default=32)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -811,7 +811,7 @@ def main() -> int:
 
     # the same solve at seeded random gantry angles, each with its own
     # measured projection (same recipe: P f(w*) + 1% noise)
-    rand = random_angles(case, dev, dt, args, base)
+    rand = random_angles(case, dev, dt, args, base) if args.angles > 0 else None
     log(f"random angles: {rand}")
 
     cpu = None
