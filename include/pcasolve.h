@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 4
+#define PCAS_ABI_VERSION 5
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -104,7 +104,11 @@ typedef struct {
     int32_t locate_max_iter;
     double locate_tol;     /* mm */
     double c0_mm[3];       /* tumour centre in the reference image (mm) */
-    int32_t profile;       /* 1: time every kernel with HIP events (report.kernel_ms) */
+    int32_t profile;       /* kernel classes to time with HIP events (report.kernel_ms): bit c
+                              for class c of the PCAS_K_* list below, PCAS_PROFILE_ALL for every
+                              class, 0 for none.  Each timed launch adds two event records to
+                              the stream, a few microseconds each, so a caller timing one kernel
+                              sets that kernel's bit alone */
     int32_t grad_mode;     /* how dJ/dw is formed (the same quantity either way, by the
                               adjoint identity <P^T r, J_k> = <r, P J_k>):
                               1: back-project r, then g = 2 U^T (df/dx) P^T r (the Appendix's
@@ -143,6 +147,7 @@ enum {
     PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
     PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_BOUNDS = 10, PCAS_K_CLASSES = 11
 };
+#define PCAS_PROFILE_ALL ((1 << PCAS_K_CLASSES) - 1)
 
 typedef struct {
     int32_t status;        /* PCAS_STOP_* */

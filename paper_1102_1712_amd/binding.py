@@ -84,6 +84,14 @@ class Report(ctypes.Structure):
 KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint_chain",
                   "grad_w", "tumour_position", "y_sums", "jacobian", "drr_forward_dot",
                   "adjoint_bounds")
+PROFILE_ALL = (1 << len(KERNEL_CLASSES)) - 1
+
+
+def profile_mask(*classes: str) -> int:
+    """opts.profile value that times the named kernel classes (all if none)."""
+    if not classes:
+        return PROFILE_ALL
+    return sum(1 << KERNEL_CLASSES.index(c) for c in set(classes))
 
 
 _lib = None

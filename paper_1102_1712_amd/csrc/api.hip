@@ -127,7 +127,7 @@ int drr_forward(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
     const VolDims vd = make_dims(vol);
     const Frame fr = make_frame(proj);
     HIPCHK(launch_drr_forward(dtype, vd, fr, plan_drr_forward(dtype, vd, fr, 1), rays, f, p_out,
-                              nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream));
+                              nullptr, nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream));
     return PCAS_OK;
 }
 
@@ -243,12 +243,13 @@ size_t solve_projection_workspace(pcas_dtype dtype, const pcas_vol *vol, const p
 // The solve.
 namespace {
 
-// Optional per-kernel timing: a pair of HIP events around each launch on
-// the solve's stream, read after the next synchronisation.
+// Optional per-kernel timing: a pair of HIP events around each launch of
+// the selected classes on the solve's stream, read after the next
+// synchronisation.
 thread_local std::vector<hipEvent_t> t_events;
 
 struct Profile {
-    bool on = false;
+    unsigned mask = 0;   // bit c: time class c
     double ms[PCAS_K_CLASSES] = {0};
     int n[PCAS_K_CLASSES] = {0};
     struct Pending {
@@ -268,11 +269,17 @@ struct Profile {
         *e = t_events[i];
         return hipSuccess;
     }
-    // Call after the stream has been synchronised.
+    // Call after a read-back: every event recorded so far precedes the
+    // publishing kernel on the stream, but the runtime may not have marked
+    // the last ones complete yet, so those are waited for.
     hipError_t collect() {
         for (const Pending &p : pending) {
             float t = 0.f;
             hipError_t err = hipEventElapsedTime(&t, t_events[p.a], t_events[p.b]);
+            if (err == hipErrorNotReady) {
+                if ((err = hipEventSynchronize(t_events[p.b])) != hipSuccess) return err;
+                err = hipEventElapsedTime(&t, t_events[p.a], t_events[p.b]);
+            }
             if (err != hipSuccess) return err;
             ms[p.cls] += t;
             n[p.cls] += 1;
@@ -298,13 +305,18 @@ struct Solver {
     int fit;
     double sy = 0.0, syy = 0.0;
     int n_fevals = 0, n_grads = 0;
+    // Reference fit of the next refitted FP32 evaluation's moments (the last
+    // fit found), and the slot and reference of the moments in scal()[0..2].
+    double ref_a = 1.0, ref_b = 0.0;
+    int mom_slot = -1;
+    double mom_a0 = 0.0, mom_b0 = 0.0;
     Profile prof;
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
 
     template <class F> hipError_t timed(int cls, F &&launch) {
-        if (!prof.on) return launch();
+        if (!(prof.mask >> cls & 1u)) return launch();
         hipEvent_t a, b;
         hipError_t e;
         const size_t ia = prof.next++, ib = prof.next++;
@@ -319,7 +331,7 @@ struct Solver {
     int sync_read(double *host, const double *dev, int count) {
         int st = readback(host, dev, count, s);
         if (st) return st;
-        if (prof.on) HIPCHK(prof.collect());
+        if (prof.mask) HIPCHK(prof.collect());
         return PCAS_OK;
     }
 
@@ -342,7 +354,12 @@ struct Solver {
     char *proj_slot(int slot) const { return ws + (slot ? L.p2 : L.p); }
 
     int residual(const double *ab_fixed, int slot, double *J, double *a, double *b) {
-        const FitArgs fa = fit_args(ab_fixed);
+        FitArgs fa = fit_args(ab_fixed);
+        if (fa.mode == FIT_REFIT) {   // the refit reads the moments of this slot's projection
+            if (slot != mom_slot) return hip_fail(hipErrorInvalidValue, "refit without moments");
+            fa.a0 = mom_a0;
+            fa.b0 = mom_b0;
+        }
         HIPCHK(timed(PCAS_K_RESIDUAL, [&] {
             return launch_residual(dt, M, proj_slot(slot), y, fa, scal(), nullptr,
                                    (double *)(ws + L.partials), &counters()[3], scal() + 3, s);
@@ -355,21 +372,53 @@ struct Solver {
         *b = out[2];
         if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
         if (!isfinite(*J)) return PCAS_ENONFINITE;
+        ref_a = *a;
+        ref_b = *b;
         return PCAS_OK;
     }
 
-    // Warp + projection at w into a slot, then the residual pass (one read-back).
+    // Warp + projection at w into a slot, then J at the fit (one read-back).
+    // FP32: the projection's last block forms J from moments about a
+    // reference fit (the fixed one, else the last fit found), and the
+    // two-pass residual runs only if that sum would cancel.  FP64: moments
+    // of p itself and the two-pass residual.
     int evaluate(const double *w, const double *ab_fixed, int slot, double *J, double *a,
                  double *b) {
         HIPCHK(timed(PCAS_K_WARP, [&] {
             return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s);
         }));
+        const bool one_pass = dt == PCAS_F32;
+        FitArgs ff = fit_args(ab_fixed);
+        if (one_pass) {
+            ff.a0 = ff.mode == FIT_FIXED ? ff.a : ref_a;
+            ff.b0 = ff.mode == FIT_FIXED ? ff.b : ref_b;
+        } else {
+            ff.mode = FIT_NONE;
+        }
         HIPCHK(timed(PCAS_K_DRR, [&] {
             return launch_drr_forward(dt, vd, fr, fplan, ws + L.rays, ws + L.f, proj_slot(slot), y,
-                                      (double *)(ws + L.partials), &counters()[0], scal(), s);
+                                      &ff, (double *)(ws + L.partials), &counters()[0], scal(), s);
         }));
         ++n_fevals;
-        return residual(ab_fixed, slot, J, a, b);
+        mom_slot = slot;
+        mom_a0 = ff.a0;
+        mom_b0 = ff.b0;
+        if (!one_pass) return residual(ab_fixed, slot, J, a, b);
+        double out[4];
+        int st = sync_read(out, scal() + 3, 4);
+        if (st) return st;
+        *J = out[0];
+        *a = out[1];
+        *b = out[2];
+        if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
+        if (!(out[3] <= MOMENT_KAPPA_MAX)) {   // cancellation: the two-pass sum at this fit
+            const double ab[2] = {*a, *b};
+            return residual(ab, slot, J, a, b);
+        }
+        if (!isfinite(*J)) return PCAS_ENONFINITE;
+        ref_a = *a;
+        ref_b = *b;
+        return PCAS_OK;
     }
 
     // Gradient at the w whose projection is in the slot, at (a, b).
@@ -404,7 +453,7 @@ struct Solver {
     // the measured image's sums and the fit's solvability.
     int prepare(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, int32_t K_,
                 const void *f0_, const void *mean_, const void *U_, const void *y_, int fit_,
-                int grad_mode_, bool profile, void *workspace, void *stream) {
+                int grad_mode_, unsigned profile, void *workspace, void *stream) {
         dt = dtype;
         vd = make_dims(vol);
         fr = make_frame(proj);
@@ -421,7 +470,7 @@ struct Solver {
         L = solve_layout(dtype, vol, proj, K_);
         s = (hipStream_t)stream;
         fit = fit_ ? 1 : 0;
-        prof.on = profile;
+        prof.mask = profile;
         HIPCHK(launch_fill_u32(counters(), 64, 0u, s));
         HIPCHK(timed(PCAS_K_RAYS, [&] { return launch_ray_table(dt, vd, fr, ws + L.rays, s); }));
         if (dt == PCAS_F32 && grad_mode == 1)
@@ -498,7 +547,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
     report->locate_iters = -1;
     Solver S;
     if ((st = S.prepare(dtype, vol, proj, K, f0, mean, U, y, opts->fit_intensity, opts->grad_mode,
-                        opts->profile != 0, workspace, stream)))
+                        (unsigned)opts->profile, workspace, stream)))
         return st;
 
     SolveMachine m;
@@ -542,7 +591,7 @@ extern "C" int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const p
     const SolveWs L = solve_layout(dtype, vol, proj, K);
     if (!workspace || !aligned(workspace, 256) || workspace_bytes < L.total) return PCAS_EWORKSPACE;
     Solver S;
-    if ((st = S.prepare(dtype, vol, proj, K, f0, mean, U, y, fit_intensity, grad_mode, false,
+    if ((st = S.prepare(dtype, vol, proj, K, f0, mean, U, y, fit_intensity, grad_mode, 0u,
                         workspace, stream)))
         return st;
     double J, a, b;

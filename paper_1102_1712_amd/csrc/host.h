@@ -127,22 +127,54 @@ inline bool finite_vec(const double *w, int K) {
     return true;
 }
 
-// Small pinned host buffer per thread for scalar read-backs.
-inline double *host_scalars() {
-    thread_local double *buf = nullptr;
-    if (!buf) {
-        if (hipHostMalloc((void **)&buf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-            buf = nullptr;
+// Scalar read-back through a per-thread mailbox in coherent, mapped host
+// memory: 64 values and a flag word.  A one-wave kernel on the stream copies
+// the values there and then publishes a sequence number in the flag; the
+// host spins until it reads that number.  Every few thousand polls it
+// queries the stream, so an error on the stream ends the wait with that
+// error.  Against a copy and a stream synchronisation this saves, on each of
+// a solve's round trips, the copy's dispatch and the synchronisation's
+// wake-up.  The stream may still be retiring the publishing kernel when
+// readback returns; work enqueued next runs after it.
+struct Mailbox {
+    double *vals = nullptr;
+    uint32_t *flag = nullptr;
+    uint32_t seq = 0;
+};
+
+inline Mailbox *host_mailbox() {
+    thread_local Mailbox mb;
+    if (!mb.vals) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 64 * sizeof(double) + 256, hipHostMallocCoherent | hipHostMallocMapped) !=
+            hipSuccess)
+            return nullptr;
+        mb.vals = (double *)p;
+        mb.flag = (uint32_t *)((char *)p + 64 * sizeof(double));
+        __atomic_store_n(mb.flag, 0u, __ATOMIC_RELEASE);
     }
-    return buf;
+    return &mb;
 }
 
 inline int readback(double *host, const double *dev, int count, hipStream_t s) {
-    double *hb = host_scalars();
-    if (!hb) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(scalars)");
-    HIPCHK(hipMemcpyAsync(hb, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    memcpy(host, hb, count * sizeof(double));
+    if (count < 0 || count > 64) return hip_fail(hipErrorInvalidValue, "scalar read-back size");
+    Mailbox *mb = host_mailbox();
+    if (!mb) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(scalar mailbox)");
+    if (++mb->seq == 0) mb->seq = 1;   // 0 is the flag's initial value
+    const uint32_t seq = mb->seq;
+    HIPCHK(launch_publish(dev, mb->vals, count, mb->flag, seq, s));
+    for (uint32_t n = 1; __atomic_load_n(mb->flag, __ATOMIC_ACQUIRE) != seq; ++n) {
+        __builtin_ia32_pause();
+        if ((n & 4095u) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {   // the stream has drained, so the flag store is visible
+                if (__atomic_load_n(mb->flag, __ATOMIC_ACQUIRE) == seq) break;
+                return hip_fail(hipErrorUnknown, "scalar read-back: value not published");
+            }
+            if (q != hipErrorNotReady) return hip_fail(q, "hipStreamQuery");
+        }
+    }
+    memcpy(host, mb->vals, count * sizeof(double));
     return PCAS_OK;
 }
 
@@ -193,6 +225,7 @@ inline int check_opts(const pcas_opts *o) {
     if (!(o->beta_lo > 0.0 && o->beta_lo <= o->beta)) return PCAS_EINVAL;
     if (!(o->ls_extrap >= 0.0) || !isfinite(o->ls_extrap) || isnan(o->ftol_rel)) return PCAS_EINVAL;
     if (o->polish != 0 && o->polish != 1) return PCAS_EINVAL;
+    if (o->profile < 0 || o->profile > PCAS_PROFILE_ALL) return PCAS_EINVAL;
     if (o->locate && !finite_vec(o->c0_mm, 3)) return PCAS_EINVAL;
     return PCAS_OK;
 }

@@ -79,12 +79,20 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
     return (bid & 7) * per + (bid >> 3);
 }
 
-// Intensity-fit mode of the residual pass (see launch_residual).
-enum { FIT_COEF = 0, FIT_REFIT = 1, FIT_FIXED = 2 };
+// Intensity-fit mode of the residual pass (see launch_residual) and of the
+// forward pass's objective (FIT_NONE: moments only).
+enum { FIT_COEF = 0, FIT_REFIT = 1, FIT_FIXED = 2, FIT_NONE = 3 };
+// (a, b): the fixed fit; sy, syy, m: sum y, sum y^2 and the pixel count;
+// (a0, b0): the reference fit of the forward pass's moments, which are sums
+// of r0 = p - a0 y - b0, r0 y and r0^2 (a0 = b0 = 0: sums of p, p y, p^2).
 struct FitArgs {
     int mode;
     double a, b, sy, syy, m;
+    double a0 = 0.0, b0 = 0.0;
 };
+// Above this cancellation factor sum(r0^2) / J the forward pass's J is
+// recomputed by the two-pass residual at the fit it found.
+constexpr double MOMENT_KAPPA_MAX = 1e4;
 
 // ---- batched launches: one launch serves several requests ----------------
 // A job holds one request's arguments and the range [block0, block0 +
@@ -107,6 +115,7 @@ struct FwdJob {                 // projection with the fit sums (FWD_SUMS)
     const void *rays, *f;
     void *p;
     const void *y;
+    FitArgs fit;                // reference (a0, b0) and, unless FIT_NONE, the objective's fit
     double *partials;
     uint32_t *counter;
     double *out;
@@ -140,6 +149,9 @@ struct AdjJob {                 // back-projection of the residual + Jacobian ch
 
 // ---- launchers (return the HIP error of the launch) ----------------------
 hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s);
+// Copies count <= 64 doubles to mapped host memory, then releases seq to *flag_host.
+hipError_t launch_publish(const double *src, double *dst_host, int count, uint32_t *flag_host,
+                          uint32_t seq, hipStream_t s);
 
 hipError_t launch_ray_table(pcas_dtype dt, const VolDims &v, const Frame &fr, void *rays,
                             hipStream_t s);
@@ -152,10 +164,14 @@ hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f
                            const void *mean, const void *U, const double *w, void *f,
                            hipStream_t s);
 
-// Forward projection.  If sums != nullptr also reduces (sum p, sum p*y,
-// sum p*p) into sums[0..2] (double) via per-block partials and a last-block
-// pass; partials needs drr_forward_blocks() * RED_SLOTS doubles, counter one
-// zeroed uint32 (left zeroed on exit).
+// Forward projection.  If sums != nullptr also reduces, with r0 = p - a0 y -
+// b0 for fit->a0, fit->b0 (zero when fit is null), (sum r0, sum r0*y,
+// sum r0*r0) into sums[0..2] (double) via per-block partials and a
+// last-block pass; partials needs drr_forward_blocks() * RED_SLOTS doubles,
+// counter one zeroed uint32 (left zeroed on exit).  Unless fit is null or
+// its mode FIT_NONE, the last block then writes the objective at that fit
+// (refitted by Eq. A.1, or fixed) from the moments: sums[3..6] = J, a, b and
+// the cancellation factor sum(r0^2) / J (infinite if J <= 0).
 // The geometry-only launch plan (slab axis and thickness) is computed once
 // per projection on the host.
 int drr_forward_blocks(int nu, int nv);
@@ -165,8 +181,8 @@ struct ForwardPlan {
 ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr, int nvol);
 hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
                               const ForwardPlan &plan, const void *rays, const void *f, void *p,
-                              const void *y, double *partials, uint32_t *counter, double *sums,
-                              hipStream_t s);
+                              const void *y, const FitArgs *fit, double *partials,
+                              uint32_t *counter, double *sums, hipStream_t s);
 // Projections of the K volumes J[k][voxel] (plan for nvol = K) against the
 // residual of the stored projection p: g_out[k] = 2 sum_rays (p - a y - b)
 // (P J_k); partials needs drr_forward_blocks() * RED_SLOTS doubles, counter
@@ -247,8 +263,8 @@ int warp_blocks(int64_t N);
 hipError_t launch_warp_pca_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,
                                  int total_blocks, hipStream_t s);
 FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, const void *rays,
-                    const void *f, void *p, const void *y, double *partials, uint32_t *counter,
-                    double *sums);
+                    const void *f, void *p, const void *y, const FitArgs &fit, double *partials,
+                    uint32_t *counter, double *sums);
 hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *jobs, int njobs,
                                          int total_blocks, hipStream_t s);
 hipError_t launch_residual_batch(pcas_dtype dt, const ResJob *jobs, int njobs, int total_blocks,

@@ -147,7 +147,9 @@ constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_L
 // depends only on the geometry, so results are bit-for-bit reproducible.
 //
 // MODE FWD_WRITE / FWD_SUMS (NV = 1): p = P f, and for FWD_SUMS also
-// (sum p, sum p y, sum p^2) into out[0..2].  MODE FWD_DOT: the ray values
+// (sum r0, sum r0 y, sum r0^2) for r0 = p - fit.a0 y - fit.b0 into
+// out[0..2], then (unless fit.mode is FIT_NONE) the objective at fit into
+// out[3..6] (ObjectiveFromMoments).  MODE FWD_DOT: the ray values
 // q_v = (P f_v) are not stored; out[v] = 2 sum_rays r q_v with the residual
 // r = p - a y - b of the stored projection p.
 template <typename T, int AX, int NV, int MODE>
@@ -155,7 +157,7 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                                                   int slab, const RayRec<T> *__restrict__ rays,
                                                   const T *__restrict__ f, T *__restrict__ p,
                                                   const T *__restrict__ y, double fa, double fb,
-                                                  double *__restrict__ partials,
+                                                  const FitArgs &fit, double *__restrict__ partials,
                                                   uint32_t *counter, double *__restrict__ out,
                                                   int lb, int nb) {
     constexpr int SPLIT = FWD_SPLIT;
@@ -384,8 +386,10 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
         }
         if constexpr (MODE == FWD_SUMS) {
             const double yv = writer ? (double)y[pix] : 0.0;
-            const double vals[3] = {pv, pv * yv, pv * pv};
-            grid_reduce<3>(vals, partials, counter, out, bid, nb, 1.0);
+            const double rv = writer ? pv - fit.a0 * yv - fit.b0 : 0.0;
+            const double vals[3] = {rv, rv * yv, rv * rv};
+            grid_reduce<3>(vals, partials, counter, out, bid, nb, 1.0,
+                           ObjectiveFromMoments{fit, out + 3});
         }
     }
 }
@@ -395,9 +399,9 @@ __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int t
                                                      const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ f, T *__restrict__ p,
                                                      const T *__restrict__ y, double fa, double fb,
-                                                     double *__restrict__ partials,
+                                                     FitArgs fit, double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ out) {
-    drr_forward_block<T, AX, NV, MODE>(vd, fr, tiles_u, slab, rays, f, p, y, fa, fb, partials,
+    drr_forward_block<T, AX, NV, MODE>(vd, fr, tiles_u, slab, rays, f, p, y, fa, fb, fit, partials,
                                        counter, out, blockIdx.x, gridDim.x);
 }
 
@@ -409,8 +413,8 @@ __global__ __launch_bounds__(256) void k_drr_forward_batch(const FwdJob *__restr
     const FwdJob &J = jobs[j];
     drr_forward_block<T, AX, 1, FWD_SUMS>(J.vd, J.fr, J.tiles_u, J.slab,
                                           (const RayRec<T> *)J.rays, (const T *)J.f, (T *)J.p,
-                                          (const T *)J.y, 0.0, 0.0, J.partials, J.counter, J.out,
-                                          blockIdx.x - J.block0, J.nblocks);
+                                          (const T *)J.y, 0.0, 0.0, J.fit, J.partials, J.counter,
+                                          J.out, blockIdx.x - J.block0, J.nblocks);
 }
 
 int drr_forward_blocks(int nu, int nv) {
@@ -463,52 +467,59 @@ ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr, i
 template <typename T, int AX, int NV, int MODE>
 static void launch_fwd(dim3 grid, const VolDims &v, const Frame &fr, int tiles_u, int slab,
                        const void *rays, const void *f, void *p, const void *y, double a, double b,
-                       double *partials, uint32_t *counter, double *out, hipStream_t s) {
+                       const FitArgs &fit, double *partials, uint32_t *counter, double *out,
+                       hipStream_t s) {
     hipLaunchKernelGGL((k_drr_forward<T, AX, NV, MODE>), grid, dim3(256), 0, s, v, fr, tiles_u, slab,
-                       (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, a, b, partials,
-                       counter, out);
+                       (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, a, b, fit,
+                       partials, counter, out);
 }
 
 template <typename T, int NV, int MODE>
 static void launch_fwd_axis(const ForwardPlan &pl, dim3 grid, const VolDims &v, const Frame &fr,
                             int tiles_u, const void *rays, const void *f, void *p, const void *y,
-                            double a, double b, double *partials, uint32_t *counter, double *out,
-                            hipStream_t s) {
+                            double a, double b, const FitArgs &fit, double *partials,
+                            uint32_t *counter, double *out, hipStream_t s) {
     if (pl.axis == 0)
-        launch_fwd<T, 0, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, partials,
-                                   counter, out, s);
+        launch_fwd<T, 0, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, fit,
+                                   partials, counter, out, s);
     else
-        launch_fwd<T, 1, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, partials,
-                                   counter, out, s);
+        launch_fwd<T, 1, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, fit,
+                                   partials, counter, out, s);
+}
+
+static FitArgs no_fit() {
+    FitArgs fa{FIT_NONE, 1.0, 0.0, 0.0, 0.0, 0.0};
+    return fa;
 }
 
 hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
                               const ForwardPlan &plan, const void *rays, const void *f, void *p,
-                              const void *y, double *partials, uint32_t *counter, double *sums,
-                              hipStream_t s) {
+                              const void *y, const FitArgs *fit, double *partials,
+                              uint32_t *counter, double *sums, hipStream_t s) {
     const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
     const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
+    const FitArgs fa = fit ? *fit : no_fit();
     if (dt == PCAS_F32) {
         if (sums)
             launch_fwd_axis<float, 1, FWD_SUMS>(plan, grid, v, fr, tiles_u, rays, f, p, y, 0.0, 0.0,
-                                                partials, counter, sums, s);
+                                                fa, partials, counter, sums, s);
         else
             launch_fwd_axis<float, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
-                                                 0.0, 0.0, nullptr, nullptr, nullptr, s);
+                                                 0.0, 0.0, fa, nullptr, nullptr, nullptr, s);
     } else {
         if (sums)
             launch_fwd_axis<double, 1, FWD_SUMS>(plan, grid, v, fr, tiles_u, rays, f, p, y, 0.0,
-                                                 0.0, partials, counter, sums, s);
+                                                 0.0, fa, partials, counter, sums, s);
         else
             launch_fwd_axis<double, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
-                                                  0.0, 0.0, nullptr, nullptr, nullptr, s);
+                                                  0.0, 0.0, fa, nullptr, nullptr, nullptr, s);
     }
     return hipGetLastError();
 }
 
 FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, const void *rays,
-                    const void *f, void *p, const void *y, double *partials, uint32_t *counter,
-                    double *sums) {
+                    const void *f, void *p, const void *y, const FitArgs &fit, double *partials,
+                    uint32_t *counter, double *sums) {
     FwdJob J;
     J.vd = v;
     J.fr = fr;
@@ -518,6 +529,7 @@ FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, 
     J.f = f;
     J.p = p;
     J.y = y;
+    J.fit = fit;
     J.partials = partials;
     J.counter = counter;
     J.out = sums;
@@ -552,9 +564,10 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
     const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
     const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
     void *pp = const_cast<void *>(p);
+    const FitArgs fa = no_fit();
 #define D(TT, KK)                                                                                  \
     case KK:                                                                                       \
-        launch_fwd_axis<TT, KK, FWD_DOT>(plan, grid, v, fr, tiles_u, rays, J, pp, y, a, b,         \
+        launch_fwd_axis<TT, KK, FWD_DOT>(plan, grid, v, fr, tiles_u, rays, J, pp, y, a, b, fa,     \
                                          partials, counter, g_out, s);                             \
         break
     if (dt == PCAS_F32) {

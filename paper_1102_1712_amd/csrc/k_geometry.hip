@@ -14,6 +14,25 @@ hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s
     return hipGetLastError();
 }
 
+// Scalar read-back.  One wave copies up to 64 values into host memory that
+// the GPU writes through (coherent, mapped), waits for those stores, and
+// then stores `seq` to the flag word with a system-scope release: a host
+// thread that loads `seq` there (acquire) also sees the values.
+__global__ __launch_bounds__(64) void k_publish(const double *__restrict__ src, double *dst, int count,
+                                                uint32_t *flag, uint32_t seq) {
+    const int i = threadIdx.x;
+    if (i < count) dst[i] = src[i];
+    __threadfence_system();
+    if (i == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_publish(const double *src, double *dst_host, int count, uint32_t *flag_host,
+                          uint32_t seq, hipStream_t s) {
+    if (count < 0 || count > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, dst_host, count, flag_host, seq);
+    return hipGetLastError();
+}
+
 // One thread per detector pixel, all geometry in double with contraction
 // off, so the record is the correctly rounded evaluation of: pixel centre,
 // unit direction from the source, slab intersection with the box of voxel

@@ -55,7 +55,11 @@ __device__ __forceinline__ void residual_block(int64_t M, const T *__restrict__ 
         A = src[0];
         B = src[1];
     } else if (fa.mode == FIT_REFIT) {
-        fit_normal_equations(src[0], src[1], fa.sy, fa.syy, fa.m, &A, &B);
+        // src holds the forward pass's moments about the reference (a0, b0):
+        // sum p = sum r0 + a0 sum y + M b0, sum p y = sum r0 y + a0 sum y^2 + b0 sum y
+        const double sp = src[0] + fa.a0 * fa.sy + fa.m * fa.b0;
+        const double spy = src[1] + fa.a0 * fa.syy + fa.b0 * fa.sy;
+        fit_normal_equations(sp, spy, fa.sy, fa.syy, fa.m, &A, &B);
     }
     if (bid == 0 && threadIdx.x == 0) {
         out[1] = A;

@@ -60,6 +60,11 @@ struct Request {
     double w[PCAS_MAX_K] = {0};
     pcas_report rep{};
     double cost = 0.0;   // relative GPU work of one of its operations (see op_cost)
+    // reference fit of the next refitted FP32 evaluation's moments, and the
+    // slot and reference of the moments in scal()[0..2] (as in a solve alone)
+    double ref_a = 1.0, ref_b = 0.0;
+    int mom_slot = -1;
+    double mom_a0 = 0.0, mom_b0 = 0.0;
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -202,6 +207,99 @@ struct Groups {
     }
 };
 
+// The objective's fit at a request, as a solve alone takes it: (a, b) fixed
+// if given, else Eq. A.1's refit if the request fits intensities, else (1, 0).
+FitArgs fit_of(const Request &r, const double *ab_fixed) {
+    FitArgs fa{FIT_FIXED, 1.0, 0.0, r.sy, r.syy, (double)r.M};
+    if (ab_fixed) {
+        fa.a = ab_fixed[0];
+        fa.b = ab_fixed[1];
+    } else if (r.opts.fit_intensity) {
+        fa.mode = FIT_REFIT;
+    }
+    return fa;
+}
+
+ResJob res_job(const Request &r, int slot, const FitArgs &fa) {
+    ResJob rj;
+    rj.M = r.M;
+    rj.p = r.proj_slot(slot);
+    rj.y = r.y;
+    rj.fa = fa;
+    rj.src = r.scal();
+    rj.partials = r.partials();
+    rj.counter = &r.counters()[3];
+    rj.out = r.scal() + 3;
+    rj.block0 = 0;
+    rj.nblocks = sums_blocks(r.M);
+    return rj;
+}
+
+// Advances one request with the scalars its operation produced.
+void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done) {
+    const Model &md = S->models[r->model];
+    bool done = false;
+    int status = PCAS_OK;
+    if (r->phase == PH_PREPARE) {
+        r->sy = sc[16];
+        r->syy = sc[18];
+        if (!isfinite(r->sy) || !isfinite(r->syy)) {
+            status = PCAS_ENONFINITE;
+            done = true;
+        } else if (r->opts.fit_intensity) {
+            const double m = (double)r->M, det = r->syy * m - r->sy * r->sy;
+            if (!(fabs(det) > 1e-12 * r->syy * m)) {
+                status = PCAS_ESINGULAR;
+                done = true;
+            }
+        }
+        if (!done) {
+            r->m.start(r->opts, md.K, noise_model(md.dt, r->opts, r->M, r->sy, r->syy), r->w0);
+            r->phase = PH_RUN;
+        }
+    } else if (r->phase == PH_RUN) {
+        const SolveOp &op = r->m.op();
+        if (op.kind == OP_EVAL || op.kind == OP_RESID) {
+            const double J = sc[3], a = sc[4], b = sc[5];
+            if (!isfinite(a) || !isfinite(b)) {
+                status = PCAS_ESINGULAR;
+                done = true;
+            } else if (!isfinite(J)) {
+                status = PCAS_ENONFINITE;
+                done = true;
+            } else {
+                r->ref_a = a;
+                r->ref_b = b;
+                r->m.eval_result(J, a, b);
+            }
+        } else if (op.kind == OP_GRAD) {
+            for (int k = 0; k < md.K; ++k)
+                if (!isfinite(sc[8 + k])) {
+                    status = PCAS_ENONFINITE;
+                    done = true;
+                }
+            if (!done) r->m.grad_result(sc + 8);
+        }
+        if (!done && r->m.done()) {
+            r->rep = r->m.report();
+            for (int k = 0; k < md.K; ++k) r->w[k] = r->m.w()[k];
+            if (r->opts.locate)
+                r->phase = PH_LOCATE;
+            else
+                done = true;
+        }
+        if (done && status != PCAS_OK) r->rep = r->m.report();
+    } else if (r->phase == PH_LOCATE) {
+        for (int c = 0; c < 3; ++c) r->rep.tumour_mm[c] = sc[24 + c];
+        r->rep.locate_iters = (int32_t)sc[27];
+        done = true;
+    }
+    if (done) {
+        finish_request(S, r, status);   // phase becomes PH_DONE
+        ++*n_done;
+    }
+}
+
 // One pass: the next operation of every request in `set`, batched by kind
 // (one launch per kind, dtype and K or slab axis), one read-back, and every
 // machine advanced.  Finished requests leave with phase PH_DONE.
@@ -214,7 +312,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     Groups<FwdJob, DK> fwds;
     Groups<ResJob, int> ress;
     Groups<AdjJob, DK> adjs;
-    std::vector<Request *> locates;
+    std::vector<Request *> locates, refused;
     for (Request *r : set) {
         const Model &md = S->models[r->model];
         if (r->phase == PH_LOCATE) {
@@ -235,30 +333,35 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             wj.block0 = 0;
             wj.nblocks = warp_blocks(nvox_of(&md.vol));
             warps.add({md.dt, md.K}, wj);
+            // the objective as a solve alone forms it: FP32 from moments about
+            // the reference fit in the projection's last block, FP64 by the
+            // two-pass residual below
+            FitArgs ff = fit_of(*r, op.fixed_ab ? op.ab : nullptr);
+            if (md.dt == PCAS_F32) {
+                ff.a0 = ff.mode == FIT_FIXED ? ff.a : r->ref_a;
+                ff.b0 = ff.mode == FIT_FIXED ? ff.b : r->ref_b;
+            } else {
+                ff.mode = FIT_NONE;
+            }
             fwds.add({md.dt, r->plan.axis},
                      make_fwd_job(md.vd, r->fr, r->plan, r->ws + r->L.rays, r->ws + r->L.f,
-                                  r->proj_slot(op.slot), r->y, r->partials(), &r->counters()[0],
-                                  r->scal()));
+                                  r->proj_slot(op.slot), r->y, ff, r->partials(),
+                                  &r->counters()[0], r->scal()));
+            r->mom_slot = op.slot;
+            r->mom_a0 = ff.a0;
+            r->mom_b0 = ff.b0;
         }
-        if (op.kind == OP_EVAL || op.kind == OP_RESID) {
-            ResJob rj;
-            rj.M = r->M;
-            rj.p = r->proj_slot(op.slot);
-            rj.y = r->y;
-            rj.fa = FitArgs{FIT_FIXED, 1.0, 0.0, r->sy, r->syy, (double)r->M};
-            if (op.fixed_ab) {
-                rj.fa.a = op.ab[0];
-                rj.fa.b = op.ab[1];
-            } else if (r->opts.fit_intensity) {
-                rj.fa.mode = FIT_REFIT;
+        if ((op.kind == OP_EVAL && md.dt != PCAS_F32) || op.kind == OP_RESID) {
+            FitArgs fa = fit_of(*r, op.fixed_ab ? op.ab : nullptr);
+            if (fa.mode == FIT_REFIT) {   // the refit reads the moments of this slot's projection
+                if (op.slot != r->mom_slot) {
+                    refused.push_back(r);
+                    continue;
+                }
+                fa.a0 = r->mom_a0;
+                fa.b0 = r->mom_b0;
             }
-            rj.src = r->scal();
-            rj.partials = r->partials();
-            rj.counter = &r->counters()[3];
-            rj.out = r->scal() + 3;
-            rj.block0 = 0;
-            rj.nblocks = sums_blocks(r->M);
-            ress.add(md.dt, rj);
+            ress.add(md.dt, res_job(*r, op.slot, fa));
         } else if (op.kind == OP_GRAD) {
             adjs.add({md.dt, md.K},
                      make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot), r->y,
@@ -315,74 +418,63 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                           hipMemcpyDeviceToHost, S->s));
     HIPCHK(hipStreamSynchronize(S->s));
 
-    // advance every request of the pass with its results
+    // advance every request of the pass with its results; FP32 evaluations
+    // whose moment sum for J would cancel wait for the two-pass residual
+    std::vector<Request *> redo;
     for (int i = 0; i < na; ++i) {
         Request *r = set[i];
         const double *sc = S->gather_host + i * GATHER;
-        const Model &md = S->models[r->model];
-        bool done = false;
-        int status = PCAS_OK;
-        if (r->phase == PH_PREPARE) {
-            r->sy = sc[16];
-            r->syy = sc[18];
-            if (!isfinite(r->sy) || !isfinite(r->syy)) {
-                status = PCAS_ENONFINITE;
-                done = true;
-            } else if (r->opts.fit_intensity) {
-                const double m = (double)r->M, det = r->syy * m - r->sy * r->sy;
-                if (!(fabs(det) > 1e-12 * r->syy * m)) {
-                    status = PCAS_ESINGULAR;
-                    done = true;
-                }
-            }
-            if (!done) {
-                r->m.start(r->opts, md.K, noise_model(md.dt, r->opts, r->M, r->sy, r->syy),
-                           r->w0);
-                r->phase = PH_RUN;
-            }
-        } else if (r->phase == PH_RUN) {
-            const SolveOp &op = r->m.op();
-            if (op.kind == OP_EVAL || op.kind == OP_RESID) {
-                const double J = sc[3], a = sc[4], b = sc[5];
-                if (!isfinite(a) || !isfinite(b)) {
-                    status = PCAS_ESINGULAR;
-                    done = true;
-                } else if (!isfinite(J)) {
-                    status = PCAS_ENONFINITE;
-                    done = true;
-                } else {
-                    r->m.eval_result(J, a, b);
-                }
-            } else if (op.kind == OP_GRAD) {
-                for (int k = 0; k < md.K; ++k)
-                    if (!isfinite(sc[8 + k])) {
-                        status = PCAS_ENONFINITE;
-                        done = true;
-                    }
-                if (!done) r->m.grad_result(sc + 8);
-            }
-            if (!done && r->m.done()) {
-                r->rep = r->m.report();
-                for (int k = 0; k < md.K; ++k) r->w[k] = r->m.w()[k];
-                if (r->opts.locate)
-                    r->phase = PH_LOCATE;
-                else
-                    done = true;
-            }
-            if (done && status != PCAS_OK) r->rep = r->m.report();
-        } else if (r->phase == PH_LOCATE) {
-            for (int c = 0; c < 3; ++c) r->rep.tumour_mm[c] = sc[24 + c];
-            r->rep.locate_iters = (int32_t)sc[27];
-            done = true;
-        }
-        if (done) {
-            finish_request(S, r, status);   // phase becomes PH_DONE
+        if (std::find(refused.begin(), refused.end(), r) != refused.end()) {
+            host::g_last_error = "serving: refit without moments";
+            finish_request(S, r, PCAS_EHIP);
             ++*n_done;
+            continue;
         }
+        if (r->phase == PH_RUN && r->m.op().kind == OP_EVAL &&
+            S->models[r->model].dt == PCAS_F32 && isfinite(sc[4]) && isfinite(sc[5]) &&
+            !(sc[6] <= MOMENT_KAPPA_MAX)) {
+            redo.push_back(r);
+            continue;
+        }
+        advance(S, r, sc, n_done);
     }
+    if (redo.empty()) return PCAS_OK;
+
+    // the two-pass residual at the fits found, for those evaluations
+    std::vector<ResJob> rj;
+    for (Request *r : redo) {
+        FitArgs fa = fit_of(*r, nullptr);
+        const double *sc = S->gather_host + (std::find(set.begin(), set.end(), r) - set.begin()) * GATHER;
+        fa.mode = FIT_FIXED;
+        fa.a = sc[4];
+        fa.b = sc[5];
+        ResJob j = res_job(*r, r->m.op().slot, fa);
+        j.block0 = 0;
+        rj.push_back(j);
+    }
+    const int nr = (int)redo.size();
+    o = 0;
+    const size_t o_r2 = carve(nr * sizeof(ResJob));
+    int blocks = 0;
+    for (int i = 0; i < nr; ++i) {   // one dtype (FP32): a single launch
+        rj[i].block0 = blocks;
+        blocks += rj[i].nblocks;
+        ((ResJob *)(h + o_r2))[i] = rj[i];
+    }
+    const size_t o_p2 = carve(nr * sizeof(double *));
+    for (int i = 0; i < nr; ++i) ((const double **)(h + o_p2))[i] = redo[i]->scal();
+    const size_t o_g2 = carve(nr * GATHER * sizeof(double));
+    if (o > S->tables_bytes) return hip_fail(hipErrorInvalidValue, "serving tables overflow");
+    HIPCHK(hipMemcpyAsync(S->tables_dev, h, o_g2, hipMemcpyHostToDevice, S->s));
+    HIPCHK(launch_residual_batch(PCAS_F32, (const ResJob *)(d + o_r2), nr, blocks, S->s));
+    HIPCHK(launch_gather_scalars((const double *const *)(d + o_p2), (double *)(d + o_g2), nr,
+                                 GATHER, S->s));
+    HIPCHK(hipMemcpyAsync(S->gather_host, d + o_g2, nr * GATHER * sizeof(double),
+                          hipMemcpyDeviceToHost, S->s));
+    HIPCHK(hipStreamSynchronize(S->s));
+    for (int i = 0; i < nr; ++i) advance(S, redo[i], S->gather_host + i * GATHER, n_done);
     return PCAS_OK;
 }
-
 
 // Relative work of one operation of a request: its warp streams the volume
 // (N voxels) and its projection marches about M * diagonal / step samples.

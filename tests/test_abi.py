@@ -50,10 +50,23 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.pcas_abi_version() == 4
+    assert L.pcas_abi_version() == 5
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.pcas_status_string(code)
     assert L.pcas_last_error() == b""
+
+
+def test_kernel_classes_match_the_header():
+    """The binding's kernel-class names and profile mask follow the header's
+    PCAS_K_* enumeration."""
+    src = open(os.path.join(ROOT, "include", "pcasolve.h")).read()
+    ids = {m.group(1): int(m.group(2)) for m in re.finditer(r"PCAS_K_(\w+) = (\d+)", src)}
+    n = ids.pop("CLASSES")
+    assert n == len(B.KERNEL_CLASSES) and sorted(ids.values()) == list(range(n))
+    assert "#define PCAS_PROFILE_ALL ((1 << PCAS_K_CLASSES) - 1)" in src
+    assert B.PROFILE_ALL == (1 << n) - 1 == B.profile_mask()
+    assert B.profile_mask("drr_adjoint_chain") == 1 << ids["ADJOINT"]
+    assert B.profile_mask("adjoint_bounds", "warp_pca") == (1 << ids["BOUNDS"]) | (1 << ids["WARP"])
 
 
 def test_default_and_paper_options(L):
@@ -185,6 +198,8 @@ def test_solve_option_and_input_validation(L, geom):
     assert call(B.default_opts(locate=1, c0_mm=(0.0, float("nan"), 0.0))) == EINVAL
     assert call(B.default_opts(), K=0) == EINVAL
     assert call(B.default_opts(grad_mode=2)) == EINVAL
+    assert call(B.default_opts(profile=-1)) == EINVAL
+    assert call(B.default_opts(profile=B.PROFILE_ALL + 1)) == EINVAL
     assert L.solve_projection(1, ctypes.byref(v), ctypes.byref(p), 3, FAKE, None, FAKE, FAKE, good_w,
                               None, FAKE, ws, wout, ctypes.byref(rep), None) == EINVAL
 

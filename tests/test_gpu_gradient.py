@@ -95,6 +95,33 @@ def test_clinical_k5_f32_projected(torch):
     assert np.linalg.norm(g - g_o) <= 1e-4 * np.linalg.norm(g_o)
 
 
+@pytest.mark.parametrize("scale", [False, True])
+def test_f32_objective_from_moments_and_fallback(torch, scale):
+    """FP32 forms J in the projection pass from moments about a reference fit,
+    (1, 0) at a solve's first point.  For a measurement 100 y + 50 that sum
+    would cancel (sum r0^2 / J far above 1e4), so exactly one two-pass residual runs;
+    for y itself none does.  Either way J and (a, b) match the oracle."""
+    c = synth.small(dtype="f32", seed=5)
+    d = Dev(c)
+    y = measured(c)
+    if scale:
+        y = 100.0 * y + 50.0
+    yd = to_dev(y, d.dt)
+    y32 = yd.cpu().numpy().astype(np.float64)
+    w = c.w_star + 0.3 * np.array([1.0, -0.5, 0.8])
+    J_o, a_o, b_o, _ = _oracle(c, y32, w, True)
+    J, a, b, _ = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, yd, w)
+    say("scale", scale, "J", J, "oracle", J_o, "a b", a, b, a_o, b_o)
+    assert abs(J - J_o) <= 1e-5 * J_o
+    assert abs(a - a_o) <= 1e-5 * abs(a_o) and abs(b - b_o) <= 1e-5 * max(1.0, abs(b_o))
+    opts = B.default_opts(max_iter=0, xtol=1e-7, profile=B.profile_mask("residual", "drr_forward"))
+    w1, rep = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, yd, w, opts)
+    say("launches", rep["kernel_launches"])
+    assert rep["kernel_launches"]["drr_forward"] == 1
+    assert rep["kernel_launches"]["residual"] == (1 if scale else 0)
+    assert rep["J"] == J and rep["a"] == a and rep["b"] == b
+
+
 @pytest.mark.parametrize("K", [1, 8])
 def test_small_f32_extreme_K(torch, K):
     """FP32 with the fewest and the most modes: the back-projection route

@@ -117,7 +117,10 @@ def test_reported_point_is_consistent(torch, method, extrap):
 @pytest.mark.parametrize("method", [1, 2])
 def test_polish_reported_point_is_consistent(torch, method):
     """FP32 with the polish step (which evaluates into the second projection
-    slot): the returned J, (a, b) and ||g|| are those of the returned w."""
+    slot): the returned J, (a, b) and ||g|| are those of the returned w.  An
+    FP32 objective is summed from moments about a reference fit (the last
+    fit found in a solve, (1, 0) in a single evaluation), so the two agree to
+    rounding rather than bit for bit."""
     c = synth.small(dtype="f32", seed=6)
     d = Dev(c)
     y = measured(c)
@@ -125,7 +128,8 @@ def test_polish_reported_point_is_consistent(torch, method):
     w, rep = _gpu_solve(d, y, B.default_opts(method=method, polish=1, xtol=1e-7))
     J, a, b, g = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w)
     say("gpu", rep, "J", J, "g", g)
-    assert rep["J"] == J and rep["a"] == a and rep["b"] == b
+    assert abs(rep["J"] - J) <= 1e-12 * J
+    assert abs(rep["a"] - a) <= 1e-13 * abs(a) and abs(rep["b"] - b) <= 1e-13 * max(1.0, abs(b))
     assert abs(rep["gnorm"] - np.linalg.norm(g)) <= 1e-12 * np.linalg.norm(g)
 
 
