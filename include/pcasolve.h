@@ -288,13 +288,17 @@ int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *p
                        void *workspace, size_t workspace_bytes, double *out, void *stream);
 
 /* ---- a1-a9: the per-projection solve -------------------------------------
- * Minimise Eq. 2 over w from w0 with the method in opts (Appendix algorithm
- * or CG; see pcas_opts), then optionally locate the tumour.
+ * Minimise Eq. 2 over w from w0 with the method in opts (Appendix algorithm,
+ * CG or BFGS; see pcas_opts), then optionally locate the tumour.
  * f0: device [N]; mean: device [3][N] or NULL; U: device [K][3][N];
  * y: device [nv][nu]; w0: host double[K]; w_out: host double[K];
  * report: host.  workspace: device, solve_projection_workspace() bytes,
  * 256-byte aligned, used exclusively by this call until it returns.
- * Synchronous: returns after the result has been copied to the host.
+ * Synchronous: returns after the result has been copied to the host.  Each
+ * of the solve's read-backs waits by spinning the calling thread on a word
+ * in mapped host memory that a one-wave kernel on `stream` sets after
+ * copying the values; the stream may still be retiring that kernel when the
+ * call returns, and work enqueued on it later runs after it.
  * Returns PCAS_OK (with the stop reason in report->status) or an error. */
 size_t solve_projection_workspace(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
                                   int32_t K);
