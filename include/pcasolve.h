@@ -88,7 +88,10 @@ typedef struct {
 } pcas_proj;
 
 typedef struct {
-    int32_t method;        /* 0: Appendix algorithm (Eq. A.1 + Eq. A.2 + Armijo); 1: PR+ CG;
+    int32_t method;        /* 0: Appendix algorithm (Eq. A.1 + Eq. A.2 + Armijo); 1: PR+ CG
+                              whose line searches start at the minimiser along d of a
+                              quadratic model (curvature d.B d, B built from the accepted
+                              steps by direct BFGS updates; mu0 / ||d|| before it exists);
                               2: BFGS (dense K x K inverse-Hessian estimate); 1 and 2 work on
                               the reduced objective min_{a,b} J and share one line search */
     int32_t max_iter;      /* accepted iterations */
@@ -119,10 +122,12 @@ typedef struct {
                                  g_k = 2 <r, P J_k> (gathers only, no back-projection) */
     double ftol_rel;       /* methods 1, 2: the noise band of J (relative): a rejected trial
                               with |J_t - J| <= ftol_rel J ends the solve as converged, and
-                              method 2 also ends, converged, when its model predicts a
-                              decrease g.H g / 2 <= ftol_rel J while trusting its model (the
-                              last step's decrease was also <= ftol_rel J, or within a factor
-                              2 of the model's prediction for that unit step).  < 0 (default): a rounding
+                              either method also ends, converged, when its model predicts a
+                              decrease <= ftol_rel J for the next first trial (method 2:
+                              g.H g / 2; method 1: (g.d)^2 / (2 d.B d)) while trusting its
+                              model (the last step's decrease was also <= ftol_rel J, or
+                              within a factor 2 of the model's prediction for that step, when
+                              it was accepted at its first trial).  < 0 (default): a rounding
                               model per point, 6 u sqrt(sum p^2 / (M J)) with u = 2^-24 for
                               PCAS_F32 and 2^-53 for PCAS_F64 (three times the spread of J
                               that rounding each p_i by u |p_i| produces) */

@@ -432,17 +432,46 @@ def _line_search(prob, o, w, phi, d, gd, t):
     return "fail", t, None, None, None, None, None, n
 
 
+def curvature_update(B, s, y):
+    """Direct BFGS update of a Hessian estimate (Nocedal and Wright,
+    Numerical Optimization, Eq. 6.19): B+ = B - (B s)(B s)^T / (s.B s) +
+    y y^T / (y.s).  B+ satisfies the secant equation B+ s = y and stays
+    symmetric positive definite when y.s > 0."""
+    Bs = B @ s
+    return B - np.outer(Bs, Bs) / float(s @ Bs) + np.outer(y, y) / float(y @ s)
+
+
+def _curvature_estimate(B, s_k, y_k):
+    """solve_cg's curvature estimate after an accepted step: (y.y / y.s) I at
+    the first usable pair (the reciprocal of Eq. 6.20's scaling), then
+    curvature_update; pairs with y.s <= 1e-12 |s| |y| skipped."""
+    sy = float(s_k @ y_k)
+    if sy > 1e-12 * float(np.linalg.norm(s_k)) * float(np.linalg.norm(y_k)):
+        if B is None:
+            B = (float(y_k @ y_k) / sy) * np.eye(s_k.size)
+        B = curvature_update(B, s_k, y_k)
+    return B
+
+
 def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     """PR+ nonlinear CG on phi(w) = min_{a,b} J(w, a, b).
 
     phi's gradient is dJ/dw at the fitted (a, b) (the fit is an exact
-    minimiser, Eq. A.1).  The first trial step is mu0/||d|| on the first
-    iteration; afterwards it minimises the quadratic model along d with the
-    curvature the last accepted step measured, c = (s.y) / (s.s) for the
-    step s and gradient change y: t = -(g.d) / (c ||d||^2), or, when s.y <= 0,
-    t_prev (g_prev.d_prev) / (g.d).  It is searched with _line_search.  A
-    failed search restarts along -g once; a second failure ends the
-    solve."""
+    minimiser, Eq. A.1).  The directions are PR+ CG's; each is searched
+    with _line_search.  Its first trial step minimises the quadratic model
+    along d: t = -(g.d) / (d.B d), with B the curvature estimate that
+    _curvature_estimate builds from the accepted steps s and gradient
+    changes y.  Before B exists the first trial is mu0/||d|| on the first
+    iteration, else t = -(g.d) / (c ||d||^2) with the curvature c =
+    (s.y) / (s.s) the last accepted step measured, or, when s.y <= 0,
+    t_prev (g_prev.d_prev) / (g.d).
+
+    With the model's first trial, its predicted decrease -(g.d) t / 2 within
+    ftol_rel of phi ends the solve as converged when the model is trusted:
+    the last accepted decrease was within ftol_rel of phi too, or, for a
+    step accepted at the model's first trial, within a factor 2 of the
+    decrease predicted for it (solve_bfgs's stop).  A failed search restarts
+    along -g once; a second failure ends the solve."""
     o = opts or SolveOptions()
     w = _f64(w0).copy()
     rep = SolveReport()
@@ -457,7 +486,9 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
     restart, first = True, True
     t_prev = gd_prev = 0.0
     curv = 0.0                                         # (s.y) / (s.s) of the last accepted step
+    B = None                                           # curvature estimate
     H = None                                           # for the polish step only
+    last_drop, last_pred = float("inf"), -1.0
     floor = False                                      # ended at the noise floor
     it = 0
     rep.status = STOP_MAXITER
@@ -471,12 +502,23 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
             d = -g
             gd = -gn * gn
             restart = True
-        if first:
+        dbd = float(d @ (B @ d)) if B is not None else 0.0
+        pred = -1.0
+        if dbd > 0.0:
+            t = -gd / dbd
+            pred = -0.5 * gd * t
+            if pred <= o.ftol_rel * phi and (
+                    last_drop <= o.ftol_rel * phi or 0.5 * last_pred <= last_drop <= 2.0 * last_pred):
+                rep.status = STOP_CONVERGED
+                floor = True
+                break
+        elif first:
             t = o.mu0 / float(np.linalg.norm(d))
         elif curv > 0.0:
             t = -gd / (curv * float(d @ d))
         else:
             t = t_prev * gd_prev / gd
+        t0 = t
         st, t, w_t, phi_t, a_t, b_t, r_t, n = _line_search(prob, o, w, phi, d, gd, t)
         rep.n_fevals += n
         if st == "noise":
@@ -496,8 +538,11 @@ def solve_cg(prob: Problem, w0, opts: Optional[SolveOptions] = None):
         s_k, y_k = w_t - w, g_new - g
         ss = float(s_k @ s_k)
         curv = float(s_k @ y_k) / ss if ss > 0.0 else 0.0
+        B = _curvature_estimate(B, s_k, y_k)
         if o.polish:
             H = _hessian_update(H, s_k, y_k)
+        last_pred = pred if t == t0 else -1.0
+        last_drop = phi - phi_t
         w, phi, a, b, r = w_t, phi_t, a_t, b_t, r_t
         beta_pr = max(0.0, float(g_new @ (g_new - g)) / float(g @ g))
         d = -g_new + beta_pr * d

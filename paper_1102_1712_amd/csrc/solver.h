@@ -149,6 +149,41 @@ private:
             for (int j = 0; j < K; ++j)
                 H[i * PCAS_MAX_K + j] += c * sv[i] * sv[j] - rho * (sv[i] * hy[j] + hy[i] * sv[j]);
     }
+    // CG's curvature estimate after an accepted step: (y.y / y.s) I at the
+    // first usable pair, then the direct BFGS update
+    //   B+ = B - (B s)(B s)^T / (s.B s) + y y^T / (y.s);
+    // a pair with y.s <= 1e-12 |s| |y| is skipped.
+    void curvature_update(double *B, bool &have, const double *sv, const double *yv) {
+        const int K = K_;
+        const double sy = dot(sv, yv, K), yy = dot(yv, yv, K);
+        if (!(sy > 1e-12 * sqrt(dot(sv, sv, K)) * sqrt(yy))) return;
+        if (!have) {
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) B[i * PCAS_MAX_K + j] = i == j ? yy / sy : 0.0;
+            have = true;
+        }
+        double bs[PCAS_MAX_K];
+        for (int i = 0; i < K; ++i) {
+            double v = 0.0;
+            for (int j = 0; j < K; ++j) v += B[i * PCAS_MAX_K + j] * sv[j];
+            bs[i] = v;
+        }
+        const double sbs = dot(sv, bs, K);
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j)
+                B[i * PCAS_MAX_K + j] += -bs[i] * bs[j] / sbs + yv[i] * yv[j] / sy;
+    }
+    // d.B d (B applied first, then the dot with d).
+    double quad_form(const double *B, const double *v) const {
+        const int K = K_;
+        double bv[PCAS_MAX_K];
+        for (int i = 0; i < K; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < K; ++j) s += B[i * PCAS_MAX_K + j] * v[j];
+            bv[i] = s;
+        }
+        return dot(v, bv, K);
+    }
     // A solve that stops at the noise floor (noise or decrement stop, failed
     // search) may take the polish step first.
     void end_at_floor(int status) {
@@ -236,6 +271,12 @@ private:
                 break;
 
             // ---- PR+ nonlinear CG on the reduced objective ----------------
+            // PR+ directions, each searched by the line search above from the
+            // minimiser of the quadratic model along d.  The model's
+            // curvature is a Hessian estimate B built from the accepted steps
+            // by direct BFGS updates (used for step lengths only; the
+            // directions stay CG's).  A predicted decrease within the noise
+            // floor ends the solve when the model is trusted, as in BFGS.
             case CG_START:
                 want_eval(w_, false, 1.0, 0.0, CG_AFTER_EVAL0);
                 return;
@@ -257,7 +298,9 @@ private:
                 restart_ = first_ = true;
                 t_prev_ = gd_prev_ = 0.0;
                 curv_ = 0.0;
-                have_hc_ = have_h_ = false;
+                have_hc_ = have_h_ = have_b_ = false;
+                last_drop_ = INFINITY;
+                last_pred_ = -1.0;
                 it_ = 0;
                 rep_.status = PCAS_STOP_MAXITER;
                 pc_ = CG_LOOP;
@@ -281,13 +324,32 @@ private:
                 }
                 dn_ = sqrt(dot(d_, d_, K));
                 // first trial: the quadratic model's minimiser along d with the
-                // curvature the last accepted step measured, (s.y) / (s.s)
-                if (first_)
-                    t_ = o_.mu0 / dn_;
-                else if (curv_ > 0.0)
-                    t_ = -gd_ / (curv_ * dn_ * dn_);
-                else
-                    t_ = t_prev_ * gd_prev_ / gd_;
+                // curvature estimate B, -(g.d) / (d.B d); before B exists,
+                // mu0 / ||d|| first, then with the curvature the last accepted
+                // step measured, (s.y) / (s.s)
+                {
+                    const double dbd = have_b_ ? quad_form(B_, d_) : 0.0;
+                    pred_ = -1.0;
+                    if (dbd > 0.0) {
+                        t_ = -gd_ / dbd;
+                        pred_ = -0.5 * gd_ * t_;
+                        // the model's decrease below the noise, and the model
+                        // trusted (as in BFGS): stop
+                        if (pred_ <= nu_ * phi_ &&
+                            (last_drop_ <= nu_ * phi_ ||
+                             (0.5 * last_pred_ <= last_drop_ && last_drop_ <= 2.0 * last_pred_))) {
+                            end_at_floor(PCAS_STOP_CONVERGED);
+                            break;
+                        }
+                    } else if (first_) {
+                        t_ = o_.mu0 / dn_;
+                    } else if (curv_ > 0.0) {
+                        t_ = -gd_ / (curv_ * dn_ * dn_);
+                    } else {
+                        t_ = t_prev_ * gd_prev_ / gd_;
+                    }
+                }
+                t0_ = t_;
                 line_search(CG_LS_END);
                 break;
             }
@@ -310,6 +372,8 @@ private:
                     wprev_[k] = w_[k];
                     w_[k] = wt_[k];
                 }
+                last_pred_ = t_ == t0_ ? pred_ : -1.0;
+                last_drop_ = phi_ - phi_t_;
                 phi_ = phi_t_;
                 a_ = a_t_;
                 b_ = b_t_;
@@ -325,6 +389,7 @@ private:
                     }
                     const double ss = dot(sv, sv, K);
                     curv_ = ss > 0.0 ? dot(sv, yv, K) / ss : 0.0;
+                    curvature_update(B_, have_b_, sv, yv);
                     if (o_.polish) hessian_update(Hc_, have_hc_, sv, yv);   // polish only
                 }
                 double num = 0.0;
@@ -619,14 +684,16 @@ private:
     double wprev_[PCAS_MAX_K] = {0};
     double g_[PCAS_MAX_K] = {0}, d_[PCAS_MAX_K] = {0};
     double H_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // BFGS inverse-Hessian estimate (row-major)
+    double B_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // CG: Hessian (curvature) estimate (row-major)
     double Hc_[PCAS_MAX_K * PCAS_MAX_K] = {0};  // estimate kept for the polish step
     double phi_ = 0.0, a_ = 0.0, b_ = 0.0, phi_t_ = 0.0, a_t_ = 0.0, b_t_ = 0.0;
     double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, tx_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
     double curv_ = 0.0;   // CG: (s.y) / (s.s) of the last accepted step
-    double last_drop_ = 0.0;   // BFGS: J decrease of the last accepted step
-    double last_pred_ = -1.0;  // BFGS: the model's prediction of it (< 0: none)
+    double t0_ = 0.0, pred_ = -1.0;   // CG: first trial step, the model's decrease for it
+    double last_drop_ = 0.0;   // CG, BFGS: J decrease of the last accepted step
+    double last_pred_ = -1.0;  // CG, BFGS: the model's prediction of it (< 0: none)
     double J_ = 0.0, gn_ = 0.0, mu_ = 0.0;
-    bool restart_ = true, first_ = true, have_h_ = false, have_hc_ = false;
+    bool restart_ = true, first_ = true, have_h_ = false, have_hc_ = false, have_b_ = false;
     int it_ = 0, bt_ = 0, ls_slot_ = 0;
     LsOutcome ls_ = LS_FAIL;
     Pc ls_ret_ = FINISHED;
