@@ -248,6 +248,19 @@ int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, co
  * Returns a negative value for an invalid volume or projection. */
 double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj);
 
+/* Per-brick bounds of the back-projection of the all-ones image: the pass
+ * the solver runs once per projection to size the FP32 gradient's 32-bit
+ * accumulators.  The volume is cut into 16 x 16 x 8 voxel bricks (brick x
+ * fastest, then y, then z); bounds_out: device float[backprojection_brick_count
+ * (vol)], each at least the largest (P^T 1)(v) over the brick's voxels, with
+ * P^T drr_adjoint's operator and 1 the all-ones image (rounded up; 0 where no
+ * sample reaches the brick).  rays: ray_table() output for (vol, proj) in
+ * dtype.  Asynchronous on `stream`.  backprojection_brick_count returns -1
+ * for an invalid volume. */
+int32_t backprojection_brick_count(const pcas_vol *vol);
+int backprojection_brick_bounds(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
+                                const void *rays, float *bounds_out, void *stream);
+
 /* ---- a5: intensity fit (Eq. A.1) and residual ----------------------------
  * stats_out: device double[8] =
  *   { J, a, b, sum p, sum p*y, sum p*p, sum y, sum y*y }

@@ -624,9 +624,14 @@ __device__ __forceinline__ unsigned long long fixed_of(double v) {
 // from the measured per-brick bound).  A voxel near the source takes ~10^4
 // adds at ~20 bits each; truncation's bias (half a unit per add, one sign
 // where the residual is smooth) would add up with the count, rounding's
-// errors only with its square root.
+// errors only with its square root.  v_cvt_rpi_i32_f32 gives floor(v + 0.5)
+// in one instruction (ties go up; on gfx950 it matched the exact value for
+// 4M floats from 2^-2 to 2^30, ties included), against a round and a
+// convert: this conversion runs eight times per sample.
 __device__ __forceinline__ unsigned int fixed32_of(float v) {
-    return (unsigned int)(int)__builtin_rintf(v);
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return (unsigned int)r;
 }
 __device__ __forceinline__ long long acc_value(unsigned int a) { return (long long)(int)a; }
 __device__ __forceinline__ long long acc_value(unsigned long long a) { return (long long)a; }
@@ -707,8 +712,11 @@ __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__re
 // which adds 32-bit fixed point (half the LDS traffic and bank conflicts).
 // Its scale comes from bounds[]: every voxel total of a brick, halo slots
 // included, is at most max|r| times the largest (P^T 1) of the brick and its
-// 26 neighbours, and S keeps that below 2^31.
-template <typename T, bool FORM_R, int K>
+// 26 neighbours, and S keeps that below 2^31.  The FP32 bound pass (B32,
+// K = 0) accumulates in 32 bits too, scaled by the analytic bound on any
+// voxel total that the 64-bit path uses (50-140 times the measured maxima),
+// and counts its samples for the rounding slack of its maxima.
+template <typename T, bool FORM_R, int K, bool B32 = false>
 __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame &fr, int nbx,
                                                   int nby, double hb, double vb,
                                                   const float *__restrict__ bounds,
@@ -722,7 +730,8 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                                                   double *__restrict__ partials,
                                                   uint32_t *counter, double *__restrict__ g_out,
                                                   int lb, int nb) {
-    constexpr bool ACC32 = std::is_same<T, float>::value && K > 0;
+    constexpr bool ACC32 = std::is_same<T, float>::value && (K > 0 || B32);
+    constexpr bool COUNT = ACC32 && K == 0;   // the bound pass counts its samples
     using AccT = typename std::conditional<ACC32, unsigned int, unsigned long long>::type;
     __shared__ AccT acc[ACC_WORDS];
     __shared__ T q_f[ADJ_WAVES][7][QCAP];       // e[3], d[3], scaled dt * r
@@ -787,7 +796,15 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     rmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     const double C = fr.step * rmax * (1.0 + 1e-6);
     double Sd = 0.0;
-    if constexpr (ACC32) {
+    if constexpr (COUNT) {
+        // all-ones image: totals <= C min(hb npix, vb), as bounded for 64 bits
+        if (C > 0.0) {
+            const double lim = 2147483648.0 * (1.0 - 1.0 / 4096.0) / (C * fmin(hb * (double)npix, vb));
+            int ex;
+            frexp(fmin(lim, 1e300), &ex);
+            Sd = ldexp(0.5, ex);
+        }
+    } else if constexpr (ACC32) {
         // largest (P^T 1) over the brick and its neighbours (halo slots hold
         // parts of the neighbours' voxel totals)
         double bmax = 0.0;
@@ -830,6 +847,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     bool busy = false;
     T e[3] = {0, 0, 0}, d[3] = {0, 0, 0}, cst = (T)0, sh = (T)0;
     int s = 0, s_end = -1;
+    unsigned nsamp = 0;   // COUNT: samples this lane accumulated
     __syncthreads();   // accumulator cleared
     for (;;) {
         // top up the queue while a whole tile of candidates fits
@@ -885,6 +903,11 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
             }
         }
         head += min(__popcll(idle), avail);
+        // Wait for the refill's LDS reads here, once per run: otherwise every
+        // sample of the run below waits for all LDS operations in flight (the
+        // previous sample's eight adds included), because along the path where
+        // a lane had no sample the reads would still be outstanding.
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt and expcnt unconstrained
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (__ballot(busy) == 0ull) {
@@ -914,6 +937,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                     atomicAdd(pa + ACC_ZP + 1, acc_image<ACC32>(w01 * xb));
                     atomicAdd(pa + ACC_ZP + ACC_YP, acc_image<ACC32>(w11 * xa));
                     atomicAdd(pa + ACC_ZP + ACC_YP + 1, acc_image<ACC32>(w11 * xb));
+                    if constexpr (COUNT) ++nsamp;
                 }
                 sh += (T)1;
                 busy = ++s <= s_end;
@@ -929,7 +953,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
             const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
             const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
             if (i < n0 && j < n1 && k < n2) {
-                const long long v = (long long)acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)];
+                const long long v = acc_value(acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)]);
                 if (bound_out)
                     vmax = v > vmax ? v : vmax;
                 else
@@ -937,14 +961,25 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
             }
         }
         if (bound_out) {
-            // each truncated addend is low by < 1 unit; 1e-6 more covers the
-            // rounding of dt * weight in T
+            // 64 bits: each truncated addend is low by < 1 unit (65536 covers
+            // that many adds per voxel); 32 bits (COUNT): each rounded addend
+            // is off by <= 1/2 unit, and a voxel takes at most one add per
+            // sample of the brick (a sample's eight corners are distinct).
+            // 1e-6 more covers the rounding of dt * weight in T.
             double m = wave_max((double)vmax);
+            double ns = COUNT ? wave_sum((double)nsamp) : 0.0;
             if (lane == 0) red[wave] = m;
             __syncthreads();
+            m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            __syncthreads();
+            if constexpr (COUNT) {
+                if (lane == 0) red[wave] = ns;
+                __syncthreads();
+                ns = red[0] + red[1] + red[2] + red[3];
+            }
             if (tid == 0) {
-                m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-                const double vb_brick = m > 0.0 ? (m + 65536.0) * inv_S * (1.0 + 1e-6) : 0.0;
+                const double slack = COUNT ? 0.5 * ns + 1.0 : 65536.0;
+                const double vb_brick = m > 0.0 ? (m + slack) * inv_S * (1.0 + 1e-6) : 0.0;
                 bound_out[bid] = __double2float_ru(vb_brick);
             }
         }
@@ -1006,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_adjoint_bounds(VolDims vd, Frame fr, in
                                                         const RayRec<T> *__restrict__ rays,
                                                         float *__restrict__ bound_out) {
     const WVec w{};
-    drr_adjoint_block<T, false, 0>(vd, fr, nbx, nby, hb, vb, nullptr, bound_out, rays, nullptr,
+    drr_adjoint_block<T, false, 0, true>(vd, fr, nbx, nby, hb, vb, nullptr, bound_out, rays, nullptr,
                                    nullptr, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr, w,
                                    nullptr, nullptr, nullptr, blockIdx.x, gridDim.x);
 }

@@ -196,3 +196,34 @@ def test_errors(torch):
     flat = torch.ones_like(y)
     with pytest.raises(B.PcasError):
         B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, flat, c.w_star)
+
+
+def _brick_max(v):
+    """Largest value per 16 x 16 x 8 brick of a [n3][n2][n1] array (x fastest)."""
+    n2, n1, n0 = v.shape
+    bz, by, bx = -(-n2 // 8), -(-n1 // 16), -(-n0 // 16)
+    pad = np.zeros((bz * 8, by * 16, bx * 16))
+    pad[:n2, :n1, :n0] = v
+    return pad.reshape(bz, 8, by, 16, bx, 16).max(axis=(1, 3, 5)).reshape(-1)
+
+
+@pytest.mark.parametrize("name", ["small", *sorted(STRESS)])
+def test_brick_bounds_cover_oracle_back_projection(torch, name):
+    """The per-brick bounds that size the FP32 gradient's 32-bit accumulators
+    (computed with 32-bit accumulators themselves) cover the oracle's P^T 1
+    in every brick, and are tight: within 1% (the rounding slack)."""
+    if name == "small":
+        c = synth.small(dtype="f32", seed=9)
+    else:
+        g = dict(STRESS[name])
+        n, spacing, det, pitch, step = g.pop("n"), g.pop("spacing"), g.pop("det"), g.pop("pitch"), g.pop("step")
+        c = synth.make_case(f"stress-{name}", n, spacing, det, pitch, step, 3, "f32", 31, **g)
+    d = Dev(c)
+    say("brick bounds", name)
+    got = B.backprojection_brick_bounds(c.vol, c.proj, d.rays).cpu().numpy().astype(np.float64)
+    ref = _brick_max(O.drr_adjoint(c.vol, c.proj, np.ones((c.proj.nv, c.proj.nu))))
+    assert got.shape == ref.shape
+    say("max", ref.max(), "ratio range", (got[ref > 0] / ref[ref > 0]).min(), (got[ref > 0] / ref[ref > 0]).max())
+    # FP32 ray parameters move samples by ~1e-7 against the FP64 oracle's
+    assert np.all(got >= ref * (1.0 - 1e-5) - 1e-6 * ref.max())
+    assert np.all(got <= ref * 1.1 + 1e-6 * ref.max())
