@@ -308,6 +308,37 @@ struct Profile {
     }
 };
 
+// A second stream (default priority) per thread and device, with two
+// events, on which a solve runs its geometry-only bound pass while its first
+// evaluation runs on the caller's stream.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    int device = -1;
+};
+
+inline AuxStream *aux_stream() {
+    thread_local AuxStream a;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (a.s && a.device == dev) return &a;
+    if (a.s) {   // another device: this thread's streams follow the current one
+        (void)hipStreamDestroy(a.s);
+        (void)hipEventDestroy(a.ready);
+        (void)hipEventDestroy(a.done);
+        a = AuxStream{};
+    }
+    if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&a.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&a.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(a.s);
+        a = AuxStream{};
+        return nullptr;
+    }
+    a.device = dev;
+    return &a;
+}
+
 struct Solver {
     pcas_dtype dt;
     VolDims vd;
@@ -329,19 +360,31 @@ struct Solver {
     int mom_slot = -1;
     double mom_a0 = 0.0, mom_b0 = 0.0;
     Profile prof;
+    // The bound pass runs on aux->s until the first gradient (or the end of
+    // the call) makes the solve's stream wait for it.
+    AuxStream *aux = nullptr;
+    bool bounds_pending = false;
+
+    ~Solver() { (void)join_bounds(); }
+    hipError_t join_bounds() {
+        if (!bounds_pending) return hipSuccess;
+        bounds_pending = false;
+        return hipStreamWaitEvent(s, aux->done, 0);
+    }
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
 
-    template <class F> hipError_t timed(int cls, F &&launch) {
+    template <class F> hipError_t timed(int cls, F &&launch) { return timed_on(s, cls, launch); }
+    template <class F> hipError_t timed_on(hipStream_t st, int cls, F &&launch) {
         if (!(prof.mask >> cls & 1u)) return launch();
         hipEvent_t a, b;
         hipError_t e;
         const size_t ia = prof.next++, ib = prof.next++;
         if ((e = prof.event(ia, &a)) != hipSuccess || (e = prof.event(ib, &b)) != hipSuccess) return e;
-        if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(a, st)) != hipSuccess) return e;
         if ((e = launch()) != hipSuccess) return e;
-        if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(b, st)) != hipSuccess) return e;
         prof.pending.push_back({cls, ia, ib});
         return hipSuccess;
     }
@@ -451,6 +494,7 @@ struct Solver {
                                               &counters()[1], scal() + 8, s);
             }));
         } else {
+            HIPCHK(join_bounds());
             // back-projection and Jacobian chain in one pass (bp stays on chip)
             HIPCHK(timed(PCAS_K_ADJOINT, [&] {
                 return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, proj_slot(slot), y, a, b, f0,
@@ -491,10 +535,24 @@ struct Solver {
         prof.mask = profile;
         HIPCHK(launch_fill_u32(counters(), 64, 0u, s));
         HIPCHK(timed(PCAS_K_RAYS, [&] { return launch_ray_table(dt, vd, fr, ws + L.rays, s); }));
-        if (dt == PCAS_F32 && grad_mode == 1)
-            HIPCHK(timed(PCAS_K_BOUNDS, [&] {
-                return launch_backprojection_bounds(dt, vd, fr, ws + L.rays, bounds(), s);
+        if (dt == PCAS_F32 && grad_mode == 1) {
+            // geometry only: overlapped with the y sums and the first
+            // evaluation on a second stream where one is available
+            aux = aux_stream();
+            hipStream_t bs = s;
+            if (aux) {
+                HIPCHK(hipEventRecord(aux->ready, s));
+                HIPCHK(hipStreamWaitEvent(aux->s, aux->ready, 0));
+                bs = aux->s;
+            }
+            HIPCHK(timed_on(bs, PCAS_K_BOUNDS, [&] {
+                return launch_backprojection_bounds(dt, vd, fr, ws + L.rays, bounds(), bs);
             }));
+            if (aux) {
+                HIPCHK(hipEventRecord(aux->done, aux->s));
+                bounds_pending = true;
+            }
+        }
         // sums of the measured image: (sum y, sum y^2, ., ., .)
         HIPCHK(timed(PCAS_K_YSUMS, [&] {
             return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],
