@@ -49,17 +49,28 @@ __device__ __forceinline__ bool voxel_jacobian(const T *__restrict__ f0, int n0,
     return true;
 }
 
-// x = xbar + U w at voxel v and the modes' three components there.
-template <typename T, int K>
+template <bool NT, typename T> __device__ __forceinline__ T load_once(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+// x = xbar + U w at voxel v and the modes' three components there.  NT: the
+// loads are non-temporal, for voxel-stream kernels whose lanes read whole
+// cache lines of mean and U exactly once.  A brick's write-out reads half
+// lines whose other halves a neighbouring brick reads later, so it keeps
+// ordinary loads (non-temporal ones measured 3% slower there).
+template <typename T, int K, bool NT>
 __device__ __forceinline__ void voxel_field(const T *__restrict__ mean, const T *__restrict__ U,
                                             const T (&wk)[K], int64_t N, int64_t v, T (&u)[K][3],
                                             T (&x)[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        x[c] = mean ? mean[c * N + v] : (T)0;
+        x[c] = mean ? load_once<NT>(&mean[c * N + v]) : (T)0;
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
-            u[kk][c] = U[(int64_t)(kk * 3 + c) * N + v];
+            u[kk][c] = load_once<NT>(&U[(int64_t)(kk * 3 + c) * N + v]);
             x[c] = fma_t(wk[kk], u[kk][c], x[c]);
         }
     }

@@ -1002,7 +1002,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                 if (bpv == (T)0) continue;
                 const int64_t vox = i + s1 * j + s2 * k;
                 T u[K][3], x[3], jac[3];
-                voxel_field<T, K>(mean, U, wk, N, vox, u, x);
+                voxel_field<T, K, false>(mean, U, wk, N, vox, u, x);
                 if (!voxel_jacobian(f0, n0, n1, n2, i, j, k, x, is0, is1, is2, jac)) continue;
                 const T j0 = jac[0] * bpv, j1 = jac[1] * bpv, j2 = jac[2] * bpv;
 #pragma unroll

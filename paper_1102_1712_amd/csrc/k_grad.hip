@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_grad_w(VolDims vd, const T *__restrict_
         const int j = (int)((v / n0) % n1);
         const int k = (int)(v / s2);
         T u[K][3], x[3], jac[3];
-        voxel_field<T, K>(mean, U, wk, N, v, u, x);
+        voxel_field<T, K, true>(mean, U, wk, N, v, u, x);
         if (!voxel_jacobian(f0, n0, n1, n2, i, j, k, x, is0, is1, is2, jac)) continue;
         const T j0 = jac[0] * bpv, j1 = jac[1] * bpv, j2 = jac[2] * bpv;
 #pragma unroll
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_jacobian(VolDims vd, const T *__restric
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) wk[kk] = (T)w.w[kk];
     T u[K][3], x[3], jac[3];
-    voxel_field<T, K>(mean, U, wk, N, v, u, x);
+    voxel_field<T, K, true>(mean, U, wk, N, v, u, x);
     if (!voxel_jacobian(f0, n0, n1, n2, i, j, k, x, (T)vd.inv_s[0], (T)vd.inv_s[1],
                         (T)vd.inv_s[2], jac)) {
         jac[0] = jac[1] = jac[2] = (T)0;

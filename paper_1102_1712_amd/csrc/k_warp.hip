@@ -86,20 +86,25 @@ __device__ __forceinline__ void warp_pca_block(const VolDims &vd, const T *__res
                                                const T *__restrict__ mean,
                                                const T *__restrict__ U, const WVec &w,
                                                T *__restrict__ f, int lb, int nb) {
+    // 32-bit index arithmetic (volumes are limited to 2^31 voxels); mean and
+    // U are read once, so their loads are non-temporal and leave the caches
+    // to the f0 neighbourhoods that neighbouring lanes share
     const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
-    const int64_t b = xcd_remap(lb, nb);
-    const int64_t v = b * blockDim.x + threadIdx.x;
-    if (v >= N) return;
-    const int i = (int)(v % vd.n0);
-    const int j = (int)((v / vd.n0) % vd.n1);
-    const int k = (int)(v / ((int64_t)vd.n0 * vd.n1));
+    const int b = xcd_remap(lb, nb);
+    const int v32 = b * (int)blockDim.x + (int)threadIdx.x;
+    if (v32 >= (int)N) return;
+    const int64_t v = v32;
+    const unsigned q = (unsigned)v32 / (unsigned)vd.n0;
+    const int i = v32 - (int)q * vd.n0;
+    const int k = (int)(q / (unsigned)vd.n1);
+    const int j = (int)q - k * vd.n1;
     T x[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        x[c] = mean ? mean[c * N + v] : (T)0;
+        x[c] = mean ? __builtin_nontemporal_load(&mean[c * N + v]) : (T)0;
 #pragma unroll
         for (int kk = 0; kk < K; ++kk)
-            x[c] = fma_t((T)w.w[kk], U[(int64_t)(kk * 3 + c) * N + v], x[c]);
+            x[c] = fma_t((T)w.w[kk], __builtin_nontemporal_load(&U[(int64_t)(kk * 3 + c) * N + v]), x[c]);
     }
     f[v] = warp_gather(f0, vd.n0, vd.n1, vd.n2, i, j, k, x[0], x[1], x[2], (T)vd.inv_s[0],
                        (T)vd.inv_s[1], (T)vd.inv_s[2]);
