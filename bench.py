@@ -831,6 +831,15 @@ def main() -> int:
               "J_rel_diff_vs_cg": float((rep_qn["J"] - rep["J"]) / rep["J"])}
         log(f"quasi-Newton: p50 {qn['p50_ms']:.3f} ms, {qn['n_fevals']} evaluations")
 
+    # how far the noise-band stop leaves w from the minimiser: against one
+    # BFGS solve with the polish step (a quasi-Newton step from the gradient,
+    # which resolves the minimiser below the noise of J)
+    w_pol, rep_pol = step(B.default_opts(**{**base, "method": 2, "polish": 1}))
+    stop = {"w_rel_diff_vs_polished": float(np.linalg.norm(w - w_pol) / np.linalg.norm(w_pol)),
+            "J_rel_diff_vs_polished": float((rep["J"] - rep_pol["J"]) / rep_pol["J"]),
+            "polished_gnorm_rel": float(rep_pol["gnorm"] / rep_pol["gnorm0"])}
+    log(f"stop resolution: {stop}")
+
     # the same solve at seeded random gantry angles, each with its own
     # measured projection (same recipe: P f(w*) + 1% noise)
     rand = random_angles(case, dev, dt, args, base) if args.angles > 0 else None
@@ -867,7 +876,7 @@ def main() -> int:
                    "samples_per_drr": S, "angle_rad": case.proj.angle},
         "solve": {"iters": rep["iters"], "n_fevals": rep["n_fevals"], "n_grads": rep["n_grads"],
                   "status": rep["status"], "w_rel_err_vs_planted": werr,
-                  "tumour_mm": rep["tumour_mm"]},
+                  "tumour_mm": rep["tumour_mm"], **stop},
         "drr_gsamples_s": drr.get("Gsamples_s"),
         "adjoint_gsamples_s": adj.get("Gsamples_s"),
         "drr_effective_hbm_frac": (drr.get("effective_GBs", 0) / HBM_PEAK_GBS) if drr else None,
