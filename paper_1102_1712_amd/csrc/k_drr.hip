@@ -7,7 +7,7 @@
 // lines.  The partial sums of a ray are combined by a fixed butterfly.
 //
 // Adjoint: the exact transpose of the forward without global atomics.  A
-// 256-thread workgroup owns a 16 x 16 x 8 voxel brick held in LDS.  It
+// 512-thread workgroup owns a 16 x 16 x 8 voxel brick held in LDS.  It
 // visits every ray whose pixel lies in the detector footprint of the brick
 // (plus a one-voxel apron), re-creates exactly the samples of that ray whose
 // 2x2x2 cell touches the brick (same ray record, same sample_cell
@@ -603,7 +603,11 @@ __device__ __forceinline__ double wave_max(double v) {
 constexpr int ACC_YP = BRICK_X + 2;
 constexpr int ACC_ZP = (BRICK_Y + 2) * ACC_YP + 1;
 constexpr int ACC_WORDS = (BRICK_Z + 2) * ACC_ZP;
-constexpr int ADJ_WAVES = 4;   // waves sharing one brick
+// Waves sharing one brick (each with its own ray queue).  8: 32 waves per
+// CU (the VGPR limit) in 4 bricks, against 28 in 7 bricks with 4 waves; the
+// fused gradient kernel measured 410 against 431 us, 2 waves 582 us.
+constexpr int ADJ_WAVES = 8;
+constexpr int ADJ_THREADS = 64 * ADJ_WAVES;
 // Ring queue of rays per wave (a power of two, at least one 64-ray tile).
 // 64 rather than 128 entries: the queues are most of a block's LDS, and
 // the smaller ones let 7 instead of 5 blocks share a CU (the fused gradient
@@ -752,7 +756,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                        min(lo[2] + BRICK_Z, n2) - 1};
     const int nn[3] = {n0, n1, n2};
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int t = tid; t < ACC_WORDS; t += 256) acc[t] = 0;
+    for (int t = tid; t < ACC_WORDS; t += ADJ_THREADS) acc[t] = 0;
 
     // Detector footprint of the region whose samples can reach the brick:
     // index box [lo - 1, hi + 1] clipped to the grid, projected through its
@@ -790,14 +794,14 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     // fixed_of's conversion is in range) and the latter below 2^62 (no 64-bit
     // overflow), and is a power of two, so scaling dt * r by it is exact.
     double rmax = 0.0;
-    for (int t = tid; t < npix; t += 256) {
+    for (int t = tid; t < npix; t += ADJ_THREADS) {
         const int pix = (iv0 + t / W) * fr.nu + (iu0 + t % W);
         rmax = fmax(rmax, fabs((double)residual_at<T, FORM_R>(rp, y, a, b, pix)));
     }
     rmax = wave_max(rmax);
     if (lane == 0) red[wave] = rmax;
     __syncthreads();
-    rmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    for (int q = 0; q < ADJ_WAVES; ++q) rmax = fmax(rmax, red[q]);
     const double C = fr.step * rmax * (1.0 + 1e-6);
     double Sd = 0.0;
     if constexpr (COUNT) {
@@ -953,7 +957,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const double inv_S = Sd > 0.0 ? 1.0 / Sd : 0.0;
     if constexpr (K == 0) {
         long long vmax = 0;
-        for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
+        for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += ADJ_THREADS) {
             const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
             const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
             if (i < n0 && j < n1 && k < n2) {
@@ -974,12 +978,13 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
             double ns = COUNT ? wave_sum((double)nsamp) : 0.0;
             if (lane == 0) red[wave] = m;
             __syncthreads();
-            m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            for (int q = 0; q < ADJ_WAVES; ++q) m = fmax(m, red[q]);
             __syncthreads();
             if constexpr (COUNT) {
                 if (lane == 0) red[wave] = ns;
                 __syncthreads();
-                ns = red[0] + red[1] + red[2] + red[3];
+                ns = 0.0;
+                for (int q = 0; q < ADJ_WAVES; ++q) ns += red[q];
             }
             if (tid == 0) {
                 const double slack = COUNT ? 0.5 * ns + 1.0 : 65536.0;
@@ -997,7 +1002,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) gacc[kk] = 0.0;
         if (Sd > 0.0) {
-            for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += 256) {
+            for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += ADJ_THREADS) {
                 const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
                 const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
                 if (i >= n0 || j >= n1 || k >= n2) continue;
@@ -1019,7 +1024,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
 }
 
 template <typename T, bool FORM_R, int K>
-__global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
+__global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
                                                      double hb, double vb,
                                                      const float *__restrict__ bounds,
                                                      float *__restrict__ bound_out,
@@ -1040,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_drr_adjoint(VolDims vd, Frame fr, int n
 // source of the FP32 gradient's 32-bit accumulators); its own entry so that
 // traces tell it from drr_adjoint.
 template <typename T>
-__global__ __launch_bounds__(256) void k_adjoint_bounds(VolDims vd, Frame fr, int nbx, int nby,
+__global__ __launch_bounds__(ADJ_THREADS) void k_adjoint_bounds(VolDims vd, Frame fr, int nbx, int nby,
                                                         double hb, double vb,
                                                         const RayRec<T> *__restrict__ rays,
                                                         float *__restrict__ bound_out) {
@@ -1052,7 +1057,7 @@ __global__ __launch_bounds__(256) void k_adjoint_bounds(VolDims vd, Frame fr, in
 
 // Several requests' gradients (back-projection + chain) in one launch.
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_drr_adjoint_batch(const AdjJob *__restrict__ jobs,
+__global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint_batch(const AdjJob *__restrict__ jobs,
                                                            int njobs) {
     const int j = job_of(jobs, njobs);
     const AdjJob &J = jobs[j];
@@ -1123,7 +1128,7 @@ static void launch_adj(const VolDims &v, const Frame &fr, const void *rays, cons
                        hipStream_t s) {
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
-    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K>), dim3(drr_adjoint_blocks(v)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0, s,
                        v, fr, nbx, nby, ray_weight_bound(v, fr), backprojection_weight_bound(v, fr),
                        bounds, bound_out, (const RayRec<T> *)rays,
                        (const T *)r_or_p, (const T *)y, a, b, (T *)bp, (const T *)f0,
@@ -1158,10 +1163,10 @@ hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const F
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
     const double hb = ray_weight_bound(v, fr), vb = backprojection_weight_bound(v, fr);
     if (dt == PCAS_F32)
-        hipLaunchKernelGGL((k_adjoint_bounds<float>), dim3(drr_adjoint_blocks(v)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_adjoint_bounds<float>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0, s,
                            v, fr, nbx, nby, hb, vb, (const RayRec<float> *)rays, bound_out);
     else
-        hipLaunchKernelGGL((k_adjoint_bounds<double>), dim3(drr_adjoint_blocks(v)), dim3(256), 0,
+        hipLaunchKernelGGL((k_adjoint_bounds<double>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0,
                            s, v, fr, nbx, nby, hb, vb, (const RayRec<double> *)rays, bound_out);
     return hipGetLastError();
 }
@@ -1227,7 +1232,7 @@ hipError_t launch_drr_adjoint_chain_batch(pcas_dtype dt, int K, const AdjJob *jo
     if (njobs <= 0) return hipSuccess;
 #define A(TT, KK)                                                                                 \
     case KK:                                                                                      \
-        hipLaunchKernelGGL((k_drr_adjoint_batch<TT, KK>), dim3(total_blocks), dim3(256), 0, s,     \
+        hipLaunchKernelGGL((k_drr_adjoint_batch<TT, KK>), dim3(total_blocks), dim3(ADJ_THREADS), 0, s,     \
                            jobs, njobs);                                                          \
         break
     if (dt == PCAS_F32) {
