@@ -439,10 +439,10 @@ struct Solver {
     }
 
     // Warp + projection at w into a slot, then J at the fit (one read-back).
-    // FP32: the projection's last block forms J from moments about a
-    // reference fit (the fixed one, else the last fit found), and the
-    // two-pass residual runs only if that sum would cancel.  FP64: moments
-    // of p itself and the two-pass residual.
+    // FP32: the projection reduces moments about a reference fit (the fixed
+    // one, else the last fit found), J and the fit follow from them on the
+    // host, and the two-pass residual runs only if that sum would cancel.
+    // FP64: moments of p itself and the two-pass residual.
     int evaluate(const double *w, const double *ab_fixed, int slot, double *J, double *a,
                  double *b) {
         HIPCHK(timed(PCAS_K_WARP, [&] {
@@ -465,14 +465,12 @@ struct Solver {
         mom_a0 = ff.a0;
         mom_b0 = ff.b0;
         if (!one_pass) return residual(ab_fixed, slot, J, a, b);
-        double out[4];
-        int st = sync_read(out, scal() + 3, 4);
+        double mo[3], kappa;
+        int st = sync_read(mo, scal(), 3);
         if (st) return st;
-        *J = out[0];
-        *a = out[1];
-        *b = out[2];
+        objective_from_moments(mo, ff, J, a, b, &kappa);
         if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
-        if (!(out[3] <= MOMENT_KAPPA_MAX)) {   // cancellation: the two-pass sum at this fit
+        if (!(kappa <= MOMENT_KAPPA_MAX)) {   // cancellation: the two-pass sum at this fit
             const double ab[2] = {*a, *b};
             return residual(ab, slot, J, a, b);
         }

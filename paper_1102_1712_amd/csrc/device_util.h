@@ -27,44 +27,6 @@ struct NoFinish {
     __device__ void operator()(const double *) const {}
 };
 
-// The objective of Eq. 2 at a fit (a, b) from moments about a reference fit
-// (a0, b0).  With r0 = p - a0 y - b0 and d = (a - a0, b - b0) the residual
-// is r = r0 - d_a y - d_b, so
-//   J = S(r0^2) - 2 (d_a S(r0 y) + d_b S(r0)) + d_a^2 S(y^2) + 2 d_a d_b S(y) + M d_b^2,
-// and the refit of Eq. A.1 solves [S(y^2) S(y); S(y) M] d = [S(r0 y); S(r0)].
-// With the reference near the fit S(r0^2) is close to J and the sum does not
-// cancel; kappa = S(r0^2) / J (written as out[3]) says how far that holds.
-// Writes J, a, b, kappa; a singular refit gives NaN a and b.  Does nothing
-// for fit modes other than FIT_REFIT and FIT_FIXED.
-struct ObjectiveFromMoments {
-    FitArgs fit;
-    double *out;
-    __device__ void operator()(const double *mo) const {
-        double A, B;
-        if (fit.mode == FIT_REFIT) {
-            const double det = fit.syy * fit.m - fit.sy * fit.sy;
-            if (fabs(det) > 1e-12 * fit.syy * fit.m) {
-                A = fit.a0 + (fit.m * mo[1] - fit.sy * mo[0]) / det;
-                B = fit.b0 + (fit.syy * mo[0] - fit.sy * mo[1]) / det;
-            } else {
-                A = B = NAN;
-            }
-        } else if (fit.mode == FIT_FIXED) {
-            A = fit.a;
-            B = fit.b;
-        } else {
-            return;
-        }
-        const double da = A - fit.a0, db = B - fit.b0;
-        const double J = mo[2] - 2.0 * (da * mo[1] + db * mo[0]) + da * da * fit.syy +
-                         2.0 * da * db * fit.sy + fit.m * db * db;
-        store_agent(&out[0], J);
-        store_agent(&out[1], A);
-        store_agent(&out[2], B);
-        store_agent(&out[3], J > 0.0 ? mo[2] / J : INFINITY);
-    }
-};
-
 // Sums vals[0..NS) over the block (any multiple of 64 threads up to 1024),
 // publishes the block's partials, and lets the last block to arrive reduce
 // all partials in block order into out[j] * scale, then call fin on those

@@ -90,9 +90,42 @@ struct FitArgs {
     double a, b, sy, syy, m;
     double a0 = 0.0, b0 = 0.0;
 };
-// Above this cancellation factor sum(r0^2) / J the forward pass's J is
-// recomputed by the two-pass residual at the fit it found.
+// Above this cancellation factor sum(r0^2) / J the J formed from the
+// forward pass's moments is recomputed by the two-pass residual at the fit
+// found.
 constexpr double MOMENT_KAPPA_MAX = 1e4;
+
+// The objective of Eq. 2 at a fit (a, b) from moments mo = (sum r0,
+// sum r0 y, sum r0^2) about a reference fit (a0, b0).  With r0 = p - a0 y -
+// b0 and d = (a - a0, b - b0) the residual is r = r0 - d_a y - d_b, so
+//   J = S(r0^2) - 2 (d_a S(r0 y) + d_b S(r0)) + d_a^2 S(y^2) + 2 d_a d_b S(y) + M d_b^2,
+// and the refit of Eq. A.1 solves [S(y^2) S(y); S(y) M] d = [S(r0 y); S(r0)].
+// With the reference near the fit S(r0^2) is close to J and the sum does not
+// cancel; kappa = S(r0^2) / J says how far that holds (infinite if J <= 0).
+// A singular refit gives NaN a and b.  fit.mode is FIT_REFIT or FIT_FIXED.
+inline void objective_from_moments(const double *mo, const FitArgs &fit, double *J, double *a,
+                                   double *b, double *kappa) {
+    double A, B;
+    if (fit.mode == FIT_REFIT) {
+        const double det = fit.syy * fit.m - fit.sy * fit.sy;
+        if (fabs(det) > 1e-12 * fit.syy * fit.m) {
+            A = fit.a0 + (fit.m * mo[1] - fit.sy * mo[0]) / det;
+            B = fit.b0 + (fit.syy * mo[0] - fit.sy * mo[1]) / det;
+        } else {
+            A = B = NAN;
+        }
+    } else {
+        A = fit.a;
+        B = fit.b;
+    }
+    const double da = A - fit.a0, db = B - fit.b0;
+    const double j = mo[2] - 2.0 * (da * mo[1] + db * mo[0]) + da * da * fit.syy +
+                     2.0 * da * db * fit.sy + fit.m * db * db;
+    *J = j;
+    *a = A;
+    *b = B;
+    *kappa = j > 0.0 ? mo[2] / j : INFINITY;
+}
 
 // ---- batched launches: one launch serves several requests ----------------
 // A job holds one request's arguments and the range [block0, block0 +
@@ -168,10 +201,7 @@ hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f
 // b0 for fit->a0, fit->b0 (zero when fit is null), (sum r0, sum r0*y,
 // sum r0*r0) into sums[0..2] (double) via per-block partials and a
 // last-block pass; partials needs drr_forward_blocks() * RED_SLOTS doubles,
-// counter one zeroed uint32 (left zeroed on exit).  Unless fit is null or
-// its mode FIT_NONE, the last block then writes the objective at that fit
-// (refitted by Eq. A.1, or fixed) from the moments: sums[3..6] = J, a, b and
-// the cancellation factor sum(r0^2) / J (infinite if J <= 0).
+// counter one zeroed uint32 (left zeroed on exit).
 // The geometry-only launch plan (slab axis and thickness) is computed once
 // per projection on the host.
 int drr_forward_blocks(int nu, int nv);

@@ -148,8 +148,8 @@ constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_L
 //
 // MODE FWD_WRITE / FWD_SUMS (NV = 1): p = P f, and for FWD_SUMS also
 // (sum r0, sum r0 y, sum r0^2) for r0 = p - fit.a0 y - fit.b0 into
-// out[0..2], then (unless fit.mode is FIT_NONE) the objective at fit into
-// out[3..6] (ObjectiveFromMoments).  MODE FWD_DOT: the ray values
+// out[0..2] (the host forms the objective from them: objective_from_moments).
+// MODE FWD_DOT: the ray values
 // q_v = (P f_v) are not stored; out[v] = 2 sum_rays r q_v with the residual
 // r = p - a y - b of the stored projection p.
 template <typename T, int AX, int NV, int MODE>
@@ -388,8 +388,7 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             const double yv = writer ? (double)y[pix] : 0.0;
             const double rv = writer ? pv - fit.a0 * yv - fit.b0 : 0.0;
             const double vals[3] = {rv, rv * yv, rv * rv};
-            grid_reduce<3>(vals, partials, counter, out, bid, nb, 1.0,
-                           ObjectiveFromMoments{fit, out + 3});
+            grid_reduce<3>(vals, partials, counter, out, bid, nb, 1.0);
         }
     }
 }

@@ -65,6 +65,7 @@ struct Request {
     double ref_a = 1.0, ref_b = 0.0;
     int mom_slot = -1;
     double mom_a0 = 0.0, mom_b0 = 0.0;
+    FitArgs eval_fit{};   // the pending FP32 evaluation's fit and reference
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -235,8 +236,10 @@ ResJob res_job(const Request &r, int slot, const FitArgs &fa) {
     return rj;
 }
 
-// Advances one request with the scalars its operation produced.
-void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done) {
+// Advances one request with the scalars its operation produced (jab: J, a,
+// b of an evaluation formed on the host, else sc[3..5]).
+void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done,
+             const double *jab = nullptr) {
     const Model &md = S->models[r->model];
     bool done = false;
     int status = PCAS_OK;
@@ -260,7 +263,7 @@ void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done) {
     } else if (r->phase == PH_RUN) {
         const SolveOp &op = r->m.op();
         if (op.kind == OP_EVAL || op.kind == OP_RESID) {
-            const double J = sc[3], a = sc[4], b = sc[5];
+            const double J = jab ? jab[0] : sc[3], a = jab ? jab[1] : sc[4], b = jab ? jab[2] : sc[5];
             if (!isfinite(a) || !isfinite(b)) {
                 status = PCAS_ESINGULAR;
                 done = true;
@@ -350,6 +353,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             r->mom_slot = op.slot;
             r->mom_a0 = ff.a0;
             r->mom_b0 = ff.b0;
+            r->eval_fit = ff;
         }
         if ((op.kind == OP_EVAL && md.dt != PCAS_F32) || op.kind == OP_RESID) {
             FitArgs fa = fit_of(*r, op.fixed_ab ? op.ab : nullptr);
@@ -430,10 +434,17 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             ++*n_done;
             continue;
         }
-        if (r->phase == PH_RUN && r->m.op().kind == OP_EVAL &&
-            S->models[r->model].dt == PCAS_F32 && isfinite(sc[4]) && isfinite(sc[5]) &&
-            !(sc[6] <= MOMENT_KAPPA_MAX)) {
-            redo.push_back(r);
+        if (r->phase == PH_RUN && r->m.op().kind == OP_EVAL && S->models[r->model].dt == PCAS_F32) {
+            // the objective from the projection's moments, as a solve alone forms it
+            double jab[3], kappa;
+            objective_from_moments(sc, r->eval_fit, &jab[0], &jab[1], &jab[2], &kappa);
+            if (isfinite(jab[1]) && isfinite(jab[2]) && !(kappa <= MOMENT_KAPPA_MAX)) {
+                r->eval_fit.a = jab[1];   // the fit found, for the two-pass sum
+                r->eval_fit.b = jab[2];
+                redo.push_back(r);
+                continue;
+            }
+            advance(S, r, sc, n_done, jab);
             continue;
         }
         advance(S, r, sc, n_done);
@@ -444,10 +455,9 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     std::vector<ResJob> rj;
     for (Request *r : redo) {
         FitArgs fa = fit_of(*r, nullptr);
-        const double *sc = S->gather_host + (std::find(set.begin(), set.end(), r) - set.begin()) * GATHER;
         fa.mode = FIT_FIXED;
-        fa.a = sc[4];
-        fa.b = sc[5];
+        fa.a = r->eval_fit.a;
+        fa.b = r->eval_fit.b;
         ResJob j = res_job(*r, r->m.op().slot, fa);
         j.block0 = 0;
         rj.push_back(j);
