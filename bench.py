@@ -60,9 +60,9 @@ KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
 
 
 def drr_bricks(vol) -> int:
-    """Bricks of the back-projection (16 x 16 x 8 voxels each)."""
-    n = vol.n
-    return -(-n[0] // 16) * -(-n[1] // 16) * -(-n[2] // 8)
+    """Bricks of the back-projection (the library's brick count)."""
+    from paper_1102_1712_amd import binding as B
+    return B.backprojection_brick_count(vol)
 
 
 def kernel_digest(kernel: str) -> str:

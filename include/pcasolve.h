@@ -250,7 +250,7 @@ double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj);
 
 /* Per-brick bounds of the back-projection of the all-ones image: the pass
  * the solver runs once per projection to size the FP32 gradient's 32-bit
- * accumulators.  The volume is cut into 16 x 16 x 8 voxel bricks (brick x
+ * accumulators.  The volume is cut into 32 x 16 x 8 voxel bricks (brick x
  * fastest, then y, then z); bounds_out: device float[backprojection_brick_count
  * (vol)], each at least the largest (P^T 1)(v) over the brick's voxels, with
  * P^T drr_adjoint's operator and 1 the all-ones image (rounded up; 0 where no

@@ -339,8 +339,16 @@ def backprojection_bound(vol, proj) -> float:
     return b
 
 
+def backprojection_brick_count(vol) -> int:
+    """Number of back-projection bricks of a volume (host-only query)."""
+    n = int(lib().backprojection_brick_count(ctypes.byref(c_vol(vol))))
+    if n < 0:
+        raise PcasError(-1, "backprojection_brick_count: invalid volume")
+    return n
+
+
 def backprojection_brick_bounds(vol, proj, rays, dtype=None, stream=None):
-    """Per-brick upper bounds of P^T 1 over 16 x 16 x 8 bricks (x fastest),
+    """Per-brick upper bounds of P^T 1 over 32 x 16 x 8 bricks (x fastest),
     float32 on the rays' device; dtype defaults to the ray table's."""
     torch = _torch()
     n = int(lib().backprojection_brick_count(ctypes.byref(c_vol(vol))))

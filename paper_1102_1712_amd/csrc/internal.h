@@ -49,7 +49,7 @@ static_assert(sizeof(RayRec<float>) == 32, "RayRec<float> layout");
 static_assert(sizeof(RayRec<double>) == 64, "RayRec<double> layout");
 
 // Adjoint brick (voxels owned by one wavefront).
-constexpr int BRICK_X = 16, BRICK_Y = 16, BRICK_Z = 8;
+constexpr int BRICK_X = 32, BRICK_Y = 16, BRICK_Z = 8;
 // Forward projection: FWD_SPLIT lanes march one ray (interleaved samples),
 // a wave covers FWD_WU x FWD_WV neighbouring rays, a 256-thread block 2 x 2
 // such wave tiles (a bundle of TILE_U x TILE_V rays).  The bundle stages its

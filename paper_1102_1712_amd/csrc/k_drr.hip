@@ -7,7 +7,7 @@
 // lines.  The partial sums of a ray are combined by a fixed butterfly.
 //
 // Adjoint: the exact transpose of the forward without global atomics.  A
-// 512-thread workgroup owns a 16 x 16 x 8 voxel brick held in LDS.  It
+// 512-thread workgroup owns a 32 x 16 x 8 voxel brick held in LDS.  It
 // visits every ray whose pixel lies in the detector footprint of the brick
 // (plus a one-voxel apron), re-creates exactly the samples of that ray whose
 // 2x2x2 cell touches the brick (same ray record, same sample_cell

@@ -101,6 +101,15 @@ def test_ray_table_bytes(L, geom):
     assert L.pcas_ray_table_bytes(7, ctypes.byref(p)) == 0
 
 
+def test_backprojection_brick_count(L, geom):
+    """Bricks tile the volume 32 x 16 x 8 (x, y, z), ragged edges rounded up."""
+    v, _ = geom
+    assert L.backprojection_brick_count(ctypes.byref(v)) == 1 * 2 * 2
+    odd = B.c_vol(synth.centred_volume((65, 17, 9), (1.0, 1.0, 1.0)))
+    assert L.backprojection_brick_count(ctypes.byref(odd)) == 3 * 2 * 2
+    assert B.backprojection_brick_count(synth.centred_volume((256, 256, 128), (1.0, 1.0, 1.0))) == 8 * 16 * 16
+
+
 def test_invalid_dtype_dims_and_pointers(L, geom):
     v, p = geom
     assert L.ray_table(7, ctypes.byref(v), ctypes.byref(p), FAKE, None) == EINVAL

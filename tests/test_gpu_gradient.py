@@ -199,12 +199,12 @@ def test_errors(torch):
 
 
 def _brick_max(v):
-    """Largest value per 16 x 16 x 8 brick of a [n3][n2][n1] array (x fastest)."""
+    """Largest value per 32 x 16 x 8 brick of a [n3][n2][n1] array (x fastest)."""
     n2, n1, n0 = v.shape
-    bz, by, bx = -(-n2 // 8), -(-n1 // 16), -(-n0 // 16)
-    pad = np.zeros((bz * 8, by * 16, bx * 16))
+    bz, by, bx = -(-n2 // 8), -(-n1 // 16), -(-n0 // 32)
+    pad = np.zeros((bz * 8, by * 16, bx * 32))
     pad[:n2, :n1, :n0] = v
-    return pad.reshape(bz, 8, by, 16, bx, 16).max(axis=(1, 3, 5)).reshape(-1)
+    return pad.reshape(bz, 8, by, 16, bx, 32).max(axis=(1, 3, 5)).reshape(-1)
 
 
 @pytest.mark.parametrize("name", ["small", *sorted(STRESS)])
