@@ -396,6 +396,17 @@ struct Solver {
         return PCAS_OK;
     }
 
+    // The same for a reduction whose launch left block partials only (no
+    // counter): the read-back kernel finishes the sum into dev[0..count).
+    int sync_read_sum(double *host, int nblocks, int threads, double scale, double *dev,
+                      int count) {
+        int st = readback_sum(host, (const double *)(ws + L.partials), nblocks, threads, scale,
+                              dev, count, s);
+        if (st) return st;
+        if (prof.mask) HIPCHK(prof.collect());
+        return PCAS_OK;
+    }
+
     FitArgs fit_args(const double *ab_fixed) const {
         FitArgs fa{FIT_FIXED, 1.0, 0.0, sy, syy, (double)M};
         if (ab_fixed) {
@@ -458,7 +469,8 @@ struct Solver {
         }
         HIPCHK(timed(PCAS_K_DRR, [&] {
             return launch_drr_forward(dt, vd, fr, fplan, ws + L.rays, ws + L.f, proj_slot(slot), y,
-                                      &ff, (double *)(ws + L.partials), &counters()[0], scal(), s);
+                                      &ff, (double *)(ws + L.partials),
+                                      one_pass ? nullptr : &counters()[0], scal(), s);
         }));
         ++n_fevals;
         mom_slot = slot;
@@ -466,7 +478,7 @@ struct Solver {
         mom_b0 = ff.b0;
         if (!one_pass) return residual(ab_fixed, slot, J, a, b);
         double mo[3], kappa;
-        int st = sync_read(mo, scal(), 3);
+        int st = sync_read_sum(mo, drr_forward_blocks(fr.nu, fr.nv), FWD_THREADS, 1.0, scal(), 3);
         if (st) return st;
         objective_from_moments(mo, ff, J, a, b, &kappa);
         if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
@@ -489,20 +501,20 @@ struct Solver {
             HIPCHK(timed(PCAS_K_DRR_DOT, [&] {
                 return launch_drr_forward_dot(dt, vd, fr, fplan_k, K, ws + L.rays, ws + L.vol2,
                                               proj_slot(slot), y, a, b, (double *)(ws + L.partials),
-                                              &counters()[1], scal() + 8, s);
+                                              nullptr, scal() + 8, s);
             }));
         } else {
             HIPCHK(join_bounds());
             // back-projection and Jacobian chain in one pass (bp stays on chip)
             HIPCHK(timed(PCAS_K_ADJOINT, [&] {
                 return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, proj_slot(slot), y, a, b, f0,
-                                                mean, U, w, (double *)(ws + L.partials),
-                                                &counters()[1], scal() + 8,
-                                                dt == PCAS_F32 ? bounds() : nullptr, s);
+                                                mean, U, w, (double *)(ws + L.partials), nullptr,
+                                                scal() + 8, dt == PCAS_F32 ? bounds() : nullptr, s);
             }));
         }
         ++n_grads;
-        int st = sync_read(g, scal() + 8, K);
+        const int nb = grad_mode == 0 ? drr_forward_blocks(fr.nu, fr.nv) : drr_adjoint_blocks(vd);
+        int st = sync_read_sum(g, nb, grad_mode == 0 ? FWD_THREADS : ADJ_THREADS, 2.0, scal() + 8, K);
         if (st) return st;
         for (int k = 0; k < K; ++k)
             if (!isfinite(g[k])) return PCAS_ENONFINITE;

@@ -23,22 +23,12 @@ __device__ __forceinline__ void store_agent(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct NoFinish {
-    __device__ void operator()(const double *) const {}
-};
-
-// Sums vals[0..NS) over the block (any multiple of 64 threads up to 1024),
-// publishes the block's partials, and lets the last block to arrive reduce
-// all partials in block order into out[j] * scale, then call fin on those
-// NS totals (one thread).  The counter must be zero on entry; the last
-// block resets it.  Every thread of every block must call this exactly once.
-template <int NS, class Fin = NoFinish>
-__device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ partials,
-                            uint32_t *counter, double *__restrict__ out, int bid, int nblocks,
-                            double scale, Fin fin = Fin()) {
+// Sums vals[0..NS) over the block (any multiple of 64 threads up to 1024)
+// and stores the block's totals in partials[bid * RED_SLOTS + j].
+template <int NS>
+__device__ void block_partials(const double (&vals)[NS], double *__restrict__ partials, int bid) {
     static_assert(NS <= RED_SLOTS, "too many reduction slots");
     __shared__ double sm[NS][16];
-    __shared__ int is_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -53,19 +43,28 @@ __device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ parti
             for (int w = 0; w < nwaves; ++w) t += sm[j][w];
             store_agent(&partials[(int64_t)bid * RED_SLOTS + j], t);
         }
-        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (prev == (uint32_t)(nblocks - 1));
     }
-    __syncthreads();
-    if (!is_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// The whole block sums the partials of nblocks blocks in one fixed order
+// (thread t takes blocks t, t + blockDim, ..., then waves in order), so a
+// block of the producer's width gets the same bits wherever it runs.
+// Thread 0 returns scale * total in tot.  COHERENT reads through to the
+// agent-coherent level (partials written by other blocks of this kernel).
+template <int NS, bool COHERENT>
+__device__ void sum_partials(const double *__restrict__ partials, int nblocks, double scale,
+                             double (&tot)[NS]) {
+    __shared__ double sm[NS][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     double acc[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) acc[j] = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) acc[j] += load_agent(&partials[(int64_t)b * RED_SLOTS + j]);
+        for (int j = 0; j < NS; ++j) {
+            const double *q = &partials[(int64_t)b * RED_SLOTS + j];
+            acc[j] += COHERENT ? load_agent(q) : *q;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -75,17 +74,54 @@ __device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ parti
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot[NS];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             double t = 0.0;
             for (int w = 0; w < nwaves; ++w) t += sm[j][w];
             tot[j] = scale * t;
-            store_agent(&out[j], tot[j]);
         }
-        fin(tot);
+    }
+}
+
+// block_partials, then the last block to arrive (an agent-scope counter)
+// runs sum_partials and writes out[j].  Each block's counter increment is a
+// release and only the last block acquires (the increments form one release
+// sequence), so one L2 invalidate per launch instead of one per block.  The
+// counter must be zero on entry; the last block resets it.  Every thread of
+// every block must call this exactly once.
+template <int NS>
+__device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ partials,
+                            uint32_t *counter, double *__restrict__ out, int bid, int nblocks,
+                            double scale) {
+    __shared__ int is_last;
+    block_partials<NS>(vals, partials, bid);
+    if (threadIdx.x == 0) {
+        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (prev == (uint32_t)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double tot[NS];
+    sum_partials<NS, true>(partials, nblocks, scale, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) store_agent(&out[j], tot[j]);
         __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// In a kernel whose totals are finished by a later launch (counter ==
+// nullptr): the block's partials only.  Otherwise grid_reduce.
+template <int NS>
+__device__ void reduce_or_defer(const double (&vals)[NS], double *__restrict__ partials,
+                                uint32_t *counter, double *__restrict__ out, int bid, int nblocks,
+                                double scale) {
+    if (counter)
+        grid_reduce<NS>(vals, partials, counter, out, bid, nblocks, scale);
+    else
+        block_partials<NS>(vals, partials, bid);
 }
 
 // Split a displacement x (mm) into whole voxels and the fractional part

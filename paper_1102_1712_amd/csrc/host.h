@@ -156,13 +156,15 @@ inline Mailbox *host_mailbox() {
     return &mb;
 }
 
-inline int readback(double *host, const double *dev, int count, hipStream_t s) {
+// Publishes count values with `launch(vals, flag, seq)` and waits for them.
+template <class Launch>
+inline int readback_with(double *host, int count, hipStream_t s, Launch launch) {
     if (count < 0 || count > 64) return hip_fail(hipErrorInvalidValue, "scalar read-back size");
     Mailbox *mb = host_mailbox();
     if (!mb) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(scalar mailbox)");
     if (++mb->seq == 0) mb->seq = 1;   // 0 is the flag's initial value
     const uint32_t seq = mb->seq;
-    HIPCHK(launch_publish(dev, mb->vals, count, mb->flag, seq, s));
+    HIPCHK(launch(mb->vals, mb->flag, seq));
     for (uint32_t n = 1; __atomic_load_n(mb->flag, __ATOMIC_ACQUIRE) != seq; ++n) {
         __builtin_ia32_pause();
         if ((n & 4095u) == 0) {
@@ -176,6 +178,22 @@ inline int readback(double *host, const double *dev, int count, hipStream_t s) {
     }
     memcpy(host, mb->vals, count * sizeof(double));
     return PCAS_OK;
+}
+
+inline int readback(double *host, const double *dev, int count, hipStream_t s) {
+    return readback_with(host, count, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
+        return launch_publish(dev, vals, count, flag, seq, s);
+    });
+}
+
+// Finishes a deferred reduction (blocks of `threads` threads left nblocks
+// partials) into dev[0..count) and reads the totals back.
+inline int readback_sum(double *host, const double *partials, int nblocks, int threads,
+                        double scale, double *dev, int count, hipStream_t s) {
+    if (count < 1 || count > RED_SLOTS) return hip_fail(hipErrorInvalidValue, "reduction width");
+    return readback_with(host, count, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
+        return launch_publish_sum(partials, nblocks, threads, count, scale, dev, vals, flag, seq, s);
+    });
 }
 
 // ---- workspace layouts ---------------------------------------------------

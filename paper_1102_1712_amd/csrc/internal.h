@@ -48,8 +48,15 @@ template <> struct alignas(16) RayRec<double> {
 static_assert(sizeof(RayRec<float>) == 32, "RayRec<float> layout");
 static_assert(sizeof(RayRec<double>) == 64, "RayRec<double> layout");
 
-// Adjoint brick (voxels owned by one wavefront).
+// Back-projection brick (the voxels one workgroup accumulates in LDS).
 constexpr int BRICK_X = 32, BRICK_Y = 16, BRICK_Z = 8;
+// Waves sharing one brick, each with its own ray queue.  8 (with 16 x 16 x 8
+// bricks): 32 waves per CU, the VGPR limit, in 4 bricks, against 28 in 7
+// bricks with 4 waves; the fused gradient kernel measured 410 against
+// 431 us, 2 waves 582 us.  FWD_THREADS: a forward-projection block.
+constexpr int ADJ_WAVES = 8;
+constexpr int ADJ_THREADS = 64 * ADJ_WAVES;
+constexpr int FWD_THREADS = 256;
 // Forward projection: FWD_SPLIT lanes march one ray (interleaved samples),
 // a wave covers FWD_WU x FWD_WV neighbouring rays, a 256-thread block 2 x 2
 // such wave tiles (a bundle of TILE_U x TILE_V rays).  The bundle stages its
@@ -183,6 +190,13 @@ struct AdjJob {                 // back-projection of the residual + Jacobian ch
 // ---- launchers (return the HIP error of the launch) ----------------------
 hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s);
 // Copies count <= 64 doubles to mapped host memory, then releases seq to *flag_host.
+// The deferred end of a reduction whose blocks left partials only: one
+// block of the producer's width (threads) sums the nblocks partials in
+// grid_reduce's order, so the totals carry the same bits, stores
+// scale * total to out[0..ns) and then publishes them like launch_publish.
+hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, int ns,
+                              double scale, double *out, double *dst_host, uint32_t *flag_host,
+                              uint32_t seq, hipStream_t s);
 hipError_t launch_publish(const double *src, double *dst_host, int count, uint32_t *flag_host,
                           uint32_t seq, hipStream_t s);
 
@@ -201,7 +215,10 @@ hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f
 // b0 for fit->a0, fit->b0 (zero when fit is null), (sum r0, sum r0*y,
 // sum r0*r0) into sums[0..2] (double) via per-block partials and a
 // last-block pass; partials needs drr_forward_blocks() * RED_SLOTS doubles,
-// counter one zeroed uint32 (left zeroed on exit).
+// counter one zeroed uint32 (left zeroed on exit).  With counter == nullptr
+// the launch leaves the block partials only (256-thread blocks), for
+// launch_publish_sum to finish.  The same holds for the dot and chain
+// launches below (the chain's blocks have ADJ_THREADS threads).
 // The geometry-only launch plan (slab axis and thickness) is computed once
 // per projection on the host.
 int drr_forward_blocks(int nu, int nv);

@@ -376,7 +376,7 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
         const double rr = writer ? (double)p[pix] - fa * (double)y[pix] - fb : 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) vals[v] = rr * ((double)r.dt * acc[v]);
-        grid_reduce<NV>(vals, partials, counter, out, bid, nb, 2.0);
+        reduce_or_defer<NV>(vals, partials, counter, out, bid, nb, 2.0);
     } else {
         double pv = 0.0;
         if (writer) {
@@ -388,7 +388,7 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             const double yv = writer ? (double)y[pix] : 0.0;
             const double rv = writer ? pv - fit.a0 * yv - fit.b0 : 0.0;
             const double vals[3] = {rv, rv * yv, rv * rv};
-            grid_reduce<3>(vals, partials, counter, out, bid, nb, 1.0);
+            reduce_or_defer<3>(vals, partials, counter, out, bid, nb, 1.0);
         }
     }
 }
@@ -468,7 +468,7 @@ static void launch_fwd(dim3 grid, const VolDims &v, const Frame &fr, int tiles_u
                        const void *rays, const void *f, void *p, const void *y, double a, double b,
                        const FitArgs &fit, double *partials, uint32_t *counter, double *out,
                        hipStream_t s) {
-    hipLaunchKernelGGL((k_drr_forward<T, AX, NV, MODE>), grid, dim3(256), 0, s, v, fr, tiles_u, slab,
+    hipLaunchKernelGGL((k_drr_forward<T, AX, NV, MODE>), grid, dim3(FWD_THREADS), 0, s, v, fr, tiles_u, slab,
                        (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, a, b, fit,
                        partials, counter, out);
 }
@@ -602,11 +602,6 @@ __device__ __forceinline__ double wave_max(double v) {
 constexpr int ACC_YP = BRICK_X + 2;
 constexpr int ACC_ZP = (BRICK_Y + 2) * ACC_YP + 1;
 constexpr int ACC_WORDS = (BRICK_Z + 2) * ACC_ZP;
-// Waves sharing one brick (each with its own ray queue).  8: 32 waves per
-// CU (the VGPR limit) in 4 bricks, against 28 in 7 bricks with 4 waves; the
-// fused gradient kernel measured 410 against 431 us, 2 waves 582 us.
-constexpr int ADJ_WAVES = 8;
-constexpr int ADJ_THREADS = 64 * ADJ_WAVES;
 // Ring queue of rays per wave (a power of two, at least one 64-ray tile).
 // 64 rather than 128 entries: the queues are most of a block's LDS, and
 // the smaller ones let 7 instead of 5 blocks share a CU (the fused gradient
@@ -1018,7 +1013,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                     gacc[kk] += (double)fma_t(u[kk][0], j0, fma_t(u[kk][1], j1, u[kk][2] * j2));
             }
         }
-        grid_reduce<K>(gacc, partials, counter, g_out, bid, nb, 2.0);
+        reduce_or_defer<K>(gacc, partials, counter, g_out, bid, nb, 2.0);
     }
 }
 

@@ -33,6 +33,53 @@ hipError_t launch_publish(const double *src, double *dst_host, int count, uint32
     return hipGetLastError();
 }
 
+// The deferred end of a reduction (launch_publish_sum): one block of the
+// producer's width finishes the sum with the same code as grid_reduce's last
+// block, stores the totals on the device and publishes them as k_publish
+// does.  The producing kernel has ended, so plain loads see its partials.
+template <int NS>
+__global__ __launch_bounds__(1024) void k_publish_sum(const double *__restrict__ partials,
+                                                      int nblocks, double scale,
+                                                      double *__restrict__ out, double *dst,
+                                                      uint32_t *flag, uint32_t seq) {
+    double tot[NS];
+    sum_partials<NS, false>(partials, nblocks, scale, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            out[j] = tot[j];
+            dst[j] = tot[j];
+        }
+        __threadfence_system();
+        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, int ns,
+                              double scale, double *out, double *dst_host, uint32_t *flag_host,
+                              uint32_t seq, hipStream_t s) {
+    if (nblocks < 1 || threads < 64 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+    switch (ns) {
+#define PCAS_PUBLISH_SUM(N)                                                                        \
+    case N:                                                                                        \
+        hipLaunchKernelGGL(k_publish_sum<N>, dim3(1), dim3(threads), 0, s, partials, nblocks,      \
+                           scale, out, dst_host, flag_host, seq);                                  \
+        break;
+        PCAS_PUBLISH_SUM(1)
+        PCAS_PUBLISH_SUM(2)
+        PCAS_PUBLISH_SUM(3)
+        PCAS_PUBLISH_SUM(4)
+        PCAS_PUBLISH_SUM(5)
+        PCAS_PUBLISH_SUM(6)
+        PCAS_PUBLISH_SUM(7)
+        PCAS_PUBLISH_SUM(8)
+#undef PCAS_PUBLISH_SUM
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // One thread per detector pixel, all geometry in double with contraction
 // off, so the record is the correctly rounded evaluation of: pixel centre,
 // unit direction from the source, slab intersection with the box of voxel
