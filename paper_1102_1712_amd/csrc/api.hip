@@ -545,9 +545,16 @@ struct Solver {
         prof.mask = profile;
         HIPCHK(launch_fill_u32(counters(), 64, 0u, s));
         HIPCHK(timed(PCAS_K_RAYS, [&] { return launch_ray_table(dt, vd, fr, ws + L.rays, s); }));
+        // sums of the measured image: (sum y, sum y^2, ., ., .)
+        HIPCHK(timed(PCAS_K_YSUMS, [&] {
+            return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],
+                                    scal() + 16, s);
+        }));
         if (dt == PCAS_F32 && grad_mode == 1) {
-            // geometry only: overlapped with the y sums and the first
-            // evaluation on a second stream where one is available
+            // geometry only: overlapped with the y sums' read-back and the
+            // first evaluation on a second stream where one is available;
+            // launched after the y sums so that their small grid is not queued
+            // behind this one on the GPU
             aux = aux_stream();
             hipStream_t bs = s;
             if (aux) {
@@ -563,11 +570,6 @@ struct Solver {
                 bounds_pending = true;
             }
         }
-        // sums of the measured image: (sum y, sum y^2, ., ., .)
-        HIPCHK(timed(PCAS_K_YSUMS, [&] {
-            return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],
-                                    scal() + 16, s);
-        }));
         double ys[5];
         int st = sync_read(ys, scal() + 16, 5);
         if (st) return st;
