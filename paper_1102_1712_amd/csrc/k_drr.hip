@@ -261,11 +261,14 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                 }
             }
         }
-        // the lane's next sample, computed once and carried across slabs
+        // the lane's next sample, computed once and carried across slabs.
+        // The cell of a sample past the ray's end is computed as well (it is
+        // clamped to the grid and never used: every loop tests `have` first);
+        // computing it unconditionally spares the loops their register copies.
         int l[3];
         T z[3];
         bool have = sh < shn;
-        if (have) sample_cell(e, d, sh, top, l, z);
+        sample_cell(e, d, sh, top, l, z);
         __syncthreads();
         for (int i = 0; i < nsl; ++i) {
             const int k = votes == 1 ? kmin + i : kmax - i;
@@ -329,7 +332,7 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                     }
                     sh += (T)SPLIT;
                     have = sh < shn;
-                    if (have) sample_cell(e, d, sh, top, l, z);
+                    sample_cell(e, d, sh, top, l, z);
                 }
             }
             if (miss) {
@@ -339,14 +342,14 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                 for (int v = 0; v < NV; ++v) part[v] = (T)0;
                 sh = sh0;
                 have = sh < shn;
-                if (have) sample_cell(e, d, sh, top, l, z);
+                sample_cell(e, d, sh, top, l, z);
                 while (have && (unsigned)(l[AX] - A0) < (unsigned)slab) {
                     const int go = (l[0] + n0 * (l[1] + n1 * l[2])) * ES;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) part[v] += gather_global(rf[v], go, sb1, sb2, z);
                     sh += (T)SPLIT;
                     have = sh < shn;
-                    if (have) sample_cell(e, d, sh, top, l, z);
+                    sample_cell(e, d, sh, top, l, z);
                 }
             }
 #pragma unroll
