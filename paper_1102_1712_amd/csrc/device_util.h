@@ -1,5 +1,6 @@
 // Device helpers: wave64 / block reductions in double and the
-// "last block finishes" grid reduction (fixed order, hence deterministic).
+// fixed-order grid reduction, finished by the last block to arrive or by a
+// later launch (deterministic either way).
 #pragma once
 
 #include "internal.h"

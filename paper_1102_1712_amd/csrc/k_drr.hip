@@ -601,7 +601,8 @@ __device__ __forceinline__ double wave_max(double v) {
 // LDS accumulator of a brick with a one-voxel halo on every side, so that
 // all eight corners of any cell touching the brick have a slot; halo slots
 // collect contributions that belong to neighbouring bricks and are dropped
-// at write-out.  Slice pitch 18*18+1 words spreads z-neighbours over banks.
+// at write-out.  The slice pitch, one word more than the (BRICK_Y + 2) x
+// (BRICK_X + 2) slice, spreads z-neighbours over banks.
 constexpr int ACC_YP = BRICK_X + 2;
 constexpr int ACC_ZP = (BRICK_Y + 2) * ACC_YP + 1;
 constexpr int ACC_WORDS = (BRICK_Z + 2) * ACC_ZP;
