@@ -47,20 +47,22 @@ __device__ void block_partials(const double (&vals)[NS], double *__restrict__ pa
     }
 }
 
-// The whole block sums the partials of nblocks blocks in one fixed order
-// (thread t takes blocks t, t + blockDim, ..., then waves in order), so a
-// block of the producer's width gets the same bits wherever it runs.
+// The first `width` threads of the block (a multiple of 64, at most
+// blockDim.x; every thread must call this) sum the partials of nblocks
+// blocks in one fixed order: thread t takes blocks t, t + width, ..., then
+// its wave's sum, then the width / 64 waves in order.  Any block thus gets
+// the same bits for the same width; grid_reduce uses its own block width.
 // Thread 0 returns scale * total in tot.  COHERENT reads through to the
 // agent-coherent level (partials written by other blocks of this kernel).
 template <int NS, bool COHERENT>
 __device__ void sum_partials(const double *__restrict__ partials, int nblocks, double scale,
-                             double (&tot)[NS]) {
+                             int width, double (&tot)[NS]) {
     __shared__ double sm[NS][16];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = width >> 6;
     double acc[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    for (int b = threadIdx.x; threadIdx.x < width && b < nblocks; b += width) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             const double *q = &partials[(int64_t)b * RED_SLOTS + j];
@@ -71,7 +73,7 @@ __device__ void sum_partials(const double *__restrict__ partials, int nblocks, d
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         double v = wave_sum(acc[j]);
-        if (lane == 0) sm[j][wave] = v;
+        if (lane == 0 && wave < nwaves) sm[j][wave] = v;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -105,7 +107,7 @@ __device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ parti
     if (!is_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double tot[NS];
-    sum_partials<NS, true>(partials, nblocks, scale, tot);
+    sum_partials<NS, true>(partials, nblocks, scale, (int)blockDim.x, tot);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) store_agent(&out[j], tot[j]);

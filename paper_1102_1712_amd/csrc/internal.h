@@ -323,7 +323,18 @@ AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, 
 hipError_t launch_drr_adjoint_chain_batch(pcas_dtype dt, int K, const AdjJob *jobs, int njobs,
                                           int total_blocks, hipStream_t s);
 // dst[i * count + t] = src[i][t] for i < n (src: device array of pointers).
+// The deferred sum of one request's reduction in a serving pass: the
+// partials of nblocks blocks of `width` threads (ns totals, 0 for none),
+// stored as scale * total to out and to gathered slots [offset, offset + ns).
+struct SumJob {
+    const double *partials = nullptr;
+    double *out = nullptr;
+    double scale = 1.0;
+    int nblocks = 0, width = 0, ns = 0, offset = 0;
+};
+// dst[b * count + t] = src[b][t] for n requests (one 512-thread block each),
+// after finishing sums[b] when sums is given and sums[b].ns > 0.
 hipError_t launch_gather_scalars(const double *const *src, double *dst, int n, int count,
-                                 hipStream_t s);
+                                 const SumJob *sums, hipStream_t s);
 
 }  // namespace pcas

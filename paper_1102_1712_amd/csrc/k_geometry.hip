@@ -43,7 +43,7 @@ __global__ __launch_bounds__(1024) void k_publish_sum(const double *__restrict__
                                                       double *__restrict__ out, double *dst,
                                                       uint32_t *flag, uint32_t seq) {
     double tot[NS];
-    sum_partials<NS, false>(partials, nblocks, scale, tot);
+    sum_partials<NS, false>(partials, nblocks, scale, (int)blockDim.x, tot);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {

@@ -147,16 +147,52 @@ hipError_t launch_fit_from_sums(int64_t M, int fit, const double *sums, double *
 
 // Copies count doubles from each of n device locations into dst (n x count),
 // so a batch's scalars come back in one transfer.
-__global__ void k_gather_scalars(const double *const *__restrict__ src, double *__restrict__ dst,
-                                 int count) {
+template <int NS>
+__device__ void finish_sum(const SumJob &J, double *tot_s) {
+    double tot[NS];
+    sum_partials<NS, false>(J.partials, J.nblocks, J.scale, J.width, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            J.out[j] = tot[j];
+            tot_s[j] = tot[j];
+        }
+    }
+}
+
+constexpr int GATHER_THREADS = 512;
+static_assert(ADJ_THREADS <= GATHER_THREADS && FWD_THREADS <= GATHER_THREADS, "gather width");
+
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather_scalars(const double *const *__restrict__ src,
+                                                                   double *__restrict__ dst, int count,
+                                                                   const SumJob *__restrict__ sums) {
+    __shared__ double tot_s[RED_SLOTS];
     const int b = blockIdx.x;
-    for (int t = threadIdx.x; t < count; t += blockDim.x) dst[b * count + t] = src[b][t];
+    int lo = 0, hi = 0;
+    if (sums && sums[b].ns > 0) {   // uniform in the block
+        const SumJob J = sums[b];
+        switch (J.ns) {
+        case 1: finish_sum<1>(J, tot_s); break;
+        case 2: finish_sum<2>(J, tot_s); break;
+        case 3: finish_sum<3>(J, tot_s); break;
+        case 4: finish_sum<4>(J, tot_s); break;
+        case 5: finish_sum<5>(J, tot_s); break;
+        case 6: finish_sum<6>(J, tot_s); break;
+        case 7: finish_sum<7>(J, tot_s); break;
+        default: finish_sum<8>(J, tot_s); break;
+        }
+        __syncthreads();
+        lo = J.offset;
+        hi = J.offset + J.ns;
+    }
+    for (int t = threadIdx.x; t < count; t += blockDim.x)
+        dst[b * count + t] = (t >= lo && t < hi) ? tot_s[t - lo] : src[b][t];
 }
 
 hipError_t launch_gather_scalars(const double *const *src, double *dst, int n, int count,
-                                 hipStream_t s) {
+                                 const SumJob *sums, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_scalars, dim3(n), dim3(64), 0, s, src, dst, count);
+    hipLaunchKernelGGL(k_gather_scalars, dim3(n), dim3(GATHER_THREADS), 0, s, src, dst, count, sums);
     return hipGetLastError();
 }
 

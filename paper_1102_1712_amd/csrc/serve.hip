@@ -146,7 +146,7 @@ namespace {
 
 size_t table_bytes(int max_active) {
     const size_t per = sizeof(WarpJob) + sizeof(FwdJob) + sizeof(ResJob) + sizeof(AdjJob) +
-                       sizeof(double *) + GATHER * sizeof(double);
+                       sizeof(double *) + sizeof(SumJob) + GATHER * sizeof(double);
     return align256(per * (size_t)max_active + 4096);
 }
 
@@ -316,7 +316,11 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     Groups<ResJob, int> ress;
     Groups<AdjJob, DK> adjs;
     std::vector<Request *> locates, refused;
-    for (Request *r : set) {
+    // FP32 projections and all gradients leave block partials only; the
+    // gather finishes each request's sum (same order as a solve alone)
+    std::vector<SumJob> sums(set.size());
+    for (size_t ri = 0; ri < set.size(); ++ri) {
+        Request *r = set[ri];
         const Model &md = S->models[r->model];
         if (r->phase == PH_LOCATE) {
             locates.push_back(r);
@@ -346,10 +350,21 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             } else {
                 ff.mode = FIT_NONE;
             }
-            fwds.add({md.dt, r->plan.axis},
-                     make_fwd_job(md.vd, r->fr, r->plan, r->ws + r->L.rays, r->ws + r->L.f,
-                                  r->proj_slot(op.slot), r->y, ff, r->partials(),
-                                  &r->counters()[0], r->scal()));
+            const bool defer = md.dt == PCAS_F32;   // FP64's residual reads the sums on the GPU
+            const FwdJob fj = make_fwd_job(md.vd, r->fr, r->plan, r->ws + r->L.rays, r->ws + r->L.f,
+                                           r->proj_slot(op.slot), r->y, ff, r->partials(),
+                                           defer ? nullptr : &r->counters()[0], r->scal());
+            fwds.add({md.dt, r->plan.axis}, fj);
+            if (defer) {
+                SumJob &sj = sums[ri];
+                sj.partials = r->partials();
+                sj.out = r->scal();
+                sj.scale = 1.0;
+                sj.nblocks = fj.nblocks;
+                sj.width = FWD_THREADS;
+                sj.ns = 3;
+                sj.offset = 0;
+            }
             r->mom_slot = op.slot;
             r->mom_a0 = ff.a0;
             r->mom_b0 = ff.b0;
@@ -367,11 +382,19 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             }
             ress.add(md.dt, res_job(*r, op.slot, fa));
         } else if (op.kind == OP_GRAD) {
-            adjs.add({md.dt, md.K},
-                     make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot), r->y,
-                                  op.ab[0], op.ab[1], md.f0, md.mean, md.U, op.w, r->partials(),
-                                  &r->counters()[1], r->scal() + 8,
-                                  md.dt == PCAS_F32 ? r->bounds() : nullptr));
+            const AdjJob aj = make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot),
+                                           r->y, op.ab[0], op.ab[1], md.f0, md.mean, md.U, op.w,
+                                           r->partials(), nullptr, r->scal() + 8,
+                                           md.dt == PCAS_F32 ? r->bounds() : nullptr);
+            adjs.add({md.dt, md.K}, aj);
+            SumJob &sj = sums[ri];
+            sj.partials = r->partials();
+            sj.out = r->scal() + 8;
+            sj.scale = 2.0;
+            sj.nblocks = aj.nblocks;
+            sj.width = ADJ_THREADS;
+            sj.ns = md.K;
+            sj.offset = 8;
         }
     }
     // tables: [warp jobs][fwd jobs][res jobs][adj jobs][gather pointers][gather out]
@@ -393,6 +416,8 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     adjs.emit((AdjJob *)(h + o_a));
     const size_t o_p = carve(na * sizeof(double *));
     for (int i = 0; i < na; ++i) ((const double **)(h + o_p))[i] = set[i]->scal();
+    const size_t o_s = carve(na * sizeof(SumJob));
+    for (int i = 0; i < na; ++i) ((SumJob *)(h + o_s))[i] = sums[i];
     const size_t o_g = carve(na * GATHER * sizeof(double));
     if (o > S->tables_bytes) return hip_fail(hipErrorInvalidValue, "serving tables overflow");
     HIPCHK(hipMemcpyAsync(S->tables_dev, h, o_g, hipMemcpyHostToDevice, S->s));
@@ -417,7 +442,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                              r->opts.locate_tol, r->opts.locate_max_iter, r->scal() + 24, S->s));
     }
     HIPCHK(launch_gather_scalars((const double *const *)(d + o_p), (double *)(d + o_g), na, GATHER,
-                                 S->s));
+                                 (const SumJob *)(d + o_s), S->s));
     HIPCHK(hipMemcpyAsync(S->gather_host, d + o_g, na * GATHER * sizeof(double),
                           hipMemcpyDeviceToHost, S->s));
     HIPCHK(hipStreamSynchronize(S->s));
@@ -478,7 +503,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     HIPCHK(hipMemcpyAsync(S->tables_dev, h, o_g2, hipMemcpyHostToDevice, S->s));
     HIPCHK(launch_residual_batch(PCAS_F32, (const ResJob *)(d + o_r2), nr, blocks, S->s));
     HIPCHK(launch_gather_scalars((const double *const *)(d + o_p2), (double *)(d + o_g2), nr,
-                                 GATHER, S->s));
+                                 GATHER, nullptr, S->s));
     HIPCHK(hipMemcpyAsync(S->gather_host, d + o_g2, nr * GATHER * sizeof(double),
                           hipMemcpyDeviceToHost, S->s));
     HIPCHK(hipStreamSynchronize(S->s));
