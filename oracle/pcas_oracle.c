@@ -170,15 +170,13 @@ void orc_drr_pixels(const orc_vol *vol, const orc_proj *pr, const double *f,
         p[t] = orc_drr_pixel(vol, pr, f, (int32_t)(pix[t] % pr->nu), (int32_t)(pix[t] / pr->nu));
 }
 
-/* P^T r (the back-projection in the gradient of the Appendix): the literal
- * transpose of orc_drr_forward -- every sample sends dt * r to the same eight
- * voxels with the same trilinear weights.  Sequential, so the summation
- * order is fixed. */
-void orc_drr_adjoint(const orc_vol *vol, const orc_proj *pr, const double *r, double *bp)
+/* Scatter of the rays of detector rows [iv0, iv1) into bp (not cleared):
+ * every sample sends dt * r to the same eight voxels, with the same
+ * trilinear weights, that orc_drr_pixel reads it from. */
+static void adjoint_rows(const orc_vol *vol, const orc_proj *pr, const double *r, int32_t iv0,
+                         int32_t iv1, double *bp)
 {
-    int64_t N = (int64_t)vol->n[0] * vol->n[1] * vol->n[2];
-    memset(bp, 0, (size_t)N * sizeof(double));
-    for (int32_t iv = 0; iv < pr->nv; ++iv)
+    for (int32_t iv = iv0; iv < iv1; ++iv)
         for (int32_t iu = 0; iu < pr->nu; ++iu) {
             double rr = r[iu + (int64_t)pr->nu * iv];
             orc_ray ray;
@@ -206,6 +204,46 @@ void orc_drr_adjoint(const orc_vol *vol, const orc_proj *pr, const double *r, do
                         }
             }
         }
+}
+
+/* P^T r (the back-projection in the gradient of the Appendix): the literal
+ * transpose of orc_drr_forward.  The detector rows are cut into a fixed
+ * number of bands (up to 16, fewer when the private copies would pass
+ * 2 GiB); each band scatters into a private zeroed volume (bands run in
+ * parallel), then every voxel sums the bands in band order.  The partition
+ * and the order depend only on the sizes, never on the thread count, so the
+ * result is the same bits on any machine. */
+void orc_drr_adjoint(const orc_vol *vol, const orc_proj *pr, const double *r, double *bp)
+{
+    int64_t N = (int64_t)vol->n[0] * vol->n[1] * vol->n[2];
+    int64_t cap = ((int64_t)1 << 31) / (N * (int64_t)sizeof(double));
+    int32_t nb = cap < 1 ? 1 : (cap > 16 ? 16 : (int32_t)cap);
+    if (nb > pr->nv) nb = pr->nv;
+    if (nb <= 1) {
+        memset(bp, 0, (size_t)N * sizeof(double));
+        adjoint_rows(vol, pr, r, 0, pr->nv, bp);
+        return;
+    }
+    double *part = (double *)calloc((size_t)nb * (size_t)N, sizeof(double));
+    if (!part) {   /* no room for the private copies: one sequential band */
+        memset(bp, 0, (size_t)N * sizeof(double));
+        adjoint_rows(vol, pr, r, 0, pr->nv, bp);
+        return;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t t = 0; t < nb; ++t) {
+        int32_t iv0 = (int32_t)((int64_t)pr->nv * t / nb);
+        int32_t iv1 = (int32_t)((int64_t)pr->nv * (t + 1) / nb);
+        adjoint_rows(vol, pr, r, iv0, iv1, part + (int64_t)t * N);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < N; ++v) {
+        double acc = 0.0;
+        for (int32_t t = 0; t < nb; ++t)
+            acc += part[(int64_t)t * N + v];
+        bp[v] = acc;
+    }
+    free(part);
 }
 
 /* Eq. 1: x = xbar + sum_k u_k w_k.  mean may be NULL (zero mean). */
@@ -275,19 +313,34 @@ void orc_warp_jacobian(const orc_vol *vol, const double *f0, const double *x, do
 }
 
 /* Gradient chain of the Appendix: dJ/dw = 2 U^T (df/dx) P^T r, with the
- * diagonal Jacobian applied component-wise.  Summed sequentially. */
+ * diagonal Jacobian applied component-wise.  The voxels are cut into 64
+ * fixed chunks summed in parallel; the chunk sums are added in chunk order,
+ * so the result does not depend on the thread count. */
 void orc_grad_chain(int64_t N, int32_t K, const double *U, const double *jac, const double *bp, double *g)
 {
+    enum { NCH = 64 };
+    double *part = (double *)malloc((size_t)NCH * (size_t)K * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < NCH; ++t) {
+        int64_t v0 = N * t / NCH, v1 = N * (t + 1) / NCH;
+        for (int32_t k = 0; k < K; ++k) {
+            double acc = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double *u = U + ((int64_t)k * 3 + c) * N;
+                const double *jc = jac + (int64_t)c * N;
+                for (int64_t v = v0; v < v1; ++v)
+                    acc += u[v] * jc[v] * bp[v];
+            }
+            part[(int64_t)t * K + k] = acc;
+        }
+    }
     for (int32_t k = 0; k < K; ++k) {
         double acc = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const double *u = U + ((int64_t)k * 3 + c) * N;
-            const double *jc = jac + (int64_t)c * N;
-            for (int64_t v = 0; v < N; ++v)
-                acc += u[v] * jc[v] * bp[v];
-        }
+        for (int t = 0; t < NCH; ++t)
+            acc += part[(int64_t)t * K + k];
         g[k] = 2.0 * acc;
     }
+    free(part);
 }
 
 /* Trilinear value of the DVF (Eq. 1 evaluated at the eight neighbours) at a

@@ -55,6 +55,7 @@ void pcas_default_opts(pcas_opts *o) {
     o->ftol_rel = -1.0;
     o->grad_mode = 1;
     o->ls_extrap = 10.0;
+    o->polish = 1;
 }
 
 void pcas_paper_opts(pcas_opts *o) {

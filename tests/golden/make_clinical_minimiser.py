@@ -28,17 +28,19 @@ def main():
     # already rounded to the case's type)
     y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
     y = y.astype(np.float32).astype(np.float64)
-    out = {"_source": "FP64 oracle (solve_bfgs, default options) on synth.clinical(); "
+    out = {"_source": "FP64 oracle (oracle.minimise: plain CG, then Newton's method on the "
+                      "gradient to ||g|| <= 1e-10 ||g0||) on synth.clinical(); "
                       "written by tests/golden/make_clinical_minimiser.py",
            "workload": c.name, "angle": c.proj.angle, "w_star": list(map(float, c.w_star))}
     for fit in (True, False):
         prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y, fit_intensity=fit)
-        w, rep = O.solve_bfgs(prob, np.zeros(c.K))
+        w, info = O.minimise(prob, np.zeros(c.K))
         loc, it = O.locate(c.vol, c.mean, c.U, w, c.tumour_c0)
         out["fit" if fit else "nofit"] = {
-            "w": list(map(float, w)), "J": rep.J, "a": rep.a, "b": rep.b, "status": rep.status,
-            "iters": rep.iters, "gnorm_rel": rep.gnorm / float(np.linalg.norm(
-                prob.gradient(np.zeros(c.K), prob.objective(np.zeros(c.K))[3]))),
+            "w": list(map(float, w)), "J": info["J"], "a": info["a"], "b": info["b"],
+            "cg_iters": info["cg"].iters, "newton_steps": info["newton_steps"],
+            "gnorm_rel": info["gnorm"] / info["gnorm0"],
+            "hessian_eigs": list(map(float, info["hessian_eigs"])),
             "tumour_mm": list(map(float, loc))}
         print(fit, out["fit" if fit else "nofit"], flush=True)
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "clinical_minimiser.json"),

@@ -29,22 +29,28 @@ def clinical():
     return c, d, y, json.load(open(GOLDEN))
 
 
-def _solve(c, d, y, fit, method, polish):
-    opts = B.default_opts(xtol=1e-7, method=method, polish=polish, fit_intensity=int(fit), locate=1,
-                          c0_mm=tuple(c.tumour_c0))
+def _solve(c, d, y, fit, method, polish=None):
+    """The benchmark's options (the library defaults, xtol 1e-7, localisation
+    on), with the method, fit and, when given, the polish step overridden."""
+    kw = dict(xtol=1e-7, method=method, fit_intensity=int(fit), locate=1,
+              c0_mm=tuple(c.tumour_c0))
+    if polish is not None:
+        kw["polish"] = polish
+    opts = B.default_opts(**kw)
     return B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K), opts)
 
 
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
-def test_clinical_polished_solve_matches_oracle_minimiser(clinical, fit, method):
-    """With the polish step: w within 1e-4 of the FP64 minimiser, tumour
-    position within 0.05 mm."""
+def test_clinical_timed_solve_matches_oracle_minimiser(clinical, fit, method):
+    """The configuration bench.py times (default options, which include the
+    polish step): w within 1e-4 of the FP64 minimiser, tumour position within
+    0.05 mm."""
     c, d, y, gold = clinical
     ref = gold["fit" if fit else "nofit"]
     assert gold["workload"] == c.name and gold["angle"] == c.proj.angle
-    say("clinical polished solve fit", fit, "method", method)
-    w, rep = _solve(c, d, y, fit, method, 1)
+    say("clinical default solve fit", fit, "method", method)
+    w, rep = _solve(c, d, y, fit, method)
     w_ref = np.array(ref["w"])
     err = np.linalg.norm(w - w_ref) / np.linalg.norm(w_ref)
     say("gpu", w, rep["status"], rep["n_fevals"], rep["n_grads"], "err", err)
@@ -55,15 +61,15 @@ def test_clinical_polished_solve_matches_oracle_minimiser(clinical, fit, method)
 
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
-def test_clinical_default_solve_stops_at_band(clinical, oracle_lib, fit, method):
-    """The default configuration (no polish): the solve ends converged where
+def test_clinical_unpolished_solve_stops_at_band(clinical, oracle_lib, fit, method):
+    """With the polish step off: the solve ends converged where
     FP32 values of J no longer resolve a decrease: the FP64 objective at the
     returned w exceeds the oracle's minimum by at most twice the noise band
     6 u sqrt(sum p^2 / (M J)) J (u = 2^-24); tumour within 0.05 mm."""
     import oracle as O
     c, d, y, gold = clinical
     ref = gold["fit" if fit else "nofit"]
-    say("clinical default solve fit", fit, "method", method)
+    say("clinical unpolished solve fit", fit, "method", method)
     w, rep = _solve(c, d, y, fit, method, 0)
     prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, measured(c), fit_intensity=fit)
     J64, a, b, r = prob.objective(w)

@@ -84,7 +84,7 @@ def test_solve_with_exact_path_measurement(torch):
     w, rep = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), np.zeros(c.K),
                                 B.default_opts())
     prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y)
-    w_o, rep_o = O.solve_cg(prob, np.zeros(c.K))
+    w_o, _ = O.minimise(prob, np.zeros(c.K))
     say("exact-path data: gpu", w, rep["status"], "oracle", w_o, "planted", c.w_star)
     assert rep["status"] in ("converged", "line_search")
     assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)

@@ -1,8 +1,11 @@
-"""Solve parity: solve_projection through the C ABI against the oracle's
-solver on the same inputs and the same w0.  The objective is non-convex in
-general and iterate sequences may part ways on rounding, so converged
-minimisers are compared (1e-4 relative in w, 0.05 mm in the tumour
-position)."""
+"""Solve parity: solve_projection through the C ABI against the oracle on
+the same inputs and the same w0.  The library's CG and BFGS take steps of
+their own (a model first trial, an extrapolated trial, a noise-band stop and
+a polish step), so converged minimisers are compared with the oracle's
+reference minimiser (oracle.minimise: plain CG, then Newton's method on the
+gradient): 1e-4 relative in w, 0.05 mm in the tumour position.  The
+Appendix algorithm, fully specified by the paper, is compared step for
+step."""
 import numpy as np
 import pytest
 
@@ -29,6 +32,17 @@ def _oracle_problem(c, y, fit=True):
     return O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y, fit_intensity=fit)
 
 
+_MINIMISERS = {}
+
+
+def _minimiser(c, y, fit=True):
+    """oracle.minimise from w0 = 0, once per (case, fit) in this module."""
+    key = (c.name, fit, y.tobytes()[:64], float(y.sum()))
+    if key not in _MINIMISERS:
+        _MINIMISERS[key] = O.minimise(_oracle_problem(c, y, fit), np.zeros(c.K))
+    return _MINIMISERS[key]
+
+
 def test_tiny_cg_matches_oracle(torch):
     """64^3 FP64, 128x128 detector, 1% noise, CG from w0 = 0 (the tiny workload)."""
     c = synth.tiny()
@@ -37,15 +51,15 @@ def test_tiny_cg_matches_oracle(torch):
     say("tiny CG solve")
     opts = B.default_opts(locate=1, c0_mm=tuple(c.tumour_c0))
     w, rep = _gpu_solve(d, y, opts)
-    w_o, rep_o = O.solve_cg(_oracle_problem(c, y), np.zeros(c.K))
+    w_o, info = _minimiser(c, y)
     say("gpu", w, rep)
-    say("oracle", w_o, rep_o.status, rep_o.iters, rep_o.J)
-    # both sides stop at a stationary point: the gradient test or a line
-    # search that can no longer decrease J (rounding floor)
+    say("oracle", w_o, info["J"], info["newton_steps"])
+    # a stationary point: the gradient test, or a stop where FP64 values of J
+    # no longer resolve a decrease, then the polish step
     assert rep["status"] in ("converged", "line_search")
     assert rep["gnorm"] <= 1e-6 * rep["gnorm0"]
     assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)
-    assert abs(rep["J"] - rep_o.J) <= 1e-8 * rep_o.J
+    assert abs(rep["J"] - info["J"]) <= 1e-8 * info["J"]
     loc_o, _ = O.locate(c.vol, c.mean, c.U, w_o, c.tumour_c0)
     assert np.linalg.norm(np.array(rep["tumour_mm"]) - loc_o) <= 0.05
     assert rep["locate_iters"] > 0
@@ -80,21 +94,21 @@ def test_recovery32_noise_free(torch, method):
 
 
 def test_tiny_bfgs_matches_oracle(torch):
-    """The tiny workload with the quasi-Newton solver: the same minimiser as
-    the oracle's BFGS, in fewer evaluations than CG."""
+    """The tiny workload with the quasi-Newton solver: the oracle's minimiser,
+    in fewer evaluations than CG."""
     c = synth.tiny()
     d = Dev(c)
     y = measured(c)
     say("tiny BFGS solve")
     w, rep = _gpu_solve(d, y, B.default_opts(method=2))
-    w_o, rep_o = O.solve_bfgs(_oracle_problem(c, y), np.zeros(c.K))
+    w_o, info = _minimiser(c, y)
     _, rep_cg = _gpu_solve(d, y, B.default_opts())
     say("gpu", w, rep)
-    say("oracle", w_o, rep_o.status, rep_o.iters, rep_o.n_fevals, rep_o.J)
+    say("oracle", w_o, info["J"])
     assert rep["status"] in ("converged", "line_search")
     assert rep["gnorm"] <= 1e-6 * rep["gnorm0"]
     assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)
-    assert abs(rep["J"] - rep_o.J) <= 1e-8 * rep_o.J
+    assert abs(rep["J"] - info["J"]) <= 1e-8 * info["J"]
     assert rep["n_fevals"] < rep_cg["n_fevals"]
 
 
@@ -136,26 +150,28 @@ def test_polish_reported_point_is_consistent(torch, method):
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
 def test_small_f32_solve_matches_oracle(torch, fit, method):
-    """Ragged anisotropic FP32 case with the polish step: converged w within
-    1e-4 of the FP64 oracle's minimiser.  (Comparisons of FP32 values of J
-    stop at J's rounding noise, about 3e-7 J on this 1920-pixel detector; the
-    polish step goes on from there with the gradient.)"""
+    """Ragged anisotropic FP32 case with the default options (the polish step
+    on): converged w within 1e-4 of the FP64 oracle's minimiser.
+    (Comparisons of FP32 values of J stop at J's rounding noise, about 3e-7 J
+    on this 1920-pixel detector; the polish step goes on from there with the
+    gradient.)"""
     c = synth.small(dtype="f32", seed=6)
     d = Dev(c)
     y = measured(c)
     say("small f32 solve fit=", fit, "method", method)
-    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method, polish=1)
+    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method)
+    assert opts.polish == 1
     w, rep = _gpu_solve(d, y, opts)
-    w_o, rep_o = O.solve(_oracle_problem(c, y, fit), np.zeros(c.K), O.SolveOptions(method=method))
+    w_o, info = _minimiser(c, y, fit)
     say("gpu", w, rep)
-    say("oracle", w_o, rep_o.status, rep_o.iters)
+    say("oracle", w_o, info["J"])
     assert np.linalg.norm(w - w_o) <= 1e-4 * np.linalg.norm(w_o)
 
 
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
 def test_small_f32_default_stops_at_noise_band(torch, fit, method):
-    """Without the polish step an FP32 solve ends where FP32 values of J can
+    """With the polish step off an FP32 solve ends where FP32 values of J can
     no longer show a decrease: the FP64 objective at the returned w exceeds
     its minimum by no more than twice the band 6 u sqrt(sum p^2 / (M J)) J
     (u = 2^-24), at any size, and the solve says it converged."""
@@ -163,16 +179,16 @@ def test_small_f32_default_stops_at_noise_band(torch, fit, method):
     d = Dev(c)
     y = measured(c)
     say("small f32 default solve fit=", fit, "method", method)
-    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method)
+    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method, polish=0)
     w, rep = _gpu_solve(d, y, opts)
     prob = _oracle_problem(c, y, fit)
-    w_o, rep_o = O.solve(prob, np.zeros(c.K), O.SolveOptions(method=method))
+    w_o, info = _minimiser(c, y, fit)
     J64, a, b, r = prob.objective(w)
     p = r + a * y + b
     band = 6.0 * 2.0 ** -24 * np.sqrt(float(np.sum(p * p)) / (p.size * J64))
-    say("gpu", w, rep["status"], "excess", (J64 - rep_o.J) / rep_o.J, "band", band)
+    say("gpu", w, rep["status"], "excess", (J64 - info["J"]) / info["J"], "band", band)
     assert rep["status"] == "converged"
-    assert J64 - rep_o.J <= 2.0 * band * rep_o.J
+    assert J64 - info["J"] <= 2.0 * band * info["J"]
     assert np.linalg.norm(w - w_o) <= 1e-3 * np.linalg.norm(w_o)
 
 
@@ -183,7 +199,7 @@ def test_k1_solve(torch):
     y = measured(c)
     say("K=1 solve")
     w, rep = _gpu_solve(d, y, B.default_opts())
-    w_o, _ = O.solve_cg(_oracle_problem(c, y), np.zeros(1))
+    w_o, _ = _minimiser(c, y)
     assert abs(w[0] - w_o[0]) <= 1e-4 * max(abs(w_o[0]), 1.0)
 
 

@@ -48,7 +48,7 @@ def test_stream_small_f64(torch):
     for t in (0, 3, 11, n_frames - 1):
         pj = dataclasses.replace(c.proj, angle=float(angles[t]))
         prob = O.Problem(c.vol, pj, c.f0, c.mean, c.U, ys[t])
-        w_o, _ = O.solve_cg(prob, w0s[t])
+        w_o, _ = O.minimise(prob, w0s[t])
         w_g = rep.frames[t].w
         assert np.linalg.norm(w_g - w_o) <= 1e-4 * max(np.linalg.norm(w_o), 1e-3), t
     truth = np.array([O.locate(c.vol, c.mean, c.U, w, c.tumour_c0)[0] for w in w_true])

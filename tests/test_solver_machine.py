@@ -1,11 +1,16 @@
 """Host logic of the solver state machine (the C++ that drives every GPU
-solve), checked on the CPU against the oracle's solvers.
+solve), checked on the CPU against its step-for-step specification
+(tests/solver_machine_spec.py, not the oracle).
 
 The machine is built with g++ into a small harness that replaces the GPU
 evaluations by callbacks.  On the same objective and the same options it
-must take the oracle's steps: the same accepted points, the same number of
-evaluations and gradients, the same stop status.  The callbacks also check
-that every gradient request names the projection slot that holds its point.
+must take the specification's steps: the same accepted points, the same
+number of evaluations and gradients, the same stop status.  The callbacks
+also check that every gradient request names the projection slot that holds
+its point.  The specification's own rules (the BFGS update, the extrapolated
+trial, the decrement stop, the polish step) are pinned below on quadratics
+with closed-form answers.  The method's parity is checked elsewhere, against
+the oracle's minimiser.
 """
 import ctypes
 import os
@@ -15,6 +20,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import solver_machine_spec as S
 from paper_1102_1712_amd import binding as B
 from paper_1102_1712_amd import synth
 
@@ -108,16 +114,16 @@ def _opts(method, **kw):
     return o
 
 
-def _oracle_opts(o: B.Opts):
-    return O.SolveOptions(method=o.method, max_iter=o.max_iter, max_backtracks=o.max_backtracks,
-                          mu0=o.mu0, alpha=o.alpha, beta=o.beta, mu_min=o.mu_min,
-                          gtol_rel=o.gtol_rel, beta_lo=o.beta_lo, xtol=o.xtol,
-                          ftol_rel=o.ftol_rel, ls_extrap=o.ls_extrap, polish=bool(o.polish))
+def _spec_opts(o: B.Opts):
+    return S.MachineOptions(method=o.method, max_iter=o.max_iter, max_backtracks=o.max_backtracks,
+                            mu0=o.mu0, alpha=o.alpha, beta=o.beta, gtol_rel=o.gtol_rel,
+                            beta_lo=o.beta_lo, xtol=o.xtol, ftol_rel=o.ftol_rel,
+                            ls_extrap=o.ls_extrap, polish=bool(o.polish))
 
 
 def _compare(lib, prob, K, w0, o, rtol):
     w_m, rep_m, acc = _machine_solve(lib, prob, K, w0, o, o.ftol_rel)
-    w_o, rep_o = O.solve(prob, w0, _oracle_opts(o))
+    w_o, rep_o = S.machine_solve(prob, w0, _spec_opts(o))
     assert (rep_m.status, rep_m.iters, rep_m.n_fevals, rep_m.n_grads) == \
         (rep_o.status, rep_o.iters, rep_o.n_fevals, rep_o.n_grads)
     np.testing.assert_allclose(w_m, w_o, rtol=rtol, atol=rtol * np.abs(w_o).max())
@@ -127,7 +133,7 @@ def _compare(lib, prob, K, w0, o, rtol):
 
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("K,kappa,seed", [(1, 1.0, 0), (3, 10.0, 1), (5, 1e3, 2), (8, 1e3, 3)])
-def test_machine_matches_oracle_on_quadratics(harness, method, K, kappa, seed):
+def test_machine_matches_spec_on_quadratics(harness, method, K, kappa, seed):
     rng = np.random.default_rng(100 + seed)
     Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
     A = Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T
@@ -142,16 +148,16 @@ def test_machine_matches_oracle_on_quadratics(harness, method, K, kappa, seed):
 
 
 @pytest.mark.parametrize("K,kappa,seed", [(3, 10.0, 4), (8, 1e3, 5)])
-def test_machine_decrement_stop_matches_oracle(harness, K, kappa, seed):
+def test_machine_decrement_stop_matches_spec(harness, K, kappa, seed):
     """BFGS ending on its predicted decrease (ftol_rel = 1e-6, no gradient
-    test): same stop, same evaluations as the oracle."""
+    test): same stop, same evaluations as the specification."""
     rng = np.random.default_rng(200 + seed)
     Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
     A = Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T
     c = 3.0 * rng.normal(size=K)
     rep, _ = _compare(harness, _Quadratic(A, c), K, np.zeros(K),
                       _opts(2, ftol_rel=1e-6, gtol_rel=0.0), 1e-9)
-    assert rep.status == O.STOP_CONVERGED
+    assert rep.status == S.STOP_CONVERGED
 
 
 @pytest.mark.parametrize("extrap", [0.0, 3.0, 10.0])
@@ -183,30 +189,30 @@ def test_machine_rejected_extrapolation_keeps_slot0(harness):
 
 
 @pytest.mark.parametrize("method", [1, 2])
-def test_machine_matches_oracle_on_small_problem(harness, oracle_lib, method):
+def test_machine_matches_spec_on_small_problem(harness, oracle_lib, method):
     """A real 24^3-class FP64 problem with the oracle as the evaluator: the
-    machine and the oracle's solver take the same steps."""
+    machine and its specification take the same steps."""
     c = synth.small(seed=18)
     y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
     prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y)
     # stops on the gradient test, above the rounding floor where a near-tie
     # between the two sides' summation orders could end them an iteration apart
     rep, acc = _compare(harness, prob, c.K, np.zeros(c.K), _opts(method, gtol_rel=1e-6), 1e-9)
-    assert rep.status == O.STOP_CONVERGED
+    assert rep.status == S.STOP_CONVERGED
 
 
 @pytest.mark.parametrize("method,K,kappa,seed", [(1, 3, 10.0, 6), (1, 5, 100.0, 7),
                                                  (2, 3, 10.0, 6), (2, 8, 1e3, 7)])
-def test_machine_polish_matches_oracle(harness, method, K, kappa, seed):
+def test_machine_polish_matches_spec(harness, method, K, kappa, seed):
     """The polish step after a stop at a coarse noise band: same steps,
-    same final point as the oracle."""
+    same final point as the specification."""
     rng = np.random.default_rng(300 + seed)
     Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
     A = Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T
     c = 3.0 * rng.normal(size=K)
     o = _opts(method, ftol_rel=1e-6, gtol_rel=0.0, max_iter=200, polish=1)
     rep, _ = _compare(harness, _Quadratic(A, c), K, np.zeros(K), o, 1e-9 if kappa <= 10.0 else 1e-6)
-    assert rep.status in (O.STOP_CONVERGED, O.STOP_LINESEARCH)   # both end at the band
+    assert rep.status in (S.STOP_CONVERGED, S.STOP_LINESEARCH)   # both end at the band
 
 
 def test_noise_model_identity_and_band(harness, oracle_lib):
@@ -241,3 +247,135 @@ def test_noise_model_identity_and_band(harness, oracle_lib):
     spread = float(np.std(Js - np.polyval(coef, e)))
     assert spread > 0.0
     assert spread <= band * J <= 30.0 * spread, (spread / J, band)
+
+
+
+# ---------------------------------------------------------------------------
+# The specification's own rules, on problems with closed-form answers.
+# ---------------------------------------------------------------------------
+
+def _spd(rng, K, kappa):
+    Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
+    return Q @ np.diag(np.geomspace(1.0, kappa, K)) @ Q.T, Q
+
+
+def test_spec_bfgs_update_secant_symmetric_definite():
+    """Eq. 6.17 of Nocedal and Wright: the updated inverse-Hessian estimate
+    maps y to s (the secant equation), is symmetric, and stays positive
+    definite for y.s > 0."""
+    rng = np.random.default_rng(40)
+    for K in (1, 3, 8):
+        A, _ = _spd(rng, K, 20.0)
+        H = np.linalg.inv(_spd(rng, K, 5.0)[0])
+        s = rng.normal(size=K)
+        y = A @ s
+        Hn = S.bfgs_update(H, s, y)
+        np.testing.assert_allclose(Hn @ y, s, rtol=0, atol=1e-12 * np.linalg.norm(s))
+        np.testing.assert_allclose(Hn, Hn.T, rtol=0, atol=1e-14 * np.abs(Hn).max())
+        assert np.linalg.eigvalsh(0.5 * (Hn + Hn.T)).min() > 0.0
+
+
+def test_spec_bfgs_update_reaches_inverse_after_conjugate_steps():
+    """On a quadratic, K updates along mutually A-conjugate steps (here A's
+    eigenvectors) with y = A s turn any SPD start into A^-1 exactly."""
+    rng = np.random.default_rng(41)
+    K = 5
+    A, Q = _spd(rng, K, 50.0)
+    H = 0.3 * np.eye(K)
+    for i in range(K):
+        H = S.bfgs_update(H, Q[:, i], A @ Q[:, i])
+    np.testing.assert_allclose(H, np.linalg.inv(A), rtol=0, atol=1e-13)
+
+
+def test_spec_curvature_update_secant():
+    """Eq. 6.19 of Nocedal and Wright (the direct update the CG's step model
+    keeps): B+ s = y, symmetric."""
+    rng = np.random.default_rng(47)
+    for K in (1, 4):
+        A, _ = _spd(rng, K, 20.0)
+        B0 = _spd(rng, K, 5.0)[0]
+        s = rng.normal(size=K)
+        Bn = S.curvature_update(B0, s, A @ s)
+        np.testing.assert_allclose(Bn @ s, A @ s, rtol=0, atol=1e-12 * np.linalg.norm(A @ s))
+        np.testing.assert_allclose(Bn, Bn.T, rtol=0, atol=1e-13 * np.abs(Bn).max())
+
+
+def test_spec_extrapolation_lands_on_1d_quadratic_minimiser():
+    """phi(w) = w^2 - 6 w: minimiser 3, gradient -6 at 0.  With mu0 = 0.6 the
+    first trial (w = 0.6) passes Armijo, and the quadratic through phi(0),
+    phi'(0), phi(0.6) is phi itself, so the extrapolated trial is the exact
+    minimiser when the cap allows it (ls_extrap >= 5), the cap otherwise,
+    and no trial at all when switched off."""
+    q = _Quadratic(np.array([[2.0]]), np.array([6.0]))
+    for extrap, want, nf in ((10.0, 3.0, 3), (3.0, 1.8, 3), (0.0, 0.6, 2)):
+        w, rep = S.machine_cg(q, np.zeros(1), S.MachineOptions(mu0=0.6, max_iter=1,
+                                                               ls_extrap=extrap))
+        assert abs(w[0] - want) <= 1e-14 * want and rep.n_fevals == nf
+
+
+def test_spec_solvers_reach_quadratic_minimiser():
+    """Both machine solvers end at A^-1 c on ill-conditioned quadratics."""
+    rng = np.random.default_rng(42)
+    for K, kappa, solver, max_iter, tol in ((5, 1e3, S.machine_bfgs, 30, 1e-7),
+                                            (8, 1e3, S.machine_bfgs, 30, 1e-7),
+                                            (5, 1e2, S.machine_cg, 200, 1e-6)):
+        A, _ = _spd(rng, K, kappa)
+        c = 3.0 * rng.normal(size=K)
+        ws = np.linalg.solve(A, c)
+        w, rep = solver(_Quadratic(A, c), np.zeros(K), S.MachineOptions(max_iter=max_iter))
+        assert np.linalg.norm(w - ws) <= tol * np.linalg.norm(ws), (K, kappa, rep)
+
+
+def test_spec_bfgs_decrement_stop():
+    """With an estimate H, BFGS ends when g.H g / 2 (the decrease its model
+    predicts) is within ftol_rel of phi.  On a quadratic, once H is near A^-1
+    that is the true remaining decrease phi - phi*: a stop at ftol_rel = 1e-6
+    is converged, leaves phi - phi* within a few ftol_rel phi, and saves
+    evaluations over a run to the rounding floor."""
+    rng = np.random.default_rng(43)
+    for K, kappa in ((3, 10.0), (5, 100.0), (8, 1e3)):
+        A, _ = _spd(rng, K, kappa)
+        c = 3.0 * rng.normal(size=K)
+        q = _Quadratic(A, c)
+        phi_star = q.objective(np.linalg.solve(A, c))[0]
+        w, rep = S.machine_bfgs(q, np.zeros(K), S.MachineOptions(ftol_rel=1e-6, gtol_rel=0.0))
+        w_f, rep_f = S.machine_bfgs(q, np.zeros(K), S.MachineOptions(ftol_rel=0.0, gtol_rel=1e-12))
+        assert rep.status == S.STOP_CONVERGED
+        assert 0.0 <= rep.J - phi_star <= 4e-6 * rep.J
+        assert rep.n_fevals < rep_f.n_fevals
+
+
+def test_spec_polish_step_on_quadratics():
+    """The polish step: a solve stopped at a coarse noise band (ftol_rel =
+    1e-6) takes one step w - H g.  On a quadratic, with H from the solver's
+    own BFGS updates (CG keeps one from its steps), the step lands far closer
+    to A^-1 c than the stop did; it costs one evaluation and one gradient."""
+    rng = np.random.default_rng(44)
+    cases = ((5, 100.0, S.machine_cg), (5, 100.0, S.machine_bfgs))
+    for K, kappa, solver in cases:
+        A, _ = _spd(rng, K, kappa)
+        c = 3.0 * rng.normal(size=K)
+        ws = np.linalg.solve(A, c)
+        q = _Quadratic(A, c)
+        o = dict(ftol_rel=1e-6, gtol_rel=0.0, max_iter=200)
+        w0, r0 = solver(q, np.zeros(K), S.MachineOptions(**o))
+        w1, r1 = solver(q, np.zeros(K), S.MachineOptions(polish=True, **o))
+        e0 = np.linalg.norm(w0 - ws) / np.linalg.norm(ws)
+        e1 = np.linalg.norm(w1 - ws) / np.linalg.norm(ws)
+        assert r0.status in (S.STOP_CONVERGED, S.STOP_LINESEARCH) and r1.status == r0.status
+        assert e1 <= 0.1 * e0, (K, e0, e1)
+        assert (r1.n_fevals, r1.n_grads) == (r0.n_fevals + 1, r0.n_grads + 1)
+        assert r1.gnorm < r0.gnorm
+
+
+def test_spec_solvers_reach_the_oracle_minimiser(oracle_lib):
+    """On a real noisy FP64 problem both machine solvers end at the oracle's
+    own minimiser (oracle.minimise, which shares none of their rules)."""
+    c = synth.small(seed=17)
+    y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
+    prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y)
+    w_ref, _ = O.minimise(prob, np.zeros(c.K))
+    for solver in (S.machine_cg, S.machine_bfgs):
+        w, rep = solver(prob, np.zeros(c.K))
+        assert rep.status == S.STOP_CONVERGED
+        assert np.linalg.norm(w - w_ref) <= 1e-6 * np.linalg.norm(w_ref)
