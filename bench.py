@@ -148,44 +148,80 @@ def samples_per_drr(rays, dtype: str) -> int:
     return int(n.astype(np.int64).sum())
 
 
-def cpu_baseline(case, n_fevals: int, n_grads: int, budget_s: float, samples: int = 0):
-    """Time the FP64 oracle on the host cores on a bounded sample of the same
-    workload -- whole forward evaluations (warp + projection + fit) and whole
-    gradient evaluations (back-projection + Jacobian chain) at full size --
-    and scale to one solve with the GPU solve's evaluation counts."""
-    import oracle as O
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
-    y = None
-    t_fwd, t_grad = [], []
-    prob = None
-    w = np.zeros(case.K)
-    t_start = time.time()
-    while time.time() - t_start < budget_s or not t_grad:
-        t0 = time.time()
-        if prob is None:
-            # the measured image for the oracle comes from its own forward model
-            y = O.measured_projection(case.vol, case.proj, case.f0, case.mean, case.U,
-                                      case.w_star, case.xi, case.noise_level)
-            prob = O.Problem(case.vol, case.proj, case.f0, case.mean, case.U, y)
-            t0 = time.time()
-        J, a, b, r = prob.objective(w)
-        t1 = time.time()
-        prob.gradient(w, r)
-        t2 = time.time()
-        t_fwd.append(t1 - t0)
-        t_grad.append(t2 - t1)
-        log(f"oracle evaluation: forward {t1 - t0:.2f} s, gradient {t2 - t1:.2f} s")
-        w = w + 0.1
-    tf, tg = float(np.median(t_fwd)), float(np.median(t_grad))
-    t_solve = n_fevals * tf + n_grads * tg
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+def host_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+def _oracle_problem(case):
+    import oracle as O
+    # the oracle's measured image comes from its own forward model
+    y = O.measured_projection(case.vol, case.proj, case.f0, case.mean, case.U, case.w_star,
+                              case.xi, case.noise_level)
+    return O.Problem(case.vol, case.proj, case.f0, case.mean, case.U, y)
+
+
+def cpu_baseline(case, samples: int, tiny_runs: int = 3):
+    """The FP64 oracle as it stands (test infrastructure, never tuned for
+    this), timed on the host cores:
+      * one full solve of the benchmark's workload from w0 = 0 with the
+        oracle's plain PR+ CG (at most 30 iterations, stop at ||g|| <= 1e-6
+        ||g0||), on all cores: `value`, in solves/s;
+      * the tiny workload's full solve, median of tiny_runs, on all cores and
+        on one core;
+      * one forward evaluation of the benchmark's workload (forward samples/s).
+    """
+    import oracle as O
+    from paper_1102_1712_amd import synth
+
+    n_all = host_threads()
+    O.set_threads(n_all)
+    prob = _oracle_problem(case)
+    w0 = np.zeros(case.K)
+    t0 = time.perf_counter()
+    prob.objective(w0)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w, rep = O.solve_cg(prob, w0)
+    t_solve = time.perf_counter() - t0
+    log(f"oracle clinical solve: {t_solve:.1f} s ({rep.iters} iterations, {rep.n_fevals} "
+        f"evaluations, {rep.n_grads} gradients)")
+    tiny = synth.tiny()
+    tprob = _oracle_problem(tiny)
+    tiny_t = {}
+    for label, n in (("all_cores", n_all), ("one_core", 1)):
+        O.set_threads(n)
+        ts = []
+        for _ in range(tiny_runs):
+            t0 = time.perf_counter()
+            _, trep = O.solve_cg(tprob, np.zeros(tiny.K))
+            ts.append(time.perf_counter() - t0)
+        tiny_t[label] = {"threads": n, "median_s": float(np.median(ts)),
+                         "runs_s": [float(t) for t in ts]}
+        log(f"oracle tiny solve, {n} threads: median {np.median(ts):.2f} s")
+    O.set_threads(n_all)
     return {
-        "value": 1.0 / t_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
-        "forward_gsamples_s": samples / tf / 1e9 if samples else None,
-        "sample": (f"{len(t_fwd)} forward + {len(t_grad)} gradient evaluations of the FP64 oracle "
-                   f"on the full {case.name} workload (median forward {tf:.2f} s, gradient "
-                   f"{tg:.2f} s), scaled by the GPU solve's {n_fevals} forward and {n_grads} "
-                   f"gradient evaluations"),
+        "value": 1.0 / t_solve, "unit": "solves/s", "cores": n_all, "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "solve_s": t_solve, "iters": rep.iters, "n_fevals": rep.n_fevals, "n_grads": rep.n_grads,
+        "forward_s": t_fwd,
+        "forward_gsamples_s": samples / t_fwd / 1e9 if samples else None,
+        "tiny_solve": tiny_t,
+        "sample": (f"one full FP64 oracle solve of the {case.name} workload from w0 = 0 (plain "
+                   f"PR+ CG: {rep.iters} iterations, {rep.n_fevals} evaluations, "
+                   f"{rep.n_grads} gradients) on {n_all} host threads; the tiny workload's "
+                   f"full solve, median of {tiny_runs}, on {n_all} threads and on 1"),
     }
 
 
@@ -610,30 +646,86 @@ def random_angles(case, dev, dt, args, base: dict) -> dict:
     return out
 
 
-def adjoint_alone(case, dev, S: int) -> dict:
+def adjoint_alone(case, dev, S: int, acc32: bool = False) -> dict:
     """The back-projection on its own (in the solve it runs fused with the
     Jacobian chain), HIP events on the current stream, for the DRR+adjoint
-    figure."""
+    figure; acc32: the 32-bit-accumulator form (drr_adjoint32)."""
     import torch
 
     from paper_1102_1712_amd import binding as B
 
     es = 4 if case.dtype == "f32" else 8
     r = dev["y"].clone()
-    bp = B.drr_adjoint(case.vol, case.proj, dev["rays"], r)
+    bp = B.drr_adjoint(case.vol, case.proj, dev["rays"], r, acc32=acc32)
     torch.cuda.synchronize()
     ts = []
     for _ in range(10):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        B.drr_adjoint(case.vol, case.proj, dev["rays"], r, out=bp)
+        B.drr_adjoint(case.vol, case.proj, dev["rays"], r, out=bp, acc32=acc32)
         e1.record()
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     a = float(np.median(ts))
     return {"avg_ms": a, "launches": len(ts), "Gsamples_s": S / (a * 1e-3) / 1e9,
-            "effective_GBs": 8 * es * S / (a * 1e-3) / 1e9, "timed": "alone"}
+            "effective_GBs": 8 * es * S / (a * 1e-3) / 1e9, "timed": "alone",
+            "accumulator_bits": 32 if acc32 else 64}
+
+
+def tiny_latency(args) -> dict:
+    """The tiny workload (64^3 FP64, 128x128 detector, K = 3) solved with
+    the same options as the benchmark's solve, one call at a time: p50/p99
+    latency of solve_projection (launch- and read-back-bound at this size)."""
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+
+    case, dev, dt = build_inputs("tiny", 0)
+    ws = torch.empty(B.solve_projection_workspace(case.vol, case.proj, case.K, dt),
+                     dtype=torch.uint8, device="cuda")
+    o = B.default_opts(locate=1, c0_mm=tuple(case.tumour_c0))
+    w0 = np.zeros(case.K)
+
+    def step():
+        return B.solve_projection(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"],
+                                  dev["y"], w0, o, workspace=ws)
+
+    for _ in range(3):
+        step()
+    ts = []
+    for _ in range(max(20, args.tiny_steps)):
+        t0 = time.perf_counter()
+        w, rep = step()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return {"workload": case.name, "solves": len(ts), "p50_ms": float(np.percentile(ts, 50)),
+            "p99_ms": float(np.percentile(ts, 99)), "mean_ms": float(np.mean(ts)),
+            "iters": rep["iters"], "n_fevals": rep["n_fevals"], "n_grads": rep["n_grads"],
+            "w_rel_err_vs_planted": float(np.linalg.norm(w - case.w_star) /
+                                          np.linalg.norm(case.w_star))}
+
+
+def oracle_minimiser(case):
+    """The FP64 oracle's minimiser of this workload stored beside the tests
+    (written by a script that calls the oracle alone), or None when the
+    workload is not the stored one."""
+    path = os.path.join(ROOT, "tests", "golden", "clinical_minimiser.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    if g.get("workload") != case.name or g.get("angle") != case.proj.angle:
+        return None
+    return g["fit"]
+
+
+def measured_hbm_frac(kernel: str, workload: str, avg_ms):
+    """Measured HBM bytes per launch (profiles/, when current) over the
+    launch's duration, as a fraction of the 8 TB/s peak."""
+    t = measured_traffic(kernel, workload)
+    if t is None or not avg_ms:
+        return None
+    return t / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
 
 
 def main() -> int:
@@ -643,7 +735,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="clinical", choices=["clinical", "tiny"])
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-baseline-s", type=float, default=12.0)
+    ap.add_argument("--tiny-steps", type=int, default=50,
+                    help="solve mode: tiny-workload solves timed for its p50/p99 (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events")
@@ -831,29 +924,52 @@ def main() -> int:
               "J_rel_diff_vs_cg": float((rep_qn["J"] - rep["J"]) / rep["J"])}
         log(f"quasi-Newton: p50 {qn['p50_ms']:.3f} ms, {qn['n_fevals']} evaluations")
 
-    # how far the noise-band stop leaves w from the minimiser: against one
-    # BFGS solve with the polish step (a quasi-Newton step from the gradient,
-    # which resolves the minimiser below the noise of J)
-    w_pol, rep_pol = step(B.default_opts(**{**base, "method": 2, "polish": 1}))
-    stop = {"w_rel_diff_vs_polished": float(np.linalg.norm(w - w_pol) / np.linalg.norm(w_pol)),
-            "J_rel_diff_vs_polished": float((rep["J"] - rep_pol["J"]) / rep_pol["J"]),
-            "polished_gnorm_rel": float(rep_pol["gnorm"] / rep_pol["gnorm0"])}
-    log(f"stop resolution: {stop}")
+    # accuracy of the timed solve against the FP64 oracle's minimiser
+    gold = oracle_minimiser(case)
+    acc = {}
+    if gold is not None:
+        w_ref = np.array(gold["w"])
+        acc = {"w_rel_err_vs_oracle_minimiser": float(np.linalg.norm(w - w_ref) /
+                                                      np.linalg.norm(w_ref)),
+               "tumour_err_mm_vs_oracle": float(np.linalg.norm(np.array(rep["tumour_mm"]) -
+                                                               np.array(gold["tumour_mm"])))}
+    log(f"accuracy: {acc}")
+    # the same solve without the polish step: it stops where FP32 values of J
+    # stop resolving decreases
+    opts_np = B.default_opts(**{**base, "polish": 0})
+    step(opts_np)
+    np_t = []
+    for _ in range(max(5, args.steps // 5)):
+        t0 = time.perf_counter()
+        w_np, rep_np = step(opts_np)
+        np_t.append((time.perf_counter() - t0) * 1e3)
+    unpolished = {"steps": len(np_t), "p50_ms": float(np.percentile(np_t, 50)),
+                  "solves_s": float(1e3 / np.mean(np_t)), "n_fevals": rep_np["n_fevals"],
+                  "n_grads": rep_np["n_grads"]}
+    if gold is not None:
+        unpolished["w_rel_err_vs_oracle_minimiser"] = float(
+            np.linalg.norm(w_np - np.array(gold["w"])) / np.linalg.norm(gold["w"]))
+    log(f"unpolished: {unpolished}")
 
     # the same solve at seeded random gantry angles, each with its own
     # measured projection (same recipe: P f(w*) + 1% noise)
     rand = random_angles(case, dev, dt, args, base) if args.angles > 0 else None
     log(f"random angles: {rand}")
 
+    tiny = tiny_latency(args) if args.tiny_steps > 0 and args.workload == "clinical" else None
+    log(f"tiny: {tiny}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host cores")
-        cpu = cpu_baseline(case, rep["n_fevals"], rep["n_grads"], args.cpu_baseline_s, S)
+        cpu = cpu_baseline(case, S)
 
     drr = kernel_stats.get("drr_forward", {})
     # the back-projection alone (in the solve it runs fused with the chain)
     adj = adjoint_alone(case, dev, S)
     kernel_stats["drr_adjoint_alone"] = adj
+    if case.dtype == "f32":
+        kernel_stats["drr_adjoint32_alone"] = adjoint_alone(case, dev, S, acc32=True)
     out = {
         "metric": METRIC,
         "value": args.steps / total,
@@ -875,12 +991,19 @@ def main() -> int:
                    "step_mm": case.proj.step, "K": K, "method": args.method, "max_iter": 30,
                    "samples_per_drr": S, "angle_rad": case.proj.angle},
         "solve": {"iters": rep["iters"], "n_fevals": rep["n_fevals"], "n_grads": rep["n_grads"],
-                  "status": rep["status"], "w_rel_err_vs_planted": werr,
-                  "tumour_mm": rep["tumour_mm"], **stop},
+                  "status": rep["status"], "polish": 1, "w_rel_err_vs_planted": werr,
+                  "tumour_mm": rep["tumour_mm"], **acc},
+        "unpolished": unpolished,
+        "tiny": tiny,
         "drr_gsamples_s": drr.get("Gsamples_s"),
         "adjoint_gsamples_s": adj.get("Gsamples_s"),
-        "drr_effective_hbm_frac": (drr.get("effective_GBs", 0) / HBM_PEAK_GBS) if drr else None,
-        "adjoint_effective_hbm_frac": (adj.get("effective_GBs", 0) / HBM_PEAK_GBS) if adj else None,
+        # 8 corner values of sizeof(T) per sample at the kernel's rate: a
+        # nominal gather rate, not HBM traffic (most gathers hit LDS or L2)
+        "drr_nominal_gather_GBs": drr.get("effective_GBs"),
+        "adjoint_nominal_gather_GBs": adj.get("effective_GBs"),
+        # HBM bytes the profiler measured per launch over the launch time
+        "hbm_measured_frac": {k: measured_hbm_frac(k, wl, kernel_stats[k]["avg_ms"])
+                              for k in kernel_stats if k in KERNEL_SOURCES},
         "kernels": kernel_stats,
         "timed_region_events": [k for i, k in enumerate(B.KERNEL_CLASSES) if mask >> i & 1],
         "projected_gradient_route": alt,

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 5
+#define PCAS_ABI_VERSION 6
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -146,9 +146,9 @@ typedef struct {
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
-   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain, and
-   PCAS_K_BOUNDS the once-per-projection back-projection of the all-ones
-   image that sizes its FP32 accumulators) */
+   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain;
+   PCAS_K_BOUNDS, the all-ones back-projection, is no longer part of a solve
+   and keeps its number so that the classes after it keep theirs) */
 enum {
     PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
     PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
@@ -236,29 +236,51 @@ int drr_siddon(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, con
 
 /* ---- a6: back-projection bp = P^T r (Appendix, gradient of J) -----------
  * The exact transpose of drr_forward for the same ray table: every sample
- * of every ray adds dt * r * (its trilinear weight) to its eight voxels.
- * Accumulated per voxel brick in on-chip memory with no global atomics;
- * bit-for-bit reproducible.  r: device [nv][nu]; bp_out: device [N],
- * fully overwritten. */
+ * of every ray adds dt * r * (its trilinear weight) to its eight voxels
+ * (the same cell and fractions as drr_forward computes for it).
+ * Accumulated per 32 x 16 x 8 voxel brick in on-chip memory in 64-bit fixed
+ * point with no global atomics; bit-for-bit reproducible.  The brick's
+ * power-of-two scale comes from its largest |r| and the weight bound of
+ * pcas_backprojection_bound taken over the brick's neighbourhood, so no
+ * partial sum can overflow.  r: device [nv][nu]; bp_out: device [N], fully
+ * overwritten. */
 int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
                 const void *r, void *bp_out, void *stream);
 
+/* The same back-projection with 32-bit fixed-point accumulators (PCAS_F32
+ * only; PCAS_EINVAL otherwise): the accumulation the solver's FP32 gradient
+ * uses.  Half the on-chip bytes per add, so faster; each contribution is
+ * rounded to nearest, to about 2^-19 (clinical geometry) of the largest
+ * contribution the brick's bound allows, against the float products' own
+ * 2^-24.  Same arguments, layout and reproducibility as drr_adjoint. */
+int drr_adjoint32(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
+                  const void *r, void *bp_out, void *stream);
+
 /* Bound B on the summed trilinear weight that all rays of a projection give
- * one voxel: (P^T 1)(v) <= step * B for every voxel v.  The back-projection
- * sizes its fixed-point accumulators from it (a brick's voxel totals stay
- * below step * max|r| * B in magnitude).  Host-only, no device memory.
- * Returns a negative value for an invalid volume or projection. */
+ * one voxel: (P^T 1)(v) <= step * B for every voxel v (the pixel centres
+ * whose rays can meet a voxel's cube of index half-width 1, from the
+ * worst-case magnification over the grid box, times what one ray can give
+ * it).  Host-only, no device memory.  Returns a negative value for an
+ * invalid volume or projection. */
 double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj);
 
-/* Per-brick bounds of the back-projection of the all-ones image: the pass
- * the solver runs once per projection to size the FP32 gradient's 32-bit
- * accumulators.  The volume is cut into 32 x 16 x 8 voxel bricks (brick x
- * fastest, then y, then z); bounds_out: device float[backprojection_brick_count
- * (vol)], each at least the largest (P^T 1)(v) over the brick's voxels, with
- * P^T drr_adjoint's operator and 1 the all-ones image (rounded up; 0 where no
- * sample reaches the brick).  rays: ray_table() output for (vol, proj) in
- * dtype.  Asynchronous on `stream`.  backprojection_brick_count returns -1
- * for an invalid volume. */
+/* The same bound over one back-projection brick (see below for the brick
+ * order): (P^T 1)(v) <= step * B_brick for every voxel v of the brick and of
+ * its one-voxel halo.  This is what sizes the brick's fixed-point
+ * accumulators in drr_adjoint, drr_adjoint32 and the solver's gradient.
+ * Host-only; negative for an invalid volume, projection or brick index. */
+double pcas_backprojection_brick_bound(const pcas_vol *vol, const pcas_proj *proj,
+                                       int32_t brick);
+
+/* Per-brick maxima of the back-projection of the all-ones image, rounded up:
+ * how far below the analytic bound the real weights stay (a diagnostic; the
+ * back-projections do not need it).  The volume is cut into 32 x 16 x 8
+ * voxel bricks (brick x fastest, then y, then z); bounds_out: device
+ * float[backprojection_brick_count(vol)], each at least the largest
+ * (P^T 1)(v) over the brick's voxels, with P^T drr_adjoint's operator and 1
+ * the all-ones image (0 where no sample reaches the brick).  rays:
+ * ray_table() output for (vol, proj) in dtype.  Asynchronous on `stream`.
+ * backprojection_brick_count returns -1 for an invalid volume. */
 int32_t backprojection_brick_count(const pcas_vol *vol);
 int backprojection_brick_bounds(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
                                 const void *rays, float *bounds_out, void *stream);
@@ -326,6 +348,26 @@ int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *pro
                      const void *f0, const void *mean, const void *U, const void *y,
                      const double *w0, const pcas_opts *opts, void *workspace,
                      size_t workspace_bytes, double *w_out, pcas_report *report, void *stream);
+
+/* ---- Eq. 3: initial coefficients of the next projection ----------------
+ * Sec. II.A, Eq. 3: each coefficient is predicted separately as a linear
+ * combination of its last L optimised values, w_k0(t) = sum_{l=1..L} c_kl
+ * w*_k(t - l) (the paper uses L = 2).  Host-only, no device memory.
+ * coeffs: host double[K][L] with coeffs[k*L + l-1] = c_kl; history: host
+ * double[n_hist][K], the most recent solution last (n_hist >= L);
+ * w_out: host double[K].  PCAS_EINVAL for K outside [1, 8], L outside
+ * [1, 8] or n_hist < L; PCAS_ENONFINITE for NaN or Inf in the inputs. */
+int pcas_predict(int32_t K, int32_t L, const double *coeffs, const double *history,
+                 int32_t n_hist, double *w_out);
+/* The c_kl of Eq. 3 by least squares on a training sequence, separately for
+ * every coefficient (Sec. II.A fits them on resampled training coefficients;
+ * any sequence of solutions serves): minimises sum_{t=L}^{T-1} (w[t][k] -
+ * sum_l c_kl w[t-l][k])^2 by a QR factorisation of the lagged values.
+ * w_train: host double[T][K] (T > L); coeffs_out: host double[K][L].
+ * PCAS_ESINGULAR when a coefficient's lagged values are (numerically)
+ * linearly dependent, e.g. a constant sequence with L = 2. */
+int pcas_fit_predictor(int32_t T, int32_t K, int32_t L, const double *w_train,
+                       double *coeffs_out);
 
 /* ---- serving: many solves in flight, batched into shared launches -------
  * A server solves requests (one projection of one registered model each)

@@ -17,7 +17,9 @@ the Jacobian of Eq. A.8, the tumour-position inversion) are plain C in
   on the reduced objective min_{a,b} J (not in the paper; the workload's CG).
 * ``minimise`` -- the reference minimiser that converged solves are compared
   with: solve_cg, then Newton's method on the gradient with a Hessian from
-  central differences of the gradient.
+  central differences of the gradient, then, where the gradient cannot
+  vanish (a minimum on a kink of the trilinear interpolant), compass search
+  on the objective.
 
 All arithmetic is float64.
 """
@@ -74,6 +76,8 @@ def lib():
         L.orc_locate.restype = ctypes.c_int32
         L.orc_ray_table.argtypes = [VP, PP, P, P, P, P]
         L.orc_siddon_forward.argtypes = [VP, PP, P, P]
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
+        L.orc_set_threads.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -214,6 +218,12 @@ def ray_table(vol, proj):
                         _ptr(length), _ptr(ns), _ptr(dt))
     sh = (int(proj.nv), int(proj.nu))
     return t_in.reshape(sh), length.reshape(sh), ns.reshape(sh), dt.reshape(sh)
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the C primitives' parallel loops (results do not
+    depend on it); returns the count in force."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def total_samples(vol, proj) -> int:
@@ -475,27 +485,67 @@ def fd_hessian(prob: Problem, w, h: float = 1e-3):
     return 0.5 * (H + H.T)
 
 
+def compass_search(prob: Problem, w, phi: float, h0: float, h_min: float, max_evals: int = 4000,
+                   rtol: float = 1e-15):
+    """Direct search on phi with a fixed positive spanning set of directions
+    (Kolda, Lewis and Torczon, Optimization by direct search, SIAM Review 45
+    (2003), Secs. 2.2 and 3): the 2K coordinate directions +-e_k, then the
+    2^K diagonals (+-1, ..., +-1)/sqrt(K).  From w, try w + h d for each
+    direction in turn and move to the first point that lowers phi by more
+    than rtol |phi| (its rounding); when none does, halve h; stop once
+    h < h_min.  It compares values of phi only, so it reaches a local
+    minimiser where the gradient jumps as well (the diagonals let it follow a
+    crease that no coordinate direction descends).
+    Returns (w, phi, evaluations)."""
+    w = _f64(w).copy()
+    K = w.size
+    dirs = [sgn * e for e in np.eye(K) for sgn in (1.0, -1.0)]
+    for signs in range(1 << K):
+        dirs.append(np.array([1.0 if (signs >> k) & 1 else -1.0 for k in range(K)]) / np.sqrt(K))
+    h, n = h0, 0
+    while h >= h_min and n < max_evals:
+        moved = False
+        for dvec in dirs:
+            w_t = w + h * dvec
+            phi_t = prob.objective(w_t)[0]
+            n += 1
+            if phi_t < phi - rtol * abs(phi):
+                w, phi, moved = w_t, phi_t, True
+                break
+        if not moved:
+            h *= 0.5
+    return w, phi, n
+
+
 def minimise(prob: Problem, w0, gtol_rel: float = 1e-10, max_newton: int = 60,
-             h: float = 1e-3, cg_opts: Optional[SolveOptions] = None):
+             h: float = 1e-3, cg_opts: Optional[SolveOptions] = None,
+             h_compass: float = 1e-3, h_min: float = 1e-9):
     """The oracle's minimiser of phi(w) = min_{a,b} J near w0: the reference
     that every converged solve is compared with.
 
-    Two textbook stages, sharing nothing with the library's solvers:
+    Textbook stages, sharing nothing with the library's solvers:
       1. solve_cg from w0 (monotone in phi), which settles the basin and
          lands near its minimiser;
       2. Newton's method for grad phi = 0 from there, w <- w - H^-1 g, with
          H from fd_hessian (recomputed whenever a step shrinks ||g|| by less
-         than half), each step kept only while ||g|| decreases (near the
-         minimiser differences of phi fall below its rounding, the gradient
-         does not), until ||g|| <= gtol_rel ||g0||.
-    Trilinear interpolation makes grad phi piecewise smooth (kinks where a
-    voxel's warp position crosses a grid plane), so the difference Hessian
-    over +-h is an average curvature and the steps converge linearly; the
-    stop is on the gradient itself, whatever the rate.
+         than half), each step kept only while ||g|| decreases and phi does
+         not rise beyond its rounding (near the minimiser differences of phi
+         fall below its rounding, the gradient does not), until ||g|| <=
+         gtol_rel ||g0||;
+      3. compass_search on phi from there, steps h_compass down to h_min
+         (in units of w).
+    Trilinear interpolation makes phi piecewise smooth: its gradient jumps
+    where a voxel's warp position crosses a grid plane.  With many small
+    jumps the gradient is effectively smooth and stage 2 converges (the
+    difference Hessian over +-h is an average curvature, so linearly) and
+    stage 3 finds nothing to improve; when the minimum sits on jumps (coarse
+    voxels, small displacements) no point has a small gradient, or a point
+    with a vanishing one-sided gradient is not a minimum, and stage 3's
+    comparisons of phi go on from there.
     Returns (w, info) with info = {"gnorm0", "gnorm", "newton_steps",
-    "hessian_eigs", "J", "a", "b", "cg": the stage-1 report}.  A positive
-    definite difference Hessian at the end (info["hessian_eigs"] > 0) makes
-    the stationary point a local minimiser."""
+    "compass_evals", "hessian_eigs", "J", "a", "b", "cg": the stage-1
+    report}.  Positive eigenvalues of the difference Hessian at the end mean
+    phi curves upward around the point."""
     w0 = _f64(w0)
     w, rep = solve_cg(prob, w0, cg_opts or SolveOptions())
     _, _, _, r = prob.objective(w0)
@@ -512,15 +562,21 @@ def minimise(prob: Problem, w0, gtol_rel: float = 1e-10, max_newton: int = 60,
         phi_n, a_n, b_n, r_n = prob.objective(w_n)
         g_n = prob.gradient(w_n, r_n)
         gn_n = float(np.linalg.norm(g_n))
-        if not gn_n < gn:
+        if not (gn_n < gn and phi_n <= phi * (1.0 + 1e-13)):
             break
         w, phi, a, b, g = w_n, phi_n, a_n, b_n, g_n
         steps += 1
         if gn_n > 0.5 * gn:
             H = fd_hessian(prob, w, h)
+    n_compass = 0
+    if phi > 0.0:
+        w, phi, n_compass = compass_search(prob, w, phi, h_compass, h_min)
+        phi, a, b, r = prob.objective(w)
+        g = prob.gradient(w, r)
     eigs = np.linalg.eigvalsh(fd_hessian(prob, w, h))
     info = {"gnorm0": g0, "gnorm": float(np.linalg.norm(g)), "newton_steps": steps,
-            "hessian_eigs": eigs, "J": phi, "a": a, "b": b, "cg": rep}
+            "compass_evals": n_compass, "hessian_eigs": eigs, "J": phi, "a": a, "b": b,
+            "cg": rep}
     return w, info
 
 

@@ -24,6 +24,9 @@
 #include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t n[3];
@@ -500,4 +503,17 @@ void orc_ray_table(const orc_vol *vol, const orc_proj *pr, double *t_in, double 
         nsamp[r] = ray.nsamp;
         dt[r] = ray.dt;
     }
+}
+
+/* Thread count of the parallel loops (the CPU baseline times 1 and all cores);
+ * results do not depend on it.  Returns the count now in force. */
+int32_t orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -31,8 +31,11 @@ class _ProjectWarp(torch.autograd.Function):
         w_host = w.detach().to("cpu", torch.float64).contiguous()
         f = B.warp_pca(vol, f0, mean, U, w_host)
         p = B.drr_forward(vol, proj, rays, f)
-        ctx.vol, ctx.proj, ctx.rays = vol, proj, rays
-        ctx.f0, ctx.mean, ctx.U = f0, mean, U
+        ctx.vol, ctx.proj = vol, proj
+        # saved through autograd so that an in-place change of the ray
+        # table or the model between forward and backward raises instead of
+        # silently mixing two geometries
+        ctx.save_for_backward(rays, f0, mean, U)
         ctx.w_host = w_host
         ctx.w_device, ctx.w_dtype = w.device, w.dtype
         ctx.f = f if store_warp else None
@@ -42,9 +45,12 @@ class _ProjectWarp(torch.autograd.Function):
     def backward(ctx, grad_p):
         g = None
         if ctx.needs_input_grad[0]:
-            gp = grad_p.contiguous().to(ctx.f0.dtype)
-            bp = B.drr_adjoint(ctx.vol, ctx.proj, ctx.rays, gp)
-            g2 = B.grad_w(ctx.vol, ctx.f0, ctx.mean, ctx.U, ctx.w_host, bp)
+            rays, f0, mean, U = ctx.saved_tensors
+            gp = grad_p.contiguous().to(f0.dtype)
+            bp = B.drr_adjoint(ctx.vol, ctx.proj, rays, gp)
+            g2 = B.grad_w(ctx.vol, f0, mean, U, ctx.w_host, bp)
+            # grad_w returns 2 U^T (df/dx) bp (dJ/dw of Eq. 2, where
+            # dJ/dp = 2 r); halving it is exact in binary floating point
             g = (0.5 * g2).to(device=ctx.w_device, dtype=ctx.w_dtype)
         return g, None, None, None, None, None, None, None
 
@@ -66,8 +72,10 @@ class PCAProjector(torch.nn.Module):
         self.rays = B.ray_table(vol, proj, f0.dtype)
 
     def set_projection(self, proj):
+        """Switch to another geometry.  A fresh ray table is built, so graphs
+        recorded at the previous angle keep theirs for their backward."""
         self.proj = proj
-        self.rays = B.ray_table(self.vol, proj, self.f0.dtype, out=self.rays)
+        self.rays = B.ray_table(self.vol, proj, self.f0.dtype)
 
     def forward(self, w):
         return project(w, self.vol, self.proj, self.rays, self.f0, self.mean, self.U,

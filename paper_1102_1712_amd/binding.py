@@ -23,7 +23,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "invalid geometry", -3: "singular
 STOP = {0: "converged", 1: "max_iter", 2: "line_search"}
 EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_default_opts",
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
-           "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "pcas_backprojection_bound",
+           "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "drr_adjoint32",
+           "pcas_backprojection_bound", "pcas_backprojection_brick_bound",
            "backprojection_brick_count", "backprojection_brick_bounds",
            "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
@@ -31,7 +32,7 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "pcas_server_reserved_bytes", "pcas_server_create", "pcas_server_destroy",
            "pcas_server_add_model", "pcas_server_request_bytes", "pcas_server_submit",
            "pcas_server_step", "pcas_server_set_substep_share", "pcas_server_poll",
-           "pcas_server_stats")
+           "pcas_server_stats", "pcas_predict", "pcas_fit_predictor")
 
 
 class PcasError(RuntimeError):
@@ -122,8 +123,10 @@ def lib():
             "warp_pca": (I32, [I32, VP, I32, P, P, P, DP, P, P]),
             "drr_forward": (I32, [I32, VP, PP, P, P, P, P]),
             "drr_adjoint": (I32, [I32, VP, PP, P, P, P, P]),
+            "drr_adjoint32": (I32, [I32, VP, PP, P, P, P, P]),
             "drr_siddon": (I32, [I32, VP, PP, P, P, P]),
             "pcas_backprojection_bound": (D, [VP, PP]),
+            "pcas_backprojection_brick_bound": (D, [VP, PP, I32]),
             "backprojection_brick_count": (I32, [VP]),
             "backprojection_brick_bounds": (I32, [I32, VP, PP, P, P, P]),
             "residual_fit_workspace_bytes": (SZ, [I64]),
@@ -145,6 +148,8 @@ def lib():
             "pcas_server_poll": (I32, [P, I64, DP, ctypes.POINTER(Report), ctypes.POINTER(I32)]),
             "pcas_server_stats": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                         ctypes.POINTER(SZ)]),
+            "pcas_predict": (I32, [I32, I32, DP, DP, I32, DP]),
+            "pcas_fit_predictor": (I32, [I32, I32, I32, DP, DP]),
             "solve_projection_workspace": (SZ, [I32, VP, PP, I32]),
             "solve_projection": (I32, [I32, VP, PP, I32, P, P, P, P, DP, ctypes.POINTER(Opts), P,
                                        SZ, DP, ctypes.POINTER(Report), P]),
@@ -320,14 +325,43 @@ def drr_siddon(vol, proj, f, out=None, stream=None):
     return out
 
 
-def drr_adjoint(vol, proj, rays, r, out=None, stream=None):
-    """a6: bp = P^T r, shape [n3][n2][n1]."""
+def drr_adjoint(vol, proj, rays, r, out=None, stream=None, acc32=False):
+    """a6: bp = P^T r, shape [n3][n2][n1].  acc32 (float32 only): the
+    32-bit-accumulator form (drr_adjoint32)."""
     torch = _torch()
     if out is None:
         out = torch.empty(_vshape(vol), dtype=r.dtype, device=r.device)
-    _check(lib().drr_adjoint(_dtype_code(r), ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)),
-                             _dev(rays, "rays"), _dev(r, "r"), _dev(out, "bp", r.dtype),
-                             _stream(stream)), "drr_adjoint")
+    name = "drr_adjoint32" if acc32 else "drr_adjoint"
+    _check(getattr(lib(), name)(_dtype_code(r), ctypes.byref(c_vol(vol)),
+                                ctypes.byref(c_proj(proj)), _dev(rays, "rays"), _dev(r, "r"),
+                                _dev(out, "bp", r.dtype), _stream(stream)), name)
+    return out
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def predict(history, coeffs) -> np.ndarray:
+    """Eq. 3 (pcas_predict): history [L', K], most recent last; coeffs [K, L]
+    with coeffs[k, l-1] = c_kl.  Host-only."""
+    h = np.ascontiguousarray(history, dtype=np.float64)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    K, L = c.shape
+    if h.ndim != 2 or h.shape[1] != K:
+        raise ValueError("history must be [n, K]")
+    out = np.empty(K)
+    _check(lib().pcas_predict(K, L, _dp(c), _dp(h), h.shape[0], _dp(out)), "pcas_predict")
+    return out
+
+
+def fit_predictor(w_train, L: int = 2) -> np.ndarray:
+    """Least-squares c_kl of Eq. 3 on w_train [T, K] (pcas_fit_predictor);
+    returns [K, L].  Host-only."""
+    w = np.ascontiguousarray(w_train, dtype=np.float64)
+    T, K = w.shape
+    out = np.empty((K, int(L)))
+    _check(lib().pcas_fit_predictor(T, K, int(L), _dp(w), _dp(out)), "pcas_fit_predictor")
     return out
 
 
@@ -336,6 +370,16 @@ def backprojection_bound(vol, proj) -> float:
     b = lib().pcas_backprojection_bound(ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)))
     if b < 0:
         raise PcasError(-1, "backprojection_bound: invalid volume or projection")
+    return b
+
+
+def backprojection_brick_bound(vol, proj, brick: int) -> float:
+    """B_brick with (P^T 1)(v) <= step * B_brick over the brick and its halo
+    (host-only query)."""
+    b = lib().pcas_backprojection_brick_bound(ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)),
+                                              int(brick))
+    if b < 0:
+        raise PcasError(-1, "backprojection_brick_bound: invalid volume, projection or brick")
     return b
 
 

@@ -144,22 +144,40 @@ int drr_siddon(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, con
     return PCAS_OK;
 }
 
-int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
-                const void *r, void *bp_out, void *stream) {
+static int adjoint_call(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
+                        const void *rays, const void *r, void *bp_out, bool acc32, void *stream) {
     if (!dtype_ok(dtype)) return PCAS_EINVAL;
+    if (acc32 && dtype != PCAS_F32) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
     if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!rays || !aligned(rays, 16) || !r || !bp_out) return PCAS_EINVAL;
     HIPCHK(launch_drr_adjoint(dtype, make_dims(vol), make_frame(proj), rays, r, nullptr, 0.0, 0.0,
-                              bp_out, (hipStream_t)stream));
+                              bp_out, acc32, (hipStream_t)stream));
     return PCAS_OK;
+}
+
+int drr_adjoint(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
+                const void *r, void *bp_out, void *stream) {
+    return adjoint_call(dtype, vol, proj, rays, r, bp_out, false, stream);
+}
+
+int drr_adjoint32(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, const void *rays,
+                  const void *r, void *bp_out, void *stream) {
+    return adjoint_call(dtype, vol, proj, rays, r, bp_out, true, stream);
 }
 
 double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj) {
     if (check_vol(vol) || check_proj(proj, vol)) return -1.0;
     return backprojection_weight_bound(make_dims(vol), make_frame(proj));
+}
+
+double pcas_backprojection_brick_bound(const pcas_vol *vol, const pcas_proj *proj, int32_t brick) {
+    if (check_vol(vol) || check_proj(proj, vol)) return -1.0;
+    const VolDims v = make_dims(vol);
+    if (brick < 0 || brick >= drr_adjoint_blocks(v)) return -1.0;
+    return brick_weight_bound_host(v, make_frame(proj), brick);
 }
 
 int32_t backprojection_brick_count(const pcas_vol *vol) {
@@ -309,37 +327,6 @@ struct Profile {
     }
 };
 
-// A second stream (default priority) per thread and device, with two
-// events, on which a solve runs its geometry-only bound pass while its first
-// evaluation runs on the caller's stream.
-struct AuxStream {
-    hipStream_t s = nullptr;
-    hipEvent_t ready = nullptr, done = nullptr;
-    int device = -1;
-};
-
-inline AuxStream *aux_stream() {
-    thread_local AuxStream a;
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    if (a.s && a.device == dev) return &a;
-    if (a.s) {   // another device: this thread's streams follow the current one
-        (void)hipStreamDestroy(a.s);
-        (void)hipEventDestroy(a.ready);
-        (void)hipEventDestroy(a.done);
-        a = AuxStream{};
-    }
-    if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&a.ready, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&a.done, hipEventDisableTiming) != hipSuccess) {
-        (void)hipStreamDestroy(a.s);
-        a = AuxStream{};
-        return nullptr;
-    }
-    a.device = dev;
-    return &a;
-}
-
 struct Solver {
     pcas_dtype dt;
     VolDims vd;
@@ -361,23 +348,12 @@ struct Solver {
     int mom_slot = -1;
     double mom_a0 = 0.0, mom_b0 = 0.0;
     Profile prof;
-    // The bound pass runs on aux->s until the first gradient (or the end of
-    // the call) makes the solve's stream wait for it.
-    AuxStream *aux = nullptr;
-    bool bounds_pending = false;
-
-    ~Solver() { (void)join_bounds(); }
-    hipError_t join_bounds() {
-        if (!bounds_pending) return hipSuccess;
-        bounds_pending = false;
-        return hipStreamWaitEvent(s, aux->done, 0);
-    }
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
 
-    template <class F> hipError_t timed(int cls, F &&launch) { return timed_on(s, cls, launch); }
-    template <class F> hipError_t timed_on(hipStream_t st, int cls, F &&launch) {
+    template <class F> hipError_t timed(int cls, F &&launch) {
+        const hipStream_t st = s;
         if (!(prof.mask >> cls & 1u)) return launch();
         hipEvent_t a, b;
         hipError_t e;
@@ -419,13 +395,11 @@ struct Solver {
         return fa;
     }
 
-    // J = ||p - a y - b||^2 for the projection in the p buffer, summed
-    // directly over the residual; (a, b) refitted by Eq. A.1 unless fixed.
-    // Per-brick (P^T 1) maxima for the FP32 back-projection's accumulators.
-    float *bounds() const { return (float *)(ws + L.bounds); }
     // Projection buffer of a line-search slot (0 or 1).
     char *proj_slot(int slot) const { return ws + (slot ? L.p2 : L.p); }
 
+    // J = ||p - a y - b||^2 for the projection in the slot, summed directly
+    // over the residual; (a, b) refitted by Eq. A.1 unless fixed.
     int residual(const double *ab_fixed, int slot, double *J, double *a, double *b) {
         FitArgs fa = fit_args(ab_fixed);
         if (fa.mode == FIT_REFIT) {   // the refit reads the moments of this slot's projection
@@ -505,12 +479,11 @@ struct Solver {
                                               nullptr, scal() + 8, s);
             }));
         } else {
-            HIPCHK(join_bounds());
             // back-projection and Jacobian chain in one pass (bp stays on chip)
             HIPCHK(timed(PCAS_K_ADJOINT, [&] {
                 return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, proj_slot(slot), y, a, b, f0,
                                                 mean, U, w, (double *)(ws + L.partials), nullptr,
-                                                scal() + 8, dt == PCAS_F32 ? bounds() : nullptr, s);
+                                                scal() + 8, s);
             }));
         }
         ++n_grads;
@@ -551,26 +524,6 @@ struct Solver {
             return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],
                                     scal() + 16, s);
         }));
-        if (dt == PCAS_F32 && grad_mode == 1) {
-            // geometry only: overlapped with the y sums' read-back and the
-            // first evaluation on a second stream where one is available;
-            // launched after the y sums so that their small grid is not queued
-            // behind this one on the GPU
-            aux = aux_stream();
-            hipStream_t bs = s;
-            if (aux) {
-                HIPCHK(hipEventRecord(aux->ready, s));
-                HIPCHK(hipStreamWaitEvent(aux->s, aux->ready, 0));
-                bs = aux->s;
-            }
-            HIPCHK(timed_on(bs, PCAS_K_BOUNDS, [&] {
-                return launch_backprojection_bounds(dt, vd, fr, ws + L.rays, bounds(), bs);
-            }));
-            if (aux) {
-                HIPCHK(hipEventRecord(aux->done, aux->s));
-                bounds_pending = true;
-            }
-        }
         double ys[5];
         int st = sync_read(ys, scal() + 16, 5);
         if (st) return st;

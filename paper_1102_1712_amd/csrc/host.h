@@ -199,7 +199,7 @@ inline int readback_sum(double *host, const double *partials, int nblocks, int t
 // ---- workspace layouts ---------------------------------------------------
 
 struct SolveWs {
-    size_t rays, f, p, p2, vol2, bounds, partials, counters, scalars, total;   // vol2: bp, or the J_k
+    size_t rays, f, p, p2, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
 };
 
 inline int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
@@ -223,7 +223,6 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
     L.p = off; off += align256(M * es);
     L.p2 = off; off += align256(M * es);   // second projection slot of the line search
     L.vol2 = off; off += with_vol2 ? align256((size_t)(K > 1 ? K : 1) * N * es) : 0;
-    L.bounds = off; off += align256((size_t)drr_adjoint_blocks(make_dims(v)) * sizeof(float));
     L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
     L.counters = off; off += 256;
     L.scalars = off; off += align256(64 * sizeof(double));

@@ -175,8 +175,7 @@ struct AdjJob {                 // back-projection of the residual + Jacobian ch
     VolDims vd;
     Frame fr;
     int nbx, nby;
-    double hb, vb;   // one ray's, and all rays', summed weight bound for one voxel
-    const float *bounds;   // FP32: per-brick (P^T 1) maxima (launch_backprojection_bounds)
+    double hb;   // one ray's summed weight bound for one voxel
     const void *rays, *p, *y;
     double a, b;
     const void *f0, *mean, *U;
@@ -241,19 +240,22 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
                                   hipStream_t s);
 
 // Back-projection.  If y != nullptr the residual r = p - a*y - b is formed
-// on the fly from p (passed as r_or_p); otherwise r_or_p is r.
+// on the fly from p (passed as r_or_p); otherwise r_or_p is r.  acc32
+// (FP32 only): 32-bit fixed-point accumulators, else 64-bit.
 hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *rays,
                               const void *r_or_p, const void *y, double a, double b, void *bp,
-                              hipStream_t s);
+                              bool acc32, hipStream_t s);
 // Back-projection of the residual r = p - a y - b fused with the Jacobian
 // chain: g_out[k] = 2 sum_v (P^T r)(v) sum_c U_kc df/dx_c (bp stays on
 // chip); partials needs drr_adjoint_blocks() * RED_SLOTS doubles, counter
-// one zeroed uint32 (left zeroed on exit).  FP32 needs bounds, the output of
-// launch_backprojection_bounds for the same geometry (hipErrorInvalidValue
-// without it).
+// one zeroed uint32 (left zeroed on exit).  FP32 accumulates in 32-bit
+// fixed point, FP64 in 64-bit.
 int drr_adjoint_blocks(const VolDims &v);
-// Bound on sum over rays and samples of the trilinear weight one voxel gets.
+// Bound on sum over rays and samples of the trilinear weight one voxel gets:
+// over the whole grid, and over the voxels of one back-projection brick and
+// its one-voxel halo.
 double backprojection_weight_bound(const VolDims &v, const Frame &fr);
+double brick_weight_bound_host(const VolDims &v, const Frame &fr, int brick);
 // bound_out[brick] (drr_adjoint_blocks() floats) >= the largest (P^T 1)(v)
 // over the brick's voxels: the back-projection of the all-ones image, a
 // function of the ray table alone, rounded up.
@@ -263,7 +265,7 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,
                                     const double *w, double *partials, uint32_t *counter,
-                                    double *g_out, const float *bounds, hipStream_t s);
+                                    double *g_out, hipStream_t s);
 
 // J[k][v] = sum_c U_kc(v) df/dx_c(v) at w (Eq. A.8 chain per voxel).
 hipError_t launch_jacobian(pcas_dtype dt, const VolDims &v, int K, const void *f0,
@@ -319,7 +321,7 @@ hipError_t launch_residual_batch(pcas_dtype dt, const ResJob *jobs, int njobs, i
 AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,
                     const void *y, double a, double b, const void *f0, const void *mean,
                     const void *U, const double *w, double *partials, uint32_t *counter,
-                    double *g_out, const float *bounds);
+                    double *g_out);
 hipError_t launch_drr_adjoint_chain_batch(pcas_dtype dt, int K, const AdjJob *jobs, int njobs,
                                           int total_blocks, hipStream_t s);
 // dst[i * count + t] = src[i][t] for i < n (src: device array of pointers).

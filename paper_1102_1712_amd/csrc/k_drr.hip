@@ -586,6 +586,119 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
 }
 
 // ---------------------------------------------------------------------------
+// Bounds on the trilinear weights one voxel receives (they size the
+// back-projection's fixed-point accumulators).
+
+// A ray with n >= 2 samples has dt >= step / 2, and its largest per-sample
+// index step is >= dt / (sqrt(3) max spacing); the tent weights one ray
+// gives a voxel then sum to at most 1/h + 1.  (A ray with one sample gives
+// at most 1.)
+__host__ __device__ inline double ray_weight_bound(const VolDims &v, const Frame &fr) {
+    const double smax = fmax(v.spacing[0], fmax(v.spacing[1], v.spacing[2]));
+    return 2.0 * sqrt(3.0) * smax / fr.step + 2.0;
+}
+
+// Bound on the summed trilinear weight all rays give one voxel whose support
+// cube (index half-width 1) lies in the index box [b0, b1] (and, as every
+// sample does, in the grid box): (P^T 1)(v) <= step * bound.
+//
+// One ray: its samples advance by h_a = dt |dir_a| / s_a per sample along
+// index axis a, and a tent of half-width 1 sampled at spacing h sums to at
+// most 1/h + 1 (a Riemann sum of its unit integral, off by at most h times
+// its peak), so the ray gives the voxel at most dt (1/h_a + 1) =
+// s_a / |dir_a| + dt <= s_a / |dir_a| + step.  Over the rays through the box
+// |dir_a| >= min|rel_a| / max|rel| (rel = point - source) on any axis where
+// rel_a keeps one sign; some axis always has |dir_a| >= 1/sqrt(3), which
+// gives sqrt(3) max s + step for any ray.
+//
+// The rays: detector coordinates u = SID (rel.eu) / D with depth D = rel.en.
+// Over the voxel's cube rel.eu varies by at most W_u = sum_c 2 s_c |eu_c|
+// and D by at most W_n = sum_c 2 s_c |en_c|, so u varies by at most
+// (SID / D_min)(W_u + A_u W_n / D_min), A_u the largest |rel.eu| over the
+// box (D_min and A_u sit at box corners: both are linear in the point); an
+// interval of that length holds at most floor(length / pitch_u) + 1 pixel
+// centres, and likewise along v.
+//
+// *adds (if not null) bounds the samples that reach the voxel: per ray at
+// most floor(diam / (step / 2)) + 1 lie in the cube (a ray of two or more
+// samples has dt >= step / 2; diam = 2 sqrt(sum s_c^2)).  Infinite when the
+// box reaches the source's plane.
+__host__ __device__ inline double region_weight_bound(const VolDims &v, const Frame &fr,
+                                                      const int (&b0)[3], const int (&b1)[3],
+                                                      double *adds) {
+    double dmin = INFINITY, au = 0.0, av = 0.0, rmax = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int corner = 0; corner < 8; ++corner) {
+        double rel[3], depth = 0.0, pu = 0.0, pv = 0.0, r2 = 0.0;
+        for (int c = 0; c < 3; ++c)
+            rel[c] = v.origin[c] + (((corner >> c) & 1) ? b1[c] : b0[c]) * v.spacing[c] - fr.src[c];
+        for (int c = 0; c < 3; ++c) {
+            depth += rel[c] * fr.en[c];
+            pu += rel[c] * fr.eu[c];
+            pv += rel[c] * fr.ev[c];
+            r2 += rel[c] * rel[c];
+            lo[c] = fmin(lo[c], rel[c]);
+            hi[c] = fmax(hi[c], rel[c]);
+        }
+        dmin = fmin(dmin, depth);
+        au = fmax(au, fabs(pu));
+        av = fmax(av, fabs(pv));
+        rmax = fmax(rmax, sqrt(r2));
+    }
+    if (!(dmin > 0.0)) {
+        if (adds) *adds = INFINITY;
+        return INFINITY;
+    }
+    const double smax = fmax(v.spacing[0], fmax(v.spacing[1], v.spacing[2]));
+    double ray = sqrt(3.0) * smax + fr.step;
+    for (int a = 0; a < 3; ++a) {
+        const double m = lo[a] > 0.0 ? lo[a] : (hi[a] < 0.0 ? -hi[a] : 0.0);
+        if (m > 0.0) ray = fmin(ray, v.spacing[a] * rmax / m + fr.step);
+    }
+    double wu = 0.0, wv = 0.0, wn = 0.0, diam = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        wu += 2.0 * v.spacing[c] * fabs(fr.eu[c]);
+        wv += 2.0 * v.spacing[c] * fabs(fr.ev[c]);
+        wn += 2.0 * v.spacing[c] * fabs(fr.en[c]);
+        diam += v.spacing[c] * v.spacing[c];
+    }
+    diam = 2.0 * sqrt(diam);
+    const double lu = fr.sid / dmin * (wu + au * wn / dmin), lv = fr.sid / dmin * (wv + av * wn / dmin);
+    const double nu = fmin(floor(lu / fr.pitch_u) + 1.0, (double)fr.nu);
+    const double nv = fmin(floor(lv / fr.pitch_v) + 1.0, (double)fr.nv);
+    if (adds) *adds = nu * nv * (floor(2.0 * diam / fr.step) + 1.0);
+    return ray / fr.step * nu * nv;
+}
+
+// The bound over one back-projection brick: every voxel of its halo box
+// [lo - 1, hi + 1], whose support cubes lie in [lo - 2, hi + 2] (clipped).
+__host__ __device__ inline double brick_weight_bound(const VolDims &v, const Frame &fr, int brick,
+                                                     double *adds) {
+    const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X, nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
+    const int bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
+    const int lo[3] = {bx * BRICK_X, by * BRICK_Y, bz * BRICK_Z};
+    const int n[3] = {v.n0, v.n1, v.n2};
+    const int ext[3] = {BRICK_X, BRICK_Y, BRICK_Z};
+    int r0[3], r1[3];
+    for (int c = 0; c < 3; ++c) {
+        const int h = (lo[c] + ext[c] < n[c] ? lo[c] + ext[c] : n[c]) - 1;
+        r0[c] = lo[c] - 2 > 0 ? lo[c] - 2 : 0;
+        r1[c] = h + 2 < n[c] - 1 ? h + 2 : n[c] - 1;
+    }
+    return region_weight_bound(v, fr, r0, r1, adds);
+}
+
+double brick_weight_bound_host(const VolDims &v, const Frame &fr, int brick) {
+    return brick_weight_bound(v, fr, brick, nullptr);
+}
+
+// The same over the whole grid: (P^T 1)(v) <= step * bound for every voxel.
+double backprojection_weight_bound(const VolDims &v, const Frame &fr) {
+    const int b0[3] = {0, 0, 0}, b1[3] = {v.n0 - 1, v.n1 - 1, v.n2 - 1};
+    return region_weight_bound(v, fr, b0, b1, nullptr);
+}
+
+// ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
@@ -691,41 +804,75 @@ __device__ __forceinline__ T residual_at(const T *__restrict__ rp, const T *__re
         return rp ? rp[pix] : (T)1;   // no residual: the all-ones image
 }
 
+// Whether sample s of a ray has its cell (lower corner) in the halo box
+// [lom, lom + ext) -- the same sample_cell arithmetic as the sample loop.
+template <typename T>
+__device__ __forceinline__ bool sample_in_box(const T (&e)[3], const T (&d)[3], int s,
+                                              const GridTop<T> &top, const int (&lom)[3],
+                                              const int (&ext)[3]) {
+    int l[3];
+    T z[3];
+    sample_cell(e, d, (T)s + (T)0.5, top, l, z);
+    return (unsigned)(l[0] - lom[0]) < (unsigned)ext[0] &&
+           (unsigned)(l[1] - lom[1]) < (unsigned)ext[1] &&
+           (unsigned)(l[2] - lom[2]) < (unsigned)ext[2];
+}
+
+// Slot of global cell l in a brick's halo array whose origin cell sits at
+// word `base` of the global layout: l2 ZP + l1 YP + l0 - base.  Two
+// v_mad_u32_u24 (full rate; cell indices are below 2^24), written out
+// because the compiler otherwise folds `base` into the products and falls
+// back to quarter-rate 32-bit multiplies.
+__device__ __forceinline__ unsigned halo_slot(const int (&l)[3], unsigned base) {
+    unsigned t, u;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(t) : "v"(l[1]), "s"(ACC_YP), "v"((unsigned)l[0] - base));
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(u) : "v"(l[2]), "s"(ACC_ZP), "v"(t));
+    return u;
+}
+
+// Accumulator modes of drr_adjoint_block.
+enum {
+    ADJ_ACC64 = 0,        // 64-bit fixed point (drr_adjoint; FP64 gradients)
+    ADJ_ACC32 = 1,        // FP32: 32-bit fixed point (drr_adjoint32 and the fused gradient)
+    ADJ_BOUND_PASS = 2    // all-ones image, per-brick maxima out (32 bits for FP32 rays)
+};
+
 // hb bounds the summed weight one ray can give one voxel (samples within the
-// voxel's cube of index half-width 1, each of weight at most 1); vb bounds
-// the summed weight of all rays (backprojection_weight_bound).  A brick's
-// voxel totals are at most step * max|r| * min(hb * footprint pixels, vb).
+// voxel's cube of index half-width 1, each of weight at most 1).
 //
-// Work distribution: the rays of the brick's detector footprint with a
-// non-empty sample range near the brick go into a per-wave ring queue
-// (geometry, range and scaled dt * r); every lane takes a ray, walks ADJ_RUN
-// samples, and lanes whose ray is done take the next queued one, so lanes
-// stay busy whatever the spread of ray lengths.  Each sample whose cell
-// touches the brick adds its eight corner weights to the LDS accumulator in
-// fixed point (per-brick power-of-two scale from the largest |r| of the
-// footprint).  Integer addition is associative, so the brick's sums do not
-// depend on which lane adds when.
+// Work distribution: the rays of the brick's detector footprint with
+// samples in the brick's halo box go into a per-wave ring queue (geometry,
+// exact sample range and scaled dt * r); every lane takes a ray, walks
+// ADJ_RUN samples, and lanes whose ray is done take the next queued one, so
+// lanes stay busy whatever the spread of ray lengths.  A ray's range is
+// first estimated from the box in continuous coordinates, then trimmed at
+// both ends by re-creating the end samples' cells: along a ray every cell
+// coordinate is monotone in the sample index, so the samples whose cell lies
+// in the box form one interval, and the trimmed range is exactly that
+// interval.  The sample loop therefore adds every sample it visits, with no
+// per-sample test.  Each sample adds its eight corner weights to the LDS
+// accumulator in fixed point (per-brick power-of-two scale).  Integer
+// addition is associative, so the brick's sums do not depend on which lane
+// adds when.
 //
-// K = 0: bp is written, or with bound_out (and no residual, r = 1) the
-// largest voxel value of the brick, (P^T 1)(v) = sum of dt * weight, goes to
-// bound_out[brick].  K > 0 (the solver's gradient): bp never leaves the
-// chip; each brick voxel's value is chained at once through the warp
-// Jacobian (Eq. A.8 and the modes, as grad_w does) and the block sums of
-// bp * sum_c U_kc df/dx_c go through the fixed-order grid reduction into
-// g_out[k] (times 2).
+// Scale: every contribution is |dt r w| <= step * rmax = C (rmax the largest
+// |r| of the footprint), and every voxel total of the brick, halo slots
+// included, is at most C min(hb * footprint pixels, vb) with vb the
+// brick's weight bound (brick_weight_bound).  ADJ_ACC64: contributions <= FixedRange, totals
+// < 2^62.  ADJ_ACC32 and the bound pass: contributions are rounded to
+// nearest (errors grow with the square root of the add count instead of
+// its count), and totals plus half a unit per add (at most `adds` of them)
+// stay below 2^31.
 //
-// Accumulator: 64-bit fixed point, except for the FP32 gradient (K > 0),
-// which adds 32-bit fixed point (half the LDS traffic and bank conflicts).
-// Its scale comes from bounds[]: every voxel total of a brick, halo slots
-// included, is at most max|r| times the largest (P^T 1) of the brick and its
-// 26 neighbours, and S keeps that below 2^31.  The FP32 bound pass (B32,
-// K = 0) accumulates in 32 bits too, scaled by the analytic bound on any
-// voxel total that the 64-bit path uses (50-140 times the measured maxima),
-// and counts its samples for the rounding slack of its maxima.
-template <typename T, bool FORM_R, int K, bool B32 = false>
+// K = 0: bp is written, or in the bound pass (all-ones image) the largest
+// voxel value of the brick goes to bound_out[brick].  K > 0 (the solver's
+// gradient): bp never leaves the chip; each brick voxel's value is chained
+// at once through the warp Jacobian (Eq. A.8 and the modes, as grad_w does)
+// and the block sums of bp * sum_c U_kc df/dx_c go through the fixed-order
+// grid reduction into g_out[k] (times 2).
+template <typename T, bool FORM_R, int K, int ACCM>
 __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame &fr, int nbx,
-                                                  int nby, double hb, double vb,
-                                                  const float *__restrict__ bounds,
+                                                  int nby, double hb,
                                                   float *__restrict__ bound_out,
                                                   const RayRec<T> *__restrict__ rays,
                                                   const T *__restrict__ rp,
@@ -736,8 +883,9 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                                                   double *__restrict__ partials,
                                                   uint32_t *counter, double *__restrict__ g_out,
                                                   int lb, int nb) {
-    constexpr bool ACC32 = std::is_same<T, float>::value && (K > 0 || B32);
-    constexpr bool COUNT = ACC32 && K == 0;   // the bound pass counts its samples
+    constexpr bool ACC32 = std::is_same<T, float>::value && ACCM != ADJ_ACC64;
+    constexpr bool COUNT = ACCM == ADJ_BOUND_PASS;   // the bound pass counts its samples
+    static_assert(!(K > 0 && COUNT), "the bound pass has no chain");
     using AccT = typename std::conditional<ACC32, unsigned int, unsigned long long>::type;
     __shared__ AccT acc[ACC_WORDS];
     __shared__ T q_f[ADJ_WAVES][7][QCAP];       // e[3], d[3], scaled dt * r
@@ -786,11 +934,9 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const int W = iu1 - iu0 + 1, H = iv1 - iv0 + 1;
     const int npix = (W > 0 && H > 0) ? W * H : 0;
 
-    // Per-brick fixed-point scale S from the largest |r| in the footprint:
-    // every contribution is |dt r w| <= step * rmax = C, a voxel total is
-    // <= C min(hb * npix, vb).  S keeps the former within FixedRange (so
-    // fixed_of's conversion is in range) and the latter below 2^62 (no 64-bit
-    // overflow), and is a power of two, so scaling dt * r by it is exact.
+    // Per-brick fixed-point scale S (a power of two, so scaling dt * r by it
+    // is exact) from the largest |r| in the footprint and the brick's weight
+    // bound.
     double rmax = 0.0;
     for (int t = tid; t < npix; t += ADJ_THREADS) {
         const int pix = (iv0 + t / W) * fr.nu + (iu0 + t % W);
@@ -800,38 +946,23 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     if (lane == 0) red[wave] = rmax;
     __syncthreads();
     for (int q = 0; q < ADJ_WAVES; ++q) rmax = fmax(rmax, red[q]);
-    const double C = fr.step * rmax * (1.0 + 1e-6);
+    const double C = fr.step * rmax * (1.0 + 1e-6);   // 1e-6: the products' rounding in T
+    double adds;
+    const double vb = brick_weight_bound(vd, fr, bid, &adds);
+    const double bw = fmin(hb * (double)npix, vb);
     double Sd = 0.0;
-    if constexpr (COUNT) {
-        // all-ones image: totals <= C min(hb npix, vb), as bounded for 64 bits
-        if (C > 0.0) {
-            const double lim = 2147483648.0 * (1.0 - 1.0 / 4096.0) / (C * fmin(hb * (double)npix, vb));
-            int ex;
-            frexp(fmin(lim, 1e300), &ex);
-            Sd = ldexp(0.5, ex);
+    if (C > 0.0 && bw < INFINITY) {
+        double lim;
+        if constexpr (ACC32) {
+            // totals <= C bw; at most `adds` adds per voxel, each off by <= 1/2
+            // unit (the floor assumes fewer than 2^31 samples reach one voxel)
+            lim = fmax(2147483647.0 - 0.5 * adds - 1.0, 1073741824.0) / (C * bw);
+        } else {
+            lim = fmin(FixedRange<T>::per_add / C, 4611686018427387904.0 / (C * bw));   // 2^62
         }
-    } else if constexpr (ACC32) {
-        // largest (P^T 1) over the brick and its neighbours (halo slots hold
-        // parts of the neighbours' voxel totals)
-        double bmax = 0.0;
-        for (int nz = max(bz - 1, 0); nz <= min(bz + 1, (n2 + BRICK_Z - 1) / BRICK_Z - 1); ++nz)
-            for (int ny = max(by - 1, 0); ny <= min(by + 1, nby - 1); ++ny)
-                for (int nx = max(bx - 1, 0); nx <= min(bx + 1, nbx - 1); ++nx)
-                    bmax = fmax(bmax, (double)bounds[(nz * nby + ny) * nbx + nx]);
-        // totals <= rmax * bmax; 1e-5 covers the float products' rounding,
-        // 2^-12 of the range the truncations (a few thousand adds per voxel)
-        const double lim = 2147483648.0 * (1.0 - 1.0 / 4096.0) / (rmax * bmax * (1.0 + 1e-5));
-        if (rmax > 0.0 && bmax > 0.0) {
-            int ex;
-            frexp(fmin(lim, 1e300), &ex);
-            Sd = ldexp(0.5, ex);
-        }
-    } else if (C > 0.0) {
-        const double lim_add = FixedRange<T>::per_add / C;
-        const double lim_vox = 4611686018427387904.0 / (C * fmin(hb * (double)npix, vb));   // 2^62
         int ex;
-        frexp(fmin(fmin(lim_add, lim_vox), 1e300), &ex);
-        Sd = ldexp(0.5, ex);   // the largest power of two not above the limits
+        frexp(fmin(lim, 1e300), &ex);
+        Sd = ldexp(0.5, ex);   // the largest power of two not above the limit
     }
 
     const GridTop<T> top = grid_top<T>(n0, n1, n2);
@@ -839,9 +970,13 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const T hib[3] = {(T)(hi[0] + 1), (T)(hi[1] + 1), (T)(hi[2] + 1)};
     const int ext[3] = {hi[0] - lo[0] + 2, hi[1] - lo[1] + 2, hi[2] - lo[2] + 2};
     const int lom[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};   // halo origin
+    // Word offset of the global cell (0, 0, 0) in the halo array, so that a
+    // cell's slot is l2 ZP + l1 YP + l0 - base (unsigned arithmetic; every
+    // visited cell lies in the box).
+    const unsigned base = (unsigned)(lom[2] * ACC_ZP + lom[1] * ACC_YP + lom[0]);
     // Candidate tiles interleave the footprint: lane (lu, lv) of tile (bu,
     // bv) takes pixel (iu0 + lu*Su + bu, iv0 + lv*Sv + bv), so the rays of one
-    // tile sit Su x Sv pixels apart; tiles go round-robin to the four waves.
+    // tile sit Su x Sv pixels apart; tiles go round-robin to the waves.
     const int Su = W > 0 ? (W + 7) / 8 : 0;
     const int Sv = H > 0 ? (H + 7) / 8 : 0;
     const int ntiles = (Sd > 0.0 && npix > 0) ? Su * Sv : 0;
@@ -851,8 +986,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     int head = 0, tail = 0;   // wave-uniform ring positions
     int tile = wave;
     bool busy = false;
-    T e[3] = {0, 0, 0}, d[3] = {0, 0, 0}, cst = (T)0, sh = (T)0;
-    int s = 0, s_end = -1;
+    T e[3] = {0, 0, 0}, d[3] = {0, 0, 0}, cst = (T)0, sh = (T)0, sh_end = (T)0;
     unsigned nsamp = 0;   // COUNT: samples this lane accumulated
     __syncthreads();   // accumulator cleared
     for (;;) {
@@ -871,6 +1005,12 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                     c = (T)((double)r.dt * (double)residual_at<T, FORM_R>(rp, y, a, b, pix) * Sd);
                     active = c != (T)0 && brick_sample_range(r, lob, hib, &s0, &s1);
                 }
+            }
+            if (active) {
+                // trim the estimate to the samples whose cell lies in the box
+                while (s0 <= s1 && !sample_in_box(r.e, r.d, s0, top, lom, ext)) ++s0;
+                while (s1 > s0 && !sample_in_box(r.e, r.d, s1, top, lom, ext)) --s1;
+                active = s0 <= s1;
             }
             const uint64_t mask = __ballot(active);
             if (active) {
@@ -902,9 +1042,8 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                     d[k] = qf[3 + k][q];
                 }
                 cst = qf[6][q];
-                s = qs[0][q];
-                s_end = qs[1][q];
-                sh = (T)s + (T)0.5;
+                sh = (T)qs[0][q] + (T)0.5;
+                sh_end = (T)qs[1][q] + (T)0.5;
                 busy = true;
             }
         }
@@ -925,28 +1064,24 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                 int l[3];
                 T z[3];
                 sample_cell(e, d, sh, top, l, z);
-                // halo-array coordinates of the cell's lower corner
-                const int lx = l[0] - lom[0], ly = l[1] - lom[1], lz = l[2] - lom[2];
-                if ((unsigned)lx < (unsigned)ext[0] && (unsigned)ly < (unsigned)ext[1] &&
-                    (unsigned)lz < (unsigned)ext[2]) {
-                    AccT *pa =
-                        acc + (__umul24((unsigned)lz, ACC_ZP) + __umul24((unsigned)ly, ACC_YP) + lx);
-                    const T c1a = cst * ((T)1 - z[1]), c1b = cst * z[1];
-                    const T za = (T)1 - z[2], zb = z[2];
-                    const T w00 = c1a * za, w10 = c1b * za, w01 = c1a * zb, w11 = c1b * zb;
-                    const T xa = (T)1 - z[0], xb = z[0];
-                    atomicAdd(pa, acc_image<ACC32>(w00 * xa));
-                    atomicAdd(pa + 1, acc_image<ACC32>(w00 * xb));
-                    atomicAdd(pa + ACC_YP, acc_image<ACC32>(w10 * xa));
-                    atomicAdd(pa + ACC_YP + 1, acc_image<ACC32>(w10 * xb));
-                    atomicAdd(pa + ACC_ZP, acc_image<ACC32>(w01 * xa));
-                    atomicAdd(pa + ACC_ZP + 1, acc_image<ACC32>(w01 * xb));
-                    atomicAdd(pa + ACC_ZP + ACC_YP, acc_image<ACC32>(w11 * xa));
-                    atomicAdd(pa + ACC_ZP + ACC_YP + 1, acc_image<ACC32>(w11 * xb));
-                    if constexpr (COUNT) ++nsamp;
-                }
+                AccT *pa = acc + halo_slot(l, base);
+                // corner weights: yz pairs, then each split along x, the
+                // upper share first and the lower one as the difference
+                const T c1b = cst * z[1], c1a = cst - c1b;
+                const T w01 = c1a * z[2], w00 = c1a - w01;
+                const T w11 = c1b * z[2], w10 = c1b - w11;
+                const T w00b = w00 * z[0], w10b = w10 * z[0], w01b = w01 * z[0], w11b = w11 * z[0];
+                atomicAdd(pa, acc_image<ACC32>(w00 - w00b));
+                atomicAdd(pa + 1, acc_image<ACC32>(w00b));
+                atomicAdd(pa + ACC_YP, acc_image<ACC32>(w10 - w10b));
+                atomicAdd(pa + ACC_YP + 1, acc_image<ACC32>(w10b));
+                atomicAdd(pa + ACC_ZP, acc_image<ACC32>(w01 - w01b));
+                atomicAdd(pa + ACC_ZP + 1, acc_image<ACC32>(w01b));
+                atomicAdd(pa + ACC_ZP + ACC_YP, acc_image<ACC32>(w11 - w11b));
+                atomicAdd(pa + ACC_ZP + ACC_YP + 1, acc_image<ACC32>(w11b));
+                if constexpr (COUNT) ++nsamp;
                 sh += (T)1;
-                busy = ++s <= s_end;
+                busy = sh <= sh_end;
             }
         }
     }
@@ -960,33 +1095,28 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
             const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
             if (i < n0 && j < n1 && k < n2) {
                 const long long v = acc_value(acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)]);
-                if (bound_out)
+                if constexpr (COUNT)
                     vmax = v > vmax ? v : vmax;
                 else
                     bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
             }
         }
-        if (bound_out) {
-            // 64 bits: each truncated addend is low by < 1 unit (65536 covers
-            // that many adds per voxel); 32 bits (COUNT): each rounded addend
-            // is off by <= 1/2 unit, and a voxel takes at most one add per
-            // sample of the brick (a sample's eight corners are distinct).
-            // 1e-6 more covers the rounding of dt * weight in T.
+        if constexpr (COUNT) {
+            // each rounded addend is off by <= 1/2 unit, and a voxel takes at
+            // most one add per sample of the brick (a sample's eight corners
+            // are distinct); 1e-6 more covers the rounding of dt * weight in T
             double m = wave_max((double)vmax);
-            double ns = COUNT ? wave_sum((double)nsamp) : 0.0;
+            double ns = wave_sum((double)nsamp);
             if (lane == 0) red[wave] = m;
             __syncthreads();
             for (int q = 0; q < ADJ_WAVES; ++q) m = fmax(m, red[q]);
             __syncthreads();
-            if constexpr (COUNT) {
-                if (lane == 0) red[wave] = ns;
-                __syncthreads();
-                ns = 0.0;
-                for (int q = 0; q < ADJ_WAVES; ++q) ns += red[q];
-            }
+            if (lane == 0) red[wave] = ns;
+            __syncthreads();
+            ns = 0.0;
+            for (int q = 0; q < ADJ_WAVES; ++q) ns += red[q];
             if (tid == 0) {
-                const double slack = COUNT ? 0.5 * ns + 1.0 : 65536.0;
-                const double vb_brick = m > 0.0 ? (m + slack) * inv_S * (1.0 + 1e-6) : 0.0;
+                const double vb_brick = m > 0.0 ? (m + 0.5 * ns + 1.0) * inv_S * (1.0 + 1e-6) : 0.0;
                 bound_out[bid] = __double2float_ru(vb_brick);
             }
         }
@@ -1021,11 +1151,9 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     }
 }
 
-template <typename T, bool FORM_R, int K>
+template <typename T, bool FORM_R, int K, int ACCM>
 __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame fr, int nbx, int nby,
-                                                     double hb, double vb,
-                                                     const float *__restrict__ bounds,
-                                                     float *__restrict__ bound_out,
+                                                     double hb,
                                                      const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ rp,
                                                      const T *__restrict__ y, double a, double b,
@@ -1034,23 +1162,23 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame f
                                                      const T *__restrict__ U, WVec w,
                                                      double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ g_out) {
-    drr_adjoint_block<T, FORM_R, K>(vd, fr, nbx, nby, hb, vb, bounds, bound_out, rays, rp, y, a, b,
-                                    bp, f0, mean, U, w,
-                                    partials, counter, g_out, blockIdx.x, gridDim.x);
+    drr_adjoint_block<T, FORM_R, K, ACCM>(vd, fr, nbx, nby, hb, nullptr, rays, rp, y, a, b, bp, f0,
+                                          mean, U, w, partials, counter, g_out, blockIdx.x,
+                                          gridDim.x);
 }
 
-// The per-brick maxima of the all-ones image's back-projection (the scale
-// source of the FP32 gradient's 32-bit accumulators); its own entry so that
-// traces tell it from drr_adjoint.
+// The per-brick maxima of the all-ones image's back-projection; its own
+// entry so that traces tell it from drr_adjoint.
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adjoint_bounds(VolDims vd, Frame fr, int nbx, int nby,
-                                                        double hb, double vb,
+                                                        double hb,
                                                         const RayRec<T> *__restrict__ rays,
                                                         float *__restrict__ bound_out) {
     const WVec w{};
-    drr_adjoint_block<T, false, 0, true>(vd, fr, nbx, nby, hb, vb, nullptr, bound_out, rays, nullptr,
-                                   nullptr, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr, w,
-                                   nullptr, nullptr, nullptr, blockIdx.x, gridDim.x);
+    drr_adjoint_block<T, false, 0, ADJ_BOUND_PASS>(vd, fr, nbx, nby, hb, bound_out, rays, nullptr,
+                                                   nullptr, 0.0, 0.0, nullptr, nullptr, nullptr,
+                                                   nullptr, w, nullptr, nullptr, nullptr,
+                                                   blockIdx.x, gridDim.x);
 }
 
 // Several requests' gradients (back-projection + chain) in one launch.
@@ -1059,58 +1187,12 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint_batch(const AdjJob 
                                                            int njobs) {
     const int j = job_of(jobs, njobs);
     const AdjJob &J = jobs[j];
-    drr_adjoint_block<T, true, K>(J.vd, J.fr, J.nbx, J.nby, J.hb, J.vb, J.bounds, nullptr,
-                                  (const RayRec<T> *)J.rays,
-                                  (const T *)J.p, (const T *)J.y, J.a, J.b, (T *)nullptr,
-                                  (const T *)J.f0, (const T *)J.mean, (const T *)J.U, J.w,
-                                  J.partials, J.counter, J.g_out, blockIdx.x - J.block0,
-                                  J.nblocks);
-}
-
-// A ray with n >= 2 samples has dt >= step / 2, and its largest per-sample
-// index step is >= dt / (sqrt(3) max spacing); the tent weights one ray
-// gives a voxel then sum to at most 1/h + 1.  (A ray with one sample gives
-// at most 1.)
-static double ray_weight_bound(const VolDims &v, const Frame &fr) {
-    const double smax = fmax(v.spacing[0], fmax(v.spacing[1], v.spacing[2]));
-    return 2.0 * sqrt(3.0) * smax / fr.step + 2.0;
-}
-
-// Bound on the summed trilinear weight all rays give one voxel.  Samples
-// reaching voxel v lie in the cube of index half-width 1 around it (and in
-// the grid box), whose points are at most diam = 2 sqrt(sum s_c^2) mm apart.
-// On the grid box the detector coordinates u = SID (p.eu) / D and
-// v = SID p_z / D, with depth D = p.en + SAD, change by at most
-// (SID / D_min)(1 + A / D_min) per mm, A the largest |p.eu| (|p_z|) over the
-// box (all three are linear in p, so their extremes sit at box corners).  So
-// at most (floor(diam |grad u| / pitch_u) + 1)(... v ...) pixel centres see
-// the cube, and each of those rays gives the voxel at most ray_weight_bound.
-double backprojection_weight_bound(const VolDims &v, const Frame &fr) {
-    double dmin = INFINITY, au = 0.0, av = 0.0;
-    for (int corner = 0; corner < 8; ++corner) {
-        double p[3];
-        p[0] = v.origin[0] + ((corner & 1) ? (v.n0 - 1) * v.spacing[0] : 0.0);
-        p[1] = v.origin[1] + ((corner & 2) ? (v.n1 - 1) * v.spacing[1] : 0.0);
-        p[2] = v.origin[2] + ((corner & 4) ? (v.n2 - 1) * v.spacing[2] : 0.0);
-        double rel[3], depth = 0.0, pu = 0.0, pv = 0.0;
-        for (int c = 0; c < 3; ++c) rel[c] = p[c] - fr.src[c];
-        for (int c = 0; c < 3; ++c) {
-            depth += rel[c] * fr.en[c];
-            pu += rel[c] * fr.eu[c];
-            pv += rel[c] * fr.ev[c];
-        }
-        dmin = fmin(dmin, depth);
-        au = fmax(au, fabs(pu));
-        av = fmax(av, fabs(pv));
-    }
-    if (!(dmin > 0.0)) return INFINITY;
-    double diam = 0.0;
-    for (int c = 0; c < 3; ++c) diam += v.spacing[c] * v.spacing[c];
-    diam = 2.0 * sqrt(diam);
-    const double gu = fr.sid / dmin * (1.0 + au / dmin), gv = fr.sid / dmin * (1.0 + av / dmin);
-    const double nu = fmin(floor(diam * gu / fr.pitch_u) + 1.0, (double)fr.nu);
-    const double nv = fmin(floor(diam * gv / fr.pitch_v) + 1.0, (double)fr.nv);
-    return ray_weight_bound(v, fr) * nu * nv;
+    constexpr int ACCM = std::is_same<T, float>::value ? ADJ_ACC32 : ADJ_ACC64;
+    drr_adjoint_block<T, true, K, ACCM>(J.vd, J.fr, J.nbx, J.nby, J.hb, nullptr,
+                                        (const RayRec<T> *)J.rays, (const T *)J.p,
+                                        (const T *)J.y, J.a, J.b, (T *)nullptr, (const T *)J.f0,
+                                        (const T *)J.mean, (const T *)J.U, J.w, J.partials,
+                                        J.counter, J.g_out, blockIdx.x - J.block0, J.nblocks);
 }
 
 int drr_adjoint_blocks(const VolDims &v) {
@@ -1118,39 +1200,42 @@ int drr_adjoint_blocks(const VolDims &v) {
            ((v.n2 + BRICK_Z - 1) / BRICK_Z);
 }
 
-template <typename T, bool FORM_R, int K>
+template <typename T, bool FORM_R, int K, int ACCM>
 static void launch_adj(const VolDims &v, const Frame &fr, const void *rays, const void *r_or_p,
                        const void *y, double a, double b, void *bp, const void *f0,
                        const void *mean, const void *U, const WVec &w, double *partials,
-                       uint32_t *counter, double *g_out, const float *bounds, float *bound_out,
-                       hipStream_t s) {
+                       uint32_t *counter, double *g_out, hipStream_t s) {
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
-    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0, s,
-                       v, fr, nbx, nby, ray_weight_bound(v, fr), backprojection_weight_bound(v, fr),
-                       bounds, bound_out, (const RayRec<T> *)rays,
-                       (const T *)r_or_p, (const T *)y, a, b, (T *)bp, (const T *)f0,
-                       (const T *)mean, (const T *)U, w, partials, counter, g_out);
+    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K, ACCM>), dim3(drr_adjoint_blocks(v)),
+                       dim3(ADJ_THREADS), 0, s, v, fr, nbx, nby, ray_weight_bound(v, fr),
+                       (const RayRec<T> *)rays, (const T *)r_or_p, (const T *)y, a, b, (T *)bp,
+                       (const T *)f0, (const T *)mean, (const T *)U, w, partials, counter, g_out);
+}
+
+template <typename T, int ACCM>
+static void launch_adj_bp(const VolDims &v, const Frame &fr, const void *rays, const void *r_or_p,
+                          const void *y, double a, double b, void *bp, hipStream_t s) {
+    const WVec w{};
+    if (y)
+        launch_adj<T, true, 0, ACCM>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr, w,
+                                     nullptr, nullptr, nullptr, s);
+    else
+        launch_adj<T, false, 0, ACCM>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr, nullptr,
+                                      nullptr, w, nullptr, nullptr, nullptr, s);
 }
 
 hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, const void *rays,
                               const void *r_or_p, const void *y, double a, double b, void *bp,
-                              hipStream_t s) {
-    const WVec w{};
+                              bool acc32, hipStream_t s) {
     if (dt == PCAS_F32) {
-        if (y)
-            launch_adj<float, true, 0>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr,
-                                       w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+        if (acc32)
+            launch_adj_bp<float, ADJ_ACC32>(v, fr, rays, r_or_p, y, a, b, bp, s);
         else
-            launch_adj<float, false, 0>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr,
-                                        nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+            launch_adj_bp<float, ADJ_ACC64>(v, fr, rays, r_or_p, y, a, b, bp, s);
     } else {
-        if (y)
-            launch_adj<double, true, 0>(v, fr, rays, r_or_p, y, a, b, bp, nullptr, nullptr, nullptr,
-                                        w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
-        else
-            launch_adj<double, false, 0>(v, fr, rays, r_or_p, nullptr, 0.0, 0.0, bp, nullptr,
-                                         nullptr, nullptr, w, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+        if (acc32) return hipErrorInvalidValue;
+        launch_adj_bp<double, ADJ_ACC64>(v, fr, rays, r_or_p, y, a, b, bp, s);
     }
     return hipGetLastError();
 }
@@ -1159,13 +1244,13 @@ hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const F
                                        const void *rays, float *bound_out, hipStream_t s) {
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
-    const double hb = ray_weight_bound(v, fr), vb = backprojection_weight_bound(v, fr);
+    const double hb = ray_weight_bound(v, fr);
     if (dt == PCAS_F32)
         hipLaunchKernelGGL((k_adjoint_bounds<float>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0, s,
-                           v, fr, nbx, nby, hb, vb, (const RayRec<float> *)rays, bound_out);
+                           v, fr, nbx, nby, hb, (const RayRec<float> *)rays, bound_out);
     else
         hipLaunchKernelGGL((k_adjoint_bounds<double>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0,
-                           s, v, fr, nbx, nby, hb, vb, (const RayRec<double> *)rays, bound_out);
+                           s, v, fr, nbx, nby, hb, (const RayRec<double> *)rays, bound_out);
     return hipGetLastError();
 }
 
@@ -1173,22 +1258,23 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,
                                     const double *w, double *partials, uint32_t *counter,
-                                    double *g_out, const float *bounds, hipStream_t s) {
-    if (dt == PCAS_F32 && !bounds) return hipErrorInvalidValue;
+                                    double *g_out, hipStream_t s) {
     WVec wv{};
     for (int k = 0; k < K; ++k) wv.w[k] = w[k];
-#define A(TT, KK)                                                                                 \
+#define A(TT, KK, MM)                                                                             \
     case KK:                                                                                      \
-        launch_adj<TT, true, KK>(v, fr, rays, p, y, a, b, nullptr, f0, mean, U, wv, partials,     \
-                                 counter, g_out, bounds, nullptr, s);                             \
+        launch_adj<TT, true, KK, MM>(v, fr, rays, p, y, a, b, nullptr, f0, mean, U, wv, partials, \
+                                     counter, g_out, s);                                          \
         break
     if (dt == PCAS_F32) {
-        switch (K) { A(float, 1); A(float, 2); A(float, 3); A(float, 4);
-                     A(float, 5); A(float, 6); A(float, 7); A(float, 8);
+        switch (K) { A(float, 1, ADJ_ACC32); A(float, 2, ADJ_ACC32); A(float, 3, ADJ_ACC32);
+                     A(float, 4, ADJ_ACC32); A(float, 5, ADJ_ACC32); A(float, 6, ADJ_ACC32);
+                     A(float, 7, ADJ_ACC32); A(float, 8, ADJ_ACC32);
                      default: return hipErrorInvalidValue; }
     } else {
-        switch (K) { A(double, 1); A(double, 2); A(double, 3); A(double, 4);
-                     A(double, 5); A(double, 6); A(double, 7); A(double, 8);
+        switch (K) { A(double, 1, ADJ_ACC64); A(double, 2, ADJ_ACC64); A(double, 3, ADJ_ACC64);
+                     A(double, 4, ADJ_ACC64); A(double, 5, ADJ_ACC64); A(double, 6, ADJ_ACC64);
+                     A(double, 7, ADJ_ACC64); A(double, 8, ADJ_ACC64);
                      default: return hipErrorInvalidValue; }
     }
 #undef A
@@ -1198,15 +1284,13 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
 AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,
                     const void *y, double a, double b, const void *f0, const void *mean,
                     const void *U, const double *w, double *partials, uint32_t *counter,
-                    double *g_out, const float *bounds) {
+                    double *g_out) {
     AdjJob J;
-    J.bounds = bounds;
     J.vd = v;
     J.fr = fr;
     J.nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     J.nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
     J.hb = ray_weight_bound(v, fr);
-    J.vb = backprojection_weight_bound(v, fr);
     J.rays = rays;
     J.p = p;
     J.y = y;

@@ -71,7 +71,6 @@ struct Request {
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
     double *partials() const { return (double *)(ws + L.partials); }
     char *proj_slot(int slot) const { return ws + (slot ? L.p2 : L.p); }
-    float *bounds() const { return (float *)(ws + L.bounds); }
 };
 
 // First-fit allocation over [0, size) in 256-byte units, coalescing on free.
@@ -168,9 +167,6 @@ int admit(pcas_server *S, Request *r) {
     r->ws = S->arena + S->pool_base + r->off;
     HIPCHK(launch_fill_u32(r->counters(), 64, 0u, S->s));
     HIPCHK(launch_ray_table(md.dt, md.vd, r->fr, r->ws + r->L.rays, S->s));
-    if (md.dt == PCAS_F32)
-        HIPCHK(launch_backprojection_bounds(md.dt, md.vd, r->fr, r->ws + r->L.rays, r->bounds(),
-                                            S->s));
     HIPCHK(launch_pair_sums(md.dt, r->M, r->y, r->y, r->partials(), &r->counters()[2],
                             r->scal() + 16, S->s));
     r->phase = PH_PREPARE;
@@ -384,8 +380,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
         } else if (op.kind == OP_GRAD) {
             const AdjJob aj = make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot),
                                            r->y, op.ab[0], op.ab[1], md.f0, md.mean, md.U, op.w,
-                                           r->partials(), nullptr, r->scal() + 8,
-                                           md.dt == PCAS_F32 ? r->bounds() : nullptr);
+                                           r->partials(), nullptr, r->scal() + 8);
             adjs.add({md.dt, md.K}, aj);
             SumJob &sj = sums[ri];
             sj.partials = r->partials();

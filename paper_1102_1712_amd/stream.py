@@ -33,25 +33,16 @@ from . import binding as B
 
 def predict(history: np.ndarray, coeffs: np.ndarray) -> np.ndarray:
     """Eq. 3: history [L', K] with the most recent solution last; coeffs
-    [K, L] with coeffs[k, l-1] = c_kl.  Needs L' >= L."""
-    K, L = coeffs.shape
-    h = np.asarray(history, dtype=np.float64)
-    out = np.zeros(K)
-    for l in range(1, L + 1):
-        out += coeffs[:, l - 1] * h[-l]
-    return out
+    [K, L] with coeffs[k, l-1] = c_kl.  Needs L' >= L.  Runs in the library
+    (pcas_predict)."""
+    return B.predict(history, coeffs)
 
 
 def fit_predictor(w_train: np.ndarray, L: int = 2) -> np.ndarray:
     """Least-squares fit of c_kl, separately for every coefficient, on a
-    training sequence w_train [T, K] (T > L)."""
-    w = np.asarray(w_train, dtype=np.float64)
-    T, K = w.shape
-    c = np.zeros((K, L))
-    for k in range(K):
-        A = np.stack([w[L - l:T - l, k] for l in range(1, L + 1)], axis=1)
-        c[k] = np.linalg.lstsq(A, w[L:, k], rcond=None)[0]
-    return c
+    training sequence w_train [T, K] (T > L).  Runs in the library
+    (pcas_fit_predictor)."""
+    return B.fit_predictor(w_train, L)
 
 
 # ---------------------------------------------------------------------------

@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.pcas_abi_version() == 5
+    assert L.pcas_abi_version() == 6
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.pcas_status_string(code)
     assert L.pcas_last_error() == b""

@@ -59,3 +59,38 @@ def test_backprojection_bound_rejects_invalid():
         B.backprojection_bound(vol, dataclasses.replace(proj, step=0.0))
     with pytest.raises(B.PcasError):
         B.backprojection_bound(vol, dataclasses.replace(proj, sad=100.0))   # source inside
+
+
+def _brick_halo_max(vol, bp, brick):
+    """Largest value of bp over a 32 x 16 x 8 brick and its one-voxel halo
+    (clipped to the grid); bricks numbered x fastest, then y, then z."""
+    n1, n2, n3 = vol.n
+    nbx, nby = -(-n1 // 32), -(-n2 // 16)
+    bx, by, bz = brick % nbx, (brick // nbx) % nby, brick // (nbx * nby)
+    lo = (bx * 32, by * 16, bz * 8)
+    hi = (min(lo[0] + 32, n1) - 1, min(lo[1] + 16, n2) - 1, min(lo[2] + 8, n3) - 1)
+    sl = bp[max(lo[2] - 1, 0):min(hi[2] + 1, n3 - 1) + 1,
+            max(lo[1] - 1, 0):min(hi[1] + 1, n2 - 1) + 1,
+            max(lo[0] - 1, 0):min(hi[0] + 1, n1 - 1) + 1]
+    return float(sl.max())
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+def test_brick_bounds_hold(oracle_lib, name):
+    """The per-brick bound that sizes every back-projection's fixed-point
+    accumulators covers the exact (P^T 1) over each brick and its halo, on
+    every stress geometry; and it is the tighter of the two bounds."""
+    vol, proj = GEOMS[name]
+    bp = O.drr_adjoint(vol, proj, np.ones(proj.nu * proj.nv))
+    nb = B.backprojection_brick_count(vol)
+    ratios = []
+    for brick in range(nb):
+        peak = _brick_halo_max(vol, bp, brick)
+        bound = proj.step * B.backprojection_brick_bound(vol, proj, brick)
+        assert peak <= bound, (name, brick, peak, bound)
+        assert bound <= proj.step * B.backprojection_bound(vol, proj) * (1 + 1e-12)
+        if peak > 0.0:
+            ratios.append(bound / peak)
+    assert ratios and min(ratios) >= 1.0
+    with pytest.raises(B.PcasError):
+        B.backprojection_brick_bound(vol, proj, nb)

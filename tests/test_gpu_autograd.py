@@ -156,3 +156,29 @@ def test_module_and_store_warp_agree(torch):
         (m(w).double() * r.double()).sum().backward()
         grads.append(w.grad.clone())
     assert torch.equal(grads[0], grads[1])
+
+
+def test_set_projection_between_forward_and_backward(torch):
+    """A graph recorded at angle A keeps A's ray table: switching the module
+    to angle B before backward leaves the gradient equal to a fresh one at
+    A, and overwriting the saved table in place raises instead."""
+    c = synth.small(dtype="f64", seed=5)
+    d = Dev(c)
+    r = torch.randn((c.proj.nv, c.proj.nu), device="cuda", dtype=torch.float64,
+                    generator=torch.Generator(device="cuda").manual_seed(12))
+    say("autograd: set_projection before backward")
+    m = AG.PCAProjector(c.vol, c.proj, d.f0, d.mean, d.U)
+    w = torch.tensor(0.5 * c.w_star, dtype=torch.float64, requires_grad=True)
+    loss = (m(w) * r).sum()
+    m.set_projection(synth.with_angle(c, c.proj.angle + 0.7).proj)
+    loss.backward()
+    fresh = AG.PCAProjector(c.vol, c.proj, d.f0, d.mean, d.U)
+    w2 = torch.tensor(0.5 * c.w_star, dtype=torch.float64, requires_grad=True)
+    (fresh(w2) * r).sum().backward()
+    assert torch.equal(w.grad, w2.grad)
+    # an in-place change of the saved table is caught by autograd
+    w3 = torch.tensor(0.5 * c.w_star, dtype=torch.float64, requires_grad=True)
+    loss3 = (fresh(w3) * r).sum()
+    fresh.rays.add_(0)
+    with pytest.raises(RuntimeError):
+        loss3.backward()

@@ -23,6 +23,21 @@ def torch():
 
 
 def test_stream_small_f64(torch):
+    """A 24-frame stream (Eq. 3 prediction once two solutions exist) on the
+    ragged small FP64 case.  Each checked frame's coefficients are (1) bit
+    for bit those of solve_projection from the same initial guess (the
+    driver adds nothing), and (2) as good as the oracle's minimiser: the
+    oracle's own search from them (compass_search on J, steps 1e-4 down to
+    1e-9) lowers J by at most 1e-6 J, J is within 1e-6 of the oracle
+    minimiser's from the same start, and w within 1e-2 of it.
+
+    The motion here is sub-voxel (displacements of 0.1-0.3 mm on 5-7 mm
+    voxels), so J is kinked where voxels' warp positions cross grid planes
+    (the interpolant's derivative jumps there): a gradient-based solve can
+    stop on a kink where the one-sided gradient vanishes yet J still falls
+    along another direction, by up to ~5e-7 J over ~2e-3 in w on this
+    fixture.  The w bar of 1e-4 is held on the tiny and clinical workloads,
+    whose finer sampling averages the kinks out."""
     c = synth.small(dtype="f64", seed=5)
     d = Dev(c)
     n_frames, fps = 24, 15.0
@@ -47,10 +62,19 @@ def test_stream_small_f64(torch):
     rep = solver.report
     for t in (0, 3, 11, n_frames - 1):
         pj = dataclasses.replace(c.proj, angle=float(angles[t]))
-        prob = O.Problem(c.vol, pj, c.f0, c.mean, c.U, ys[t])
-        w_o, _ = O.minimise(prob, w0s[t])
         w_g = rep.frames[t].w
-        assert np.linalg.norm(w_g - w_o) <= 1e-4 * max(np.linalg.norm(w_o), 1e-3), t
+        w_p, _ = B.solve_projection(c.vol, pj, d.f0, d.mean, d.U, to_dev(ys[t], d.dt), w0s[t],
+                                    solver.opts)
+        assert np.array_equal(w_g, w_p), t
+        prob = O.Problem(c.vol, pj, c.f0, c.mean, c.U, ys[t])
+        J_g = prob.objective(w_g)[0]
+        _, J_local, _ = O.compass_search(prob, w_g, J_g, 1e-4, 1e-9)
+        w_o, info = O.minimise(prob, w0s[t])
+        say("frame", t, "J gpu", J_g, "oracle search from it", J_local, "oracle minimum", info["J"],
+            "w diff", np.linalg.norm(w_g - w_o) / np.linalg.norm(w_o))
+        assert J_g - J_local <= 1e-6 * J_g, t
+        assert J_g <= info["J"] * (1.0 + 1e-6), t
+        assert np.linalg.norm(w_g - w_o) <= 1e-2 * max(np.linalg.norm(w_o), 1e-3), t
     truth = np.array([O.locate(c.vol, c.mean, c.U, w, c.tumour_c0)[0] for w in w_true])
     located = np.array([f.tumour_mm for f in rep.frames])
     err = S.localisation_errors(located, truth)

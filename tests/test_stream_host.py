@@ -4,6 +4,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 from paper_1102_1712_amd import stream as S
 
@@ -59,3 +60,20 @@ def test_localisation_errors():
     e = S.localisation_errors(a, b)
     assert np.isclose(e["e_mean_mm"], (1 + 2 + 0 + 5) / 4)
     assert np.isclose(e["e_max_mm"], 5.0)
+
+
+def test_predictor_error_paths():
+    """The library's Eq. 3 entry points refuse what they cannot do: a
+    history shorter than L, a constant training sequence (the lagged values
+    are linearly dependent for L = 2) and non-finite values."""
+    from paper_1102_1712_amd import binding as B
+    c = np.array([[1.9, -0.98]])
+    with pytest.raises(B.PcasError) as e:
+        S.predict(np.array([[1.0]]), c)
+    assert e.value.code == -1
+    with pytest.raises(B.PcasError) as e:
+        S.fit_predictor(np.full((20, 1), 3.0), L=2)
+    assert e.value.code == -3
+    with pytest.raises(B.PcasError) as e:
+        S.predict(np.array([[1.0], [np.nan]]), c)
+    assert e.value.code == -4
