@@ -309,6 +309,24 @@ int grad_w(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0, con
            const void *U, const double *w, const void *bp, double *g_out, void *workspace,
            size_t workspace_bytes, void *stream);
 
+/* ---- grad_w for callers that cannot allocate ----------------------------
+ * For code that must not call hipMalloc or take a caller workspace: work
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Computes exactly what grad_w computes (same kernels, same
+ * fixed-order reduction, bit-identical g_out) but keeps the reduction's
+ * block partials and counter in a file-scope device array of the library,
+ * grad_w_noalloc_scratch_bytes() bytes (about 128 KiB), one per GPU, held
+ * until the process ends.  Every volume that grad_w accepts fits (its grid
+ * is capped at 2048 blocks); a larger need would return PCAS_EWORKSPACE.
+ * The array is shared by all calls on a GPU and keeps the last call's
+ * contents: each call first zeroes the counter on `stream`, and calls that
+ * overlap on one GPU (other streams or threads) race on it.  Asynchronous on
+ * `stream`; allocates nothing.  Arguments as grad_w without the workspace. */
+size_t grad_w_noalloc_scratch_bytes(void);
+int grad_w_noalloc(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void *f0,
+                   const void *mean, const void *U, const double *w, const void *bp,
+                   double *g_out, void *stream);
+
 /* ---- a9: tumour position (Sec. II.A, pull-back inversion at one point) --
  * Fixed point y <- c0 - x(y) from y = c0, with x the trilinear value of the
  * field of Eq. 1 at y (zero outside the grid); stops when a step is shorter

@@ -32,7 +32,8 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "pcas_server_reserved_bytes", "pcas_server_create", "pcas_server_destroy",
            "pcas_server_add_model", "pcas_server_request_bytes", "pcas_server_submit",
            "pcas_server_step", "pcas_server_set_substep_share", "pcas_server_poll",
-           "pcas_server_stats", "pcas_predict", "pcas_fit_predictor")
+           "pcas_server_stats", "pcas_predict", "pcas_fit_predictor",
+           "grad_w_noalloc_scratch_bytes", "grad_w_noalloc")
 
 
 class PcasError(RuntimeError):
@@ -149,6 +150,8 @@ def lib():
             "pcas_server_stats": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                         ctypes.POINTER(SZ)]),
             "pcas_predict": (I32, [I32, I32, DP, DP, I32, DP]),
+            "grad_w_noalloc_scratch_bytes": (SZ, []),
+            "grad_w_noalloc": (I32, [I32, VP, I32, P, P, P, DP, P, P, P]),
             "pcas_fit_predictor": (I32, [I32, I32, I32, DP, DP]),
             "solve_projection_workspace": (SZ, [I32, VP, PP, I32]),
             "solve_projection": (I32, [I32, VP, PP, I32, P, P, P, P, DP, ctypes.POINTER(Opts), P,
@@ -443,6 +446,20 @@ def grad_w(vol, f0, mean, U, w, bp, out=None, workspace=None, stream=None):
                         _dev(U, "U", f0.dtype), wp, _dev(bp, "bp", f0.dtype),
                         _dev(out, "g", torch.float64), _dev(workspace, "workspace"),
                         workspace.numel(), _stream(stream)), "grad_w")
+    return out
+
+
+def grad_w_noalloc(vol, f0, mean, U, w, bp, out, stream=None):
+    """grad_w with the library's static scratch instead of a workspace
+    (grad_w_noalloc): out is a caller-provided float64 device tensor [K];
+    nothing is allocated."""
+    torch = _torch()
+    K = _K_of(U, vol)
+    _, wp = _host_doubles(w, K)
+    _check(lib().grad_w_noalloc(_dtype_code(f0), ctypes.byref(c_vol(vol)), K, _dev(f0, "f0"),
+                                _dev(mean, "mean", f0.dtype), _dev(U, "U", f0.dtype), wp,
+                                _dev(bp, "bp", f0.dtype), _dev(out, "g", torch.float64),
+                                _stream(stream)), "grad_w_noalloc")
     return out
 
 
