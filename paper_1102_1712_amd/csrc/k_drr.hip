@@ -723,8 +723,14 @@ constexpr int ACC_WORDS = (BRICK_Z + 2) * ACC_ZP;
 // 64 rather than 128 entries: the queues are most of a block's LDS, and
 // the smaller ones let 7 instead of 5 blocks share a CU (the fused gradient
 // kernel measured 428 against 460 us).
-constexpr int QCAP = 64;
-constexpr int ADJ_RUN = 8;     // samples per lane between queue refills
+#ifndef PCAS_ADJ_QCAP
+#define PCAS_ADJ_QCAP 64
+#endif
+#ifndef PCAS_ADJ_RUN
+#define PCAS_ADJ_RUN 8
+#endif
+constexpr int QCAP = PCAS_ADJ_QCAP;
+constexpr int ADJ_RUN = PCAS_ADJ_RUN;   // samples per lane between queue refills
 
 // Fixed-point image of one already-scaled contribution v as a 64-bit two's
 // complement integer.  float: |v| <= 2^30, truncated toward zero and
