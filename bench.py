@@ -42,7 +42,7 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # volumes at once: position and fractions once (9), then 22 per volume.
 def flops_per_sample(kernel: str, K: int) -> float:
     return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_adjoint_chain": 34.0,
-            "adjoint_bounds": 34.0, "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
+            "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
 
 
 # Jacobian chain per voxel: field 6K, displacement split 6, Eq. A.8 and its
@@ -51,24 +51,17 @@ def chain_flops_per_voxel(K: int) -> float:
     return 12.0 * K + 51.0
 
 
-SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot",
-                  "adjoint_bounds")
+SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot")
 KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
                   "drr_adjoint_chain": "k_drr.hip", "drr_forward_dot": "k_drr.hip",
-                  "adjoint_bounds": "k_drr.hip",
                   "warp_pca": "k_warp.hip", "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
-
-
-def drr_bricks(vol) -> int:
-    """Bricks of the back-projection (the library's brick count)."""
-    from paper_1102_1712_amd import binding as B
-    return B.backprojection_brick_count(vol)
 
 
 def kernel_digest(kernel: str) -> str:
     """sha256[:16] of the kernel's source file and every header it includes,
     directly or through other headers (device code only: host-side files
-    such as the solver do not change a kernel's traffic)."""
+    such as the solver's state machine, which the shared header pulls in for
+    its gradient rule, do not change a kernel's traffic)."""
     import hashlib
     import re
 
@@ -76,7 +69,7 @@ def kernel_digest(kernel: str) -> str:
     files, todo = [], [KERNEL_SOURCES[kernel]]
     while todo:
         f = todo.pop(0)
-        if f in files or not os.path.exists(os.path.join(csrc, f)):
+        if f in files or f == "solver.h" or not os.path.exists(os.path.join(csrc, f)):
             continue
         files.append(f)
         with open(os.path.join(csrc, f)) as fh:
@@ -728,6 +721,33 @@ def measured_hbm_frac(kernel: str, workload: str, avg_ms):
     return t / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
 
 
+def host_time(step, base, wms, args):
+    """Wall time of the solve with no timing events at all (the binding call
+    included), against the kernels' busy time per solve from the warmup
+    steps, which time every kernel class: the difference is the time the GPU
+    waits on the host (read-backs, launches, the Python call).  Also the
+    same without speculative gradients."""
+    if args.warmup < 1 or args.no_profile:
+        return None
+    busy = sum(wms.values()) / args.warmup
+    out = {"kernel_busy_ms": busy}
+    for name, spec in (("", 1), ("no_speculation_", 0)):
+        o = B.default_opts(profile=0, speculate=spec, **base)
+        step(o)
+        ts = []
+        for _ in range(max(10, args.steps // 2)):
+            t0 = time.perf_counter()
+            _, r = step(o)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        ts = np.array(ts)
+        out[name + "p50_ms"] = float(np.percentile(ts, 50))
+        out[name + "idle_ms"] = float(np.mean(ts) - busy)
+        out[name + "spec_grads"] = r["spec_grads"]
+    out["n_grads"] = r["n_grads"]
+    log(f"host time: {out}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -831,6 +851,7 @@ def main() -> int:
     log(f"timed {args.steps} steps in {total:.3f} s")
 
     ms = np.array(times) * 1e3
+    host = host_time(step, base, wms, args)
     werr = float(np.linalg.norm(w - case.w_star) / np.linalg.norm(case.w_star))
     N, M = case.vol.nvox, case.proj.npix
     es = 4 if case.dtype == "f32" else 8
@@ -844,7 +865,6 @@ def main() -> int:
         "drr_forward": es * N + 32 * M + 2 * es * M,
         "drr_adjoint": es * N + 32 * M + 2 * es * M,
         "drr_adjoint_chain": (3 + 3 * K + 1) * es * N + 32 * M + 2 * es * M,
-        "adjoint_bounds": 32 * M + 4 * drr_bricks(case.vol),
         "drr_forward_dot": K * es * N + 32 * M + 2 * es * M,
     }
     # per-class figures: from the timed steps where that class carried events,
@@ -994,6 +1014,7 @@ def main() -> int:
                   "status": rep["status"], "polish": 1, "w_rel_err_vs_planted": werr,
                   "tumour_mm": rep["tumour_mm"], **acc},
         "unpolished": unpolished,
+        "host": host,
         "tiny": tiny,
         "drr_gsamples_s": drr.get("Gsamples_s"),
         "adjoint_gsamples_s": adj.get("Gsamples_s"),

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 6
+#define PCAS_ABI_VERSION 7
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -143,16 +143,25 @@ typedef struct {
                               minimiser below the noise of J: without it an FP32 solve stops
                               where FP32 values of J stop resolving decreases, about 1.5e-4
                               from the minimiser in w at the clinical size.  Default 1 */
+    int32_t speculate;     /* methods 1, 2 with PCAS_F32 and grad_mode 1: 1 = launch the
+                              gradient right behind each evaluation after which the solve may
+                              ask for it (its start and polish points, line-search trials),
+                              gated on the GPU by the solve's own rule (Armijo acceptance,
+                              the extrapolation test) applied to the evaluated J, so that an
+                              accepted trial costs one host round trip instead of two.  A
+                              launch whose gate is shut exits at once (report class
+                              PCAS_K_SPEC_SKIP).  Results are bit-identical with 0.
+                              Default 1 */
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
-   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain;
-   PCAS_K_BOUNDS, the all-ones back-projection, is no longer part of a solve
-   and keeps its number so that the classes after it keep theirs) */
+   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain, and
+   PCAS_K_SPEC_SKIP a speculative launch of it (opts.speculate) whose gate
+   was shut, so that it exited at once) */
 enum {
     PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
     PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
-    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_BOUNDS = 10, PCAS_K_CLASSES = 11
+    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_SPEC_SKIP = 10, PCAS_K_CLASSES = 11
 };
 #define PCAS_PROFILE_ALL ((1 << PCAS_K_CLASSES) - 1)
 
@@ -166,7 +175,7 @@ typedef struct {
     double gnorm0, gnorm;  /* ||dJ/dw|| at w0 and at the returned w */
     double tumour_mm[3];   /* located tumour position (if opts.locate) */
     int32_t locate_iters;  /* fixed-point iterations, -1 if not converged */
-    int32_t reserved;
+    int32_t spec_grads;    /* of n_grads, how many a speculative launch supplied */
     double kernel_ms[PCAS_K_CLASSES];   /* with opts.profile: summed kernel time per class (ms) */
     int32_t kernel_launches[PCAS_K_CLASSES];
 } pcas_report;

@@ -68,7 +68,7 @@ class Opts(ctypes.Structure):
                 ("locate_tol", ctypes.c_double), ("c0_mm", ctypes.c_double * 3),
                 ("profile", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
                 ("ftol_rel", ctypes.c_double), ("ls_extrap", ctypes.c_double),
-                ("polish", ctypes.c_int32)]
+                ("polish", ctypes.c_int32), ("speculate", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -77,16 +77,16 @@ class Report(ctypes.Structure):
                 ("J0", ctypes.c_double), ("J", ctypes.c_double), ("a", ctypes.c_double),
                 ("b", ctypes.c_double), ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double),
                 ("tumour_mm", ctypes.c_double * 3), ("locate_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 11),
+                ("spec_grads", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 11),
                 ("kernel_launches", ctypes.c_int32 * 11)]
 
 
 # report.kernel_ms classes; in a solve class 4 is the back-projection with the
-# Jacobian chain fused into it, class 10 the per-projection all-ones
-# back-projection that bounds its FP32 accumulators
+# Jacobian chain fused into it, class 10 a speculative launch of it whose gate
+# was shut (it exited at once)
 KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint_chain",
                   "grad_w", "tumour_position", "y_sums", "jacobian", "drr_forward_dot",
-                  "adjoint_bounds")
+                  "spec_skipped")
 PROFILE_ALL = (1 << len(KERNEL_CLASSES)) - 1
 
 
@@ -497,7 +497,7 @@ def _apply(o: Opts, overrides) -> Opts:
             for c in range(3):
                 o.c0_mm[c] = float(v[c])
         elif k in ("method", "max_iter", "fit_intensity", "max_backtracks", "locate",
-                   "locate_max_iter", "profile", "grad_mode", "polish"):
+                   "locate_max_iter", "profile", "grad_mode", "polish", "speculate"):
             setattr(o, k, int(v))
         else:
             setattr(o, k, float(v))
@@ -508,7 +508,7 @@ def report_dict(r: Report) -> dict:
     return {"status": STOP.get(r.status, r.status), "iters": r.iters, "n_fevals": r.n_fevals,
             "n_grads": r.n_grads, "J0": r.J0, "J": r.J, "a": r.a, "b": r.b,
             "gnorm0": r.gnorm0, "gnorm": r.gnorm, "tumour_mm": list(r.tumour_mm),
-            "locate_iters": r.locate_iters,
+            "locate_iters": r.locate_iters, "spec_grads": r.spec_grads,
             "kernel_ms": {k: r.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
             "kernel_launches": {k: r.kernel_launches[i] for i, k in enumerate(KERNEL_CLASSES)}}
 

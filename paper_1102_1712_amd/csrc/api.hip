@@ -56,6 +56,7 @@ void pcas_default_opts(pcas_opts *o) {
     o->grad_mode = 1;
     o->ls_extrap = 10.0;
     o->polish = 1;
+    o->speculate = 1;
 }
 
 void pcas_paper_opts(pcas_opts *o) {
@@ -281,8 +282,9 @@ size_t solve_projection_workspace(pcas_dtype dtype, const pcas_vol *vol, const p
 namespace {
 
 // Optional per-kernel timing: a pair of HIP events around each launch of
-// the selected classes on the solve's stream, read after the next
-// synchronisation.
+// the selected classes on the solve's stream, read once the solve has
+// ended (reading them between a read-back and the next launch would put the
+// runtime's event bookkeeping on the solve's critical path).
 thread_local std::vector<hipEvent_t> t_events;
 
 struct Profile {
@@ -308,7 +310,8 @@ struct Profile {
     }
     // Call after a read-back: every event recorded so far precedes the
     // publishing kernel on the stream, but the runtime may not have marked
-    // the last ones complete yet, so those are waited for.
+    // the last ones complete yet, so those are waited for.  Event slots are
+    // reused after a collect.
     hipError_t collect() {
         for (const Pending &p : pending) {
             float t = 0.f;
@@ -348,6 +351,18 @@ struct Solver {
     int mom_slot = -1;
     double mom_a0 = 0.0, mom_b0 = 0.0;
     Profile prof;
+    // Speculative gradients (opts.speculate; FP32 one-pass evaluations with
+    // the fused back-projection): the gradient at the last evaluated point,
+    // launched behind the evaluation and gated on the GPU by the machine's
+    // rule.  Valid until consumed or until the next evaluation; used only
+    // when the machine asks for exactly that point, fit and slot.
+    bool speculate = false;
+    int spec_grads = 0;
+    struct {
+        bool valid = false;
+        int slot = 0;
+        double w[PCAS_MAX_K] = {0}, a = 0.0, b = 0.0, g[PCAS_MAX_K] = {0};
+    } spec;
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -367,21 +382,15 @@ struct Solver {
     }
 
     int sync_read(double *host, const double *dev, int count) {
-        int st = readback(host, dev, count, s);
-        if (st) return st;
-        if (prof.mask) HIPCHK(prof.collect());
-        return PCAS_OK;
+        return readback(host, dev, count, s);
     }
 
     // The same for a reduction whose launch left block partials only (no
     // counter): the read-back kernel finishes the sum into dev[0..count).
     int sync_read_sum(double *host, int nblocks, int threads, double scale, double *dev,
                       int count) {
-        int st = readback_sum(host, (const double *)(ws + L.partials), nblocks, threads, scale,
-                              dev, count, s);
-        if (st) return st;
-        if (prof.mask) HIPCHK(prof.collect());
-        return PCAS_OK;
+        return readback_sum(host, (const double *)(ws + L.partials), nblocks, threads, scale, dev,
+                            count, s);
     }
 
     FitArgs fit_args(const double *ab_fixed) const {
@@ -429,8 +438,12 @@ struct Solver {
     // one, else the last fit found), J and the fit follow from them on the
     // host, and the two-pass residual runs only if that sum would cancel.
     // FP64: moments of p itself and the two-pass residual.
+    // With a gradient rule (the machine's, for this evaluation) and
+    // speculation on, the gradient at w is started behind the projection and
+    // comes back with the moments in the same read-back.
     int evaluate(const double *w, const double *ab_fixed, int slot, double *J, double *a,
-                 double *b) {
+                 double *b, const GradRule *rule = nullptr) {
+        spec.valid = false;
         HIPCHK(timed(PCAS_K_WARP, [&] {
             return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s);
         }));
@@ -453,7 +466,12 @@ struct Solver {
         mom_b0 = ff.b0;
         if (!one_pass) return residual(ab_fixed, slot, J, a, b);
         double mo[3], kappa;
-        int st = sync_read_sum(mo, drr_forward_blocks(fr.nu, fr.nv), FWD_THREADS, 1.0, scal(), 3);
+        const int nbf = drr_forward_blocks(fr.nu, fr.nv);
+        int st;
+        if (speculate && rule && rule->mode != GRAD_NEVER)
+            st = speculative_gradient(w, slot, ff, *rule, nbf, mo);
+        else
+            st = sync_read_sum(mo, nbf, FWD_THREADS, 1.0, scal(), 3);
         if (st) return st;
         objective_from_moments(mo, ff, J, a, b, &kappa);
         if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
@@ -467,8 +485,66 @@ struct Solver {
         return PCAS_OK;
     }
 
+    // The projection's moments (mo[0..2]) and, when the gate opens, the
+    // gradient at w, (a, b) of the moments' fit, in one read-back.  The gate
+    // (launch_spec_decide) applies the machine's rule to J from the same
+    // moments with the host's arithmetic; a shut gate makes the gradient
+    // launch exit at once (profile class PCAS_K_SPEC_SKIP).
+    int speculative_gradient(const double *w, int slot, const FitArgs &ff, const GradRule &rule,
+                             int nbf, double *mo) {
+        double *partials = (double *)(ws + L.partials);
+        double *gate = scal() + 32;
+        HIPCHK(launch_spec_decide(partials, nbf, FWD_THREADS, ff, rule, scal(), gate, s));
+        const unsigned both = (1u << PCAS_K_ADJOINT) | (1u << PCAS_K_SPEC_SKIP);
+        const size_t mark = prof.pending.size();
+        HIPCHK(timed(prof.mask >> PCAS_K_ADJOINT & 1u ? PCAS_K_ADJOINT : PCAS_K_SPEC_SKIP, [&] {
+            return launch_drr_adjoint_chain(dt, vd, fr, K, ws + L.rays, proj_slot(slot), y, 0.0, 0.0,
+                                            f0, mean, U, w, partials, nullptr, scal() + 8, s, gate);
+        }));
+        double out[6 + PCAS_MAX_K];
+        const int nba = drr_adjoint_blocks(vd);
+        int st = readback_with(out, 6 + K, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
+            return launch_publish_spec(partials, nba, ADJ_THREADS, K, 2.0, scal(), gate, scal() + 8,
+                                       vals, flag, seq, s);
+        });
+        if (st) return st;
+        const bool go = out[5] != 0.0;
+        if ((prof.mask & both) && prof.pending.size() > mark) {
+            const int cls = go ? PCAS_K_ADJOINT : PCAS_K_SPEC_SKIP;
+            if (prof.mask >> cls & 1u)
+                prof.pending[mark].cls = cls;
+            else
+                prof.pending.erase(prof.pending.begin() + (long)mark);
+        }
+        for (int j = 0; j < 3; ++j) mo[j] = out[j];
+        if (go) {
+            spec.valid = true;
+            spec.slot = slot;
+            for (int k = 0; k < K; ++k) {
+                spec.w[k] = w[k];
+                spec.g[k] = out[6 + k];
+            }
+            spec.a = out[3];
+            spec.b = out[4];
+        }
+        return PCAS_OK;
+    }
+
     // Gradient at the w whose projection is in the slot, at (a, b).
     int gradient(const double *w, double a, double b, int slot, double *g) {
+        if (spec.valid) {
+            spec.valid = false;
+            if (spec.slot == slot && !memcmp(spec.w, w, K * sizeof(double)) &&
+                !memcmp(&spec.a, &a, sizeof(a)) && !memcmp(&spec.b, &b, sizeof(b))) {
+                ++n_grads;
+                ++spec_grads;
+                for (int k = 0; k < K; ++k) {
+                    g[k] = spec.g[k];
+                    if (!isfinite(g[k])) return PCAS_ENONFINITE;
+                }
+                return PCAS_OK;
+            }
+        }
         if (grad_mode == 0) {
             HIPCHK(timed(PCAS_K_JACOBIAN, [&] {
                 return launch_jacobian(dt, vd, K, f0, mean, U, w, ws + L.vol2, s);
@@ -499,12 +575,14 @@ struct Solver {
     // the measured image's sums and the fit's solvability.
     int prepare(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, int32_t K_,
                 const void *f0_, const void *mean_, const void *U_, const void *y_, int fit_,
-                int grad_mode_, unsigned profile, void *workspace, void *stream) {
+                int grad_mode_, unsigned profile, void *workspace, void *stream,
+                int speculate_ = 0) {
         dt = dtype;
         vd = make_dims(vol);
         fr = make_frame(proj);
         K = K_;
         grad_mode = grad_mode_;
+        speculate = speculate_ && grad_mode_ == 1 && dtype == PCAS_F32;
         fplan = plan_drr_forward(dtype, vd, fr, 1);
         fplan_k = plan_drr_forward(dtype, vd, fr, K_);
         M = npix_of(proj);
@@ -546,7 +624,8 @@ int drive(Solver &S, SolveMachine &m) {
         int st;
         switch (op.kind) {
         case OP_EVAL:
-            if ((st = S.evaluate(op.w, op.fixed_ab ? op.ab : nullptr, op.slot, &J, &a, &b)))
+            if ((st = S.evaluate(op.w, op.fixed_ab ? op.ab : nullptr, op.slot, &J, &a, &b,
+                                 &op.next_grad)))
                 return st;
             m.eval_result(J, a, b);
             break;
@@ -589,13 +668,14 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
     report->locate_iters = -1;
     Solver S;
     if ((st = S.prepare(dtype, vol, proj, K, f0, mean, U, y, opts->fit_intensity, opts->grad_mode,
-                        (unsigned)opts->profile, workspace, stream)))
+                        (unsigned)opts->profile, workspace, stream, opts->speculate)))
         return st;
 
     SolveMachine m;
     m.start(*opts, K, noise_model(dtype, *opts, S.M, S.sy, S.syy), w0);
     st = drive(S, m);
     *report = m.report();
+    report->spec_grads = S.spec_grads;
     if (st) return st;
     double w[PCAS_MAX_K];
     for (int k = 0; k < K; ++k) w_out[k] = w[k] = m.w()[k];
@@ -610,6 +690,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
         for (int c = 0; c < 3; ++c) report->tumour_mm[c] = loc[c];
         report->locate_iters = (int32_t)loc[3];
     }
+    if (S.prof.mask) HIPCHK(S.prof.collect());
     for (int c = 0; c < PCAS_K_CLASSES; ++c) {
         report->kernel_ms[c] = S.prof.ms[c];
         report->kernel_launches[c] = S.prof.n[c];

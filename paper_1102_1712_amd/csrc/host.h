@@ -242,6 +242,7 @@ inline int check_opts(const pcas_opts *o) {
     if (!(o->beta_lo > 0.0 && o->beta_lo <= o->beta)) return PCAS_EINVAL;
     if (!(o->ls_extrap >= 0.0) || !isfinite(o->ls_extrap) || isnan(o->ftol_rel)) return PCAS_EINVAL;
     if (o->polish != 0 && o->polish != 1) return PCAS_EINVAL;
+    if (o->speculate != 0 && o->speculate != 1) return PCAS_EINVAL;
     if (o->profile < 0 || o->profile > PCAS_PROFILE_ALL) return PCAS_EINVAL;
     if (o->locate && !finite_vec(o->c0_mm, 3)) return PCAS_EINVAL;
     return PCAS_OK;

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "pcasolve.h"
+#include "solver.h"
 
 namespace pcas {
 
@@ -110,8 +111,12 @@ constexpr double MOMENT_KAPPA_MAX = 1e4;
 // With the reference near the fit S(r0^2) is close to J and the sum does not
 // cancel; kappa = S(r0^2) / J says how far that holds (infinite if J <= 0).
 // A singular refit gives NaN a and b.  fit.mode is FIT_REFIT or FIT_FIXED.
-inline void objective_from_moments(const double *mo, const FitArgs &fit, double *J, double *a,
-                                   double *b, double *kappa) {
+// Compiled for host and device without contraction, so both sides get the
+// same bits from the same moments.
+__host__ __device__ inline void objective_from_moments(const double *mo, const FitArgs &fit,
+                                                       double *J, double *a, double *b,
+                                                       double *kappa) {
+#pragma clang fp contract(off)
     double A, B;
     if (fit.mode == FIT_REFIT) {
         const double det = fit.syy * fit.m - fit.sy * fit.sy;
@@ -132,6 +137,31 @@ inline void objective_from_moments(const double *mo, const FitArgs &fit, double 
     *a = A;
     *b = B;
     *kappa = j > 0.0 ? mo[2] / j : INFINITY;
+}
+
+// The device's reading of a GradRule (solver.h): true when the machine,
+// fed J, asks next for the gradient at the evaluated point.  The quadratic's
+// minimiser is computed as the machine computes it, without contraction; a
+// disagreement at a boundary costs a gradient, never a wrong one, since the
+// driver uses a speculative gradient only when the machine asks for exactly
+// that point, fit and slot.
+__host__ __device__ inline bool grad_follows(const GradRule &r, double J) {
+#pragma clang fp contract(off)
+    if (!(J == J)) return false;   // NaN
+    switch (r.mode) {
+    case GRAD_ALWAYS:
+        return true;
+    case GRAD_IF_ARMIJO: {
+        if (!(J <= r.thr)) return false;
+        if (!r.extrap) return true;
+        const double tq = -r.gd * r.t * r.t / (2.0 * (J - r.phi - r.gd * r.t));
+        return !(tq > 2.0 * r.t);
+    }
+    case GRAD_IF_BELOW:
+        return J < r.thr;
+    default:
+        return false;
+    }
 }
 
 // ---- batched launches: one launch serves several requests ----------------
@@ -198,6 +228,20 @@ hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, 
                               uint32_t seq, hipStream_t s);
 hipError_t launch_publish(const double *src, double *dst_host, int count, uint32_t *flag_host,
                           uint32_t seq, hipStream_t s);
+// A gradient started behind its evaluation (FP32 one-pass evaluations):
+// launch_spec_decide finishes the evaluation's moment sums (as
+// launch_publish_sum with ns = 3, scale 1, does) into mo[0..2] and writes
+// gate = (a, b, go) from them; the adjoint chain given the gate exits at
+// once when go = 0 and otherwise takes (a, b) from it; launch_publish_spec
+// then publishes (mo[0..2], a, b, go, g[0..ns)) with g summed from the
+// chain's partials as launch_publish_sum does (zeros when go = 0).
+hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
+                              const FitArgs &fit, const GradRule &rule, double *mo, double *gate,
+                              hipStream_t s);
+hipError_t launch_publish_spec(const double *partials, int nblocks, int threads, int ns,
+                               double scale, const double *mo, const double *gate, double *g_out,
+                               double *dst_host, uint32_t *flag_host, uint32_t seq,
+                               hipStream_t s);
 
 hipError_t launch_ray_table(pcas_dtype dt, const VolDims &v, const Frame &fr, void *rays,
                             hipStream_t s);
@@ -265,7 +309,7 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,
                                     const double *w, double *partials, uint32_t *counter,
-                                    double *g_out, hipStream_t s);
+                                    double *g_out, hipStream_t s, const double *gate = nullptr);
 
 // J[k][v] = sum_c U_kc(v) df/dx_c(v) at w (Eq. A.8 chain per voxel).
 hipError_t launch_jacobian(pcas_dtype dt, const VolDims &v, int K, const void *f0,

@@ -1167,7 +1167,13 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame f
                                                      const T *__restrict__ mean,
                                                      const T *__restrict__ U, WVec w,
                                                      double *__restrict__ partials,
-                                                     uint32_t *counter, double *__restrict__ g_out) {
+                                                     uint32_t *counter, double *__restrict__ g_out,
+                                                     const double *__restrict__ gate) {
+    if (gate) {   // a speculative gradient: (a, b, go) from the device's decision
+        if (gate[2] == 0.0) return;
+        a = gate[0];
+        b = gate[1];
+    }
     drr_adjoint_block<T, FORM_R, K, ACCM>(vd, fr, nbx, nby, hb, nullptr, rays, rp, y, a, b, bp, f0,
                                           mean, U, w, partials, counter, g_out, blockIdx.x,
                                           gridDim.x);
@@ -1210,13 +1216,15 @@ template <typename T, bool FORM_R, int K, int ACCM>
 static void launch_adj(const VolDims &v, const Frame &fr, const void *rays, const void *r_or_p,
                        const void *y, double a, double b, void *bp, const void *f0,
                        const void *mean, const void *U, const WVec &w, double *partials,
-                       uint32_t *counter, double *g_out, hipStream_t s) {
+                       uint32_t *counter, double *g_out, hipStream_t s,
+                       const double *gate = nullptr) {
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
     hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K, ACCM>), dim3(drr_adjoint_blocks(v)),
                        dim3(ADJ_THREADS), 0, s, v, fr, nbx, nby, ray_weight_bound(v, fr),
                        (const RayRec<T> *)rays, (const T *)r_or_p, (const T *)y, a, b, (T *)bp,
-                       (const T *)f0, (const T *)mean, (const T *)U, w, partials, counter, g_out);
+                       (const T *)f0, (const T *)mean, (const T *)U, w, partials, counter, g_out,
+                       gate);
 }
 
 template <typename T, int ACCM>
@@ -1264,13 +1272,13 @@ hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,
                                     const double *w, double *partials, uint32_t *counter,
-                                    double *g_out, hipStream_t s) {
+                                    double *g_out, hipStream_t s, const double *gate) {
     WVec wv{};
     for (int k = 0; k < K; ++k) wv.w[k] = w[k];
 #define A(TT, KK, MM)                                                                             \
     case KK:                                                                                      \
         launch_adj<TT, true, KK, MM>(v, fr, rays, p, y, a, b, nullptr, f0, mean, U, wv, partials, \
-                                     counter, g_out, s);                                          \
+                                     counter, g_out, s, gate);                                    \
         break
     if (dt == PCAS_F32) {
         switch (K) { A(float, 1, ADJ_ACC32); A(float, 2, ADJ_ACC32); A(float, 3, ADJ_ACC32);

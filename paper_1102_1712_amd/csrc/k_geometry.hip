@@ -80,6 +80,98 @@ hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, 
     return hipGetLastError();
 }
 
+// Speculative gradient, first half: finishes the projection's moment sums
+// exactly as k_publish_sum<3> does (same block width, same order), stores
+// them at mo[0..2], and from them the fit and J as the host does
+// (objective_from_moments).  gate = (a, b, go): go = 1 when the fit is
+// regular, the one-pass sum does not cancel (kappa <= MOMENT_KAPPA_MAX, else
+// the host recomputes J by two passes) and the machine's rule says a
+// gradient at this point follows.
+__global__ __launch_bounds__(1024) void k_spec_decide(const double *__restrict__ partials,
+                                                      int nblocks, FitArgs fit, GradRule rule,
+                                                      double *__restrict__ mo,
+                                                      double *__restrict__ gate) {
+    double tot[3];
+    sum_partials<3, false>(partials, nblocks, 1.0, (int)blockDim.x, tot);
+    if (threadIdx.x == 0) {
+        double J, a, b, kappa;
+        objective_from_moments(tot, fit, &J, &a, &b, &kappa);
+        const bool go = isfinite(a) && isfinite(b) && kappa <= MOMENT_KAPPA_MAX && isfinite(J) &&
+                        grad_follows(rule, J);
+        for (int j = 0; j < 3; ++j) mo[j] = tot[j];
+        gate[0] = a;
+        gate[1] = b;
+        gate[2] = go ? 1.0 : 0.0;
+    }
+}
+
+hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
+                              const FitArgs &fit, const GradRule &rule, double *mo, double *gate,
+                              hipStream_t s) {
+    if (nblocks < 1 || threads < 64 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_spec_decide, dim3(1), dim3(threads), 0, s, partials, nblocks, fit, rule,
+                       mo, gate);
+    return hipGetLastError();
+}
+
+// Speculative gradient, second half: publishes (mo[0..2], a, b, go, g) in
+// one read-back, g = scale * the gradient kernel's partials summed as
+// k_publish_sum<NS> does (zeros when go = 0: the gradient kernel exited at
+// once and left no partials).
+template <int NS>
+__global__ __launch_bounds__(1024) void k_publish_spec(const double *__restrict__ partials,
+                                                       int nblocks, double scale,
+                                                       const double *__restrict__ mo,
+                                                       const double *__restrict__ gate,
+                                                       double *__restrict__ g_out, double *dst,
+                                                       uint32_t *flag, uint32_t seq) {
+    const bool go = gate[2] != 0.0;   // uniform over the block
+    double tot[NS];
+    if (go) {
+        sum_partials<NS, false>(partials, nblocks, scale, (int)blockDim.x, tot);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) tot[j] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < 3; ++j) dst[j] = mo[j];
+        for (int j = 0; j < 3; ++j) dst[3 + j] = gate[j];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            g_out[j] = tot[j];
+            dst[6 + j] = tot[j];
+        }
+        __threadfence_system();
+        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+hipError_t launch_publish_spec(const double *partials, int nblocks, int threads, int ns,
+                               double scale, const double *mo, const double *gate, double *g_out,
+                               double *dst_host, uint32_t *flag_host, uint32_t seq,
+                               hipStream_t s) {
+    if (nblocks < 1 || threads < 64 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+    switch (ns) {
+#define PCAS_PUBLISH_SPEC(N)                                                                       \
+    case N:                                                                                        \
+        hipLaunchKernelGGL(k_publish_spec<N>, dim3(1), dim3(threads), 0, s, partials, nblocks,     \
+                           scale, mo, gate, g_out, dst_host, flag_host, seq);                      \
+        break;
+        PCAS_PUBLISH_SPEC(1)
+        PCAS_PUBLISH_SPEC(2)
+        PCAS_PUBLISH_SPEC(3)
+        PCAS_PUBLISH_SPEC(4)
+        PCAS_PUBLISH_SPEC(5)
+        PCAS_PUBLISH_SPEC(6)
+        PCAS_PUBLISH_SPEC(7)
+        PCAS_PUBLISH_SPEC(8)
+#undef PCAS_PUBLISH_SPEC
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // One thread per detector pixel, all geometry in double with contraction
 // off, so the record is the correctly rounded evaluation of: pixel centre,
 // unit direction from the source, slab intersection with the box of voxel

@@ -17,6 +17,24 @@ namespace pcas {
 
 enum OpKind { OP_EVAL = 0, OP_RESID = 1, OP_GRAD = 2, OP_DONE = 3 };
 
+// Whether the machine, fed J at an OP_EVAL's point, asks next for the
+// gradient there (at that evaluation's own fit and slot), so that a driver
+// can start the gradient before J is back.  The machine's own decision is
+// made as always from the J it is fed; the rule only restates it:
+//   GRAD_ALWAYS     a start or polish evaluation;
+//   GRAD_IF_ARMIJO  a line-search trial: J <= thr (accepted), unless extrap
+//                   is set and the quadratic through phi(0) = phi,
+//                   phi'(0) = gd and phi(t) = J has its minimiser beyond 2 t
+//                   (then an extrapolated trial comes first);
+//   GRAD_IF_BELOW   an extrapolated trial: J < thr (it is kept);
+//   GRAD_NEVER      anything else.
+enum { GRAD_NEVER = 0, GRAD_ALWAYS = 1, GRAD_IF_ARMIJO = 2, GRAD_IF_BELOW = 3 };
+struct GradRule {
+    int mode = GRAD_NEVER;
+    int extrap = 0;
+    double thr = 0.0, phi = 0.0, gd = 0.0, t = 0.0;
+};
+
 // Two projection buffers ("slots") per solve: OP_EVAL writes its projection
 // to op.slot, OP_RESID and OP_GRAD read the projection in op.slot.  A line
 // search that tries one more point after an accepted one keeps both, so the
@@ -27,6 +45,7 @@ struct SolveOp {
     bool fixed_ab = false;        // OP_EVAL / OP_RESID: (a, b) = ab instead of Eq. A.1
     double ab[2] = {1.0, 0.0};    // OP_EVAL fixed: (a, b); OP_GRAD: (a, b) of the residual
     int slot = 0;                 // projection buffer, 0 or 1
+    GradRule next_grad;           // OP_EVAL: whether OP_GRAD at this point follows
 };
 
 // Relative rounding noise of an evaluated J, the band within which two
@@ -101,8 +120,11 @@ private:
         return s;
     }
 
-    void want_eval(const double *w, bool fixed, double a, double b, Pc next, int slot = 0) {
+    void want_eval(const double *w, bool fixed, double a, double b, Pc next, int slot = 0,
+                   int grad = GRAD_NEVER) {
         op_.kind = OP_EVAL;
+        op_.next_grad = GradRule{};
+        op_.next_grad.mode = grad;
         for (int k = 0; k < K_; ++k) op_.w[k] = w[k];
         op_.fixed_ab = fixed;
         op_.ab[0] = a;
@@ -230,18 +252,25 @@ private:
                     break;
                 }
                 for (int k = 0; k < K; ++k) wt_[k] = w_[k] + t_ * d_[k];
-                want_eval(wt_, false, 1.0, 0.0, LS_AFTER_TRIAL, 0);
+                thr_ = phi_ + o_.alpha * t_ * gd_;
+                want_eval(wt_, false, 1.0, 0.0, LS_AFTER_TRIAL, 0, GRAD_IF_ARMIJO);
+                op_.next_grad.extrap = bt_ == 0 && o_.ls_extrap > 0.0;
+                op_.next_grad.thr = thr_;
+                op_.next_grad.phi = phi_;
+                op_.next_grad.gd = gd_;
+                op_.next_grad.t = t_;
                 return;
             case LS_AFTER_TRIAL: {
                 phi_t_ = rJ_;
                 a_t_ = ra_;
                 b_t_ = rb_;
                 const double tq = -gd_ * t_ * t_ / (2.0 * (phi_t_ - phi_ - gd_ * t_));
-                if (phi_t_ <= phi_ + o_.alpha * t_ * gd_) {
+                if (phi_t_ <= thr_) {
                     if (bt_ == 0 && o_.ls_extrap > 0.0 && tq > 2.0 * t_) {
                         tx_ = tq < o_.ls_extrap * t_ ? tq : o_.ls_extrap * t_;
                         for (int k = 0; k < K; ++k) wx_[k] = w_[k] + tx_ * d_[k];
-                        want_eval(wx_, false, 1.0, 0.0, LS_AFTER_EXTRAP, 1);
+                        want_eval(wx_, false, 1.0, 0.0, LS_AFTER_EXTRAP, 1, GRAD_IF_BELOW);
+                        op_.next_grad.thr = phi_t_;
                         return;
                     }
                     ls_end(LS_OK, 0);
@@ -278,7 +307,7 @@ private:
             // directions stay CG's).  A predicted decrease within the noise
             // floor ends the solve when the model is trusted, as in BFGS.
             case CG_START:
-                want_eval(w_, false, 1.0, 0.0, CG_AFTER_EVAL0);
+                want_eval(w_, false, 1.0, 0.0, CG_AFTER_EVAL0, 0, GRAD_ALWAYS);
                 return;
             case CG_AFTER_EVAL0:
                 phi_ = rJ_;
@@ -423,7 +452,7 @@ private:
             // factor 2 of its prediction (H can still underestimate flat
             // directions).
             case QN_START:
-                want_eval(w_, false, 1.0, 0.0, QN_AFTER_EVAL0);
+                want_eval(w_, false, 1.0, 0.0, QN_AFTER_EVAL0, 0, GRAD_ALWAYS);
                 return;
             case QN_AFTER_EVAL0:
                 phi_ = rJ_;
@@ -549,7 +578,7 @@ private:
                     pc_ = SOLVE_FINISH;
                     break;
                 }
-                want_eval(wx_, false, 1.0, 0.0, POLISH_AFTER_EVAL, 1);
+                want_eval(wx_, false, 1.0, 0.0, POLISH_AFTER_EVAL, 1, GRAD_ALWAYS);
                 return;
             }
             case POLISH_AFTER_EVAL:
@@ -688,6 +717,7 @@ private:
     double Hc_[PCAS_MAX_K * PCAS_MAX_K] = {0};  // estimate kept for the polish step
     double phi_ = 0.0, a_ = 0.0, b_ = 0.0, phi_t_ = 0.0, a_t_ = 0.0, b_t_ = 0.0;
     double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, tx_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
+    double thr_ = 0.0;    // Armijo threshold of the current trial
     double curv_ = 0.0;   // CG: (s.y) / (s.s) of the last accepted step
     double t0_ = 0.0, pred_ = -1.0;   // CG: first trial step, the model's decrease for it
     double last_drop_ = 0.0;   // CG, BFGS: J decrease of the last accepted step

@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.pcas_abi_version() == 6
+    assert L.pcas_abi_version() == 7
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.pcas_status_string(code)
     assert L.pcas_last_error() == b""
@@ -66,7 +66,7 @@ def test_kernel_classes_match_the_header():
     assert "#define PCAS_PROFILE_ALL ((1 << PCAS_K_CLASSES) - 1)" in src
     assert B.PROFILE_ALL == (1 << n) - 1 == B.profile_mask()
     assert B.profile_mask("drr_adjoint_chain") == 1 << ids["ADJOINT"]
-    assert B.profile_mask("adjoint_bounds", "warp_pca") == (1 << ids["BOUNDS"]) | (1 << ids["WARP"])
+    assert B.profile_mask("spec_skipped", "warp_pca") == (1 << ids["SPEC_SKIP"]) | (1 << ids["WARP"])
 
 
 def test_default_and_paper_options(L):
@@ -74,6 +74,7 @@ def test_default_and_paper_options(L):
     assert (o.method, o.max_iter, o.fit_intensity, o.max_backtracks) == (1, 30, 1, 12)
     assert (o.mu0, o.alpha, o.beta, o.beta_lo) == (1.0, 0.1, 0.5, 0.1)
     assert o.grad_mode == 1 and o.ls_extrap == 10.0 and o.ftol_rel < 0
+    assert o.polish == 1 and o.speculate == 1
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
     p = B.paper_opts()
     scale = 1.0 / g["coefficient_std"]

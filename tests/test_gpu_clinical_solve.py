@@ -79,3 +79,22 @@ def test_clinical_unpolished_solve_stops_at_band(clinical, oracle_lib, fit, meth
     assert rep["status"] == "converged"
     assert J64 - ref["J"] <= 2.0 * band * ref["J"]
     assert np.linalg.norm(np.array(rep["tumour_mm"]) - np.array(ref["tumour_mm"])) <= 0.05
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_clinical_speculation_is_bit_identical(clinical, method):
+    """The timed configuration with and without speculative gradients:
+    identical results, and all but at most two gradients from speculative
+    launches."""
+    c, d, y, _ = clinical
+    say("clinical speculation on/off, method", method)
+    kw = dict(xtol=1e-7, method=method, locate=1, c0_mm=tuple(c.tumour_c0))
+    w0, r0 = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
+                                B.default_opts(speculate=0, **kw))
+    w1, r1 = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
+                                B.default_opts(**kw))
+    say("n_grads", r1["n_grads"], "spec_grads", r1["spec_grads"])
+    assert np.array_equal(w0, w1)
+    for k in ("status", "iters", "n_fevals", "n_grads", "J", "a", "b", "gnorm", "tumour_mm"):
+        assert r0[k] == r1[k], k
+    assert r0["spec_grads"] == 0 and r1["spec_grads"] >= r1["n_grads"] - 2
