@@ -143,7 +143,7 @@ typedef struct {
                               minimiser below the noise of J: without it an FP32 solve stops
                               where FP32 values of J stop resolving decreases, about 1.5e-4
                               from the minimiser in w at the clinical size.  Default 1 */
-    int32_t speculate;     /* methods 1, 2 with PCAS_F32 and grad_mode 1: 1 = launch the
+    int32_t speculate;     /* methods 1, 2 with grad_mode 1: 1 = launch the
                               gradient right behind each evaluation after which the solve may
                               ask for it (its start and polish points, line-search trials),
                               gated on the GPU by the solve's own rule (Armijo acceptance,
@@ -178,6 +178,9 @@ typedef struct {
     int32_t spec_grads;    /* of n_grads, how many a speculative launch supplied */
     double kernel_ms[PCAS_K_CLASSES];   /* with opts.profile: summed kernel time per class (ms) */
     int32_t kernel_launches[PCAS_K_CLASSES];
+    double host_ms;        /* wall time of the solve_projection call on the host (ms) */
+    double wait_ms;        /* of host_ms, the time spent waiting for the GPU's read-backs; the
+                              rest is host work (checks, the state machine, launch calls) */
 } pcas_report;
 
 /* ---- utilities --------------------------------------------------------- */

@@ -78,7 +78,8 @@ class Report(ctypes.Structure):
                 ("b", ctypes.c_double), ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double),
                 ("tumour_mm", ctypes.c_double * 3), ("locate_iters", ctypes.c_int32),
                 ("spec_grads", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 11),
-                ("kernel_launches", ctypes.c_int32 * 11)]
+                ("kernel_launches", ctypes.c_int32 * 11), ("host_ms", ctypes.c_double),
+                ("wait_ms", ctypes.c_double)]
 
 
 # report.kernel_ms classes; in a solve class 4 is the back-projection with the
@@ -508,7 +509,8 @@ def report_dict(r: Report) -> dict:
     return {"status": STOP.get(r.status, r.status), "iters": r.iters, "n_fevals": r.n_fevals,
             "n_grads": r.n_grads, "J0": r.J0, "J": r.J, "a": r.a, "b": r.b,
             "gnorm0": r.gnorm0, "gnorm": r.gnorm, "tumour_mm": list(r.tumour_mm),
-            "locate_iters": r.locate_iters, "spec_grads": r.spec_grads,
+            "locate_iters": r.locate_iters, "spec_grads": r.spec_grads, "host_ms": r.host_ms,
+            "wait_ms": r.wait_ms,
             "kernel_ms": {k: r.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
             "kernel_launches": {k: r.kernel_launches[i] for i, k in enumerate(KERNEL_CLASSES)}}
 

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -381,16 +382,28 @@ struct Solver {
         return hipSuccess;
     }
 
+    // Host time spent waiting in read-backs (report.wait_ms).
+    double wait_ms = 0.0;
+    template <class F> int waited(F &&read) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int st = read();
+        wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                       .count();
+        return st;
+    }
+
     int sync_read(double *host, const double *dev, int count) {
-        return readback(host, dev, count, s);
+        return waited([&] { return readback(host, dev, count, s); });
     }
 
     // The same for a reduction whose launch left block partials only (no
     // counter): the read-back kernel finishes the sum into dev[0..count).
     int sync_read_sum(double *host, int nblocks, int threads, double scale, double *dev,
                       int count) {
-        return readback_sum(host, (const double *)(ws + L.partials), nblocks, threads, scale, dev,
-                            count, s);
+        return waited([&] {
+            return readback_sum(host, (const double *)(ws + L.partials), nblocks, threads, scale,
+                                dev, count, s);
+        });
     }
 
     FitArgs fit_args(const double *ab_fixed) const {
@@ -409,7 +422,10 @@ struct Solver {
 
     // J = ||p - a y - b||^2 for the projection in the slot, summed directly
     // over the residual; (a, b) refitted by Eq. A.1 unless fixed.
-    int residual(const double *ab_fixed, int slot, double *J, double *a, double *b) {
+    // With a gradient rule and the point w of the slot's projection (an FP64
+    // evaluation), the gradient at w comes back with J in one read-back.
+    int residual(const double *ab_fixed, int slot, double *J, double *a, double *b,
+                 const GradRule *rule = nullptr, const double *w = nullptr) {
         FitArgs fa = fit_args(ab_fixed);
         if (fa.mode == FIT_REFIT) {   // the refit reads the moments of this slot's projection
             if (slot != mom_slot) return hip_fail(hipErrorInvalidValue, "refit without moments");
@@ -421,7 +437,13 @@ struct Solver {
                                    (double *)(ws + L.partials), &counters()[3], scal() + 3, s);
         }));
         double out[3];
-        int st = sync_read(out, scal() + 3, 3);
+        int st;
+        if (speculate && rule && w && rule->mode != GRAD_NEVER) {
+            HIPCHK(launch_spec_decide_jab(scal() + 3, *rule, scal() + 32, s));
+            st = gated_gradient(w, slot, scal() + 3, out);
+        } else {
+            st = sync_read(out, scal() + 3, 3);
+        }
         if (st) return st;
         *J = out[0];
         *a = out[1];
@@ -464,13 +486,15 @@ struct Solver {
         mom_slot = slot;
         mom_a0 = ff.a0;
         mom_b0 = ff.b0;
-        if (!one_pass) return residual(ab_fixed, slot, J, a, b);
+        if (!one_pass) return residual(ab_fixed, slot, J, a, b, rule, w);
         double mo[3], kappa;
         const int nbf = drr_forward_blocks(fr.nu, fr.nv);
         int st;
-        if (speculate && rule && rule->mode != GRAD_NEVER)
-            st = speculative_gradient(w, slot, ff, *rule, nbf, mo);
-        else
+        if (speculate && rule && rule->mode != GRAD_NEVER) {
+            HIPCHK(launch_spec_decide((const double *)(ws + L.partials), nbf, FWD_THREADS, ff, *rule,
+                                      scal(), scal() + 32, s));
+            st = gated_gradient(w, slot, scal(), mo);
+        } else
             st = sync_read_sum(mo, nbf, FWD_THREADS, 1.0, scal(), 3);
         if (st) return st;
         objective_from_moments(mo, ff, J, a, b, &kappa);
@@ -485,16 +509,15 @@ struct Solver {
         return PCAS_OK;
     }
 
-    // The projection's moments (mo[0..2]) and, when the gate opens, the
-    // gradient at w, (a, b) of the moments' fit, in one read-back.  The gate
-    // (launch_spec_decide) applies the machine's rule to J from the same
-    // moments with the host's arithmetic; a shut gate makes the gradient
-    // launch exit at once (profile class PCAS_K_SPEC_SKIP).
-    int speculative_gradient(const double *w, int slot, const FitArgs &ff, const GradRule &rule,
-                             int nbf, double *mo) {
+    // Behind an evaluation whose gate (a, b, go) is at scal()[32..34]: the
+    // fused back-projection and chain at w in the slot, which exits at once
+    // when the gate is shut (profile class PCAS_K_SPEC_SKIP), then one
+    // read-back of the evaluation's three values at src (moments, or J, a, b)
+    // into head[0..2] with the decision and the gradient.  An open gate
+    // leaves the gradient at (w, a, b of the gate) for gradient() to take.
+    int gated_gradient(const double *w, int slot, const double *src, double *head) {
         double *partials = (double *)(ws + L.partials);
         double *gate = scal() + 32;
-        HIPCHK(launch_spec_decide(partials, nbf, FWD_THREADS, ff, rule, scal(), gate, s));
         const unsigned both = (1u << PCAS_K_ADJOINT) | (1u << PCAS_K_SPEC_SKIP);
         const size_t mark = prof.pending.size();
         HIPCHK(timed(prof.mask >> PCAS_K_ADJOINT & 1u ? PCAS_K_ADJOINT : PCAS_K_SPEC_SKIP, [&] {
@@ -503,9 +526,11 @@ struct Solver {
         }));
         double out[6 + PCAS_MAX_K];
         const int nba = drr_adjoint_blocks(vd);
-        int st = readback_with(out, 6 + K, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
-            return launch_publish_spec(partials, nba, ADJ_THREADS, K, 2.0, scal(), gate, scal() + 8,
-                                       vals, flag, seq, s);
+        int st = waited([&] {
+            return readback_with(out, 6 + K, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
+                return launch_publish_spec(partials, nba, ADJ_THREADS, K, 2.0, src, gate,
+                                           scal() + 8, vals, flag, seq, s);
+            });
         });
         if (st) return st;
         const bool go = out[5] != 0.0;
@@ -516,7 +541,7 @@ struct Solver {
             else
                 prof.pending.erase(prof.pending.begin() + (long)mark);
         }
-        for (int j = 0; j < 3; ++j) mo[j] = out[j];
+        for (int j = 0; j < 3; ++j) head[j] = out[j];
         if (go) {
             spec.valid = true;
             spec.slot = slot;
@@ -582,7 +607,7 @@ struct Solver {
         fr = make_frame(proj);
         K = K_;
         grad_mode = grad_mode_;
-        speculate = speculate_ && grad_mode_ == 1 && dtype == PCAS_F32;
+        speculate = speculate_ && grad_mode_ == 1;
         fplan = plan_drr_forward(dtype, vd, fr, 1);
         fplan_k = plan_drr_forward(dtype, vd, fr, K_);
         M = npix_of(proj);
@@ -653,6 +678,7 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
                                 const void *y, const double *w0, const pcas_opts *opts,
                                 void *workspace, size_t workspace_bytes, double *w_out,
                                 pcas_report *report, void *stream) {
+    const auto t_start = std::chrono::steady_clock::now();
     if (!dtype_ok(dtype) || K < 1 || K > PCAS_MAX_K) return PCAS_EINVAL;
     int st = check_vol(vol);
     if (st) return st;
@@ -695,6 +721,9 @@ extern "C" int solve_projection(pcas_dtype dtype, const pcas_vol *vol, const pca
         report->kernel_ms[c] = S.prof.ms[c];
         report->kernel_launches[c] = S.prof.n[c];
     }
+    report->host_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    report->wait_ms = S.wait_ms;
     return PCAS_OK;
 }
 

@@ -228,8 +228,8 @@ hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, 
                               uint32_t seq, hipStream_t s);
 hipError_t launch_publish(const double *src, double *dst_host, int count, uint32_t *flag_host,
                           uint32_t seq, hipStream_t s);
-// A gradient started behind its evaluation (FP32 one-pass evaluations):
-// launch_spec_decide finishes the evaluation's moment sums (as
+// A gradient started behind its evaluation: launch_spec_decide (FP32
+// one-pass evaluations) finishes the evaluation's moment sums (as
 // launch_publish_sum with ns = 3, scale 1, does) into mo[0..2] and writes
 // gate = (a, b, go) from them; the adjoint chain given the gate exits at
 // once when go = 0 and otherwise takes (a, b) from it; launch_publish_spec
@@ -238,6 +238,9 @@ hipError_t launch_publish(const double *src, double *dst_host, int count, uint32
 hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
                               const FitArgs &fit, const GradRule &rule, double *mo, double *gate,
                               hipStream_t s);
+// gate from (J, a, b) already on the device (the two-pass residual's).
+hipError_t launch_spec_decide_jab(const double *jab, const GradRule &rule, double *gate,
+                                  hipStream_t s);
 hipError_t launch_publish_spec(const double *partials, int nblocks, int threads, int ns,
                                double scale, const double *mo, const double *gate, double *g_out,
                                double *dst_host, uint32_t *flag_host, uint32_t seq,

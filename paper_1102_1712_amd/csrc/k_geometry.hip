@@ -105,6 +105,24 @@ __global__ __launch_bounds__(1024) void k_spec_decide(const double *__restrict__
     }
 }
 
+// The same decision from an objective already summed on the device:
+// jab = (J, a, b) of the two-pass residual (the FP64 evaluation).
+__global__ void k_spec_decide_jab(const double *__restrict__ jab, GradRule rule,
+                                  double *__restrict__ gate) {
+    if (threadIdx.x != 0) return;
+    const double J = jab[0], a = jab[1], b = jab[2];
+    const bool go = isfinite(a) && isfinite(b) && isfinite(J) && grad_follows(rule, J);
+    gate[0] = a;
+    gate[1] = b;
+    gate[2] = go ? 1.0 : 0.0;
+}
+
+hipError_t launch_spec_decide_jab(const double *jab, const GradRule &rule, double *gate,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_spec_decide_jab, dim3(1), dim3(64), 0, s, jab, rule, gate);
+    return hipGetLastError();
+}
+
 hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
                               const FitArgs &fit, const GradRule &rule, double *mo, double *gate,
                               hipStream_t s) {

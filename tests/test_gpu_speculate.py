@@ -74,14 +74,21 @@ def test_speculation_with_profiling(small32):
         assert skip < 0.5 * full
 
 
-def test_f64_and_jacobian_mode_do_not_speculate():
+def test_f64_speculates_and_jacobian_mode_does_not():
+    """FP64 evaluations gate on J, a, b of the two-pass residual: the same
+    results with and without speculation.  The projected-Jacobian gradient
+    (grad_mode 0) never speculates."""
     torch_or_skip()
     c = synth.small(dtype="f64", seed=21)
     d = Dev(c)
     y = measured(c)
-    say("f64 solve with speculate=1")
-    w, rep = _solve(c, d, y, speculate=1, max_iter=6)
-    assert rep["spec_grads"] == 0
+    for method in (1, 2):
+        say("f64 solve with and without speculation, method", method)
+        off = _solve(c, d, y, speculate=0, max_iter=6, method=method)
+        on = _solve(c, d, y, speculate=1, max_iter=6, method=method)
+        _same(off, on)
+        assert off[1]["spec_grads"] == 0
+        assert on[1]["n_grads"] - 2 <= on[1]["spec_grads"] <= on[1]["n_grads"]
     c32 = synth.small(dtype="f32", seed=6)
     d32 = Dev(c32)
     y32 = measured(c32)
