@@ -276,26 +276,18 @@ int drr_adjoint32(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, 
  * invalid volume or projection. */
 double pcas_backprojection_bound(const pcas_vol *vol, const pcas_proj *proj);
 
-/* The same bound over one back-projection brick (see below for the brick
- * order): (P^T 1)(v) <= step * B_brick for every voxel v of the brick and of
+/* The same bound over one back-projection brick (brick order: see
+ * backprojection_brick_count): (P^T 1)(v) <= step * B_brick for every voxel v of the brick and of
  * its one-voxel halo.  This is what sizes the brick's fixed-point
  * accumulators in drr_adjoint, drr_adjoint32 and the solver's gradient.
  * Host-only; negative for an invalid volume, projection or brick index. */
 double pcas_backprojection_brick_bound(const pcas_vol *vol, const pcas_proj *proj,
                                        int32_t brick);
 
-/* Per-brick maxima of the back-projection of the all-ones image, rounded up:
- * how far below the analytic bound the real weights stay (a diagnostic; the
- * back-projections do not need it).  The volume is cut into 32 x 16 x 8
- * voxel bricks (brick x fastest, then y, then z); bounds_out: device
- * float[backprojection_brick_count(vol)], each at least the largest
- * (P^T 1)(v) over the brick's voxels, with P^T drr_adjoint's operator and 1
- * the all-ones image (0 where no sample reaches the brick).  rays:
- * ray_table() output for (vol, proj) in dtype.  Asynchronous on `stream`.
- * backprojection_brick_count returns -1 for an invalid volume. */
+/* Number of back-projection bricks: the volume is cut into 32 x 16 x 8
+ * voxel bricks (brick x fastest, then y, then z), the brick index of
+ * pcas_backprojection_brick_bound.  Host-only; -1 for an invalid volume. */
 int32_t backprojection_brick_count(const pcas_vol *vol);
-int backprojection_brick_bounds(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
-                                const void *rays, float *bounds_out, void *stream);
 
 /* ---- a5: intensity fit (Eq. A.1) and residual ----------------------------
  * stats_out: device double[8] =

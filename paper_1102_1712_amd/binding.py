@@ -25,7 +25,7 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
            "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "drr_adjoint32",
            "pcas_backprojection_bound", "pcas_backprojection_brick_bound",
-           "backprojection_brick_count", "backprojection_brick_bounds",
+           "backprojection_brick_count",
            "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
            "objective_gradient", "solve_projection_workspace", "solve_projection",
@@ -130,7 +130,6 @@ def lib():
             "pcas_backprojection_bound": (D, [VP, PP]),
             "pcas_backprojection_brick_bound": (D, [VP, PP, I32]),
             "backprojection_brick_count": (I32, [VP]),
-            "backprojection_brick_bounds": (I32, [I32, VP, PP, P, P, P]),
             "residual_fit_workspace_bytes": (SZ, [I64]),
             "residual_fit": (I32, [I32, I64, P, P, I32, P, P, P, SZ, P]),
             "grad_w_workspace_bytes": (SZ, [I32, VP, I32]),
@@ -393,26 +392,6 @@ def backprojection_brick_count(vol) -> int:
     if n < 0:
         raise PcasError(-1, "backprojection_brick_count: invalid volume")
     return n
-
-
-def backprojection_brick_bounds(vol, proj, rays, dtype=None, stream=None):
-    """Per-brick upper bounds of P^T 1 over 32 x 16 x 8 bricks (x fastest),
-    float32 on the rays' device; dtype defaults to the ray table's."""
-    torch = _torch()
-    n = int(lib().backprojection_brick_count(ctypes.byref(c_vol(vol))))
-    if n < 0:
-        raise PcasError(-1, "backprojection_brick_bounds: invalid volume")
-    out = torch.empty(n, dtype=torch.float32, device=rays.device)
-    if dtype is not None:
-        code = PCAS_F32 if dtype == torch.float32 else PCAS_F64
-    else:
-        code = getattr(rays, "_pcas_dtype", None)
-        if code is None:
-            raise ValueError("backprojection_brick_bounds: give the ray table's dtype")
-    _check(lib().backprojection_brick_bounds(code, ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj)),
-                                             _dev(rays, "rays"), _dev(out, "bounds", torch.float32),
-                                             _stream(stream)), "backprojection_brick_bounds")
-    return out
 
 
 def residual_fit(p, y, fit_intensity: bool = True, r_out=None, want_r: bool = True, stream=None):

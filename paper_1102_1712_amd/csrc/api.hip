@@ -187,19 +187,6 @@ int32_t backprojection_brick_count(const pcas_vol *vol) {
     return drr_adjoint_blocks(make_dims(vol));
 }
 
-int backprojection_brick_bounds(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj,
-                                const void *rays, float *bounds_out, void *stream) {
-    if (!dtype_ok(dtype)) return PCAS_EINVAL;
-    int st = check_vol(vol);
-    if (st) return st;
-    if ((st = check_vol_bytes(vol, dtype))) return st;
-    if ((st = check_proj(proj, vol))) return st;
-    if (!rays || !aligned(rays, 16) || !bounds_out || !aligned(bounds_out, 4)) return PCAS_EINVAL;
-    HIPCHK(launch_backprojection_bounds(dtype, make_dims(vol), make_frame(proj), rays, bounds_out,
-                                        (hipStream_t)stream));
-    return PCAS_OK;
-}
-
 size_t residual_fit_workspace_bytes(int64_t npix) {
     if (npix < 1) return 0;
     return align256((size_t)sums_blocks(npix) * RED_SLOTS * sizeof(double)) + 512;

@@ -303,11 +303,6 @@ int drr_adjoint_blocks(const VolDims &v);
 // its one-voxel halo.
 double backprojection_weight_bound(const VolDims &v, const Frame &fr);
 double brick_weight_bound_host(const VolDims &v, const Frame &fr, int brick);
-// bound_out[brick] (drr_adjoint_blocks() floats) >= the largest (P^T 1)(v)
-// over the brick's voxels: the back-projection of the all-ones image, a
-// function of the ray table alone, rounded up.
-hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const Frame &fr,
-                                       const void *rays, float *bound_out, hipStream_t s);
 hipError_t launch_drr_adjoint_chain(pcas_dtype dt, const VolDims &v, const Frame &fr, int K,
                                     const void *rays, const void *p, const void *y, double a,
                                     double b, const void *f0, const void *mean, const void *U,

@@ -839,8 +839,7 @@ __device__ __forceinline__ unsigned halo_slot(const int (&l)[3], unsigned base) 
 // Accumulator modes of drr_adjoint_block.
 enum {
     ADJ_ACC64 = 0,        // 64-bit fixed point (drr_adjoint; FP64 gradients)
-    ADJ_ACC32 = 1,        // FP32: 32-bit fixed point (drr_adjoint32 and the fused gradient)
-    ADJ_BOUND_PASS = 2    // all-ones image, per-brick maxima out (32 bits for FP32 rays)
+    ADJ_ACC32 = 1         // FP32: 32-bit fixed point (drr_adjoint32 and the fused gradient)
 };
 
 // hb bounds the summed weight one ray can give one voxel (samples within the
@@ -865,13 +864,12 @@ enum {
 // |r| of the footprint), and every voxel total of the brick, halo slots
 // included, is at most C min(hb * footprint pixels, vb) with vb the
 // brick's weight bound (brick_weight_bound).  ADJ_ACC64: contributions <= FixedRange, totals
-// < 2^62.  ADJ_ACC32 and the bound pass: contributions are rounded to
+// < 2^62.  ADJ_ACC32: contributions are rounded to
 // nearest (errors grow with the square root of the add count instead of
 // its count), and totals plus half a unit per add (at most `adds` of them)
 // stay below 2^31.
 //
-// K = 0: bp is written, or in the bound pass (all-ones image) the largest
-// voxel value of the brick goes to bound_out[brick].  K > 0 (the solver's
+// K = 0: bp is written.  K > 0 (the solver's
 // gradient): bp never leaves the chip; each brick voxel's value is chained
 // at once through the warp Jacobian (Eq. A.8 and the modes, as grad_w does)
 // and the block sums of bp * sum_c U_kc df/dx_c go through the fixed-order
@@ -879,7 +877,6 @@ enum {
 template <typename T, bool FORM_R, int K, int ACCM>
 __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame &fr, int nbx,
                                                   int nby, double hb,
-                                                  float *__restrict__ bound_out,
                                                   const RayRec<T> *__restrict__ rays,
                                                   const T *__restrict__ rp,
                                                   const T *__restrict__ y, double a, double b,
@@ -890,8 +887,6 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                                                   uint32_t *counter, double *__restrict__ g_out,
                                                   int lb, int nb) {
     constexpr bool ACC32 = std::is_same<T, float>::value && ACCM != ADJ_ACC64;
-    constexpr bool COUNT = ACCM == ADJ_BOUND_PASS;   // the bound pass counts its samples
-    static_assert(!(K > 0 && COUNT), "the bound pass has no chain");
     using AccT = typename std::conditional<ACC32, unsigned int, unsigned long long>::type;
     __shared__ AccT acc[ACC_WORDS];
     __shared__ T q_f[ADJ_WAVES][7][QCAP];       // e[3], d[3], scaled dt * r
@@ -993,7 +988,6 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     int tile = wave;
     bool busy = false;
     T e[3] = {0, 0, 0}, d[3] = {0, 0, 0}, cst = (T)0, sh = (T)0, sh_end = (T)0;
-    unsigned nsamp = 0;   // COUNT: samples this lane accumulated
     __syncthreads();   // accumulator cleared
     for (;;) {
         // top up the queue while a whole tile of candidates fits
@@ -1085,7 +1079,6 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                 atomicAdd(pa + ACC_ZP + 1, acc_image<ACC32>(w01b));
                 atomicAdd(pa + ACC_ZP + ACC_YP, acc_image<ACC32>(w11 - w11b));
                 atomicAdd(pa + ACC_ZP + ACC_YP + 1, acc_image<ACC32>(w11b));
-                if constexpr (COUNT) ++nsamp;
                 sh += (T)1;
                 busy = sh <= sh_end;
             }
@@ -1095,35 +1088,12 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
     const double inv_S = Sd > 0.0 ? 1.0 / Sd : 0.0;
     if constexpr (K == 0) {
-        long long vmax = 0;
         for (int t = tid; t < BRICK_X * BRICK_Y * BRICK_Z; t += ADJ_THREADS) {
             const int li = t % BRICK_X, lj = (t / BRICK_X) % BRICK_Y, lk = t / (BRICK_X * BRICK_Y);
             const int i = lo[0] + li, j = lo[1] + lj, k = lo[2] + lk;
             if (i < n0 && j < n1 && k < n2) {
                 const long long v = acc_value(acc[(lk + 1) * ACC_ZP + (lj + 1) * ACC_YP + (li + 1)]);
-                if constexpr (COUNT)
-                    vmax = v > vmax ? v : vmax;
-                else
-                    bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
-            }
-        }
-        if constexpr (COUNT) {
-            // each rounded addend is off by <= 1/2 unit, and a voxel takes at
-            // most one add per sample of the brick (a sample's eight corners
-            // are distinct); 1e-6 more covers the rounding of dt * weight in T
-            double m = wave_max((double)vmax);
-            double ns = wave_sum((double)nsamp);
-            if (lane == 0) red[wave] = m;
-            __syncthreads();
-            for (int q = 0; q < ADJ_WAVES; ++q) m = fmax(m, red[q]);
-            __syncthreads();
-            if (lane == 0) red[wave] = ns;
-            __syncthreads();
-            ns = 0.0;
-            for (int q = 0; q < ADJ_WAVES; ++q) ns += red[q];
-            if (tid == 0) {
-                const double vb_brick = m > 0.0 ? (m + 0.5 * ns + 1.0) * inv_S * (1.0 + 1e-6) : 0.0;
-                bound_out[bid] = __double2float_ru(vb_brick);
+                bp[i + s1 * j + s2 * k] = (T)((double)v * inv_S);
             }
         }
     } else {
@@ -1174,23 +1144,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame f
         a = gate[0];
         b = gate[1];
     }
-    drr_adjoint_block<T, FORM_R, K, ACCM>(vd, fr, nbx, nby, hb, nullptr, rays, rp, y, a, b, bp, f0,
+    drr_adjoint_block<T, FORM_R, K, ACCM>(vd, fr, nbx, nby, hb, rays, rp, y, a, b, bp, f0,
                                           mean, U, w, partials, counter, g_out, blockIdx.x,
                                           gridDim.x);
-}
-
-// The per-brick maxima of the all-ones image's back-projection; its own
-// entry so that traces tell it from drr_adjoint.
-template <typename T>
-__global__ __launch_bounds__(ADJ_THREADS) void k_adjoint_bounds(VolDims vd, Frame fr, int nbx, int nby,
-                                                        double hb,
-                                                        const RayRec<T> *__restrict__ rays,
-                                                        float *__restrict__ bound_out) {
-    const WVec w{};
-    drr_adjoint_block<T, false, 0, ADJ_BOUND_PASS>(vd, fr, nbx, nby, hb, bound_out, rays, nullptr,
-                                                   nullptr, 0.0, 0.0, nullptr, nullptr, nullptr,
-                                                   nullptr, w, nullptr, nullptr, nullptr,
-                                                   blockIdx.x, gridDim.x);
 }
 
 // Several requests' gradients (back-projection + chain) in one launch.
@@ -1200,7 +1156,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint_batch(const AdjJob 
     const int j = job_of(jobs, njobs);
     const AdjJob &J = jobs[j];
     constexpr int ACCM = std::is_same<T, float>::value ? ADJ_ACC32 : ADJ_ACC64;
-    drr_adjoint_block<T, true, K, ACCM>(J.vd, J.fr, J.nbx, J.nby, J.hb, nullptr,
+    drr_adjoint_block<T, true, K, ACCM>(J.vd, J.fr, J.nbx, J.nby, J.hb,
                                         (const RayRec<T> *)J.rays, (const T *)J.p,
                                         (const T *)J.y, J.a, J.b, (T *)nullptr, (const T *)J.f0,
                                         (const T *)J.mean, (const T *)J.U, J.w, J.partials,
@@ -1251,20 +1207,6 @@ hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, 
         if (acc32) return hipErrorInvalidValue;
         launch_adj_bp<double, ADJ_ACC64>(v, fr, rays, r_or_p, y, a, b, bp, s);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_backprojection_bounds(pcas_dtype dt, const VolDims &v, const Frame &fr,
-                                       const void *rays, float *bound_out, hipStream_t s) {
-    const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
-    const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
-    const double hb = ray_weight_bound(v, fr);
-    if (dt == PCAS_F32)
-        hipLaunchKernelGGL((k_adjoint_bounds<float>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0, s,
-                           v, fr, nbx, nby, hb, (const RayRec<float> *)rays, bound_out);
-    else
-        hipLaunchKernelGGL((k_adjoint_bounds<double>), dim3(drr_adjoint_blocks(v)), dim3(ADJ_THREADS), 0,
-                           s, v, fr, nbx, nby, hb, (const RayRec<double> *)rays, bound_out);
     return hipGetLastError();
 }
 

@@ -7,9 +7,10 @@ oracle), so each comparison isolates one operator: the projection (Sec.
 II.A, Eq. 2) and its transpose, the back-projection of the Appendix's
 gradient, in both accumulator widths (64-bit drr_adjoint, and the 32-bit
 accumulation of drr_adjoint32, which the solver's fused FP32 gradient
-uses).  Two gantry angles: the benchmark's, whose rays travel mostly along
-x, and one a quarter turn away, along y, so the projection's slab plan runs
-along each in-plane axis.  Bar: relative L2 <= 1e-5."""
+uses).  Three gantry angles: the benchmark's, whose rays travel mostly along
+x; a quarter turn away, along y, so the projection's slab plan runs along
+each in-plane axis; and 45 degrees, where rays cross both in-plane axes
+alike and the staged boxes are largest.  Bar: relative L2 <= 1e-5."""
 import numpy as np
 import pytest
 
@@ -37,7 +38,8 @@ def clinical():
 
 
 def _angles(c):
-    return {"bench": c.proj.angle, "quarter": c.proj.angle + 0.5 * np.pi}
+    return {"bench": c.proj.angle, "quarter": c.proj.angle + 0.5 * np.pi,
+            "diagonal": 0.25 * np.pi}
 
 
 def _sample_pixels(proj):
@@ -54,7 +56,7 @@ def _sample_pixels(proj):
     return np.unique(np.concatenate([flat, extra]))
 
 
-@pytest.mark.parametrize("which", ["bench", "quarter"])
+@pytest.mark.parametrize("which", ["bench", "quarter", "diagonal"])
 def test_clinical_forward_pixels(clinical, which):
     torch, c, f, _ = clinical
     proj = synth.with_angle(c, _angles(c)[which]).proj
@@ -72,7 +74,7 @@ def test_clinical_forward_pixels(clinical, which):
 
 
 @pytest.mark.parametrize("acc32", [False, True])
-@pytest.mark.parametrize("which", ["bench", "quarter"])
+@pytest.mark.parametrize("which", ["bench", "quarter", "diagonal"])
 def test_clinical_adjoint_whole_volume(clinical, which, acc32):
     torch, c, _, r = clinical
     proj = synth.with_angle(c, _angles(c)[which]).proj

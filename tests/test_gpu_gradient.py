@@ -9,7 +9,7 @@ import oracle as O
 from paper_1102_1712_amd import binding as B
 from paper_1102_1712_amd import synth
 
-from gpu_common import Dev, measured, say, to_dev, torch_or_skip
+from gpu_common import Dev, measured, rel_l2, say, to_dev, to_np, torch_or_skip
 
 pytestmark = pytest.mark.gpu
 
@@ -198,20 +198,13 @@ def test_errors(torch):
         B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, flat, c.w_star)
 
 
-def _brick_max(v):
-    """Largest value per 32 x 16 x 8 brick of a [n3][n2][n1] array (x fastest)."""
-    n2, n1, n0 = v.shape
-    bz, by, bx = -(-n2 // 8), -(-n1 // 16), -(-n0 // 32)
-    pad = np.zeros((bz * 8, by * 16, bx * 32))
-    pad[:n2, :n1, :n0] = v
-    return pad.reshape(bz, 8, by, 16, bx, 32).max(axis=(1, 3, 5)).reshape(-1)
-
-
 @pytest.mark.parametrize("name", ["small", *sorted(STRESS)])
-def test_brick_bounds_cover_oracle_back_projection(torch, name):
-    """The per-brick bounds that size the FP32 gradient's 32-bit accumulators
-    (computed with 32-bit accumulators themselves) cover the oracle's P^T 1
-    in every brick, and are tight: within 1% (the rounding slack)."""
+def test_adjoint32_on_stress_geometries(torch, name):
+    """The 32-bit accumulators are sized per brick by the analytic bound,
+    which is loosest where the depth varies most across a brick (close
+    source, steep cone: up to about 100x the real peak).  Even there P^T 1
+    in 32-bit sums matches the oracle's to 1e-5 relative L2, and no voxel is
+    off by more than 1e-4 of the largest value."""
     if name == "small":
         c = synth.small(dtype="f32", seed=9)
     else:
@@ -219,11 +212,12 @@ def test_brick_bounds_cover_oracle_back_projection(torch, name):
         n, spacing, det, pitch, step = g.pop("n"), g.pop("spacing"), g.pop("det"), g.pop("pitch"), g.pop("step")
         c = synth.make_case(f"stress-{name}", n, spacing, det, pitch, step, 3, "f32", 31, **g)
     d = Dev(c)
-    say("brick bounds", name)
-    got = B.backprojection_brick_bounds(c.vol, c.proj, d.rays).cpu().numpy().astype(np.float64)
-    ref = _brick_max(O.drr_adjoint(c.vol, c.proj, np.ones((c.proj.nv, c.proj.nu))))
-    assert got.shape == ref.shape
-    say("max", ref.max(), "ratio range", (got[ref > 0] / ref[ref > 0]).min(), (got[ref > 0] / ref[ref > 0]).max())
-    # FP32 ray parameters move samples by ~1e-7 against the FP64 oracle's
-    assert np.all(got >= ref * (1.0 - 1e-5) - 1e-6 * ref.max())
-    assert np.all(got <= ref * 1.1 + 1e-6 * ref.max())
+    say("32-bit back-projection of ones", name)
+    ones = torch.ones((c.proj.nv, c.proj.nu), dtype=torch.float32, device="cuda")
+    got = to_np(B.drr_adjoint(c.vol, c.proj, d.rays, ones, acc32=True)).astype(np.float64)
+    ref = O.drr_adjoint(c.vol, c.proj, np.ones((c.proj.nv, c.proj.nu))).reshape(got.shape)
+    err = rel_l2(got, ref)
+    worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    say("rel L2", err, "max |diff| / max", worst)
+    assert err <= 1e-5
+    assert worst <= 1e-4
