@@ -512,7 +512,7 @@ struct Solver {
                                             f0, mean, U, w, partials, nullptr, scal() + 8, s, gate);
         }));
         double out[6 + PCAS_MAX_K];
-        const int nba = drr_adjoint_blocks(vd);
+        const int nba = drr_adjoint_chain_blocks(vd);
         int st = waited([&] {
             return readback_with(out, 6 + K, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
                 return launch_publish_spec(partials, nba, ADJ_THREADS, K, 2.0, src, gate,
@@ -575,7 +575,7 @@ struct Solver {
             }));
         }
         ++n_grads;
-        const int nb = grad_mode == 0 ? drr_forward_blocks(fr.nu, fr.nv) : drr_adjoint_blocks(vd);
+        const int nb = grad_mode == 0 ? drr_forward_blocks(fr.nu, fr.nv) : drr_adjoint_chain_blocks(vd);
         int st = sync_read_sum(g, nb, grad_mode == 0 ? FWD_THREADS : ADJ_THREADS, 2.0, scal() + 8, K);
         if (st) return st;
         for (int k = 0; k < K; ++k)

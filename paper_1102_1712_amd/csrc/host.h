@@ -204,7 +204,7 @@ struct SolveWs {
 
 inline int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
     int m = drr_forward_blocks(p->nu, p->nv);
-    const int nbr = drr_adjoint_blocks(make_dims(v));
+    const int nbr = drr_adjoint_chain_blocks(make_dims(v));
     m = m > nbr ? m : nbr;
     m = m > grad_w_blocks(nvox_of(v)) ? m : grad_w_blocks(nvox_of(v));
     m = m > sums_blocks(npix_of(p)) ? m : sums_blocks(npix_of(p));

@@ -214,6 +214,7 @@ struct AdjJob {                 // back-projection of the residual + Jacobian ch
     uint32_t *counter;
     double *g_out;
     int block0, nblocks;
+    int split;   // blocks per brick (adjoint_chain_split)
 };
 
 // ---- launchers (return the HIP error of the launch) ----------------------
@@ -294,10 +295,15 @@ hipError_t launch_drr_adjoint(pcas_dtype dt, const VolDims &v, const Frame &fr, 
                               bool acc32, hipStream_t s);
 // Back-projection of the residual r = p - a y - b fused with the Jacobian
 // chain: g_out[k] = 2 sum_v (P^T r)(v) sum_c U_kc df/dx_c (bp stays on
-// chip); partials needs drr_adjoint_blocks() * RED_SLOTS doubles, counter
+// chip); partials needs drr_adjoint_chain_blocks() * RED_SLOTS doubles, counter
 // one zeroed uint32 (left zeroed on exit).  FP32 accumulates in 32-bit
 // fixed point, FP64 in 64-bit.
 int drr_adjoint_blocks(const VolDims &v);
+// The fused gradient (back-projection + chain) runs adjoint_chain_split(v)
+// blocks per brick on small grids: drr_adjoint_chain_blocks(v) blocks, each
+// leaving one block partial.
+int adjoint_chain_split(const VolDims &v);
+int drr_adjoint_chain_blocks(const VolDims &v);
 // Bound on sum over rays and samples of the trilinear weight one voxel gets:
 // over the whole grid, and over the voxels of one back-projection brick and
 // its one-voxel halo.

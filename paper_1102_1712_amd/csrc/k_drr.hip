@@ -885,7 +885,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                                                   const T *__restrict__ U, const WVec &w,
                                                   double *__restrict__ partials,
                                                   uint32_t *counter, double *__restrict__ g_out,
-                                                  int lb, int nb) {
+                                                  int lb, int nb, int split) {
     constexpr bool ACC32 = std::is_same<T, float>::value && ACCM != ADJ_ACC64;
     using AccT = typename std::conditional<ACC32, unsigned int, unsigned long long>::type;
     __shared__ AccT acc[ACC_WORDS];
@@ -895,8 +895,11 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
     // Bricks go round-robin over the XCDs in launch order: only bricks inside
     // the x-ray cone carry work, so contiguous per-XCD ranges would leave the
-    // XCDs that hold the outer z-slabs idle.
-    const int bid = lb;
+    // XCDs that hold the outer z-slabs idle.  With K > 0, `split` blocks may
+    // share one brick's footprint rays (block lb: brick lb % bricks, part
+    // lb / bricks): each part chains its own partial sums, and the chain being
+    // linear in P^T r, the parts meet in the block reduction.
+    const int nbricks = nb / split, bid = lb % nbricks, part = lb / nbricks;
     const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
     const int lo[3] = {bx * BRICK_X, by * BRICK_Y, bz * BRICK_Z};
     const int hi[3] = {min(lo[0] + BRICK_X, n0) - 1, min(lo[1] + BRICK_Y, n1) - 1,
@@ -985,7 +988,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
     int(*qs)[QCAP] = q_s[wave];
     const uint64_t lt = (1ull << lane) - 1ull;
     int head = 0, tail = 0;   // wave-uniform ring positions
-    int tile = wave;
+    int tile = part * ADJ_WAVES + wave;
     bool busy = false;
     T e[3] = {0, 0, 0}, d[3] = {0, 0, 0}, cst = (T)0, sh = (T)0, sh_end = (T)0;
     __syncthreads();   // accumulator cleared
@@ -1025,7 +1028,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                 qs[1][q] = s1;
             }
             tail += __popcll(mask);
-            tile += ADJ_WAVES;
+            tile += ADJ_WAVES * split;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1123,7 +1126,7 @@ __device__ __forceinline__ void drr_adjoint_block(const VolDims &vd, const Frame
                     gacc[kk] += (double)fma_t(u[kk][0], j0, fma_t(u[kk][1], j1, u[kk][2] * j2));
             }
         }
-        reduce_or_defer<K>(gacc, partials, counter, g_out, bid, nb, 2.0);
+        reduce_or_defer<K>(gacc, partials, counter, g_out, lb, nb, 2.0);
     }
 }
 
@@ -1138,7 +1141,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame f
                                                      const T *__restrict__ U, WVec w,
                                                      double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ g_out,
-                                                     const double *__restrict__ gate) {
+                                                     const double *__restrict__ gate, int split) {
     if (gate) {   // a speculative gradient: (a, b, go) from the device's decision
         if (gate[2] == 0.0) return;
         a = gate[0];
@@ -1146,7 +1149,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint(VolDims vd, Frame f
     }
     drr_adjoint_block<T, FORM_R, K, ACCM>(vd, fr, nbx, nby, hb, rays, rp, y, a, b, bp, f0,
                                           mean, U, w, partials, counter, g_out, blockIdx.x,
-                                          gridDim.x);
+                                          gridDim.x, split);
 }
 
 // Several requests' gradients (back-projection + chain) in one launch.
@@ -1160,7 +1163,8 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint_batch(const AdjJob 
                                         (const RayRec<T> *)J.rays, (const T *)J.p,
                                         (const T *)J.y, J.a, J.b, (T *)nullptr, (const T *)J.f0,
                                         (const T *)J.mean, (const T *)J.U, J.w, J.partials,
-                                        J.counter, J.g_out, blockIdx.x - J.block0, J.nblocks);
+                                        J.counter, J.g_out, blockIdx.x - J.block0, J.nblocks,
+                                        J.split);
 }
 
 int drr_adjoint_blocks(const VolDims &v) {
@@ -1168,19 +1172,31 @@ int drr_adjoint_blocks(const VolDims &v) {
            ((v.n2 + BRICK_Z - 1) / BRICK_Z);
 }
 
+// Blocks per brick of the fused gradient: enough to give the chip two
+// blocks per CU on small grids (64^3 has 64 bricks), 1 from 512 bricks up.
+int adjoint_chain_split(const VolDims &v) {
+    const int nb = drr_adjoint_blocks(v);
+    int split = 1;
+    while (split < 8 && nb * split < 512) split *= 2;
+    return split;
+}
+
+int drr_adjoint_chain_blocks(const VolDims &v) { return drr_adjoint_blocks(v) * adjoint_chain_split(v); }
+
 template <typename T, bool FORM_R, int K, int ACCM>
 static void launch_adj(const VolDims &v, const Frame &fr, const void *rays, const void *r_or_p,
                        const void *y, double a, double b, void *bp, const void *f0,
                        const void *mean, const void *U, const WVec &w, double *partials,
                        uint32_t *counter, double *g_out, hipStream_t s,
                        const double *gate = nullptr) {
+    const int split = K > 0 ? adjoint_chain_split(v) : 1;   // bp is written whole: one block per brick
     const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X;
     const int nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
-    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K, ACCM>), dim3(drr_adjoint_blocks(v)),
+    hipLaunchKernelGGL((k_drr_adjoint<T, FORM_R, K, ACCM>), dim3(drr_adjoint_blocks(v) * split),
                        dim3(ADJ_THREADS), 0, s, v, fr, nbx, nby, ray_weight_bound(v, fr),
                        (const RayRec<T> *)rays, (const T *)r_or_p, (const T *)y, a, b, (T *)bp,
                        (const T *)f0, (const T *)mean, (const T *)U, w, partials, counter, g_out,
-                       gate);
+                       gate, split);
 }
 
 template <typename T, int ACCM>
@@ -1261,7 +1277,8 @@ AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, 
     J.counter = counter;
     J.g_out = g_out;
     J.block0 = 0;
-    J.nblocks = drr_adjoint_blocks(v);
+    J.split = adjoint_chain_split(v);
+    J.nblocks = drr_adjoint_blocks(v) * J.split;
     return J;
 }
 
