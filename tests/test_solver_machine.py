@@ -32,6 +32,10 @@ GRAD = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.c_int, cty
                         ctypes.c_double, ctypes.POINTER(ctypes.c_double))
 
 
+RULE = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int)
+
+
 @pytest.fixture(scope="module")
 def harness(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("harness") / "libsolver_harness.so")
@@ -43,6 +47,10 @@ def harness(tmp_path_factory):
     lib = ctypes.CDLL(out)
     lib.harness_noise_rel.restype = ctypes.c_double
     lib.harness_noise_rel.argtypes = [ctypes.c_double] * 8
+    lib.harness_solve_rules.restype = ctypes.c_int
+    lib.harness_solve_rules.argtypes = [ctypes.POINTER(B.Opts), ctypes.c_int, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_double), EVAL, GRAD, RULE,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(B.Report)]
     lib.harness_solve.restype = ctypes.c_int
     lib.harness_solve.argtypes = [ctypes.POINTER(B.Opts), ctypes.c_int, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_double), EVAL, GRAD,
@@ -379,3 +387,75 @@ def test_spec_solvers_reach_the_oracle_minimiser(oracle_lib):
         w, rep = solver(prob, np.zeros(c.K))
         assert rep.status == S.STOP_CONVERGED
         assert np.linalg.norm(w - w_ref) <= 1e-6 * np.linalg.norm(w_ref)
+
+
+def _rule_says(mode, extrap, thr, phi, gd, t, J):
+    """The gradient rule of an evaluation as solver.h states it (GRAD_NEVER,
+    GRAD_ALWAYS, GRAD_IF_ARMIJO, GRAD_IF_BELOW), restated from its comment."""
+    if J != J:
+        return False
+    if mode == 1:
+        return True
+    if mode == 2:
+        if not J <= thr:
+            return False
+        if not extrap:
+            return True
+        tq = -gd * t * t / (2.0 * (J - phi - gd * t))
+        return not tq > 2.0 * t
+    if mode == 3:
+        return J < thr
+    return False
+
+
+def _rule_cases():
+    rng = np.random.default_rng(77)
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    A = Q @ np.diag([1.0, 30.0, 1e3]) @ Q.T
+    return {"quadratic": (_Quadratic(A, 3.0 * rng.normal(size=3)), 3, 1e-14),
+            "quadratic_band": (_Quadratic(A, 3.0 * rng.normal(size=3)), 3, 1e-6)}
+
+
+@pytest.mark.parametrize("case", ["quadratic", "quadratic_band", "small"])
+@pytest.mark.parametrize("method,extrap,polish", [(1, 10.0, 0), (1, 10.0, 1), (1, 0.0, 1),
+                                                  (2, 10.0, 1), (2, 0.0, 0)])
+def test_gradient_rule_predicts_the_machine(harness, oracle_lib, case, method, extrap, polish):
+    """Speculative gradients rest on this: the rule the machine states with
+    each evaluation, applied to the J it is then fed, says exactly whether
+    its next request is the gradient at that point, fit and slot."""
+    if case == "small":
+        c = synth.small(seed=18)
+        y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
+        prob, K, ftol = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y), c.K, 1e-12
+    else:
+        prob, K, ftol = _rule_cases()[case]
+    o = _opts(method, ls_extrap=extrap, polish=polish, ftol_rel=ftol, gtol_rel=1e-10)
+    slots, seen = {}, []
+
+    def ev(wp, slot, fixed, ab, a_out, b_out):
+        w = np.array([wp[k] for k in range(K)]) if wp else slots[slot]
+        phi, a, b, _ = prob.objective(w)
+        slots[slot] = w
+        a_out[0], b_out[0] = a, b
+        return phi
+
+    def gr(wp, slot, a, b, g_out):
+        w = np.array([wp[k] for k in range(K)])
+        assert np.array_equal(slots[slot], w)
+        _, _, _, r = prob.objective(w)
+        g = prob.gradient(w, r)
+        for k in range(K):
+            g_out[k] = g[k]
+
+    def rule(mode, ext, thr, phi, gd, t, J, nxt):
+        seen.append((_rule_says(mode, ext, thr, phi, gd, t, J), bool(nxt), mode))
+
+    w_out = (ctypes.c_double * K)()
+    rep = B.Report()
+    cbs = EVAL(ev), GRAD(gr), RULE(rule)
+    assert harness.harness_solve_rules(ctypes.byref(o), K, ftol, (ctypes.c_double * K)(*np.zeros(K)),
+                                       *cbs, w_out, ctypes.byref(rep)) == 0
+    assert seen and all(said == nxt for said, nxt, _ in seen), seen
+    assert any(nxt for _, nxt, _ in seen)
+    # the start evaluation always says so
+    assert seen[0][2] == 1 and seen[0][1]
