@@ -433,9 +433,10 @@ def serve_mode(args) -> int:
                    np.linalg.norm(arrivals[dn.index].w_true) for dn in done if dn.model == m]
             out[label][f"model{m}_w_rel_err_vs_planted_median"] = float(np.median(err))
             out[label][f"model{m}_w_rel_err_vs_planted_max"] = float(np.max(err))
-    # small requests only: where one request leaves the GPU idle between
-    # launches, batching many pays most
-    small = [a for a in arrivals if a.model == 0]
+    # small requests only, all submitted at once (a burst, so that the
+    # server's throughput and not the arrival process sets the rate): where
+    # one request leaves the GPU idle between launches, batching pays most
+    small = [dataclasses.replace(a, t=0.0) for a in arrivals if a.model == 0]
     srv, _ = new_server()
     SV.run(srv, small[:2], opts, Ks, warm=False)
     done = SV.run(srv, small, opts, Ks, warm=False)
