@@ -426,7 +426,7 @@ struct Solver {
         double out[3];
         int st;
         if (speculate && rule && w && rule->mode != GRAD_NEVER) {
-            HIPCHK(launch_spec_decide_jab(scal() + 3, *rule, scal() + 32, s));
+            HIPCHK(launch_spec_decide_jab(scal() + 3, *rule, scal() + SCAL_GATE, s));
             st = gated_gradient(w, slot, scal() + 3, out);
         } else {
             st = sync_read(out, scal() + 3, 3);
@@ -479,7 +479,7 @@ struct Solver {
         int st;
         if (speculate && rule && rule->mode != GRAD_NEVER) {
             HIPCHK(launch_spec_decide((const double *)(ws + L.partials), nbf, FWD_THREADS, ff, *rule,
-                                      scal(), scal() + 32, s));
+                                      scal(), scal() + SCAL_GATE, s));
             st = gated_gradient(w, slot, scal(), mo);
         } else
             st = sync_read_sum(mo, nbf, FWD_THREADS, 1.0, scal(), 3);
@@ -504,7 +504,7 @@ struct Solver {
     // leaves the gradient at (w, a, b of the gate) for gradient() to take.
     int gated_gradient(const double *w, int slot, const double *src, double *head) {
         double *partials = (double *)(ws + L.partials);
-        double *gate = scal() + 32;
+        double *gate = scal() + SCAL_GATE;
         const unsigned both = (1u << PCAS_K_ADJOINT) | (1u << PCAS_K_SPEC_SKIP);
         const size_t mark = prof.pending.size();
         HIPCHK(timed(prof.mask >> PCAS_K_ADJOINT & 1u ? PCAS_K_ADJOINT : PCAS_K_SPEC_SKIP, [&] {

@@ -215,6 +215,7 @@ struct AdjJob {                 // back-projection of the residual + Jacobian ch
     double *g_out;
     int block0, nblocks;
     int split;   // blocks per brick (adjoint_chain_split)
+    const double *gate = nullptr;   // speculative: (a, b, go) in place of a, b; go = 0 exits
 };
 
 // ---- launchers (return the HIP error of the launch) ----------------------
@@ -239,6 +240,23 @@ hipError_t launch_publish(const double *src, double *dst_host, int count, uint32
 hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
                               const FitArgs &fit, const GradRule &rule, double *mo, double *gate,
                               hipStream_t s);
+// Scalar slot of a solve's speculative gate (a, b, go), inside the scalars
+// the serving loop reads back per request.
+constexpr int SCAL_GATE = 28;
+// Several requests' gates in one launch (one FWD_THREADS-wide block each):
+// from the moment partials of an FP32 evaluation (partials != null, summed
+// as launch_spec_decide does, written to mo) or from an FP64 evaluation's
+// (J, a, b) at jab.
+struct SpecJob {
+    const double *partials = nullptr;
+    const double *jab = nullptr;
+    int nblocks = 0;
+    FitArgs fit{};
+    GradRule rule{};
+    double *mo = nullptr;
+    double *gate = nullptr;
+};
+hipError_t launch_spec_decide_batch(const SpecJob *jobs, int njobs, hipStream_t s);
 // gate from (J, a, b) already on the device (the two-pass residual's).
 hipError_t launch_spec_decide_jab(const double *jab, const GradRule &rule, double *gate,
                                   hipStream_t s);
@@ -381,6 +399,7 @@ struct SumJob {
     double *out = nullptr;
     double scale = 1.0;
     int nblocks = 0, width = 0, ns = 0, offset = 0;
+    const double *gate = nullptr;   // a speculative gradient's (a, b, go): no sum when go = 0
 };
 // dst[b * count + t] = src[b][t] for n requests (one 512-thread block each),
 // after finishing sums[b] when sums is given and sums[b].ns > 0.

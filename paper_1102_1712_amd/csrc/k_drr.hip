@@ -1159,9 +1159,15 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_drr_adjoint_batch(const AdjJob 
     const int j = job_of(jobs, njobs);
     const AdjJob &J = jobs[j];
     constexpr int ACCM = std::is_same<T, float>::value ? ADJ_ACC32 : ADJ_ACC64;
+    double a = J.a, b = J.b;
+    if (J.gate) {   // a speculative gradient: (a, b, go) from the request's gate
+        if (J.gate[2] == 0.0) return;
+        a = J.gate[0];
+        b = J.gate[1];
+    }
     drr_adjoint_block<T, true, K, ACCM>(J.vd, J.fr, J.nbx, J.nby, J.hb,
                                         (const RayRec<T> *)J.rays, (const T *)J.p,
-                                        (const T *)J.y, J.a, J.b, (T *)nullptr, (const T *)J.f0,
+                                        (const T *)J.y, a, b, (T *)nullptr, (const T *)J.f0,
                                         (const T *)J.mean, (const T *)J.U, J.w, J.partials,
                                         J.counter, J.g_out, blockIdx.x - J.block0, J.nblocks,
                                         J.split);

@@ -123,6 +123,34 @@ hipError_t launch_spec_decide_jab(const double *jab, const GradRule &rule, doubl
     return hipGetLastError();
 }
 
+// The serving loop's gates, one block per request (see SpecJob).
+__global__ __launch_bounds__(FWD_THREADS) void k_spec_decide_batch(const SpecJob *__restrict__ jobs) {
+    const SpecJob J = jobs[blockIdx.x];
+    double tot[3] = {0.0, 0.0, 0.0};
+    if (J.partials) sum_partials<3, false>(J.partials, J.nblocks, 1.0, FWD_THREADS, tot);
+    if (threadIdx.x != 0) return;
+    double Jv, a, b, kappa = 0.0;
+    if (J.partials) {
+        objective_from_moments(tot, J.fit, &Jv, &a, &b, &kappa);
+        for (int j = 0; j < 3; ++j) J.mo[j] = tot[j];
+    } else {
+        Jv = J.jab[0];
+        a = J.jab[1];
+        b = J.jab[2];
+    }
+    const bool go = isfinite(a) && isfinite(b) && isfinite(Jv) && kappa <= MOMENT_KAPPA_MAX &&
+                    grad_follows(J.rule, Jv);
+    J.gate[0] = a;
+    J.gate[1] = b;
+    J.gate[2] = go ? 1.0 : 0.0;
+}
+
+hipError_t launch_spec_decide_batch(const SpecJob *jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spec_decide_batch, dim3(njobs), dim3(FWD_THREADS), 0, s, jobs);
+    return hipGetLastError();
+}
+
 hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
                               const FitArgs &fit, const GradRule &rule, double *mo, double *gate,
                               hipStream_t s) {

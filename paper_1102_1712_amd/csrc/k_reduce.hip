@@ -169,7 +169,7 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather_scalars(const double 
     __shared__ double tot_s[RED_SLOTS];
     const int b = blockIdx.x;
     int lo = 0, hi = 0;
-    if (sums && sums[b].ns > 0) {   // uniform in the block
+    if (sums && sums[b].ns > 0 && (!sums[b].gate || sums[b].gate[2] != 0.0)) {   // uniform
         const SumJob J = sums[b];
         switch (J.ns) {
         case 1: finish_sum<1>(J, tot_s); break;

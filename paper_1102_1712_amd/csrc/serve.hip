@@ -66,6 +66,12 @@ struct Request {
     int mom_slot = -1;
     double mom_a0 = 0.0, mom_b0 = 0.0;
     FitArgs eval_fit{};   // the pending FP32 evaluation's fit and reference
+    // a speculative gradient launched behind this pass's evaluation (as in a
+    // solve alone): its point and slot, and how many were taken
+    bool spec = false;
+    int spec_slot = 0;
+    double spec_w[PCAS_MAX_K] = {0};
+    int spec_grads = 0;
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -145,7 +151,8 @@ namespace {
 
 size_t table_bytes(int max_active) {
     const size_t per = sizeof(WarpJob) + sizeof(FwdJob) + sizeof(ResJob) + sizeof(AdjJob) +
-                       sizeof(double *) + sizeof(SumJob) + GATHER * sizeof(double);
+                       sizeof(SpecJob) + sizeof(double *) + sizeof(SumJob) +
+                       GATHER * sizeof(double);
     return align256(per * (size_t)max_active + 4096);
 }
 
@@ -155,6 +162,7 @@ size_t request_bytes(const Model &md, const pcas_proj *proj) {
 
 void finish_request(pcas_server *S, Request *r, int status) {
     r->status = status;
+    r->rep.spec_grads = r->spec_grads;
     r->phase = PH_DONE;
     S->pool.release(r->off, r->L.total);
     r->ws = nullptr;
@@ -299,6 +307,46 @@ void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done,
     }
 }
 
+// Queues the gradient at an evaluation's point behind it, gated by the
+// request's gate (a, b, go) at scal()[SCAL_GATE]: the same job a gradient pass
+// would run, and its sum in the gather (skipped when the gate is shut).
+template <class Groups_>
+void speculate(const Model &md, Request *r, const SolveOp &op, Groups_ &adjs, SumJob &sj) {
+    AdjJob aj = make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot), r->y, 0.0,
+                             0.0, md.f0, md.mean, md.U, op.w, r->partials(), nullptr, r->scal() + 8);
+    aj.gate = r->scal() + SCAL_GATE;
+    adjs.add({md.dt, md.K}, aj);
+    sj = SumJob{};
+    sj.partials = r->partials();
+    sj.out = r->scal() + 8;
+    sj.scale = 2.0;
+    sj.nblocks = aj.nblocks;
+    sj.width = ADJ_THREADS;
+    sj.ns = md.K;
+    sj.offset = 8;
+    sj.gate = r->scal() + SCAL_GATE;
+    r->spec = true;
+    r->spec_slot = op.slot;
+    for (int k = 0; k < md.K; ++k) r->spec_w[k] = op.w[k];
+}
+
+// After an evaluation's result: when the gate opened and the machine asks
+// for the gradient at exactly that point, fit and slot, feed it the one
+// that came back with the evaluation.
+void take_speculative_gradient(pcas_server *S, Request *r, const double *sc, int32_t *n_done) {
+    if (!r->spec) return;
+    r->spec = false;
+    if (r->phase != PH_RUN || sc[SCAL_GATE + 2] == 0.0) return;
+    const SolveOp &op = r->m.op();
+    const int K = S->models[r->model].K;
+    if (op.kind != OP_GRAD || op.slot != r->spec_slot ||
+        memcmp(op.w, r->spec_w, K * sizeof(double)) || memcmp(&op.ab[0], &sc[SCAL_GATE], sizeof(double)) ||
+        memcmp(&op.ab[1], &sc[SCAL_GATE + 1], sizeof(double)))
+        return;
+    ++r->spec_grads;
+    advance(S, r, sc, n_done);   // OP_GRAD: the gradient at sc[8..]
+}
+
 // One pass: the next operation of every request in `set`, batched by kind
 // (one launch per kind, dtype and K or slab axis), one read-back, and every
 // machine advanced.  Finished requests leave with phase PH_DONE.
@@ -311,6 +359,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     Groups<FwdJob, DK> fwds;
     Groups<ResJob, int> ress;
     Groups<AdjJob, DK> adjs;
+    std::vector<SpecJob> specs;
     std::vector<Request *> locates, refused;
     // FP32 projections and all gradients leave block partials only; the
     // gather finishes each request's sum (same order as a solve alone)
@@ -365,6 +414,18 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             r->mom_a0 = ff.a0;
             r->mom_b0 = ff.b0;
             r->eval_fit = ff;
+            r->spec = false;
+            if (defer && r->opts.speculate && op.next_grad.mode != GRAD_NEVER) {
+                SpecJob sp;
+                sp.partials = r->partials();
+                sp.nblocks = fj.nblocks;
+                sp.fit = ff;
+                sp.rule = op.next_grad;
+                sp.mo = r->scal();
+                sp.gate = r->scal() + SCAL_GATE;
+                specs.push_back(sp);
+                speculate(md, r, op, adjs, sums[ri]);
+            }
         }
         if ((op.kind == OP_EVAL && md.dt != PCAS_F32) || op.kind == OP_RESID) {
             FitArgs fa = fit_of(*r, op.fixed_ab ? op.ab : nullptr);
@@ -377,6 +438,14 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                 fa.b0 = r->mom_b0;
             }
             ress.add(md.dt, res_job(*r, op.slot, fa));
+            if (op.kind == OP_EVAL && r->opts.speculate && op.next_grad.mode != GRAD_NEVER) {
+                SpecJob sp;   // FP64: the gate reads the two-pass residual's (J, a, b)
+                sp.jab = r->scal() + 3;
+                sp.rule = op.next_grad;
+                sp.gate = r->scal() + SCAL_GATE;
+                specs.push_back(sp);
+                speculate(md, r, op, adjs, sums[ri]);
+            }
         } else if (op.kind == OP_GRAD) {
             const AdjJob aj = make_adj_job(md.vd, r->fr, md.K, r->ws + r->L.rays, r->proj_slot(op.slot),
                                            r->y, op.ab[0], op.ab[1], md.f0, md.mean, md.U, op.w,
@@ -409,6 +478,8 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     ress.emit((ResJob *)(h + o_r));
     const size_t o_a = carve(adjs.items.size() * sizeof(AdjJob));
     adjs.emit((AdjJob *)(h + o_a));
+    const size_t o_sp = carve(specs.size() * sizeof(SpecJob));
+    for (size_t i = 0; i < specs.size(); ++i) ((SpecJob *)(h + o_sp))[i] = specs[i];
     const size_t o_p = carve(na * sizeof(double *));
     for (int i = 0; i < na; ++i) ((const double **)(h + o_p))[i] = set[i]->scal();
     const size_t o_s = carve(na * sizeof(SumJob));
@@ -427,6 +498,8 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     for (auto &g : ress.groups)
         HIPCHK(launch_residual_batch((pcas_dtype)g.key, (const ResJob *)(d + o_r) + g.first,
                                      g.count, g.blocks, S->s));
+    // the gates of the speculative gradients, after the evaluations they read
+    HIPCHK(launch_spec_decide_batch((const SpecJob *)(d + o_sp), (int)specs.size(), S->s));
     for (auto &g : adjs.groups)
         HIPCHK(launch_drr_adjoint_chain_batch((pcas_dtype)g.key.first, g.key.second,
                                               (const AdjJob *)(d + o_a) + g.first, g.count,
@@ -461,13 +534,16 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             if (isfinite(jab[1]) && isfinite(jab[2]) && !(kappa <= MOMENT_KAPPA_MAX)) {
                 r->eval_fit.a = jab[1];   // the fit found, for the two-pass sum
                 r->eval_fit.b = jab[2];
+                r->spec = false;          // its gate stayed shut (kappa)
                 redo.push_back(r);
                 continue;
             }
             advance(S, r, sc, n_done, jab);
+            take_speculative_gradient(S, r, sc, n_done);
             continue;
         }
         advance(S, r, sc, n_done);
+        take_speculative_gradient(S, r, sc, n_done);
     }
     if (redo.empty()) return PCAS_OK;
 

@@ -100,6 +100,13 @@ def test_batched_results_equal_alone(torch, share):
         assert np.array_equal(w, w1), (m, w, w1)
         for key in ("status", "iters", "n_fevals", "n_grads", "J", "a", "b", "gnorm", "tumour_mm"):
             assert rep[key] == rep1[key], key
+        # CG and BFGS requests take gradients launched behind their
+        # evaluations, as a solve alone does (the Appendix algorithm never)
+        if o.method in (1, 2):
+            assert rep["n_grads"] - 2 <= rep["spec_grads"] <= rep["n_grads"], (rep["spec_grads"], rep["n_grads"])
+            assert rep["spec_grads"] == rep1["spec_grads"]
+        else:
+            assert rep["spec_grads"] == 0
     srv.close()
 
 
