@@ -454,7 +454,8 @@ struct Solver {
                  double *b, const GradRule *rule = nullptr) {
         spec.valid = false;
         HIPCHK(timed(PCAS_K_WARP, [&] {
-            return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s);
+            return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s,
+                                   (const uint8_t *)(ws + L.live));
         }));
         const bool one_pass = dt == PCAS_F32;
         FitArgs ff = fit_args(ab_fixed);
@@ -609,6 +610,7 @@ struct Solver {
         prof.mask = profile;
         HIPCHK(launch_fill_u32(counters(), 64, 0u, s));
         HIPCHK(timed(PCAS_K_RAYS, [&] { return launch_ray_table(dt, vd, fr, ws + L.rays, s); }));
+        HIPCHK(launch_brick_live(vd, fr, (uint8_t *)(ws + L.live), s));
         // sums of the measured image: (sum y, sum y^2, ., ., .)
         HIPCHK(timed(PCAS_K_YSUMS, [&] {
             return launch_pair_sums(dt, M, y, y, (double *)(ws + L.partials), &counters()[2],

@@ -199,7 +199,7 @@ inline int readback_sum(double *host, const double *partials, int nblocks, int t
 // ---- workspace layouts ---------------------------------------------------
 
 struct SolveWs {
-    size_t rays, f, p, p2, vol2, partials, counters, scalars, total;   // vol2: bp, or the J_k
+    size_t rays, f, p, p2, vol2, partials, counters, scalars, live, total;   // vol2: bp, or the J_k
 };
 
 inline int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
@@ -226,6 +226,7 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
     L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
     L.counters = off; off += 256;
     L.scalars = off; off += align256(64 * sizeof(double));
+    L.live = off; off += align256((size_t)drr_adjoint_blocks(make_dims(v)));   // brick liveness
     L.total = off;
     return L;
 }

@@ -177,6 +177,7 @@ struct WarpJob {
     WVec w;
     void *f;
     int block0, nblocks;
+    const uint8_t *live = nullptr;   // brick liveness (launch_brick_live), or every voxel
 };
 struct FwdJob {                 // projection with the fit sums (FWD_SUMS)
     VolDims vd;
@@ -272,9 +273,16 @@ hipError_t launch_pca_dvf(pcas_dtype dt, int64_t N, int K, const void *mean, con
                           const double *w, void *dvf, hipStream_t s);
 hipError_t launch_warp_trilinear(pcas_dtype dt, const VolDims &v, const void *f0, const void *dvf,
                                  void *f, hipStream_t s);
+// With live (launch_brick_live's flags), only the voxels of live bricks are
+// written: the projection of that geometry reads no other.
 hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f0,
                            const void *mean, const void *U, const double *w, void *f,
-                           hipStream_t s);
+                           hipStream_t s, const uint8_t *live = nullptr);
+// live[brick] = 1 unless the projection of the brick's box with its one-voxel
+// halo (back-projection bricks, x fastest) misses the detector by more than
+// a pixel: no ray of the projection reaches a voxel of, or a sample cell
+// touching, a dead brick.
+hipError_t launch_brick_live(const VolDims &v, const Frame &fr, uint8_t *live, hipStream_t s);
 
 // Forward projection.  If sums != nullptr also reduces, with r0 = p - a0 y -
 // b0 for fit->a0, fit->b0 (zero when fit is null), (sum r0, sum r0*y,

@@ -1178,6 +1178,54 @@ int drr_adjoint_blocks(const VolDims &v) {
            ((v.n2 + BRICK_Z - 1) / BRICK_Z);
 }
 
+// Liveness of the bricks for one projection: the brick's box with its
+// one-voxel halo (which holds every sample whose cell touches a voxel of the
+// brick), clipped to the grid and projected through its eight corners, in
+// detector pixel coordinates as the back-projection's footprint.  The image
+// of a box in front of the source lies in the convex hull of its corners'
+// images, so a box whose corner images all fall more than a pixel off the
+// detector meets no ray; a corner at or behind the source's plane keeps the
+// brick live.
+__global__ __launch_bounds__(256) void k_brick_live(VolDims vd, Frame fr, uint8_t *__restrict__ live) {
+    const int nbx = (vd.n0 + BRICK_X - 1) / BRICK_X, nby = (vd.n1 + BRICK_Y - 1) / BRICK_Y;
+    const int nbz = (vd.n2 + BRICK_Z - 1) / BRICK_Z;
+    const int bid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bid >= nbx * nby * nbz) return;
+    const int b[3] = {bid % nbx, (bid / nbx) % nby, bid / (nbx * nby)};
+    const int ext[3] = {BRICK_X, BRICK_Y, BRICK_Z}, n[3] = {vd.n0, vd.n1, vd.n2};
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    bool behind = false;
+    for (int corner = 0; corner < 8; ++corner) {
+        double rel[3];
+        for (int c = 0; c < 3; ++c) {
+            const int lo = b[c] * ext[c], hi = min(lo + ext[c], n[c]) - 1;
+            const int idx = ((corner >> c) & 1) ? min(hi + 1, n[c] - 1) : max(lo - 1, 0);
+            rel[c] = vd.origin[c] + idx * vd.spacing[c] - fr.src[c];
+        }
+        const double depth = rel[0] * fr.en[0] + rel[1] * fr.en[1] + rel[2] * fr.en[2];
+        if (!(depth > 0.0)) {
+            behind = true;
+            continue;
+        }
+        const double pu = (rel[0] * fr.eu[0] + rel[1] * fr.eu[1] + rel[2] * fr.eu[2]) * fr.sid / depth;
+        const double pv = (rel[0] * fr.ev[0] + rel[1] * fr.ev[1] + rel[2] * fr.ev[2]) * fr.sid / depth;
+        const double u = (pu - fr.offset_u) / fr.pitch_u + 0.5 * (fr.nu - 1);
+        const double v = (pv - fr.offset_v) / fr.pitch_v + 0.5 * (fr.nv - 1);
+        umin = fmin(umin, u);
+        umax = fmax(umax, u);
+        vmin = fmin(vmin, v);
+        vmax = fmax(vmax, v);
+    }
+    const bool hit = umax >= -1.0 && umin <= (double)fr.nu && vmax >= -1.0 && vmin <= (double)fr.nv;
+    live[bid] = (behind || hit) ? 1 : 0;
+}
+
+hipError_t launch_brick_live(const VolDims &v, const Frame &fr, uint8_t *live, hipStream_t s) {
+    const int nb = drr_adjoint_blocks(v);
+    hipLaunchKernelGGL(k_brick_live, dim3((nb + 255) / 256), dim3(256), 0, s, v, fr, live);
+    return hipGetLastError();
+}
+
 // Blocks per brick of the fused gradient: enough to give the chip two
 // blocks per CU on small grids (64^3 has 64 bricks), 1 from 512 bricks up.
 int adjoint_chain_split(const VolDims &v) {

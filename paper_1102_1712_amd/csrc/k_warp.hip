@@ -85,7 +85,8 @@ template <typename T, int K>
 __device__ __forceinline__ void warp_pca_block(const VolDims &vd, const T *__restrict__ f0,
                                                const T *__restrict__ mean,
                                                const T *__restrict__ U, const WVec &w,
-                                               T *__restrict__ f, int lb, int nb) {
+                                               T *__restrict__ f, int lb, int nb,
+                                               const uint8_t *__restrict__ live) {
     // 32-bit index arithmetic (volumes are limited to 2^31 voxels); mean and
     // U are read once, so their loads are non-temporal and leave the caches
     // to the f0 neighbourhoods that neighbouring lanes share
@@ -98,6 +99,10 @@ __device__ __forceinline__ void warp_pca_block(const VolDims &vd, const T *__res
     const int i = v32 - (int)q * vd.n0;
     const int k = (int)(q / (unsigned)vd.n1);
     const int j = (int)q - k * vd.n1;
+    if (live) {   // voxels of bricks no ray reaches are never projected
+        const int nbx = (vd.n0 + BRICK_X - 1) / BRICK_X, nby = (vd.n1 + BRICK_Y - 1) / BRICK_Y;
+        if (!live[(k / BRICK_Z * nby + j / BRICK_Y) * nbx + i / BRICK_X]) return;
+    }
     T x[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -114,8 +119,9 @@ template <typename T, int K>
 __global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restrict__ f0,
                                                   const T *__restrict__ mean,
                                                   const T *__restrict__ U, WVec w,
-                                                  T *__restrict__ f) {
-    warp_pca_block<T, K>(vd, f0, mean, U, w, f, blockIdx.x, gridDim.x);
+                                                  T *__restrict__ f,
+                                                  const uint8_t *__restrict__ live) {
+    warp_pca_block<T, K>(vd, f0, mean, U, w, f, blockIdx.x, gridDim.x, live);
 }
 
 // Several requests' warps in one launch (jobs sorted by block0).
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(256) void k_warp_pca_batch(const WarpJob *__restric
     const int j = job_of(jobs, njobs);
     const WarpJob &J = jobs[j];
     warp_pca_block<T, K>(J.vd, (const T *)J.f0, (const T *)J.mean, (const T *)J.U, J.w, (T *)J.f,
-                         blockIdx.x - J.block0, J.nblocks);
+                         blockIdx.x - J.block0, J.nblocks, J.live);
 }
 
 namespace {
@@ -139,11 +145,11 @@ hipError_t pca_dvf_k(int64_t N, const void *mean, const void *U, const WVec &w, 
 }
 template <typename T, int K>
 hipError_t warp_pca_k(const VolDims &v, const void *f0, const void *mean, const void *U,
-                      const WVec &w, void *f, hipStream_t s) {
+                      const WVec &w, void *f, hipStream_t s, const uint8_t *live) {
     const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
     dim3 grid((unsigned)((N + 255) / 256)), block(256);
     hipLaunchKernelGGL((k_warp_pca<T, K>), grid, block, 0, s, v, (const T *)f0, (const T *)mean,
-                       (const T *)U, w, (T *)f);
+                       (const T *)U, w, (T *)f, live);
     return hipGetLastError();
 }
 WVec make_w(const double *w, int K) {
@@ -217,14 +223,14 @@ hipError_t launch_warp_trilinear(pcas_dtype dt, const VolDims &v, const void *f0
 
 hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f0,
                            const void *mean, const void *U, const double *w, void *f,
-                           hipStream_t s) {
+                           hipStream_t s, const uint8_t *live) {
     const WVec wv = make_w(w, K);
     if (dt == PCAS_F32) {
-#define CALL(KK) warp_pca_k<float, KK>(v, f0, mean, U, wv, f, s)
+#define CALL(KK) warp_pca_k<float, KK>(v, f0, mean, U, wv, f, s, live)
         PCAS_K_SWITCH(K, CALL)
 #undef CALL
     }
-#define CALL(KK) warp_pca_k<double, KK>(v, f0, mean, U, wv, f, s)
+#define CALL(KK) warp_pca_k<double, KK>(v, f0, mean, U, wv, f, s, live)
     PCAS_K_SWITCH(K, CALL)
 #undef CALL
 }

@@ -175,6 +175,7 @@ int admit(pcas_server *S, Request *r) {
     r->ws = S->arena + S->pool_base + r->off;
     HIPCHK(launch_fill_u32(r->counters(), 64, 0u, S->s));
     HIPCHK(launch_ray_table(md.dt, md.vd, r->fr, r->ws + r->L.rays, S->s));
+    HIPCHK(launch_brick_live(md.vd, r->fr, (uint8_t *)(r->ws + r->L.live), S->s));
     HIPCHK(launch_pair_sums(md.dt, r->M, r->y, r->y, r->partials(), &r->counters()[2],
                             r->scal() + 16, S->s));
     r->phase = PH_PREPARE;
@@ -384,6 +385,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             wj.f = r->ws + r->L.f;
             wj.block0 = 0;
             wj.nblocks = warp_blocks(nvox_of(&md.vol));
+            wj.live = (const uint8_t *)(r->ws + r->L.live);
             warps.add({md.dt, md.K}, wj);
             // the objective as a solve alone forms it: FP32 from moments about
             // the reference fit in the projection's last block, FP64 by the
