@@ -141,6 +141,19 @@ def samples_per_drr(rays, dtype: str) -> int:
     return int(n.astype(np.int64).sum())
 
 
+def reached_voxels(case, dev) -> int:
+    """Voxels that at least one projection sample touches (P^T 1 > 0): the
+    gradient's chain has work only there, since it skips voxels where the
+    back-projected residual is zero."""
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+
+    ones = torch.ones((case.proj.nv, case.proj.nu), dtype=dev["f0"].dtype, device="cuda")
+    bp = B.drr_adjoint(case.vol, case.proj, dev["rays"], ones)
+    return int((bp > 0).sum().item())
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -817,6 +830,9 @@ def main() -> int:
     if args.mode == "resolution":
         return resolution_mode(case, dev, dt, args)
     S = samples_per_drr(dev["rays"], case.dtype)
+    # voxels the solve's warp writes (live bricks) and the chain works on
+    live = B.live_voxels(case.vol, case.proj)
+    reach = reached_voxels(case, dev)
     ws = torch.empty(B.solve_projection_workspace(case.vol, case.proj, case.K, dt),
                      dtype=torch.uint8, device="cuda")
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
@@ -869,14 +885,16 @@ def main() -> int:
     es = 4 if case.dtype == "f32" else 8
     K = case.K
     avg = {k: (kms[k] / kn[k] if kn.get(k) else None) for k in kms}
-    # algorithmic bytes per launch ("Roofline accounting")
+    # algorithmic bytes per launch ("Roofline accounting");
+    # the solve's warp writes only live bricks, its chain reads the fields
+    # only where P^T r can be nonzero
     alg_bytes = {
-        "warp_pca": (3 + 3 * K + 2) * es * N,
+        "warp_pca": (3 + 3 * K + 2) * es * live,
         "grad_w": (3 + 3 * K + 2) * es * N,
         "jacobian": (3 + 3 * K + 1 + K) * es * N,
         "drr_forward": es * N + 32 * M + 2 * es * M,
         "drr_adjoint": es * N + 32 * M + 2 * es * M,
-        "drr_adjoint_chain": (3 + 3 * K + 1) * es * N + 32 * M + 2 * es * M,
+        "drr_adjoint_chain": (3 + 3 * K + 1) * es * reach + 32 * M + 2 * es * M,
         "drr_forward_dot": K * es * N + 32 * M + 2 * es * M,
     }
     # per-class figures: from the timed steps where that class carried events,
@@ -913,7 +931,7 @@ def main() -> int:
             # the chain per voxel for the fused back-projection)
             work = flops_per_sample(dominant, K) * S
             if dominant == "drr_adjoint_chain":
-                work += chain_flops_per_voxel(K) * N
+                work += chain_flops_per_voxel(K) * reach
             ach = work / (avg[dominant] * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": ach, "peak": VALU_F32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": traffic,
@@ -1021,7 +1039,8 @@ def main() -> int:
                    "spacing_mm": list(case.vol.spacing),
                    "detector": [case.proj.nu, case.proj.nv], "pitch_mm": case.proj.pitch_u,
                    "step_mm": case.proj.step, "K": K, "method": args.method, "max_iter": 30,
-                   "samples_per_drr": S, "angle_rad": case.proj.angle},
+                   "samples_per_drr": S, "angle_rad": case.proj.angle,
+                   "live_voxels": live, "reached_voxels": reach},
         "solve": {"iters": rep["iters"], "n_fevals": rep["n_fevals"], "n_grads": rep["n_grads"],
                   "status": rep["status"], "polish": 1, "w_rel_err_vs_planted": werr,
                   "tumour_mm": rep["tumour_mm"], **acc},

@@ -289,6 +289,13 @@ double pcas_backprojection_brick_bound(const pcas_vol *vol, const pcas_proj *pro
  * pcas_backprojection_brick_bound.  Host-only; -1 for an invalid volume. */
 int32_t backprojection_brick_count(const pcas_vol *vol);
 
+/* Voxels of the bricks a projection can read: a brick is live unless the
+ * image of its box with a one-voxel halo (which holds every sample whose
+ * cell touches a voxel of the brick) misses the detector by more than a
+ * pixel.  Inside solve_projection and the serving loop the warp writes only
+ * these voxels.  Host-only; -1 for an invalid volume or projection. */
+int64_t pcas_live_voxels(const pcas_vol *vol, const pcas_proj *proj);
+
 /* ---- a5: intensity fit (Eq. A.1) and residual ----------------------------
  * stats_out: device double[8] =
  *   { J, a, b, sum p, sum p*y, sum p*p, sum y, sum y*y }

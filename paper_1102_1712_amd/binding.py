@@ -25,7 +25,7 @@ EXPORTS = ("pcas_abi_version", "pcas_status_string", "pcas_last_error", "pcas_de
            "pcas_paper_opts", "pcas_ray_table_bytes", "ray_table", "pca_dvf", "warp_trilinear",
            "warp_pca", "drr_forward", "drr_siddon", "drr_adjoint", "drr_adjoint32",
            "pcas_backprojection_bound", "pcas_backprojection_brick_bound",
-           "backprojection_brick_count",
+           "backprojection_brick_count", "pcas_live_voxels",
            "residual_fit_workspace_bytes",
            "residual_fit", "grad_w_workspace_bytes", "grad_w", "tumour_position",
            "objective_gradient", "solve_projection_workspace", "solve_projection",
@@ -130,6 +130,7 @@ def lib():
             "pcas_backprojection_bound": (D, [VP, PP]),
             "pcas_backprojection_brick_bound": (D, [VP, PP, I32]),
             "backprojection_brick_count": (I32, [VP]),
+            "pcas_live_voxels": (I64, [VP, PP]),
             "residual_fit_workspace_bytes": (SZ, [I64]),
             "residual_fit": (I32, [I32, I64, P, P, I32, P, P, P, SZ, P]),
             "grad_w_workspace_bytes": (SZ, [I32, VP, I32]),
@@ -384,6 +385,15 @@ def backprojection_brick_bound(vol, proj, brick: int) -> float:
     if b < 0:
         raise PcasError(-1, "backprojection_brick_bound: invalid volume, projection or brick")
     return b
+
+
+def live_voxels(vol, proj) -> int:
+    """Voxels of the bricks the projection can read (the solve's warp writes
+    only these; host-only query)."""
+    n = int(lib().pcas_live_voxels(ctypes.byref(c_vol(vol)), ctypes.byref(c_proj(proj))))
+    if n < 0:
+        raise PcasError(-1, "live_voxels: invalid volume or projection")
+    return n
 
 
 def backprojection_brick_count(vol) -> int:

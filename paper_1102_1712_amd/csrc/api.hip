@@ -182,6 +182,11 @@ double pcas_backprojection_brick_bound(const pcas_vol *vol, const pcas_proj *pro
     return brick_weight_bound_host(v, make_frame(proj), brick);
 }
 
+int64_t pcas_live_voxels(const pcas_vol *vol, const pcas_proj *proj) {
+    if (check_vol(vol) || check_proj(proj, vol)) return -1;
+    return live_voxels(make_dims(vol), make_frame(proj));
+}
+
 int32_t backprojection_brick_count(const pcas_vol *vol) {
     if (check_vol(vol)) return -1;
     return drr_adjoint_blocks(make_dims(vol));

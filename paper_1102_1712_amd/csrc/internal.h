@@ -283,6 +283,8 @@ hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f
 // a pixel: no ray of the projection reaches a voxel of, or a sample cell
 // touching, a dead brick.
 hipError_t launch_brick_live(const VolDims &v, const Frame &fr, uint8_t *live, hipStream_t s);
+// Voxels of the live bricks (the same test, on the host).
+int64_t live_voxels(const VolDims &v, const Frame &fr);
 
 // Forward projection.  If sums != nullptr also reduces, with r0 = p - a0 y -
 // b0 for fit->a0, fit->b0 (zero when fit is null), (sum r0, sum r0*y,

@@ -1186,11 +1186,8 @@ int drr_adjoint_blocks(const VolDims &v) {
 // images, so a box whose corner images all fall more than a pixel off the
 // detector meets no ray; a corner at or behind the source's plane keeps the
 // brick live.
-__global__ __launch_bounds__(256) void k_brick_live(VolDims vd, Frame fr, uint8_t *__restrict__ live) {
+__host__ __device__ inline bool brick_live(const VolDims &vd, const Frame &fr, int bid) {
     const int nbx = (vd.n0 + BRICK_X - 1) / BRICK_X, nby = (vd.n1 + BRICK_Y - 1) / BRICK_Y;
-    const int nbz = (vd.n2 + BRICK_Z - 1) / BRICK_Z;
-    const int bid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (bid >= nbx * nby * nbz) return;
     const int b[3] = {bid % nbx, (bid / nbx) % nby, bid / (nbx * nby)};
     const int ext[3] = {BRICK_X, BRICK_Y, BRICK_Z}, n[3] = {vd.n0, vd.n1, vd.n2};
     double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
@@ -1198,8 +1195,10 @@ __global__ __launch_bounds__(256) void k_brick_live(VolDims vd, Frame fr, uint8_
     for (int corner = 0; corner < 8; ++corner) {
         double rel[3];
         for (int c = 0; c < 3; ++c) {
-            const int lo = b[c] * ext[c], hi = min(lo + ext[c], n[c]) - 1;
-            const int idx = ((corner >> c) & 1) ? min(hi + 1, n[c] - 1) : max(lo - 1, 0);
+            const int lo = b[c] * ext[c];
+            const int hi = (lo + ext[c] < n[c] ? lo + ext[c] : n[c]) - 1;
+            const int idx = ((corner >> c) & 1) ? (hi + 1 < n[c] - 1 ? hi + 1 : n[c] - 1)
+                                                : (lo - 1 > 0 ? lo - 1 : 0);
             rel[c] = vd.origin[c] + idx * vd.spacing[c] - fr.src[c];
         }
         const double depth = rel[0] * fr.en[0] + rel[1] * fr.en[1] + rel[2] * fr.en[2];
@@ -1217,7 +1216,27 @@ __global__ __launch_bounds__(256) void k_brick_live(VolDims vd, Frame fr, uint8_
         vmax = fmax(vmax, v);
     }
     const bool hit = umax >= -1.0 && umin <= (double)fr.nu && vmax >= -1.0 && vmin <= (double)fr.nv;
-    live[bid] = (behind || hit) ? 1 : 0;
+    return behind || hit;
+}
+
+__global__ __launch_bounds__(256) void k_brick_live(VolDims vd, Frame fr, uint8_t *__restrict__ live) {
+    const int bid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = ((vd.n0 + BRICK_X - 1) / BRICK_X) * ((vd.n1 + BRICK_Y - 1) / BRICK_Y) *
+                   ((vd.n2 + BRICK_Z - 1) / BRICK_Z);
+    if (bid >= nb) return;
+    live[bid] = brick_live(vd, fr, bid) ? 1 : 0;
+}
+
+int64_t live_voxels(const VolDims &v, const Frame &fr) {
+    const int nbx = (v.n0 + BRICK_X - 1) / BRICK_X, nby = (v.n1 + BRICK_Y - 1) / BRICK_Y;
+    int64_t n = 0;
+    for (int bid = 0; bid < drr_adjoint_blocks(v); ++bid) {
+        if (!brick_live(v, fr, bid)) continue;
+        const int lo[3] = {bid % nbx * BRICK_X, bid / nbx % nby * BRICK_Y, bid / (nbx * nby) * BRICK_Z};
+        n += (int64_t)(min(lo[0] + BRICK_X, v.n0) - lo[0]) * (min(lo[1] + BRICK_Y, v.n1) - lo[1]) *
+             (min(lo[2] + BRICK_Z, v.n2) - lo[2]);
+    }
+    return n;
 }
 
 hipError_t launch_brick_live(const VolDims &v, const Frame &fr, uint8_t *live, hipStream_t s) {

@@ -94,3 +94,63 @@ def test_brick_bounds_hold(oracle_lib, name):
     assert ratios and min(ratios) >= 1.0
     with pytest.raises(B.PcasError):
         B.backprojection_brick_bound(vol, proj, nb)
+
+
+def _live_bricks(vol, proj):
+    """The liveness rule restated: a brick is live unless the images of the
+    eight corners of its box with a one-voxel halo (clipped to the grid) all
+    fall more than a pixel off the detector on one side (or one corner lies
+    at or behind the source's plane)."""
+    t = proj.angle
+    src = np.array([proj.sad * np.sin(t), -proj.sad * np.cos(t), 0.0])
+    eu, ev = np.array([np.cos(t), np.sin(t), 0.0]), np.array([0.0, 0.0, 1.0])
+    en = np.array([-np.sin(t), np.cos(t), 0.0])
+    n, s, o = np.array(vol.n), np.array(vol.spacing), np.array(vol.origin)
+    ext = np.array([32, 16, 8])
+    nb = -(-n // ext)
+    live = np.zeros(nb[::-1], dtype=bool)          # [bz][by][bx]
+    for bz in range(nb[2]):
+        for by in range(nb[1]):
+            for bx in range(nb[0]):
+                lo = np.array([bx, by, bz]) * ext
+                hi = np.minimum(lo + ext, n) - 1
+                a, b = np.maximum(lo - 1, 0), np.minimum(hi + 1, n - 1)
+                us, vs, behind = [], [], False
+                for corner in range(8):
+                    idx = np.where([(corner >> c) & 1 for c in range(3)], b, a)
+                    rel = o + idx * s - src
+                    depth = rel @ en
+                    if not depth > 0.0:
+                        behind = True
+                        continue
+                    us.append((rel @ eu) * proj.sid / depth - proj.offset_u)
+                    vs.append((rel @ ev) * proj.sid / depth - proj.offset_v)
+                u = np.array(us) / proj.pitch_u + 0.5 * (proj.nu - 1)
+                v = np.array(vs) / proj.pitch_v + 0.5 * (proj.nv - 1)
+                hit = len(us) > 0 and u.max() >= -1 and u.min() <= proj.nu and \
+                    v.max() >= -1 and v.min() <= proj.nv
+                live[bz, by, bx] = behind or hit
+    return live
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+def test_live_bricks_hold_every_sampled_voxel(oracle_lib, name):
+    """The warp inside a solve writes only the voxels of live bricks.  That
+    is safe when every voxel a sample's cell touches -- every voxel where
+    the oracle's P^T 1 is nonzero -- lies in a live brick; the library's
+    count of live voxels follows the same rule."""
+    vol, proj = GEOMS[name]
+    live = _live_bricks(vol, proj)
+    n = np.array(vol.n)
+    mask = np.repeat(np.repeat(np.repeat(live, 8, 0), 16, 1), 32, 2)[:n[2], :n[1], :n[0]]
+    assert B.live_voxels(vol, proj) == int(mask.sum())
+    bp = O.drr_adjoint(vol, proj, np.ones(proj.nu * proj.nv)).reshape(n[2], n[1], n[0])
+    assert np.all(mask[bp > 0.0])
+    assert (bp > 0.0).sum() > 0
+
+
+def test_clinical_live_fraction():
+    """At the benchmark's geometry a little over half the bricks are live."""
+    c = synth.clinical()
+    frac = B.live_voxels(c.vol, c.proj) / np.prod(c.vol.n)
+    assert 0.5 < frac < 0.7
