@@ -2,12 +2,15 @@
 """Benchmark of the per-projection PCA solve on one MI355X.
 
 One step = one call of solve_projection on the clinical-size workload: ray
-table, then CG iterations of (DVF synthesis + warp, cone-beam projection,
-intensity fit and objective, and at accepted points back-projection of the
-residual and the Jacobian chain), then the tumour-position inversion.  The
-same solve with the gradient formed from projections of the Jacobian
-volumes (no back-projection) is reported beside it.  Inputs (reference volume, mean field and K = 3
-modes, measured projection) are resident in HBM before the timed region.
+table, then CG iterations of evaluations, then the tumour-position
+inversion.  By default an evaluation is the fused one (grad_mode 2): DVF
+synthesis, warp and the K Jacobian volumes in one voxel pass, then one
+cone-beam projection of all K + 1 volumes whose sums give the intensity
+fit, the objective and the gradient.  The same solve by the other two
+gradient routes (back-projection of the residual + Jacobian chain;
+projections of the Jacobian volumes after the evaluation) is reported
+beside it.  Inputs (reference volume, mean field and K = 3 modes, measured
+projection) are resident in HBM before the timed region.
 
 Prints ONE JSON line (see the keys below).  Kernel durations come from HIP
 events recorded by the library on the solve's stream around its launches:
@@ -39,10 +42,11 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # (3 fma = 6), fractions (3), trilinear value as 7 lerps of 3 flops (21),
 # accumulation (1) = 31.  Back-projection: position (6), fractions (3),
 # corner weights (9), 8 weighted accumulations (16) = 34.  Projection of K
-# volumes at once: position and fractions once (9), then 22 per volume.
+# volumes at once: position and fractions once (9), then 22 per volume (the
+# fused evaluation projects K + 1).
 def flops_per_sample(kernel: str, K: int) -> float:
     return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_adjoint_chain": 34.0,
-            "drr_forward_dot": 9.0 + 22.0 * K}[kernel]
+            "drr_forward_dot": 9.0 + 22.0 * K, "drr_forward_eval": 9.0 + 22.0 * (K + 1)}[kernel]
 
 
 # Jacobian chain per voxel: field 6K, displacement split 6, Eq. A.8 and its
@@ -51,10 +55,13 @@ def chain_flops_per_voxel(K: int) -> float:
     return 12.0 * K + 51.0
 
 
-SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot")
+SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot",
+                  "drr_forward_eval")
 KERNEL_SOURCES = {"drr_forward": "k_drr.hip", "drr_adjoint": "k_drr.hip",
                   "drr_adjoint_chain": "k_drr.hip", "drr_forward_dot": "k_drr.hip",
-                  "warp_pca": "k_warp.hip", "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
+                  "drr_forward_eval": "k_drr.hip", "warp_pca": "k_warp.hip",
+                  "warp_jac": "k_warp.hip", "grad_w": "k_grad.hip", "jacobian": "k_grad.hip"}
+HBM_KERNELS = ("warp_pca", "warp_jac", "grad_w", "jacobian")
 
 
 def kernel_digest(kernel: str) -> str:
@@ -693,8 +700,9 @@ def tiny_latency(args) -> dict:
                      dtype=torch.uint8, device="cuda")
     w0 = np.zeros(case.K)
 
-    def run(speculate, n):
-        o = B.default_opts(locate=1, c0_mm=tuple(case.tumour_c0), speculate=speculate)
+    def run(speculate, n, grad_mode=args.grad_mode):
+        kw = {} if grad_mode is None else {"grad_mode": grad_mode}
+        o = B.default_opts(locate=1, c0_mm=tuple(case.tumour_c0), speculate=speculate, **kw)
         for _ in range(3):
             B.solve_projection(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"], dev["y"],
                                w0, o, workspace=ws)
@@ -708,12 +716,16 @@ def tiny_latency(args) -> dict:
         return w, rep, ts, np.array(hs)
 
     w, rep, ts, hs = run(1, max(20, args.tiny_steps))
-    _, rep0, ts0, _ = run(0, 20)
+    _, rep0, ts0, _ = run(0, 20, 1)
+    routes = {str(gm): float(np.percentile(run(1, 20, gm)[2], 50)) for gm in (0, 1, 2)}
     return {"workload": case.name, "solves": len(ts), "p50_ms": float(np.percentile(ts, 50)),
+            "grad_mode": B.default_opts(**({} if args.grad_mode is None else
+                                           {"grad_mode": args.grad_mode})).grad_mode,
+            "p50_ms_by_gradient_route": routes,
             "p99_ms": float(np.percentile(ts, 99)), "mean_ms": float(np.mean(ts)),
             "library_p50_ms": float(np.percentile(hs[:, 0], 50)),
             "host_work_p50_ms": float(np.percentile(hs[:, 1], 50)),
-            "no_speculation_p50_ms": float(np.percentile(ts0, 50)),
+            "route1_no_speculation_p50_ms": float(np.percentile(ts0, 50)),
             "iters": rep["iters"], "n_fevals": rep["n_fevals"], "n_grads": rep["n_grads"],
             "spec_grads": rep["spec_grads"],
             "w_rel_err_vs_planted": float(np.linalg.norm(w - case.w_star) /
@@ -792,6 +804,8 @@ def main() -> int:
                          "projection sequence; serve: batched mixed-size serving; "
                          "resolution: detector-binning sweep on exact-path data; autograd: "
                          "the differentiation form against the plain solve")
+    ap.add_argument("--grad-mode", type=int, default=2, choices=[0, 1, 2],
+                    help="gradient route of the timed solve (opts.grad_mode)")
     ap.add_argument("--method", default="cg", choices=list(METHODS),
                     help="solver: PR+ CG (the configured one), BFGS, or the Appendix algorithm")
     ap.add_argument("--angles", type=int, default=100,
@@ -838,6 +852,9 @@ def main() -> int:
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
     base = dict(locate=1, c0_mm=tuple(case.tumour_c0), xtol=xtol)
     base["method"] = METHODS[args.method]
+    if args.grad_mode is not None:
+        base["grad_mode"] = args.grad_mode
+    timed_route = B.default_opts(**base).grad_mode
     opts_warm = B.default_opts(profile=0 if args.no_profile else B.PROFILE_ALL, **base)
     w0 = np.zeros(case.K)
 
@@ -890,6 +907,9 @@ def main() -> int:
     # only where P^T r can be nonzero
     alg_bytes = {
         "warp_pca": (3 + 3 * K + 2) * es * live,
+        # reads mean, U, f0; writes f and the K Jacobian volumes
+        "warp_jac": (3 + 3 * K + 1 + 1 + K) * es * live,
+        "drr_forward_eval": (K + 1) * es * N + 32 * M + 2 * es * M,
         "grad_w": (3 + 3 * K + 2) * es * N,
         "jacobian": (3 + 3 * K + 1 + K) * es * N,
         "drr_forward": es * N + 32 * M + 2 * es * M,
@@ -911,7 +931,7 @@ def main() -> int:
         if k in alg_bytes:
             d["alg_GBs"] = alg_bytes[k] / (a * 1e-3) / 1e9
         if k in SAMPLE_KERNELS:
-            nvol = K if k == "drr_forward_dot" else 1
+            nvol = {"drr_forward_dot": K, "drr_forward_eval": K + 1}.get(k, 1)
             d["Gsamples_s"] = S / (a * 1e-3) / 1e9
             d["effective_GBs"] = 8 * es * nvol * S / (a * 1e-3) / 1e9
         kernel_stats[k] = d
@@ -922,7 +942,7 @@ def main() -> int:
     wl = "clinical" if args.workload == "clinical" else args.workload
     traffic = measured_traffic(dominant, wl) if dominant else None
     if dominant in alg_bytes and avg.get(dominant):
-        if dominant in ("warp_pca", "grad_w", "jacobian"):
+        if dominant in HBM_KERNELS:
             ach = alg_bytes[dominant] / (avg[dominant] * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant}
@@ -937,22 +957,29 @@ def main() -> int:
                         "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": traffic,
                         "kernel": dominant}
 
-    # the other gradient route (projected Jacobian volumes, no back-projection),
-    # same solve otherwise; reported beside the contract line, not as `value`
-    alt_t = []
-    opts_alt = B.default_opts(grad_mode=0, **base)
-    step(opts_alt)
-    for _ in range(max(5, args.steps // 5)):
-        t0 = time.perf_counter()
-        w_alt, rep_alt = step(opts_alt)
-        alt_t.append(time.perf_counter() - t0)
-    alt_ms = np.array(alt_t) * 1e3
-    alt = {"grad_mode": 0, "steps": len(alt_t), "p50_ms": float(np.percentile(alt_ms, 50)),
-           "p99_ms": float(np.percentile(alt_ms, 99)),
-           "solves_s": float(1e3 / np.mean(alt_ms)), "n_fevals": rep_alt["n_fevals"],
-           "n_grads": rep_alt["n_grads"],
-           "w_rel_diff_vs_default_route": float(np.linalg.norm(w_alt - w) / np.linalg.norm(w))}
-    log(f"projected-gradient route: p50 {alt['p50_ms']:.3f} ms")
+    # the other gradient routes (0: projected Jacobian volumes; 1: back-
+    # projection + chain; 2: fused evaluation), same solve otherwise; reported
+    # beside the contract line, not as `value`
+    alt = {}
+    for gm in (0, 1, 2):
+        if gm == timed_route:
+            continue
+        alt_t = []
+        opts_alt = B.default_opts(**{**base, "grad_mode": gm})
+        step(opts_alt)
+        for _ in range(max(5, args.steps // 5)):
+            t0 = time.perf_counter()
+            w_alt, rep_alt = step(opts_alt)
+            alt_t.append(time.perf_counter() - t0)
+        alt_ms = np.array(alt_t) * 1e3
+        alt[str(gm)] = {"grad_mode": gm, "steps": len(alt_t),
+                        "p50_ms": float(np.percentile(alt_ms, 50)),
+                        "p99_ms": float(np.percentile(alt_ms, 99)),
+                        "solves_s": float(1e3 / np.mean(alt_ms)), "n_fevals": rep_alt["n_fevals"],
+                        "n_grads": rep_alt["n_grads"],
+                        "w_rel_diff_vs_timed_route": float(np.linalg.norm(w_alt - w) /
+                                                           np.linalg.norm(w))}
+        log(f"gradient route {gm}: p50 {alt[str(gm)]['p50_ms']:.3f} ms")
 
     # the quasi-Newton solver on the same problem (same line search, same
     # stops), beside the configured CG: latency and agreement of the minimisers
@@ -1058,7 +1085,8 @@ def main() -> int:
                               for k in kernel_stats if k in KERNEL_SOURCES},
         "kernels": kernel_stats,
         "timed_region_events": [k for i, k in enumerate(B.KERNEL_CLASSES) if mask >> i & 1],
-        "projected_gradient_route": alt,
+        "grad_mode": timed_route,
+        "other_gradient_routes": alt,
         "quasi_newton": qn,
         "random_angles": rand,
         "roofline": roofline,

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define PCAS_ABI_VERSION 7
+#define PCAS_ABI_VERSION 8
 #define PCAS_MAX_K 8
 
 typedef enum { PCAS_F32 = 0, PCAS_F64 = 1 } pcas_dtype;
@@ -119,7 +119,13 @@ typedef struct {
                                  with grad_w's chain applied to each brick as it completes,
                                  so P^T r never goes to device memory
                               0: project the K Jacobian volumes J_k = U_k^T (df/dx) and take
-                                 g_k = 2 <r, P J_k> (gathers only, no back-projection) */
+                                 g_k = 2 <r, P J_k> (gathers only, no back-projection)
+                              2: fused evaluation: every evaluation forms f and the J_k in
+                                 one voxel pass and projects all K + 1 volumes together,
+                                 keeping per pixel r0 = p - a0 y - b0 (a0, b0 a reference
+                                 fit) and q_k = (P J_k); the sums of r0, r0 y, r0^2, q_k r0,
+                                 q_k y and q_k give J, the fit and g_k = 2 <r, P J_k> at
+                                 the fit found, so a gradient costs no launch of its own */
     double ftol_rel;       /* methods 1, 2: the noise band of J (relative): a rejected trial
                               with |J_t - J| <= ftol_rel J ends the solve as converged, and
                               either method also ends, converged, when its model predicts a
@@ -155,13 +161,15 @@ typedef struct {
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
-   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain, and
+   PCAS_K_ADJOINT is the back-projection fused with the Jacobian chain,
    PCAS_K_SPEC_SKIP a speculative launch of it (opts.speculate) whose gate
-   was shut, so that it exited at once) */
+   was shut, so that it exited at once, and PCAS_K_WARP_JAC /
+   PCAS_K_DRR_EVAL the two launches of a fused evaluation (grad_mode 2)) */
 enum {
     PCAS_K_RAYS = 0, PCAS_K_WARP = 1, PCAS_K_DRR = 2, PCAS_K_RESIDUAL = 3,
     PCAS_K_ADJOINT = 4, PCAS_K_GRAD = 5, PCAS_K_LOCATE = 6, PCAS_K_YSUMS = 7,
-    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_SPEC_SKIP = 10, PCAS_K_CLASSES = 11
+    PCAS_K_JACOBIAN = 8, PCAS_K_DRR_DOT = 9, PCAS_K_SPEC_SKIP = 10, PCAS_K_WARP_JAC = 11,
+    PCAS_K_DRR_EVAL = 12, PCAS_K_CLASSES = 13
 };
 #define PCAS_PROFILE_ALL ((1 << PCAS_K_CLASSES) - 1)
 

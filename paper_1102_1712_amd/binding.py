@@ -77,17 +77,18 @@ class Report(ctypes.Structure):
                 ("J0", ctypes.c_double), ("J", ctypes.c_double), ("a", ctypes.c_double),
                 ("b", ctypes.c_double), ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double),
                 ("tumour_mm", ctypes.c_double * 3), ("locate_iters", ctypes.c_int32),
-                ("spec_grads", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 11),
-                ("kernel_launches", ctypes.c_int32 * 11), ("host_ms", ctypes.c_double),
+                ("spec_grads", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 13),
+                ("kernel_launches", ctypes.c_int32 * 13), ("host_ms", ctypes.c_double),
                 ("wait_ms", ctypes.c_double)]
 
 
 # report.kernel_ms classes; in a solve class 4 is the back-projection with the
 # Jacobian chain fused into it, class 10 a speculative launch of it whose gate
-# was shut (it exited at once)
+# was shut (it exited at once), classes 11 and 12 the two launches of a fused
+# evaluation (grad_mode 2)
 KERNEL_CLASSES = ("ray_table", "warp_pca", "drr_forward", "residual", "drr_adjoint_chain",
                   "grad_w", "tumour_position", "y_sums", "jacobian", "drr_forward_dot",
-                  "spec_skipped")
+                  "spec_skipped", "warp_jac", "drr_forward_eval")
 PROFILE_ALL = (1 << len(KERNEL_CLASSES)) - 1
 
 

@@ -327,7 +327,7 @@ struct Solver {
     pcas_dtype dt;
     VolDims vd;
     Frame fr;
-    ForwardPlan fplan, fplan_k;   // projection of f; of the K Jacobian volumes
+    ForwardPlan fplan, fplan_k, fplan_e;   // projection of f; of the K Jacobian volumes; of both
     int K;
     int grad_mode = 0;
     int64_t M;
@@ -343,6 +343,7 @@ struct Solver {
     double ref_a = 1.0, ref_b = 0.0;
     int mom_slot = -1;
     double mom_a0 = 0.0, mom_b0 = 0.0;
+    double *mom_src = nullptr;   // where those moments are (scal() or the fused sums)
     Profile prof;
     // Speculative gradients (opts.speculate; FP32 one-pass evaluations with
     // the fused back-projection): the gradient at the last evaluated point,
@@ -356,6 +357,16 @@ struct Solver {
         int slot = 0;
         double w[PCAS_MAX_K] = {0}, a = 0.0, b = 0.0, g[PCAS_MAX_K] = {0};
     } spec;
+
+    // The fused evaluation (grad_mode 2): per line-search slot, the point
+    // and the sums its projection left (launch_drr_forward_eval), from which
+    // the gradient at any fit follows without another launch.
+    struct Fused {
+        bool valid = false;
+        double w[PCAS_MAX_K] = {0};
+        double a0 = 0.0, b0 = 0.0;
+        double m[6 + 3 * PCAS_MAX_K] = {0};
+    } fused[2];
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -416,27 +427,33 @@ struct Solver {
     // over the residual; (a, b) refitted by Eq. A.1 unless fixed.
     // With a gradient rule and the point w of the slot's projection (an FP64
     // evaluation), the gradient at w comes back with J in one read-back.
+    // The moments come from mom_src (the slot's evaluation left them there);
+    // J, a, b go to jab_dst, and with `tail` the `ntail` values after them
+    // come back in the same read-back.
     int residual(const double *ab_fixed, int slot, double *J, double *a, double *b,
-                 const GradRule *rule = nullptr, const double *w = nullptr) {
+                 const GradRule *rule = nullptr, const double *w = nullptr,
+                 double *tail = nullptr, int ntail = 0) {
         FitArgs fa = fit_args(ab_fixed);
         if (fa.mode == FIT_REFIT) {   // the refit reads the moments of this slot's projection
             if (slot != mom_slot) return hip_fail(hipErrorInvalidValue, "refit without moments");
             fa.a0 = mom_a0;
             fa.b0 = mom_b0;
         }
+        double *jab = mom_src + 3;
         HIPCHK(timed(PCAS_K_RESIDUAL, [&] {
-            return launch_residual(dt, M, proj_slot(slot), y, fa, scal(), nullptr,
-                                   (double *)(ws + L.partials), &counters()[3], scal() + 3, s);
+            return launch_residual(dt, M, proj_slot(slot), y, fa, mom_src, nullptr,
+                                   (double *)(ws + L.partials), &counters()[3], jab, s);
         }));
-        double out[3];
+        double out[3 + 3 * PCAS_MAX_K];
         int st;
         if (speculate && rule && w && rule->mode != GRAD_NEVER) {
-            HIPCHK(launch_spec_decide_jab(scal() + 3, *rule, scal() + SCAL_GATE, s));
-            st = gated_gradient(w, slot, scal() + 3, out);
+            HIPCHK(launch_spec_decide_jab(jab, *rule, scal() + SCAL_GATE, s));
+            st = gated_gradient(w, slot, jab, out);
         } else {
-            st = sync_read(out, scal() + 3, 3);
+            st = sync_read(out, jab, 3 + ntail);
         }
         if (st) return st;
+        for (int j = 0; j < ntail; ++j) tail[j] = out[3 + j];
         *J = out[0];
         *a = out[1];
         *b = out[2];
@@ -458,6 +475,7 @@ struct Solver {
     int evaluate(const double *w, const double *ab_fixed, int slot, double *J, double *a,
                  double *b, const GradRule *rule = nullptr) {
         spec.valid = false;
+        if (grad_mode == 2) return evaluate_fused(w, ab_fixed, slot, J, a, b);
         HIPCHK(timed(PCAS_K_WARP, [&] {
             return launch_warp_pca(dt, vd, K, f0, mean, U, w, ws + L.f, s,
                                    (const uint8_t *)(ws + L.live));
@@ -479,6 +497,7 @@ struct Solver {
         mom_slot = slot;
         mom_a0 = ff.a0;
         mom_b0 = ff.b0;
+        mom_src = scal();
         if (!one_pass) return residual(ab_fixed, slot, J, a, b, rule, w);
         double mo[3], kappa;
         const int nbf = drr_forward_blocks(fr.nu, fr.nv);
@@ -499,6 +518,69 @@ struct Solver {
         if (!isfinite(*J)) return PCAS_ENONFINITE;
         ref_a = *a;
         ref_b = *b;
+        return PCAS_OK;
+    }
+
+    // grad_mode 2: the warp and the K Jacobian volumes in one voxel pass,
+    // then one projection of all K + 1 volumes that leaves the objective's
+    // moments and the gradient's sums (launch_drr_forward_eval), read back
+    // together.  FP32 forms J and the fit from the moments as evaluate()
+    // does; FP64 takes them from the two-pass residual (moments of p
+    // itself, a0 = b0 = 0), whose J, a, b land in front of the gradient's
+    // sums so that one read-back returns both.
+    int evaluate_fused(const double *w, const double *ab_fixed, int slot, double *J, double *a,
+                       double *b) {
+        Fused &F = fused[slot];
+        F.valid = false;
+        char *vols = ws + L.vol2;
+        HIPCHK(timed(PCAS_K_WARP_JAC, [&] {
+            return launch_warp_jac(dt, vd, K, f0, mean, U, w, vols, s,
+                                   (const uint8_t *)(ws + L.live));
+        }));
+        const bool one_pass = dt == PCAS_F32;
+        FitArgs ff = fit_args(ab_fixed);
+        if (one_pass) {
+            ff.a0 = ff.mode == FIT_FIXED ? ff.a : ref_a;
+            ff.b0 = ff.mode == FIT_FIXED ? ff.b : ref_b;
+        }
+        double *sums = scal() + SCAL_EVAL;
+        HIPCHK(timed(PCAS_K_DRR_EVAL, [&] {
+            return launch_drr_forward_eval(dt, vd, fr, fplan_e, K, ws + L.rays, vols,
+                                           proj_slot(slot), y, ff, (double *)(ws + L.partials),
+                                           one_pass ? nullptr : &counters()[0], sums, s);
+        }));
+        ++n_fevals;
+        mom_slot = slot;
+        mom_a0 = ff.a0;
+        mom_b0 = ff.b0;
+        mom_src = sums;
+        const int ns = 6 + 3 * K;
+        int st;
+        if (!one_pass) {
+            if ((st = residual(ab_fixed, slot, J, a, b, nullptr, nullptr, F.m + 6, 3 * K)))
+                return st;
+        } else {
+            const int nbf = drr_forward_blocks(fr.nu, fr.nv);
+            if ((st = sync_read_sum(F.m, nbf, FWD_THREADS, 1.0, sums, ns))) return st;
+            double kappa;
+            objective_from_moments(F.m, ff, J, a, b, &kappa);
+            if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
+            if (!(kappa <= MOMENT_KAPPA_MAX)) {   // cancellation: the two-pass sum at this fit
+                const double ab[2] = {*a, *b};
+                double keep[3 * PCAS_MAX_K];
+                for (int j = 0; j < 3 * K; ++j) keep[j] = F.m[6 + j];
+                if ((st = residual(ab, slot, J, a, b))) return st;
+                for (int j = 0; j < 3 * K; ++j) F.m[6 + j] = keep[j];
+            } else {
+                if (!isfinite(*J)) return PCAS_ENONFINITE;
+                ref_a = *a;
+                ref_b = *b;
+            }
+        }
+        F.valid = true;
+        F.a0 = ff.a0;
+        F.b0 = ff.b0;
+        for (int k = 0; k < K; ++k) F.w[k] = w[k];
         return PCAS_OK;
     }
 
@@ -550,6 +632,14 @@ struct Solver {
 
     // Gradient at the w whose projection is in the slot, at (a, b).
     int gradient(const double *w, double a, double b, int slot, double *g) {
+        if (grad_mode == 2 && fused[slot].valid && !memcmp(fused[slot].w, w, K * sizeof(double))) {
+            const Fused &F = fused[slot];
+            gradient_from_moments(F.m, K, a, b, F.a0, F.b0, g);
+            ++n_grads;
+            for (int k = 0; k < K; ++k)
+                if (!isfinite(g[k])) return PCAS_ENONFINITE;
+            return PCAS_OK;
+        }
         if (spec.valid) {
             spec.valid = false;
             if (spec.slot == slot && !memcmp(spec.w, w, K * sizeof(double)) &&
@@ -603,6 +693,8 @@ struct Solver {
         speculate = speculate_ && grad_mode_ == 1;
         fplan = plan_drr_forward(dtype, vd, fr, 1);
         fplan_k = plan_drr_forward(dtype, vd, fr, K_);
+        fplan_e = plan_drr_forward(dtype, vd, fr, K_ + 1);
+        fused[0].valid = fused[1].valid = false;
         M = npix_of(proj);
         f0 = f0_;
         mean = mean_;
@@ -610,6 +702,7 @@ struct Solver {
         y = y_;
         ws = (char *)workspace;
         L = solve_layout(dtype, vol, proj, K_);
+        mom_src = scal();
         s = (hipStream_t)stream;
         fit = fit_ ? 1 : 0;
         prof.mask = profile;
@@ -732,7 +825,7 @@ extern "C" int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const p
     if ((st = check_vol_bytes(vol, dtype))) return st;
     if ((st = check_proj(proj, vol))) return st;
     if (!f0 || !U || !y || !w || !out) return PCAS_EINVAL;
-    if (grad_mode != 0 && grad_mode != 1) return PCAS_EINVAL;
+    if (grad_mode < 0 || grad_mode > 2) return PCAS_EINVAL;
     if (!finite_vec(w, K)) return PCAS_ENONFINITE;
     const SolveWs L = solve_layout(dtype, vol, proj, K);
     if (!workspace || !aligned(workspace, 256) || workspace_bytes < L.total) return PCAS_EWORKSPACE;

@@ -25,10 +25,10 @@ __device__ __forceinline__ void store_agent(double *p, double v) {
 }
 
 // Sums vals[0..NS) over the block (any multiple of 64 threads up to 1024)
-// and stores the block's totals in partials[bid * RED_SLOTS + j].
+// and stores the block's totals in partials[bid * red_stride(NS) + j].
 template <int NS>
 __device__ void block_partials(const double (&vals)[NS], double *__restrict__ partials, int bid) {
-    static_assert(NS <= RED_SLOTS, "too many reduction slots");
+    static_assert(NS <= RED_SLOTS_WIDE, "too many reduction slots");
     __shared__ double sm[NS][16];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
 #pragma unroll
@@ -42,7 +42,7 @@ __device__ void block_partials(const double (&vals)[NS], double *__restrict__ pa
         for (int j = 0; j < NS; ++j) {
             double t = 0.0;
             for (int w = 0; w < nwaves; ++w) t += sm[j][w];
-            store_agent(&partials[(int64_t)bid * RED_SLOTS + j], t);
+            store_agent(&partials[(int64_t)bid * red_stride(NS) + j], t);
         }
     }
 }
@@ -65,7 +65,7 @@ __device__ void sum_partials(const double *__restrict__ partials, int nblocks, d
     for (int b = threadIdx.x; threadIdx.x < width && b < nblocks; b += width) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
-            const double *q = &partials[(int64_t)b * RED_SLOTS + j];
+            const double *q = &partials[(int64_t)b * red_stride(NS) + j];
             acc[j] += COHERENT ? load_agent(q) : *q;
         }
     }

@@ -190,7 +190,7 @@ inline int readback(double *host, const double *dev, int count, hipStream_t s) {
 // partials) into dev[0..count) and reads the totals back.
 inline int readback_sum(double *host, const double *partials, int nblocks, int threads,
                         double scale, double *dev, int count, hipStream_t s) {
-    if (count < 1 || count > RED_SLOTS) return hip_fail(hipErrorInvalidValue, "reduction width");
+    if (count < 1 || count > RED_SLOTS_WIDE) return hip_fail(hipErrorInvalidValue, "reduction width");
     return readback_with(host, count, s, [&](double *vals, uint32_t *flag, uint32_t seq) {
         return launch_publish_sum(partials, nblocks, threads, count, scale, dev, vals, flag, seq, s);
     });
@@ -211,8 +211,10 @@ inline int red_blocks_max(const pcas_vol *v, const pcas_proj *p) {
     return m;
 }
 
-// vol2 holds bp or the K Jacobian volumes; with_vol2 = false drops it (the
-// fused back-projection + chain needs neither).
+// vol2 holds bp, the K Jacobian volumes, or the warped image and its K
+// Jacobian volumes (the fused evaluation); with_vol2 = false drops it (the
+// fused back-projection + chain needs none of them).  The partials hold the
+// widest reduction: the fused evaluation's forward blocks at RED_SLOTS_WIDE.
 inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p, int K,
                             bool with_vol2 = true) {
     SolveWs L;
@@ -222,10 +224,12 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
     L.f = off; off += align256(N * es);
     L.p = off; off += align256(M * es);
     L.p2 = off; off += align256(M * es);   // second projection slot of the line search
-    L.vol2 = off; off += with_vol2 ? align256((size_t)(K > 1 ? K : 1) * N * es) : 0;
-    L.partials = off; off += align256((size_t)red_blocks_max(v, p) * RED_SLOTS * sizeof(double));
+    L.vol2 = off; off += with_vol2 ? align256((size_t)(K + 1) * N * es) : 0;
+    const size_t narrow = (size_t)red_blocks_max(v, p) * RED_SLOTS;
+    const size_t wide = with_vol2 ? (size_t)drr_forward_blocks(p->nu, p->nv) * RED_SLOTS_WIDE : 0;
+    L.partials = off; off += align256((narrow > wide ? narrow : wide) * sizeof(double));
     L.counters = off; off += 256;
-    L.scalars = off; off += align256(64 * sizeof(double));
+    L.scalars = off; off += align256(SCAL_COUNT * sizeof(double));
     L.live = off; off += align256((size_t)drr_adjoint_blocks(make_dims(v)));   // brick liveness
     L.total = off;
     return L;
@@ -234,7 +238,7 @@ inline SolveWs solve_layout(pcas_dtype dt, const pcas_vol *v, const pcas_proj *p
 inline int check_opts(const pcas_opts *o) {
     if (!o) return PCAS_EINVAL;
     if (o->method < 0 || o->method > 2) return PCAS_EINVAL;
-    if (o->grad_mode != 0 && o->grad_mode != 1) return PCAS_EINVAL;
+    if (o->grad_mode < 0 || o->grad_mode > 2) return PCAS_EINVAL;
     if (o->max_iter < 0 || o->max_backtracks < 1 || o->locate_max_iter < 1) return PCAS_EINVAL;
     if (!(o->mu0 > 0.0) || !(o->alpha > 0.0 && o->alpha < 1.0) || !(o->beta > 0.0 && o->beta < 1.0))
         return PCAS_EINVAL;

@@ -68,8 +68,11 @@ constexpr int TILE_U = 2 * FWD_WU, TILE_V = 2 * FWD_WV;
 constexpr int FWD_LDS_BYTES = 16384;
 constexpr int FWD_MAX_SLABS = 128;
 static_assert(FWD_WU * FWD_WV * FWD_SPLIT == 64, "forward wave tile");
-// Reductions: partial-sum slots per block.
+// Reductions: partial-sum slots per block; a reduction of more than
+// RED_SLOTS values (the fused evaluation's moments) strides RED_SLOTS_WIDE.
 constexpr int RED_SLOTS = 8;
+constexpr int RED_SLOTS_WIDE = 32;
+constexpr int red_stride(int ns) { return ns <= RED_SLOTS ? RED_SLOTS : RED_SLOTS_WIDE; }
 constexpr int GRAD_BLOCKS_MAX = 2048;
 
 // Coefficients passed by value to kernels.
@@ -244,6 +247,10 @@ hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
 // Scalar slot of a solve's speculative gate (a, b, go), inside the scalars
 // the serving loop reads back per request.
 constexpr int SCAL_GATE = 28;
+// Scalars of a solve's workspace, and the slot of the fused evaluation's
+// moments (6 + 3K values: see launch_drr_forward_eval).
+constexpr int SCAL_COUNT = 128;
+constexpr int SCAL_EVAL = 64;
 // Several requests' gates in one launch (one FWD_THREADS-wide block each):
 // from the moment partials of an FP32 evaluation (partials != null, summed
 // as launch_spec_decide does, written to mo) or from an FP64 evaluation's
@@ -314,6 +321,42 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
                                   const void *p, const void *y, double a, double b,
                                   double *partials, uint32_t *counter, double *g_out,
                                   hipStream_t s);
+// The fused evaluation's projection (plan for nvol = K + 1): vols holds the
+// warped image f and then its K Jacobian volumes J_k, each N values.  It
+// stores p = P f and reduces 6 + 3K sums with r0 = p - fit.a0 y - fit.b0
+// and q_k = P J_k (unrounded ray sums):
+//   sums[0..2]          = (sum r0, sum r0 y, sum r0^2)   (the objective's moments)
+//   sums[3..5]          = 0                              (room for J, a, b)
+//   sums[6 + 3k .. +2]  = (sum q_k r0, sum q_k y, sum q_k)
+// so that for any fit (a, b), sum_rays (p - a y - b) q_k = sums[6+3k]
+// - (a - a0) sums[7+3k] - (b - b0) sums[8+3k] (gradient_from_moments).
+// counter == nullptr leaves block partials (RED_SLOTS_WIDE apart) for
+// launch_publish_sum; otherwise the last block writes sums.
+hipError_t launch_drr_forward_eval(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                                   const ForwardPlan &plan, int K, const void *rays,
+                                   const void *vols, void *p, const void *y, const FitArgs &fit,
+                                   double *partials, uint32_t *counter, double *sums,
+                                   hipStream_t s);
+// The warped image and its K Jacobian volumes in one voxel pass: out[0..N)
+// = f exactly as launch_warp_pca computes it, out[(1 + k) N ..) = J_k exactly
+// as launch_jacobian computes it.  With live (launch_brick_live), voxels of
+// bricks no ray reaches are skipped (left as they were).
+hipError_t launch_warp_jac(pcas_dtype dt, const VolDims &v, int K, const void *f0,
+                           const void *mean, const void *U, const double *w, void *out,
+                           hipStream_t s, const uint8_t *live = nullptr);
+
+// dJ/dw_k = 2 sum_rays (p - a y - b) q_k from the fused evaluation's sums
+// taken about the reference fit (a0, b0) (see launch_drr_forward_eval).
+// Compiled without contraction so that host and device agree.
+__host__ __device__ inline void gradient_from_moments(const double *sums, int K, double a,
+                                                      double b, double a0, double b0, double *g) {
+#pragma clang fp contract(off)
+    const double da = a - a0, db = b - b0;
+    for (int k = 0; k < K; ++k) {
+        const double *m = sums + 6 + 3 * k;
+        g[k] = 2.0 * (m[0] - da * m[1] - db * m[2]);
+    }
+}
 
 // Back-projection.  If y != nullptr the residual r = p - a*y - b is formed
 // on the fly from p (passed as r_or_p); otherwise r_or_p is r.  acc32

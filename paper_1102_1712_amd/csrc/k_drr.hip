@@ -127,7 +127,7 @@ static bool slab_cells_host(const VolDims &v, const Frame &fr, int AX, int iu0, 
 }
 
 // What the projection kernel does with each ray's value.
-enum { FWD_WRITE = 0, FWD_SUMS = 1, FWD_DOT = 2 };
+enum { FWD_WRITE = 0, FWD_SUMS = 1, FWD_DOT = 2, FWD_EVAL = 3 };
 
 // LDS budget of the staged boxes: one volume 16 KB, several 32 KB.
 constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_LDS_BYTES; }
@@ -151,7 +151,8 @@ constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_L
 // out[0..2] (the host forms the objective from them: objective_from_moments).
 // MODE FWD_DOT: the ray values
 // q_v = (P f_v) are not stored; out[v] = 2 sum_rays r q_v with the residual
-// r = p - a y - b of the stored projection p.
+// r = p - a y - b of the stored projection p.  MODE FWD_EVAL (NV = K + 1):
+// p = P f of volume 0 and the moment sums of launch_drr_forward_eval.
 template <typename T, int AX, int NV, int MODE>
 __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame &fr, int tiles_u,
                                                   int slab, const RayRec<T> *__restrict__ rays,
@@ -392,6 +393,25 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             const double rv = writer ? pv - fit.a0 * yv - fit.b0 : 0.0;
             const double vals[3] = {rv, rv * yv, rv * rv};
             reduce_or_defer<3>(vals, partials, counter, out, bid, nb, 1.0);
+        } else if constexpr (MODE == FWD_EVAL) {
+            // volume 0 is f, volumes 1.. its Jacobian volumes: the objective's
+            // moments and, per mode, the sums that give the gradient's
+            // residual dot product at whatever fit the moments select
+            const double yv = writer ? (double)y[pix] : 0.0;
+            const double rv = writer ? pv - fit.a0 * yv - fit.b0 : 0.0;
+            double vals[3 + 3 * NV];
+            vals[0] = rv;
+            vals[1] = rv * yv;
+            vals[2] = rv * rv;
+            vals[3] = vals[4] = vals[5] = 0.0;
+#pragma unroll
+            for (int v = 1; v < NV; ++v) {
+                const double q = writer ? (double)r.dt * acc[v] : 0.0;
+                vals[3 + 3 * v] = q * rv;
+                vals[4 + 3 * v] = q * yv;
+                vals[5 + 3 * v] = q;
+            }
+            reduce_or_defer<3 + 3 * NV>(vals, partials, counter, out, bid, nb, 1.0);
         }
     }
 }
@@ -571,6 +591,31 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
     case KK:                                                                                       \
         launch_fwd_axis<TT, KK, FWD_DOT>(plan, grid, v, fr, tiles_u, rays, J, pp, y, a, b, fa,     \
                                          partials, counter, g_out, s);                             \
+        break
+    if (dt == PCAS_F32) {
+        switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);
+                     D(float, 5); D(float, 6); D(float, 7); D(float, 8);
+                     default: return hipErrorInvalidValue; }
+    } else {
+        switch (K) { D(double, 1); D(double, 2); D(double, 3); D(double, 4);
+                     D(double, 5); D(double, 6); D(double, 7); D(double, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+#undef D
+    return hipGetLastError();
+}
+
+hipError_t launch_drr_forward_eval(pcas_dtype dt, const VolDims &v, const Frame &fr,
+                                   const ForwardPlan &plan, int K, const void *rays,
+                                   const void *vols, void *p, const void *y, const FitArgs &fit,
+                                   double *partials, uint32_t *counter, double *sums,
+                                   hipStream_t s) {
+    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
+    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
+#define D(TT, KK)                                                                                  \
+    case KK:                                                                                       \
+        launch_fwd_axis<TT, KK + 1, FWD_EVAL>(plan, grid, v, fr, tiles_u, rays, vols, p, y, 0.0,   \
+                                              0.0, fit, partials, counter, sums, s);               \
         break
     if (dt == PCAS_F32) {
         switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);

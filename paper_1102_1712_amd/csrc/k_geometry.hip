@@ -73,6 +73,15 @@ hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, 
         PCAS_PUBLISH_SUM(6)
         PCAS_PUBLISH_SUM(7)
         PCAS_PUBLISH_SUM(8)
+        // the fused evaluation's 6 + 3K sums
+        PCAS_PUBLISH_SUM(9)
+        PCAS_PUBLISH_SUM(12)
+        PCAS_PUBLISH_SUM(15)
+        PCAS_PUBLISH_SUM(18)
+        PCAS_PUBLISH_SUM(21)
+        PCAS_PUBLISH_SUM(24)
+        PCAS_PUBLISH_SUM(27)
+        PCAS_PUBLISH_SUM(30)
 #undef PCAS_PUBLISH_SUM
     default:
         return hipErrorInvalidValue;

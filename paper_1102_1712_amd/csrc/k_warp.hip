@@ -3,6 +3,7 @@
 // output streams are fully coalesced; the eight f0 neighbours of a voxel lie
 // within a few voxels of it and are served by L2.
 #include "device_util.h"
+#include "jacobian.h"
 
 namespace pcas {
 
@@ -124,6 +125,46 @@ __global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restric
     warp_pca_block<T, K>(vd, f0, mean, U, w, f, blockIdx.x, gridDim.x, live);
 }
 
+// The warped image and its K Jacobian volumes J_k = sum_c U_kc df/dx_c
+// (Eq. A.8 per mm, through the modes) in one voxel pass, for the fused
+// evaluation that projects all K + 1 volumes together.  The field, f and
+// J_k take exactly the operations of k_warp_pca and k_jacobian, so the three
+// kernels agree bit for bit; the eight f0 neighbours are read once for the
+// value and once for the derivatives, the second time from cache.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_warp_jac(VolDims vd, const T *__restrict__ f0,
+                                                  const T *__restrict__ mean,
+                                                  const T *__restrict__ U, WVec w,
+                                                  T *__restrict__ out,
+                                                  const uint8_t *__restrict__ live) {
+    const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int v32 = b * (int)blockDim.x + (int)threadIdx.x;
+    if (v32 >= (int)N) return;
+    const int64_t v = v32;
+    const unsigned q = (unsigned)v32 / (unsigned)vd.n0;
+    const int i = v32 - (int)q * vd.n0;
+    const int k = (int)(q / (unsigned)vd.n1);
+    const int j = (int)q - k * vd.n1;
+    if (live) {
+        const int nbx = (vd.n0 + BRICK_X - 1) / BRICK_X, nby = (vd.n1 + BRICK_Y - 1) / BRICK_Y;
+        if (!live[(k / BRICK_Z * nby + j / BRICK_Y) * nbx + i / BRICK_X]) return;
+    }
+    T wk[K];
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) wk[kk] = (T)w.w[kk];
+    const T is0 = (T)vd.inv_s[0], is1 = (T)vd.inv_s[1], is2 = (T)vd.inv_s[2];
+    T u[K][3], x[3], jac[3];
+    voxel_field<T, K, true>(mean, U, wk, N, v, u, x);
+    out[v] = warp_gather(f0, vd.n0, vd.n1, vd.n2, i, j, k, x[0], x[1], x[2], is0, is1, is2);
+    if (!voxel_jacobian(f0, vd.n0, vd.n1, vd.n2, i, j, k, x, is0, is1, is2, jac))
+        jac[0] = jac[1] = jac[2] = (T)0;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+        out[(int64_t)(kk + 1) * N + v] =
+            fma_t(u[kk][0], jac[0], fma_t(u[kk][1], jac[1], u[kk][2] * jac[2]));
+}
+
 // Several requests' warps in one launch (jobs sorted by block0).
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_warp_pca_batch(const WarpJob *__restrict__ jobs,
@@ -150,6 +191,15 @@ hipError_t warp_pca_k(const VolDims &v, const void *f0, const void *mean, const 
     dim3 grid((unsigned)((N + 255) / 256)), block(256);
     hipLaunchKernelGGL((k_warp_pca<T, K>), grid, block, 0, s, v, (const T *)f0, (const T *)mean,
                        (const T *)U, w, (T *)f, live);
+    return hipGetLastError();
+}
+template <typename T, int K>
+hipError_t warp_jac_k(const VolDims &v, const void *f0, const void *mean, const void *U,
+                      const WVec &w, void *out, hipStream_t s, const uint8_t *live) {
+    const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
+    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    hipLaunchKernelGGL((k_warp_jac<T, K>), grid, block, 0, s, v, (const T *)f0, (const T *)mean,
+                       (const T *)U, w, (T *)out, live);
     return hipGetLastError();
 }
 WVec make_w(const double *w, int K) {
@@ -231,6 +281,20 @@ hipError_t launch_warp_pca(pcas_dtype dt, const VolDims &v, int K, const void *f
 #undef CALL
     }
 #define CALL(KK) warp_pca_k<double, KK>(v, f0, mean, U, wv, f, s, live)
+    PCAS_K_SWITCH(K, CALL)
+#undef CALL
+}
+
+hipError_t launch_warp_jac(pcas_dtype dt, const VolDims &v, int K, const void *f0,
+                           const void *mean, const void *U, const double *w, void *out,
+                           hipStream_t s, const uint8_t *live) {
+    const WVec wv = make_w(w, K);
+    if (dt == PCAS_F32) {
+#define CALL(KK) warp_jac_k<float, KK>(v, f0, mean, U, wv, out, s, live)
+        PCAS_K_SWITCH(K, CALL)
+#undef CALL
+    }
+#define CALL(KK) warp_jac_k<double, KK>(v, f0, mean, U, wv, out, s, live)
     PCAS_K_SWITCH(K, CALL)
 #undef CALL
 }

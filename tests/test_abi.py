@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version_and_status_strings(L):
-    assert L.pcas_abi_version() == 7
+    assert L.pcas_abi_version() == 8
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.pcas_status_string(code)
     assert L.pcas_last_error() == b""
@@ -207,7 +207,7 @@ def test_solve_option_and_input_validation(L, geom):
     assert call(B.default_opts(beta_lo=0.9)) == EINVAL
     assert call(B.default_opts(locate=1, c0_mm=(0.0, float("nan"), 0.0))) == EINVAL
     assert call(B.default_opts(), K=0) == EINVAL
-    assert call(B.default_opts(grad_mode=2)) == EINVAL
+    assert call(B.default_opts(grad_mode=3)) == EINVAL
     assert call(B.default_opts(profile=-1)) == EINVAL
     assert call(B.default_opts(profile=B.PROFILE_ALL + 1)) == EINVAL
     assert L.solve_projection(1, ctypes.byref(v), ctypes.byref(p), 3, FAKE, None, FAKE, FAKE, good_w,
@@ -227,7 +227,7 @@ def test_objective_gradient_validation(L, geom):
         return L.objective_gradient(0, ctypes.byref(v), ctypes.byref(p), K, FAKE, None, FAKE, FAKE,
                                     w, 1, mode, ws_ptr, ws_bytes, out, None)
 
-    assert call(mode=2) == EINVAL
+    assert call(mode=3) == EINVAL
     assert call(K=9) == EINVAL
     assert call(w=(ctypes.c_double * 3)(0.1, float("nan"), 0.3)) == ENONFIN
     assert call(ws_bytes=ws - 1) == EWS

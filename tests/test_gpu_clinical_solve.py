@@ -29,28 +29,32 @@ def clinical():
     return c, d, y, json.load(open(GOLDEN))
 
 
-def _solve(c, d, y, fit, method, polish=None):
+def _solve(c, d, y, fit, method, polish=None, grad_mode=None):
     """The benchmark's options (the library defaults, xtol 1e-7, localisation
-    on), with the method, fit and, when given, the polish step overridden."""
+    on), with the method, fit and, when given, the polish step and the
+    gradient route overridden."""
     kw = dict(xtol=1e-7, method=method, fit_intensity=int(fit), locate=1,
               c0_mm=tuple(c.tumour_c0))
+    if grad_mode is not None:
+        kw["grad_mode"] = grad_mode
     if polish is not None:
         kw["polish"] = polish
     opts = B.default_opts(**kw)
     return B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K), opts)
 
 
+@pytest.mark.parametrize("grad_mode", [1, 2])
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
-def test_clinical_timed_solve_matches_oracle_minimiser(clinical, fit, method):
+def test_clinical_timed_solve_matches_oracle_minimiser(clinical, fit, method, grad_mode):
     """The configuration bench.py times (default options, which include the
-    polish step): w within 1e-4 of the FP64 minimiser, tumour position within
-    0.05 mm."""
+    polish step), by the back-projection route and by the fused evaluation:
+    w within 1e-4 of the FP64 minimiser, tumour position within 0.05 mm."""
     c, d, y, gold = clinical
     ref = gold["fit" if fit else "nofit"]
     assert gold["workload"] == c.name and gold["angle"] == c.proj.angle
-    say("clinical default solve fit", fit, "method", method)
-    w, rep = _solve(c, d, y, fit, method)
+    say("clinical default solve fit", fit, "method", method, "grad_mode", grad_mode)
+    w, rep = _solve(c, d, y, fit, method, grad_mode=grad_mode)
     w_ref = np.array(ref["w"])
     err = np.linalg.norm(w - w_ref) / np.linalg.norm(w_ref)
     say("gpu", w, rep["status"], rep["n_fevals"], rep["n_grads"], "err", err)
@@ -88,7 +92,7 @@ def test_clinical_speculation_is_bit_identical(clinical, method):
     launches."""
     c, d, y, _ = clinical
     say("clinical speculation on/off, method", method)
-    kw = dict(xtol=1e-7, method=method, locate=1, c0_mm=tuple(c.tumour_c0))
+    kw = dict(xtol=1e-7, method=method, locate=1, c0_mm=tuple(c.tumour_c0), grad_mode=1)
     w0, r0 = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
                                 B.default_opts(speculate=0, **kw))
     w1, r1 = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),

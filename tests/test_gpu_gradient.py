@@ -1,7 +1,8 @@
-"""objective_gradient through the C ABI: J, (a, b) and dJ/dw by both routes
-(projected Jacobian volumes, grad_mode 0; back-projection + Jacobian chain,
-grad_mode 1) against the FP64 oracle's objective and Appendix gradient, and
-the solve by either route."""
+"""objective_gradient through the C ABI: J, (a, b) and dJ/dw by the three
+routes (projected Jacobian volumes, grad_mode 0; back-projection + Jacobian
+chain, grad_mode 1; the fused evaluation that projects f and its Jacobian
+volumes together, grad_mode 2) against the FP64 oracle's objective and
+Appendix gradient, and the solve by each route."""
 import numpy as np
 import pytest
 
@@ -28,7 +29,7 @@ def _oracle(c, y, w, fit):
 def _check(c, d, y, w, fit, tol_g, tol_j):
     J_o, a_o, b_o, g_o = _oracle(c, y, w, fit)
     gs = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         J, a, b, g = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w,
                                           fit_intensity=fit, grad_mode=mode)
         say(f"mode {mode}: J {J:.10e} (oracle {J_o:.10e}) g {g} (oracle {g_o})")
@@ -41,14 +42,15 @@ def _check(c, d, y, w, fit, tol_g, tol_j):
 
 @pytest.mark.parametrize("fit", [True, False])
 def test_small_f64_both_routes(torch, fit):
-    """Ragged anisotropic 40x36x28 FP64 case: both routes reach the oracle's
-    gradient to rounding and agree with each other."""
+    """Ragged anisotropic 40x36x28 FP64 case: every route reaches the oracle's
+    gradient to rounding and they agree with each other."""
     c = synth.small(dtype="f64", seed=5)
     d = Dev(c)
     y = measured(c)
     w = c.w_star + 0.3 * np.array([1.0, -0.5, 0.8])
-    g0, g1 = _check(c, d, y, w, fit, 1e-10, 1e-12)
+    g0, g1, g2 = _check(c, d, y, w, fit, 1e-10, 1e-12)
     assert np.linalg.norm(g0 - g1) <= 1e-11 * np.linalg.norm(g1)
+    assert np.linalg.norm(g2 - g1) <= 1e-11 * np.linalg.norm(g1)
 
 
 def test_tiny_f64_at_zero(torch):
@@ -72,7 +74,7 @@ def test_small_f64_angles(torch, angle):
 
 def test_clinical_f32(torch):
     """256x256x128 FP32, K = 3, 512x384 detector, away from the optimum
-    (w* + 0.3 xi): both routes within 1e-4 of the FP64 oracle."""
+    (w* + 0.3 xi): every route within 1e-4 of the FP64 oracle."""
     c = synth.clinical()
     d = Dev(c)
     y = measured(c)
@@ -81,16 +83,18 @@ def test_clinical_f32(torch):
     _check(c, d, y, np.asarray(w, dtype=np.float64), True, 1e-4, 1e-5)
 
 
-def test_clinical_k5_f32_projected(torch):
-    """K = 5 modes: the projected-Jacobian route with five volumes at once."""
+@pytest.mark.parametrize("mode", [0, 2])
+def test_clinical_k5_f32_projected(torch, mode):
+    """K = 5 modes: the projected-Jacobian route with five volumes at once,
+    and the fused evaluation with six."""
     c = synth.clinical_k5()
     d = Dev(c)
     y = measured(c)
     w = 0.5 * c.w_star
     J_o, a_o, b_o, g_o = _oracle(c, y, w, True)
     J, a, b, g = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w,
-                                      grad_mode=0)
-    say("K=5", g, g_o)
+                                      grad_mode=mode)
+    say("K=5 mode", mode, g, g_o)
     assert abs(J - J_o) <= 1e-5 * J_o
     assert np.linalg.norm(g - g_o) <= 1e-4 * np.linalg.norm(g_o)
 
@@ -132,8 +136,9 @@ def test_small_f32_extreme_K(torch, K):
     d = Dev(c)
     y = measured(c)
     w = c.w_star + 0.2 * np.linspace(-1.0, 1.0, K)
-    g0, g1 = _check(c, d, y, w, True, 1e-4, 1e-5)
+    g0, g1, g2 = _check(c, d, y, w, True, 1e-4, 1e-5)
     assert np.linalg.norm(g0 - g1) <= 1e-5 * np.linalg.norm(g1)
+    assert np.linalg.norm(g2 - g0) <= 1e-5 * np.linalg.norm(g0)
 
 
 # Geometries that stress the FP32 gradient's 32-bit accumulators: their
@@ -166,23 +171,25 @@ def test_f32_gradient_stress_geometries(torch, name):
     d = Dev(c)
     y = measured(c)
     w = c.w_star + np.array([0.3, -0.2, 0.25])
-    g0, g1 = _check(c, d, y, w, True, 1e-4, 1e-5)
+    g0, g1, g2 = _check(c, d, y, w, True, 1e-4, 1e-5)
     assert np.linalg.norm(g0 - g1) <= 1e-5 * np.linalg.norm(g1)
+    assert np.linalg.norm(g2 - g0) <= 1e-5 * np.linalg.norm(g0)
 
 
 def test_solve_same_by_either_route(torch):
-    """FP64 small solve: both gradient routes converge to the same w."""
+    """FP64 small solve: every gradient route converges to the same w."""
     c = synth.small(dtype="f64", seed=5)
     d = Dev(c)
     y = to_dev(measured(c), d.dt)
     ws = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         w, rep = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
                                     B.default_opts(grad_mode=mode))
         say(f"mode {mode}", w, rep["status"], rep["iters"])
         assert rep["status"] in ("converged", "line_search")
         ws.append(w)
     assert np.linalg.norm(ws[0] - ws[1]) <= 1e-8 * np.linalg.norm(ws[1])
+    assert np.linalg.norm(ws[2] - ws[1]) <= 1e-8 * np.linalg.norm(ws[1])
 
 
 def test_errors(torch):
@@ -190,7 +197,7 @@ def test_errors(torch):
     d = Dev(c)
     y = to_dev(measured(c), d.dt)
     with pytest.raises(B.PcasError):
-        B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, y, c.w_star, grad_mode=2)
+        B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, y, c.w_star, grad_mode=3)
     with pytest.raises(B.PcasError):
         B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, y, c.w_star * np.nan)
     flat = torch.ones_like(y)
@@ -221,3 +228,27 @@ def test_adjoint32_on_stress_geometries(torch, name):
     say("rel L2", err, "max |diff| / max", worst)
     assert err <= 1e-5
     assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_evaluation_launches(torch, dtype):
+    """A grad_mode 2 solve launches the fused pair once per evaluation and
+    nothing else for its gradients: every gradient comes from the sums its
+    evaluation left, at the fit the machine chose."""
+    c = synth.small(dtype=dtype, seed=6)
+    d = Dev(c)
+    y = to_dev(measured(c), d.dt)
+    opts = B.default_opts(grad_mode=2, xtol=1e-7 if dtype == "f32" else 1e-10,
+                          profile=B.PROFILE_ALL)
+    w, rep = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K), opts)
+    L = rep["kernel_launches"]
+    say(dtype, rep["status"], rep["n_fevals"], rep["n_grads"], L)
+    assert rep["status"] in ("converged", "max_iter", "line_search")
+    assert L["warp_jac"] == rep["n_fevals"] and L["drr_forward_eval"] == rep["n_fevals"]
+    assert L["warp_pca"] == 0 and L["drr_forward"] == 0
+    assert L["drr_adjoint_chain"] == 0 and L["spec_skipped"] == 0 and L["drr_forward_dot"] == 0
+    assert rep["n_grads"] >= 1
+    ref, rep1 = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
+                                   B.default_opts(xtol=opts.xtol))
+    say("w", w, "route 1", ref)
+    assert np.linalg.norm(w - ref) <= 1e-4 * np.linalg.norm(ref)

@@ -43,13 +43,15 @@ def _minimiser(c, y, fit=True):
     return _MINIMISERS[key]
 
 
-def test_tiny_cg_matches_oracle(torch):
-    """64^3 FP64, 128x128 detector, 1% noise, CG from w0 = 0 (the tiny workload)."""
+@pytest.mark.parametrize("grad_mode", [1, 2])
+def test_tiny_cg_matches_oracle(torch, grad_mode):
+    """64^3 FP64, 128x128 detector, 1% noise, CG from w0 = 0 (the tiny
+    workload), by the back-projection route and by the fused evaluation."""
     c = synth.tiny()
     d = Dev(c)
     y = measured(c)
-    say("tiny CG solve")
-    opts = B.default_opts(locate=1, c0_mm=tuple(c.tumour_c0))
+    say("tiny CG solve, grad_mode", grad_mode)
+    opts = B.default_opts(locate=1, c0_mm=tuple(c.tumour_c0), grad_mode=grad_mode)
     w, rep = _gpu_solve(d, y, opts)
     w_o, info = _minimiser(c, y)
     say("gpu", w, rep)
@@ -147,9 +149,10 @@ def test_polish_reported_point_is_consistent(torch, method):
     assert abs(rep["gnorm"] - np.linalg.norm(g)) <= 1e-12 * np.linalg.norm(g)
 
 
+@pytest.mark.parametrize("grad_mode", [1, 2])
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("fit", [True, False])
-def test_small_f32_solve_matches_oracle(torch, fit, method):
+def test_small_f32_solve_matches_oracle(torch, fit, method, grad_mode):
     """Ragged anisotropic FP32 case with the default options (the polish step
     on): converged w within 1e-4 of the FP64 oracle's minimiser.
     (Comparisons of FP32 values of J stop at J's rounding noise, about 3e-7 J
@@ -158,8 +161,8 @@ def test_small_f32_solve_matches_oracle(torch, fit, method):
     c = synth.small(dtype="f32", seed=6)
     d = Dev(c)
     y = measured(c)
-    say("small f32 solve fit=", fit, "method", method)
-    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method)
+    say("small f32 solve fit=", fit, "method", method, "grad_mode", grad_mode)
+    opts = B.default_opts(fit_intensity=int(fit), xtol=1e-7, method=method, grad_mode=grad_mode)
     assert opts.polish == 1
     w, rep = _gpu_solve(d, y, opts)
     w_o, info = _minimiser(c, y, fit)
