@@ -41,12 +41,18 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # Algorithmic flops per projection sample.  Forward: position e + sh d
 # (3 fma = 6), fractions (3), trilinear value as 7 lerps of 3 flops (21),
 # accumulation (1) = 31.  Back-projection: position (6), fractions (3),
-# corner weights (9), 8 weighted accumulations (16) = 34.  Projection of K
-# volumes at once: position and fractions once (9), then 22 per volume (the
-# fused evaluation projects K + 1).
+# corner weights (9), 8 weighted accumulations (16) = 34.  Projection of nv
+# volumes at once: position and fractions once (9), then either 22 per volume
+# (lerps) or the eight corner weights once (15) and 16 per volume (eight
+# products and the accumulation), whichever is fewer; the fused evaluation
+# projects K + 1 volumes.
+def proj_flops(nv: int) -> float:
+    return float(min(9 + 22 * nv, 24 + 16 * nv))
+
+
 def flops_per_sample(kernel: str, K: int) -> float:
-    return {"drr_forward": 31.0, "drr_adjoint": 34.0, "drr_adjoint_chain": 34.0,
-            "drr_forward_dot": 9.0 + 22.0 * K, "drr_forward_eval": 9.0 + 22.0 * (K + 1)}[kernel]
+    return {"drr_forward": proj_flops(1), "drr_adjoint": 34.0, "drr_adjoint_chain": 34.0,
+            "drr_forward_dot": proj_flops(K), "drr_forward_eval": proj_flops(K + 1)}[kernel]
 
 
 # Jacobian chain per voxel: field 6K, displacement split 6, Eq. A.8 and its

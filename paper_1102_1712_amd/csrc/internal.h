@@ -338,9 +338,10 @@ hipError_t launch_drr_forward_eval(pcas_dtype dt, const VolDims &v, const Frame 
                                    double *partials, uint32_t *counter, double *sums,
                                    hipStream_t s);
 // The warped image and its K Jacobian volumes in one voxel pass: out[0..N)
-// = f exactly as launch_warp_pca computes it, out[(1 + k) N ..) = J_k exactly
-// as launch_jacobian computes it.  With live (launch_brick_live), voxels of
-// bricks no ray reaches are skipped (left as they were).
+// = f (the quantity launch_warp_pca computes), out[(1 + k) N ..) = J_k (the
+// quantity launch_jacobian computes), from one read of each voxel's f0
+// neighbours.  With live (launch_brick_live), voxels of bricks no ray
+// reaches are skipped (left as they were).
 hipError_t launch_warp_jac(pcas_dtype dt, const VolDims &v, int K, const void *f0,
                            const void *mean, const void *U, const double *w, void *out,
                            hipStream_t s, const uint8_t *live = nullptr);

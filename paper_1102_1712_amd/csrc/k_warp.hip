@@ -125,12 +125,56 @@ __global__ __launch_bounds__(256) void k_warp_pca(VolDims vd, const T *__restric
     warp_pca_block<T, K>(vd, f0, mean, U, w, f, blockIdx.x, gridDim.x, live);
 }
 
+// Value (Eqs. A.3 / A.5) and diagonal Jacobian (Eq. A.8 and its analogues,
+// per mm) of the pulled-back image at voxel (i, j, k) displaced by x (mm),
+// from one read of the eight f0 neighbours, each taken as zero outside the
+// grid.  Offsets are 32-bit (volumes hold fewer than 2^31 voxels).
+template <typename T>
+__device__ __forceinline__ T warp_value_jac(const T *__restrict__ f0, int n0, int n1, int n2,
+                                            int i, int j, int k, const T (&x)[3], T is0, T is1,
+                                            T is2, T (&jac)[3]) {
+    int o0, o1, o2;
+    T z1, z2, z3;   // the Appendix's z_1..z_3
+    split_disp(x[0], is0, o0, z1);
+    split_disp(x[1], is1, o1, z2);
+    split_disp(x[2], is2, o2, z3);
+    const int l = i + o0, m = j + o1, n = k + o2;
+    const bool vl = (unsigned)l < (unsigned)n0, vl1 = (unsigned)(l + 1) < (unsigned)n0;
+    const bool vm = (unsigned)m < (unsigned)n1, vm1 = (unsigned)(m + 1) < (unsigned)n1;
+    const bool vn = (unsigned)n < (unsigned)n2, vn1 = (unsigned)(n + 1) < (unsigned)n2;
+    jac[0] = jac[1] = jac[2] = (T)0;
+    if (!((vl || vl1) && (vm || vm1) && (vn || vn1))) return (T)0;
+    const int cl = min(max(l, 0), n0 - 1), cl1 = min(max(l + 1, 0), n0 - 1);
+    const int rm = min(max(m, 0), n1 - 1) * n0, rm1 = min(max(m + 1, 0), n1 - 1) * n0;
+    const int pn = min(max(n, 0), n2 - 1) * (n0 * n1), pn1 = min(max(n + 1, 0), n2 - 1) * (n0 * n1);
+    auto F = [&](int c, int r, int p, bool ok) -> T { return ok ? f0[p + r + c] : (T)0; };
+    const T f000 = F(cl, rm, pn, vl && vm && vn), f100 = F(cl1, rm, pn, vl1 && vm && vn);
+    const T f010 = F(cl, rm1, pn, vl && vm1 && vn), f110 = F(cl1, rm1, pn, vl1 && vm1 && vn);
+    const T f001 = F(cl, rm, pn1, vl && vm && vn1), f101 = F(cl1, rm, pn1, vl1 && vm && vn1);
+    const T f011 = F(cl, rm1, pn1, vl && vm1 && vn1), f111 = F(cl1, rm1, pn1, vl1 && vm1 && vn1);
+    const T w1 = (T)1 - z1, w2 = (T)1 - z2, w3 = (T)1 - z3;
+    // value: the tent-weighted sum along x, then y, then z
+    const T x00 = w1 * f000 + z1 * f100, x10 = w1 * f010 + z1 * f110;
+    const T x01 = w1 * f001 + z1 * f101, x11 = w1 * f011 + z1 * f111;
+    const T y0 = w2 * x00 + z2 * x10, y1 = w2 * x01 + z2 * x11;
+    // Eq. A.8 and its analogues for the other axes (index units), then per mm
+    const T g1 = ((f100 - f000) * w2 + (f110 - f010) * z2) * w3 +
+                 ((f101 - f001) * w2 + (f111 - f011) * z2) * z3;
+    const T g2 = ((f010 - f000) * w1 + (f110 - f100) * z1) * w3 +
+                 ((f011 - f001) * w1 + (f111 - f101) * z1) * z3;
+    const T g3 = ((f001 - f000) * w1 + (f101 - f100) * z1) * w2 +
+                 ((f011 - f010) * w1 + (f111 - f110) * z1) * z2;
+    jac[0] = g1 * is0;
+    jac[1] = g2 * is1;
+    jac[2] = g3 * is2;
+    return w3 * y0 + z3 * y1;
+}
+
 // The warped image and its K Jacobian volumes J_k = sum_c U_kc df/dx_c
 // (Eq. A.8 per mm, through the modes) in one voxel pass, for the fused
-// evaluation that projects all K + 1 volumes together.  The field, f and
-// J_k take exactly the operations of k_warp_pca and k_jacobian, so the three
-// kernels agree bit for bit; the eight f0 neighbours are read once for the
-// value and once for the derivatives, the second time from cache.
+// evaluation that projects all K + 1 volumes together.  The field is formed
+// as k_warp_pca forms it; the value and the three derivatives share one
+// read of the eight f0 neighbours.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_warp_jac(VolDims vd, const T *__restrict__ f0,
                                                   const T *__restrict__ mean,
@@ -153,12 +197,10 @@ __global__ __launch_bounds__(256) void k_warp_jac(VolDims vd, const T *__restric
     T wk[K];
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) wk[kk] = (T)w.w[kk];
-    const T is0 = (T)vd.inv_s[0], is1 = (T)vd.inv_s[1], is2 = (T)vd.inv_s[2];
     T u[K][3], x[3], jac[3];
     voxel_field<T, K, true>(mean, U, wk, N, v, u, x);
-    out[v] = warp_gather(f0, vd.n0, vd.n1, vd.n2, i, j, k, x[0], x[1], x[2], is0, is1, is2);
-    if (!voxel_jacobian(f0, vd.n0, vd.n1, vd.n2, i, j, k, x, is0, is1, is2, jac))
-        jac[0] = jac[1] = jac[2] = (T)0;
+    out[v] = warp_value_jac(f0, vd.n0, vd.n1, vd.n2, i, j, k, x, (T)vd.inv_s[0],
+                            (T)vd.inv_s[1], (T)vd.inv_s[2], jac);
 #pragma unroll
     for (int kk = 0; kk < K; ++kk)
         out[(int64_t)(kk + 1) * N + v] =
