@@ -165,7 +165,10 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
     constexpr int CAPT = fwd_lds_bytes(NV) / (int)sizeof(T);   // all volumes
     constexpr int CAP = CAPT / NV;                               // one volume's box
     constexpr int ES = (int)sizeof(T);
-    __shared__ T box[CAPT];
+    // NV >= 3: the box interleaves the volumes (element t of volume v at
+    // t * NV + v), so that one sample's corners of every volume sit together
+    constexpr bool IL = NV >= 3;
+    __shared__ __align__(16) T box[CAPT];
     __shared__ int sbox[FWD_MAX_SLABS][4];
     __shared__ int sred[3];
     const int n0 = vd.n0, n1 = vd.n1, n2 = vd.n2;
@@ -301,13 +304,24 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                     const int tz = (int)(((float)q + 0.5f) * iey);
                     const int ty = q - __mul24(tz, ext[1]);
                     const int go = (gbase + tx + __mul24(ty, n0) + tz * (n0 * n1)) * ES;
+                    if constexpr (IL) {
+                        T val[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) box[v * size + t] = buf_load(rf[v], go, 0, T());
+                        for (int v = 0; v < NV; ++v) val[v] = buf_load(rf[v], go, 0, T());
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) box[t * NV + v] = val[v];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) box[v * size + t] = buf_load(rf[v], go, 0, T());
+                    }
                 }
             }
             __syncthreads();
-            // byte pitches of the box; offsets fit 24-bit products
-            const int px = ex * ES, pxy = exy * ES, pv = size * ES;
+            // byte pitches of the box (of one voxel's NV values when
+            // interleaved); offsets fit 24-bit products
+            constexpr int EV = IL ? NV * ES : ES;
+            const int px = ex * EV, pxy = exy * EV;
+            [[maybe_unused]] const int pv = size * ES;
             const char *boxb = (const char *)box;
             T part[NV];   // this slab's samples, added to acc once
 #pragma unroll
@@ -323,7 +337,8 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                     const bool in = (unsigned)lb < (unsigned)(ext[B2] - 1) &&
                                     (unsigned)lz < (unsigned)(ext[2] - 1);
                     miss |= !in;
-                    const int off = in ? lx * ES + __mul24(ly, px) + __mul24(lz, pxy) : 0;
+                    const int off =
+                        in ? (lx + __mul24(ly, ex) + __mul24(lz, exy)) * EV : 0;
                     if constexpr (NV >= 3) {
                         // several volumes: the eight corner weights once, then
                         // eight products per volume instead of seven lerps
@@ -332,19 +347,19 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                         const T w000 = a00 * c2, w100 = a10 * c2, w010 = a01 * c2, w110 = a11 * c2;
                         const T w001 = a00 * z[2], w101 = a10 * z[2], w011 = a01 * z[2],
                                 w111 = a11 * z[2];
+                        const char *c = boxb + off;
+                        const T *q0 = (const T *)c, *q1 = (const T *)(c + px);
+                        const T *q2 = (const T *)(c + pxy), *q3 = (const T *)(c + pxy + px);
 #pragma unroll
                         for (int v = 0; v < NV; ++v) {
-                            const char *c = boxb + (off + v * pv);
-                            const T *q0 = (const T *)c, *q1 = (const T *)(c + px);
-                            const T *q2 = (const T *)(c + pxy), *q3 = (const T *)(c + pxy + px);
-                            T t = w000 * q0[0];
-                            t = fma_t(w100, q0[1], t);
-                            t = fma_t(w010, q1[0], t);
-                            t = fma_t(w110, q1[1], t);
-                            t = fma_t(w001, q2[0], t);
-                            t = fma_t(w101, q2[1], t);
-                            t = fma_t(w011, q3[0], t);
-                            t = fma_t(w111, q3[1], t);
+                            T t = w000 * q0[v];
+                            t = fma_t(w100, q0[NV + v], t);
+                            t = fma_t(w010, q1[v], t);
+                            t = fma_t(w110, q1[NV + v], t);
+                            t = fma_t(w001, q2[v], t);
+                            t = fma_t(w101, q2[NV + v], t);
+                            t = fma_t(w011, q3[v], t);
+                            t = fma_t(w111, q3[NV + v], t);
                             part[v] += t;
                         }
                     } else {
