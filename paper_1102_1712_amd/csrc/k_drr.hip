@@ -350,17 +350,17 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                         const char *c = boxb + off;
                         const T *q0 = (const T *)c, *q1 = (const T *)(c + px);
                         const T *q2 = (const T *)(c + pxy), *q3 = (const T *)(c + pxy + px);
+                        // the slab's running sum takes the eight products directly
 #pragma unroll
                         for (int v = 0; v < NV; ++v) {
-                            T t = w000 * q0[v];
+                            T t = fma_t(w000, q0[v], part[v]);
                             t = fma_t(w100, q0[NV + v], t);
                             t = fma_t(w010, q1[v], t);
                             t = fma_t(w110, q1[NV + v], t);
                             t = fma_t(w001, q2[v], t);
                             t = fma_t(w101, q2[NV + v], t);
                             t = fma_t(w011, q3[v], t);
-                            t = fma_t(w111, q3[NV + v], t);
-                            part[v] += t;
+                            part[v] = fma_t(w111, q3[NV + v], t);
                         }
                     } else {
 #pragma unroll
