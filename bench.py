@@ -395,14 +395,15 @@ def serve_mode(args) -> int:
         arrivals.append(SV.Arrival(t=float(times[j]), model=m, proj=pj, y=y, w_true=w_true))
         del rays, f, p
     torch.cuda.synchronize()
-    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method]) for m in range(2)}
+    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=args.grad_mode)
+            for m in range(2)}
     Ks = {m: cases[m].K for m in range(2)}
 
     def new_server(share=args.substep_share):
         srv0 = B.Server(B.Server.reserved_bytes(args.slots) + (64 << 20), max_active=args.slots)
         for c, d in zip(cases, devs):
             srv0.add_model(c.vol, d["f0"], d["mean"], d["U"])
-        need = max(srv0.request_bytes(m, cases[m].proj) for m in range(2))
+        need = max(srv0.request_bytes(m, cases[m].proj, opts[m]) for m in range(2))
         srv0.close()
         srv = B.Server(B.Server.reserved_bytes(args.slots) + args.slots * need + (1 << 20),
                        max_active=args.slots)
@@ -412,6 +413,7 @@ def serve_mode(args) -> int:
         return srv, need
 
     out = {"mode": "serve", "requests": n, "rate_hz": args.rate, "slots": args.slots,
+           "grad_mode": args.grad_mode,
            "substep_share": args.substep_share,
            "models": [{"workload": c.name, "volume": list(c.vol.n), "K": c.K,
                        "detector": [c.proj.nu, c.proj.nv], "pitch_mm": c.proj.pitch_u,

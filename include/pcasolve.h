@@ -422,10 +422,12 @@ int pcas_fit_predictor(int32_t T, int32_t K, int32_t L, const double *w_train,
  * tumour localisation), batching each kind of operation for all requests
  * of one dtype and K (or slab axis) into one launch, reads back all their
  * scalars in one transfer and returns the number of requests completed.
+ * A grad_mode 2 request's evaluation is the fused one and its gradients
+ * follow from the evaluation's sums on the host, without a step of their own.
  * A batched block runs what the request's own launch would run, so every
  * result equals solve_projection's for the same request, bit for bit.
- * Requests run the solve of their opts (method, fit, tolerances, locate);
- * grad_mode must be 1.  report.kernel_ms is not filled.
+ * Requests run the solve of their opts (method, fit, tolerances, locate,
+ * grad_mode 1 or 2).  report.kernel_ms is not filled.
  * The server keeps pinned host staging for its tables and read-backs.
  * Synchronous steps on `stream`; one thread at a time per server. */
 typedef struct pcas_server pcas_server;
@@ -437,8 +439,11 @@ int pcas_server_destroy(pcas_server *server);
 int pcas_server_add_model(pcas_server *server, pcas_dtype dtype, const pcas_vol *vol, int32_t K,
                           const void *f0, const void *mean, const void *U, int32_t *model_id);
 /* Arena bytes a request of this model and geometry occupies while admitted
- * (0 for an invalid model or geometry). */
-size_t pcas_server_request_bytes(pcas_server *server, int32_t model_id, const pcas_proj *proj);
+ * with these options (opts may be NULL: the defaults); a grad_mode 2
+ * request also holds the warped image with its K Jacobian volumes.  0 for
+ * an invalid model or geometry. */
+size_t pcas_server_request_bytes(pcas_server *server, int32_t model_id, const pcas_proj *proj,
+                                 const pcas_opts *opts);
 /* w0: host double[K]; request_id: unique, increasing.  PCAS_EWORKSPACE if
  * the request could never fit in the arena. */
 int pcas_server_submit(pcas_server *server, int32_t model_id, const pcas_proj *proj,

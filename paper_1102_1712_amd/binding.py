@@ -143,7 +143,7 @@ def lib():
             "pcas_server_create": (I32, [P, SZ, I32, P, ctypes.POINTER(P)]),
             "pcas_server_destroy": (I32, [P]),
             "pcas_server_add_model": (I32, [P, I32, VP, I32, P, P, P, ctypes.POINTER(I32)]),
-            "pcas_server_request_bytes": (SZ, [P, I32, PP]),
+            "pcas_server_request_bytes": (SZ, [P, I32, PP, ctypes.POINTER(Opts)]),
             "pcas_server_submit": (I32, [P, I32, PP, P, DP, ctypes.POINTER(Opts),
                                          ctypes.POINTER(I64)]),
             "pcas_server_set_substep_share": (I32, [P, D]),
@@ -595,9 +595,10 @@ class Server:
         self._models.append((vol, K, f0.dtype, (f0, mean, U)))
         return int(mid.value)
 
-    def request_bytes(self, model_id: int, proj) -> int:
+    def request_bytes(self, model_id: int, proj, opts: Optional[Opts] = None) -> int:
+        o = default_opts() if opts is None else opts
         return int(lib().pcas_server_request_bytes(self._h, int(model_id),
-                                                   ctypes.byref(c_proj(proj))))
+                                                   ctypes.byref(c_proj(proj)), ctypes.byref(o)))
 
     def submit(self, model_id: int, proj, y, w0, opts: Optional[Opts] = None) -> int:
         vol, K, dt, _ = self._models[model_id]

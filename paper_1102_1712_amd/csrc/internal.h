@@ -436,6 +436,15 @@ FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, 
                     uint32_t *counter, double *sums);
 hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *jobs, int njobs,
                                          int total_blocks, hipStream_t s);
+// Several requests' fused-evaluation projections (launch_drr_forward_eval;
+// J.f holds the K + 1 volumes, J.fit the reference fit) of one dtype, K and
+// slab axis in one launch.
+hipError_t launch_drr_forward_eval_batch(pcas_dtype dt, int K, int axis, const FwdJob *jobs,
+                                         int njobs, int total_blocks, hipStream_t s);
+// Several requests' warps with their Jacobian volumes (launch_warp_jac; J.f
+// receives the K + 1 volumes) of one dtype and K in one launch.
+hipError_t launch_warp_jac_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,
+                                 int total_blocks, hipStream_t s);
 hipError_t launch_residual_batch(pcas_dtype dt, const ResJob *jobs, int njobs, int total_blocks,
                                  hipStream_t s);
 AdjJob make_adj_job(const VolDims &v, const Frame &fr, int K, const void *rays, const void *p,

@@ -480,6 +480,19 @@ __global__ __launch_bounds__(256) void k_drr_forward_batch(const FwdJob *__restr
                                           J.out, blockIdx.x - J.block0, J.nblocks);
 }
 
+// Several requests' fused-evaluation projections in one launch.
+template <typename T, int AX, int K>
+__global__ __launch_bounds__(256) void k_drr_forward_eval_batch(const FwdJob *__restrict__ jobs,
+                                                                int njobs) {
+    const int j = job_of(jobs, njobs);
+    const FwdJob &J = jobs[j];
+    drr_forward_block<T, AX, K + 1, FWD_EVAL>(J.vd, J.fr, J.tiles_u, J.slab,
+                                              (const RayRec<T> *)J.rays, (const T *)J.f,
+                                              (T *)J.p, (const T *)J.y, 0.0, 0.0, J.fit,
+                                              J.partials, J.counter, J.out,
+                                              blockIdx.x - J.block0, J.nblocks);
+}
+
 int drr_forward_blocks(int nu, int nv) {
     return ((nu + TILE_U - 1) / TILE_U) * ((nv + TILE_V - 1) / TILE_V);
 }
@@ -616,6 +629,37 @@ hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *
         else
             hipLaunchKernelGGL((k_drr_forward_batch<double, 1>), grid, block, 0, s, jobs, njobs);
     }
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+static void eval_batch_axis(int axis, const FwdJob *jobs, int njobs, int total_blocks,
+                            hipStream_t s) {
+    if (axis == 0)
+        hipLaunchKernelGGL((k_drr_forward_eval_batch<T, 0, K>), dim3(total_blocks), dim3(256), 0, s,
+                           jobs, njobs);
+    else
+        hipLaunchKernelGGL((k_drr_forward_eval_batch<T, 1, K>), dim3(total_blocks), dim3(256), 0, s,
+                           jobs, njobs);
+}
+
+hipError_t launch_drr_forward_eval_batch(pcas_dtype dt, int K, int axis, const FwdJob *jobs,
+                                         int njobs, int total_blocks, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+#define D(TT, KK)                                                                                  \
+    case KK:                                                                                       \
+        eval_batch_axis<TT, KK>(axis, jobs, njobs, total_blocks, s);                               \
+        break
+    if (dt == PCAS_F32) {
+        switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);
+                     D(float, 5); D(float, 6); D(float, 7); D(float, 8);
+                     default: return hipErrorInvalidValue; }
+    } else {
+        switch (K) { D(double, 1); D(double, 2); D(double, 3); D(double, 4);
+                     D(double, 5); D(double, 6); D(double, 7); D(double, 8);
+                     default: return hipErrorInvalidValue; }
+    }
+#undef D
     return hipGetLastError();
 }
 

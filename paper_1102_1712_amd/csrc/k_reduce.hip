@@ -166,7 +166,7 @@ static_assert(ADJ_THREADS <= GATHER_THREADS && FWD_THREADS <= GATHER_THREADS, "g
 __global__ __launch_bounds__(GATHER_THREADS) void k_gather_scalars(const double *const *__restrict__ src,
                                                                    double *__restrict__ dst, int count,
                                                                    const SumJob *__restrict__ sums) {
-    __shared__ double tot_s[RED_SLOTS];
+    __shared__ double tot_s[RED_SLOTS_WIDE];
     const int b = blockIdx.x;
     int lo = 0, hi = 0;
     if (sums && sums[b].ns > 0 && (!sums[b].gate || sums[b].gate[2] != 0.0)) {   // uniform
@@ -179,7 +179,16 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather_scalars(const double 
         case 5: finish_sum<5>(J, tot_s); break;
         case 6: finish_sum<6>(J, tot_s); break;
         case 7: finish_sum<7>(J, tot_s); break;
-        default: finish_sum<8>(J, tot_s); break;
+        case 8: finish_sum<8>(J, tot_s); break;
+        // the fused evaluation's 6 + 3K sums
+        case 9: finish_sum<9>(J, tot_s); break;
+        case 12: finish_sum<12>(J, tot_s); break;
+        case 15: finish_sum<15>(J, tot_s); break;
+        case 18: finish_sum<18>(J, tot_s); break;
+        case 21: finish_sum<21>(J, tot_s); break;
+        case 24: finish_sum<24>(J, tot_s); break;
+        case 27: finish_sum<27>(J, tot_s); break;
+        default: finish_sum<30>(J, tot_s); break;
         }
         __syncthreads();
         lo = J.offset;

@@ -176,13 +176,13 @@ __device__ __forceinline__ T warp_value_jac(const T *__restrict__ f0, int n0, in
 // as k_warp_pca forms it; the value and the three derivatives share one
 // read of the eight f0 neighbours.
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_warp_jac(VolDims vd, const T *__restrict__ f0,
-                                                  const T *__restrict__ mean,
-                                                  const T *__restrict__ U, WVec w,
-                                                  T *__restrict__ out,
-                                                  const uint8_t *__restrict__ live) {
+__device__ __forceinline__ void warp_jac_block(const VolDims &vd, const T *__restrict__ f0,
+                                               const T *__restrict__ mean,
+                                               const T *__restrict__ U, const WVec &w,
+                                               T *__restrict__ out, int lb, int nb,
+                                               const uint8_t *__restrict__ live) {
     const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = xcd_remap(lb, nb);
     const int v32 = b * (int)blockDim.x + (int)threadIdx.x;
     if (v32 >= (int)N) return;
     const int64_t v = v32;
@@ -205,6 +205,25 @@ __global__ __launch_bounds__(256) void k_warp_jac(VolDims vd, const T *__restric
     for (int kk = 0; kk < K; ++kk)
         out[(int64_t)(kk + 1) * N + v] =
             fma_t(u[kk][0], jac[0], fma_t(u[kk][1], jac[1], u[kk][2] * jac[2]));
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_warp_jac(VolDims vd, const T *__restrict__ f0,
+                                                  const T *__restrict__ mean,
+                                                  const T *__restrict__ U, WVec w,
+                                                  T *__restrict__ out,
+                                                  const uint8_t *__restrict__ live) {
+    warp_jac_block<T, K>(vd, f0, mean, U, w, out, blockIdx.x, gridDim.x, live);
+}
+
+// Several requests' warps with their Jacobian volumes in one launch.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_warp_jac_batch(const WarpJob *__restrict__ jobs,
+                                                        int njobs) {
+    const int j = job_of(jobs, njobs);
+    const WarpJob &J = jobs[j];
+    warp_jac_block<T, K>(J.vd, (const T *)J.f0, (const T *)J.mean, (const T *)J.U, J.w, (T *)J.f,
+                         blockIdx.x - J.block0, J.nblocks, J.live);
 }
 
 // Several requests' warps in one launch (jobs sorted by block0).
@@ -285,6 +304,11 @@ hipError_t warp_batch_k(const WarpJob *jobs, int njobs, int total_blocks, hipStr
     hipLaunchKernelGGL((k_warp_pca_batch<T, K>), dim3(total_blocks), dim3(256), 0, s, jobs, njobs);
     return hipGetLastError();
 }
+template <typename T, int K>
+hipError_t warp_jac_batch_k(const WarpJob *jobs, int njobs, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_warp_jac_batch<T, K>), dim3(total_blocks), dim3(256), 0, s, jobs, njobs);
+    return hipGetLastError();
+}
 }  // namespace
 
 hipError_t launch_warp_pca_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,
@@ -337,6 +361,19 @@ hipError_t launch_warp_jac(pcas_dtype dt, const VolDims &v, int K, const void *f
 #undef CALL
     }
 #define CALL(KK) warp_jac_k<double, KK>(v, f0, mean, U, wv, out, s, live)
+    PCAS_K_SWITCH(K, CALL)
+#undef CALL
+}
+
+hipError_t launch_warp_jac_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,
+                                 int total_blocks, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    if (dt == PCAS_F32) {
+#define CALL(KK) warp_jac_batch_k<float, KK>(jobs, njobs, total_blocks, s)
+        PCAS_K_SWITCH(K, CALL)
+#undef CALL
+    }
+#define CALL(KK) warp_jac_batch_k<double, KK>(jobs, njobs, total_blocks, s)
     PCAS_K_SWITCH(K, CALL)
 #undef CALL
 }

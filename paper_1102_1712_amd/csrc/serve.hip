@@ -72,6 +72,17 @@ struct Request {
     int spec_slot = 0;
     double spec_w[PCAS_MAX_K] = {0};
     int spec_grads = 0;
+    // grad_mode 2 (the fused evaluation): the projection plan of the K + 1
+    // volumes and, per line-search slot, the point and sums of its last
+    // evaluation, from which its gradient follows on the host
+    ForwardPlan plan_e{};
+    struct Fused {
+        bool valid = false;
+        double w[PCAS_MAX_K] = {0};
+        double a0 = 0.0, b0 = 0.0;
+        double m[6 + 3 * PCAS_MAX_K] = {0};
+    } fused[2];
+    bool fused_eval() const { return opts.grad_mode == 2; }
 
     double *scal() const { return (double *)(ws + L.scalars); }
     uint32_t *counters() const { return (uint32_t *)(ws + L.counters); }
@@ -156,8 +167,13 @@ size_t table_bytes(int max_active) {
     return align256(per * (size_t)max_active + 4096);
 }
 
-size_t request_bytes(const Model &md, const pcas_proj *proj) {
-    return solve_layout(md.dt, &md.vol, proj, md.K, false).total;
+// A request's workspace: the fused evaluation (grad_mode 2) also holds the
+// warped image with its K Jacobian volumes and the wider reduction scratch.
+SolveWs request_layout(const Model &md, const pcas_proj *proj, int grad_mode) {
+    return solve_layout(md.dt, &md.vol, proj, md.K, grad_mode == 2);
+}
+size_t request_bytes(const Model &md, const pcas_proj *proj, int grad_mode) {
+    return request_layout(md, proj, grad_mode).total;
 }
 
 void finish_request(pcas_server *S, Request *r, int status) {
@@ -348,6 +364,22 @@ void take_speculative_gradient(pcas_server *S, Request *r, const double *sc, int
     advance(S, r, sc, n_done);   // OP_GRAD: the gradient at sc[8..]
 }
 
+// grad_mode 2: while the machine asks for the gradient at the point whose
+// sums a slot holds, the gradient follows from them on the host (as
+// solve_projection forms it) and the machine advances without a launch.
+void feed_fused_gradients(pcas_server *S, Request *r, int32_t *n_done) {
+    const int K = S->models[r->model].K;
+    while (r->fused_eval() && r->phase == PH_RUN) {
+        const SolveOp &op = r->m.op();
+        if (op.kind != OP_GRAD) return;
+        const Request::Fused &F = r->fused[op.slot];
+        if (!F.valid || memcmp(F.w, op.w, K * sizeof(double))) return;
+        double sc[GATHER] = {0};
+        gradient_from_moments(F.m, K, op.ab[0], op.ab[1], F.a0, F.b0, sc + 8);
+        advance(S, r, sc, n_done);   // OP_GRAD: the gradient at sc[8..]
+    }
+}
+
 // One pass: the next operation of every request in `set`, batched by kind
 // (one launch per kind, dtype and K or slab axis), one read-back, and every
 // machine advanced.  Finished requests leave with phase PH_DONE.
@@ -356,8 +388,8 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
 
     // this pass's operations, batched
     typedef std::pair<int, int> DK;   // (dtype, K) or (dtype, axis)
-    Groups<WarpJob, DK> warps;
-    Groups<FwdJob, DK> fwds;
+    Groups<WarpJob, DK> warps, warpjacs;
+    Groups<FwdJob, DK> fwds, fwd_evals;   // fwd_evals: ((dtype, K), axis) as (16 dtype + K, axis)
     Groups<ResJob, int> ress;
     Groups<AdjJob, DK> adjs;
     std::vector<SpecJob> specs;
@@ -374,7 +406,52 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
         }
         if (r->phase != PH_RUN) continue;
         const SolveOp &op = r->m.op();
-        if (op.kind == OP_EVAL) {
+        if (op.kind == OP_EVAL && r->fused_eval()) {
+            // the warp with the Jacobian volumes, then one projection of all
+            // K + 1 that leaves the objective's moments and the gradient's
+            // sums (FP32: finished by the gather; FP64: by the projection's
+            // last block, then the two-pass residual below writes J, a, b
+            // in front of the gradient's sums)
+            r->fused[op.slot].valid = false;
+            WarpJob wj;
+            wj.vd = md.vd;
+            wj.f0 = md.f0;
+            wj.mean = md.mean;
+            wj.U = md.U;
+            wj.w = WVec{};
+            for (int k = 0; k < md.K; ++k) wj.w.w[k] = op.w[k];
+            wj.f = r->ws + r->L.vol2;
+            wj.block0 = 0;
+            wj.nblocks = warp_blocks(nvox_of(&md.vol));
+            wj.live = (const uint8_t *)(r->ws + r->L.live);
+            warpjacs.add({md.dt, md.K}, wj);
+            FitArgs ff = fit_of(*r, op.fixed_ab ? op.ab : nullptr);
+            if (md.dt == PCAS_F32) {
+                ff.a0 = ff.mode == FIT_FIXED ? ff.a : r->ref_a;
+                ff.b0 = ff.mode == FIT_FIXED ? ff.b : r->ref_b;
+            }
+            const bool defer = md.dt == PCAS_F32;
+            const FwdJob fj = make_fwd_job(md.vd, r->fr, r->plan_e, r->ws + r->L.rays,
+                                           r->ws + r->L.vol2, r->proj_slot(op.slot), r->y, ff,
+                                           r->partials(), defer ? nullptr : &r->counters()[0],
+                                           r->scal());
+            fwd_evals.add({16 * (int)md.dt + md.K, r->plan_e.axis}, fj);
+            if (defer) {
+                SumJob &sj = sums[ri];
+                sj.partials = r->partials();
+                sj.out = r->scal();
+                sj.scale = 1.0;
+                sj.nblocks = fj.nblocks;
+                sj.width = FWD_THREADS;
+                sj.ns = 6 + 3 * md.K;
+                sj.offset = 0;
+            }
+            r->mom_slot = op.slot;
+            r->mom_a0 = ff.a0;
+            r->mom_b0 = ff.b0;
+            r->eval_fit = ff;
+            r->spec = false;
+        } else if (op.kind == OP_EVAL) {
             WarpJob wj;
             wj.vd = md.vd;
             wj.f0 = md.f0;
@@ -417,7 +494,8 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             r->mom_b0 = ff.b0;
             r->eval_fit = ff;
             r->spec = false;
-            if (defer && r->opts.speculate && op.next_grad.mode != GRAD_NEVER) {
+            if (defer && r->opts.speculate && r->opts.grad_mode == 1 &&
+                op.next_grad.mode != GRAD_NEVER) {
                 SpecJob sp;
                 sp.partials = r->partials();
                 sp.nblocks = fj.nblocks;
@@ -440,7 +518,8 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                 fa.b0 = r->mom_b0;
             }
             ress.add(md.dt, res_job(*r, op.slot, fa));
-            if (op.kind == OP_EVAL && r->opts.speculate && op.next_grad.mode != GRAD_NEVER) {
+            if (op.kind == OP_EVAL && r->opts.speculate && r->opts.grad_mode == 1 &&
+                op.next_grad.mode != GRAD_NEVER) {
                 SpecJob sp;   // FP64: the gate reads the two-pass residual's (J, a, b)
                 sp.jab = r->scal() + 3;
                 sp.rule = op.next_grad;
@@ -474,8 +553,12 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     };
     const size_t o_w = carve(warps.items.size() * sizeof(WarpJob));
     warps.emit((WarpJob *)(h + o_w));
+    const size_t o_wj = carve(warpjacs.items.size() * sizeof(WarpJob));
+    warpjacs.emit((WarpJob *)(h + o_wj));
     const size_t o_f = carve(fwds.items.size() * sizeof(FwdJob));
     fwds.emit((FwdJob *)(h + o_f));
+    const size_t o_fe = carve(fwd_evals.items.size() * sizeof(FwdJob));
+    fwd_evals.emit((FwdJob *)(h + o_fe));
     const size_t o_r = carve(ress.items.size() * sizeof(ResJob));
     ress.emit((ResJob *)(h + o_r));
     const size_t o_a = carve(adjs.items.size() * sizeof(AdjJob));
@@ -493,10 +576,17 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     for (auto &g : warps.groups)
         HIPCHK(launch_warp_pca_batch((pcas_dtype)g.key.first, g.key.second,
                                      (const WarpJob *)(d + o_w) + g.first, g.count, g.blocks, S->s));
+    for (auto &g : warpjacs.groups)
+        HIPCHK(launch_warp_jac_batch((pcas_dtype)g.key.first, g.key.second,
+                                     (const WarpJob *)(d + o_wj) + g.first, g.count, g.blocks, S->s));
     for (auto &g : fwds.groups)
         HIPCHK(launch_drr_forward_sums_batch((pcas_dtype)g.key.first, g.key.second,
                                              (const FwdJob *)(d + o_f) + g.first, g.count, g.blocks,
                                              S->s));
+    for (auto &g : fwd_evals.groups)
+        HIPCHK(launch_drr_forward_eval_batch((pcas_dtype)(g.key.first / 16), g.key.first % 16,
+                                             g.key.second, (const FwdJob *)(d + o_fe) + g.first,
+                                             g.count, g.blocks, S->s));
     for (auto &g : ress.groups)
         HIPCHK(launch_residual_batch((pcas_dtype)g.key, (const ResJob *)(d + o_r) + g.first,
                                      g.count, g.blocks, S->s));
@@ -529,6 +619,18 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             ++*n_done;
             continue;
         }
+        if (r->phase == PH_RUN && r->m.op().kind == OP_EVAL && r->fused_eval()) {
+            // keep the sums the evaluation left in its slot (the gradient's
+            // part: sc[6..]; FP64's J, a, b are at sc[3..5])
+            const SolveOp &op = r->m.op();
+            const int K = S->models[r->model].K;
+            Request::Fused &F = r->fused[op.slot];
+            for (int j = 0; j < 6 + 3 * K; ++j) F.m[j] = sc[j];
+            for (int k = 0; k < K; ++k) F.w[k] = op.w[k];
+            F.a0 = r->eval_fit.a0;
+            F.b0 = r->eval_fit.b0;
+            F.valid = true;
+        }
         if (r->phase == PH_RUN && r->m.op().kind == OP_EVAL && S->models[r->model].dt == PCAS_F32) {
             // the objective from the projection's moments, as a solve alone forms it
             double jab[3], kappa;
@@ -542,10 +644,12 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             }
             advance(S, r, sc, n_done, jab);
             take_speculative_gradient(S, r, sc, n_done);
+            feed_fused_gradients(S, r, n_done);
             continue;
         }
         advance(S, r, sc, n_done);
         take_speculative_gradient(S, r, sc, n_done);
+        feed_fused_gradients(S, r, n_done);
     }
     if (redo.empty()) return PCAS_OK;
 
@@ -580,7 +684,10 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     HIPCHK(hipMemcpyAsync(S->gather_host, d + o_g2, nr * GATHER * sizeof(double),
                           hipMemcpyDeviceToHost, S->s));
     HIPCHK(hipStreamSynchronize(S->s));
-    for (int i = 0; i < nr; ++i) advance(S, redo[i], S->gather_host + i * GATHER, n_done);
+    for (int i = 0; i < nr; ++i) {
+        advance(S, redo[i], S->gather_host + i * GATHER, n_done);
+        feed_fused_gradients(S, redo[i], n_done);
+    }
     return PCAS_OK;
 }
 
@@ -707,11 +814,14 @@ int pcas_server_add_model(pcas_server *S, pcas_dtype dtype, const pcas_vol *vol,
     return PCAS_OK;
 }
 
-size_t pcas_server_request_bytes(pcas_server *S, int32_t model_id, const pcas_proj *proj) {
+size_t pcas_server_request_bytes(pcas_server *S, int32_t model_id, const pcas_proj *proj,
+                                 const pcas_opts *opts) {
     if (!S || model_id < 0 || model_id >= (int)S->models.size()) return 0;
     const Model &md = S->models[model_id];
     if (check_proj(proj, &md.vol) != PCAS_OK) return 0;
-    return request_bytes(md, proj);
+    pcas_opts o;
+    if (!opts) pcas_default_opts(&o);
+    return request_bytes(md, proj, opts ? opts->grad_mode : o.grad_mode);
 }
 
 int pcas_server_submit(pcas_server *S, int32_t model_id, const pcas_proj *proj, const void *y,
@@ -722,9 +832,9 @@ int pcas_server_submit(pcas_server *S, int32_t model_id, const pcas_proj *proj, 
     int st = check_proj(proj, &md.vol);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    if (opts->grad_mode != 1) return PCAS_EINVAL;   // the server runs the fused back-projection
+    if (opts->grad_mode == 0) return PCAS_EINVAL;   // routes 1 and 2 are served
     if (!finite_vec(w0, md.K)) return PCAS_ENONFINITE;
-    const size_t need = request_bytes(md, proj);
+    const size_t need = request_bytes(md, proj, opts->grad_mode);
     if (need > S->arena_bytes - S->pool_base) return PCAS_EWORKSPACE;   // could never be admitted
     Request *r = new Request();
     r->id = S->next_id++;
@@ -732,10 +842,11 @@ int pcas_server_submit(pcas_server *S, int32_t model_id, const pcas_proj *proj, 
     r->proj = *proj;
     r->fr = make_frame(proj);
     r->plan = plan_drr_forward(md.dt, md.vd, r->fr, 1);
+    if (opts->grad_mode == 2) r->plan_e = plan_drr_forward(md.dt, md.vd, r->fr, md.K + 1);
     r->y = y;
     r->opts = *opts;
     for (int k = 0; k < md.K; ++k) r->w0[k] = w0[k];
-    r->L = solve_layout(md.dt, &md.vol, proj, md.K, false);
+    r->L = request_layout(md, proj, opts->grad_mode);
     r->M = npix_of(proj);
     S->pending.push_back(r);
     *request_id = r->id;

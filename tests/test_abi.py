@@ -249,4 +249,4 @@ def test_server_validation(L):
     assert L.pcas_server_step(None, None) == EINVAL
     assert L.pcas_server_set_substep_share(None, 0.25) == EINVAL
     assert L.pcas_server_destroy(None) == EINVAL
-    assert L.pcas_server_request_bytes(None, 0, None) == 0
+    assert L.pcas_server_request_bytes(None, 0, None, None) == 0

@@ -48,10 +48,13 @@ def _opts(c):
     return B.default_opts(xtol=xtol, locate=1, c0_mm=tuple(c.tumour_c0))
 
 
-@pytest.mark.parametrize("share", [0.25, 0.0, 4.0])
-def test_batched_results_equal_alone(torch, share):
+@pytest.mark.parametrize("share,route", [(0.25, 1), (0.0, 1), (4.0, 1), (0.25, 2), (4.0, 2),
+                                         (0.25, "mixed")])
+def test_batched_results_equal_alone(torch, share, route):
     """Every request's result equals its solve alone, bit for bit, whatever
-    the passes it ran in (one per step, or extra passes for cheap ones)."""
+    the passes it ran in (one per step, or extra passes for cheap ones) and
+    whichever gradient route it takes (back-projection, or the fused
+    evaluation; "mixed": both kinds in flight together)."""
     cases = _models()
     devs = [Dev(c) for c in cases]
     reqs = _requests(cases, devs, 3)
@@ -72,6 +75,7 @@ def test_batched_results_equal_alone(torch, share):
             o.method = 2
         if i in (5, 6):
             o.polish = 1
+        o.grad_mode = (1 + i % 2) if route == "mixed" else route
         opts.append(o)
     srv = B.Server(256 << 20, max_active=16)
     srv.set_substep_share(share)
@@ -100,9 +104,10 @@ def test_batched_results_equal_alone(torch, share):
         assert np.array_equal(w, w1), (m, w, w1)
         for key in ("status", "iters", "n_fevals", "n_grads", "J", "a", "b", "gnorm", "tumour_mm"):
             assert rep[key] == rep1[key], key
-        # CG and BFGS requests take gradients launched behind their
-        # evaluations, as a solve alone does (the Appendix algorithm never)
-        if o.method in (1, 2):
+        # CG and BFGS requests by the back-projection route take gradients
+        # launched behind their evaluations, as a solve alone does (the
+        # Appendix algorithm never; the fused evaluation needs none)
+        if o.method in (1, 2) and o.grad_mode == 1:
             assert rep["n_grads"] - 2 <= rep["spec_grads"] <= rep["n_grads"], (rep["spec_grads"], rep["n_grads"])
             assert rep["spec_grads"] == rep1["spec_grads"]
         else:

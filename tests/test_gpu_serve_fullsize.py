@@ -9,7 +9,8 @@ large one is drawn here on the GPU (the same kinds of fields: an ellipsoid
 phantom with textured lungs and a tumour, smooth Gaussian-bump modes), which
 takes well under a second against about two minutes for the host recipe;
 the comparison is between two GPU paths, so the inputs only need the right
-sizes and shapes."""
+sizes and shapes.  Both served gradient routes are checked: back-projection
+with the chain fused, and the fused evaluation."""
 import dataclasses
 import math
 
@@ -77,7 +78,8 @@ def _measured(torch, vol, proj, f0, mean, U, w, seed):
     return (p.double() + 0.01 * rms * noise).float().contiguous()
 
 
-def test_mixed_full_size_served_equals_alone():
+@pytest.mark.parametrize("grad_mode", [1, 2])
+def test_mixed_full_size_served_equals_alone(grad_mode):
     torch = torch_or_skip()
     say("building the 512x512x256 K=5 model on the GPU")
     large_vol = synth.centred_volume((512, 512, 256), (0.75, 0.75, 1.25))
@@ -95,11 +97,11 @@ def test_mixed_full_size_served_equals_alone():
             pj = dataclasses.replace(base, angle=base.angle + 1.3 * j + 0.4 * m)
             y = _measured(torch, vol, pj, f0, mean, U, w * (1.0 + 0.2 * j), 100 + 10 * m + j)
             reqs.append((m, pj, y))
-    opts = B.default_opts(xtol=1e-7)
+    opts = B.default_opts(xtol=1e-7, grad_mode=grad_mode)
     srv0 = B.Server(B.Server.reserved_bytes(4) + (1 << 20), max_active=4)
     for vol, f0, mean, U, K, _ in models:
         srv0.add_model(vol, f0, mean, U)
-    need = sum(srv0.request_bytes(m, pj) for m, pj, _ in reqs)
+    need = sum(srv0.request_bytes(m, pj, opts) for m, pj, _ in reqs)
     srv0.close()
     srv = B.Server(B.Server.reserved_bytes(4) + need + (4 << 20), max_active=4)
     for vol, f0, mean, U, K, _ in models:
