@@ -395,9 +395,33 @@ def serve_mode(args) -> int:
         arrivals.append(SV.Arrival(t=float(times[j]), model=m, proj=pj, y=y, w_true=w_true))
         del rays, f, p
     torch.cuda.synchronize()
-    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=args.grad_mode)
-            for m in range(2)}
     Ks = {m: cases[m].K for m in range(2)}
+    # gradient route per model: the faster of the back-projection route and
+    # the fused evaluation on one of the model's own requests (the fused
+    # evaluation projects K + 1 volumes, which pays at K = 3 and can lose on
+    # the large K = 5 model)
+    route_ms = {}
+    for m in range(2):
+        a = next(x for x in arrivals if x.model == m)
+        d = devs[m]
+        ws_m = torch.empty(B.solve_projection_workspace(cases[m].vol, a.proj, Ks[m], torch.float32),
+                           dtype=torch.uint8, device="cuda")
+        for gm in (1, 2):
+            o = B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=gm)
+            B.solve_projection(cases[m].vol, a.proj, d["f0"], d["mean"], d["U"], a.y, np.zeros(Ks[m]),
+                               o, workspace=ws_m)
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                B.solve_projection(cases[m].vol, a.proj, d["f0"], d["mean"], d["U"], a.y,
+                                   np.zeros(Ks[m]), o, workspace=ws_m)
+                ts.append((time.perf_counter() - t0) * 1e3)
+            route_ms[(m, gm)] = float(np.median(ts))
+        del ws_m
+    route = {m: min((1, 2), key=lambda gm: route_ms[(m, gm)]) for m in range(2)}
+    log(f"serve: route per model {route} from {route_ms}")
+    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=route[m])
+            for m in range(2)}
 
     def new_server(share=args.substep_share):
         srv0 = B.Server(B.Server.reserved_bytes(args.slots) + (64 << 20), max_active=args.slots)
@@ -413,7 +437,8 @@ def serve_mode(args) -> int:
         return srv, need
 
     out = {"mode": "serve", "requests": n, "rate_hz": args.rate, "slots": args.slots,
-           "grad_mode": args.grad_mode,
+           "grad_mode_per_model": [route[m] for m in range(2)],
+           "solve_ms_per_model_and_route": {f"model{m}_route{gm}": v for (m, gm), v in route_ms.items()},
            "substep_share": args.substep_share,
            "models": [{"workload": c.name, "volume": list(c.vol.n), "K": c.K,
                        "detector": [c.proj.nu, c.proj.nv], "pitch_mm": c.proj.pitch_u,
