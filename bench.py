@@ -6,10 +6,11 @@ table, then CG iterations of evaluations, then the tumour-position
 inversion.  By default an evaluation is the fused one (grad_mode 2): DVF
 synthesis, warp and the K Jacobian volumes in one voxel pass, then one
 cone-beam projection of all K + 1 volumes whose sums give the intensity
-fit, the objective and the gradient.  The same solve by the other two
-gradient routes (back-projection of the residual + Jacobian chain;
-projections of the Jacobian volumes after the evaluation) is reported
-beside it.  Inputs (reference volume, mean field and K = 3 modes, measured
+fit, the objective, the gradient and the Gauss-Newton matrix that
+preconditions CG (precond 1).  The same solve by plain CG and by the other
+two gradient routes (back-projection of the residual + Jacobian chain;
+projections of the Jacobian volumes after the evaluation), and by BFGS, is
+reported beside it.  Inputs (reference volume, mean field and K = 3 modes, measured
 projection) are resident in HBM before the timed region.
 
 Prints ONE JSON line (see the keys below).  Kernel durations come from HIP
@@ -60,6 +61,10 @@ def flops_per_sample(kernel: str, K: int) -> float:
 def chain_flops_per_voxel(K: int) -> float:
     return 12.0 * K + 51.0
 
+
+# solver configurations reported beside the timed one: (label, grad_mode, precond)
+SOLVER_VARIANTS = (("cg_route0", 0, 0), ("cg_route1", 1, 0), ("cg_route2", 2, 0),
+                   ("pcg_route2", 2, 1))
 
 SAMPLE_KERNELS = ("drr_forward", "drr_adjoint", "drr_adjoint_chain", "drr_forward_dot",
                   "drr_forward_eval")
@@ -397,9 +402,11 @@ def serve_mode(args) -> int:
     torch.cuda.synchronize()
     Ks = {m: cases[m].K for m in range(2)}
     # gradient route per model: the faster of the back-projection route and
-    # the fused evaluation on one of the model's own requests (the fused
-    # evaluation projects K + 1 volumes, which pays at K = 3 and can lose on
-    # the large K = 5 model)
+    # the fused evaluation (with CG preconditioned by its Gauss-Newton matrix
+    # unless --precond 0) on one of the model's own requests (the fused
+    # evaluation projects K + 1 volumes, which can lose on the large K = 5
+    # model when it does not save evaluations)
+    pre = args.precond if args.method == "cg" else 0
     route_ms = {}
     for m in range(2):
         a = next(x for x in arrivals if x.model == m)
@@ -407,7 +414,8 @@ def serve_mode(args) -> int:
         ws_m = torch.empty(B.solve_projection_workspace(cases[m].vol, a.proj, Ks[m], torch.float32),
                            dtype=torch.uint8, device="cuda")
         for gm in (1, 2):
-            o = B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=gm)
+            o = B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=gm,
+                               precond=pre if gm == 2 else 0)
             B.solve_projection(cases[m].vol, a.proj, d["f0"], d["mean"], d["U"], a.y, np.zeros(Ks[m]),
                                o, workspace=ws_m)
             ts = []
@@ -420,7 +428,8 @@ def serve_mode(args) -> int:
         del ws_m
     route = {m: min((1, 2), key=lambda gm: route_ms[(m, gm)]) for m in range(2)}
     log(f"serve: route per model {route} from {route_ms}")
-    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=route[m])
+    opts = {m: B.default_opts(xtol=1e-7, method=METHODS[args.method], grad_mode=route[m],
+                              precond=pre if route[m] == 2 else 0)
             for m in range(2)}
 
     def new_server(share=args.substep_share):
@@ -437,7 +446,7 @@ def serve_mode(args) -> int:
         return srv, need
 
     out = {"mode": "serve", "requests": n, "rate_hz": args.rate, "slots": args.slots,
-           "grad_mode_per_model": [route[m] for m in range(2)],
+           "grad_mode_per_model": [route[m] for m in range(2)], "precond": pre,
            "solve_ms_per_model_and_route": {f"model{m}_route{gm}": v for (m, gm), v in route_ms.items()},
            "substep_share": args.substep_share,
            "models": [{"workload": c.name, "volume": list(c.vol.n), "K": c.K,
@@ -733,8 +742,9 @@ def tiny_latency(args) -> dict:
                      dtype=torch.uint8, device="cuda")
     w0 = np.zeros(case.K)
 
-    def run(speculate, n, grad_mode=args.grad_mode):
-        kw = {} if grad_mode is None else {"grad_mode": grad_mode}
+    def run(speculate, n, grad_mode=args.grad_mode, precond=None):
+        kw = {"grad_mode": grad_mode}
+        kw["precond"] = (args.precond if grad_mode == 2 else 0) if precond is None else precond
         o = B.default_opts(locate=1, c0_mm=tuple(case.tumour_c0), speculate=speculate, **kw)
         for _ in range(3):
             B.solve_projection(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"], dev["y"],
@@ -750,11 +760,11 @@ def tiny_latency(args) -> dict:
 
     w, rep, ts, hs = run(1, max(20, args.tiny_steps))
     _, rep0, ts0, _ = run(0, 20, 1)
-    routes = {str(gm): float(np.percentile(run(1, 20, gm)[2], 50)) for gm in (0, 1, 2)}
+    others = {label: float(np.percentile(run(1, 20, gm, pc)[2], 50))
+              for label, gm, pc in SOLVER_VARIANTS}
     return {"workload": case.name, "solves": len(ts), "p50_ms": float(np.percentile(ts, 50)),
-            "grad_mode": B.default_opts(**({} if args.grad_mode is None else
-                                           {"grad_mode": args.grad_mode})).grad_mode,
-            "p50_ms_by_gradient_route": routes,
+            "grad_mode": args.grad_mode, "precond": args.precond if args.grad_mode == 2 else 0,
+            "p50_ms_by_solver": others,
             "p99_ms": float(np.percentile(ts, 99)), "mean_ms": float(np.mean(ts)),
             "library_p50_ms": float(np.percentile(hs[:, 0], 50)),
             "host_work_p50_ms": float(np.percentile(hs[:, 1], 50)),
@@ -839,6 +849,9 @@ def main() -> int:
                          "the differentiation form against the plain solve")
     ap.add_argument("--grad-mode", type=int, default=2, choices=[0, 1, 2],
                     help="gradient route of the timed solve (opts.grad_mode)")
+    ap.add_argument("--precond", type=int, default=1, choices=[0, 1],
+                    help="CG preconditioned by the Gauss-Newton matrix (opts.precond; "
+                         "grad_mode 2 and cg only)")
     ap.add_argument("--method", default="cg", choices=list(METHODS),
                     help="solver: PR+ CG (the configured one), BFGS, or the Appendix algorithm")
     ap.add_argument("--angles", type=int, default=100,
@@ -885,9 +898,9 @@ def main() -> int:
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
     base = dict(locate=1, c0_mm=tuple(case.tumour_c0), xtol=xtol)
     base["method"] = METHODS[args.method]
-    if args.grad_mode is not None:
-        base["grad_mode"] = args.grad_mode
-    timed_route = B.default_opts(**base).grad_mode
+    base["grad_mode"] = args.grad_mode
+    base["precond"] = args.precond if (args.grad_mode == 2 and args.method == "cg") else 0
+    timed = ("pcg" if base["precond"] else args.method) + f"_route{args.grad_mode}"
     opts_warm = B.default_opts(profile=0 if args.no_profile else B.PROFILE_ALL, **base)
     w0 = np.zeros(case.K)
 
@@ -990,35 +1003,36 @@ def main() -> int:
                         "unit": "TFLOP/s", "frac": ach / VALU_F32_PEAK_TFLOPS, "traffic": traffic,
                         "kernel": dominant}
 
-    # the other gradient routes (0: projected Jacobian volumes; 1: back-
-    # projection + chain; 2: fused evaluation), same solve otherwise; reported
-    # beside the contract line, not as `value`
+    # the other solver configurations (gradient route 0: projected Jacobian
+    # volumes; 1: back-projection + chain; 2: fused evaluation; CG plain or
+    # preconditioned by the Gauss-Newton matrix), same solve otherwise;
+    # reported beside the contract line, not as `value`
     alt = {}
-    for gm in (0, 1, 2):
-        if gm == timed_route:
+    for label, gm, pc in SOLVER_VARIANTS:
+        if label == timed:
             continue
         alt_t = []
-        opts_alt = B.default_opts(**{**base, "grad_mode": gm})
+        opts_alt = B.default_opts(**{**base, "grad_mode": gm, "precond": pc})
         step(opts_alt)
         for _ in range(max(5, args.steps // 5)):
             t0 = time.perf_counter()
             w_alt, rep_alt = step(opts_alt)
             alt_t.append(time.perf_counter() - t0)
         alt_ms = np.array(alt_t) * 1e3
-        alt[str(gm)] = {"grad_mode": gm, "steps": len(alt_t),
+        alt[label] = {"grad_mode": gm, "precond": pc, "steps": len(alt_t),
                         "p50_ms": float(np.percentile(alt_ms, 50)),
                         "p99_ms": float(np.percentile(alt_ms, 99)),
                         "solves_s": float(1e3 / np.mean(alt_ms)), "n_fevals": rep_alt["n_fevals"],
                         "n_grads": rep_alt["n_grads"],
-                        "w_rel_diff_vs_timed_route": float(np.linalg.norm(w_alt - w) /
-                                                           np.linalg.norm(w))}
-        log(f"gradient route {gm}: p50 {alt[str(gm)]['p50_ms']:.3f} ms")
+                        "w_rel_diff_vs_timed": float(np.linalg.norm(w_alt - w) /
+                                                     np.linalg.norm(w))}
+        log(f"solver {label}: p50 {alt[label]['p50_ms']:.3f} ms")
 
     # the quasi-Newton solver on the same problem (same line search, same
     # stops), beside the configured CG: latency and agreement of the minimisers
     qn = None
     if args.method == "cg":
-        opts_qn = B.default_opts(**{**base, "method": 2})
+        opts_qn = B.default_opts(**{**base, "method": 2, "precond": 0})
         step(opts_qn)
         qn_t = []
         for _ in range(args.steps):
@@ -1030,8 +1044,9 @@ def main() -> int:
               "p99_ms": float(np.percentile(qn_ms, 99)), "solves_s": float(1e3 / np.mean(qn_ms)),
               "iters": rep_qn["iters"], "n_fevals": rep_qn["n_fevals"],
               "n_grads": rep_qn["n_grads"], "status": rep_qn["status"],
-              "w_rel_diff_vs_cg": float(np.linalg.norm(w_qn - w) / np.linalg.norm(w)),
-              "J_rel_diff_vs_cg": float((rep_qn["J"] - rep["J"]) / rep["J"])}
+              "grad_mode": args.grad_mode,
+              "w_rel_diff_vs_timed": float(np.linalg.norm(w_qn - w) / np.linalg.norm(w)),
+              "J_rel_diff_vs_timed": float((rep_qn["J"] - rep["J"]) / rep["J"])}
         log(f"quasi-Newton: p50 {qn['p50_ms']:.3f} ms, {qn['n_fevals']} evaluations")
 
     # accuracy of the timed solve against the FP64 oracle's minimiser
@@ -1118,8 +1133,9 @@ def main() -> int:
                               for k in kernel_stats if k in KERNEL_SOURCES},
         "kernels": kernel_stats,
         "timed_region_events": [k for i, k in enumerate(B.KERNEL_CLASSES) if mask >> i & 1],
-        "grad_mode": timed_route,
-        "other_gradient_routes": alt,
+        "solver": {"method": args.method, "grad_mode": args.grad_mode,
+                   "precond": base["precond"], "label": timed},
+        "other_solvers": alt,
         "quasi_newton": qn,
         "random_angles": rand,
         "roofline": roofline,

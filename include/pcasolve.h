@@ -158,6 +158,15 @@ typedef struct {
                               launch whose gate is shut exits at once (report class
                               PCAS_K_SPEC_SKIP).  Results are bit-identical with 0.
                               Default 1 */
+    int32_t precond;       /* method 1 with grad_mode 2: 1 = precondition CG by the
+                              Gauss-Newton matrix of the reduced objective at each point,
+                              H = 2 (Q^T Q - Q^T Y (Y^T Y)^-1 Y^T Q) with Q = dp/dw (the
+                              projected Jacobian volumes, columns q_k) and Y = [y, 1]
+                              (2 Q^T Q when the fit is fixed), which the fused evaluation's
+                              sums give: directions -H^-1 g + beta d (PR+ with
+                              preconditioned inner products), first trials and the stop
+                              from the model g.d + d.H d / 2, and the polish step the
+                              Gauss-Newton step.  Default 0 */
 } pcas_opts;
 
 /* kernel classes of pcas_report.kernel_ms / kernel_launches (in a solve,
@@ -360,7 +369,9 @@ int tumour_position(pcas_dtype dtype, const pcas_vol *vol, int32_t K, const void
  * and dJ/dw at that (a, b), exactly as solve_projection forms them, the
  * gradient by the route grad_mode selects (see pcas_opts.grad_mode).
  * Arguments as solve_projection; w: host double[K];
- * out: host double[3 + K] = { J, a, b, g_0 .. g_{K-1} }.  Synchronous. */
+ * out: host double[3 + K] = { J, a, b, g_0 .. g_{K-1} }, and for grad_mode 2
+ * double[3 + K + K * K] with the Gauss-Newton matrix of the reduced
+ * objective at w after g (row-major; see pcas_opts.precond).  Synchronous. */
 int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const pcas_proj *proj, int32_t K,
                        const void *f0, const void *mean, const void *U, const void *y,
                        const double *w, int32_t fit_intensity, int32_t grad_mode,

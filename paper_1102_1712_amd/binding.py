@@ -68,7 +68,8 @@ class Opts(ctypes.Structure):
                 ("locate_tol", ctypes.c_double), ("c0_mm", ctypes.c_double * 3),
                 ("profile", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
                 ("ftol_rel", ctypes.c_double), ("ls_extrap", ctypes.c_double),
-                ("polish", ctypes.c_int32), ("speculate", ctypes.c_int32)]
+                ("polish", ctypes.c_int32), ("speculate", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -488,7 +489,7 @@ def _apply(o: Opts, overrides) -> Opts:
             for c in range(3):
                 o.c0_mm[c] = float(v[c])
         elif k in ("method", "max_iter", "fit_intensity", "max_backtracks", "locate",
-                   "locate_max_iter", "profile", "grad_mode", "polish", "speculate"):
+                   "locate_max_iter", "profile", "grad_mode", "polish", "speculate", "precond"):
             setattr(o, k, int(v))
         else:
             setattr(o, k, float(v))
@@ -537,10 +538,12 @@ def solve_projection(vol, proj, f0, mean, U, y, w0, opts: Optional[Opts] = None,
 
 
 def objective_gradient(vol, proj, f0, mean, U, y, w, fit_intensity: bool = True,
-                       grad_mode: int = 1, workspace=None, stream=None):
+                       grad_mode: int = 1, workspace=None, stream=None, gauss_newton=False):
     """a5 + a6 + a7 at one point: (J, a, b, g as float64 numpy [K]) exactly as
     the solver forms them (grad_mode 1: back-projection + Jacobian chain; 0:
-    projected Jacobian volumes).  Synchronous."""
+    projected Jacobian volumes; 2: the fused evaluation), and with
+    gauss_newton (grad_mode 2) also the Gauss-Newton matrix [K, K] of the
+    reduced objective.  Synchronous."""
     torch = _torch()
     K = _K_of(U, vol)
     code = _dtype_code(f0)
@@ -549,7 +552,7 @@ def objective_gradient(vol, proj, f0, mean, U, y, w, fit_intensity: bool = True,
     if workspace is None:
         workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=f0.device)
     _, wp = _host_doubles(w, K)
-    out = np.zeros(3 + K)
+    out = np.zeros(3 + K + (K * K if int(grad_mode) == 2 else 0))
     _check(lib().objective_gradient(code, ctypes.byref(cv), ctypes.byref(cp), K, _dev(f0, "f0"),
                                     _dev(mean, "mean", f0.dtype), _dev(U, "U", f0.dtype),
                                     _dev(y, "y", f0.dtype), wp, int(bool(fit_intensity)),
@@ -557,7 +560,10 @@ def objective_gradient(vol, proj, f0, mean, U, y, w, fit_intensity: bool = True,
                                     workspace.numel(),
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     _stream(stream)), "objective_gradient")
-    return float(out[0]), float(out[1]), float(out[2]), out[3:].copy()
+    if gauss_newton:
+        return (float(out[0]), float(out[1]), float(out[2]), out[3:3 + K].copy(),
+                out[3 + K:].reshape(K, K).copy())
+    return float(out[0]), float(out[1]), float(out[2]), out[3:3 + K].copy()
 
 
 class Server:

@@ -58,6 +58,7 @@ void pcas_default_opts(pcas_opts *o) {
     o->ls_extrap = 10.0;
     o->polish = 1;
     o->speculate = 1;
+    o->precond = 0;
 }
 
 void pcas_paper_opts(pcas_opts *o) {
@@ -365,7 +366,7 @@ struct Solver {
         bool valid = false;
         double w[PCAS_MAX_K] = {0};
         double a0 = 0.0, b0 = 0.0;
-        double m[6 + 3 * PCAS_MAX_K] = {0};
+        double m[eval_sums(PCAS_MAX_K)] = {0};
     } fused[2];
 
     double *scal() const { return (double *)(ws + L.scalars); }
@@ -444,7 +445,7 @@ struct Solver {
             return launch_residual(dt, M, proj_slot(slot), y, fa, mom_src, nullptr,
                                    (double *)(ws + L.partials), &counters()[3], jab, s);
         }));
-        double out[3 + 3 * PCAS_MAX_K];
+        double out[eval_sums(PCAS_MAX_K)];
         int st;
         if (speculate && rule && w && rule->mode != GRAD_NEVER) {
             HIPCHK(launch_spec_decide_jab(jab, *rule, scal() + SCAL_GATE, s));
@@ -554,10 +555,10 @@ struct Solver {
         mom_a0 = ff.a0;
         mom_b0 = ff.b0;
         mom_src = sums;
-        const int ns = 6 + 3 * K;
+        const int ns = eval_sums(K);
         int st;
         if (!one_pass) {
-            if ((st = residual(ab_fixed, slot, J, a, b, nullptr, nullptr, F.m + 6, 3 * K)))
+            if ((st = residual(ab_fixed, slot, J, a, b, nullptr, nullptr, F.m + 6, ns - 6)))
                 return st;
         } else {
             const int nbf = drr_forward_blocks(fr.nu, fr.nv);
@@ -567,10 +568,7 @@ struct Solver {
             if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;
             if (!(kappa <= MOMENT_KAPPA_MAX)) {   // cancellation: the two-pass sum at this fit
                 const double ab[2] = {*a, *b};
-                double keep[3 * PCAS_MAX_K];
-                for (int j = 0; j < 3 * K; ++j) keep[j] = F.m[6 + j];
                 if ((st = residual(ab, slot, J, a, b))) return st;
-                for (int j = 0; j < 3 * K; ++j) F.m[6 + j] = keep[j];
             } else {
                 if (!isfinite(*J)) return PCAS_ENONFINITE;
                 ref_a = *a;
@@ -630,11 +628,19 @@ struct Solver {
         return PCAS_OK;
     }
 
-    // Gradient at the w whose projection is in the slot, at (a, b).
-    int gradient(const double *w, double a, double b, int slot, double *g) {
+    // Gradient at the w whose projection is in the slot, at (a, b); with H,
+    // also the Gauss-Newton matrix there when the fused evaluation gives it
+    // (*h_ok says whether it did).
+    int gradient(const double *w, double a, double b, int slot, double *g, double *H = nullptr,
+                 bool *h_ok = nullptr) {
+        if (h_ok) *h_ok = false;
         if (grad_mode == 2 && fused[slot].valid && !memcmp(fused[slot].w, w, K * sizeof(double))) {
             const Fused &F = fused[slot];
             gradient_from_moments(F.m, K, a, b, F.a0, F.b0, g);
+            if (H) {
+                gn_matrix_from_moments(F.m, K, fit != 0, sy, syy, (double)M, H);
+                *h_ok = true;
+            }
             ++n_grads;
             for (int k = 0; k < K; ++k)
                 if (!isfinite(g[k])) return PCAS_ENONFINITE;
@@ -746,9 +752,10 @@ int drive(Solver &S, SolveMachine &m) {
             m.eval_result(J, a, b);
             break;
         case OP_GRAD: {
-            double g[PCAS_MAX_K];
-            if ((st = S.gradient(op.w, op.ab[0], op.ab[1], op.slot, g))) return st;
-            m.grad_result(g);
+            double g[PCAS_MAX_K], H[PCAS_MAX_K * PCAS_MAX_K];
+            bool h_ok = false;
+            if ((st = S.gradient(op.w, op.ab[0], op.ab[1], op.slot, g, H, &h_ok))) return st;
+            m.grad_result(g, h_ok ? H : nullptr);
             break;
         }
         case OP_DONE:
@@ -835,7 +842,10 @@ extern "C" int objective_gradient(pcas_dtype dtype, const pcas_vol *vol, const p
         return st;
     double J, a, b;
     if ((st = S.evaluate(w, nullptr, 0, &J, &a, &b))) return st;
-    if ((st = S.gradient(w, a, b, 0, out + 3))) return st;
+    bool h_ok = false;
+    if ((st = S.gradient(w, a, b, 0, out + 3, grad_mode == 2 ? out + 3 + K : nullptr, &h_ok)))
+        return st;
+    if (grad_mode == 2 && !h_ok) return hip_fail(hipErrorInvalidValue, "no Gauss-Newton matrix");
     out[0] = J;
     out[1] = a;
     out[2] = b;

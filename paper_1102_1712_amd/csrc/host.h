@@ -128,7 +128,7 @@ inline bool finite_vec(const double *w, int K) {
 }
 
 // Scalar read-back through a per-thread mailbox in coherent, mapped host
-// memory: 64 values and a flag word.  A one-wave kernel on the stream copies
+// memory: MAILBOX_VALUES values and a flag word.  A one-wave kernel on the stream copies
 // the values there and then publishes a sequence number in the flag; the
 // host spins until it reads that number.  Every few thousand polls it
 // queries the stream, so an error on the stream ends the wait with that
@@ -146,11 +146,12 @@ inline Mailbox *host_mailbox() {
     thread_local Mailbox mb;
     if (!mb.vals) {
         void *p = nullptr;
-        if (hipHostMalloc(&p, 64 * sizeof(double) + 256, hipHostMallocCoherent | hipHostMallocMapped) !=
+        if (hipHostMalloc(&p, MAILBOX_VALUES * sizeof(double) + 256,
+                          hipHostMallocCoherent | hipHostMallocMapped) !=
             hipSuccess)
             return nullptr;
         mb.vals = (double *)p;
-        mb.flag = (uint32_t *)((char *)p + 64 * sizeof(double));
+        mb.flag = (uint32_t *)((char *)p + MAILBOX_VALUES * sizeof(double));
         __atomic_store_n(mb.flag, 0u, __ATOMIC_RELEASE);
     }
     return &mb;
@@ -159,7 +160,8 @@ inline Mailbox *host_mailbox() {
 // Publishes count values with `launch(vals, flag, seq)` and waits for them.
 template <class Launch>
 inline int readback_with(double *host, int count, hipStream_t s, Launch launch) {
-    if (count < 0 || count > 64) return hip_fail(hipErrorInvalidValue, "scalar read-back size");
+    if (count < 0 || count > MAILBOX_VALUES)
+        return hip_fail(hipErrorInvalidValue, "scalar read-back size");
     Mailbox *mb = host_mailbox();
     if (!mb) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc(scalar mailbox)");
     if (++mb->seq == 0) mb->seq = 1;   // 0 is the flag's initial value
@@ -248,6 +250,9 @@ inline int check_opts(const pcas_opts *o) {
     if (!(o->ls_extrap >= 0.0) || !isfinite(o->ls_extrap) || isnan(o->ftol_rel)) return PCAS_EINVAL;
     if (o->polish != 0 && o->polish != 1) return PCAS_EINVAL;
     if (o->speculate != 0 && o->speculate != 1) return PCAS_EINVAL;
+    // the preconditioner is the fused evaluation's Gauss-Newton matrix, for CG
+    if (o->precond != 0 && o->precond != 1) return PCAS_EINVAL;
+    if (o->precond && (o->method != 1 || o->grad_mode != 2)) return PCAS_EINVAL;
     if (o->profile < 0 || o->profile > PCAS_PROFILE_ALL) return PCAS_EINVAL;
     if (o->locate && !finite_vec(o->c0_mm, 3)) return PCAS_EINVAL;
     return PCAS_OK;

@@ -68,10 +68,17 @@ constexpr int TILE_U = 2 * FWD_WU, TILE_V = 2 * FWD_WV;
 constexpr int FWD_LDS_BYTES = 16384;
 constexpr int FWD_MAX_SLABS = 128;
 static_assert(FWD_WU * FWD_WV * FWD_SPLIT == 64, "forward wave tile");
+// Values one scalar read-back can return (the mapped mailbox's size).
+constexpr int MAILBOX_VALUES = 80;
+// Sums the fused evaluation's projection reduces for K modes (see
+// launch_drr_forward_eval): 6 + 3K + K(K + 1) / 2, at most 66.
+constexpr int eval_sums(int K) { return 6 + 3 * K + K * (K + 1) / 2; }
 // Reductions: partial-sum slots per block; a reduction of more than
-// RED_SLOTS values (the fused evaluation's moments) strides RED_SLOTS_WIDE.
+// RED_SLOTS values (the fused evaluation's sums) strides RED_SLOTS_WIDE.
 constexpr int RED_SLOTS = 8;
-constexpr int RED_SLOTS_WIDE = 32;
+constexpr int RED_SLOTS_WIDE = 72;
+static_assert(eval_sums(PCAS_MAX_K) <= RED_SLOTS_WIDE && eval_sums(PCAS_MAX_K) <= MAILBOX_VALUES,
+              "fused evaluation sums");
 constexpr int red_stride(int ns) { return ns <= RED_SLOTS ? RED_SLOTS : RED_SLOTS_WIDE; }
 constexpr int GRAD_BLOCKS_MAX = 2048;
 
@@ -248,9 +255,10 @@ hipError_t launch_spec_decide(const double *partials, int nblocks, int threads,
 // the serving loop reads back per request.
 constexpr int SCAL_GATE = 28;
 // Scalars of a solve's workspace, and the slot of the fused evaluation's
-// moments (6 + 3K values: see launch_drr_forward_eval).
-constexpr int SCAL_COUNT = 128;
+// sums (eval_sums(K) values: see launch_drr_forward_eval).
+constexpr int SCAL_COUNT = 160;
 constexpr int SCAL_EVAL = 64;
+static_assert(SCAL_EVAL + eval_sums(PCAS_MAX_K) <= SCAL_COUNT, "solve scalars");
 // Several requests' gates in one launch (one FWD_THREADS-wide block each):
 // from the moment partials of an FP32 evaluation (partials != null, summed
 // as launch_spec_decide does, written to mo) or from an FP64 evaluation's
@@ -323,11 +331,12 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
                                   hipStream_t s);
 // The fused evaluation's projection (plan for nvol = K + 1): vols holds the
 // warped image f and then its K Jacobian volumes J_k, each N values.  It
-// stores p = P f and reduces 6 + 3K sums with r0 = p - fit.a0 y - fit.b0
-// and q_k = P J_k (unrounded ray sums):
+// stores p = P f and reduces eval_sums(K) sums with r0 = p - fit.a0 y -
+// fit.b0 and q_k = P J_k (unrounded ray sums):
 //   sums[0..2]          = (sum r0, sum r0 y, sum r0^2)   (the objective's moments)
 //   sums[3..5]          = 0                              (room for J, a, b)
 //   sums[6 + 3k .. +2]  = (sum q_k r0, sum q_k y, sum q_k)
+//   then sum q_i q_j for i <= j, row by row (the Gauss-Newton matrix's part)
 // so that for any fit (a, b), sum_rays (p - a y - b) q_k = sums[6+3k]
 // - (a - a0) sums[7+3k] - (b - b0) sums[8+3k] (gradient_from_moments).
 // counter == nullptr leaves block partials (RED_SLOTS_WIDE apart) for
@@ -357,6 +366,33 @@ __host__ __device__ inline void gradient_from_moments(const double *sums, int K,
         const double *m = sums + 6 + 3 * k;
         g[k] = 2.0 * (m[0] - da * m[1] - db * m[2]);
     }
+}
+
+// The Gauss-Newton matrix of the reduced objective phi(w) = min_(a,b) J at
+// the evaluated point, from the same sums: with the Jacobian of the
+// projection dp/dw = Q = [q_1 .. q_K] (pixels x K) and Y = [y, 1],
+//   fit refitted (Eq. A.1):  H = 2 (Q^T Q - Q^T Y (Y^T Y)^-1 Y^T Q)
+//   fit fixed:               H = 2 Q^T Q
+// (r's dependence on w through the refitted (a, b) is projected out; the
+// residual's curvature term is dropped).  sy, syy, m: sum y, sum y^2 and the
+// pixel count.  H: K x K, row-major.
+__host__ __device__ inline void gn_matrix_from_moments(const double *sums, int K, bool refit,
+                                                       double sy, double syy, double m,
+                                                       double *H) {
+#pragma clang fp contract(off)
+    const double *qq = sums + 6 + 3 * K;
+    const double det = syy * m - sy * sy;
+    for (int i = 0, t = 0; i < K; ++i)
+        for (int j = i; j < K; ++j, ++t) {
+            double h = qq[t];
+            if (refit) {
+                // (Y^T Y)^-1 = [[m, -sy], [-sy, syy]] / det
+                const double ui = sums[7 + 3 * i], vi = sums[8 + 3 * i];
+                const double uj = sums[7 + 3 * j], vj = sums[8 + 3 * j];
+                h -= (ui * (m * uj - sy * vj) + vi * (syy * vj - sy * uj)) / det;
+            }
+            H[i * K + j] = H[j * K + i] = 2.0 * h;
+        }
 }
 
 // Back-projection.  If y != nullptr the residual r = p - a*y - b is formed

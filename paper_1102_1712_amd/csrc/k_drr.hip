@@ -440,7 +440,8 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             // residual dot product at whatever fit the moments select
             const double yv = writer ? (double)y[pix] : 0.0;
             const double rv = writer ? pv - fit.a0 * yv - fit.b0 : 0.0;
-            double vals[3 + 3 * NV];
+            constexpr int KV = NV - 1;
+            double vals[eval_sums(KV)];
             vals[0] = rv;
             vals[1] = rv * yv;
             vals[2] = rv * rv;
@@ -452,7 +453,11 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                 vals[4 + 3 * v] = q * yv;
                 vals[5 + 3 * v] = q;
             }
-            reduce_or_defer<3 + 3 * NV>(vals, partials, counter, out, bid, nb, 1.0);
+#pragma unroll
+            for (int i = 0, t = 3 + 3 * NV; i < KV; ++i)
+#pragma unroll
+                for (int j = i; j < KV; ++j, ++t) vals[t] = vals[8 + 3 * i] * vals[8 + 3 * j];
+            reduce_or_defer<eval_sums(KV)>(vals, partials, counter, out, bid, nb, 1.0);
         }
     }
 }

@@ -14,21 +14,22 @@ hipError_t launch_fill_u32(uint32_t *p, int count, uint32_t value, hipStream_t s
     return hipGetLastError();
 }
 
-// Scalar read-back.  One wave copies up to 64 values into host memory that
-// the GPU writes through (coherent, mapped), waits for those stores, and
-// then stores `seq` to the flag word with a system-scope release: a host
-// thread that loads `seq` there (acquire) also sees the values.
+// Scalar read-back.  One wave copies up to MAILBOX_VALUES values into host
+// memory that the GPU writes through (coherent, mapped), waits for those
+// stores, and then stores `seq` to the flag word with a system-scope
+// release: a host thread that loads `seq` there (acquire) also sees the
+// values.
 __global__ __launch_bounds__(64) void k_publish(const double *__restrict__ src, double *dst, int count,
                                                 uint32_t *flag, uint32_t seq) {
     const int i = threadIdx.x;
-    if (i < count) dst[i] = src[i];
+    for (int t = i; t < count; t += 64) dst[t] = src[t];
     __threadfence_system();
     if (i == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 hipError_t launch_publish(const double *src, double *dst_host, int count, uint32_t *flag_host,
                           uint32_t seq, hipStream_t s) {
-    if (count < 0 || count > 64) return hipErrorInvalidValue;
+    if (count < 0 || count > MAILBOX_VALUES) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, dst_host, count, flag_host, seq);
     return hipGetLastError();
 }
@@ -73,15 +74,15 @@ hipError_t launch_publish_sum(const double *partials, int nblocks, int threads, 
         PCAS_PUBLISH_SUM(6)
         PCAS_PUBLISH_SUM(7)
         PCAS_PUBLISH_SUM(8)
-        // the fused evaluation's 6 + 3K sums
-        PCAS_PUBLISH_SUM(9)
-        PCAS_PUBLISH_SUM(12)
+        // the fused evaluation's sums, eval_sums(1..8)
+        PCAS_PUBLISH_SUM(10)
         PCAS_PUBLISH_SUM(15)
-        PCAS_PUBLISH_SUM(18)
         PCAS_PUBLISH_SUM(21)
-        PCAS_PUBLISH_SUM(24)
-        PCAS_PUBLISH_SUM(27)
-        PCAS_PUBLISH_SUM(30)
+        PCAS_PUBLISH_SUM(28)
+        PCAS_PUBLISH_SUM(36)
+        PCAS_PUBLISH_SUM(45)
+        PCAS_PUBLISH_SUM(55)
+        PCAS_PUBLISH_SUM(66)
 #undef PCAS_PUBLISH_SUM
     default:
         return hipErrorInvalidValue;

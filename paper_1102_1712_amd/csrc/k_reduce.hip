@@ -180,15 +180,15 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather_scalars(const double 
         case 6: finish_sum<6>(J, tot_s); break;
         case 7: finish_sum<7>(J, tot_s); break;
         case 8: finish_sum<8>(J, tot_s); break;
-        // the fused evaluation's 6 + 3K sums
-        case 9: finish_sum<9>(J, tot_s); break;
-        case 12: finish_sum<12>(J, tot_s); break;
+        // the fused evaluation's sums, eval_sums(1..8)
+        case 10: finish_sum<10>(J, tot_s); break;
         case 15: finish_sum<15>(J, tot_s); break;
-        case 18: finish_sum<18>(J, tot_s); break;
         case 21: finish_sum<21>(J, tot_s); break;
-        case 24: finish_sum<24>(J, tot_s); break;
-        case 27: finish_sum<27>(J, tot_s); break;
-        default: finish_sum<30>(J, tot_s); break;
+        case 28: finish_sum<28>(J, tot_s); break;
+        case 36: finish_sum<36>(J, tot_s); break;
+        case 45: finish_sum<45>(J, tot_s); break;
+        case 55: finish_sum<55>(J, tot_s); break;
+        default: finish_sum<66>(J, tot_s); break;
         }
         __syncthreads();
         lo = J.offset;

@@ -28,7 +28,10 @@ using namespace pcas::host;
 
 namespace {
 
-constexpr int GATHER = 32;   // scalars read back per request and step
+// scalars read back per request and step (the fused evaluation's sums are
+// the most: eval_sums(K))
+constexpr int GATHER = 72;
+static_assert(eval_sums(PCAS_MAX_K) <= GATHER, "gather width");
 
 struct Model {
     pcas_dtype dt;
@@ -80,7 +83,7 @@ struct Request {
         bool valid = false;
         double w[PCAS_MAX_K] = {0};
         double a0 = 0.0, b0 = 0.0;
-        double m[6 + 3 * PCAS_MAX_K] = {0};
+        double m[eval_sums(PCAS_MAX_K)] = {0};
     } fused[2];
     bool fused_eval() const { return opts.grad_mode == 2; }
 
@@ -260,7 +263,7 @@ ResJob res_job(const Request &r, int slot, const FitArgs &fa) {
 // Advances one request with the scalars its operation produced (jab: J, a,
 // b of an evaluation formed on the host, else sc[3..5]).
 void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done,
-             const double *jab = nullptr) {
+             const double *jab = nullptr, const double *H = nullptr) {
     const Model &md = S->models[r->model];
     bool done = false;
     int status = PCAS_OK;
@@ -302,7 +305,7 @@ void advance(pcas_server *S, Request *r, const double *sc, int32_t *n_done,
                     status = PCAS_ENONFINITE;
                     done = true;
                 }
-            if (!done) r->m.grad_result(sc + 8);
+            if (!done) r->m.grad_result(sc + 8, H);
         }
         if (!done && r->m.done()) {
             r->rep = r->m.report();
@@ -374,9 +377,10 @@ void feed_fused_gradients(pcas_server *S, Request *r, int32_t *n_done) {
         if (op.kind != OP_GRAD) return;
         const Request::Fused &F = r->fused[op.slot];
         if (!F.valid || memcmp(F.w, op.w, K * sizeof(double))) return;
-        double sc[GATHER] = {0};
+        double sc[GATHER] = {0}, H[PCAS_MAX_K * PCAS_MAX_K];
         gradient_from_moments(F.m, K, op.ab[0], op.ab[1], F.a0, F.b0, sc + 8);
-        advance(S, r, sc, n_done);   // OP_GRAD: the gradient at sc[8..]
+        gn_matrix_from_moments(F.m, K, r->opts.fit_intensity != 0, r->sy, r->syy, (double)r->M, H);
+        advance(S, r, sc, n_done, nullptr, H);   // OP_GRAD: the gradient at sc[8..]
     }
 }
 
@@ -443,7 +447,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                 sj.scale = 1.0;
                 sj.nblocks = fj.nblocks;
                 sj.width = FWD_THREADS;
-                sj.ns = 6 + 3 * md.K;
+                sj.ns = eval_sums(md.K);
                 sj.offset = 0;
             }
             r->mom_slot = op.slot;
@@ -625,7 +629,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             const SolveOp &op = r->m.op();
             const int K = S->models[r->model].K;
             Request::Fused &F = r->fused[op.slot];
-            for (int j = 0; j < 6 + 3 * K; ++j) F.m[j] = sc[j];
+            for (int j = 0; j < eval_sums(K); ++j) F.m[j] = sc[j];
             for (int k = 0; k < K; ++k) F.w[k] = op.w[k];
             F.a0 = r->eval_fit.a0;
             F.b0 = r->eval_fit.b0;

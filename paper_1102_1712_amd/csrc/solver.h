@@ -93,9 +93,15 @@ public:
         if (op_.kind == OP_EVAL) ++rep_.n_fevals;
         run();
     }
-    // Result of OP_GRAD.
-    void grad_result(const double *g) {
+    // Result of OP_GRAD; H (K x K, row-major, may be null): the Gauss-Newton
+    // matrix of the reduced objective at the same point, which a
+    // preconditioned CG (opts.precond) uses.
+    void grad_result(const double *g, const double *H = nullptr) {
         for (int k = 0; k < K_; ++k) rg_[k] = g[k];
+        rH_ok_ = H != nullptr;
+        if (H)
+            for (int i = 0; i < K_; ++i)
+                for (int j = 0; j < K_; ++j) rH_[i * PCAS_MAX_K + j] = H[i * K_ + j];
         ++rep_.n_grads;
         run();
     }
@@ -194,6 +200,42 @@ private:
         for (int i = 0; i < K; ++i)
             for (int j = 0; j < K; ++j)
                 B[i * PCAS_MAX_K + j] += -bs[i] * bs[j] / sbs + yv[i] * yv[j] / sy;
+    }
+    // z = H^-1 g by the Cholesky factors of H (the preconditioner of CG);
+    // false, with z = g, when H is missing or not positive definite.
+    bool precondition(const double *H, bool ok, const double *g, double *z) const {
+        const int K = K_;
+        double L[PCAS_MAX_K * PCAS_MAX_K];
+        for (int i = 0; ok && i < K; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double s = H[i * PCAS_MAX_K + j];
+                for (int k = 0; k < j; ++k) s -= L[i * PCAS_MAX_K + k] * L[j * PCAS_MAX_K + k];
+                if (i == j) {
+                    if (!(s > 0.0)) {
+                        ok = false;
+                        break;
+                    }
+                    L[i * PCAS_MAX_K + i] = sqrt(s);
+                } else {
+                    L[i * PCAS_MAX_K + j] = s / L[j * PCAS_MAX_K + j];
+                }
+            }
+        if (!ok) {
+            for (int k = 0; k < K; ++k) z[k] = g[k];
+            return false;
+        }
+        double v[PCAS_MAX_K];
+        for (int i = 0; i < K; ++i) {   // L v = g
+            double s = g[i];
+            for (int k = 0; k < i; ++k) s -= L[i * PCAS_MAX_K + k] * v[k];
+            v[i] = s / L[i * PCAS_MAX_K + i];
+        }
+        for (int i = K - 1; i >= 0; --i) {   // L^T z = v
+            double s = v[i];
+            for (int k = i + 1; k < K; ++k) s -= L[k * PCAS_MAX_K + i] * z[k];
+            z[i] = s / L[i * PCAS_MAX_K + i];
+        }
+        return true;
     }
     // d.B d (B applied first, then the dot with d).
     double quad_form(const double *B, const double *v) const {
@@ -306,6 +348,11 @@ private:
             // by direct BFGS updates (used for step lengths only; the
             // directions stay CG's).  A predicted decrease within the noise
             // floor ends the solve when the model is trusted, as in BFGS.
+            // Preconditioned (opts.precond, Nocedal and Wright Sec. 5.1 and
+            // the PR+ rule with preconditioned inner products): each gradient
+            // comes with the Gauss-Newton matrix H of its point; directions
+            // are -z + beta d with z = H^-1 g and beta = max(0, z+.(g+ - g) /
+            // (z.g)), and H is the model of the first trial and of the stop.
             case CG_START:
                 want_eval(w_, false, 1.0, 0.0, CG_AFTER_EVAL0, 0, GRAD_ALWAYS);
                 return;
@@ -317,10 +364,13 @@ private:
                 want_grad(w_, a_, b_, CG_AFTER_GRAD0);
                 return;
             case CG_AFTER_GRAD0:
-                for (int k = 0; k < K; ++k) {
-                    g_[k] = rg_[k];
-                    d_[k] = -g_[k];
+                for (int k = 0; k < K; ++k) g_[k] = rg_[k];
+                pre_ = o_.precond != 0;
+                if (pre_) {
+                    memcpy(Hg_, rH_, sizeof(Hg_));
+                    have_hg_ = precondition(Hg_, rH_ok_, g_, z_);
                 }
+                for (int k = 0; k < K; ++k) d_[k] = pre_ ? -z_[k] : -g_[k];
                 rep_.J0 = phi_;
                 g0_ = sqrt(dot(g_, g_, K));
                 rep_.gnorm0 = g0_;
@@ -347,8 +397,13 @@ private:
                 }
                 gd_ = dot(g_, d_, K);
                 if (gd_ >= 0.0) {
-                    for (int k = 0; k < K; ++k) d_[k] = -g_[k];
-                    gd_ = -gn * gn;
+                    if (pre_ && have_hg_) {   // restart along the preconditioned gradient
+                        for (int k = 0; k < K; ++k) d_[k] = -z_[k];
+                        gd_ = -dot(g_, z_, K);
+                    } else {
+                        for (int k = 0; k < K; ++k) d_[k] = -g_[k];
+                        gd_ = -gn * gn;
+                    }
                     restart_ = true;
                 }
                 dn_ = sqrt(dot(d_, d_, K));
@@ -357,7 +412,9 @@ private:
                 // mu0 / ||d|| first, then with the curvature the last accepted
                 // step measured, (s.y) / (s.s)
                 {
-                    const double dbd = have_b_ ? quad_form(B_, d_) : 0.0;
+                    // preconditioned: the Gauss-Newton matrix at this point is the model
+                    const double dbd = pre_ && have_hg_ ? quad_form(Hg_, d_)
+                                                        : (have_b_ ? quad_form(B_, d_) : 0.0);
                     pred_ = -1.0;
                     if (dbd > 0.0) {
                         t_ = -gd_ / dbd;
@@ -421,13 +478,31 @@ private:
                     curvature_update(B_, have_b_, sv, yv);
                     if (o_.polish) hessian_update(Hc_, have_hc_, sv, yv);   // polish only
                 }
-                double num = 0.0;
-                for (int k = 0; k < K; ++k) num += rg_[k] * (rg_[k] - g_[k]);
-                double beta_pr = num / dot(g_, g_, K);
-                beta_pr = beta_pr > 0.0 ? beta_pr : 0.0;
-                for (int k = 0; k < K; ++k) {
-                    d_[k] = -rg_[k] + beta_pr * d_[k];
-                    g_[k] = rg_[k];
+                if (pre_) {
+                    // preconditioned PR+: z = H^-1 g with the new point's
+                    // Gauss-Newton matrix, beta = z+.(g+ - g) / (z.g)
+                    double zn[PCAS_MAX_K];
+                    const double zg = dot(z_, g_, K);
+                    memcpy(Hg_, rH_, sizeof(Hg_));
+                    have_hg_ = precondition(Hg_, rH_ok_, rg_, zn);
+                    double num = 0.0;
+                    for (int k = 0; k < K; ++k) num += zn[k] * (rg_[k] - g_[k]);
+                    double beta_pr = zg > 0.0 ? num / zg : 0.0;
+                    beta_pr = beta_pr > 0.0 ? beta_pr : 0.0;
+                    for (int k = 0; k < K; ++k) {
+                        d_[k] = -zn[k] + beta_pr * d_[k];
+                        g_[k] = rg_[k];
+                        z_[k] = zn[k];
+                    }
+                } else {
+                    double num = 0.0;
+                    for (int k = 0; k < K; ++k) num += rg_[k] * (rg_[k] - g_[k]);
+                    double beta_pr = num / dot(g_, g_, K);
+                    beta_pr = beta_pr > 0.0 ? beta_pr : 0.0;
+                    for (int k = 0; k < K; ++k) {
+                        d_[k] = -rg_[k] + beta_pr * d_[k];
+                        g_[k] = rg_[k];
+                    }
                 }
                 t_prev_ = t_;
                 gd_prev_ = gd_;
@@ -562,15 +637,21 @@ private:
             // The step is kept if ||g|| drops; the gradient resolves the
             // minimiser far below the noise of J.
             case POLISH: {
+                // preconditioned CG: the Gauss-Newton step H^-1 g at the point
+                const bool gn = o_.method == 1 && pre_ && have_hg_;
                 const double *H = o_.method == 2 && have_h_ ? H_ : (have_hc_ ? Hc_ : nullptr);
-                if (!H) {
+                if (!H && !gn) {
                     pc_ = SOLVE_FINISH;
                     break;
                 }
                 double gd = 0.0;
                 for (int i = 0; i < K; ++i) {
                     double v = 0.0;
-                    for (int j = 0; j < K; ++j) v += H[i * PCAS_MAX_K + j] * g_[j];
+                    if (gn) {
+                        v = z_[i];
+                    } else {
+                        for (int j = 0; j < K; ++j) v += H[i * PCAS_MAX_K + j] * g_[j];
+                    }
                     wx_[i] = w_[i] - v;
                     gd -= g_[i] * v;
                 }
@@ -708,6 +789,8 @@ private:
     pcas_report rep_{};
     // results of the last operation
     double rJ_ = 0.0, ra_ = 0.0, rb_ = 0.0, rg_[PCAS_MAX_K] = {0};
+    double rH_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // Gauss-Newton matrix with rg_ (row-major)
+    bool rH_ok_ = false;
     // solver state
     double w_[PCAS_MAX_K] = {0}, wt_[PCAS_MAX_K] = {0}, wx_[PCAS_MAX_K] = {0};
     double wprev_[PCAS_MAX_K] = {0};
@@ -715,6 +798,9 @@ private:
     double H_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // BFGS inverse-Hessian estimate (row-major)
     double B_[PCAS_MAX_K * PCAS_MAX_K] = {0};   // CG: Hessian (curvature) estimate (row-major)
     double Hc_[PCAS_MAX_K * PCAS_MAX_K] = {0};  // estimate kept for the polish step
+    // preconditioned CG: the Gauss-Newton matrix at w_ and z = H^-1 g there
+    double Hg_[PCAS_MAX_K * PCAS_MAX_K] = {0}, z_[PCAS_MAX_K] = {0};
+    bool pre_ = false, have_hg_ = false;
     double phi_ = 0.0, a_ = 0.0, b_ = 0.0, phi_t_ = 0.0, a_t_ = 0.0, b_t_ = 0.0;
     double g0_ = 0.0, gd_ = 0.0, dn_ = 0.0, t_ = 0.0, tx_ = 0.0, t_prev_ = 0.0, gd_prev_ = 0.0;
     double thr_ = 0.0;    // Armijo threshold of the current trial

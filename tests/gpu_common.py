@@ -83,3 +83,23 @@ SMALL_F32 = dict(dtype="f32", seed=6)
 
 def small(**kw):
     return synth.small(**kw)
+
+
+def oracle_gauss_newton(case, y, w, fit=True):
+    """The Gauss-Newton matrix of the reduced objective at w in oracle
+    arithmetic: Q = [P J_1 .. P J_K] from the oracle's projections of the
+    Jacobian volumes J_k = sum_c U_kc df/dx_c (Eq. A.8), then
+    2 (Q^T Q - Q^T Y (Y^T Y)^-1 Y^T Q) with Y = [y, 1] (2 Q^T Q without the
+    fit)."""
+    c = case
+    N = c.vol.nvox
+    U = np.asarray(c.U, dtype=np.float64).reshape(c.K, 3, N)
+    x = O.pca_dvf(c.vol, c.mean, c.U, w).reshape(3, N)
+    jac = O.warp_jacobian(c.vol, c.f0, x).reshape(3, N)
+    Q = np.stack([O.drr_forward(c.vol, c.proj, (U[k] * jac).sum(0)).ravel() for k in range(c.K)], 1)
+    if not fit:
+        return 2.0 * Q.T @ Q
+    yv = np.asarray(y, dtype=np.float64).ravel()
+    Y = np.stack([yv, np.ones_like(yv)], 1)
+    QY = Q.T @ Y
+    return 2.0 * (Q.T @ Q - QY @ np.linalg.solve(Y.T @ Y, QY.T))

@@ -79,6 +79,38 @@ int harness_solve_rules(const pcas_opts *opts, int K, double ftol, const double 
     return 0;
 }
 
+// The same drive with a gradient callback that may also return the
+// Gauss-Newton matrix at the point (K x K, row-major; return value 1 when
+// it did), for the preconditioned CG.
+typedef int (*harness_grad_gn_fn)(const double *w, int slot, double a, double b, double *g,
+                                  double *H);
+
+int harness_solve_gn(const pcas_opts *opts, int K, double ftol, const double *w0,
+                     harness_eval_fn ev, harness_grad_gn_fn gr, double *w_out, pcas_report *rep) {
+    pcas::SolveMachine m;
+    pcas::NoiseModel noise;
+    noise.fixed = ftol;
+    m.start(*opts, K, noise, w0);
+    int guard = 0;
+    while (!m.done()) {
+        if (++guard > 100000) return -1;
+        const pcas::SolveOp &op = m.op();
+        if (op.kind == pcas::OP_EVAL || op.kind == pcas::OP_RESID) {
+            double a = 1.0, b = 0.0;
+            const double J = ev(op.kind == pcas::OP_EVAL ? op.w : nullptr, op.slot,
+                                op.fixed_ab ? 1 : 0, op.ab, &a, &b);
+            m.eval_result(J, a, b);
+        } else {
+            double g[PCAS_MAX_K], H[PCAS_MAX_K * PCAS_MAX_K];
+            const int have = gr(op.w, op.slot, op.ab[0], op.ab[1], g, H);
+            m.grad_result(g, have ? H : nullptr);
+        }
+    }
+    for (int k = 0; k < K; ++k) w_out[k] = m.w()[k];
+    *rep = m.report();
+    return 0;
+}
+
 // The solver's noise band at one point (the rounding model, or `fixed`).
 double harness_noise_rel(double fixed, double u, double M, double sy, double syy, double J,
                          double a, double b) {

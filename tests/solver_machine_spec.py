@@ -37,7 +37,10 @@ class MachineOptions:
     polish: when a solve ends at the noise floor (the noise or decrement
     stop, or a failed search), one more step w - H g is tried with an
     inverse-Hessian estimate H (BFGS's own; CG keeps one from its steps by
-    the same updates) and kept if it lowers ||g||."""
+    the same updates) and kept if it lowers ||g||.
+
+    precond (machine_cg): each gradient comes with the Gauss-Newton matrix H
+    of its point (prob.gauss_newton(w, r)); CG is preconditioned by it."""
     method: int = 1
     max_iter: int = 30
     max_backtracks: int = 12
@@ -50,6 +53,7 @@ class MachineOptions:
     ftol_rel: float = 1e-14
     ls_extrap: float = 10.0
     polish: bool = False
+    precond: bool = False
 
 
 @dataclass
@@ -131,6 +135,18 @@ def _curvature_estimate(B, s_k, y_k):
     return B
 
 
+def _precondition(H, g):
+    """z = H^-1 g by Cholesky factors; (g, False) when H is missing or not
+    positive definite."""
+    if H is None:
+        return g.copy(), False
+    try:
+        L = np.linalg.cholesky(H)
+    except np.linalg.LinAlgError:
+        return g.copy(), False
+    return np.linalg.solve(L.T, np.linalg.solve(L, g)), True
+
+
 def machine_cg(prob, w0, opts: Optional[MachineOptions] = None):
     """PR+ nonlinear CG on phi(w) = min_{a,b} J(w, a, b).
 
@@ -149,7 +165,15 @@ def machine_cg(prob, w0, opts: Optional[MachineOptions] = None):
     the last accepted decrease was within ftol_rel of phi too, or, for a
     step accepted at the model's first trial, within a factor 2 of the
     decrease predicted for it (machine_bfgs's stop).  A failed search restarts
-    along -g once; a second failure ends the solve."""
+    along -g once; a second failure ends the solve.
+
+    Preconditioned (opts.precond): with z = H^-1 g for the Gauss-Newton
+    matrix H of the current point, the directions are -z + beta d with the
+    PR+ rule in preconditioned inner products, beta = max(0, z+.(g+ - g) /
+    (z.g)); a direction that is not downhill restarts along -z; H replaces B
+    as the model of the first trial and of the stop; and the polish step is
+    the Gauss-Newton step -z.  An H that is not positive definite falls back
+    to z = g and to B."""
     o = opts or MachineOptions()
     w = np.asarray(w0, dtype=np.float64).copy()
     rep = SolveReport()
@@ -160,7 +184,12 @@ def machine_cg(prob, w0, opts: Optional[MachineOptions] = None):
     rep.J0 = phi
     rep.J_trace.append(phi)
     g0 = float(np.linalg.norm(g))
-    d = -g
+    pre = o.precond
+    Hg, z, have_hg = None, None, False
+    if pre:
+        Hg = prob.gauss_newton(w, r)
+        z, have_hg = _precondition(Hg, g)
+    d = -z if pre else -g
     restart, first = True, True
     t_prev = gd_prev = 0.0
     curv = 0.0                                         # (s.y) / (s.s) of the last accepted step
@@ -177,10 +206,17 @@ def machine_cg(prob, w0, opts: Optional[MachineOptions] = None):
             break
         gd = float(g @ d)
         if gd >= 0.0:                                  # not a descent direction
-            d = -g
-            gd = -gn * gn
+            if pre and have_hg:
+                d = -z
+                gd = -float(g @ z)
+            else:
+                d = -g
+                gd = -gn * gn
             restart = True
-        dbd = float(d @ (B @ d)) if B is not None else 0.0
+        if pre and have_hg:
+            dbd = float(d @ (Hg @ d))
+        else:
+            dbd = float(d @ (B @ d)) if B is not None else 0.0
         pred = -1.0
         if dbd > 0.0:
             t = -gd / dbd
@@ -221,16 +257,25 @@ def machine_cg(prob, w0, opts: Optional[MachineOptions] = None):
             H = _hessian_update(H, s_k, y_k)
         last_pred = pred if t == t0 else -1.0
         last_drop = phi - phi_t
+        if pre:
+            zg = float(z @ g)
+            Hg = prob.gauss_newton(w_t, r_t)
+            zn, have_hg = _precondition(Hg, g_new)
+            beta_pr = max(0.0, float(zn @ (g_new - g)) / zg if zg > 0.0 else 0.0)
+            d = -zn + beta_pr * d
+            z = zn
+        else:
+            beta_pr = max(0.0, float(g_new @ (g_new - g)) / float(g @ g))
+            d = -g_new + beta_pr * d
         w, phi, a, b, r = w_t, phi_t, a_t, b_t, r_t
-        beta_pr = max(0.0, float(g_new @ (g_new - g)) / float(g @ g))
-        d = -g_new + beta_pr * d
         t_prev, gd_prev = t, gd
         g = g_new
         restart, first = False, False
         it += 1
         rep.J_trace.append(phi)
     if floor and o.polish:
-        w, phi, a, b, g = _polish(prob, H, w, phi, a, b, g, rep)
+        w, phi, a, b, g = _polish(prob, H, w, phi, a, b, g, rep,
+                                  step=z if pre and have_hg else None)
     rep.iters = it
     rep.J, rep.a, rep.b = phi, a, b
     rep.gnorm = float(np.linalg.norm(g))
@@ -260,11 +305,12 @@ def _hessian_update(H, s_k, y_k):
     return H
 
 
-def _polish(prob, H, w, phi, a, b, g, rep):
-    """One step w - H g, kept if ||g|| drops (MachineOptions.polish)."""
-    if H is None:
+def _polish(prob, H, w, phi, a, b, g, rep, step=None):
+    """One step w - H g (or w - step), kept if ||g|| drops
+    (MachineOptions.polish)."""
+    if H is None and step is None:
         return w, phi, a, b, g
-    d = -(H @ g)
+    d = -step if step is not None else -(H @ g)
     if float(g @ d) >= 0.0:
         return w, phi, a, b, g
     w_p = w + d

@@ -102,3 +102,22 @@ def test_clinical_speculation_is_bit_identical(clinical, method):
     for k in ("status", "iters", "n_fevals", "n_grads", "J", "a", "b", "gnorm", "tumour_mm"):
         assert r0[k] == r1[k], k
     assert r0["spec_grads"] == 0 and r1["spec_grads"] >= r1["n_grads"] - 2
+
+
+@pytest.mark.parametrize("fit", [True, False])
+def test_clinical_preconditioned_cg_matches_oracle_minimiser(clinical, fit):
+    """CG preconditioned by the Gauss-Newton matrix (grad_mode 2, precond 1)
+    at the benchmark's options: w within 1e-4 of the FP64 minimiser, tumour
+    within 0.05 mm."""
+    c, d, y, gold = clinical
+    ref = gold["fit" if fit else "nofit"]
+    kw = dict(xtol=1e-7, method=1, fit_intensity=int(fit), locate=1, c0_mm=tuple(c.tumour_c0),
+              grad_mode=2, precond=1)
+    w, rep = B.solve_projection(c.vol, c.proj, d.f0, d.mean, d.U, y, np.zeros(c.K),
+                                B.default_opts(**kw))
+    w_ref = np.array(ref["w"])
+    err = np.linalg.norm(w - w_ref) / np.linalg.norm(w_ref)
+    say("clinical preconditioned CG fit", fit, w, rep["status"], rep["n_fevals"], "err", err)
+    assert rep["status"] == "converged"
+    assert err <= 1e-4
+    assert np.linalg.norm(np.array(rep["tumour_mm"]) - np.array(ref["tumour_mm"])) <= 0.05

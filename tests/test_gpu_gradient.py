@@ -10,7 +10,8 @@ import oracle as O
 from paper_1102_1712_amd import binding as B
 from paper_1102_1712_amd import synth
 
-from gpu_common import Dev, measured, rel_l2, say, to_dev, to_np, torch_or_skip
+from gpu_common import (Dev, measured, oracle_gauss_newton, rel_l2, say, to_dev, to_np,
+                        torch_or_skip)
 
 pytestmark = pytest.mark.gpu
 
@@ -252,3 +253,23 @@ def test_fused_evaluation_launches(torch, dtype):
                                    B.default_opts(xtol=opts.xtol))
     say("w", w, "route 1", ref)
     assert np.linalg.norm(w - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("case,fit,tol", [("small64", True, 1e-10), ("small64", False, 1e-10),
+                                          ("tiny", True, 1e-10), ("clinical", True, 1e-4)])
+def test_gauss_newton_matrix(torch, case, fit, tol):
+    """The fused evaluation's Gauss-Newton matrix of the reduced objective
+    (the preconditioner of opts.precond) against the oracle's, formed from
+    its own projections of the Jacobian volumes."""
+    c = {"small64": lambda: synth.small(dtype="f64", seed=5), "tiny": synth.tiny,
+         "clinical": synth.clinical}[case]()
+    d = Dev(c)
+    y = measured(c)
+    w = c.w_star + 0.3 * np.linspace(-1.0, 1.0, c.K)
+    say("Gauss-Newton matrix", case, "fit", fit)
+    J, a, b, g, H = B.objective_gradient(c.vol, c.proj, d.f0, d.mean, d.U, to_dev(y, d.dt), w,
+                                         fit_intensity=fit, grad_mode=2, gauss_newton=True)
+    H_o = oracle_gauss_newton(c, y, w, fit)
+    say("H", H.ravel(), "oracle", H_o.ravel())
+    assert np.allclose(H, H.T, rtol=0, atol=0)
+    assert np.linalg.norm(H - H_o) <= tol * np.linalg.norm(H_o)

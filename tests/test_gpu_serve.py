@@ -76,6 +76,8 @@ def test_batched_results_equal_alone(torch, share, route):
         if i in (5, 6):
             o.polish = 1
         o.grad_mode = (1 + i % 2) if route == "mixed" else route
+        if o.grad_mode == 2 and o.method == 1 and i % 3 == 0:
+            o.precond = 1   # CG preconditioned by the Gauss-Newton matrix
         opts.append(o)
     srv = B.Server(256 << 20, max_active=16)
     srv.set_substep_share(share)

@@ -34,6 +34,9 @@ GRAD = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.c_int, cty
 
 RULE = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int)
+GRAD_GN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                           ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double))
 
 
 @pytest.fixture(scope="module")
@@ -51,6 +54,10 @@ def harness(tmp_path_factory):
     lib.harness_solve_rules.argtypes = [ctypes.POINTER(B.Opts), ctypes.c_int, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_double), EVAL, GRAD, RULE,
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(B.Report)]
+    lib.harness_solve_gn.restype = ctypes.c_int
+    lib.harness_solve_gn.argtypes = [ctypes.POINTER(B.Opts), ctypes.c_int, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_double), EVAL, GRAD_GN,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(B.Report)]
     lib.harness_solve.restype = ctypes.c_int
     lib.harness_solve.argtypes = [ctypes.POINTER(B.Opts), ctypes.c_int, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_double), EVAL, GRAD,
@@ -85,12 +92,29 @@ def _machine_solve(lib, prob, K, w0, opts: B.Opts, ftol):
         for k in range(K):
             g_out[k] = g[k]
 
+    def gr_gn(wp, slot, a, b, g_out, h_out):
+        gr(wp, slot, a, b, g_out)
+        w = np.array([wp[k] for k in range(K)])
+        H = prob.gauss_newton(w, slots[slot][1])
+        if H is None:
+            return 0
+        for i in range(K):
+            for j in range(K):
+                h_out[i * K + j] = H[i, j]
+        return 1
+
     w_out = (ctypes.c_double * K)()
     rep = B.Report()
     w0c = (ctypes.c_double * K)(*w0)
-    cb_e, cb_g = EVAL(ev), GRAD(gr)
-    assert lib.harness_solve(ctypes.byref(opts), K, ftol, w0c, cb_e, cb_g, w_out,
-                             ctypes.byref(rep)) == 0
+    cb_e = EVAL(ev)
+    if getattr(opts, "precond", 0):
+        cb_g = GRAD_GN(gr_gn)
+        assert lib.harness_solve_gn(ctypes.byref(opts), K, ftol, w0c, cb_e, cb_g, w_out,
+                                    ctypes.byref(rep)) == 0
+    else:
+        cb_g = GRAD(gr)
+        assert lib.harness_solve(ctypes.byref(opts), K, ftol, w0c, cb_e, cb_g, w_out,
+                                 ctypes.byref(rep)) == 0
     return np.array(w_out[:]), rep, accepted
 
 
@@ -126,7 +150,8 @@ def _spec_opts(o: B.Opts):
     return S.MachineOptions(method=o.method, max_iter=o.max_iter, max_backtracks=o.max_backtracks,
                             mu0=o.mu0, alpha=o.alpha, beta=o.beta, gtol_rel=o.gtol_rel,
                             beta_lo=o.beta_lo, xtol=o.xtol, ftol_rel=o.ftol_rel,
-                            ls_extrap=o.ls_extrap, polish=bool(o.polish))
+                            ls_extrap=o.ls_extrap, polish=bool(o.polish),
+                            precond=bool(o.precond))
 
 
 def _compare(lib, prob, K, w0, o, rtol):
@@ -459,3 +484,139 @@ def test_gradient_rule_predicts_the_machine(harness, oracle_lib, case, method, e
     assert any(nxt for _, nxt, _ in seen)
     # the start evaluation always says so
     assert seen[0][2] == 1 and seen[0][1]
+
+
+# ---- CG preconditioned by a Gauss-Newton matrix (opts.precond) -----------------
+
+class _QuadraticGN(_Quadratic):
+    """A quadratic whose gradients come with a given matrix G as their
+    Gauss-Newton matrix."""
+
+    def __init__(self, A, c, G):
+        super().__init__(A, c)
+        self.G = G
+
+    def gauss_newton(self, w, r):
+        return self.G
+
+
+@pytest.mark.parametrize("K,kappa,seed,model", [(3, 10.0, 8, "exact"), (5, 1e3, 9, "exact"),
+                                                (3, 10.0, 10, "diag"), (8, 1e3, 11, "perturbed"),
+                                                (3, 10.0, 12, "indefinite")])
+def test_preconditioned_cg_matches_spec(harness, K, kappa, seed, model):
+    """With the exact Hessian as preconditioner the first direction is
+    Newton's and its unit first trial lands on the minimiser; with the
+    Hessian's diagonal, or the Hessian perturbed by 20% (as a Gauss-Newton
+    matrix differs from the Hessian), the PR+ rule in preconditioned inner
+    products takes several steps; an indefinite matrix falls back to plain
+    CG.  In every case the machine takes the specification's steps."""
+    rng = np.random.default_rng(400 + seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(K, K)))
+    lam = np.geomspace(1.0, kappa, K)
+    A = Q @ np.diag(lam) @ Q.T
+    c = 3.0 * rng.normal(size=K)
+    E = rng.normal(size=(K, K))
+    E = (E + E.T) / np.abs(np.linalg.eigvalsh(E + E.T)).max()   # spectral norm 1
+    Ah = Q @ np.diag(np.sqrt(lam)) @ Q.T
+    G = {"exact": A, "diag": np.diag(np.diag(A)),
+         "perturbed": Ah @ (np.eye(K) + 0.2 * E) @ Ah,   # eigenvalues of A^-1 G in [0.8, 1.2]
+         "indefinite": A - 2.0 * lam[-1] * np.eye(K)}[model]
+    if model == "perturbed":
+        assert np.linalg.eigvalsh(G).min() > 0.0
+    o = _opts(1, gtol_rel=1e-7, precond=1, grad_mode=2)
+    rep, _ = _compare(harness, _QuadraticGN(A, c, G), K, np.zeros(K), o,
+                      1e-9 if kappa <= 10.0 else 1e-6)
+    assert rep.status == S.STOP_CONVERGED
+    if model == "exact":
+        assert rep.iters == 1 and rep.n_fevals == 2
+    plain, _ = _compare(harness, _Quadratic(A, c), K, np.zeros(K), _opts(1, gtol_rel=1e-7),
+                        1e-9 if kappa <= 10.0 else 1e-6)
+    if model == "indefinite":   # the fallback is plain CG
+        assert (rep.iters, rep.n_fevals) == (plain.iters, plain.n_fevals)
+
+
+def _reduced_gauss_newton(Q, y, fit):
+    """2 (Q^T Q - Q^T Y (Y^T Y)^-1 Y^T Q) with Y = [y, 1] (fit refitted), else
+    2 Q^T Q: the Gauss-Newton matrix of min_(a,b) ||p(w) - a y - b||^2."""
+    if not fit:
+        return 2.0 * Q.T @ Q
+    Y = np.stack([y, np.ones_like(y)], 1)
+    QY = Q.T @ Y
+    return 2.0 * (Q.T @ Q - QY @ np.linalg.solve(Y.T @ Y, QY.T))
+
+
+@pytest.mark.parametrize("fit", [True, False])
+def test_gauss_newton_matrix_is_the_reduced_hessian_of_a_linear_model(fit):
+    """For a projection linear in w, p(w) = p0 + Q w, the reduced objective
+    phi(w) = min_(a,b) ||p(w) - a y - b||^2 is exactly quadratic and its
+    Hessian is the Gauss-Newton matrix: checked by central differences."""
+    rng = np.random.default_rng(77)
+    M, K = 200, 4
+    Q = rng.normal(size=(M, K))
+    y = rng.normal(size=M) + 3.0
+    p0 = 2.0 * y + 1.0 + 0.1 * rng.normal(size=M)
+
+    def phi(w):
+        p = p0 + Q @ w
+        if fit:
+            a, b = O.intensity_fit(p, y)
+        else:
+            a, b = 1.0, 0.0
+        r = p - a * y - b
+        return float(r @ r)
+
+    h = 1e-2
+    H_fd = np.empty((K, K))
+    w0 = rng.normal(size=K)
+    E = np.eye(K) * h
+    for i in range(K):
+        for j in range(K):
+            H_fd[i, j] = (phi(w0 + E[i] + E[j]) - phi(w0 + E[i] - E[j]) -
+                          phi(w0 - E[i] + E[j]) + phi(w0 - E[i] - E[j])) / (4 * h * h)
+    H = _reduced_gauss_newton(Q, y, fit)
+    np.testing.assert_allclose(H_fd, H, rtol=1e-7, atol=1e-7 * np.abs(H).max())
+
+
+class _OracleGN:
+    """The oracle's problem with the Gauss-Newton matrix of each point from
+    the projections of its Jacobian volumes (oracle arithmetic)."""
+
+    def __init__(self, c, y, fit=True):
+        self.c, self.fit = c, fit
+        self.prob = O.Problem(c.vol, c.proj, c.f0, c.mean, c.U, y, fit_intensity=fit)
+        self.y = np.asarray(y, dtype=np.float64).ravel()
+
+    def objective(self, w, ab=None):
+        return self.prob.objective(w, ab) if ab is not None else self.prob.objective(w)
+
+    def gradient(self, w, r):
+        return self.prob.gradient(w, r)
+
+    def gauss_newton(self, w, r):
+        c = self.c
+        N = c.vol.nvox
+        U = np.asarray(c.U, dtype=np.float64).reshape(c.K, 3, N)
+        x = O.pca_dvf(c.vol, c.mean, c.U, w).reshape(3, N)
+        jac = O.warp_jacobian(c.vol, c.f0, x).reshape(3, N)
+        Q = np.stack([O.drr_forward(c.vol, c.proj, (U[k] * jac).sum(0)).ravel()
+                      for k in range(c.K)], 1)
+        return _reduced_gauss_newton(Q, self.y, self.fit)
+
+
+def test_preconditioned_cg_on_small_problem(harness, oracle_lib):
+    """The ragged FP64 problem with the oracle as the evaluator and its
+    Gauss-Newton matrices as the preconditioner: the machine takes the
+    specification's steps, in fewer evaluations than plain CG, to the
+    oracle's minimiser."""
+    c = synth.small(seed=18)
+    y = O.measured_projection(c.vol, c.proj, c.f0, c.mean, c.U, c.w_star, c.xi, c.noise_level)
+    prob = _OracleGN(c, y)
+    rep, _ = _compare(harness, prob, c.K, np.zeros(c.K),
+                      _opts(1, gtol_rel=1e-6, precond=1, grad_mode=2), 1e-9)
+    plain, _ = _compare(harness, prob, c.K, np.zeros(c.K), _opts(1, gtol_rel=1e-6), 1e-9)
+    assert rep.status == S.STOP_CONVERGED
+    assert rep.n_fevals < plain.n_fevals
+    w_m, rep_m, _ = _machine_solve(harness, prob, c.K, np.zeros(c.K),
+                                   _opts(1, gtol_rel=1e-6, precond=1, grad_mode=2), 1e-14)
+    w_ref, _ = O.minimise(prob.prob, np.zeros(c.K))
+    assert np.linalg.norm(w_m - w_ref) <= 1e-5 * np.linalg.norm(w_ref)
