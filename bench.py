@@ -686,7 +686,8 @@ def random_angles(case, dev, dt, args, base: dict) -> dict:
                      dtype=torch.uint8, device="cuda")
     out = {"angles": int(args.angles)}
     for label, method in (("cg", 1), ("bfgs", 2)):
-        o = B.default_opts(**{**base, "method": method})
+        o = B.default_opts(**{**base, "method": method,
+                              "precond": base.get("precond", 0) if method == 1 else 0})
         ts, ev, err = [], [], []
         for pj, y in probs:
             torch.cuda.synchronize()
