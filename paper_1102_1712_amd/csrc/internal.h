@@ -351,6 +351,9 @@ hipError_t launch_drr_forward_eval(pcas_dtype dt, const VolDims &v, const Frame 
 // quantity launch_jacobian computes), from one read of each voxel's f0
 // neighbours.  With live (launch_brick_live), voxels of bricks no ray
 // reaches are skipped (left as they were).
+// Voxels per thread of the fused warp, and its block count for N voxels.
+constexpr int WJ_VOX = 2;
+int warp_jac_blocks(int64_t N);
 hipError_t launch_warp_jac(pcas_dtype dt, const VolDims &v, int K, const void *f0,
                            const void *mean, const void *U, const double *w, void *out,
                            hipStream_t s, const uint8_t *live = nullptr);

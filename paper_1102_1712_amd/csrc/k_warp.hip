@@ -175,6 +175,9 @@ __device__ __forceinline__ T warp_value_jac(const T *__restrict__ f0, int n0, in
 // evaluation that projects all K + 1 volumes together.  The field is formed
 // as k_warp_pca forms it; the value and the three derivatives share one
 // read of the eight f0 neighbours.
+// A block covers WJ_VOX * 256 consecutive voxels, each thread WJ_VOX of
+// them 256 apart: the streams of mean and U for all of them are in flight
+// before the neighbour gathers that depend on them.
 template <typename T, int K>
 __device__ __forceinline__ void warp_jac_block(const VolDims &vd, const T *__restrict__ f0,
                                                const T *__restrict__ mean,
@@ -183,28 +186,40 @@ __device__ __forceinline__ void warp_jac_block(const VolDims &vd, const T *__res
                                                const uint8_t *__restrict__ live) {
     const int64_t N = (int64_t)vd.n0 * vd.n1 * vd.n2;
     const int b = xcd_remap(lb, nb);
-    const int v32 = b * (int)blockDim.x + (int)threadIdx.x;
-    if (v32 >= (int)N) return;
-    const int64_t v = v32;
-    const unsigned q = (unsigned)v32 / (unsigned)vd.n0;
-    const int i = v32 - (int)q * vd.n0;
-    const int k = (int)(q / (unsigned)vd.n1);
-    const int j = (int)q - k * vd.n1;
-    if (live) {
-        const int nbx = (vd.n0 + BRICK_X - 1) / BRICK_X, nby = (vd.n1 + BRICK_Y - 1) / BRICK_Y;
-        if (!live[(k / BRICK_Z * nby + j / BRICK_Y) * nbx + i / BRICK_X]) return;
-    }
+    const int nbx = (vd.n0 + BRICK_X - 1) / BRICK_X, nby = (vd.n1 + BRICK_Y - 1) / BRICK_Y;
     T wk[K];
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) wk[kk] = (T)w.w[kk];
-    T u[K][3], x[3], jac[3];
-    voxel_field<T, K, true>(mean, U, wk, N, v, u, x);
-    out[v] = warp_value_jac(f0, vd.n0, vd.n1, vd.n2, i, j, k, x, (T)vd.inv_s[0],
-                            (T)vd.inv_s[1], (T)vd.inv_s[2], jac);
+    bool on[WJ_VOX];
+    int vi[WJ_VOX], ii[WJ_VOX], jj[WJ_VOX], kx[WJ_VOX];
+    T u[WJ_VOX][K][3], x[WJ_VOX][3];
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk)
-        out[(int64_t)(kk + 1) * N + v] =
-            fma_t(u[kk][0], jac[0], fma_t(u[kk][1], jac[1], u[kk][2] * jac[2]));
+    for (int e = 0; e < WJ_VOX; ++e) {
+        const int v32 = (b * WJ_VOX + e) * (int)blockDim.x + (int)threadIdx.x;
+        on[e] = v32 < (int)N;
+        const int vc = on[e] ? v32 : 0;
+        const unsigned q = (unsigned)vc / (unsigned)vd.n0;
+        ii[e] = vc - (int)q * vd.n0;
+        kx[e] = (int)(q / (unsigned)vd.n1);
+        jj[e] = (int)q - kx[e] * vd.n1;
+        vi[e] = vc;
+        // voxels of bricks no ray reaches are never projected
+        if (on[e] && live)
+            on[e] = live[(kx[e] / BRICK_Z * nby + jj[e] / BRICK_Y) * nbx + ii[e] / BRICK_X] != 0;
+        if (on[e]) voxel_field<T, K, true>(mean, U, wk, N, vc, u[e], x[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < WJ_VOX; ++e) {
+        if (!on[e]) continue;
+        const int64_t v = vi[e];
+        T jac[3];
+        out[v] = warp_value_jac(f0, vd.n0, vd.n1, vd.n2, ii[e], jj[e], kx[e], x[e],
+                                (T)vd.inv_s[0], (T)vd.inv_s[1], (T)vd.inv_s[2], jac);
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk)
+            out[(int64_t)(kk + 1) * N + v] =
+                fma_t(u[e][kk][0], jac[0], fma_t(u[e][kk][1], jac[1], u[e][kk][2] * jac[2]));
+    }
 }
 
 template <typename T, int K>
@@ -258,7 +273,7 @@ template <typename T, int K>
 hipError_t warp_jac_k(const VolDims &v, const void *f0, const void *mean, const void *U,
                       const WVec &w, void *out, hipStream_t s, const uint8_t *live) {
     const int64_t N = (int64_t)v.n0 * v.n1 * v.n2;
-    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    dim3 grid((unsigned)warp_jac_blocks(N)), block(256);
     hipLaunchKernelGGL((k_warp_jac<T, K>), grid, block, 0, s, v, (const T *)f0, (const T *)mean,
                        (const T *)U, w, (T *)out, live);
     return hipGetLastError();
@@ -297,6 +312,7 @@ hipError_t launch_pca_dvf(pcas_dtype dt, int64_t N, int K, const void *mean, con
 }
 
 int warp_blocks(int64_t N) { return (int)((N + 255) / 256); }
+int warp_jac_blocks(int64_t N) { return (int)((N + 256 * WJ_VOX - 1) / (256 * WJ_VOX)); }
 
 namespace {
 template <typename T, int K>

@@ -426,7 +426,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
             for (int k = 0; k < md.K; ++k) wj.w.w[k] = op.w[k];
             wj.f = r->ws + r->L.vol2;
             wj.block0 = 0;
-            wj.nblocks = warp_blocks(nvox_of(&md.vol));
+            wj.nblocks = warp_jac_blocks(nvox_of(&md.vol));
             wj.live = (const uint8_t *)(r->ws + r->L.live);
             warpjacs.add({md.dt, md.K}, wj);
             FitArgs ff = fit_of(*r, op.fixed_ab ? op.ab : nullptr);
