@@ -562,7 +562,7 @@ struct Solver {
                 return st;
         } else {
             const int nbf = drr_forward_blocks(fr.nu, fr.nv);
-            if ((st = sync_read_sum(F.m, nbf, FWD_THREADS, 1.0, sums, ns))) return st;
+            if ((st = sync_read_sum(F.m, nbf, EVAL_SUM_WIDTH, 1.0, sums, ns))) return st;
             double kappa;
             objective_from_moments(F.m, ff, J, a, b, &kappa);
             if (!isfinite(*a) || !isfinite(*b)) return PCAS_ESINGULAR;

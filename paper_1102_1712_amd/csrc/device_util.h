@@ -25,9 +25,10 @@ __device__ __forceinline__ void store_agent(double *p, double v) {
 }
 
 // Sums vals[0..NS) over the block (any multiple of 64 threads up to 1024)
-// and stores the block's totals in partials[bid * red_stride(NS) + j].
+// and stores the block's totals in partials[red_slot(NS, j, bid, nblocks)].
 template <int NS>
-__device__ void block_partials(const double (&vals)[NS], double *__restrict__ partials, int bid) {
+__device__ void block_partials(const double (&vals)[NS], double *__restrict__ partials, int bid,
+                               int nblocks) {
     static_assert(NS <= RED_SLOTS_WIDE, "too many reduction slots");
     __shared__ double sm[NS][16];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -42,7 +43,7 @@ __device__ void block_partials(const double (&vals)[NS], double *__restrict__ pa
         for (int j = 0; j < NS; ++j) {
             double t = 0.0;
             for (int w = 0; w < nwaves; ++w) t += sm[j][w];
-            store_agent(&partials[(int64_t)bid * red_stride(NS) + j], t);
+            store_agent(&partials[red_slot(NS, j, bid, nblocks)], t);
         }
     }
 }
@@ -62,10 +63,13 @@ __device__ void sum_partials(const double *__restrict__ partials, int nblocks, d
     double acc[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) acc[j] = 0.0;
+    // unrolled so that several blocks' loads are in flight at once (the
+    // order of the additions into acc[j] stays the same)
+#pragma unroll 4
     for (int b = threadIdx.x; threadIdx.x < width && b < nblocks; b += width) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
-            const double *q = &partials[(int64_t)b * red_stride(NS) + j];
+            const double *q = &partials[red_slot(NS, j, b, nblocks)];
             acc[j] += COHERENT ? load_agent(q) : *q;
         }
     }
@@ -97,7 +101,7 @@ __device__ void grid_reduce(const double (&vals)[NS], double *__restrict__ parti
                             uint32_t *counter, double *__restrict__ out, int bid, int nblocks,
                             double scale) {
     __shared__ int is_last;
-    block_partials<NS>(vals, partials, bid);
+    block_partials<NS>(vals, partials, bid, nblocks);
     if (threadIdx.x == 0) {
         uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE,
                                                __HIP_MEMORY_SCOPE_AGENT);
@@ -124,7 +128,7 @@ __device__ void reduce_or_defer(const double (&vals)[NS], double *__restrict__ p
     if (counter)
         grid_reduce<NS>(vals, partials, counter, out, bid, nblocks, scale);
     else
-        block_partials<NS>(vals, partials, bid);
+        block_partials<NS>(vals, partials, bid, nblocks);
 }
 
 // Split a displacement x (mm) into whole voxels and the fractional part

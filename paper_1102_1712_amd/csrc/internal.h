@@ -74,12 +74,22 @@ constexpr int MAILBOX_VALUES = 80;
 // launch_drr_forward_eval): 6 + 3K + K(K + 1) / 2, at most 66.
 constexpr int eval_sums(int K) { return 6 + 3 * K + K * (K + 1) / 2; }
 // Reductions: partial-sum slots per block; a reduction of more than
-// RED_SLOTS values (the fused evaluation's sums) strides RED_SLOTS_WIDE.
+// RED_SLOTS values (the fused evaluation's sums) takes up to RED_SLOTS_WIDE.
 constexpr int RED_SLOTS = 8;
 constexpr int RED_SLOTS_WIDE = 72;
 static_assert(eval_sums(PCAS_MAX_K) <= RED_SLOTS_WIDE && eval_sums(PCAS_MAX_K) <= MAILBOX_VALUES,
               "fused evaluation sums");
-constexpr int red_stride(int ns) { return ns <= RED_SLOTS ? RED_SLOTS : RED_SLOTS_WIDE; }
+// Threads that finish the fused evaluation's deferred sums (the solve's
+// read-back and the serving gather use the same width, hence the same
+// summation order): wide, since the pass reads every block's partials.
+constexpr int EVAL_SUM_WIDTH = 512;
+// Where block bid's total of value j goes: a reduction of at most RED_SLOTS
+// values keeps each block's totals together; a wider one keeps value j of
+// all nblocks blocks together, so that the finishing pass reads them
+// coalesced (it reads every value of every block either way).
+__host__ __device__ constexpr int64_t red_slot(int ns, int j, int bid, int nblocks) {
+    return ns <= RED_SLOTS ? (int64_t)bid * RED_SLOTS + j : (int64_t)j * nblocks + bid;
+}
 constexpr int GRAD_BLOCKS_MAX = 2048;
 
 // Coefficients passed by value to kernels.

@@ -44,15 +44,21 @@ __global__ __launch_bounds__(1024) void k_publish_sum(const double *__restrict__
                                                       double *__restrict__ out, double *dst,
                                                       uint32_t *flag, uint32_t seq) {
     double tot[NS];
+    __shared__ double tot_s[NS];
     sum_partials<NS, false>(partials, nblocks, scale, (int)blockDim.x, tot);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            out[j] = tot[j];
-            dst[j] = tot[j];
+        for (int j = 0; j < NS; ++j) tot_s[j] = tot[j];
+    }
+    __syncthreads();
+    // the first wave stores the totals, one per lane, then publishes
+    if (threadIdx.x < 64) {
+        for (int j = threadIdx.x; j < NS; j += 64) {
+            out[j] = tot_s[j];
+            dst[j] = tot_s[j];
         }
         __threadfence_system();
-        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

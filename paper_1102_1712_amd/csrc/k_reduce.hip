@@ -161,7 +161,9 @@ __device__ void finish_sum(const SumJob &J, double *tot_s) {
 }
 
 constexpr int GATHER_THREADS = 512;
-static_assert(ADJ_THREADS <= GATHER_THREADS && FWD_THREADS <= GATHER_THREADS, "gather width");
+static_assert(ADJ_THREADS <= GATHER_THREADS && FWD_THREADS <= GATHER_THREADS &&
+                  EVAL_SUM_WIDTH <= GATHER_THREADS,
+              "gather width");
 
 __global__ __launch_bounds__(GATHER_THREADS) void k_gather_scalars(const double *const *__restrict__ src,
                                                                    double *__restrict__ dst, int count,

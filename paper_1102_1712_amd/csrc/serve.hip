@@ -446,7 +446,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                 sj.out = r->scal();
                 sj.scale = 1.0;
                 sj.nblocks = fj.nblocks;
-                sj.width = FWD_THREADS;
+                sj.width = EVAL_SUM_WIDTH;
                 sj.ns = eval_sums(md.K);
                 sj.offset = 0;
             }
