@@ -7,10 +7,40 @@
 
 namespace pcas {
 
+// A lane's value moved by a DPP pattern (both halves of the double), zero in
+// the lanes of rows that ROW_MASK leaves out.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane (a butterfly of
+// lane permutes).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// The same sum by register moves across lanes (pairs, quads, half rows and
+// rows of 16, then the row broadcasts) instead of LDS permutes, then the
+// last lane's total: no LDS round trips, for the single-block passes that
+// finish a reduction (inside the large kernels the permute form keeps the
+// register count down).  The order of the additions is fixed.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);   // row_mirror: every lane holds its row's sum
+    v += dpp_move<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
 }
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -76,7 +106,7 @@ __device__ void sum_partials(const double *__restrict__ partials, int nblocks, d
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-        double v = wave_sum(acc[j]);
+        double v = wave_sum_dpp(acc[j]);
         if (lane == 0 && wave < nwaves) sm[j][wave] = v;
     }
     __syncthreads();
