@@ -159,6 +159,15 @@ def samples_per_drr(rays, dtype: str) -> int:
     return int(n.astype(np.int64).sum())
 
 
+def solver_opts(args, method: int, **kw):
+    """The benchmark's solver options for a method: the gradient route of
+    --grad-mode and, for CG on the fused evaluation, the Gauss-Newton
+    preconditioner of --precond."""
+    from paper_1102_1712_amd import binding as B
+    pre = args.precond if (method == 1 and args.grad_mode == 2) else 0
+    return B.default_opts(method=method, grad_mode=args.grad_mode, precond=pre, **kw)
+
+
 def reached_voxels(case, dev) -> int:
     """Voxels that at least one projection sample touches (P^T 1 > 0): the
     gradient's chain has work only there, since it skips voxels where the
@@ -333,10 +342,11 @@ def stream_mode(case, dev, dt, args) -> int:
         truth[t] = loc.cpu().numpy()[:3]
     log(f"stream: {n} measured projections made")
     out = {"mode": "stream", "workload": case.name, "frames": n, "fps": fps, "method": args.method,
+           "grad_mode": args.grad_mode, "precond": args.precond if args.method == "cg" else 0,
            "data": "synthetic (measured images from the same forward model, 1% noise)"}
     for init in ("predict", "previous"):
         solver = S.StreamSolver(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"],
-                                opts=B.default_opts(xtol=xtol, method=METHODS[args.method]),
+                                opts=solver_opts(args, METHODS[args.method], xtol=xtol),
                                 c0_mm=case.tumour_c0,
                                 predictor=coeffs, init=init)
         for t in range(n):
@@ -540,8 +550,8 @@ def resolution_mode(case, dev, dt, args) -> int:
     B.tumour_position(case.vol, dev["mean"], dev["U"], case.w_star, case.tumour_c0, out=loc)
     truth = loc.cpu().numpy()[:3]
     xtol = 1e-7 if case.dtype == "f32" else 1e-10
-    opts = B.default_opts(xtol=xtol, locate=1, c0_mm=tuple(case.tumour_c0),
-                          method=METHODS[args.method])
+    opts = solver_opts(args, METHODS[args.method], xtol=xtol, locate=1,
+                       c0_mm=tuple(case.tumour_c0))
     rows = []
     for b in (1, 2, 4, 8, 16, 32):
         pj = dataclasses.replace(fine, nu=fine.nu // b, nv=fine.nv // b, pitch_u=fine.pitch_u * b,
@@ -624,7 +634,7 @@ def autograd_mode(args) -> int:
                      dtype=torch.uint8, device="cuda")
 
     def plain(method):
-        opts = B.default_opts(xtol=xtol, method=method)
+        opts = solver_opts(args, method, xtol=xtol)
 
         def solve_plain():
             w, rep = B.solve_projection(case.vol, case.proj, dev["f0"], dev["mean"], dev["U"], y,
@@ -632,7 +642,8 @@ def autograd_mode(args) -> int:
             return w, rep["J"], rep["n_fevals"] + rep["n_grads"]
         return solve_plain
 
-    out = {"mode": "autograd", "workload": case.name, "K": case.K,
+    out = {"mode": "autograd", "workload": case.name, "K": case.K, "grad_mode": args.grad_mode,
+           "precond_of_plain_cg": args.precond if args.grad_mode == 2 else 0,
            "autograd_optimizer": "torch.optim.LBFGS, strong Wolfe, history 10"}
     for label, fn in (("plain", plain(1)), ("plain_bfgs", plain(2)), ("autograd", solve_autograd)):
         fn()
