@@ -741,6 +741,32 @@ def adjoint_alone(case, dev, S: int, acc32: bool = False) -> dict:
             "accumulator_bits": 32 if acc32 else 64}
 
 
+def drr_alone(case, dev, S: int) -> dict:
+    """The one-volume projection p = P f on its own (drr_forward: no
+    moments), HIP events on the current stream, for the DRR figure; the
+    timed solve projects f with its Jacobian volumes instead."""
+    import torch
+
+    from paper_1102_1712_amd import binding as B
+
+    es = 4 if case.dtype == "f32" else 8
+    f = B.warp_pca(case.vol, dev["f0"], dev["mean"], dev["U"], case.w_star)
+    p = B.drr_forward(case.vol, case.proj, dev["rays"], f)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.drr_forward(case.vol, case.proj, dev["rays"], f, out=p)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    a = float(np.median(ts))
+    return {"avg_ms": a, "launches": len(ts), "Gsamples_s": S / (a * 1e-3) / 1e9,
+            "effective_GBs": 8 * es * S / (a * 1e-3) / 1e9, "timed": "alone"}
+
+
 def tiny_latency(args) -> dict:
     """The tiny workload (64^3 FP64, 128x128 detector, K = 3) solved with
     the same options as the benchmark's solve, one call at a time: p50/p99
@@ -1101,7 +1127,10 @@ def main() -> int:
         log("timing the FP64 oracle on the host cores")
         cpu = cpu_baseline(case, S)
 
-    drr = kernel_stats.get("drr_forward", {})
+    drr = kernel_stats.get("drr_forward") or drr_alone(case, dev, S)
+    if "drr_forward" not in kernel_stats:
+        kernel_stats["drr_forward_alone"] = drr
+    fused = kernel_stats.get("drr_forward_eval", {})
     # the back-projection alone (in the solve it runs fused with the chain)
     adj = adjoint_alone(case, dev, S)
     kernel_stats["drr_adjoint_alone"] = adj
@@ -1136,6 +1165,8 @@ def main() -> int:
         "tiny": tiny,
         "drr_gsamples_s": drr.get("Gsamples_s"),
         "adjoint_gsamples_s": adj.get("Gsamples_s"),
+        # the timed solve's projection of f with its K Jacobian volumes
+        "fused_evaluation_gsamples_s": fused.get("Gsamples_s"),
         # 8 corner values of sizeof(T) per sample at the kernel's rate: a
         # nominal gather rate, not HBM traffic (most gathers hit LDS or L2)
         "drr_nominal_gather_GBs": drr.get("effective_GBs"),
