@@ -279,7 +279,14 @@ namespace {
 // the selected classes on the solve's stream, read once the solve has
 // ended (reading them between a read-back and the next launch would put the
 // runtime's event bookkeeping on the solve's critical path).
-thread_local std::vector<hipEvent_t> t_events;
+// A thread that exits destroys its events (see Mailbox).
+struct EventPool : std::vector<hipEvent_t> {
+    ~EventPool() {
+        if (on_main_thread()) return;
+        for (hipEvent_t e : *this) (void)hipEventDestroy(e);
+    }
+};
+thread_local EventPool t_events;
 
 struct Profile {
     unsigned mask = 0;   // bit c: time class c

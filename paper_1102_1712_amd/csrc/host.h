@@ -5,6 +5,8 @@
 
 #include <math.h>
 #include <string.h>
+#include <sys/syscall.h>
+#include <unistd.h>
 
 #include <string>
 
@@ -127,6 +129,9 @@ inline bool finite_vec(const double *w, int K) {
     return true;
 }
 
+// True on the process's initial thread.
+inline bool on_main_thread() { return (pid_t)syscall(SYS_gettid) == getpid(); }
+
 // Scalar read-back through a per-thread mailbox in coherent, mapped host
 // memory: MAILBOX_VALUES values and a flag word.  A one-wave kernel on the stream copies
 // the values there and then publishes a sequence number in the flag; the
@@ -140,6 +145,11 @@ struct Mailbox {
     double *vals = nullptr;
     uint32_t *flag = nullptr;
     uint32_t seq = 0;
+    // A thread that exits returns its mailbox; the main thread's exit ends
+    // the process, whose teardown releases it after the runtime's own.
+    ~Mailbox() {
+        if (vals && !on_main_thread()) (void)hipHostFree(vals);
+    }
 };
 
 inline Mailbox *host_mailbox() {

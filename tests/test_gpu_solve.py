@@ -251,3 +251,27 @@ def test_precond_option_is_checked(torch):
     for kw in (dict(precond=1), dict(precond=1, grad_mode=2, method=2), dict(precond=2, grad_mode=2)):
         with pytest.raises(B.PcasError):
             _gpu_solve(d, y, B.default_opts(**kw))
+
+
+def test_solves_on_short_lived_threads(torch):
+    """Each host thread keeps its own read-back mailbox and timing events and
+    gives them back when it exits: solves on a run of threads that start and
+    end one after another, with every kernel class timed, return what the
+    same solve returns on this thread, bit for bit."""
+    import threading
+    c = synth.small(dtype="f32", seed=6)
+    d = Dev(c)
+    y = measured(c)
+    opts = B.default_opts(grad_mode=2, precond=1, xtol=1e-7, profile=B.PROFILE_ALL)
+    w0, rep0 = _gpu_solve(d, y, opts)
+    out = []
+    for i in range(6):
+        say("solve on thread", i)
+        t = threading.Thread(target=lambda: out.append(_gpu_solve(d, y, opts)))
+        t.start()
+        t.join()
+    assert len(out) == 6
+    for w, rep in out:
+        assert np.array_equal(w, w0)
+        assert rep["n_fevals"] == rep0["n_fevals"] and rep["J"] == rep0["J"]
+        assert sum(rep["kernel_launches"].values()) > 0
