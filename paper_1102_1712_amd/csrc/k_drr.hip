@@ -126,6 +126,15 @@ static bool slab_cells_host(const VolDims &v, const Frame &fr, int AX, int iu0, 
     return true;
 }
 
+// Row pitch of a staged box, in voxels, for an extent e along x: e rounded
+// up to 3 mod 8.  One LDS access of a wave reads cells of neighbouring rays
+// and samples, a row or two and a column or two apart.  Cells whose index
+// differs by dx + dy * pitch with |dx| <= 1, |dy| <= 2 or |dx| <= 2, |dy| <= 1
+// then never differ by a multiple of 8 (nor of 16), so the voxels (16 bytes
+// each for four interleaved FP32 volumes) fall in different bank groups;
+// at pitches near a multiple of 8 they collide.
+__host__ __device__ constexpr int box_pitch_x(int e) { return e + ((3 - e) & 7); }
+
 // What the projection kernel does with each ray's value.
 enum { FWD_WRITE = 0, FWD_SUMS = 1, FWD_DOT = 2, FWD_EVAL = 3 };
 
@@ -287,32 +296,37 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             ext[B] = sb[1] - sb[0] + 2;
             o[2] = sb[2];
             ext[2] = sb[3] - sb[2] + 2;
+            // the box's row pitch (in voxels) may exceed its extent, so that
+            // neighbouring rows fall in other LDS banks
+            const int ex = box_pitch_x(ext[0]), exy = ex * ext[1];
             const bool staged = sb[0] <= sb[1] && sb[2] <= sb[3] && ext[0] <= CAP &&
-                                ext[1] <= CAP && ext[2] <= CAP && ext[0] * ext[1] <= CAP &&
-                                ext[0] * ext[1] * ext[2] <= CAP;
-            const int ex = ext[0], exy = ext[0] * ext[1];
-            const int size = exy * ext[2];
+                                ext[1] <= CAP && ext[2] <= CAP && exy <= CAP &&
+                                exy * ext[2] <= CAP;
+            const int size = exy * ext[2];          // box elements with the padding
+            const int count = ext[0] * ext[1] * ext[2];   // voxels staged
             if (staged) {
-                // element t of a box is voxel o + (t % ex, t / ex % ey, t / exy); the
-                // quotients are exact in float for t < 2^13 (rounding error well
-                // below the 0.5 / divisor margin of (t + 0.5) / divisor)
-                const float iex = 1.0f / (float)ex, iey = 1.0f / (float)ext[1];
+                // voxel t of the box is o + (t % ex0, t / ex0 % ex1, t / (ex0 ex1)),
+                // stored at element tx + ty ex + tz exy; the quotients are exact in
+                // float for t < 2^13 (rounding error well below the 0.5 / divisor
+                // margin of (t + 0.5) / divisor)
+                const float iex = 1.0f / (float)ext[0], iey = 1.0f / (float)ext[1];
                 const int gbase = o[0] + n0 * (o[1] + n1 * o[2]);
-                for (int t = tid; t < size; t += 256) {
+                for (int t = tid; t < count; t += 256) {
                     const int q = (int)(((float)t + 0.5f) * iex);
-                    const int tx = t - __mul24(q, ex);
+                    const int tx = t - __mul24(q, ext[0]);
                     const int tz = (int)(((float)q + 0.5f) * iey);
                     const int ty = q - __mul24(tz, ext[1]);
                     const int go = (gbase + tx + __mul24(ty, n0) + tz * (n0 * n1)) * ES;
+                    const int bt = tx + __mul24(ty, ex) + __mul24(tz, exy);
                     if constexpr (IL) {
                         T val[NV];
 #pragma unroll
                         for (int v = 0; v < NV; ++v) val[v] = buf_load(rf[v], go, 0, T());
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) box[t * NV + v] = val[v];
+                        for (int v = 0; v < NV; ++v) box[bt * NV + v] = val[v];
                     } else {
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) box[v * size + t] = buf_load(rf[v], go, 0, T());
+                        for (int v = 0; v < NV; ++v) box[v * size + bt] = buf_load(rf[v], go, 0, T());
                     }
                 }
             }
@@ -329,16 +343,27 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             const T sh0 = sh;
             bool miss = !staged;
             if (staged) {
+                // A ray's cells are monotone in sh along every axis, so the box
+                // holds all of a lane's samples in this slab iff it holds the
+                // first and the last.  The march reads at offsets clamped into
+                // the box (every corner read stays inside it) and the two ends
+                // are checked after it; along AX the slab test bounds the cell.
+                constexpr int B2 = AX == 0 ? 1 : 0;
+                auto inside = [&](const int (&c)[3]) {
+                    return (unsigned)(c[B2] - o[B2]) < (unsigned)(ext[B2] - 1) &&
+                           (unsigned)(c[2] - o[2]) < (unsigned)(ext[2] - 1);
+                };
+                const bool first_in = inside(l);
+                // byte offset of a cell = its index in box pitches x EV - obase
+                // (mod 2^32: cells below the box wrap past omax), at most omax =
+                // the offset of the box's last cell
+                const uint32_t obase = (uint32_t)((o[0] + o[1] * ex + o[2] * exy) * EV);
+                const uint32_t omax =
+                    (uint32_t)(((ext[0] - 2) + (ext[1] - 2) * ex + (ext[2] - 2) * exy) * EV);
                 while (have && (unsigned)(l[AX] - A0) < (unsigned)slab) {
-                    // along AX the slab test already bounds the cell (l <= n - 2)
-                    constexpr int B2 = AX == 0 ? 1 : 0;
-                    const int lx = l[0] - o[0], ly = l[1] - o[1], lz = l[2] - o[2];
-                    const int lb = B2 == 0 ? lx : ly;
-                    const bool in = (unsigned)lb < (unsigned)(ext[B2] - 1) &&
-                                    (unsigned)lz < (unsigned)(ext[2] - 1);
-                    miss |= !in;
-                    const int off =
-                        in ? (lx + __mul24(ly, ex) + __mul24(lz, exy)) * EV : 0;
+                    const uint32_t idx = __umul24((uint32_t)l[2], (uint32_t)exy) +
+                                         __umul24((uint32_t)l[1], (uint32_t)ex) + (uint32_t)l[0];
+                    const int off = (int)min(idx * (uint32_t)EV - obase, omax);
                     if constexpr (NV >= 3) {
                         // several volumes: the eight corner weights once, then
                         // eight products per volume instead of seven lerps
@@ -375,6 +400,12 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                     sh += (T)SPLIT;
                     have = sh < shn;
                     sample_cell(e, d, sh, top, l, z);
+                }
+                if (sh != sh0) {   // the lane took samples in this slab
+                    int lq[3];
+                    T zq[3];
+                    sample_cell(e, d, sh - (T)SPLIT, top, lq, zq);
+                    miss = !(first_in && inside(lq));
                 }
             }
             if (miss) {
@@ -527,7 +558,10 @@ static void forward_plan(const VolDims &v, const Frame &fr, int cap, int *axis, 
                         fits = false;
                         break;
                     }
-                    const long long size = (long long)(S + 1) * (hi[0] - lo[0] + 2) * (hi[1] - lo[1] + 2);
+                    const int eb = hi[0] - lo[0] + 2, ec = hi[1] - lo[1] + 2;
+                    const long long size = AX == 0
+                        ? (long long)box_pitch_x(S + 1) * eb * ec
+                        : (long long)box_pitch_x(eb) * (S + 1) * ec;
                     if (size > cap) fits = false;
                 }
             }
