@@ -24,7 +24,7 @@ def _loss_and_grad(torch, d, w_np, r):
     p = AG.project(w, c.vol, c.proj, d.rays, d.f0, d.mean, d.U)
     L = (p.double() * r.double()).sum()
     L.backward()
-    return float(L), w.grad.numpy().copy()
+    return float(L.detach()), w.grad.numpy().copy()
 
 
 def _fd_grad(torch, d, f0, w0, r, h):
