@@ -305,19 +305,12 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
             const int size = exy * ext[2];          // box elements with the padding
             const int count = ext[0] * ext[1] * ext[2];   // voxels staged
             if (staged) {
-                // voxel t of the box is o + (t % ex0, t / ex0 % ex1, t / (ex0 ex1)),
-                // stored at element tx + ty ex + tz exy; the quotients are exact in
-                // float for t < 2^13 (rounding error well below the 0.5 / divisor
-                // margin of (t + 0.5) / divisor)
-                const float iex = 1.0f / (float)ext[0], iey = 1.0f / (float)ext[1];
+                const int e0 = ext[0], e1 = ext[1];
+                const int n01 = n0 * n1;
                 const int gbase = o[0] + n0 * (o[1] + n1 * o[2]);
-                for (int t = tid; t < count; t += 256) {
-                    const int q = (int)(((float)t + 0.5f) * iex);
-                    const int tx = t - __mul24(q, ext[0]);
-                    const int tz = (int)(((float)q + 0.5f) * iey);
-                    const int ty = q - __mul24(tz, ext[1]);
-                    const int go = (gbase + tx + __mul24(ty, n0) + tz * (n0 * n1)) * ES;
-                    const int bt = tx + __mul24(ty, ex) + __mul24(tz, exy);
+                // the voxel (tx, ty, tz) of the box, read at byte go of each
+                // volume and stored at element bt = tx + ty ex + tz exy
+                auto stage = [&](int go, int bt) {
                     if constexpr (IL) {
                         T val[NV];
 #pragma unroll
@@ -327,6 +320,52 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                     } else {
 #pragma unroll
                         for (int v = 0; v < NV; ++v) box[v * size + bt] = buf_load(rf[v], go, 0, T());
+                    }
+                };
+                // Quotients by float: exact for dividends below 2^13 (the
+                // rounding error stays well below the 0.5 / divisor margin of
+                // (t + 0.5) / divisor).
+                const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
+                const int R = (int)(256.5f * ie0);   // whole rows per pass of the block
+                if (R > 0) {
+                    // lane tid takes column tx = tid % e0 of rows r0 = tid / e0,
+                    // r0 + R, ...; row r is (ty, tz) = (r % e1, r / e1), and a step
+                    // of R rows adds (Ry, Rz) with at most one carry into z
+                    const int r0 = (int)(((float)tid + 0.5f) * ie0);
+                    const int tx = tid - __mul24(r0, e0);
+                    const int Rz = (int)(((float)R + 0.5f) * ie1), Ry = R - __mul24(Rz, e1);
+                    const int tz = (int)(((float)r0 + 0.5f) * ie1);
+                    int ty = r0 - __mul24(tz, e1);
+                    // byte offsets in the volume step modulo 2^32 (the carry's
+                    // n0 n1 - e1 n0 may be negative); every offset read is a
+                    // voxel's, below 2^31.  Box elements are tx + r ex (exy = e1 ex).
+                    uint32_t go = (uint32_t)((gbase + tx + __mul24(ty, n0) + tz * n01) * ES);
+                    const uint32_t dgo = ((uint32_t)Ry * (uint32_t)n0 + (uint32_t)Rz * (uint32_t)n01) * ES;
+                    const uint32_t cgo = ((uint32_t)n01 - (uint32_t)e1 * (uint32_t)n0) * ES;
+                    int bt = tx + __mul24(r0, ex);
+                    const int dbt = __mul24(R, ex);
+                    const int rows = e1 * ext[2];
+                    if (r0 < R) {
+                        for (int r = r0; r < rows; r += R) {
+                            stage((int)go, bt);
+                            ty += Ry;
+                            go += dgo;
+                            bt += dbt;
+                            if (ty >= e1) {
+                                ty -= e1;
+                                go += cgo;
+                            }
+                        }
+                    }
+                } else {
+                    // rows longer than the block: voxel t = tx + e0 (ty + e1 tz)
+                    for (int t = tid; t < count; t += 256) {
+                        const int q = (int)(((float)t + 0.5f) * ie0);
+                        const int tx = t - __mul24(q, e0);
+                        const int tz = (int)(((float)q + 0.5f) * ie1);
+                        const int ty = q - __mul24(tz, e1);
+                        stage((gbase + tx + __mul24(ty, n0) + tz * n01) * ES,
+                              tx + __mul24(ty, ex) + __mul24(tz, exy));
                     }
                 }
             }
