@@ -508,7 +508,7 @@ struct Solver {
         mom_src = scal();
         if (!one_pass) return residual(ab_fixed, slot, J, a, b, rule, w);
         double mo[3], kappa;
-        const int nbf = drr_forward_blocks(fr.nu, fr.nv);
+        const int nbf = drr_forward_blocks(fr.nu, fr.nv, fplan.tile);
         int st;
         if (speculate && rule && rule->mode != GRAD_NEVER) {
             HIPCHK(launch_spec_decide((const double *)(ws + L.partials), nbf, FWD_THREADS, ff, *rule,
@@ -568,7 +568,7 @@ struct Solver {
             if ((st = residual(ab_fixed, slot, J, a, b, nullptr, nullptr, F.m + 6, ns - 6)))
                 return st;
         } else {
-            const int nbf = drr_forward_blocks(fr.nu, fr.nv);
+            const int nbf = drr_forward_blocks(fr.nu, fr.nv, fplan_e.tile);
             if ((st = sync_read_sum(F.m, nbf, EVAL_SUM_WIDTH, 1.0, sums, ns))) return st;
             double kappa;
             objective_from_moments(F.m, ff, J, a, b, &kappa);
@@ -684,7 +684,8 @@ struct Solver {
             }));
         }
         ++n_grads;
-        const int nb = grad_mode == 0 ? drr_forward_blocks(fr.nu, fr.nv) : drr_adjoint_chain_blocks(vd);
+        const int nb = grad_mode == 0 ? drr_forward_blocks(fr.nu, fr.nv, fplan_k.tile)
+                                      : drr_adjoint_chain_blocks(vd);
         int st = sync_read_sum(g, nb, grad_mode == 0 ? FWD_THREADS : ADJ_THREADS, 2.0, scal() + 8, K);
         if (st) return st;
         for (int k = 0; k < K; ++k)

@@ -58,16 +58,24 @@ constexpr int BRICK_X = 32, BRICK_Y = 16, BRICK_Z = 8;
 constexpr int ADJ_WAVES = 8;
 constexpr int ADJ_THREADS = 64 * ADJ_WAVES;
 constexpr int FWD_THREADS = 256;
-// Forward projection: FWD_SPLIT lanes march one ray (interleaved samples),
-// a wave covers FWD_WU x FWD_WV neighbouring rays, a 256-thread block 2 x 2
-// such wave tiles (a bundle of TILE_U x TILE_V rays).  The bundle stages its
-// footprint in the volume slab by slab in an LDS box of FWD_LDS_BYTES.
-constexpr int FWD_SPLIT = 4, FWD_WU = 4;
-constexpr int FWD_WV = 64 / FWD_SPLIT / FWD_WU;
-constexpr int TILE_U = 2 * FWD_WU, TILE_V = 2 * FWD_WV;
+// Forward projection, tile shape ts: fwd_split(ts) lanes march one ray
+// (interleaved samples), a wave covers fwd_wu(ts) x fwd_wv(ts) neighbouring
+// rays, a 256-thread block 2 x 2 such wave tiles (a bundle of tile_u(ts) x
+// tile_v(ts) rays).  The bundle stages its footprint in the volume slab by
+// slab in an LDS box of FWD_LDS_BYTES per volume (two for several volumes).
+// Shape 0: 4 lanes a ray, 8 x 8 rays.  Shape 1: one lane a ray, 16 x 16 rays,
+// whose larger box serves four times the rays (the plan takes it for FP32
+// projections of three or more volumes whenever its boxes fit some slabs).
+constexpr int fwd_split(int ts) { return ts == 0 ? 4 : 1; }
+constexpr int fwd_wu(int ts) { return ts == 0 ? 4 : 8; }
+constexpr int fwd_wv(int ts) { return 64 / fwd_split(ts) / fwd_wu(ts); }
+constexpr int tile_u(int ts) { return 2 * fwd_wu(ts); }
+constexpr int tile_v(int ts) { return 2 * fwd_wv(ts); }
 constexpr int FWD_LDS_BYTES = 16384;
 constexpr int FWD_MAX_SLABS = 128;
-static_assert(FWD_WU * FWD_WV * FWD_SPLIT == 64, "forward wave tile");
+static_assert(fwd_wu(0) * fwd_wv(0) * fwd_split(0) == 64, "forward wave tile");
+static_assert(fwd_wu(1) * fwd_wv(1) * fwd_split(1) == 64, "forward wave tile");
+static_assert(tile_u(1) * tile_v(1) >= tile_u(0) * tile_v(0), "shape 0 has the most blocks");
 // Values one scalar read-back can return (the mapped mailbox's size).
 constexpr int MAILBOX_VALUES = 80;
 // Sums the fused evaluation's projection reduces for K modes (see
@@ -321,9 +329,11 @@ int64_t live_voxels(const VolDims &v, const Frame &fr);
 // launches below (the chain's blocks have ADJ_THREADS threads).
 // The geometry-only launch plan (slab axis and thickness) is computed once
 // per projection on the host.
-int drr_forward_blocks(int nu, int nv);
+// Blocks of a forward launch in tile shape ts; shape 0, the default, gives
+// the most (workspaces are sized with it).
+int drr_forward_blocks(int nu, int nv, int ts = 0);
 struct ForwardPlan {
-    int axis = 0, slab = 0;
+    int axis = 0, slab = 0, tile = 0;
 };
 ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr, int nvol);
 hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
@@ -486,10 +496,11 @@ FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, 
 hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *jobs, int njobs,
                                          int total_blocks, hipStream_t s);
 // Several requests' fused-evaluation projections (launch_drr_forward_eval;
-// J.f holds the K + 1 volumes, J.fit the reference fit) of one dtype, K and
-// slab axis in one launch.
-hipError_t launch_drr_forward_eval_batch(pcas_dtype dt, int K, int axis, const FwdJob *jobs,
-                                         int njobs, int total_blocks, hipStream_t s);
+// J.f holds the K + 1 volumes, J.fit the reference fit) of one dtype, K,
+// slab axis and tile shape in one launch.
+hipError_t launch_drr_forward_eval_batch(pcas_dtype dt, int K, int axis, int tile,
+                                         const FwdJob *jobs, int njobs, int total_blocks,
+                                         hipStream_t s);
 // Several requests' warps with their Jacobian volumes (launch_warp_jac; J.f
 // receives the K + 1 volumes) of one dtype and K in one launch.
 hipError_t launch_warp_jac_batch(pcas_dtype dt, int K, const WarpJob *jobs, int njobs,

@@ -1,10 +1,10 @@
 // a4: forward projection P f and a6: back-projection P^T r.
 //
-// Forward: each ray is marched by FWD_SPLIT lanes that take interleaved
-// samples (s = seg, seg + FWD_SPLIT, ...); a wave covers a tile of
-// neighbouring rays, whose samples at equal index sit within a few voxels of
-// each other, so the 8-neighbour gathers of a wave hit a handful of cache
-// lines.  The partial sums of a ray are combined by a fixed butterfly.
+// Forward: each ray is marched by fwd_split(ts) lanes that take interleaved
+// samples (s = seg, seg + split, ...); a wave covers a tile of neighbouring
+// rays, whose samples at equal index sit within a few voxels of each other.
+// A block stages the voxels its bundle of rays can reach slab by slab in LDS.
+// The partial sums of a ray are combined by a fixed butterfly.
 //
 // Adjoint: the exact transpose of the forward without global atomics.  A
 // 512-thread workgroup owns a 32 x 16 x 8 voxel brick held in LDS.  It
@@ -141,7 +141,7 @@ enum { FWD_WRITE = 0, FWD_SUMS = 1, FWD_DOT = 2, FWD_EVAL = 3 };
 // LDS budget of the staged boxes: one volume 16 KB, several 32 KB.
 constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_LDS_BYTES; }
 
-// Forward projection of one bundle of TILE_U x TILE_V rays through NV
+// Forward projection of one bundle of tile_u(TS) x tile_v(TS) rays through NV
 // volumes f[v * N + voxel] at once (same rays, same samples, same weights).
 // The bundle walks the volume in slabs of `slab` cells along the axis AX
 // its rays mostly travel (x or y): per slab the block copies the box of
@@ -162,7 +162,7 @@ constexpr int fwd_lds_bytes(int nv) { return nv == 1 ? FWD_LDS_BYTES : 2 * FWD_L
 // q_v = (P f_v) are not stored; out[v] = 2 sum_rays r q_v with the residual
 // r = p - a y - b of the stored projection p.  MODE FWD_EVAL (NV = K + 1):
 // p = P f of volume 0 and the moment sums of launch_drr_forward_eval.
-template <typename T, int AX, int NV, int MODE>
+template <typename T, int AX, int NV, int MODE, int TS>
 __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame &fr, int tiles_u,
                                                   int slab, const RayRec<T> *__restrict__ rays,
                                                   const T *__restrict__ f, T *__restrict__ p,
@@ -170,7 +170,8 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
                                                   const FitArgs &fit, double *__restrict__ partials,
                                                   uint32_t *counter, double *__restrict__ out,
                                                   int lb, int nb) {
-    constexpr int SPLIT = FWD_SPLIT;
+    constexpr int SPLIT = fwd_split(TS), WU = fwd_wu(TS), WV = fwd_wv(TS);
+    constexpr int TU = tile_u(TS), TV = tile_v(TS);
     constexpr int CAPT = fwd_lds_bytes(NV) / (int)sizeof(T);   // all volumes
     constexpr int CAP = CAPT / NV;                               // one volume's box
     constexpr int ES = (int)sizeof(T);
@@ -188,8 +189,8 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
     const int tu = bid % tiles_u, tv = bid / tiles_u;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int seg = lane % SPLIT, rl = lane / SPLIT;
-    const int iu = tu * TILE_U + (wave & 1) * FWD_WU + rl % FWD_WU;
-    const int iv = tv * TILE_V + (wave >> 1) * FWD_WV + rl / FWD_WU;
+    const int iu = tu * TU + (wave & 1) * WU + rl % WU;
+    const int iv = tv * TV + (wave >> 1) * WV + rl / WU;
     const bool valid = iu < nu && iv < nv;
     const int pix = iv * nu + iu;
     RayRec<T> r;
@@ -235,8 +236,8 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
     const T shn = (T)r.n;          // sample s exists iff s + 1/2 < n
     T sh = (T)seg + (T)0.5;
     if (use_slabs) {
-        const int iu0 = tu * TILE_U, iu1 = min(iu0 + TILE_U, nu) - 1;
-        const int iv0 = tv * TILE_V, iv1 = min(iv0 + TILE_V, nv) - 1;
+        const int iu0 = tu * TU, iu1 = min(iu0 + TU, nu) - 1;
+        const int iv0 = tv * TV, iv1 = min(iv0 + TV, nv) - 1;
         // staged box of every slab: eight lanes per slab, one per corner ray
         // and plane, reduced with shuffles (keeps the FP64 geometry out of
         // the march's register budget)
@@ -532,15 +533,15 @@ __device__ __forceinline__ void drr_forward_block(const VolDims &vd, const Frame
     }
 }
 
-template <typename T, int AX, int NV, int MODE>
+template <typename T, int AX, int NV, int MODE, int TS>
 __global__ __launch_bounds__(256) void k_drr_forward(VolDims vd, Frame fr, int tiles_u, int slab,
                                                      const RayRec<T> *__restrict__ rays,
                                                      const T *__restrict__ f, T *__restrict__ p,
                                                      const T *__restrict__ y, double fa, double fb,
                                                      FitArgs fit, double *__restrict__ partials,
                                                      uint32_t *counter, double *__restrict__ out) {
-    drr_forward_block<T, AX, NV, MODE>(vd, fr, tiles_u, slab, rays, f, p, y, fa, fb, fit, partials,
-                                       counter, out, blockIdx.x, gridDim.x);
+    drr_forward_block<T, AX, NV, MODE, TS>(vd, fr, tiles_u, slab, rays, f, p, y, fa, fb, fit,
+                                           partials, counter, out, blockIdx.x, gridDim.x);
 }
 
 // Several requests' projections (with the fit sums) in one launch.
@@ -549,38 +550,41 @@ __global__ __launch_bounds__(256) void k_drr_forward_batch(const FwdJob *__restr
                                                            int njobs) {
     const int j = job_of(jobs, njobs);
     const FwdJob &J = jobs[j];
-    drr_forward_block<T, AX, 1, FWD_SUMS>(J.vd, J.fr, J.tiles_u, J.slab,
+    drr_forward_block<T, AX, 1, FWD_SUMS, 0>(J.vd, J.fr, J.tiles_u, J.slab,
                                           (const RayRec<T> *)J.rays, (const T *)J.f, (T *)J.p,
                                           (const T *)J.y, 0.0, 0.0, J.fit, J.partials, J.counter,
                                           J.out, blockIdx.x - J.block0, J.nblocks);
 }
 
 // Several requests' fused-evaluation projections in one launch.
-template <typename T, int AX, int K>
+template <typename T, int AX, int K, int TS>
 __global__ __launch_bounds__(256) void k_drr_forward_eval_batch(const FwdJob *__restrict__ jobs,
                                                                 int njobs) {
     const int j = job_of(jobs, njobs);
     const FwdJob &J = jobs[j];
-    drr_forward_block<T, AX, K + 1, FWD_EVAL>(J.vd, J.fr, J.tiles_u, J.slab,
+    drr_forward_block<T, AX, K + 1, FWD_EVAL, TS>(J.vd, J.fr, J.tiles_u, J.slab,
                                               (const RayRec<T> *)J.rays, (const T *)J.f,
                                               (T *)J.p, (const T *)J.y, 0.0, 0.0, J.fit,
                                               J.partials, J.counter, J.out,
                                               blockIdx.x - J.block0, J.nblocks);
 }
 
-int drr_forward_blocks(int nu, int nv) {
-    return ((nu + TILE_U - 1) / TILE_U) * ((nv + TILE_V - 1) / TILE_V);
+int drr_forward_blocks(int nu, int nv, int ts) {
+    const int TU = tile_u(ts), TV = tile_v(ts);
+    return ((nu + TU - 1) / TU) * ((nv + TV - 1) / TV);
 }
 
 // Slab axis and thickness for a projection: the in-plane axis (x or y) the
 // central ray advances fastest along in index units, and the thickest slab
 // (32, 16 or 8 cells) whose staged boxes fit the LDS budget for bundles at
 // the centre, edges and corners of the detector.  slab 0 means "no slabs".
-static void forward_plan(const VolDims &v, const Frame &fr, int cap, int *axis, int *slab) {
+static void forward_plan(const VolDims &v, const Frame &fr, int cap, int ts, int *axis,
+                         int *slab) {
     const double ax = fabs(fr.en[0]) * v.inv_s[0], ay = fabs(fr.en[1]) * v.inv_s[1];
     const int AX = ay > ax ? 1 : 0;
     const int na = AX == 0 ? v.n0 : v.n1;
-    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U, tiles_v = (fr.nv + TILE_V - 1) / TILE_V;
+    const int TU = tile_u(ts), TV = tile_v(ts);
+    const int tiles_u = (fr.nu + TU - 1) / TU, tiles_v = (fr.nv + TV - 1) / TV;
     *axis = AX;
     *slab = 0;
     for (int S = 32; S >= 8; S >>= 1) {
@@ -589,8 +593,8 @@ static void forward_plan(const VolDims &v, const Frame &fr, int cap, int *axis, 
         for (int gv = 0; gv < 3 && fits; ++gv)
             for (int gu = 0; gu < 3 && fits; ++gu) {
                 const int tu = gu * (tiles_u - 1) / 2, tv = gv * (tiles_v - 1) / 2;
-                const int iu0 = tu * TILE_U, iu1 = std::min(iu0 + TILE_U, fr.nu) - 1;
-                const int iv0 = tv * TILE_V, iv1 = std::min(iv0 + TILE_V, fr.nv) - 1;
+                const int iu0 = tu * TU, iu1 = std::min(iu0 + TU, fr.nu) - 1;
+                const int iv0 = tv * TV, iv1 = std::min(iv0 + TV, fr.nv) - 1;
                 for (int A0 = 0; A0 <= na - 2 && fits; A0 += S) {
                     int lo[2], hi[2];
                     if (!slab_cells_host(v, fr, AX, iu0, iu1, iv0, iv1, A0, S, lo, hi)) {
@@ -611,34 +615,65 @@ static void forward_plan(const VolDims &v, const Frame &fr, int cap, int *axis, 
     }
 }
 
+// FP32 projections of three or more volumes take tile shape 1 when its
+// boxes fit slabs of some thickness (8 cells at least); otherwise, and for
+// one or two volumes, shape 0.  On the clinical workload at seven angles,
+// shape 1 took the four-volume projection 3-18% below shape 0, also where it
+// needed thinner slabs, and the one-volume projection 15-27% above it.
 ForwardPlan plan_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr, int nvol) {
     ForwardPlan pl;
     const int es = dt == PCAS_F32 ? 4 : 8;
-    forward_plan(v, fr, fwd_lds_bytes(nvol) / es / nvol, &pl.axis, &pl.slab);
+    const int cap = fwd_lds_bytes(nvol) / es / nvol;
+    if (dt == PCAS_F32 && nvol >= 3) {
+        forward_plan(v, fr, cap, 1, &pl.axis, &pl.slab);
+        if (pl.slab > 0) {
+            pl.tile = 1;
+            return pl;
+        }
+    }
+    forward_plan(v, fr, cap, 0, &pl.axis, &pl.slab);
+    pl.tile = 0;
     return pl;
 }
 
-template <typename T, int AX, int NV, int MODE>
-static void launch_fwd(dim3 grid, const VolDims &v, const Frame &fr, int tiles_u, int slab,
-                       const void *rays, const void *f, void *p, const void *y, double a, double b,
+template <typename T, int AX, int NV, int MODE, int TS>
+static void launch_fwd(const VolDims &v, const Frame &fr, int slab, const void *rays,
+                       const void *f, void *p, const void *y, double a, double b,
                        const FitArgs &fit, double *partials, uint32_t *counter, double *out,
                        hipStream_t s) {
-    hipLaunchKernelGGL((k_drr_forward<T, AX, NV, MODE>), grid, dim3(FWD_THREADS), 0, s, v, fr, tiles_u, slab,
-                       (const RayRec<T> *)rays, (const T *)f, (T *)p, (const T *)y, a, b, fit,
-                       partials, counter, out);
+    const int tiles_u = (fr.nu + tile_u(TS) - 1) / tile_u(TS);
+    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv, TS));
+    hipLaunchKernelGGL((k_drr_forward<T, AX, NV, MODE, TS>), grid, dim3(FWD_THREADS), 0, s, v, fr,
+                       tiles_u, slab, (const RayRec<T> *)rays, (const T *)f, (T *)p,
+                       (const T *)y, a, b, fit, partials, counter, out);
 }
 
+// Shape 1 is instantiated only where the plan can pick it (FP32, NV >= 3).
+template <typename T, int NV>
+constexpr bool has_shape1() { return sizeof(T) == 4 && NV >= 3; }
+
 template <typename T, int NV, int MODE>
-static void launch_fwd_axis(const ForwardPlan &pl, dim3 grid, const VolDims &v, const Frame &fr,
-                            int tiles_u, const void *rays, const void *f, void *p, const void *y,
-                            double a, double b, const FitArgs &fit, double *partials,
-                            uint32_t *counter, double *out, hipStream_t s) {
+static void launch_fwd_axis(const ForwardPlan &pl, const VolDims &v, const Frame &fr,
+                            const void *rays, const void *f, void *p, const void *y, double a,
+                            double b, const FitArgs &fit, double *partials, uint32_t *counter,
+                            double *out, hipStream_t s) {
+    if constexpr (has_shape1<T, NV>()) {
+        if (pl.tile == 1) {
+            if (pl.axis == 0)
+                launch_fwd<T, 0, NV, MODE, 1>(v, fr, pl.slab, rays, f, p, y, a, b, fit, partials,
+                                              counter, out, s);
+            else
+                launch_fwd<T, 1, NV, MODE, 1>(v, fr, pl.slab, rays, f, p, y, a, b, fit, partials,
+                                              counter, out, s);
+            return;
+        }
+    }
     if (pl.axis == 0)
-        launch_fwd<T, 0, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, fit,
-                                   partials, counter, out, s);
+        launch_fwd<T, 0, NV, MODE, 0>(v, fr, pl.slab, rays, f, p, y, a, b, fit, partials, counter,
+                                      out, s);
     else
-        launch_fwd<T, 1, NV, MODE>(grid, v, fr, tiles_u, pl.slab, rays, f, p, y, a, b, fit,
-                                   partials, counter, out, s);
+        launch_fwd<T, 1, NV, MODE, 0>(v, fr, pl.slab, rays, f, p, y, a, b, fit, partials, counter,
+                                      out, s);
 }
 
 static FitArgs no_fit() {
@@ -650,23 +685,21 @@ hipError_t launch_drr_forward(pcas_dtype dt, const VolDims &v, const Frame &fr,
                               const ForwardPlan &plan, const void *rays, const void *f, void *p,
                               const void *y, const FitArgs *fit, double *partials,
                               uint32_t *counter, double *sums, hipStream_t s) {
-    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
-    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
     const FitArgs fa = fit ? *fit : no_fit();
     if (dt == PCAS_F32) {
         if (sums)
-            launch_fwd_axis<float, 1, FWD_SUMS>(plan, grid, v, fr, tiles_u, rays, f, p, y, 0.0, 0.0,
-                                                fa, partials, counter, sums, s);
+            launch_fwd_axis<float, 1, FWD_SUMS>(plan, v, fr, rays, f, p, y, 0.0, 0.0, fa, partials,
+                                                counter, sums, s);
         else
-            launch_fwd_axis<float, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
-                                                 0.0, 0.0, fa, nullptr, nullptr, nullptr, s);
+            launch_fwd_axis<float, 1, FWD_WRITE>(plan, v, fr, rays, f, p, nullptr, 0.0, 0.0, fa,
+                                                 nullptr, nullptr, nullptr, s);
     } else {
         if (sums)
-            launch_fwd_axis<double, 1, FWD_SUMS>(plan, grid, v, fr, tiles_u, rays, f, p, y, 0.0,
-                                                 0.0, fa, partials, counter, sums, s);
+            launch_fwd_axis<double, 1, FWD_SUMS>(plan, v, fr, rays, f, p, y, 0.0, 0.0, fa, partials,
+                                                 counter, sums, s);
         else
-            launch_fwd_axis<double, 1, FWD_WRITE>(plan, grid, v, fr, tiles_u, rays, f, p, nullptr,
-                                                  0.0, 0.0, fa, nullptr, nullptr, nullptr, s);
+            launch_fwd_axis<double, 1, FWD_WRITE>(plan, v, fr, rays, f, p, nullptr, 0.0, 0.0, fa,
+                                                  nullptr, nullptr, nullptr, s);
     }
     return hipGetLastError();
 }
@@ -677,7 +710,7 @@ FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, 
     FwdJob J;
     J.vd = v;
     J.fr = fr;
-    J.tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
+    J.tiles_u = (fr.nu + tile_u(plan.tile) - 1) / tile_u(plan.tile);
     J.slab = plan.slab;
     J.rays = rays;
     J.f = f;
@@ -688,7 +721,7 @@ FwdJob make_fwd_job(const VolDims &v, const Frame &fr, const ForwardPlan &plan, 
     J.counter = counter;
     J.out = sums;
     J.block0 = 0;
-    J.nblocks = drr_forward_blocks(fr.nu, fr.nv);
+    J.nblocks = drr_forward_blocks(fr.nu, fr.nv, plan.tile);
     return J;
 }
 
@@ -710,23 +743,39 @@ hipError_t launch_drr_forward_sums_batch(pcas_dtype dt, int axis, const FwdJob *
     return hipGetLastError();
 }
 
-template <typename T, int K>
-static void eval_batch_axis(int axis, const FwdJob *jobs, int njobs, int total_blocks,
-                            hipStream_t s) {
+template <typename T, int K, int TS>
+static void eval_batch_shape(int axis, const FwdJob *jobs, int njobs, int total_blocks,
+                             hipStream_t s) {
     if (axis == 0)
-        hipLaunchKernelGGL((k_drr_forward_eval_batch<T, 0, K>), dim3(total_blocks), dim3(256), 0, s,
-                           jobs, njobs);
+        hipLaunchKernelGGL((k_drr_forward_eval_batch<T, 0, K, TS>), dim3(total_blocks), dim3(256),
+                           0, s, jobs, njobs);
     else
-        hipLaunchKernelGGL((k_drr_forward_eval_batch<T, 1, K>), dim3(total_blocks), dim3(256), 0, s,
-                           jobs, njobs);
+        hipLaunchKernelGGL((k_drr_forward_eval_batch<T, 1, K, TS>), dim3(total_blocks), dim3(256),
+                           0, s, jobs, njobs);
 }
 
-hipError_t launch_drr_forward_eval_batch(pcas_dtype dt, int K, int axis, const FwdJob *jobs,
-                                         int njobs, int total_blocks, hipStream_t s) {
+template <typename T, int K>
+static hipError_t eval_batch_axis(int axis, int tile, const FwdJob *jobs, int njobs,
+                                  int total_blocks, hipStream_t s) {
+    if constexpr (has_shape1<T, K + 1>()) {
+        if (tile == 1) {
+            eval_batch_shape<T, K, 1>(axis, jobs, njobs, total_blocks, s);
+            return hipSuccess;
+        }
+    }
+    if (tile != 0) return hipErrorInvalidValue;
+    eval_batch_shape<T, K, 0>(axis, jobs, njobs, total_blocks, s);
+    return hipSuccess;
+}
+
+hipError_t launch_drr_forward_eval_batch(pcas_dtype dt, int K, int axis, int tile,
+                                         const FwdJob *jobs, int njobs, int total_blocks,
+                                         hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
 #define D(TT, KK)                                                                                  \
     case KK:                                                                                       \
-        eval_batch_axis<TT, KK>(axis, jobs, njobs, total_blocks, s);                               \
+        if (hipError_t e = eval_batch_axis<TT, KK>(axis, tile, jobs, njobs, total_blocks, s))     \
+            return e;                                                                              \
         break
     if (dt == PCAS_F32) {
         switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);
@@ -746,14 +795,12 @@ hipError_t launch_drr_forward_dot(pcas_dtype dt, const VolDims &v, const Frame &
                                   const void *p, const void *y, double a, double b,
                                   double *partials, uint32_t *counter, double *g_out,
                                   hipStream_t s) {
-    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
-    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
     void *pp = const_cast<void *>(p);
     const FitArgs fa = no_fit();
 #define D(TT, KK)                                                                                  \
     case KK:                                                                                       \
-        launch_fwd_axis<TT, KK, FWD_DOT>(plan, grid, v, fr, tiles_u, rays, J, pp, y, a, b, fa,     \
-                                         partials, counter, g_out, s);                             \
+        launch_fwd_axis<TT, KK, FWD_DOT>(plan, v, fr, rays, J, pp, y, a, b, fa, partials, counter, \
+                                         g_out, s);                                                \
         break
     if (dt == PCAS_F32) {
         switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);
@@ -773,12 +820,10 @@ hipError_t launch_drr_forward_eval(pcas_dtype dt, const VolDims &v, const Frame 
                                    const void *vols, void *p, const void *y, const FitArgs &fit,
                                    double *partials, uint32_t *counter, double *sums,
                                    hipStream_t s) {
-    const int tiles_u = (fr.nu + TILE_U - 1) / TILE_U;
-    const dim3 grid(drr_forward_blocks(fr.nu, fr.nv));
 #define D(TT, KK)                                                                                  \
     case KK:                                                                                       \
-        launch_fwd_axis<TT, KK + 1, FWD_EVAL>(plan, grid, v, fr, tiles_u, rays, vols, p, y, 0.0,   \
-                                              0.0, fit, partials, counter, sums, s);               \
+        launch_fwd_axis<TT, KK + 1, FWD_EVAL>(plan, v, fr, rays, vols, p, y, 0.0, 0.0, fit,        \
+                                              partials, counter, sums, s);                         \
         break
     if (dt == PCAS_F32) {
         switch (K) { D(float, 1); D(float, 2); D(float, 3); D(float, 4);

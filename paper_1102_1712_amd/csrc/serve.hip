@@ -393,7 +393,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
     // this pass's operations, batched
     typedef std::pair<int, int> DK;   // (dtype, K) or (dtype, axis)
     Groups<WarpJob, DK> warps, warpjacs;
-    Groups<FwdJob, DK> fwds, fwd_evals;   // fwd_evals: ((dtype, K), axis) as (16 dtype + K, axis)
+    Groups<FwdJob, DK> fwds, fwd_evals;   // fwd_evals: (16 dtype + K, axis + 2 tile shape)
     Groups<ResJob, int> ress;
     Groups<AdjJob, DK> adjs;
     std::vector<SpecJob> specs;
@@ -439,7 +439,7 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                                            r->ws + r->L.vol2, r->proj_slot(op.slot), r->y, ff,
                                            r->partials(), defer ? nullptr : &r->counters()[0],
                                            r->scal());
-            fwd_evals.add({16 * (int)md.dt + md.K, r->plan_e.axis}, fj);
+            fwd_evals.add({16 * (int)md.dt + md.K, r->plan_e.axis + 2 * r->plan_e.tile}, fj);
             if (defer) {
                 SumJob &sj = sums[ri];
                 sj.partials = r->partials();
@@ -589,8 +589,9 @@ int run_pass(pcas_server *S, const std::vector<Request *> &set, int32_t *n_done)
                                              S->s));
     for (auto &g : fwd_evals.groups)
         HIPCHK(launch_drr_forward_eval_batch((pcas_dtype)(g.key.first / 16), g.key.first % 16,
-                                             g.key.second, (const FwdJob *)(d + o_fe) + g.first,
-                                             g.count, g.blocks, S->s));
+                                             g.key.second & 1, g.key.second >> 1,
+                                             (const FwdJob *)(d + o_fe) + g.first, g.count,
+                                             g.blocks, S->s));
     for (auto &g : ress.groups)
         HIPCHK(launch_residual_batch((pcas_dtype)g.key, (const ResJob *)(d + o_r) + g.first,
                                      g.count, g.blocks, S->s));
