@@ -34,7 +34,7 @@ def _declared_functions():
     return sorted(set(names))
 
 
-def test_header_declares_the_north_star_entry_points():
+def test_header_declares_the_hot_path_entry_points():
     names = _declared_functions()
     for n in ("pca_dvf", "warp_trilinear", "drr_forward", "drr_adjoint", "grad_w",
               "solve_projection", "ray_table", "residual_fit", "tumour_position"):
